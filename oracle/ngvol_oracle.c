@@ -1,0 +1,695 @@
+/*
+ * FP64 CPU oracle for the neural-volume hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or constant generator with the HIP library, and the HIP
+ * library never calls it.
+ *
+ * It computes, plainly and slowly, what the paper's method computes:
+ *   - a multi-resolution hash-grid encoding (Section 3.1, Fig. 1B): per level,
+ *     the 8 corners of the enclosing grid cell are looked up in that level's
+ *     table and trilinearly interpolated, and level features are concatenated;
+ *   - a bias-free ReLU MLP on the concatenated features (Section 3.1);
+ *   - the sampling step (Section 4): uniform random coordinates in [0,1)^3
+ *     with a trilinearly interpolated ground-truth value;
+ *   - one optimisation step: loss, analytic gradient, Adam (Section 3.1;
+ *     Kingma and Ba 2014);
+ *   - the ray-marched emission-absorption renderer fed by streamed samples
+ *     (Section 5.2.1);
+ *   - decoding the whole grid and its PSNR (Section 6).
+ *
+ * Readings of the paper where it is silent (the hash, the resolution rule,
+ * the sampler convention, the loss form, the camera and transfer function)
+ * are listed at the top of the design notes; each function names the one it
+ * uses.  Every floating-point value is FP64 except where noted (the ray
+ * geometry, which is specified in binary32 and evaluated here with one
+ * IEEE rounding per operation; build with -ffp-contract=off).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_MAX_LEVELS 32
+
+/* ------------------------------------------------------------------------ */
+/* Counter-based random numbers: SplitMix64 (Steele, Lea, Flood 2014).      */
+/* Output n of stream (seed, stream) is the n-th output of a SplitMix64     */
+/* sequence whose initial state is seed XOR (stream << 56).                 */
+/* ------------------------------------------------------------------------ */
+static uint64_t orc_mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+uint64_t orc_rng_u64(uint64_t seed, uint32_t stream, uint64_t index)
+{
+    uint64_t s0 = seed ^ ((uint64_t)stream << 56);
+    return orc_mix64(s0 + (index + 1ull) * 0x9E3779B97F4A7C15ull);
+}
+
+/* Uniform in [0,1): top 24 bits, exactly representable in binary32. */
+double orc_rng_u01(uint64_t seed, uint32_t stream, uint64_t index)
+{
+    return (double)(orc_rng_u64(seed, stream, index) >> 40) * 0x1p-24;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Model description and parameter layout.                                  */
+/*                                                                          */
+/* desc = { L, F, log2T, width, n_hidden, N_0, ..., N_{L-1} }               */
+/* Level l is a grid of N_l vertices per axis spanning [0,1].  It is stored */
+/* densely when N_l^3 <= T and hashed into T entries otherwise, so its      */
+/* table has min(T, N_l^3) entries of F features (entry-major).  Tables     */
+/* come first in level order; then the bias-free MLP matrices, row-major    */
+/* [out][in]: [width][L*F], (n_hidden-1) x [width][width], [1][width].      */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int L, F, log2T, width, n_hidden, n_in;
+    int64_t T;
+    int32_t N[ORC_MAX_LEVELS];
+    int dense[ORC_MAX_LEVELS];
+    int64_t size[ORC_MAX_LEVELS];
+    int64_t off[ORC_MAX_LEVELS + 1];
+    int64_t n_table, n_mlp, n_params;
+    int n_layers;         /* n_hidden + 1 matrices */
+    int64_t w_off[16];    /* offset of each matrix, relative to the MLP block */
+    int w_in[16], w_out[16];
+} orc_model;
+
+static int orc_model_from_desc(const int32_t* desc, orc_model* m)
+{
+    memset(m, 0, sizeof(*m));
+    m->L = desc[0];
+    m->F = desc[1];
+    m->log2T = desc[2];
+    m->width = desc[3];
+    m->n_hidden = desc[4];
+    if (m->L < 1 || m->L > ORC_MAX_LEVELS || m->F < 1 || m->log2T < 1 || m->log2T > 30 ||
+        m->width < 1 || m->n_hidden < 1 || m->n_hidden > 14)
+        return -1;
+    m->T = (int64_t)1 << m->log2T;
+    m->n_in = m->L * m->F;
+    m->off[0] = 0;
+    for (int l = 0; l < m->L; ++l) {
+        int64_t N = desc[5 + l];
+        if (N < 2) return -1;
+        m->N[l] = (int32_t)N;
+        int64_t cube = N * N * N;
+        m->dense[l] = cube <= m->T;
+        m->size[l] = m->dense[l] ? cube : m->T;
+        m->off[l + 1] = m->off[l] + m->size[l];
+    }
+    m->n_table = m->off[m->L] * m->F;
+    m->n_layers = m->n_hidden + 1;
+    int64_t pos = 0;
+    for (int i = 0; i < m->n_layers; ++i) {
+        m->w_in[i] = (i == 0) ? m->n_in : m->width;
+        m->w_out[i] = (i == m->n_layers - 1) ? 1 : m->width;
+        m->w_off[i] = pos;
+        pos += (int64_t)m->w_in[i] * m->w_out[i];
+    }
+    m->n_mlp = pos;
+    m->n_params = m->n_table + m->n_mlp;
+    return 0;
+}
+
+/* Writes level sizes, level offsets (entries) and {n_table, n_mlp, n_params}. */
+int orc_layout(const int32_t* desc, int64_t* size, int64_t* off, int64_t* counts)
+{
+    orc_model m;
+    if (orc_model_from_desc(desc, &m)) return -1;
+    for (int l = 0; l < m.L; ++l) {
+        size[l] = m.size[l];
+        off[l] = m.off[l];
+    }
+    off[m.L] = m.off[m.L];
+    counts[0] = m.n_table;
+    counts[1] = m.n_mlp;
+    counts[2] = m.n_params;
+    return 0;
+}
+
+/*
+ * Vertices per axis of each level: N_l = N_min * b^l.  When that is an
+ * integer (within 1e-9 relative) it is used as is, otherwise rounded up.
+ * If max_res > 0 the growth factor is b = exp((ln N_max - ln N_min)/(L-1)).
+ */
+int orc_resolutions(int L, int base, double scale, int max_res, int32_t* out)
+{
+    if (L < 1 || L > ORC_MAX_LEVELS || base < 2) return -1;
+    double b = scale;
+    if (max_res > 0) b = (L > 1) ? exp((log((double)max_res) - log((double)base)) / (double)(L - 1)) : 1.0;
+    for (int l = 0; l < L; ++l) {
+        double r = (double)base * pow(b, (double)l);
+        double rr = floor(r + 0.5);
+        out[l] = (int32_t)((fabs(r - rr) < 1e-9 * r) ? rr : ceil(r));
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Encoding (Section 3.1, Fig. 1B).                                         */
+/* ------------------------------------------------------------------------ */
+
+/* Clamp a binary32 coordinate to [0,1]; NaN maps to 0. */
+static double orc_clamp01f(float x)
+{
+    float y = fminf(fmaxf(x, 0.0f), 1.0f);
+    return (double)y;
+}
+
+/*
+ * Geometry of one level along one axis: p = x*(N-1) (exact in FP64 for a
+ * binary32 x and N <= 2^24), cell c = min(floor(p), N-2), weight w = p - c.
+ */
+static void orc_axis(double x, int32_t N, int64_t* c, double* w)
+{
+    double p = x * (double)(N - 1);
+    double fl = floor(p);
+    if (fl > (double)(N - 2)) fl = (double)(N - 2);
+    *c = (int64_t)fl;
+    *w = p - fl;
+}
+
+/*
+ * Table slot of vertex (vx,vy,vz) at a level: dense row-major index when the
+ * level is dense, else the spatial hash of Mueller et al. 2022 (the encoding
+ * the paper adopts), (vx*1 XOR vy*2654435761 XOR vz*805459861) mod 2^32,
+ * reduced modulo T (a power of two).
+ */
+static uint32_t orc_slot(const orc_model* m, int l, int64_t vx, int64_t vy, int64_t vz)
+{
+    if (m->dense[l]) {
+        int64_t N = m->N[l];
+        return (uint32_t)(vx + N * (vy + N * vz));
+    }
+    uint32_t h = ((uint32_t)vx * 1u) ^ ((uint32_t)vy * 2654435761u) ^ ((uint32_t)vz * 805459861u);
+    return h & (uint32_t)(m->T - 1);
+}
+
+/*
+ * Corners of level l for one point: global entry index (level offset added)
+ * and trilinear weight, corner order delta = (dx, dy, dz) with dx fastest.
+ */
+static void orc_corners(const orc_model* m, int l, const double x[3], int64_t idx[8], double wt[8])
+{
+    int64_t c[3];
+    double w[3];
+    for (int a = 0; a < 3; ++a) orc_axis(x[a], m->N[l], &c[a], &w[a]);
+    for (int k = 0; k < 8; ++k) {
+        int dx = k & 1, dy = (k >> 1) & 1, dz = (k >> 2) & 1;
+        double wk = (dx ? w[0] : 1.0 - w[0]) * (dy ? w[1] : 1.0 - w[1]) * (dz ? w[2] : 1.0 - w[2]);
+        idx[k] = m->off[l] + (int64_t)orc_slot(m, l, c[0] + dx, c[1] + dy, c[2] + dz);
+        wt[k] = wk;
+    }
+}
+
+static void orc_encode_one(const orc_model* m, const double* table, const float* xyz, double* e)
+{
+    double x[3] = {orc_clamp01f(xyz[0]), orc_clamp01f(xyz[1]), orc_clamp01f(xyz[2])};
+    for (int l = 0; l < m->L; ++l) {
+        int64_t idx[8];
+        double wt[8];
+        orc_corners(m, l, x, idx, wt);
+        for (int f = 0; f < m->F; ++f) {
+            double s = 0.0;
+            for (int k = 0; k < 8; ++k) s += wt[k] * table[idx[k] * m->F + f];
+            e[l * m->F + f] = s;
+        }
+    }
+}
+
+/* feat[n][L*F] = encoding of xyz[n][3] under the table part of params. */
+int orc_encode(const int32_t* desc, const double* params, const float* xyz, int64_t n, double* feat)
+{
+    orc_model m;
+    if (orc_model_from_desc(desc, &m)) return -1;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) orc_encode_one(&m, params, xyz + 3 * i, feat + i * m.n_in);
+    return 0;
+}
+
+/* idx[n][L][8] = slot within the level's table (no level offset); w[n][L][8]. */
+int orc_encode_debug(const int32_t* desc, const float* xyz, int64_t n, uint32_t* idx, double* w)
+{
+    orc_model m;
+    if (orc_model_from_desc(desc, &m)) return -1;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double x[3] = {orc_clamp01f(xyz[3 * i]), orc_clamp01f(xyz[3 * i + 1]), orc_clamp01f(xyz[3 * i + 2])};
+        for (int l = 0; l < m.L; ++l) {
+            int64_t g[8];
+            double wt[8];
+            orc_corners(&m, l, x, g, wt);
+            for (int k = 0; k < 8; ++k) {
+                idx[(i * m.L + l) * 8 + k] = (uint32_t)(g[k] - m.off[l]);
+                w[(i * m.L + l) * 8 + k] = wt[k];
+            }
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* MLP (Section 3.1): bias-free, ReLU on hidden layers, identity output.    */
+/* ------------------------------------------------------------------------ */
+
+/* Forward for one sample; keeps pre-activations z[layer][width] if asked. */
+static double orc_mlp_one(const orc_model* m, const double* W, const double* e, double* z_keep)
+{
+    double a[1024], b[1024];
+    const double* in = e;
+    int n_in = m->n_in;
+    for (int li = 0; li < m->n_layers; ++li) {
+        const double* Wl = W + m->w_off[li];
+        int no = m->w_out[li];
+        for (int o = 0; o < no; ++o) {
+            double s = 0.0;
+            for (int k = 0; k < n_in; ++k) s += Wl[(int64_t)o * n_in + k] * in[k];
+            if (li == m->n_layers - 1) return s;
+            if (z_keep) z_keep[li * m->width + o] = s;
+            b[o] = s > 0.0 ? s : 0.0;
+        }
+        memcpy(a, b, sizeof(double) * (size_t)no);
+        in = a;
+        n_in = no;
+    }
+    return 0.0; /* not reached */
+}
+
+int orc_mlp_fwd(const int32_t* desc, const double* W, const double* feat, int64_t n, double* out)
+{
+    orc_model m;
+    if (orc_model_from_desc(desc, &m) || m.width > 1024 || m.n_in > 1024) return -1;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) out[i] = orc_mlp_one(&m, W, feat + i * m.n_in, NULL);
+    return 0;
+}
+
+/* out[n] = Phi(xyz) = MLP(encode(xyz)). */
+int orc_forward(const int32_t* desc, const double* params, const float* xyz, int64_t n, double* out)
+{
+    orc_model m;
+    if (orc_model_from_desc(desc, &m) || m.width > 1024 || m.n_in > 1024) return -1;
+    const double* W = params + m.n_table;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double e[1024];
+        orc_encode_one(&m, params, xyz + 3 * i, e);
+        out[i] = orc_mlp_one(&m, W, e, NULL);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sampling step (Section 4).                                               */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Cell-centred trilinear sample with clamp-to-edge of a volume with dims
+ * (Dx, Dy, Dz), x fastest.  Voxel i has its centre at (i + 1/2)/D, so the
+ * sample is exact at voxel centres.
+ */
+static double orc_volume_at(const float* vol, const int32_t* dims, const float* xyz)
+{
+    int64_t i0[3];
+    double t[3];
+    for (int a = 0; a < 3; ++a) {
+        int64_t D = dims[a];
+        double u = (double)xyz[a] * (double)D - 0.5;
+        double fl = floor(u);
+        if (fl < 0.0) fl = 0.0;
+        if (fl > (double)(D - 2)) fl = (double)(D - 2);
+        double tt = u - fl;
+        if (tt < 0.0) tt = 0.0;
+        if (tt > 1.0) tt = 1.0;
+        i0[a] = (int64_t)fl;
+        t[a] = tt;
+    }
+    double s = 0.0;
+    for (int k = 0; k < 8; ++k) {
+        int dx = k & 1, dy = (k >> 1) & 1, dz = (k >> 2) & 1;
+        double w = (dx ? t[0] : 1.0 - t[0]) * (dy ? t[1] : 1.0 - t[1]) * (dz ? t[2] : 1.0 - t[2]);
+        int64_t id = (i0[0] + dx) + (int64_t)dims[0] * ((i0[1] + dy) + (int64_t)dims[1] * (i0[2] + dz));
+        s += w * (double)vol[id];
+    }
+    return s;
+}
+
+int orc_sample_volume(const float* vol, const int32_t* dims, const float* xyz, int64_t n, double* y)
+{
+    if (dims[0] < 2 || dims[1] < 2 || dims[2] < 2) return -1;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) y[i] = orc_volume_at(vol, dims, xyz + 3 * i);
+    return 0;
+}
+
+/* Training batch of step `step`: stream 3, index = step*B*3 + i*3 + axis. */
+int orc_batch_coords(uint64_t seed, int64_t step, int64_t B, float* xyz)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < B; ++i)
+        for (int a = 0; a < 3; ++a)
+            xyz[3 * i + a] = (float)orc_rng_u01(seed, 3u, (uint64_t)(step * B * 3 + i * 3 + a));
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Loss and analytic gradient.                                              */
+/* L = (1/B) sum_i (Phi(x_i) - y_i)^2; grad = dL/dparams (all parameters).   */
+/* ------------------------------------------------------------------------ */
+int orc_loss_grad(const int32_t* desc, const double* params, const float* xyz, const double* y, int64_t n,
+                  double* grad, double* loss_out)
+{
+    orc_model m;
+    if (orc_model_from_desc(desc, &m) || m.width > 1024 || m.n_in > 1024 || m.n_layers > 16) return -1;
+    const double* W = params + m.n_table;
+    memset(grad, 0, sizeof(double) * (size_t)m.n_params);
+    double* gW = grad + m.n_table;
+    /* per-sample feature gradient, then a sequential scatter in sample order */
+    double* de_all = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * (size_t)m.n_in);
+    if (!de_all) return -2;
+    int nt = 1;
+#ifdef _OPENMP
+    nt = omp_get_max_threads();
+#endif
+    double* gW_t = (double*)calloc((size_t)nt * (size_t)m.n_mlp, sizeof(double));
+    double* loss_t = (double*)calloc((size_t)nt, sizeof(double));
+    if (!gW_t || !loss_t) {
+        free(de_all);
+        free(gW_t);
+        free(loss_t);
+        return -2;
+    }
+#pragma omp parallel
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double* gw = gW_t + (size_t)tid * (size_t)m.n_mlp;
+        double* e = (double*)malloc(sizeof(double) * 1024);
+        double* z = (double*)malloc(sizeof(double) * 16 * 1024);
+        double* h = (double*)malloc(sizeof(double) * 16 * 1024);
+        double* dz = (double*)malloc(sizeof(double) * 1024);
+        double* dh = (double*)malloc(sizeof(double) * 1024);
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            orc_encode_one(&m, params, xyz + 3 * i, e);
+            double yhat = orc_mlp_one(&m, W, e, z);
+            double r = yhat - y[i];
+            loss_t[tid] += r * r;
+            double g = 2.0 * r / (double)n; /* dL/dyhat */
+            /* hidden activations h_j = relu(z_j) */
+            for (int li = 0; li < m.n_hidden; ++li)
+                for (int o = 0; o < m.width; ++o) {
+                    double v = z[li * m.width + o];
+                    h[li * m.width + o] = v > 0.0 ? v : 0.0;
+                }
+            /* output layer: yhat = w_out . h_last */
+            int last = m.n_layers - 1;
+            const double* Wo = W + m.w_off[last];
+            for (int k = 0; k < m.width; ++k) {
+                gw[m.w_off[last] + k] += g * h[(m.n_hidden - 1) * m.width + k];
+                dh[k] = g * Wo[k];
+            }
+            /* hidden layers, last to first */
+            for (int li = m.n_hidden - 1; li >= 0; --li) {
+                int nin = m.w_in[li];
+                const double* Wl = W + m.w_off[li];
+                const double* a_in = (li == 0) ? e : h + (li - 1) * m.width;
+                for (int o = 0; o < m.width; ++o) dz[o] = z[li * m.width + o] > 0.0 ? dh[o] : 0.0;
+                for (int o = 0; o < m.width; ++o)
+                    for (int k = 0; k < nin; ++k) gw[m.w_off[li] + (int64_t)o * nin + k] += dz[o] * a_in[k];
+                double* dprev = (li == 0) ? de_all + i * m.n_in : dh;
+                double tmp[1024];
+                for (int k = 0; k < nin; ++k) {
+                    double s = 0.0;
+                    for (int o = 0; o < m.width; ++o) s += Wl[(int64_t)o * nin + k] * dz[o];
+                    tmp[k] = s;
+                }
+                memcpy(dprev, tmp, sizeof(double) * (size_t)nin);
+            }
+        }
+        free(e);
+        free(z);
+        free(h);
+        free(dz);
+        free(dh);
+    }
+    double loss = 0.0;
+    for (int t = 0; t < nt; ++t) {
+        loss += loss_t[t];
+        for (int64_t k = 0; k < m.n_mlp; ++k) gW[k] += gW_t[(size_t)t * (size_t)m.n_mlp + (size_t)k];
+    }
+    /* table gradient: grad[idx][f] += w * de[l*F+f] */
+    for (int64_t i = 0; i < n; ++i) {
+        const float* p = xyz + 3 * i;
+        double x[3] = {orc_clamp01f(p[0]), orc_clamp01f(p[1]), orc_clamp01f(p[2])};
+        for (int l = 0; l < m.L; ++l) {
+            int64_t idx[8];
+            double wt[8];
+            orc_corners(&m, l, x, idx, wt);
+            for (int k = 0; k < 8; ++k)
+                for (int f = 0; f < m.F; ++f) grad[idx[k] * m.F + f] += wt[k] * de_all[i * m.n_in + l * m.F + f];
+        }
+    }
+    if (loss_out) *loss_out = (n > 0) ? loss / (double)n : 0.0;
+    free(de_all);
+    free(gW_t);
+    free(loss_t);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Adam (Kingma and Ba 2014), dense, bias-corrected, eps outside the root.  */
+/* t is the 1-based step number.                                            */
+/* ------------------------------------------------------------------------ */
+int orc_adam(int64_t n, double* theta, double* m, double* v, const double* g, int64_t t, double lr, double b1,
+             double b2, double eps)
+{
+    double c1 = 1.0 - pow(b1, (double)t);
+    double c2 = 1.0 - pow(b2, (double)t);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+        v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+        double mh = m[i] / c1;
+        double vh = v[i] / c2;
+        theta[i] -= lr * mh / (sqrt(vh) + eps);
+    }
+    return 0;
+}
+
+/*
+ * `steps` training steps of batch B on a volume: coordinates of step s from
+ * orc_batch_coords(seed, step0 + s), targets by orc_sample_volume, MSE loss,
+ * Adam at 1-based step t = step0 + s + 1.  m and v are caller-owned state.
+ */
+int orc_train(const int32_t* desc, double* params, double* adam_m, double* adam_v, const float* vol,
+              const int32_t* dims, uint64_t seed, int64_t step0, int64_t steps, int64_t B, double lr, double b1,
+              double b2, double eps, double* losses)
+{
+    orc_model m;
+    if (orc_model_from_desc(desc, &m)) return -1;
+    float* xyz = (float*)malloc(sizeof(float) * 3 * (size_t)B);
+    double* y = (double*)malloc(sizeof(double) * (size_t)B);
+    double* g = (double*)malloc(sizeof(double) * (size_t)m.n_params);
+    if (!xyz || !y || !g) {
+        free(xyz);
+        free(y);
+        free(g);
+        return -2;
+    }
+    int rc = 0;
+    for (int64_t s = 0; s < steps && rc == 0; ++s) {
+        orc_batch_coords(seed, step0 + s, B, xyz);
+        orc_sample_volume(vol, dims, xyz, B, y);
+        double loss = 0.0;
+        rc = orc_loss_grad(desc, params, xyz, y, B, g, &loss);
+        if (losses) losses[s] = loss;
+        if (rc == 0) orc_adam(m.n_params, params, adam_m, adam_v, g, step0 + s + 1, lr, b1, b2, eps);
+    }
+    free(xyz);
+    free(y);
+    free(g);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Decode and PSNR (Section 6): MSE over all voxel centres (i+1/2)/D.        */
+/* ------------------------------------------------------------------------ */
+int orc_mse_grid(const int32_t* desc, const double* params, const float* vol, const int32_t* dims, double* mse)
+{
+    orc_model m;
+    if (orc_model_from_desc(desc, &m) || m.width > 1024 || m.n_in > 1024) return -1;
+    const double* W = params + m.n_table;
+    int64_t nx = dims[0], ny = dims[1], nz = dims[2];
+    double acc = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : acc)
+    for (int64_t z = 0; z < nz; ++z) {
+        double e[1024];
+        for (int64_t yv = 0; yv < ny; ++yv)
+            for (int64_t xv = 0; xv < nx; ++xv) {
+                float p[3] = {((float)xv + 0.5f) / (float)nx, ((float)yv + 0.5f) / (float)ny,
+                              ((float)z + 0.5f) / (float)nz};
+                orc_encode_one(&m, params, p, e);
+                double d = orc_mlp_one(&m, W, e, NULL) - (double)vol[xv + nx * (yv + ny * z)];
+                acc += d * d;
+            }
+    }
+    *mse = acc / (double)(nx * ny * nz);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Ray-marched emission-absorption rendering (Section 5.2.1).               */
+/*                                                                          */
+/* Ray geometry is binary32, one rounding per operation, no FMA:            */
+/*   dir = (W + (px+1/2) U) + (py+1/2) V, d = dir / sqrt(dir.dir);          */
+/*   slab test against [0,1]^3 with inv = 1/d; t_near = max(t_min, 0);       */
+/*   hit iff t_near < t_max; n = max(0, ceil((t_max - t_near)/dt - j));      */
+/*   t_k = t_near + (k + j) dt; p_k = o + t_k d.                             */
+/* Everything after p_k is FP64: Phi(p_k) -> v = clamp(Phi, 0, 1) ->         */
+/* linear lookup in a 256-entry RGBA table -> front-to-back compositing,     */
+/* stopping after the sample at which accumulated alpha reaches 0.99.        */
+/* cam = { o[3], U[3], V[3], W[3] }.                                         */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    float o[3], d[3], t0, j;
+    uint32_t n;
+} orc_ray;
+
+static orc_ray orc_make_ray(const float* cam, int W, int px, int py, uint32_t frame_seed, float dt)
+{
+    orc_ray r;
+    float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+    float dir[3];
+    for (int a = 0; a < 3; ++a) {
+        float t1 = fx * cam[3 + a];
+        float t2 = cam[9 + a] + t1;
+        float t3 = fy * cam[6 + a];
+        dir[a] = t2 + t3;
+    }
+    float q0 = dir[0] * dir[0], q1 = dir[1] * dir[1], q2 = dir[2] * dir[2];
+    float n2 = (q0 + q1) + q2;
+    float nrm = sqrtf(n2);
+    float tmin = -INFINITY, tmax = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        r.o[a] = cam[a];
+        r.d[a] = dir[a] / nrm;
+        float inv = 1.0f / r.d[a];
+        float ta = (0.0f - r.o[a]) * inv;
+        float tb = (1.0f - r.o[a]) * inv;
+        tmin = fmaxf(tmin, fminf(ta, tb));
+        tmax = fminf(tmax, fmaxf(ta, tb));
+    }
+    float tn = fmaxf(tmin, 0.0f);
+    r.t0 = tn;
+    r.j = (float)orc_rng_u01((uint64_t)frame_seed, 5u, (uint64_t)py * (uint64_t)W + (uint64_t)px);
+    r.n = 0;
+    if (tn < tmax) {
+        float span = tmax - tn;
+        float q = span / dt;
+        float c = ceilf(q - r.j);
+        if (c > 0.0f) r.n = (uint32_t)c;
+    }
+    return r;
+}
+
+static void orc_ray_point(const orc_ray* r, uint32_t k, float dt, float p[3])
+{
+    float kj = (float)k + r->j;
+    float t = r->t0 + kj * dt;
+    for (int a = 0; a < 3; ++a) {
+        float td = t * r->d[a];
+        p[a] = r->o[a] + td;
+    }
+}
+
+/* Per-pixel geometric sample counts n[H*W] and the k-th sample coordinate
+ * of pixel `pix` (for bit-exact coordinate checks). */
+int orc_ray_counts(const float* cam, int W, int H, uint32_t frame_seed, float dt, uint32_t* n)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < (int64_t)W * H; ++p) {
+        orc_ray r = orc_make_ray(cam, W, (int)(p % W), (int)(p / W), frame_seed, dt);
+        n[p] = r.n;
+    }
+    return 0;
+}
+
+int orc_ray_points(const float* cam, int W, int H, uint32_t frame_seed, float dt, int64_t pix, uint32_t k0,
+                   uint32_t count, float* xyz)
+{
+    (void)H;
+    orc_ray r = orc_make_ray(cam, W, (int)(pix % W), (int)(pix / W), frame_seed, dt);
+    for (uint32_t k = 0; k < count; ++k) orc_ray_point(&r, k0 + k, dt, xyz + 3 * k);
+    return 0;
+}
+
+/*
+ * Render the pixels listed in pix[n_pix] (row-major pixel ids, py*W + px).
+ * rgba[n_pix][4] (premultiplied colour, accumulated alpha), n_geo[n_pix]
+ * (geometric count), n_used[n_pix] (samples composited before stopping).
+ */
+int orc_render_pixels(const int32_t* desc, const double* params, const float* cam, const float* lut, int W, int H,
+                      float dt, uint32_t frame_seed, const int64_t* pix, int64_t n_pix, double* rgba,
+                      uint32_t* n_geo, uint32_t* n_used)
+{
+    orc_model m;
+    (void)H;
+    if (orc_model_from_desc(&desc[0], &m) || m.width > 1024 || m.n_in > 1024) return -1;
+    const double* Wm = params + m.n_table;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t q = 0; q < n_pix; ++q) {
+        int64_t p = pix[q];
+        orc_ray r = orc_make_ray(cam, W, (int)(p % W), (int)(p / W), frame_seed, dt);
+        double C[3] = {0.0, 0.0, 0.0}, A = 0.0;
+        uint32_t used = 0;
+        double e[1024];
+        for (uint32_t k = 0; k < r.n; ++k) {
+            float pt[3];
+            orc_ray_point(&r, k, dt, pt);
+            orc_encode_one(&m, params, pt, e);
+            double v = orc_mlp_one(&m, Wm, e, NULL);
+            if (!(v > 0.0)) v = 0.0;
+            if (v > 1.0) v = 1.0;
+            double u = 255.0 * v;
+            double fi = floor(u);
+            if (fi > 254.0) fi = 254.0;
+            int i0 = (int)fi;
+            double f = u - fi;
+            double c4[4];
+            for (int ch = 0; ch < 4; ++ch)
+                c4[ch] = (double)lut[4 * i0 + ch] * (1.0 - f) + (double)lut[4 * (i0 + 1) + ch] * f;
+            double a = c4[3];
+            for (int ch = 0; ch < 3; ++ch) C[ch] += (1.0 - A) * a * c4[ch];
+            A += (1.0 - A) * a;
+            used = k + 1;
+            if (A >= 0.99) break;
+        }
+        for (int ch = 0; ch < 3; ++ch) rgba[4 * q + ch] = C[ch];
+        rgba[4 * q + 3] = A;
+        n_geo[q] = r.n;
+        n_used[q] = used;
+    }
+    return 0;
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,438 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+None of these checks re-types an oracle formula: each compares the oracle
+with a printed value, a library routine, a closed form or an invariant, chosen
+so that a dropped term, a wrong sign or index or a transposed operand fails.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.interpolate import RegularGridInterpolator
+
+import oracle
+import synth
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def small_model(L=3, F=2, log2T=12, res=(5, 9, 17), width=16, n_hidden=2):
+    return oracle.Model(L, F, log2T, list(res), width, n_hidden)
+
+
+def rand_params(m, seed=7, table_scale=0.5):
+    rng = np.random.default_rng(seed)
+    p = np.concatenate([rng.uniform(-table_scale, table_scale, m.n_table),
+                        rng.uniform(-0.6, 0.6, m.n_mlp)])
+    return p
+
+
+# ---------------------------------------------------------------- RNG -----
+
+def test_splitmix64_published_outputs():
+    g = json.load(open(os.path.join(GOLD, "splitmix64_seed0.json")))
+    # stream 0, seed 0 is the plain generator started from state 0
+    for n, hx in enumerate(g["outputs_hex"]):
+        assert oracle.rng_u64(0, 0, n) == int(hx, 16)
+
+
+def test_rng_two_implementations_agree():
+    # the NumPy input generator and the C oracle implement the same definition
+    idx = np.arange(0, 5000, 7, dtype=np.uint64)
+    a = synth.rng_u64(2207_11620, 3, idx)
+    b = np.array([oracle.rng_u64(2207_11620, 3, int(i)) for i in idx], dtype=np.uint64)
+    assert np.array_equal(a, b)
+    u = oracle.batch_coords(99, 5, 300)
+    ref = synth.rng_u01(99, synth.STREAM_BATCH, np.arange(5 * 300 * 3, 6 * 300 * 3)).reshape(300, 3)
+    assert np.array_equal(u, ref)
+    assert u.min() >= 0.0 and u.max() < 1.0
+    # uniformity sanity: mean of 2^16 draws within 5 sigma of 1/2
+    v = synth.rng_u01_f64(1, 4, np.arange(1 << 16))
+    assert abs(v.mean() - 0.5) < 5 * math.sqrt(1 / 12 / (1 << 16))
+
+
+# --------------------------------------------------- layout / counts -----
+
+def test_resolution_lists():
+    # growth 1.5 from 4 (8 levels) and 16 -> 2048 geometric (16 levels)
+    assert oracle.resolutions(8, 4, 1.5) == [4, 6, 9, 14, 21, 31, 46, 69]
+    r = oracle.resolutions(16, 16, 0.0, 2048)
+    assert r[0] == 16 and r[-1] == 2048 and len(r) == 16
+    b = 128 ** (1 / 15)
+    for l, n in enumerate(r):  # ceil of the real resolution, exact ends
+        assert n == (round(16 * b ** l) if l in (0, 15) else math.ceil(16 * b ** l))
+    assert oracle.resolutions(5, 4, 2.0) == [4, 8, 16, 32, 64]
+
+
+def test_param_counts_match_paper():
+    g = json.load(open(os.path.join(GOLD, "param_counts.json")))
+    for mdl in g["models"]:
+        res = oracle.resolutions(mdl["L"], mdl["base"], 2.0)
+        m = oracle.Model(mdl["L"], mdl["F"], mdl["log2T"], res, mdl["width"], mdl["n_hidden"])
+        w, nin = mdl["width"], mdl["L"] * mdl["F"]
+        nin_pad = -(-nin // 16) * 16
+        mlp_padded = nin_pad * w + (mdl["n_hidden"] - 1) * w * w + w * 16
+        # unpadded storage: the last layer has a single output row
+        assert m.n_mlp == nin * w + (mdl["n_hidden"] - 1) * w * w + w
+        total = m.n_table + mlp_padded
+        assert total == mdl["printed_params"], mdl["name"]
+        assert round(total * 2 / 2 ** 20, 1) == mdl["table1_size_mb"], mdl["name"]
+
+
+def test_level_sizes_dense_then_capped():
+    m = oracle.Model(8, 2, 14, oracle.resolutions(8, 4, 1.5), 32, 2)
+    assert list(m.level_size) == [64, 216, 729, 2744, 9261, 16384, 16384, 16384]
+    assert list(np.diff(m.level_offset)) == list(m.level_size)
+    assert m.n_params == 125900
+
+
+# ------------------------------------------------------------ hash -----
+
+def test_hash_vectors():
+    # Mueller et al. spatial hash with primes (1, 2654435761, 805459861),
+    # evaluated by hand: 2654435761 = 0x9E3779B1, 805459861 = 0x30025795.
+    # level with N=64 vertices (64^3 > 2^14: hashed)
+    m = oracle.Model(1, 1, 14, [64], 8, 1)
+    s = 1.0 / 63.0
+    pts = np.array([[0.5 * s, 1.5 * s, 0.5 * s],     # cell (0,1,0): corner 0 = (0,1,0)
+                    [0.5 * s, 0.5 * s, 1.5 * s],     # cell (0,0,1): corner 0 = (0,0,1)
+                    [0.5 * s, 0.5 * s, 0.5 * s],     # cell (0,0,0): corner 7 = (1,1,1)
+                    [5.5 * s, 7.5 * s, 11.5 * s]],   # cell (5,7,11): corner 0
+                   dtype=np.float32)
+    idx, _ = oracle.encode_debug(m, pts)
+    assert idx[0, 0, 0] == 0x39B1 == 14769          # 0x9E3779B1 & 0x3FFF
+    assert idx[1, 0, 0] == 0x1795 == 6037           # 0x30025795 & 0x3FFF
+    assert idx[2, 0, 7] == 11813                    # (1 ^ 0x9E3779B1 ^ 0x30025795) & 0x3FFF
+    assert idx[2, 0, 0] == 0                        # vertex (0,0,0) hashes to 0
+    assert idx[3, 0, 0] == 4277
+    # T = 2^19 on the finest cfg1 level (N = 2048)
+    m2 = oracle.Model(1, 1, 19, [2048], 8, 1)
+    t = 1.0 / 2047.0
+    p2 = np.array([[1.5 * t, 1.5 * t, 1.5 * t], [1.0, 1.0, 1.0]], dtype=np.float32)
+    idx2, w2 = oracle.encode_debug(m2, p2)
+    assert idx2[0, 0, 0] == 339493                  # vertex (1,1,1)
+    assert idx2[1, 0, 7] == 285147                  # vertex (2047,2047,2047): x=1 -> last cell, w=1
+    assert w2[1, 0, 7] == 1.0 and np.all(w2[1, 0, :7] == 0.0)
+
+
+def test_dense_index_and_corner_order():
+    # a dense level: slot = vx + N*(vy + N*vz); corner k has delta (k&1, k>>1&1, k>>2&1)
+    N = 9
+    m = oracle.Model(1, 1, 12, [N], 8, 1)
+    c = np.array([3, 5, 7])
+    p = ((c + 0.25) / (N - 1)).astype(np.float32)[None]
+    idx, w = oracle.encode_debug(m, p)
+    for k in range(8):
+        d = np.array([k & 1, (k >> 1) & 1, (k >> 2) & 1])
+        v = c + d
+        assert idx[0, 0, k] == v[0] + N * (v[1] + N * v[2])
+    # weights for fractional offset 0.25 on every axis
+    for k in range(8):
+        n1 = bin(k).count("1")
+        assert w[0, 0, k] == pytest.approx(0.25 ** n1 * 0.75 ** (3 - n1), abs=1e-12)
+
+
+# ---------------------------------------------------- interpolation -----
+
+def test_collision_free_equals_dense_trilinear_library():
+    # cfg0 resolutions with T = 2^19: every level dense (69^3 < 2^19)
+    res = oracle.resolutions(8, 4, 1.5)
+    m = oracle.Model(8, 2, 19, res, 16, 1)
+    assert all(s == n ** 3 for s, n in zip(m.level_size, res))
+    rng = np.random.default_rng(3)
+    params = rng.normal(size=m.n_params)
+    xyz = rng.random((500, 3)).astype(np.float32)
+    xyz[:5] = [[0, 0, 0], [1, 1, 1], [1, 0, 0.5], [0.999999, 1e-7, 0.5], [0.5, 0.5, 0.5]]
+    e = oracle.encode(m, params, xyz)
+    for l, N in enumerate(res):
+        off = int(m.level_offset[l])
+        g = np.linspace(0.0, 1.0, N)
+        for f in range(2):
+            tab = params[2 * off + f: 2 * (off + N ** 3): 2].reshape(N, N, N)  # [vz][vy][vx]
+            interp = RegularGridInterpolator((g, g, g), tab, method="linear")
+            ref = interp(xyz[:, ::-1].astype(np.float64))
+            np.testing.assert_allclose(e[:, 2 * l + f], ref, rtol=0, atol=1e-12)
+
+
+def test_affine_field_reproduced_exactly():
+    res = [5, 9, 17, 33]
+    m = oracle.Model(4, 1, 17, res, 8, 1)  # all dense (33^3 < 2^17)
+    a = np.array([0.3, -1.7, 2.5])
+    b = 0.125
+    params = np.zeros(m.n_params)
+    for l, N in enumerate(res):
+        v = np.arange(N) / (N - 1)
+        vz, vy, vx = np.meshgrid(v, v, v, indexing="ij")
+        params[m.level_offset[l]: m.level_offset[l + 1]] = (a[0] * vx + a[1] * vy + a[2] * vz + b).ravel()
+    xyz = np.random.default_rng(5).random((1000, 3)).astype(np.float32)
+    e = oracle.encode(m, params, xyz)
+    exact = xyz.astype(np.float64) @ a + b
+    for l in range(4):
+        np.testing.assert_allclose(e[:, l], exact, atol=2e-15 * 8)
+
+
+def test_partition_of_unity_and_vertex_values():
+    m = oracle.Model(8, 2, 14, oracle.resolutions(8, 4, 1.5), 32, 2)
+    xyz = np.random.default_rng(11).random((2000, 3)).astype(np.float32)
+    idx, w = oracle.encode_debug(m, xyz)
+    assert np.all(w >= 0.0) and np.all(w <= 1.0)
+    np.testing.assert_allclose(w.sum(axis=2), 1.0, atol=1e-14)
+    # at a vertex the feature equals that vertex's table entry
+    params = rand_params(m)
+    for l, N in enumerate(m.res):
+        v = np.array([[2, 1, N - 1]])
+        p = (v / (N - 1)).astype(np.float32)
+        exact = np.all(p.astype(np.float64) * (N - 1) == v)
+        if not exact:
+            continue
+        i, ww = oracle.encode_debug(m, p)
+        k = int(np.argmax(ww[0, l]))
+        assert ww[0, l, k] == 1.0
+        e = oracle.encode(m, params, p)
+        slot = int(m.level_offset[l]) + int(i[0, l, k])
+        assert e[0, 2 * l] == params[2 * slot] and e[0, 2 * l + 1] == params[2 * slot + 1]
+
+
+def test_clamp_outside_unit_cube():
+    m = small_model()
+    params = rand_params(m)
+    a = np.array([[-0.5, 0.3, 1.5], [2.0, -1.0, 0.5]], np.float32)
+    b = np.clip(a, 0, 1)
+    np.testing.assert_array_equal(oracle.encode(m, params, a), oracle.encode(m, params, b))
+
+
+# --------------------------------------------------------------- MLP -----
+
+def test_mlp_equals_blas_chain():
+    m = oracle.Model(16, 2, 19, oracle.resolutions(16, 16, 0, 2048), 64, 2)
+    rng = np.random.default_rng(1)
+    W = rng.normal(size=m.n_mlp) * 0.2
+    feat = rng.normal(size=(300, 32))
+    out = oracle.mlp_fwd(m, W, feat)
+    W1 = W[:64 * 32].reshape(64, 32)
+    W2 = W[64 * 32: 64 * 32 + 64 * 64].reshape(64, 64)
+    W3 = W[64 * 32 + 64 * 64:].reshape(1, 64)
+    h = np.maximum(feat @ W1.T, 0)
+    h = np.maximum(h @ W2.T, 0)
+    ref = (h @ W3.T)[:, 0]
+    np.testing.assert_allclose(out, ref, rtol=1e-13, atol=1e-13)
+
+
+def test_forward_is_encode_then_mlp():
+    m = small_model()
+    params = rand_params(m)
+    xyz = np.random.default_rng(2).random((100, 3)).astype(np.float32)
+    a = oracle.forward(m, params, xyz)
+    b = oracle.mlp_fwd(m, params[m.n_table:], oracle.encode(m, params, xyz))
+    np.testing.assert_allclose(a, b, rtol=1e-14, atol=1e-15)
+
+
+# ---------------------------------------------------------- gradient -----
+
+def _loss(m, params, xyz, y):
+    out = oracle.forward(m, params, xyz)
+    return float(np.mean((out - y) ** 2))
+
+
+def test_gradient_central_differences():
+    m = small_model(L=3, F=2, log2T=10, res=(5, 9, 17), width=16, n_hidden=2)
+    params = rand_params(m, seed=4)
+    rng = np.random.default_rng(8)
+    xyz = rng.random((64, 3)).astype(np.float32)
+    y = rng.random(64)
+    loss, g = oracle.loss_grad(m, params, xyz, y)
+    assert loss == pytest.approx(_loss(m, params, xyz, y), rel=1e-13)
+    h = 1e-3
+    # every MLP weight, and the table entries the batch touches plus some it does not
+    idx, _ = oracle.encode_debug(m, xyz)
+    touched = set()
+    for l in range(m.L):
+        for s in np.unique(idx[:, l, :]):
+            touched.update({2 * (int(m.level_offset[l]) + int(s)) + f for f in range(2)})
+    cand = sorted(touched)[::7] + list(range(m.n_table, m.n_params))
+    cand += [i for i in range(0, m.n_table, 97) if i not in touched][:10]
+    checked = 0
+    for i in cand:
+        p1, p2 = params.copy(), params.copy()
+        p1[i] += h
+        p2[i] -= h
+        fd = (_loss(m, p1, xyz, y) - _loss(m, p2, xyz, y)) / (2 * h)
+        # piecewise quadratic in one parameter: FD exact unless a ReLU flips
+        # within +-h; detect flips by comparing one-sided second differences
+        l0 = _loss(m, params, xyz, y)
+        c2a = (_loss(m, p1, xyz, y) - l0)
+        c2b = (l0 - _loss(m, p2, xyz, y))
+        p3 = params.copy()
+        p3[i] += 2 * h
+        c2c = (_loss(m, p3, xyz, y) - _loss(m, p1, xyz, y))
+        if abs((c2c - c2a) - (c2a - c2b)) > 1e-9 * max(1.0, abs(c2a)):
+            continue
+        assert fd == pytest.approx(g[i], rel=1e-7, abs=1e-11), i
+        checked += 1
+    assert checked > 0.8 * len(cand)
+    # untouched table entries have exactly zero gradient
+    un = [i for i in range(m.n_table) if i not in touched]
+    assert np.all(g[un] == 0.0)
+
+
+def test_gradient_matches_torch_autograd_for_mlp_block():
+    torch = pytest.importorskip("torch")
+    m = small_model(L=3, F=2, log2T=10, res=(5, 9, 17), width=16, n_hidden=3)
+    params = rand_params(m, seed=9)
+    rng = np.random.default_rng(10)
+    xyz = rng.random((128, 3)).astype(np.float32)
+    y = rng.random(128)
+    _, g = oracle.loss_grad(m, params, xyz, y)
+    e = torch.tensor(oracle.encode(m, params, xyz), dtype=torch.float64, requires_grad=True)
+    Ws = []
+    pos = m.n_table
+    for (o, i) in synth.mlp_shapes(m.n_in, m.width, m.n_hidden):
+        Ws.append(torch.tensor(params[pos:pos + o * i].reshape(o, i), dtype=torch.float64, requires_grad=True))
+        pos += o * i
+    h = e
+    for W in Ws[:-1]:
+        h = torch.relu(torch.nn.functional.linear(h, W))
+    out = torch.nn.functional.linear(h, Ws[-1])[:, 0]
+    loss = torch.mean((out - torch.tensor(y)) ** 2)
+    loss.backward()
+    gm = np.concatenate([W.grad.numpy().ravel() for W in Ws])
+    np.testing.assert_allclose(g[m.n_table:], gm, rtol=1e-12, atol=1e-15)
+    # table gradient = scatter of dL/de through the corner weights
+    idx, w = oracle.encode_debug(m, xyz)
+    de = e.grad.numpy()
+    gt = np.zeros(m.n_table)
+    for l in range(m.L):
+        for f in range(m.F):
+            slots = 2 * (m.level_offset[l] + idx[:, l, :].astype(np.int64)) + f
+            np.add.at(gt, slots.ravel(), (w[:, l, :] * de[:, 2 * l + f][:, None]).ravel())
+    np.testing.assert_allclose(g[:m.n_table], gt, rtol=1e-12, atol=1e-15)
+
+
+# -------------------------------------------------------------- Adam -----
+
+def test_adam_first_step_closed_form():
+    rng = np.random.default_rng(0)
+    n = 1000
+    theta = rng.normal(size=n)
+    th0 = theta.copy()
+    g = rng.normal(size=n) * 10 ** rng.uniform(-8, 2, n)
+    g[::10] = 0.0
+    mm, vv = np.zeros(n), np.zeros(n)
+    oracle.adam(theta, mm, vv, g, 1, 1e-2, 0.9, 0.99, 1e-15)
+    step = theta - th0
+    # step 1: m_hat = g, v_hat = g^2, so the move is -lr g / (|g| + eps): -lr sign(g) up to eps/|g|
+    gz = g[g != 0]
+    np.testing.assert_allclose(step[g != 0], -1e-2 * gz / (np.abs(gz) + 1e-15), rtol=1e-12)
+    np.testing.assert_allclose(step[g != 0], -1e-2 * np.sign(gz), rtol=1e-4)
+    assert np.all(step[g == 0] == 0.0)
+
+
+def test_adam_matches_torch_optim():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(1)
+    n = 257
+    theta = rng.normal(size=n)
+    tp = torch.tensor(theta.copy(), dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([tp], lr=1e-2, betas=(0.9, 0.99), eps=1e-15)
+    mm, vv = np.zeros(n), np.zeros(n)
+    for t in range(1, 21):
+        g = rng.normal(size=n)
+        g[rng.random(n) < 0.3] = 0.0
+        oracle.adam(theta, mm, vv, g, t, 1e-2, 0.9, 0.99, 1e-15)
+        tp.grad = torch.tensor(g)
+        opt.step()
+    np.testing.assert_allclose(theta, tp.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+# ---------------------------------------------------------- sampler -----
+
+def test_sampler_voxel_centres_affine_and_library():
+    rng = np.random.default_rng(4)
+    D = (7, 5, 6)  # x, y, z
+    vol = rng.random((D[2], D[1], D[0])).astype(np.float32)
+    # exact at voxel centres
+    zz, yy, xx = np.meshgrid(*[np.arange(d) for d in D[::-1]], indexing="ij")
+    ctr = np.stack([(xx + 0.5) / D[0], (yy + 0.5) / D[1], (zz + 0.5) / D[2]], -1).reshape(-1, 3).astype(np.float32)
+    y = oracle.sample_volume(vol, ctr)
+    # (i+1/2)/D is not binary32-exact for D=7: error bounded by slope * ulp
+    np.testing.assert_allclose(y, vol.ravel().astype(np.float64), atol=1e-6)
+    # power-of-two dims: voxel centres are exact in binary32, so the sample is exact
+    D2 = (8, 4, 16)
+    vol2 = rng.random((D2[2], D2[1], D2[0])).astype(np.float32)
+    z2, y2, x2 = np.meshgrid(*[np.arange(d) for d in D2[::-1]], indexing="ij")
+    c2 = np.stack([(x2 + 0.5) / D2[0], (y2 + 0.5) / D2[1], (z2 + 0.5) / D2[2]], -1).reshape(-1, 3)
+    assert np.array_equal(oracle.sample_volume(vol2, c2.astype(np.float32)), vol2.ravel().astype(np.float64))
+    # interior points: scipy trilinear on the cell-centre grid
+    pts = rng.uniform(0.0, 1.0, (400, 3)).astype(np.float32)
+    g = [(np.arange(d) + 0.5) / d for d in D]
+    interp = RegularGridInterpolator((g[2], g[1], g[0]), vol.astype(np.float64), method="linear",
+                                     bounds_error=False, fill_value=None)
+    clamp = np.stack([np.clip(pts[:, a], g[a][0], g[a][-1]) for a in range(3)], -1)
+    ref = interp(clamp[:, ::-1])
+    np.testing.assert_allclose(oracle.sample_volume(vol, pts), ref, atol=1e-6)
+    # affine volume is reproduced inside the centre hull
+    a = np.array([0.2, -0.1, 0.3])
+    lin = (a[0] * (xx + 0.5) / D[0] + a[1] * (yy + 0.5) / D[1] + a[2] * (zz + 0.5) / D[2]).astype(np.float32)
+    inside = rng.uniform(0.2, 0.8, (200, 3)).astype(np.float32)
+    np.testing.assert_allclose(oracle.sample_volume(lin, inside), inside.astype(np.float64) @ a, atol=1e-7)
+
+
+# -------------------------------------------------------------- PSNR -----
+
+def test_psnr_closed_form():
+    # volume = 0.25 + 0.5 x; a one-level affine table reproduces it, the MLP
+    # passes the feature through (positive values) and adds no bias.
+    D = 16
+    xs = (np.arange(D) + 0.5) / D
+    vol = np.broadcast_to((0.25 + 0.5 * xs)[None, None, :], (D, D, D)).astype(np.float32).copy()
+    N = 17
+    m = oracle.Model(1, 1, 14, [N], 1, 1)
+    delta = 1e-2
+    v = np.arange(N) / (N - 1)
+    vz, vy, vx = np.meshgrid(v, v, v, indexing="ij")
+    params = np.zeros(m.n_params)
+    params[:N ** 3] = (0.25 + 0.5 * vx + delta).ravel()
+    params[m.n_table:] = [1.0, 1.0]  # W1 = [[1]], W_out = [[1]]
+    mse = oracle.mse_grid(m, params, vol)
+    assert oracle.psnr_from_mse(mse) == pytest.approx(-20 * math.log10(delta), abs=1e-5)
+
+
+# ---------------------------------------------------------- renderer -----
+
+def _const_model():
+    m = oracle.Model(1, 1, 10, [5], 4, 1)
+    return m, np.zeros(m.n_params)  # all weights 0 -> Phi = 0 everywhere
+
+
+def test_ray_count_axis_aligned():
+    # every pixel looks along +z through the cube: t in [1, 2], 1024 steps of 2^-10
+    cam = np.array([0.3, 0.6, -1.0, 0, 0, 0, 0, 0, 0, 0, 0, 1], np.float32)
+    for seed in range(5):
+        n = oracle.ray_counts(cam, 8, 8, seed, 2.0 ** -10)
+        assert np.all(n == 1024)
+    cam_miss = np.array([1.5, 0.6, -1.0, 0, 0, 0, 0, 0, 0, 0, 0, 1], np.float32)
+    assert np.all(oracle.ray_counts(cam_miss, 4, 4, 0, 2.0 ** -10) == 0)
+
+
+def test_render_constant_alpha_closed_form():
+    m, params = _const_model()
+    lut = np.zeros((256, 4), np.float32)
+    lut[:] = [0.2, 0.4, 0.8, 0.05]
+    cam = np.array([0.3, 0.6, -1.0, 0, 0, 0, 0, 0, 0, 0, 0, 1], np.float32)
+    rgba, ng, nu = oracle.render_pixels(m, params, cam, lut, 4, 4, 2.0 ** -10, 3, np.arange(16))
+    n_stop = math.ceil(math.log(0.01) / math.log(0.95))
+    assert n_stop == 90
+    assert np.all(ng == 1024) and np.all(nu == n_stop)
+    a = float(np.float32(0.05))  # the table holds binary32 alpha
+    A = 1 - (1 - a) ** n_stop
+    np.testing.assert_allclose(rgba[:, 3], A, rtol=1e-13)
+    np.testing.assert_allclose(rgba[:, :3], np.broadcast_to(np.array([0.2, 0.4, 0.8], np.float32) * A, (16, 3)),
+                               rtol=1e-7)
+    # short rays (fewer samples than needed to stop): A = 1 - (1-a)^n
+    cam2 = np.array([0.3, 0.6, 0.96, 0, 0, 0, 0, 0, 0, 0, 0, 1], np.float32)  # 40/1024 of the cube left
+    rgba2, ng2, nu2 = oracle.render_pixels(m, params, cam2, lut, 2, 2, 2.0 ** -10, 0, np.arange(4))
+    assert np.all(nu2 == ng2)
+    for q in range(4):
+        np.testing.assert_allclose(rgba2[q, 3], 1 - (1 - a) ** int(ng2[q]), rtol=1e-13)
