@@ -599,8 +599,12 @@ static orc_ray orc_make_ray(const float* cam, int W, int px, int py, uint32_t fr
     if (tn < tmax) {
         float span = tmax - tn;
         float q = span / dt;
-        float c = ceilf(q - r.j);
-        if (c > 0.0f) r.n = (uint32_t)c;
+        /* a chord of the unit cube is at most sqrt(3) long: a ray with more
+         * than 2^24 steps (or a NaN span) is degenerate and gets no samples */
+        if (q <= 16777216.0f) {
+            float c = ceilf(q - r.j);
+            if (c > 0.0f) r.n = (uint32_t)c;
+        }
     }
     return r;
 }
