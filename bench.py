@@ -1,0 +1,230 @@
+#!/usr/bin/env python3
+"""Benchmark of the neural-volume hot path on one MI355X.
+
+One step = one training step (sampling step, encode+MLP forward, L2 loss,
+backward with recompute, Adam; batch 2^18 on a 512^3 fractal-noise target)
+plus one batch query of the model being trained (2^24 random coordinates),
+both in the BF16-MFMA form with FP16 hash features and FP32 masters.  The
+metric is encode+MLP samples/s over the whole step: (2^18 + 2^24) / step
+time.  Inputs are synthetic and resident in HBM before timing starts.
+
+Also reported: the same two legs in the plain FP32 form, the PSNR of both
+forms after identical training (quality leg), the roofline of the query
+kernel (measured with events on the launch stream) and the FP64 CPU oracle
+timed on a bounded sample of the same workload.
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "encode+MLP samples/s (infer, train) BF16-MFMA vs FP32 at ≤0.5 dB PSNR loss"
+SEED = 2207_11620
+
+# the query/training model: 16 levels 16 -> 2048, F = 2, 2^19 entries, 32-64-64-1
+MODEL = dict(n_levels=16, n_features=2, log2_hashmap_size=19, base_resolution=16, max_resolution=2048,
+             n_neurons=64, n_hidden_layers=2)
+N_QUERY = 1 << 24
+B_TRAIN = 1 << 18
+VOL_D = 512
+ADAM = dict(lr=1e-2, betas=(0.9, 0.99), eps=1e-15)
+LOSS_SCALE = 128.0
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--quality-steps", type=int, default=2000)
+    ap.add_argument("--no-quality", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--out", default=None, help="also write the JSON line to this file")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU only; --gpus N > 1 is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2207_11620_amd as ngv
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+
+    # ---------------------------------------------------------------- inputs
+    t0 = time.time()
+    plan16 = ngv.Plan(**MODEL, precision="bf16")
+    plan32 = ngv.Plan(**MODEL, precision="fp32")
+    p0 = synth.init_params(plan16.n_table_params, plan16.n_input, MODEL["n_neurons"], MODEL["n_hidden_layers"],
+                           1e-2, SEED)
+    xyz_h = synth.query_coords(N_QUERY, SEED)
+    vol_h = synth.fractal_value_noise(VOL_D, SEED)
+    log(f"inputs generated in {time.time() - t0:.1f}s")
+    params0 = torch.from_numpy(p0).to(dev)
+    xyz = torch.from_numpy(xyz_h).to(dev)
+    vol = torch.from_numpy(vol_h).to(dev)
+    out = torch.empty(N_QUERY, dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    # ------------------------------------------------- timed BF16 step loop
+    st = ngv.TrainState(plan16, params0, B_TRAIN, f16_tables=True)
+    step_idx = 0
+
+    def step(rec=None):
+        nonlocal step_idx
+        if rec:
+            rec[0].record()
+        ngv.train_step(st, volume=vol, seed=SEED, step_index=step_idx, loss_scale=LOSS_SCALE, **ADAM)
+        step_idx += 1
+        if rec:
+            rec[1].record()
+        ngv.infer(plan16, st.params, xyz, table_f16=st.table_f16, out=out)
+        if rec:
+            rec[2].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    recs = [(ev(), ev(), ev()) for _ in range(args.steps)]
+    start, stop = ev(), ev()
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    start.record()
+    for i in range(args.steps):
+        step(recs[i])
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = start.elapsed_time(stop)
+    ms_step = total_ms / args.steps
+    train_ms = sum(r[0].elapsed_time(r[1]) for r in recs) / args.steps
+    infer_ms = sum(r[1].elapsed_time(r[2]) for r in recs) / args.steps
+    value = (B_TRAIN + N_QUERY) / (ms_step * 1e-3)
+    log(f"bf16 step {ms_step:.3f} ms (train {train_ms:.3f}, infer {infer_ms:.3f}); wall {wall:.2f}s")
+
+    # ------------------------------------------------------ FP32 plain form
+    fp32 = None
+    if not args.no_fp32:
+        st32 = ngv.TrainState(plan32, params0, B_TRAIN, f16_tables=False)
+        reps = max(3, min(args.steps, 10))
+        for s in range(2):
+            ngv.train_step(st32, volume=vol, seed=SEED, step_index=s, loss_scale=1.0, **ADAM)
+            ngv.infer(plan32, st32.params, xyz, out=out)
+        torch.cuda.synchronize()
+        e = [ev() for _ in range(3)]
+        e[0].record()
+        for s in range(reps):
+            ngv.train_step(st32, volume=vol, seed=SEED, step_index=2 + s, loss_scale=1.0, **ADAM)
+        e[1].record()
+        for s in range(reps):
+            ngv.infer(plan32, st32.params, xyz, out=out)
+        e[2].record()
+        torch.cuda.synchronize()
+        t32 = e[0].elapsed_time(e[1]) / reps
+        i32 = e[1].elapsed_time(e[2]) / reps
+        fp32 = {"train_ms": round(t32, 4), "infer_ms": round(i32, 4),
+                "train_samples_per_s": B_TRAIN / (t32 * 1e-3), "infer_samples_per_s": N_QUERY / (i32 * 1e-3),
+                "step_samples_per_s": (B_TRAIN + N_QUERY) / ((t32 + i32) * 1e-3)}
+        del st32
+        log(f"fp32 train {t32:.3f} ms, infer {i32:.3f} ms")
+
+    # ------------------------------------------------------------ quality leg
+    quality = None
+    if not args.no_quality:
+        res = {}
+        for name, plan, f16, ls in (("bf16", plan16, True, LOSS_SCALE), ("fp32", plan32, False, 1.0)):
+            s = ngv.TrainState(plan, params0, B_TRAIN, f16_tables=f16)
+            q0 = time.perf_counter()
+            for k in range(args.quality_steps):
+                ngv.train_step(s, volume=vol, seed=SEED, step_index=k, loss_scale=ls, **ADAM)
+            torch.cuda.synchronize()
+            pr, tf = s.weights()
+            res[name] = ngv.psnr(plan, pr, vol, table_f16=tf)
+            log(f"quality {name}: {args.quality_steps} steps in {time.perf_counter() - q0:.1f}s, "
+                f"PSNR {res[name]:.3f} dB")
+            del s
+        quality = {"steps": args.quality_steps, "batch": B_TRAIN, "volume": f"{VOL_D}^3 fbm f32",
+                   "psnr_bf16_db": round(res["bf16"], 4), "psnr_fp32_db": round(res["fp32"], 4),
+                   "psnr_loss_db": round(res["fp32"] - res["bf16"], 4)}
+
+    # --------------------------------------------------------------- roofline
+    # query kernel: algorithmic bytes per query = L*8*F FP16 table reads + 12 B xyz + 4 B out
+    bytes_q = MODEL["n_levels"] * 8 * MODEL["n_features"] * 2 + 12 + 4
+    achieved = bytes_q * N_QUERY / (infer_ms * 1e-3) / 1e9
+    roofline = {"kernel": "k_infer (bf16 MLP, fp16 tables)", "bound": "hbm", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_query": bytes_q, "queries_per_launch": N_QUERY, "avg_launch_ms": round(infer_ms, 4)}
+
+    # ------------------------------------------------------------ CPU oracle
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        res_l = plan16.resolution
+        om = oracle.Model(MODEL["n_levels"], MODEL["n_features"], MODEL["log2_hashmap_size"], res_l,
+                          MODEL["n_neurons"], MODEL["n_hidden_layers"])
+        pd = p0.astype(np.float64)
+        nq, nb = 1 << 20, 1 << 16
+        c0 = time.perf_counter()
+        oracle.forward(om, pd, xyz_h[:nq])
+        t_inf = time.perf_counter() - c0
+        bx = oracle.batch_coords(SEED, 0, nb)
+        by = oracle.sample_volume(vol_h, bx)
+        c0 = time.perf_counter()
+        _, g = oracle.loss_grad(om, pd, bx, by)
+        t_lg = time.perf_counter() - c0
+        m_, v_ = np.zeros_like(pd), np.zeros_like(pd)
+        c0 = time.perf_counter()
+        oracle.adam(pd, m_, v_, g, 1, **{"lr": 1e-2, "b1": 0.9, "b2": 0.99, "eps": 1e-15})
+        t_adam = time.perf_counter() - c0
+        t_step = t_inf * (N_QUERY / nq) + t_lg * (B_TRAIN / nb) + t_adam
+        cpu = {"value": (B_TRAIN + N_QUERY) / t_step, "unit": "samples/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": f"FP64 oracle: query of {nq} of the 2^24 coordinates ({t_inf:.2f}s), loss+gradient of a "
+                         f"{nb}-sample batch ({t_lg:.2f}s) and one dense Adam update ({t_adam:.2f}s), scaled to "
+                         f"one step of 2^18 training + 2^24 query samples"}
+        log(f"cpu oracle: {cpu['value']:.3e} samples/s on {cpu['cores']} threads")
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "train step (B=2^18, 512^3 fbm target, L2, Adam) + query of 2^24 random coords",
+                   "model": "hash grid L16 F2 T2^19 N16..2048 + MLP 32-64-64-1",
+                   "global_batch": B_TRAIN, "queries": N_QUERY, "tables": "fp16 (fp32 masters)",
+                   "loss_scale": LOSS_SCALE},
+        "breakdown": {"train_ms": round(train_ms, 4), "infer_ms": round(infer_ms, 4),
+                      "train_samples_per_s": B_TRAIN / (train_ms * 1e-3),
+                      "infer_samples_per_s": N_QUERY / (infer_ms * 1e-3)},
+        "fp32_plain": fp32, "quality": quality, "roofline": roofline, "cpu_baseline": cpu,
+    }
+    s = json.dumps(line)
+    print(s, flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(s + "\n")
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,291 @@
+/*
+ * ngvol — querying and training a volumetric neural representation on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The representation is the paper's Phi: R^3 -> R (Section 3): a
+ * multi-resolution hash-grid encoding (Section 3.1, Fig. 1B) feeding a tiny
+ * bias-free ReLU MLP.  This library evaluates it (forward, for batch queries
+ * and for the sample-streaming ray marcher of Section 5.2.1), differentiates
+ * it, and runs the training step of Section 4 (sampling step, loss, backward,
+ * Adam) — all on the GPU, as hand-written HIP kernels.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Status: every call returns NGVOL_OK (0) or a negative NGVOL_E* code;
+ *   ngvol_last_error() gives a message for the calling thread.  Arguments are
+ *   validated on the host before anything is launched; a failing call has
+ *   launched nothing.  No C++ exception crosses this interface.
+ * Memory: every pointer named d_* or documented as "device" is device memory
+ *   owned by the caller; the library allocates no device memory in any call
+ *   (workspaces are passed in).  Parameter vectors, FP16 tables, feature
+ *   inputs of ngvol_mlp_fwd, volumes, the transfer-function table, images,
+ *   counters and workspaces must be 16-byte aligned; coordinate, target,
+ *   output and gradient buffers 4-byte aligned.  The library owns only the
+ *   host-side plan.
+ * Streams: calls enqueue work on the given hipStream_t (NULL = the legacy
+ *   default stream) and return without synchronising, unless stated.
+ * Plans: a plan is immutable after creation and may be shared between
+ *   threads; calls that write the same output buffers must not overlap.
+ * n = 0 is a no-op that returns NGVOL_OK.
+ * Coordinates are clamped to [0,1] before use; a NaN coordinate is treated
+ *   as 0.
+ *
+ * Parameter vector (FP32 master, n_params floats)
+ * ----------------------------------------------
+ *   [ level 0 table | level 1 table | ... | W_0 | W_1 | ... | W_out ]
+ * Level l has N_l vertices per axis spanning [0,1]; its table holds
+ * T_l = min(2^log2T, N_l^3) entries of F features, entry-major ([T_l][F]).
+ * A level with N_l^3 <= 2^log2T is dense (slot = vx + N_l (vy + N_l vz));
+ * otherwise the slot is the spatial hash of the encoding the paper adopts
+ * (vx*1 XOR vy*2654435761 XOR vz*805459861, mod 2^32, then mod 2^log2T).
+ * The MLP matrices follow, row-major [out][in], without biases or padding:
+ * W_0 [width][L*F], then (n_hidden-1) x [width][width], then W_out [1][width].
+ * The optional FP16 table copy has the table part's order (n_table_params
+ * halves).
+ */
+#ifndef NGVOL_H
+#define NGVOL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NGVOL_OK 0
+#define NGVOL_EINVAL (-1)       /* bad argument (shape, pointer, alignment, size) */
+#define NGVOL_ENOMEM (-2)       /* host allocation failed, or workspace too small */
+#define NGVOL_EDEVICE (-3)      /* a HIP runtime call failed */
+#define NGVOL_EUNSUPPORTED (-4) /* valid but unsupported combination (e.g. width 48) */
+
+#define NGVOL_MAX_LEVELS 32
+#define NGVOL_MAX_LAYERS 9
+
+/* MLP arithmetic of a plan. */
+#define NGVOL_FP32 0 /* FP32 operands on the matrix cores (v_mfma_f32_16x16x4_f32) */
+#define NGVOL_BF16 1 /* BF16 operands on MFMA with FP32 accumulation */
+
+/* Element types of volumes and feature buffers. */
+#define NGVOL_DT_F32 0
+#define NGVOL_DT_F16 1
+#define NGVOL_DT_BF16 2
+
+typedef struct ngvol_plan ngvol_plan;
+
+/*
+ * Model configuration (Section 3.1; hyper-parameter names follow the
+ * configuration listings of the paper's appendix).
+ * Supported: 1 <= n_levels <= 32; n_features in {2,4,8};
+ * n_levels * n_features <= 64; 1 <= log2_hashmap_size <= 28;
+ * n_neurons in {32,64}; 1 <= n_hidden_layers <= 8; the weights of a
+ * forward must fit in LDS and the backward (ngvol_mlp_bwd,
+ * ngvol_train_step) needs W, W^T and dW in LDS (else NGVOL_EUNSUPPORTED).
+ * Vertices per axis: resolutions[l] if given; else N_l = base * b^l, used as
+ * is when it is an integer (within 1e-9 relative) and rounded up otherwise,
+ * with b = per_level_scale, or b = exp((ln max_resolution - ln base)/(L-1))
+ * when max_resolution > 0.  Every N_l must be in [2, 65536].
+ */
+typedef struct ngvol_config {
+    int32_t n_levels;
+    int32_t n_features;
+    int32_t log2_hashmap_size;
+    int32_t base_resolution;
+    double per_level_scale;
+    int32_t max_resolution;
+    const int32_t* resolutions; /* host pointer, optional */
+    int32_t n_neurons;
+    int32_t n_hidden_layers;
+    int32_t precision; /* NGVOL_FP32 | NGVOL_BF16 */
+} ngvol_config;
+
+/* Derived layout of a plan (host struct filled by ngvol_get_layout). */
+typedef struct ngvol_layout {
+    int32_t n_levels, n_features, n_input, n_neurons, n_hidden_layers, precision;
+    int32_t resolution[NGVOL_MAX_LEVELS];
+    int32_t dense[NGVOL_MAX_LEVELS];
+    int64_t level_entries[NGVOL_MAX_LEVELS];
+    int64_t level_offset[NGVOL_MAX_LEVELS + 1]; /* in entries; times F gives floats */
+    int64_t n_table_params;
+    int64_t n_mlp_params;
+    int64_t n_params;
+    int64_t layer_offset[NGVOL_MAX_LAYERS]; /* offset of each matrix in the parameter vector */
+} ngvol_layout;
+
+/* Weights used by forward calls.  table_f16 (optional) is an FP16 copy of
+ * the table part; when non-NULL the encoding gathers it instead of the FP32
+ * tables (the MLP always reads the FP32 matrices). */
+typedef struct ngvol_weights {
+    const float* params;       /* device [n_params] */
+    const uint16_t* table_f16; /* device [n_table_params] or NULL */
+} ngvol_weights;
+
+/* Training state (all device memory).  grad must be all zero before the
+ * first step; every step leaves it zero again.  m and v start at zero. */
+typedef struct ngvol_train_state {
+    float* params;       /* [n_params] FP32 master */
+    uint16_t* table_f16; /* [n_table_params] FP16 shadow, or NULL */
+    float* grad;         /* [n_params] */
+    float* adam_m;       /* [n_params] */
+    float* adam_v;       /* [n_params] */
+    int64_t* step;       /* [1] number of applied (not skipped) Adam steps */
+    int32_t* skipped;    /* [1] 1 if the last step was skipped (non-finite gradient) */
+    double* loss;        /* [1] mean loss of the last step (unscaled) */
+    void* workspace;     /* ngvol_train_workspace_bytes(plan, B) bytes */
+    size_t workspace_bytes;
+} ngvol_train_state;
+
+/* One training batch (Section 4, the sampling step).  Either explicit
+ * samples (xyz != NULL: coordinates and targets given), or generated on the
+ * device: coordinate axis a of sample i is the binary32 uniform
+ * (r >> 40) * 2^-24 of counter-based SplitMix64 output r for (seed, stream 3,
+ * index = step_index*B*3 + 3*i + a), and its target is the cell-centred
+ * trilinear, clamp-to-edge sample of the volume (voxel i centred at
+ * (i+1/2)/D, x fastest). */
+typedef struct ngvol_batch {
+    int64_t batch_size;
+    const float* xyz;    /* device [B][3] or NULL */
+    const float* target; /* device [B] (when xyz != NULL) */
+    const void* volume;  /* device [Dz][Dy][Dx] (when xyz == NULL) */
+    int32_t dims[3];     /* Dx, Dy, Dz, each >= 2 */
+    int32_t volume_dtype; /* NGVOL_DT_F32 | NGVOL_DT_F16 */
+    uint64_t seed;       /* < 2^56 */
+    int64_t step_index;
+} ngvol_batch;
+
+/* Adam (Kingma and Ba) with bias correction; the paper trains with Adam
+ * (Section 3.1).  Gradients are divided by loss_scale before use; if any
+ * unscaled contribution is non-finite the whole step is skipped. */
+typedef struct ngvol_adam {
+    double learning_rate, beta1, beta2, epsilon;
+} ngvol_adam;
+
+/* Pinhole camera: the unnormalised direction through pixel centre (px,py)
+ * is (dir00 + (px+1/2) du) + (py+1/2) dv, evaluated in binary32. */
+typedef struct ngvol_camera {
+    float origin[3];
+    float du[3];
+    float dv[3];
+    float dir00[3];
+} ngvol_camera;
+
+/* Counters a render call writes to device memory (optional). */
+typedef struct ngvol_render_counters {
+    unsigned long long samples_evaluated; /* network samples computed */
+    unsigned long long samples_used;      /* samples composited before termination */
+    unsigned long long rays;              /* rays with at least one sample */
+    unsigned long long pad;
+} ngvol_render_counters;
+
+/* ----------------------------------------------------------------------- */
+const char* ngvol_last_error(void);
+const char* ngvol_version(void);
+
+/* Create / destroy a plan.  EINVAL for out-of-range fields, EUNSUPPORTED for
+ * valid but unsupported widths or feature counts. */
+int ngvol_plan_create(const ngvol_config* cfg, ngvol_plan** out);
+int ngvol_plan_destroy(ngvol_plan* plan);
+int ngvol_get_layout(const ngvol_plan* plan, ngvol_layout* out);
+
+/* Encoding (Section 3.1): feat[n][L*F] (FP32, device) = concatenation over
+ * levels of the trilinear interpolation of the 8 enclosing vertices'
+ * features. */
+int ngvol_encode(const ngvol_plan* plan, const ngvol_weights* w, const float* d_xyz, int64_t n, float* d_feat,
+                 hipStream_t stream);
+
+/* Corner slots and weights of the encoding: idx[n][L][8] (slot within the
+ * level's table, no level offset) and w[n][L][8]; corner k has offset
+ * (k&1, (k>>1)&1, (k>>2)&1).  Either output may be NULL. */
+int ngvol_encode_debug(const ngvol_plan* plan, const float* d_xyz, int64_t n, uint32_t* d_idx, float* d_w,
+                       hipStream_t stream);
+
+/* MLP forward (Section 3.1) on given features: out[n] (FP32) from
+ * feat[n][L*F] of type feat_dtype (NGVOL_DT_F32 or NGVOL_DT_BF16), with the
+ * plan's precision. */
+int ngvol_mlp_fwd(const ngvol_plan* plan, const float* d_params, const void* d_feat, int32_t feat_dtype, int64_t n,
+                  float* d_out, hipStream_t stream);
+
+/* Fused query: out[n] = Phi(xyz) (encoding + MLP in one kernel). */
+int ngvol_infer(const ngvol_plan* plan, const ngvol_weights* w, const float* d_xyz, int64_t n, float* d_out,
+                hipStream_t stream);
+
+/* MLP backward: given d_out[n] = dL/dout, adds dL/dW into the MLP part of
+ * d_grad (n_params floats, the table part is untouched) and, if
+ * d_dfeat != NULL, writes dL/dfeat [n][L*F].  The forward is recomputed from
+ * d_feat in the plan's precision (BF16 rounds the features first, as
+ * ngvol_mlp_fwd does).  Needs ngvol_mlp_bwd_workspace_bytes(plan, n) bytes
+ * of workspace. */
+int ngvol_mlp_bwd_workspace_bytes(const ngvol_plan* plan, int64_t n, size_t* bytes);
+int ngvol_mlp_bwd(const ngvol_plan* plan, const float* d_params, const float* d_feat, int64_t n, const float* d_dout,
+                  float* d_dfeat, float* d_grad, void* d_workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Encoding backward: accumulates grad_table[slot][f] += w_corner *
+ * dfeat[l*F+f] over all samples, levels and corners into d_grad (atomic,
+ * so the summation order is unspecified). */
+int ngvol_encode_bwd(const ngvol_plan* plan, const float* d_xyz, int64_t n, const float* d_dfeat, float* d_grad,
+                     hipStream_t stream);
+
+/* Sampling step alone: fills xyz[B][3] and target[B] as a generated batch
+ * would (batch->xyz must be NULL). */
+int ngvol_sample_batch(const ngvol_plan* plan, const ngvol_batch* batch, float* d_xyz, float* d_target,
+                       hipStream_t stream);
+
+/* Workspace a training step of batch B needs. */
+int ngvol_train_workspace_bytes(const ngvol_plan* plan, int64_t batch_size, size_t* bytes);
+
+/* One training step (Section 4): sampling, forward, mean-squared loss
+ * L = (1/B) sum (Phi(x)-y)^2, backward through the MLP (activations
+ * recomputed from the stored encoding) and the encoding, then Adam on all
+ * parameters; the FP16 shadow (if any) is refreshed by round-to-nearest-even
+ * from the master.  Gradients are formed at loss_scale times their value
+ * and divided by it in the update. */
+int ngvol_train_step(const ngvol_plan* plan, const ngvol_train_state* state, const ngvol_batch* batch,
+                     const ngvol_adam* adam, float loss_scale, hipStream_t stream);
+
+/* Adam update alone on state->grad (left zero afterwards). */
+int ngvol_adam_step(const ngvol_plan* plan, const ngvol_train_state* state, const ngvol_adam* adam, float loss_scale,
+                    hipStream_t stream);
+
+/* FP16 copy of the tables from FP32 parameters. */
+int ngvol_make_f16_tables(const ngvol_plan* plan, const float* d_params, uint16_t* d_table_f16, hipStream_t stream);
+
+/* Sum over all voxel centres (i+1/2)/D of (Phi - volume)^2, added to
+ * *d_sum_sq (device double).  MSE = sum / (Dx Dy Dz); PSNR = -10 log10 MSE
+ * for values normalised to [0,1] (Section 6). */
+int ngvol_sq_error_grid(const ngvol_plan* plan, const ngvol_weights* w, const void* d_volume, const int32_t dims[3],
+                        int32_t volume_dtype, double* d_sum_sq, hipStream_t stream);
+
+/* Workspace for ngvol_render (a few counters). */
+size_t ngvol_render_workspace_bytes(void);
+
+/*
+ * Ray-marched emission-absorption rendering through Phi (Section 5.2.1),
+ * sample streaming in one persistent launch: rays are taken from a device
+ * queue; each round a ray streams K = 8 sample coordinates, the network is
+ * evaluated on them, and the samples are shaded front to back; finished rays
+ * are replaced from the queue.
+ * Geometry in binary32 without FMA: d = dir/sqrt(dir.dir); slab test against
+ * [0,1]^3; t_near = max(t_min,0); n = max(0, ceil((t_max-t_near)/dt - j)) if
+ * t_near < t_max else 0; t_k = t_near + (k+j) dt; p_k = o + t_k d, with
+ * jitter j the binary32 uniform of (frame_seed, stream 5, pixel py*W+px).
+ * Shading: v = clamp(Phi,0,1); u = 255 v; i = min(floor(u),254);
+ * c = lut[i](1-(u-i)) + lut[i+1](u-i); C += (1-A) c.a c.rgb; A += (1-A) c.a;
+ * a ray stops after the sample at which A >= 0.99.
+ * rgba[H][W][4] FP32 (premultiplied colour, alpha); n_geo[H][W] (nullable):
+ * geometric sample counts n; n_used (nullable): samples composited;
+ * counters (nullable, device): totals.  lut: device [256][4].
+ */
+/* dt must be in [2^-20, 1]; a ray whose span exceeds 2^24 steps (only a
+ * degenerate camera can produce one) gets no samples. */
+int ngvol_render(const ngvol_plan* plan, const ngvol_weights* w, const ngvol_camera* cam, const float* d_lut,
+                 int32_t width, int32_t height, float dt, uint32_t frame_seed, float* d_rgba, uint32_t* d_n_geo,
+                 uint32_t* d_n_used, ngvol_render_counters* d_counters, void* d_workspace, size_t workspace_bytes,
+                 hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NGVOL_H */

@@ -1,0 +1,349 @@
+"""ngvol: neural-volume query and training on MI355X (gfx950).
+
+Thin Python binding of the C-ABI in ``include/ngvol.h`` (``libngvol.so``,
+built by ``python -m paper_2207_11620_amd.build``).  Every function marshals
+torch tensors into device pointers and the current HIP stream and calls the
+library; all arithmetic runs in the library's HIP kernels.  PyTorch supplies
+device memory and streams only.  There is no fallback: if the library is not
+built, or no GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libngvol.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -4
+FP32, BF16 = 0, 1
+DT_F32, DT_F16, DT_BF16 = 0, 1, 2
+MAX_LEVELS, MAX_LAYERS = 32, 9
+
+
+class NgvolError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ngvol error {code}: {msg}")
+        self.code = code
+
+
+# --------------------------------------------------------------------------
+# C structs (mirror include/ngvol.h)
+# --------------------------------------------------------------------------
+class Config(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("n_features", C.c_int32), ("log2_hashmap_size", C.c_int32),
+                ("base_resolution", C.c_int32), ("per_level_scale", C.c_double), ("max_resolution", C.c_int32),
+                ("resolutions", C.POINTER(C.c_int32)), ("n_neurons", C.c_int32), ("n_hidden_layers", C.c_int32),
+                ("precision", C.c_int32)]
+
+
+class Layout(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("n_features", C.c_int32), ("n_input", C.c_int32),
+                ("n_neurons", C.c_int32), ("n_hidden_layers", C.c_int32), ("precision", C.c_int32),
+                ("resolution", C.c_int32 * MAX_LEVELS), ("dense", C.c_int32 * MAX_LEVELS),
+                ("level_entries", C.c_int64 * MAX_LEVELS), ("level_offset", C.c_int64 * (MAX_LEVELS + 1)),
+                ("n_table_params", C.c_int64), ("n_mlp_params", C.c_int64), ("n_params", C.c_int64),
+                ("layer_offset", C.c_int64 * MAX_LAYERS)]
+
+
+class Weights(C.Structure):
+    _fields_ = [("params", C.c_void_p), ("table_f16", C.c_void_p)]
+
+
+class TrainStateC(C.Structure):
+    _fields_ = [("params", C.c_void_p), ("table_f16", C.c_void_p), ("grad", C.c_void_p), ("adam_m", C.c_void_p),
+                ("adam_v", C.c_void_p), ("step", C.c_void_p), ("skipped", C.c_void_p), ("loss", C.c_void_p),
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t)]
+
+
+class Batch(C.Structure):
+    _fields_ = [("batch_size", C.c_int64), ("xyz", C.c_void_p), ("target", C.c_void_p), ("volume", C.c_void_p),
+                ("dims", C.c_int32 * 3), ("volume_dtype", C.c_int32), ("seed", C.c_uint64),
+                ("step_index", C.c_int64)]
+
+
+class Adam(C.Structure):
+    _fields_ = [("learning_rate", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
+                ("epsilon", C.c_double)]
+
+
+class Camera(C.Structure):
+    _fields_ = [("origin", C.c_float * 3), ("du", C.c_float * 3), ("dv", C.c_float * 3), ("dir00", C.c_float * 3)]
+
+
+_P = C.c_void_p
+_SIGS = {
+    "ngvol_last_error": (C.c_char_p, []),
+    "ngvol_version": (C.c_char_p, []),
+    "ngvol_plan_create": (C.c_int, [C.POINTER(Config), C.POINTER(_P)]),
+    "ngvol_plan_destroy": (C.c_int, [_P]),
+    "ngvol_get_layout": (C.c_int, [_P, C.POINTER(Layout)]),
+    "ngvol_encode": (C.c_int, [_P, C.POINTER(Weights), _P, C.c_int64, _P, _P]),
+    "ngvol_encode_debug": (C.c_int, [_P, _P, C.c_int64, _P, _P, _P]),
+    "ngvol_mlp_fwd": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int64, _P, _P]),
+    "ngvol_infer": (C.c_int, [_P, C.POINTER(Weights), _P, C.c_int64, _P, _P]),
+    "ngvol_mlp_bwd_workspace_bytes": (C.c_int, [_P, C.c_int64, C.POINTER(C.c_size_t)]),
+    "ngvol_mlp_bwd": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P, _P, _P, C.c_size_t, _P]),
+    "ngvol_encode_bwd": (C.c_int, [_P, _P, C.c_int64, _P, _P, _P]),
+    "ngvol_sample_batch": (C.c_int, [_P, C.POINTER(Batch), _P, _P, _P]),
+    "ngvol_train_workspace_bytes": (C.c_int, [_P, C.c_int64, C.POINTER(C.c_size_t)]),
+    "ngvol_train_step": (C.c_int, [_P, C.POINTER(TrainStateC), C.POINTER(Batch), C.POINTER(Adam), C.c_float, _P]),
+    "ngvol_adam_step": (C.c_int, [_P, C.POINTER(TrainStateC), C.POINTER(Adam), C.c_float, _P]),
+    "ngvol_make_f16_tables": (C.c_int, [_P, _P, _P, _P]),
+    "ngvol_sq_error_grid": (C.c_int, [_P, C.POINTER(Weights), _P, C.POINTER(C.c_int32), C.c_int32, _P, _P]),
+    "ngvol_render_workspace_bytes": (C.c_size_t, []),
+    "ngvol_render": (C.c_int, [_P, C.POINTER(Weights), C.POINTER(Camera), _P, C.c_int32, C.c_int32, C.c_float,
+                               C.c_uint32, _P, _P, _P, _P, _P, C.c_size_t, _P]),
+}
+EXPORTED = tuple(_SIGS)
+
+_lib = None
+
+
+def lib():
+    """Load libngvol.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2207_11620_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != OK:
+        raise NgvolError(rc, lib().ngvol_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("ngvol needs device tensors")
+    if not t.is_contiguous():
+        raise ValueError("ngvol needs contiguous tensors")
+    return C.c_void_p(t.data_ptr())
+
+
+# --------------------------------------------------------------------------
+# Plan
+# --------------------------------------------------------------------------
+class Plan:
+    """Resolved model: hash grid (L levels, F features, 2^log2T entries) + MLP."""
+
+    def __init__(self, n_levels, n_features, log2_hashmap_size, base_resolution=16, per_level_scale=2.0,
+                 max_resolution=0, resolutions=None, n_neurons=64, n_hidden_layers=2, precision="fp32"):
+        prec = {"fp32": FP32, "bf16": BF16, FP32: FP32, BF16: BF16}[precision]
+        self._res = None
+        if resolutions is not None:
+            self._res = (C.c_int32 * len(resolutions))(*[int(r) for r in resolutions])
+        cfg = Config(n_levels, n_features, log2_hashmap_size, base_resolution, float(per_level_scale),
+                     int(max_resolution), C.cast(self._res, C.POINTER(C.c_int32)) if self._res else None,
+                     n_neurons, n_hidden_layers, prec)
+        h = C.c_void_p()
+        _check(lib().ngvol_plan_create(C.byref(cfg), C.byref(h)))
+        self.handle = h
+        lay = Layout()
+        _check(lib().ngvol_get_layout(h, C.byref(lay)))
+        L = lay.n_levels
+        self.n_levels, self.n_features, self.n_input = L, lay.n_features, lay.n_input
+        self.n_neurons, self.n_hidden_layers, self.precision = lay.n_neurons, lay.n_hidden_layers, lay.precision
+        self.resolution = list(lay.resolution[:L])
+        self.dense = [bool(d) for d in lay.dense[:L]]
+        self.level_entries = list(lay.level_entries[:L])
+        self.level_offset = list(lay.level_offset[:L + 1])
+        self.n_table_params, self.n_mlp_params, self.n_params = lay.n_table_params, lay.n_mlp_params, lay.n_params
+        self.layer_offset = list(lay.layer_offset[:lay.n_hidden_layers + 1])
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.ngvol_plan_destroy(h)
+            self.handle = None
+
+
+def _weights(params, table_f16=None):
+    return Weights(_ptr(params), _ptr(table_f16))
+
+
+def encode(plan, params, xyz, table_f16=None):
+    torch = _torch()
+    n = xyz.shape[0]
+    feat = torch.empty((n, plan.n_input), dtype=torch.float32, device=xyz.device)
+    w = _weights(params, table_f16)
+    _check(lib().ngvol_encode(plan.handle, C.byref(w), _ptr(xyz), n, _ptr(feat), _stream()))
+    return feat
+
+
+def encode_debug(plan, xyz):
+    torch = _torch()
+    n = xyz.shape[0]
+    idx = torch.empty((n, plan.n_levels, 8), dtype=torch.int32, device=xyz.device)
+    w = torch.empty((n, plan.n_levels, 8), dtype=torch.float32, device=xyz.device)
+    _check(lib().ngvol_encode_debug(plan.handle, _ptr(xyz), n, _ptr(idx), _ptr(w), _stream()))
+    return idx, w
+
+
+def mlp_fwd(plan, params, feat):
+    torch = _torch()
+    n = feat.shape[0]
+    dt = {torch.float32: DT_F32, torch.bfloat16: DT_BF16}[feat.dtype]
+    out = torch.empty(n, dtype=torch.float32, device=feat.device)
+    _check(lib().ngvol_mlp_fwd(plan.handle, _ptr(params), _ptr(feat), dt, n, _ptr(out), _stream()))
+    return out
+
+
+def infer(plan, params, xyz, table_f16=None, out=None):
+    torch = _torch()
+    n = xyz.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=xyz.device)
+    w = _weights(params, table_f16)
+    _check(lib().ngvol_infer(plan.handle, C.byref(w), _ptr(xyz), n, _ptr(out), _stream()))
+    return out
+
+
+def mlp_bwd(plan, params, feat, dout, grad, want_dfeat=True):
+    """Adds dL/dW into grad's MLP block; returns dL/dfeat (or None)."""
+    torch = _torch()
+    n = feat.shape[0]
+    nb = C.c_size_t()
+    _check(lib().ngvol_mlp_bwd_workspace_bytes(plan.handle, n, C.byref(nb)))
+    ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=feat.device)
+    dfeat = torch.empty((n, plan.n_input), dtype=torch.float32, device=feat.device) if want_dfeat else None
+    _check(lib().ngvol_mlp_bwd(plan.handle, _ptr(params), _ptr(feat), n, _ptr(dout), _ptr(dfeat), _ptr(grad),
+                               _ptr(ws), nb.value, _stream()))
+    return dfeat
+
+
+def encode_bwd(plan, xyz, dfeat, grad):
+    _check(lib().ngvol_encode_bwd(plan.handle, _ptr(xyz), xyz.shape[0], _ptr(dfeat), _ptr(grad), _stream()))
+
+
+def _volume_batch(volume, B, seed, step):
+    torch = _torch()
+    dt = {torch.float32: DT_F32, torch.float16: DT_F16}[volume.dtype]
+    Dz, Dy, Dx = volume.shape
+    return Batch(B, None, None, _ptr(volume), (C.c_int32 * 3)(Dx, Dy, Dz), dt, seed, step)
+
+
+def sample_batch(plan, volume, B, seed, step):
+    torch = _torch()
+    xyz = torch.empty((B, 3), dtype=torch.float32, device=volume.device)
+    y = torch.empty(B, dtype=torch.float32, device=volume.device)
+    b = _volume_batch(volume, B, seed, step)
+    _check(lib().ngvol_sample_batch(plan.handle, C.byref(b), _ptr(xyz), _ptr(y), _stream()))
+    return xyz, y
+
+
+def make_f16_tables(plan, params, out=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty(plan.n_table_params, dtype=torch.float16, device=params.device)
+    _check(lib().ngvol_make_f16_tables(plan.handle, _ptr(params), _ptr(out), _stream()))
+    return out
+
+
+class TrainState:
+    """Device buffers of a training run (FP32 master, optional FP16 table shadow)."""
+
+    def __init__(self, plan, params, batch_size, f16_tables=False):
+        torch = _torch()
+        dev = params.device
+        self.plan = plan
+        self.params = params.detach().clone().contiguous()
+        self.table_f16 = make_f16_tables(plan, self.params) if f16_tables else None
+        self.grad = torch.zeros_like(self.params)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.step = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.skipped = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        nb = C.c_size_t()
+        _check(lib().ngvol_train_workspace_bytes(plan.handle, batch_size, C.byref(nb)))
+        self.workspace = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+        self.batch_size = batch_size
+        self._c = TrainStateC(_ptr(self.params), _ptr(self.table_f16), _ptr(self.grad), _ptr(self.m), _ptr(self.v),
+                              _ptr(self.step), _ptr(self.skipped), _ptr(self.loss), _ptr(self.workspace), nb.value)
+
+    def weights(self):
+        return self.params, self.table_f16
+
+
+def train_step(state, volume=None, seed=0, step_index=0, xyz=None, target=None, lr=1e-2, betas=(0.9, 0.99),
+               eps=1e-15, loss_scale=1.0):
+    B = state.batch_size
+    if xyz is not None:
+        b = Batch(B, _ptr(xyz), _ptr(target), None, (C.c_int32 * 3)(0, 0, 0), 0, 0, 0)
+    else:
+        b = _volume_batch(volume, B, seed, step_index)
+    a = Adam(lr, betas[0], betas[1], eps)
+    _check(lib().ngvol_train_step(state.plan.handle, C.byref(state._c), C.byref(b), C.byref(a),
+                                  float(loss_scale), _stream()))
+
+
+def adam_step(state, lr=1e-2, betas=(0.9, 0.99), eps=1e-15, loss_scale=1.0):
+    a = Adam(lr, betas[0], betas[1], eps)
+    _check(lib().ngvol_adam_step(state.plan.handle, C.byref(state._c), C.byref(a), float(loss_scale), _stream()))
+
+
+def sq_error_grid(plan, params, volume, table_f16=None, out=None):
+    """Device FP64 sum of squared errors over all voxel centres."""
+    torch = _torch()
+    if out is None:
+        out = torch.zeros(1, dtype=torch.float64, device=volume.device)
+    dt = {torch.float32: DT_F32, torch.float16: DT_F16}[volume.dtype]
+    Dz, Dy, Dx = volume.shape
+    dims = (C.c_int32 * 3)(Dx, Dy, Dz)
+    w = _weights(params, table_f16)
+    _check(lib().ngvol_sq_error_grid(plan.handle, C.byref(w), _ptr(volume), dims, dt, _ptr(out), _stream()))
+    return out
+
+
+def psnr(plan, params, volume, table_f16=None):
+    import math
+    s = sq_error_grid(plan, params, volume, table_f16)
+    mse = float(s.item()) / volume.numel()
+    return -10.0 * math.log10(mse)
+
+
+def render(plan, params, cam, lut, width, height, dt, frame_seed, table_f16=None, want_counts=True,
+           rgba=None, workspace=None, counters=None):
+    """Returns (rgba [H][W][4], n_geo [H][W] or None, n_used or None, counters [4] int64)."""
+    torch = _torch()
+    dev = params.device
+    if rgba is None:
+        rgba = torch.empty((height, width, 4), dtype=torch.float32, device=dev)
+    n_geo = torch.empty((height, width), dtype=torch.int32, device=dev) if want_counts else None
+    n_used = torch.empty((height, width), dtype=torch.int32, device=dev) if want_counts else None
+    if workspace is None:
+        workspace = torch.empty(int(lib().ngvol_render_workspace_bytes()), dtype=torch.uint8, device=dev)
+    if counters is None:
+        counters = torch.zeros(4, dtype=torch.int64, device=dev)
+    c = [float(v) for v in cam]
+    camc = Camera((C.c_float * 3)(*c[0:3]), (C.c_float * 3)(*c[3:6]), (C.c_float * 3)(*c[6:9]),
+                  (C.c_float * 3)(*c[9:12]))
+    w = _weights(params, table_f16)
+    _check(lib().ngvol_render(plan.handle, C.byref(w), C.byref(camc), _ptr(lut), width, height, float(dt),
+                              frame_seed, _ptr(rgba), _ptr(n_geo), _ptr(n_used), _ptr(counters), _ptr(workspace),
+                              workspace.numel(), _stream()))
+    return rgba, n_geo, n_used, counters
+
+
+def version():
+    return lib().ngvol_version().decode()

@@ -1,0 +1,462 @@
+// C-ABI of libngvol: argument validation, plan construction and workspace
+// carve-up.  Every step of the computation runs in the kernels; this file
+// only checks arguments and enqueues launches.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <cmath>
+
+#include <new>
+#include <string>
+
+#include "kernels.hpp"
+
+using namespace ngvol;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return NGVOL_OK;
+  return fail(NGVOL_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+bool aligned4(const void* p) { return ((uintptr_t)p & 3u) == 0; }
+
+constexpr size_t kLdsBytes = 160 * 1024;  // LDS per workgroup on gfx950
+
+#define NGV_REQUIRE(cond, ...) \
+  do {                         \
+    if (!(cond)) return fail(NGVOL_EINVAL, __VA_ARGS__); \
+  } while (0)
+
+int check_plan(const ngvol_plan* p) {
+  if (!p) return fail(NGVOL_EINVAL, "plan is NULL");
+  return NGVOL_OK;
+}
+
+// Vertices per axis: N_l = base * b^l, kept when integral (1e-9 relative),
+// else rounded up; b from max_resolution when given.
+int resolve_resolutions(const ngvol_config* c, int32_t* out) {
+  if (c->resolutions) {
+    for (int l = 0; l < c->n_levels; ++l) out[l] = c->resolutions[l];
+    return NGVOL_OK;
+  }
+  double b = c->per_level_scale;
+  if (c->max_resolution > 0)
+    b = c->n_levels > 1 ? exp((log((double)c->max_resolution) - log((double)c->base_resolution)) / (c->n_levels - 1))
+                        : 1.0;
+  if (!(b >= 1.0) || !std::isfinite(b)) return fail(NGVOL_EINVAL, "per-level scale must be >= 1 (got %g)", b);
+  for (int l = 0; l < c->n_levels; ++l) {
+    const double r = (double)c->base_resolution * pow(b, (double)l);
+    const double rr = floor(r + 0.5);
+    const double v = fabs(r - rr) < 1e-9 * r ? rr : ceil(r);
+    if (v > 65536.0) return fail(NGVOL_EINVAL, "level %d resolution %g exceeds 65536", l, v);
+    out[l] = (int32_t)v;
+  }
+  return NGVOL_OK;
+}
+
+TablePtrs tables_of(const ngvol_plan* p, const ngvol_weights* w) {
+  TablePtrs t;
+  t.f32 = w->params;
+  t.f16 = reinterpret_cast<const __half*>(w->table_f16);
+  (void)p;
+  return t;
+}
+
+// The backward keeps W, W^T, dW and per-wave activations in LDS.
+int check_bwd_lds(const ngvol_plan* p) {
+  const size_t b = bwd_lds_bytes(p, 4);
+  if (b > kLdsBytes)
+    return fail(NGVOL_EUNSUPPORTED, "network too large for the LDS-resident backward (%zu > %zu bytes)", b, kLdsBytes);
+  return NGVOL_OK;
+}
+
+int check_weights(const ngvol_weights* w) {
+  NGV_REQUIRE(w && w->params, "weights or weights->params is NULL");
+  NGV_REQUIRE(aligned16(w->params) && aligned16(w->table_f16), "weights must be 16-byte aligned");
+  return NGVOL_OK;
+}
+
+}  // namespace
+
+namespace ngvol {
+
+TrainWorkspace train_workspace(const ngvol_plan* plan, int64_t B) {
+  TrainWorkspace ws;
+  auto up = [](size_t v) { return (v + 255) / 256 * 256; };
+  const size_t esz = plan->layout.precision ? 2 : 4;
+  ws.bwd_grid = bwd_grid(plan, B);
+  ws.e_off = 0;
+  ws.g_off = up((size_t)B * plan->kin * esz);
+  ws.partial_off = ws.g_off + up((size_t)B * 4);
+  ws.misc_off = ws.partial_off + up((size_t)ws.bwd_grid * plan->md.n_mlp * 4);
+  ws.total = ws.misc_off + 256;
+  return ws;
+}
+
+}  // namespace ngvol
+
+extern "C" {
+
+const char* ngvol_last_error(void) { return g_err.c_str(); }
+const char* ngvol_version(void) { return "ngvol 0.1 (gfx950)"; }
+
+int ngvol_plan_create(const ngvol_config* c, ngvol_plan** out) {
+  NGV_REQUIRE(c && out, "config and out must be non-NULL");
+  *out = nullptr;
+  NGV_REQUIRE(c->n_levels >= 1 && c->n_levels <= NGVOL_MAX_LEVELS, "n_levels must be in [1,%d]", NGVOL_MAX_LEVELS);
+  NGV_REQUIRE(c->n_features >= 1 && c->n_features <= 8, "n_features must be in [1,8]");
+  NGV_REQUIRE(c->log2_hashmap_size >= 1 && c->log2_hashmap_size <= 28, "log2_hashmap_size must be in [1,28]");
+  NGV_REQUIRE(c->resolutions || c->base_resolution >= 2, "base_resolution must be >= 2");
+  NGV_REQUIRE(c->n_hidden_layers >= 1 && c->n_hidden_layers <= NGVOL_MAX_LAYERS - 1, "n_hidden_layers must be in [1,%d]",
+              NGVOL_MAX_LAYERS - 1);
+  NGV_REQUIRE(c->n_neurons >= 1, "n_neurons must be positive");
+  NGV_REQUIRE(c->precision == NGVOL_FP32 || c->precision == NGVOL_BF16, "precision must be NGVOL_FP32 or NGVOL_BF16");
+  if (c->n_features != 2 && c->n_features != 4 && c->n_features != 8)
+    return fail(NGVOL_EUNSUPPORTED, "n_features %d unsupported (2, 4 or 8)", c->n_features);
+  if (c->n_neurons != 32 && c->n_neurons != 64)
+    return fail(NGVOL_EUNSUPPORTED, "n_neurons %d unsupported (32 or 64)", c->n_neurons);
+  const int n_in = c->n_levels * c->n_features;
+  if (n_in > 64) return fail(NGVOL_EUNSUPPORTED, "n_levels * n_features = %d exceeds 64", n_in);
+
+  int32_t res[NGVOL_MAX_LEVELS];
+  int rc = resolve_resolutions(c, res);
+  if (rc) return rc;
+  for (int l = 0; l < c->n_levels; ++l)
+    NGV_REQUIRE(res[l] >= 2 && res[l] <= 65536, "resolution of level %d (%d) must be in [2,65536]", l, res[l]);
+
+  ngvol_plan* p = new (std::nothrow) ngvol_plan;
+  if (!p) return fail(NGVOL_ENOMEM, "out of host memory");
+  memset(p, 0, sizeof *p);
+  ngvol_layout& L = p->layout;
+  ModelDesc& md = p->md;
+  const int64_t T = (int64_t)1 << c->log2_hashmap_size;
+  L.n_levels = md.L = c->n_levels;
+  L.n_features = md.F = c->n_features;
+  L.n_input = md.n_in = n_in;
+  L.n_neurons = md.width = c->n_neurons;
+  L.n_hidden_layers = md.n_hidden = c->n_hidden_layers;
+  L.precision = c->precision;
+  md.n_layers = md.n_hidden + 1;
+  int64_t off = 0;
+  for (int l = 0; l < md.L; ++l) {
+    const int64_t N = res[l];
+    const int64_t cube = N * N * N;
+    const bool dense = cube <= T;
+    const int64_t entries = dense ? cube : T;
+    L.resolution[l] = (int32_t)N;
+    L.dense[l] = dense;
+    L.level_entries[l] = entries;
+    L.level_offset[l] = off;
+    md.lv[l].N = (int32_t)N;
+    md.lv[l].dense = dense;
+    md.lv[l].offset = (uint32_t)off;
+    md.lv[l].mask = (uint32_t)(T - 1);
+    off += entries;
+  }
+  L.level_offset[md.L] = off;
+  if (off * md.F > ((int64_t)1 << 31)) {
+    delete p;
+    return fail(NGVOL_EUNSUPPORTED, "tables of %lld entries exceed 2^31 floats", (long long)off);
+  }
+  md.n_table = L.n_table_params = off * md.F;
+  int64_t pos = 0;
+  for (int i = 0; i < md.n_layers; ++i) {
+    const int in = i == 0 ? n_in : md.width;
+    const int outd = i == md.n_layers - 1 ? 1 : md.width;
+    md.w_off[i] = (int32_t)pos;
+    L.layer_offset[i] = md.n_table + pos;
+    pos += (int64_t)in * outd;
+  }
+  md.n_mlp = (int32_t)pos;
+  L.n_mlp_params = pos;
+  md.n_params = L.n_params = md.n_table + pos;
+  p->kin = n_in <= 32 ? 32 : 64;
+
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+  p->cus = cus;
+  p->device = dev;
+  if (fwd_lds_bytes(p) + 8192 > kLdsBytes) {
+    const size_t b = fwd_lds_bytes(p);
+    delete p;
+    return fail(NGVOL_EUNSUPPORTED, "network too large for LDS-resident weights (%zu bytes)", b);
+  }
+  *out = p;
+  return NGVOL_OK;
+}
+
+int ngvol_plan_destroy(ngvol_plan* plan) {
+  delete plan;
+  return NGVOL_OK;
+}
+
+int ngvol_get_layout(const ngvol_plan* plan, ngvol_layout* out) {
+  if (int rc = check_plan(plan)) return rc;
+  NGV_REQUIRE(out, "out is NULL");
+  *out = plan->layout;
+  return NGVOL_OK;
+}
+
+int ngvol_encode(const ngvol_plan* plan, const ngvol_weights* w, const float* xyz, int64_t n, float* feat,
+                 hipStream_t st) {
+  if (int rc = check_plan(plan)) return rc;
+  if (int rc = check_weights(w)) return rc;
+  NGV_REQUIRE(n >= 0, "n must be >= 0");
+  if (n == 0) return NGVOL_OK;
+  NGV_REQUIRE(xyz && feat && aligned4(xyz) && aligned4(feat), "xyz and feat must be non-NULL and 4-byte aligned");
+  return hip_check(launch_encode(plan, tables_of(plan, w), xyz, n, feat, st), "encode launch");
+}
+
+int ngvol_encode_debug(const ngvol_plan* plan, const float* xyz, int64_t n, uint32_t* idx, float* w, hipStream_t st) {
+  if (int rc = check_plan(plan)) return rc;
+  NGV_REQUIRE(n >= 0, "n must be >= 0");
+  if (n == 0) return NGVOL_OK;
+  NGV_REQUIRE(xyz && aligned4(xyz) && aligned4(idx) && aligned4(w), "xyz must be non-NULL; buffers 4-byte aligned");
+  NGV_REQUIRE(n * plan->md.L < ((int64_t)1 << 31) * 256, "n too large");
+  return hip_check(launch_encode_debug(plan, xyz, n, idx, w, st), "encode_debug launch");
+}
+
+int ngvol_mlp_fwd(const ngvol_plan* plan, const float* params, const void* feat, int32_t dtype, int64_t n, float* out,
+                  hipStream_t st) {
+  if (int rc = check_plan(plan)) return rc;
+  NGV_REQUIRE(n >= 0, "n must be >= 0");
+  if (n == 0) return NGVOL_OK;
+  NGV_REQUIRE(params && feat && out && aligned16(params) && aligned16(feat) && aligned4(out),
+              "params and feat must be non-NULL and 16-byte aligned, out 4-byte aligned");
+  NGV_REQUIRE(dtype == NGVOL_DT_F32 || dtype == NGVOL_DT_BF16, "feat dtype must be NGVOL_DT_F32 or NGVOL_DT_BF16");
+  return hip_check(launch_mlp_fwd(plan, params + plan->md.n_table, feat, dtype, n, out, st), "mlp_fwd launch");
+}
+
+int ngvol_infer(const ngvol_plan* plan, const ngvol_weights* w, const float* xyz, int64_t n, float* out,
+                hipStream_t st) {
+  if (int rc = check_plan(plan)) return rc;
+  if (int rc = check_weights(w)) return rc;
+  NGV_REQUIRE(n >= 0, "n must be >= 0");
+  if (n == 0) return NGVOL_OK;
+  NGV_REQUIRE(xyz && out && aligned4(xyz) && aligned4(out), "xyz and out must be non-NULL and 4-byte aligned");
+  return hip_check(launch_infer(plan, tables_of(plan, w), w->params + plan->md.n_table, xyz, n, out, st),
+                   "infer launch");
+}
+
+int ngvol_mlp_bwd_workspace_bytes(const ngvol_plan* plan, int64_t n, size_t* bytes) {
+  if (int rc = check_plan(plan)) return rc;
+  NGV_REQUIRE(bytes && n >= 0, "bytes must be non-NULL and n >= 0");
+  *bytes = ((size_t)bwd_grid(plan, n) * plan->md.n_mlp * 4 + 255) / 256 * 256 + 256;
+  return NGVOL_OK;
+}
+
+int ngvol_mlp_bwd(const ngvol_plan* plan, const float* params, const float* feat, int64_t n, const float* dout,
+                  float* dfeat, float* grad, void* ws, size_t ws_bytes, hipStream_t st) {
+  if (int rc = check_plan(plan)) return rc;
+  NGV_REQUIRE(n >= 0, "n must be >= 0");
+  if (n == 0) return NGVOL_OK;
+  NGV_REQUIRE(params && feat && dout && grad && ws, "params, feat, dout, grad and workspace must be non-NULL");
+  NGV_REQUIRE(aligned16(params) && aligned4(feat) && aligned4(dout) && aligned4(grad) && aligned4(dfeat) &&
+                  aligned16(ws),
+              "params and workspace must be 16-byte aligned, other buffers 4-byte aligned");
+  if (int rc = check_bwd_lds(plan)) return rc;
+  size_t need = 0;
+  ngvol_mlp_bwd_workspace_bytes(plan, n, &need);
+  if (ws_bytes < need) return fail(NGVOL_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, need);
+  const int grid = bwd_grid(plan, n);
+  float* partial = reinterpret_cast<float*>(ws);
+  int32_t* flag = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(ws) + need - 256);
+  BatchArgs ba{};
+  ba.B = n;
+  hipError_t e = launch_bwd(plan, 1, params + plan->md.n_table, feat, dout, ba, grad, dfeat, partial, grid, flag, st);
+  if (e == hipSuccess) e = launch_reduce_partials(plan, partial, grid, grad, flag, st);
+  return hip_check(e, "mlp_bwd launch");
+}
+
+int ngvol_encode_bwd(const ngvol_plan* plan, const float* xyz, int64_t n, const float* dfeat, float* grad,
+                     hipStream_t st) {
+  if (int rc = check_plan(plan)) return rc;
+  NGV_REQUIRE(n >= 0, "n must be >= 0");
+  if (n == 0) return NGVOL_OK;
+  NGV_REQUIRE(xyz && dfeat && grad && aligned4(xyz) && aligned4(dfeat) && aligned4(grad),
+              "xyz, dfeat and grad must be non-NULL and 4-byte aligned");
+  return hip_check(launch_encode_bwd(plan, xyz, n, dfeat, grad, st), "encode_bwd launch");
+}
+
+static int resolve_batch(const ngvol_plan* plan, const ngvol_batch* b, BatchArgs& ba) {
+  (void)plan;
+  NGV_REQUIRE(b, "batch is NULL");
+  NGV_REQUIRE(b->batch_size > 0 && b->batch_size < ((int64_t)1 << 31), "batch_size must be in [1, 2^31)");
+  ba.B = b->batch_size;
+  ba.xyz = b->xyz;
+  ba.target = b->target;
+  ba.volume = b->volume;
+  ba.dims[0] = b->dims[0];
+  ba.dims[1] = b->dims[1];
+  ba.dims[2] = b->dims[2];
+  ba.vdtype = b->volume_dtype;
+  ba.seed = b->seed;
+  ba.step = b->step_index;
+  if (b->xyz) {
+    NGV_REQUIRE(b->target && aligned4(b->xyz) && aligned4(b->target),
+                "explicit batch needs 4-byte aligned xyz and target");
+  } else {
+    NGV_REQUIRE(b->volume && aligned16(b->volume), "generated batch needs a 16-byte aligned volume");
+    NGV_REQUIRE(b->dims[0] >= 2 && b->dims[1] >= 2 && b->dims[2] >= 2, "volume dims must be >= 2");
+    NGV_REQUIRE(b->volume_dtype == NGVOL_DT_F32 || b->volume_dtype == NGVOL_DT_F16, "volume dtype must be F32 or F16");
+    NGV_REQUIRE(b->seed < (1ull << 56), "seed must be < 2^56");
+    NGV_REQUIRE(b->step_index >= 0, "step_index must be >= 0");
+  }
+  return NGVOL_OK;
+}
+
+int ngvol_sample_batch(const ngvol_plan* plan, const ngvol_batch* b, float* xyz, float* y, hipStream_t st) {
+  if (int rc = check_plan(plan)) return rc;
+  BatchArgs ba{};
+  if (int rc = resolve_batch(plan, b, ba)) return rc;
+  NGV_REQUIRE(!b->xyz, "ngvol_sample_batch needs a generated batch (xyz == NULL)");
+  NGV_REQUIRE(xyz && y && aligned4(xyz) && aligned4(y), "outputs must be non-NULL and 4-byte aligned");
+  return hip_check(launch_sample_batch(ba, xyz, y, st), "sample_batch launch");
+}
+
+int ngvol_train_workspace_bytes(const ngvol_plan* plan, int64_t B, size_t* bytes) {
+  if (int rc = check_plan(plan)) return rc;
+  NGV_REQUIRE(bytes && B > 0, "bytes must be non-NULL and B > 0");
+  *bytes = train_workspace(plan, B).total;
+  return NGVOL_OK;
+}
+
+static int check_state(const ngvol_plan* plan, const ngvol_train_state* s) {
+  (void)plan;
+  NGV_REQUIRE(s, "state is NULL");
+  NGV_REQUIRE(s->params && s->grad && s->adam_m && s->adam_v && s->step && s->workspace,
+              "state needs params, grad, adam_m, adam_v, step and workspace");
+  NGV_REQUIRE(aligned16(s->params) && aligned16(s->grad) && aligned16(s->adam_m) && aligned16(s->adam_v) &&
+                  aligned16(s->table_f16) && aligned16(s->workspace),
+              "state buffers must be 16-byte aligned");
+  return NGVOL_OK;
+}
+
+static int check_adam(const ngvol_adam* a, float loss_scale) {
+  NGV_REQUIRE(a, "adam is NULL");
+  NGV_REQUIRE(a->learning_rate >= 0 && a->beta1 >= 0 && a->beta1 < 1 && a->beta2 >= 0 && a->beta2 < 1 &&
+                  a->epsilon >= 0,
+              "Adam hyper-parameters out of range");
+  NGV_REQUIRE(loss_scale > 0.0f && std::isfinite(loss_scale), "loss_scale must be positive and finite");
+  return NGVOL_OK;
+}
+
+int ngvol_train_step(const ngvol_plan* plan, const ngvol_train_state* s, const ngvol_batch* b, const ngvol_adam* a,
+                     float loss_scale, hipStream_t st) {
+  if (int rc = check_plan(plan)) return rc;
+  if (int rc = check_state(plan, s)) return rc;
+  if (int rc = check_adam(a, loss_scale)) return rc;
+  if (int rc = check_bwd_lds(plan)) return rc;
+  BatchArgs ba{};
+  if (int rc = resolve_batch(plan, b, ba)) return rc;
+  const TrainWorkspace ws = train_workspace(plan, ba.B);
+  if (s->workspace_bytes < ws.total)
+    return fail(NGVOL_ENOMEM, "workspace of %zu bytes < %zu needed", s->workspace_bytes, ws.total);
+  char* base = reinterpret_cast<char*>(s->workspace);
+  void* e_buf = base + ws.e_off;
+  float* g_buf = reinterpret_cast<float*>(base + ws.g_off);
+  float* partial = reinterpret_cast<float*>(base + ws.partial_off);
+  double* loss_acc = reinterpret_cast<double*>(base + ws.misc_off);
+  int32_t* flag = reinterpret_cast<int32_t*>(base + ws.misc_off + 8);
+  TablePtrs tp;
+  tp.f32 = s->params;
+  tp.f16 = reinterpret_cast<const __half*>(s->table_f16);
+  const float* mlp = s->params + plan->md.n_table;
+  const float gscale = (float)((double)loss_scale * 2.0 / (double)ba.B);
+  hipError_t e = launch_step_begin(loss_acc, flag, st);
+  if (e == hipSuccess) e = launch_train_fwd(plan, tp, mlp, ba, e_buf, g_buf, loss_acc, gscale, st);
+  if (e == hipSuccess) e = launch_bwd(plan, 0, mlp, e_buf, g_buf, ba, s->grad, nullptr, partial, ws.bwd_grid, flag, st);
+  if (e == hipSuccess) e = launch_reduce_partials(plan, partial, ws.bwd_grid, s->grad, flag, st);
+  AdamArgs aa{a->learning_rate, a->beta1, a->beta2, a->epsilon, 1.0f / loss_scale};
+  if (e == hipSuccess)
+    e = launch_adam(plan, s->params, reinterpret_cast<__half*>(s->table_f16), s->grad, s->adam_m, s->adam_v, s->step,
+                    flag, aa, st);
+  if (e == hipSuccess) e = launch_step_end(loss_acc, flag, s->step, s->skipped, s->loss, 1.0 / (double)ba.B, st);
+  return hip_check(e, "train_step launch");
+}
+
+int ngvol_adam_step(const ngvol_plan* plan, const ngvol_train_state* s, const ngvol_adam* a, float loss_scale,
+                    hipStream_t st) {
+  if (int rc = check_plan(plan)) return rc;
+  if (int rc = check_state(plan, s)) return rc;
+  if (int rc = check_adam(a, loss_scale)) return rc;
+  NGV_REQUIRE(s->workspace_bytes >= 256, "workspace must hold at least 256 bytes");
+  char* base = reinterpret_cast<char*>(s->workspace);
+  double* loss_acc = reinterpret_cast<double*>(base);
+  int32_t* flag = reinterpret_cast<int32_t*>(base + 8);
+  AdamArgs aa{a->learning_rate, a->beta1, a->beta2, a->epsilon, 1.0f / loss_scale};
+  hipError_t e = launch_step_begin(loss_acc, flag, st);
+  if (e == hipSuccess)
+    e = launch_adam(plan, s->params, reinterpret_cast<__half*>(s->table_f16), s->grad, s->adam_m, s->adam_v, s->step,
+                    flag, aa, st);
+  if (e == hipSuccess) e = launch_step_end(loss_acc, flag, s->step, s->skipped, nullptr, 1.0, st);
+  return hip_check(e, "adam launch");
+}
+
+int ngvol_make_f16_tables(const ngvol_plan* plan, const float* params, uint16_t* out, hipStream_t st) {
+  if (int rc = check_plan(plan)) return rc;
+  NGV_REQUIRE(params && out && aligned16(params) && aligned16(out), "params and out must be non-NULL, 16-byte aligned");
+  return hip_check(launch_make_f16(params, reinterpret_cast<__half*>(out), plan->md.n_table, st), "make_f16 launch");
+}
+
+int ngvol_sq_error_grid(const ngvol_plan* plan, const ngvol_weights* w, const void* vol, const int32_t dims[3],
+                        int32_t dtype, double* sq, hipStream_t st) {
+  if (int rc = check_plan(plan)) return rc;
+  if (int rc = check_weights(w)) return rc;
+  NGV_REQUIRE(vol && sq && dims && aligned16(vol), "volume, dims and output must be non-NULL");
+  NGV_REQUIRE(dims[0] >= 1 && dims[1] >= 1 && dims[2] >= 1, "dims must be positive");
+  NGV_REQUIRE(dtype == NGVOL_DT_F32 || dtype == NGVOL_DT_F16, "volume dtype must be F32 or F16");
+  return hip_check(launch_sq_error_grid(plan, tables_of(plan, w), w->params + plan->md.n_table, vol, dtype, dims, sq, st),
+                   "sq_error_grid launch");
+}
+
+size_t ngvol_render_workspace_bytes(void) { return 256; }
+
+int ngvol_render(const ngvol_plan* plan, const ngvol_weights* w, const ngvol_camera* cam, const float* lut, int32_t W,
+                 int32_t H, float dt, uint32_t seed, float* rgba, uint32_t* n_geo, uint32_t* n_used,
+                 ngvol_render_counters* counters, void* ws, size_t ws_bytes, hipStream_t st) {
+  if (int rc = check_plan(plan)) return rc;
+  if (int rc = check_weights(w)) return rc;
+  NGV_REQUIRE(cam && lut && rgba && ws, "camera, lut, rgba and workspace must be non-NULL");
+  NGV_REQUIRE(aligned16(lut) && aligned16(rgba) && aligned16(ws) && aligned4(n_geo) && aligned4(n_used) &&
+                  aligned16(counters),
+              "lut, rgba, counters and workspace must be 16-byte aligned, counts 4-byte aligned");
+  NGV_REQUIRE(W >= 1 && H >= 1 && (int64_t)W * H < ((int64_t)1 << 31), "image size out of range");
+  NGV_REQUIRE(dt >= 0x1p-20f && dt <= 1.0f, "dt must be in [2^-20, 1]");
+  NGV_REQUIRE(ws_bytes >= ngvol_render_workspace_bytes(), "render workspace too small");
+  RenderArgs ra;
+  memcpy(ra.cam, cam, sizeof ra.cam);
+  ra.lut = lut;
+  ra.width = W;
+  ra.height = H;
+  ra.dt = dt;
+  ra.seed = seed;
+  ra.rgba = rgba;
+  ra.n_geo = n_geo;
+  ra.n_used = n_used;
+  ra.queue = reinterpret_cast<unsigned int*>(ws);
+  ra.counters = reinterpret_cast<unsigned long long*>(counters);
+  return hip_check(launch_render(plan, tables_of(plan, w), w->params + plan->md.n_table, ra, st), "render launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,102 @@
+// Internal interface between the C-ABI layer and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#include "plan.hpp"
+
+namespace ngvol {
+
+// Table storage read by the encoding: FP16 copy if present, else FP32 master.
+struct TablePtrs {
+  const float* f32;
+  const __half* f16;
+};
+
+template <typename TT>
+__device__ __forceinline__ const TT* table_ptr(const TablePtrs& t);
+template <>
+__device__ __forceinline__ const float* table_ptr<float>(const TablePtrs& t) { return t.f32; }
+template <>
+__device__ __forceinline__ const __half* table_ptr<__half>(const TablePtrs& t) { return t.f16; }
+
+// A training batch, resolved for the kernels.
+struct BatchArgs {
+  int64_t B;
+  const float* xyz;     // explicit coordinates, or NULL to generate
+  const float* target;  // explicit targets
+  const void* volume;   // ground truth for generated batches
+  int32_t dims[3];
+  int32_t vdtype;
+  uint64_t seed;
+  int64_t step;
+};
+
+// Workspace carve-up of a training step (byte offsets).
+struct TrainWorkspace {
+  size_t e_off, g_off, partial_off, misc_off, total;
+  int bwd_grid;
+};
+
+size_t fwd_lds_bytes(const ngvol_plan* plan);
+size_t bwd_lds_bytes(const ngvol_plan* plan, int waves);
+int bwd_grid(const ngvol_plan* plan, int64_t n);
+TrainWorkspace train_workspace(const ngvol_plan* plan, int64_t B);
+
+hipError_t launch_encode(const ngvol_plan* plan, TablePtrs tp, const float* xyz, int64_t n, float* feat,
+                         hipStream_t st);
+hipError_t launch_encode_debug(const ngvol_plan* plan, const float* xyz, int64_t n, uint32_t* idx, float* w,
+                               hipStream_t st);
+hipError_t launch_infer(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const float* xyz, int64_t n,
+                        float* out, hipStream_t st);
+hipError_t launch_sq_error_grid(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const void* vol, int dtype,
+                                const int32_t dims[3], double* sq, hipStream_t st);
+hipError_t launch_mlp_fwd(const ngvol_plan* plan, const float* mlp, const void* feat, int dtype, int64_t n,
+                          float* out, hipStream_t st);
+hipError_t launch_train_fwd(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const BatchArgs& ba, void* e_buf,
+                            float* g_buf, double* loss_acc, float gscale, hipStream_t st);
+hipError_t launch_sample_batch(const BatchArgs& ba, float* xyz, float* y, hipStream_t st);
+
+// Backward.  MODE 0: training (e_buf holds the stored encoding in the
+// plan's precision, de is scattered into the table gradient; coordinates
+// from ba).  MODE 1: standalone MLP backward on FP32 features, writing
+// dfeat (nullable).  dW partial sums per block go to `partial`
+// ([grid][n_mlp]); launch_reduce_partials adds them into grad.
+hipError_t launch_bwd(const ngvol_plan* plan, int mode, const float* mlp, const void* e_buf, const float* g_buf,
+                      const BatchArgs& ba, float* grad, float* dfeat, float* partial, int grid, int32_t* nonfinite,
+                      hipStream_t st);
+hipError_t launch_reduce_partials(const ngvol_plan* plan, const float* partial, int grid, float* grad,
+                                  int32_t* nonfinite, hipStream_t st);
+hipError_t launch_encode_bwd(const ngvol_plan* plan, const float* xyz, int64_t n, const float* dfeat, float* grad,
+                             hipStream_t st);
+
+struct AdamArgs {
+  double lr, b1, b2, eps;
+  float inv_scale;
+};
+hipError_t launch_adam(const ngvol_plan* plan, float* params, __half* table_f16, float* grad, float* m, float* v,
+                       int64_t* step, const int32_t* nonfinite, const AdamArgs& a, hipStream_t st);
+hipError_t launch_step_begin(double* loss_acc, int32_t* nonfinite, hipStream_t st);
+hipError_t launch_step_end(const double* loss_acc, int32_t* nonfinite, int64_t* step, int32_t* skipped,
+                           double* loss_out, double inv_b, hipStream_t st);
+hipError_t launch_make_f16(const float* params, __half* out, int64_t n, hipStream_t st);
+
+struct RenderArgs {
+  float cam[12];
+  const float* lut;
+  int32_t width, height;
+  float dt;
+  uint32_t seed;
+  float* rgba;
+  uint32_t* n_geo;
+  uint32_t* n_used;
+  unsigned long long* counters;  // [4] in the workspace or caller's struct
+  unsigned int* queue;           // ray queue head
+};
+size_t render_lds_bytes(const ngvol_plan* plan, int waves);
+hipError_t launch_render(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const RenderArgs& ra,
+                         hipStream_t st);
+
+}  // namespace ngvol

@@ -1,0 +1,442 @@
+// Forward kernels: encoding, fused query, standalone MLP, training forward,
+// grid squared error, sampling step.
+#include "kernels.hpp"
+#include "mlp_tile.hpp"
+
+namespace ngvol {
+
+// ---------------------------------------------------------------------------
+// Persistent tile loop helpers.  A wave owns tiles wave_id, wave_id + n_waves,
+// ...; each tile is 16 samples, one per lane%16.
+// ---------------------------------------------------------------------------
+struct TileIter {
+  int64_t first, stride;
+  __device__ TileIter() {
+    const int wpb = blockDim.x >> 6;
+    first = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
+    stride = (int64_t)gridDim.x * wpb;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Standalone encoding: feat[n][n_in] FP32.
+// ---------------------------------------------------------------------------
+template <int F, int KIN, typename TT>
+__global__ void __launch_bounds__(256) k_encode(ModelDesc md, TablePtrs tp, const float* __restrict__ xyz, int64_t n,
+                                                float* __restrict__ feat) {
+  const TT* table = table_ptr<TT>(tp);
+  const int lane = threadIdx.x & 63, nl = lane & 15, g = lane >> 4;
+  TileIter it;
+  const int64_t n_tiles = (n + 15) >> 4;
+  for (int64_t t = it.first; t < n_tiles; t += it.stride) {
+    const int64_t s = t * 16 + nl;
+    if (s >= n) continue;
+    const float x = clamp01(xyz[3 * s]), y = clamp01(xyz[3 * s + 1]), z = clamp01(xyz[3 * s + 2]);
+    float f[KIN / 32][8];
+    encode_lane<F, KIN>(md, table, x, y, z, f);
+#pragma unroll
+    for (int b = 0; b < KIN / 32; ++b)
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) {
+        const int k = 32 * b + 8 * g + jj;
+        if (k < md.n_in) feat[s * md.n_in + k] = f[b][jj];
+      }
+  }
+}
+
+// Corner slots and weights: one thread per (sample, level).
+__global__ void __launch_bounds__(256) k_encode_debug(ModelDesc md, const float* __restrict__ xyz, int64_t n,
+                                                      uint32_t* __restrict__ idx, float* __restrict__ w) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * md.L) return;
+  const int64_t s = t / md.L;
+  const int l = (int)(t % md.L);
+  Corners cr;
+  level_corners(md.lv[l], clamp01(xyz[3 * s]), clamp01(xyz[3 * s + 1]), clamp01(xyz[3 * s + 2]), cr);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (idx) idx[t * 8 + k] = cr.slot[k] - md.lv[l].offset;
+    if (w) w[t * 8 + k] = cr.w[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused query.  MODE 0: out[s] = Phi(xyz[s]).  MODE 1: grid voxel centres,
+// accumulate (Phi - volume)^2 in FP64.
+// ---------------------------------------------------------------------------
+template <int P, int F, int KIN, int W, typename TT, int MODE, typename VT>
+__global__ void __launch_bounds__(256) k_infer(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp,
+                                               const float* __restrict__ xyz, int64_t n, float* __restrict__ out,
+                                               const VT* __restrict__ vol, int dx, int dy, int dz,
+                                               double* __restrict__ sq_sum) {
+  typedef typename Prec<P>::Frag Frag;
+  typedef WeightLayout<P, KIN, W> WL;
+  extern __shared__ __align__(16) unsigned char smem[];
+  Frag* lds_frag = reinterpret_cast<Frag*>(smem);
+  float* lds_wout = reinterpret_cast<float*>(smem + (size_t)WL::frags(md.n_hidden, false) * 64 * sizeof(Frag));
+  stage_weights<P, KIN, W>(md, mlp, lds_frag, lds_wout, false);
+  __syncthreads();
+
+  const TT* table = table_ptr<TT>(tp);
+  const int lane = threadIdx.x & 63, nl = lane & 15, g = lane >> 4;
+  double err = 0.0;
+  TileIter it;
+  const int64_t n_tiles = (n + 15) >> 4;
+  for (int64_t t = it.first; t < n_tiles; t += it.stride) {
+    const int64_t s = t * 16 + nl;
+    const bool valid = s < n;
+    float x, y, z;
+    if constexpr (MODE == 0) {
+      const int64_t sc = valid ? s : n - 1;
+      x = clamp01(xyz[3 * sc]);
+      y = clamp01(xyz[3 * sc + 1]);
+      z = clamp01(xyz[3 * sc + 2]);
+    } else {
+      const int64_t sc = valid ? s : n - 1;
+      const int64_t ix = sc % dx, iy = (sc / dx) % dy, iz = sc / ((int64_t)dx * dy);
+      x = ((float)ix + 0.5f) / (float)dx;
+      y = ((float)iy + 0.5f) / (float)dy;
+      z = ((float)iz + 0.5f) / (float)dz;
+    }
+    float f[KIN / 32][8];
+    encode_lane<F, KIN>(md, table, x, y, z, f);
+    Frag in[InChunks<P, KIN>::n];
+    feat_to_frag<P, KIN>(f, in);
+    f32x4 act[W / 16];
+    mlp_hidden_fwd<P, KIN, W, false>(md.n_hidden, lds_frag, in, act, nullptr);
+    const float yv = mlp_output<W>(act, lds_wout);
+    if (valid && g == 0) {
+      if constexpr (MODE == 0) {
+        out[s] = yv;
+      } else {
+        const double d = (double)yv - (double)load_vox<VT>(vol, (size_t)s);
+        err += d * d;
+      }
+    }
+  }
+  if constexpr (MODE == 1) {
+    err = wave_sum(err);
+    if (lane == 0 && err != 0.0) atomicAdd(sq_sum, err);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Standalone MLP on given features ([n][n_in], FP32 or BF16).
+// ---------------------------------------------------------------------------
+template <typename IT>
+__device__ __forceinline__ float load_feat(const IT* p, int64_t i);
+template <>
+__device__ __forceinline__ float load_feat<float>(const float* p, int64_t i) { return p[i]; }
+template <>
+__device__ __forceinline__ float load_feat<__bf16>(const __bf16* p, int64_t i) { return (float)p[i]; }
+
+template <int P, int KIN, int W, typename IT>
+__global__ void __launch_bounds__(256) k_mlp_fwd(ModelDesc md, const float* __restrict__ mlp,
+                                                 const IT* __restrict__ feat, int64_t n, float* __restrict__ out) {
+  typedef typename Prec<P>::Frag Frag;
+  typedef WeightLayout<P, KIN, W> WL;
+  extern __shared__ __align__(16) unsigned char smem[];
+  Frag* lds_frag = reinterpret_cast<Frag*>(smem);
+  float* lds_wout = reinterpret_cast<float*>(smem + (size_t)WL::frags(md.n_hidden, false) * 64 * sizeof(Frag));
+  stage_weights<P, KIN, W>(md, mlp, lds_frag, lds_wout, false);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, nl = lane & 15, g = lane >> 4;
+  const int n_in = md.n_in;
+  TileIter it;
+  const int64_t n_tiles = (n + 15) >> 4;
+  for (int64_t t = it.first; t < n_tiles; t += it.stride) {
+    const int64_t s = t * 16 + nl;
+    const bool valid = s < n;
+    const int64_t sc = valid ? s : n - 1;
+    float f[KIN / 32][8];
+    if constexpr (sizeof(IT) == 2) {
+      if (n_in == KIN) {
+        // 16-byte vector loads: 8 BF16 features per lane per block
+#pragma unroll
+        for (int b = 0; b < KIN / 32; ++b) {
+          const uint4 raw = *reinterpret_cast<const uint4*>(feat + sc * KIN + 32 * b + 8 * g);
+          const __bf16* h = reinterpret_cast<const __bf16*>(&raw);
+#pragma unroll
+          for (int jj = 0; jj < 8; ++jj) f[b][jj] = (float)h[jj];
+        }
+      } else {
+#pragma unroll
+        for (int b = 0; b < KIN / 32; ++b)
+#pragma unroll
+          for (int jj = 0; jj < 8; ++jj) {
+            const int k = 32 * b + 8 * g + jj;
+            f[b][jj] = k < n_in ? load_feat<IT>(feat, sc * n_in + k) : 0.0f;
+          }
+      }
+    } else {
+#pragma unroll
+      for (int b = 0; b < KIN / 32; ++b)
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) {
+          const int k = 32 * b + 8 * g + jj;
+          f[b][jj] = k < n_in ? load_feat<IT>(feat, sc * n_in + k) : 0.0f;
+        }
+    }
+    Frag in[InChunks<P, KIN>::n];
+    feat_to_frag<P, KIN>(f, in);
+    f32x4 act[W / 16];
+    mlp_hidden_fwd<P, KIN, W, false>(md.n_hidden, lds_frag, in, act, nullptr);
+    const float yv = mlp_output<W>(act, lds_wout);
+    if (valid && g == 0) out[s] = yv;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Training forward: sampling step (or explicit batch), encoding (stored for
+// the backward), MLP, loss, and g = S * dL/dy = S * 2 (y_hat - y) / B.
+// ---------------------------------------------------------------------------
+template <int P, int F, int KIN, int W, typename TT, typename VT>
+__global__ void __launch_bounds__(256) k_train_fwd(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp,
+                                                   BatchArgs ba, void* __restrict__ e_buf, float* __restrict__ g_buf,
+                                                   double* __restrict__ loss_acc, float gscale) {
+  typedef typename Prec<P>::Frag Frag;
+  typedef WeightLayout<P, KIN, W> WL;
+  extern __shared__ __align__(16) unsigned char smem[];
+  Frag* lds_frag = reinterpret_cast<Frag*>(smem);
+  float* lds_wout = reinterpret_cast<float*>(smem + (size_t)WL::frags(md.n_hidden, false) * 64 * sizeof(Frag));
+  stage_weights<P, KIN, W>(md, mlp, lds_frag, lds_wout, false);
+  __syncthreads();
+
+  const TT* table = table_ptr<TT>(tp);
+  const VT* vol = reinterpret_cast<const VT*>(ba.volume);
+  const int lane = threadIdx.x & 63, nl = lane & 15, g = lane >> 4;
+  const int64_t B = ba.B;
+  double lsum = 0.0;
+  TileIter it;
+  const int64_t n_tiles = (B + 15) >> 4;
+  for (int64_t t = it.first; t < n_tiles; t += it.stride) {
+    const int64_t s = t * 16 + nl;
+    const bool valid = s < B;
+    const int64_t sc = valid ? s : B - 1;
+    float x, y, z, target;
+    if (ba.xyz) {
+      x = clamp01(ba.xyz[3 * sc]);
+      y = clamp01(ba.xyz[3 * sc + 1]);
+      z = clamp01(ba.xyz[3 * sc + 2]);
+      target = ba.target[sc];
+    } else {
+      x = batch_coord(ba.seed, ba.step, B, sc, 0);
+      y = batch_coord(ba.seed, ba.step, B, sc, 1);
+      z = batch_coord(ba.seed, ba.step, B, sc, 2);
+      target = volume_sample<VT>(vol, ba.dims[0], ba.dims[1], ba.dims[2], x, y, z);
+    }
+    float f[KIN / 32][8];
+    encode_lane<F, KIN>(md, table, x, y, z, f);
+    if (valid) {
+      if constexpr (P) {
+#pragma unroll
+        for (int b = 0; b < KIN / 32; ++b) {
+          bf16x8 v;
+#pragma unroll
+          for (int jj = 0; jj < 8; ++jj) v[jj] = (__bf16)f[b][jj];
+          *reinterpret_cast<bf16x8*>(reinterpret_cast<__bf16*>(e_buf) + sc * KIN + 32 * b + 8 * g) = v;
+        }
+      } else {
+#pragma unroll
+        for (int b = 0; b < KIN / 32; ++b) {
+          float* dst = reinterpret_cast<float*>(e_buf) + sc * KIN + 32 * b + 8 * g;
+          *reinterpret_cast<float4*>(dst) = make_float4(f[b][0], f[b][1], f[b][2], f[b][3]);
+          *reinterpret_cast<float4*>(dst + 4) = make_float4(f[b][4], f[b][5], f[b][6], f[b][7]);
+        }
+      }
+    }
+    Frag in[InChunks<P, KIN>::n];
+    feat_to_frag<P, KIN>(f, in);
+    f32x4 act[W / 16];
+    mlp_hidden_fwd<P, KIN, W, false>(md.n_hidden, lds_frag, in, act, nullptr);
+    const float yv = mlp_output<W>(act, lds_wout);
+    if (valid && g == 0) {
+      const float r = yv - target;
+      g_buf[s] = gscale * r;
+      lsum += (double)r * (double)r;
+    }
+  }
+  lsum = wave_sum(lsum);
+  if (lane == 0 && lsum != 0.0) atomicAdd(loss_acc, lsum);
+}
+
+// ---------------------------------------------------------------------------
+// Sampling step alone.
+// ---------------------------------------------------------------------------
+template <typename VT>
+__global__ void __launch_bounds__(256) k_sample_batch(BatchArgs ba, float* __restrict__ xyz, float* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ba.B) return;
+  const float a = batch_coord(ba.seed, ba.step, ba.B, i, 0);
+  const float b = batch_coord(ba.seed, ba.step, ba.B, i, 1);
+  const float c = batch_coord(ba.seed, ba.step, ba.B, i, 2);
+  xyz[3 * i] = a;
+  xyz[3 * i + 1] = b;
+  xyz[3 * i + 2] = c;
+  y[i] = volume_sample<VT>(reinterpret_cast<const VT*>(ba.volume), ba.dims[0], ba.dims[1], ba.dims[2], a, b, c);
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (dispatch over the compile-time shapes).
+// ---------------------------------------------------------------------------
+#define NGV_DISPATCH_F_KIN(F_, KIN_, ...)                                    \
+  switch (F_ * 1000 + KIN_) {                                                \
+    case 2032: { constexpr int F = 2, KIN = 32; __VA_ARGS__; } break;        \
+    case 2064: { constexpr int F = 2, KIN = 64; __VA_ARGS__; } break;        \
+    case 4032: { constexpr int F = 4, KIN = 32; __VA_ARGS__; } break;        \
+    case 4064: { constexpr int F = 4, KIN = 64; __VA_ARGS__; } break;        \
+    case 8032: { constexpr int F = 8, KIN = 32; __VA_ARGS__; } break;        \
+    case 8064: { constexpr int F = 8, KIN = 64; __VA_ARGS__; } break;        \
+    default: return hipErrorInvalidValue;                                    \
+  }
+#define NGV_DISPATCH_W(W_, ...)                                              \
+  switch (W_) {                                                              \
+    case 32: { constexpr int W = 32; __VA_ARGS__; } break;                   \
+    case 64: { constexpr int W = 64; __VA_ARGS__; } break;                   \
+    default: return hipErrorInvalidValue;                                    \
+  }
+#define NGV_DISPATCH_P(P_, ...)                                              \
+  switch (P_) {                                                              \
+    case 0: { constexpr int P = 0; __VA_ARGS__; } break;                     \
+    case 1: { constexpr int P = 1; __VA_ARGS__; } break;                     \
+    default: return hipErrorInvalidValue;                                    \
+  }
+
+size_t fwd_lds_bytes(const ngvol_plan* plan) {
+  const int P = plan->layout.precision, KIN = plan->kin, W = plan->layout.n_neurons, nh = plan->md.n_hidden;
+  const int ch0 = P ? KIN / 32 : KIN / 4;
+  const int chh = P ? (W + 31) / 32 : W / 4;
+  const int frags = (W / 16) * ch0 + (nh - 1) * (W / 16) * chh;
+  return (size_t)frags * 64 * (P ? 16 : 4) + (size_t)W * 4;
+}
+
+static int grid_for(const ngvol_plan* plan, int64_t n_tiles, int waves_per_block, int blocks_per_cu) {
+  int64_t need = (n_tiles + waves_per_block - 1) / waves_per_block;
+  int64_t cap = (int64_t)plan->cus * blocks_per_cu;
+  if (need > cap) need = cap;
+  if (need < 1) need = 1;
+  return (int)need;
+}
+
+hipError_t launch_encode(const ngvol_plan* plan, TablePtrs tp, const float* xyz, int64_t n, float* feat,
+                         hipStream_t st) {
+  const ModelDesc& md = plan->md;
+  const int64_t n_tiles = (n + 15) / 16;
+  const int grid = grid_for(plan, n_tiles, 4, 8);
+  NGV_DISPATCH_F_KIN(md.F, plan->kin, {
+    if (tp.f16)
+      hipLaunchKernelGGL((k_encode<F, KIN, __half>), dim3(grid), dim3(256), 0, st, md, tp, xyz, n, feat);
+    else
+      hipLaunchKernelGGL((k_encode<F, KIN, float>), dim3(grid), dim3(256), 0, st, md, tp, xyz, n, feat);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_encode_debug(const ngvol_plan* plan, const float* xyz, int64_t n, uint32_t* idx, float* w,
+                               hipStream_t st) {
+  const int64_t total = n * plan->md.L;
+  const int64_t grid = (total + 255) / 256;
+  hipLaunchKernelGGL(k_encode_debug, dim3((unsigned)grid), dim3(256), 0, st, plan->md, xyz, n, idx, w);
+  return hipGetLastError();
+}
+
+template <int MODE, typename VT>
+static hipError_t launch_infer_t(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const float* xyz, int64_t n,
+                                 float* out, const VT* vol, int dx, int dy, int dz, double* sq, hipStream_t st) {
+  const ModelDesc& md = plan->md;
+  const int64_t n_tiles = (n + 15) / 16;
+  const size_t lds = fwd_lds_bytes(plan);
+  const int grid = grid_for(plan, n_tiles, 4, 8);
+  NGV_DISPATCH_P(plan->layout.precision, NGV_DISPATCH_F_KIN(md.F, plan->kin, NGV_DISPATCH_W(md.width, {
+    if (tp.f16)
+      hipLaunchKernelGGL((k_infer<P, F, KIN, W, __half, MODE, VT>), dim3(grid), dim3(256), lds, st, md, tp, mlp, xyz,
+                         n, out, vol, dx, dy, dz, sq);
+    else
+      hipLaunchKernelGGL((k_infer<P, F, KIN, W, float, MODE, VT>), dim3(grid), dim3(256), lds, st, md, tp, mlp, xyz,
+                         n, out, vol, dx, dy, dz, sq);
+  })));
+  return hipGetLastError();
+}
+
+hipError_t launch_infer(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const float* xyz, int64_t n,
+                        float* out, hipStream_t st) {
+  return launch_infer_t<0, float>(plan, tp, mlp, xyz, n, out, nullptr, 1, 1, 1, nullptr, st);
+}
+
+hipError_t launch_sq_error_grid(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const void* vol, int dtype,
+                                const int32_t dims[3], double* sq, hipStream_t st) {
+  const int64_t n = (int64_t)dims[0] * dims[1] * dims[2];
+  if (dtype == NGVOL_DT_F16)
+    return launch_infer_t<1, __half>(plan, tp, mlp, nullptr, n, nullptr, reinterpret_cast<const __half*>(vol),
+                                     dims[0], dims[1], dims[2], sq, st);
+  return launch_infer_t<1, float>(plan, tp, mlp, nullptr, n, nullptr, reinterpret_cast<const float*>(vol), dims[0],
+                                  dims[1], dims[2], sq, st);
+}
+
+hipError_t launch_mlp_fwd(const ngvol_plan* plan, const float* mlp, const void* feat, int dtype, int64_t n,
+                          float* out, hipStream_t st) {
+  const ModelDesc& md = plan->md;
+  const int64_t n_tiles = (n + 15) / 16;
+  const size_t lds = fwd_lds_bytes(plan);
+  const int grid = grid_for(plan, n_tiles, 4, 8);
+  NGV_DISPATCH_P(plan->layout.precision, {
+    switch (plan->kin * 100 + md.width) {
+      case 3232: { constexpr int KIN = 32, W = 32;
+        if (dtype == NGVOL_DT_BF16) hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, __bf16>), dim3(grid), dim3(256), lds, st, md, mlp, (const __bf16*)feat, n, out);
+        else hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, float>), dim3(grid), dim3(256), lds, st, md, mlp, (const float*)feat, n, out);
+      } break;
+      case 3264: { constexpr int KIN = 32, W = 64;
+        if (dtype == NGVOL_DT_BF16) hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, __bf16>), dim3(grid), dim3(256), lds, st, md, mlp, (const __bf16*)feat, n, out);
+        else hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, float>), dim3(grid), dim3(256), lds, st, md, mlp, (const float*)feat, n, out);
+      } break;
+      case 6432: { constexpr int KIN = 64, W = 32;
+        if (dtype == NGVOL_DT_BF16) hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, __bf16>), dim3(grid), dim3(256), lds, st, md, mlp, (const __bf16*)feat, n, out);
+        else hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, float>), dim3(grid), dim3(256), lds, st, md, mlp, (const float*)feat, n, out);
+      } break;
+      case 6464: { constexpr int KIN = 64, W = 64;
+        if (dtype == NGVOL_DT_BF16) hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, __bf16>), dim3(grid), dim3(256), lds, st, md, mlp, (const __bf16*)feat, n, out);
+        else hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, float>), dim3(grid), dim3(256), lds, st, md, mlp, (const float*)feat, n, out);
+      } break;
+      default: return hipErrorInvalidValue;
+    }
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_train_fwd(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const BatchArgs& ba, void* e_buf,
+                            float* g_buf, double* loss_acc, float gscale, hipStream_t st) {
+  const ModelDesc& md = plan->md;
+  const int64_t n_tiles = (ba.B + 15) / 16;
+  const size_t lds = fwd_lds_bytes(plan);
+  const int grid = grid_for(plan, n_tiles, 4, 8);
+  const bool vf16 = ba.xyz == nullptr && ba.vdtype == NGVOL_DT_F16;
+  NGV_DISPATCH_P(plan->layout.precision, NGV_DISPATCH_F_KIN(md.F, plan->kin, NGV_DISPATCH_W(md.width, {
+    if (tp.f16) {
+      if (vf16)
+        hipLaunchKernelGGL((k_train_fwd<P, F, KIN, W, __half, __half>), dim3(grid), dim3(256), lds, st, md, tp, mlp, ba,
+                           e_buf, g_buf, loss_acc, gscale);
+      else
+        hipLaunchKernelGGL((k_train_fwd<P, F, KIN, W, __half, float>), dim3(grid), dim3(256), lds, st, md, tp, mlp, ba,
+                           e_buf, g_buf, loss_acc, gscale);
+    } else {
+      if (vf16)
+        hipLaunchKernelGGL((k_train_fwd<P, F, KIN, W, float, __half>), dim3(grid), dim3(256), lds, st, md, tp, mlp, ba,
+                           e_buf, g_buf, loss_acc, gscale);
+      else
+        hipLaunchKernelGGL((k_train_fwd<P, F, KIN, W, float, float>), dim3(grid), dim3(256), lds, st, md, tp, mlp, ba,
+                           e_buf, g_buf, loss_acc, gscale);
+    }
+  })));
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_batch(const BatchArgs& ba, float* xyz, float* y, hipStream_t st) {
+  const int64_t grid = (ba.B + 255) / 256;
+  if (ba.vdtype == NGVOL_DT_F16)
+    hipLaunchKernelGGL(k_sample_batch<__half>, dim3((unsigned)grid), dim3(256), 0, st, ba, xyz, y);
+  else
+    hipLaunchKernelGGL(k_sample_batch<float>, dim3((unsigned)grid), dim3(256), 0, st, ba, xyz, y);
+  return hipGetLastError();
+}
+
+}  // namespace ngvol

@@ -1,0 +1,299 @@
+// Ray-marched emission-absorption rendering through the network with sample
+// streaming (Section 5.2.1), as one persistent launch.
+//
+// The paper's host loop {compaction; coordinates; batch inference; shading}
+// becomes a loop inside each wave: the wave keeps 8 rays in flight; each
+// round it streams K = 8 sample coordinates per ray (a 64-sample batch,
+// four 16-sample MFMA tiles), evaluates the network on them, and composites
+// them front to back.  A ray that has terminated or run out of samples is
+// written out and its slot refilled from a device work queue, which plays
+// the role of stream compaction: no wave ever works on a dead ray, and no
+// control returns to the host until the frame is done.
+//
+// Work distribution is XCD-aware: the frame is cut into 8 bands of rows,
+// workgroups fetch rays from the band of their XCD (workgroup id mod 8),
+// so neighbouring rays (coherent hash-table footprints) share an L2, and
+// steal from the other bands once their own is empty.
+#include "kernels.hpp"
+#include "mlp_tile.hpp"
+
+namespace ngvol {
+
+namespace {
+constexpr int kSlots = 8;  // rays per wave
+constexpr int kK = 8;      // samples per ray per round
+constexpr int kBands = 8;  // one work band per XCD
+}  // namespace
+
+struct RayGeom {
+  float o[3], d[3], t0, j;
+  uint32_t n;
+};
+
+// Ray of pixel (px, py): binary32, one rounding per operation, no FMA.
+__device__ __forceinline__ RayGeom make_ray(const float* cam, int W, int px, int py, uint32_t seed, float dt) {
+  RayGeom r;
+  const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+  float dir[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float t1 = __fmul_rn(fx, cam[3 + a]);
+    const float t2 = __fadd_rn(cam[9 + a], t1);
+    const float t3 = __fmul_rn(fy, cam[6 + a]);
+    dir[a] = __fadd_rn(t2, t3);
+  }
+  const float n2 = __fadd_rn(__fadd_rn(__fmul_rn(dir[0], dir[0]), __fmul_rn(dir[1], dir[1])), __fmul_rn(dir[2], dir[2]));
+  const float nrm = __fsqrt_rn(n2);
+  float tmin = -INFINITY, tmax = INFINITY;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    r.o[a] = cam[a];
+    r.d[a] = __fdiv_rn(dir[a], nrm);
+    const float inv = __fdiv_rn(1.0f, r.d[a]);
+    const float ta = __fmul_rn(__fsub_rn(0.0f, r.o[a]), inv);
+    const float tb = __fmul_rn(__fsub_rn(1.0f, r.o[a]), inv);
+    tmin = fmaxf(tmin, fminf(ta, tb));
+    tmax = fminf(tmax, fmaxf(ta, tb));
+  }
+  const float tn = fmaxf(tmin, 0.0f);
+  r.t0 = tn;
+  r.j = rng_u01((uint64_t)seed, 5u, (uint64_t)py * (uint64_t)W + (uint64_t)px);
+  r.n = 0;
+  if (tn < tmax) {
+    const float q = __fdiv_rn(__fsub_rn(tmax, tn), dt);
+    // a unit-cube chord is at most sqrt(3) long; more than 2^24 steps (or a
+    // NaN span) means a degenerate ray, which gets no samples
+    if (q <= 16777216.0f) {
+      const float c = ceilf(__fsub_rn(q, r.j));
+      if (c > 0.0f) r.n = (uint32_t)c;
+    }
+  }
+  return r;
+}
+
+__device__ __forceinline__ void ray_point(const RayGeom& r, uint32_t k, float dt, float& x, float& y, float& z) {
+  const float kj = __fadd_rn((float)k, r.j);
+  const float t = __fadd_rn(r.t0, __fmul_rn(kj, dt));
+  x = __fadd_rn(r.o[0], __fmul_rn(t, r.d[0]));
+  y = __fadd_rn(r.o[1], __fmul_rn(t, r.d[1]));
+  z = __fadd_rn(r.o[2], __fmul_rn(t, r.d[2]));
+}
+
+struct SlotState {
+  RayGeom g;
+  int32_t pix;  // -1: empty
+  uint32_t k;   // next sample index
+  uint32_t used;
+  float C[3], A;
+};
+
+__global__ void k_render_init(unsigned int* queue, unsigned long long* counters) {
+  const int t = threadIdx.x;
+  if (t < kBands) queue[t] = 0u;
+  if (t < 4 && counters) counters[t] = 0ull;
+}
+
+// Fetch the next pixel: own band first, then steal from the others.
+__device__ __forceinline__ int32_t fetch_pixel(unsigned int* queue, int band0, int64_t n_pix) {
+  for (int i = 0; i < kBands; ++i) {
+    const int b = (band0 + i) % kBands;
+    const int64_t lo = n_pix * b / kBands, hi = n_pix * (b + 1) / kBands;
+    if (__hip_atomic_load(queue + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= (unsigned)(hi - lo)) continue;
+    const unsigned q = atomicAdd(queue + b, 1u);
+    if ((int64_t)q < hi - lo) return (int32_t)(lo + q);
+  }
+  return -1;
+}
+
+template <int P, int F, int KIN, int W, typename TT>
+__global__ void __launch_bounds__(256) k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp,
+                                                RenderArgs ra) {
+  typedef typename Prec<P>::Frag Frag;
+  typedef WeightLayout<P, KIN, W> WL;
+  extern __shared__ __align__(16) unsigned char smem[];
+  Frag* lds_frag = reinterpret_cast<Frag*>(smem);
+  const size_t wbytes = (size_t)WL::frags(md.n_hidden, false) * 64 * sizeof(Frag);
+  float* lds_wout = reinterpret_cast<float*>(smem + wbytes);
+  float* lds_lut = lds_wout + W;  // [256][4]
+  const int wave = threadIdx.x >> 6;
+  SlotState* slots = reinterpret_cast<SlotState*>(lds_lut + 1024) + wave * kSlots;
+  float* yv = reinterpret_cast<float*>(reinterpret_cast<SlotState*>(lds_lut + 1024) + (blockDim.x >> 6) * kSlots) +
+              wave * kSlots * kK;
+
+  stage_weights<P, KIN, W>(md, mlp, lds_frag, lds_wout, false);
+  for (int t = threadIdx.x; t < 1024; t += blockDim.x) lds_lut[t] = ra.lut[t];
+  __syncthreads();
+
+  const TT* table = table_ptr<TT>(tp);
+  const int lane = threadIdx.x & 63, nl = lane & 15, g = lane >> 4;
+  const int band0 = blockIdx.x % kBands;
+  const int64_t n_pix = (int64_t)ra.width * ra.height;
+  unsigned long long n_eval = 0, n_used_tot = 0, n_rays = 0;
+
+  // Owner lanes (lane < kSlots) keep their slot in LDS.
+  auto refill = [&](SlotState& sl) {
+    for (;;) {
+      const int32_t p = fetch_pixel(ra.queue, band0, n_pix);
+      sl.pix = p;
+      if (p < 0) return;
+      const int px = p % ra.width, py = p / ra.width;
+      sl.g = make_ray(ra.cam, ra.width, px, py, ra.seed, ra.dt);
+      sl.k = 0;
+      sl.used = 0;
+      sl.C[0] = sl.C[1] = sl.C[2] = 0.0f;
+      sl.A = 0.0f;
+      if (sl.g.n > 0) {
+        ++n_rays;
+        return;
+      }
+      // empty ray: write it out and take another
+      float4* o4 = reinterpret_cast<float4*>(ra.rgba) + p;
+      *o4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (ra.n_geo) ra.n_geo[p] = 0u;
+      if (ra.n_used) ra.n_used[p] = 0u;
+    }
+  };
+
+  if (lane < kSlots) {
+    SlotState sl;
+    refill(sl);
+    slots[lane] = sl;
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+
+  for (;;) {
+    // any live slot in this wave?
+    const bool live = lane < kSlots && slots[lane].pix >= 0;
+    if (!__any(live)) break;
+    // four 16-sample tiles: slot = 2*tile + nl/8, sample k = slot.k + nl%8
+#pragma unroll 1
+    for (int tile = 0; tile < kSlots * kK / 16; ++tile) {
+      const int si = 2 * tile + (nl >> 3);
+      const SlotState& sl = slots[si];
+      const uint32_t k = sl.k + (nl & 7);
+      const bool valid = sl.pix >= 0 && k < sl.g.n;
+      float x = 0.5f, y = 0.5f, z = 0.5f;
+      if (valid) {
+        ray_point(sl.g, k, ra.dt, x, y, z);
+        x = clamp01(x);
+        y = clamp01(y);
+        z = clamp01(z);
+      }
+      float f[KIN / 32][8];
+      encode_lane<F, KIN>(md, table, x, y, z, f);
+      Frag in[InChunks<P, KIN>::n];
+      feat_to_frag<P, KIN>(f, in);
+      f32x4 act[W / 16];
+      mlp_hidden_fwd<P, KIN, W, false>(md.n_hidden, lds_frag, in, act, nullptr);
+      const float v = mlp_output<W>(act, lds_wout);
+      if (g == 0) {
+        yv[si * kK + (nl & 7)] = v;
+        if (valid) ++n_eval;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    if (lane < kSlots) {
+      SlotState sl = slots[lane];
+      if (sl.pix >= 0) {
+        bool done = false;
+        const uint32_t kend = sl.g.n - sl.k < (uint32_t)kK ? sl.g.n - sl.k : (uint32_t)kK;
+        for (uint32_t q = 0; q < kend; ++q) {
+          const float val = fminf(fmaxf(yv[lane * kK + q], 0.0f), 1.0f);
+          const float u = 255.0f * val;
+          const float fi = fminf(floorf(u), 254.0f);
+          const int i0 = (int)fi;
+          const float fr = u - fi;
+          float c4[4];
+#pragma unroll
+          for (int ch = 0; ch < 4; ++ch) c4[ch] = __builtin_fmaf(fr, lds_lut[4 * (i0 + 1) + ch] - lds_lut[4 * i0 + ch],
+                                                                   lds_lut[4 * i0 + ch]);
+          const float w = (1.0f - sl.A) * c4[3];
+          sl.C[0] = __builtin_fmaf(w, c4[0], sl.C[0]);
+          sl.C[1] = __builtin_fmaf(w, c4[1], sl.C[1]);
+          sl.C[2] = __builtin_fmaf(w, c4[2], sl.C[2]);
+          sl.A += w;
+          sl.used += 1;
+          if (sl.A >= 0.99f) {
+            done = true;
+            break;
+          }
+        }
+        sl.k += kend;
+        if (done || sl.k >= sl.g.n) {
+          const int32_t p = sl.pix;
+          float4* o4 = reinterpret_cast<float4*>(ra.rgba) + p;
+          *o4 = make_float4(sl.C[0], sl.C[1], sl.C[2], sl.A);
+          if (ra.n_geo) ra.n_geo[p] = sl.g.n;
+          if (ra.n_used) ra.n_used[p] = sl.used;
+          n_used_tot += sl.used;
+          refill(sl);
+        }
+        slots[lane] = sl;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  }
+  if (ra.counters) {
+    const unsigned long long e = (unsigned long long)wave_sum((double)n_eval);
+    const unsigned long long u = (unsigned long long)wave_sum((double)n_used_tot);
+    const unsigned long long r = (unsigned long long)wave_sum((double)n_rays);
+    if (lane == 0) {
+      atomicAdd(ra.counters + 0, e);
+      atomicAdd(ra.counters + 1, u);
+      atomicAdd(ra.counters + 2, r);
+    }
+  }
+}
+
+size_t render_lds_bytes(const ngvol_plan* plan, int waves) {
+  return fwd_lds_bytes(plan) + 1024 * 4 + (size_t)waves * kSlots * sizeof(SlotState) +
+         (size_t)waves * kSlots * kK * 4;
+}
+
+hipError_t launch_render(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const RenderArgs& ra,
+                         hipStream_t st) {
+  const ModelDesc& md = plan->md;
+  hipLaunchKernelGGL(k_render_init, dim3(1), dim3(64), 0, st, ra.queue, ra.counters);
+  const size_t lds = render_lds_bytes(plan, 4);
+  const int64_t n_pix = (int64_t)ra.width * ra.height;
+  int64_t grid = (n_pix + 4 * kSlots - 1) / (4 * kSlots);
+  const int64_t cap = (int64_t)plan->cus * 8;
+  if (grid > cap) grid = cap;
+  if (grid < 1) grid = 1;
+#define NGV_RENDER(P, F, KIN, W)                                                                                    \
+  do {                                                                                                              \
+    if (tp.f16)                                                                                                     \
+      hipLaunchKernelGGL((k_render<P, F, KIN, W, __half>), dim3((unsigned)grid), dim3(256), lds, st, md, tp, mlp, ra); \
+    else                                                                                                            \
+      hipLaunchKernelGGL((k_render<P, F, KIN, W, float>), dim3((unsigned)grid), dim3(256), lds, st, md, tp, mlp, ra);  \
+  } while (0)
+#define NGV_RENDER_W(P, F, KIN)                              \
+  do {                                                       \
+    if (md.width == 32) NGV_RENDER(P, F, KIN, 32);            \
+    else if (md.width == 64) NGV_RENDER(P, F, KIN, 64);       \
+    else return hipErrorInvalidValue;                        \
+  } while (0)
+#define NGV_RENDER_FK(P)                                              \
+  do {                                                                \
+    switch (md.F * 1000 + plan->kin) {                                \
+      case 2032: NGV_RENDER_W(P, 2, 32); break;                       \
+      case 2064: NGV_RENDER_W(P, 2, 64); break;                       \
+      case 4032: NGV_RENDER_W(P, 4, 32); break;                       \
+      case 4064: NGV_RENDER_W(P, 4, 64); break;                       \
+      case 8032: NGV_RENDER_W(P, 8, 32); break;                       \
+      case 8064: NGV_RENDER_W(P, 8, 64); break;                       \
+      default: return hipErrorInvalidValue;                           \
+    }                                                                 \
+  } while (0)
+  if (plan->layout.precision == 1) NGV_RENDER_FK(1);
+  else NGV_RENDER_FK(0);
+#undef NGV_RENDER_FK
+#undef NGV_RENDER_W
+#undef NGV_RENDER
+  return hipGetLastError();
+}
+
+}  // namespace ngvol

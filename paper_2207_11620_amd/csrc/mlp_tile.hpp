@@ -1,0 +1,304 @@
+// Wavefront-tile MLP on the matrix cores (gfx950).
+//
+// A wave evaluates the network on tiles of 16 samples.  Activations live in
+// the MFMA accumulator layout, transposed: for a layer of width Wd the lane
+// (n = lane%16, g = lane/16) holds, for each 16-neuron block m, the values of
+// neurons 16m + 4g + j (j = 0..3) of sample n.  The next layer contracts over
+// neurons, and since the order of a contraction is free, its K chunks are
+// formed directly from the registers a lane already holds; the matching
+// permutation is applied to the weights once, when a workgroup stages them in
+// LDS.  No shuffles are needed between layers.
+//
+// Two precisions share this structure:
+//   P = 1: BF16 operands, v_mfma_f32_16x16x32_bf16 (K = 32 per instruction);
+//   P = 0: FP32 operands, v_mfma_f32_16x16x4_f32 (K = 4 per instruction).
+// Both accumulate in FP32.
+//
+// Encoded inputs use a different lane ownership: in every 32-feature block b,
+// lane group g owns features 32b + 8g + jj (jj = 0..7) of its sample, i.e.
+// 8/F whole levels, so each lane gathers whole levels.
+#pragma once
+
+#include "device_common.hpp"
+
+namespace ngvol {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f32x4 mfma(const bf16x8& a, const bf16x8& b, const f32x4& c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mfma(float a, float b, const f32x4& c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+// K = 16 BF16 product, used where the contraction runs over the 16 samples of a tile.
+__device__ __forceinline__ f32x4 mfma_k16(const bf16x4& a, const bf16x4& b, const f32x4& c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ f32x4 zero4() { return f32x4{0.0f, 0.0f, 0.0f, 0.0f}; }
+
+template <int P>
+struct Prec;
+
+template <>
+struct Prec<1> {
+  typedef bf16x8 Frag;
+  static constexpr int K = 32;
+  static __device__ __forceinline__ Frag zero() {
+    Frag f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) f[i] = (__bf16)0.0f;
+    return f;
+  }
+};
+
+template <>
+struct Prec<0> {
+  typedef float Frag;
+  static constexpr int K = 4;
+  static __device__ __forceinline__ Frag zero() { return 0.0f; }
+};
+
+// Number of K chunks of a layer's input.
+//   encoded input of KIN features: P1: KIN/32, P0: KIN/4
+//   hidden input of width W:       P1: ceil(W/32), P0: W/4
+template <int P, int KIN>
+struct InChunks {
+  static constexpr int n = P ? KIN / 32 : KIN / 4;
+};
+template <int P, int W>
+struct HidChunks {
+  static constexpr int n = P ? (W + 31) / 32 : W / 4;
+};
+
+// Input feature (column) that lane group g feeds at position jj of chunk c.
+template <int P>
+__device__ __forceinline__ int enc_col(int c, int g, int jj) {
+  if constexpr (P) return 32 * c + 8 * g + jj;
+  else return 32 * (c >> 3) + 8 * g + (c & 7);
+}
+template <int P>
+__device__ __forceinline__ int hid_col(int c, int g, int jj) {
+  if constexpr (P) return 16 * (2 * c + (jj >> 2)) + 4 * g + (jj & 3);
+  else return 16 * (c >> 2) + 4 * g + (c & 3);
+}
+
+// ---------------------------------------------------------------------------
+// Weight staging.  Layer li's fragments for output block mb and chunk c are
+// stored at frag index (layer_base[li] + mb * chunks[li] + c) * 64 + lane.
+// Entries whose row or column falls outside the matrix are zero.
+// ---------------------------------------------------------------------------
+template <int P, int KIN, int W>
+struct WeightLayout {
+  static constexpr int CH0 = InChunks<P, KIN>::n;
+  static constexpr int CHH = HidChunks<P, W>::n;
+  static constexpr int MB = W / 16;
+  static constexpr int FR0 = MB * CH0;  // fragments of the input layer
+  static constexpr int FRH = MB * CHH;  // fragments of each hidden layer
+  // fragments of the transposed matrices (backward): input dim becomes the M side
+  static constexpr int MB0T = KIN / 16;  // blocks of W0^T rows
+  static constexpr int FR0T = MB0T * CHH;
+  static constexpr int FRHT = MB * CHH;
+  __host__ __device__ static constexpr int frags(int n_hidden, bool bwd) {
+    return FR0 + (n_hidden - 1) * FRH + (bwd ? FR0T + (n_hidden - 1) * FRHT : 0);
+  }
+};
+
+// Stage W0..W_{h-1} (and, for the backward, their transposes) into LDS in
+// fragment order, plus W_out in FP32.  Called by the whole workgroup.
+template <int P, int KIN, int W>
+__device__ void stage_weights(const ModelDesc& md, const float* __restrict__ mlp, typename Prec<P>::Frag* lds_frag,
+                              float* lds_wout, bool bwd) {
+  typedef WeightLayout<P, KIN, W> WL;
+  typedef typename Prec<P>::Frag Frag;
+  constexpr int EPF = P ? 8 : 1;  // elements per fragment
+  const int nh = md.n_hidden;
+  const int n_in = md.n_in;
+  const int total = WL::frags(nh, bwd) * 64;
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    const int lane = t & 63;
+    int fr = t >> 6;
+    const int i = lane & 15, g = lane >> 4;
+    Frag val = Prec<P>::zero();
+    // which matrix
+    int li, mb, c;
+    bool trans = false;
+    const int fw = WL::FR0 + (nh - 1) * WL::FRH;
+    if (fr >= fw) {
+      trans = true;
+      fr -= fw;
+      if (fr < WL::FR0T) {
+        li = 0;
+        mb = fr / WL::CHH;
+        c = fr % WL::CHH;
+      } else {
+        fr -= WL::FR0T;
+        li = 1 + fr / WL::FRHT;
+        fr %= WL::FRHT;
+        mb = fr / WL::CHH;
+        c = fr % WL::CHH;
+      }
+    } else if (fr < WL::FR0) {
+      li = 0;
+      mb = fr / WL::CH0;
+      c = fr % WL::CH0;
+    } else {
+      fr -= WL::FR0;
+      li = 1 + fr / WL::FRH;
+      fr %= WL::FRH;
+      mb = fr / WL::CHH;
+      c = fr % WL::CHH;
+    }
+    const float* Wm = mlp + md.w_off[li];
+    const int in_dim = li == 0 ? n_in : W;
+#pragma unroll
+    for (int jj = 0; jj < EPF; ++jj) {
+      float x = 0.0f;
+      if (!trans) {
+        // forward: A[row = 16mb + i][k] = W[row][col(k)]
+        const int row = 16 * mb + i;
+        const int col = li == 0 ? enc_col<P>(c, g, jj) : hid_col<P>(c, g, jj);
+        if (row < W && col < in_dim) x = Wm[row * in_dim + col];
+      } else {
+        // backward: A[row = 16mb + i][k] = W^T[row][col(k)] = W[col][row], contracting over W's rows
+        const int row = 16 * mb + i;  // input-side index
+        const int col = hid_col<P>(c, g, jj);
+        if (row < in_dim && col < W) x = Wm[col * in_dim + row];
+      }
+      if constexpr (P) val[jj] = (__bf16)x;
+      else val = x;
+    }
+    lds_frag[t] = val;
+  }
+  const float* wo = mlp + md.w_off[nh];
+  for (int t = threadIdx.x; t < W; t += blockDim.x) lds_wout[t] = wo[t];
+}
+
+// ---------------------------------------------------------------------------
+// Forward through the hidden layers.
+//   in_frag[c]   : B operands of the encoded input (chunks of layer 0)
+//   z[li][mb]    : pre-activations kept for the backward (optional)
+//   returns the last hidden activation in act[mb] (FP32, accumulator layout)
+// ---------------------------------------------------------------------------
+template <int P, int W>
+__device__ __forceinline__ void pack_hidden(const f32x4 act[W / 16], typename Prec<P>::Frag out[HidChunks<P, W>::n],
+                                            bool relu) {
+  constexpr int CHH = HidChunks<P, W>::n;
+#pragma unroll
+  for (int c = 0; c < CHH; ++c) {
+    if constexpr (P) {
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) {
+        const int m = 2 * c + (jj >> 2);
+        float v = (m < W / 16) ? act[m < W / 16 ? m : 0][jj & 3] : 0.0f;
+        if (relu) v = fmaxf(v, 0.0f);
+        out[c][jj] = (__bf16)v;
+      }
+    } else {
+      float v = act[c >> 2][c & 3];
+      if (relu) v = fmaxf(v, 0.0f);
+      out[c] = v;
+    }
+  }
+}
+
+template <int P, int KIN, int W, bool KEEP_Z>
+__device__ __forceinline__ void mlp_hidden_fwd(int n_hidden, const typename Prec<P>::Frag* __restrict__ lds_frag,
+                                               const typename Prec<P>::Frag in_frag[InChunks<P, KIN>::n],
+                                               f32x4 act[W / 16], f32x4 (*zkeep)[W / 16]) {
+  typedef WeightLayout<P, KIN, W> WL;
+  typedef typename Prec<P>::Frag Frag;
+  constexpr int MB = W / 16;
+  const int lane = threadIdx.x & 63;
+  // layer 0
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) {
+    f32x4 acc = zero4();
+#pragma unroll
+    for (int c = 0; c < WL::CH0; ++c) acc = mfma(lds_frag[(mb * WL::CH0 + c) * 64 + lane], in_frag[c], acc);
+    act[mb] = acc;
+  }
+  if constexpr (KEEP_Z) {
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) zkeep[0][mb] = act[mb];
+  }
+  // hidden layers 1..n_hidden-1
+  for (int li = 1; li < n_hidden; ++li) {
+    Frag b[WL::CHH];
+    pack_hidden<P, W>(act, b, true);
+    const Frag* base = lds_frag + (WL::FR0 + (li - 1) * WL::FRH) * 64;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      f32x4 acc = zero4();
+#pragma unroll
+      for (int c = 0; c < WL::CHH; ++c) acc = mfma(base[(mb * WL::CHH + c) * 64 + lane], b[c], acc);
+      act[mb] = acc;
+    }
+    if constexpr (KEEP_Z) {
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) zkeep[li][mb] = act[mb];
+    }
+  }
+}
+
+// Output neuron: y = w_out . relu(z_last); every lane of the sample gets y.
+template <int W>
+__device__ __forceinline__ float mlp_output(const f32x4 zlast[W / 16], const float* __restrict__ lds_wout) {
+  const int g = (threadIdx.x & 63) >> 4;
+  float s = 0.0f;
+#pragma unroll
+  for (int mb = 0; mb < W / 16; ++mb)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s = __builtin_fmaf(lds_wout[16 * mb + 4 * g + j], fmaxf(zlast[mb][j], 0.0f), s);
+  s += __shfl_xor(s, 16, 64);
+  s += __shfl_xor(s, 32, 64);
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Encoding of the lane's share of one sample: features 32b + 8g + jj.
+// ---------------------------------------------------------------------------
+template <int F, int KIN, typename TT>
+__device__ __forceinline__ void encode_lane(const ModelDesc& md, const TT* __restrict__ table, float x, float y,
+                                            float z, float feat[KIN / 32][8]) {
+  const int g = (threadIdx.x & 63) >> 4;
+  constexpr int LPL = 8 / F;  // levels per lane per block
+#pragma unroll
+  for (int b = 0; b < KIN / 32; ++b) {
+#pragma unroll
+    for (int q = 0; q < LPL; ++q) {
+      const int l = (32 * b + 8 * g) / F + q;
+      float acc[F];
+      if (l < md.L) {
+        Corners cr;
+        level_corners(md.lv[l], x, y, z, cr);
+        gather_level<F>(cr, table, acc);
+      } else {
+#pragma unroll
+        for (int f = 0; f < F; ++f) acc[f] = 0.0f;
+      }
+#pragma unroll
+      for (int f = 0; f < F; ++f) feat[b][q * F + f] = acc[f];
+    }
+  }
+}
+
+template <int P, int KIN>
+__device__ __forceinline__ void feat_to_frag(const float feat[KIN / 32][8],
+                                             typename Prec<P>::Frag out[InChunks<P, KIN>::n]) {
+#pragma unroll
+  for (int b = 0; b < KIN / 32; ++b) {
+    if constexpr (P) {
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) out[b][jj] = (__bf16)feat[b][jj];
+    } else {
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) out[8 * b + jj] = feat[b][jj];
+    }
+  }
+}
+
+}  // namespace ngvol

@@ -1,0 +1,122 @@
+"""Host-side checks of the C-ABI library: it loads, exports every symbol the
+header declares, and its plan/layout logic agrees with the oracle.  No
+kernel is launched here."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ngv = pytest.importorskip("paper_2207_11620_amd")
+
+
+def _lib_or_skip():
+    if not os.path.exists(ngv.LIB_PATH):
+        pytest.skip("libngvol.so not built")
+    return ngv.lib()
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "ngvol.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ngvol_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    L = _lib_or_skip()
+    names = header_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(names) == sorted(ngv.EXPORTED)
+
+
+def test_nm_lists_symbols():
+    _lib_or_skip()
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", ngv.LIB_PATH], capture_output=True, text=True).stdout
+    for n in header_functions():
+        assert re.search(rf"\bT {n}\b", out), n
+
+
+CFG0 = dict(n_levels=8, n_features=2, log2_hashmap_size=14, base_resolution=4, per_level_scale=1.5, n_neurons=32,
+            n_hidden_layers=2)
+CFG1 = dict(n_levels=16, n_features=2, log2_hashmap_size=19, base_resolution=16, max_resolution=2048, n_neurons=64,
+            n_hidden_layers=2)
+
+
+@pytest.mark.parametrize("cfg,base,scale,maxr", [(CFG0, 4, 1.5, 0), (CFG1, 16, 0.0, 2048)])
+def test_layout_matches_oracle(cfg, base, scale, maxr):
+    _lib_or_skip()
+    for prec in ("fp32", "bf16"):
+        p = ngv.Plan(**cfg, precision=prec)
+        res = oracle.resolutions(cfg["n_levels"], base, scale, maxr)
+        assert p.resolution == res
+        m = oracle.Model(cfg["n_levels"], 2, cfg["log2_hashmap_size"], res, cfg["n_neurons"], cfg["n_hidden_layers"])
+        assert p.level_entries == list(m.level_size)
+        assert p.level_offset == list(m.level_offset)
+        assert (p.n_table_params, p.n_mlp_params, p.n_params) == (m.n_table, m.n_mlp, m.n_params)
+        assert p.layer_offset[0] == m.n_table
+
+
+def test_paper_configs_layout():
+    _lib_or_skip()
+    # Table-2 fixed network: L8 F8 T2^19 base 4, 64 wide, 4 hidden (parameter count pinned in the oracle tests)
+    p = ngv.Plan(8, 8, 19, 4, 2.0, n_neurons=64, n_hidden_layers=4)
+    res = oracle.resolutions(8, 4, 2.0)
+    m = oracle.Model(8, 8, 19, res, 64, 4)
+    assert p.n_params == m.n_params
+
+
+def test_explicit_resolutions():
+    _lib_or_skip()
+    p = ngv.Plan(3, 2, 10, resolutions=[3, 7, 40], n_neurons=32, n_hidden_layers=1)
+    assert p.resolution == [3, 7, 40]
+    assert p.dense == [True, True, False]
+    assert p.level_entries == [27, 343, 1024]
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n_levels=0), ngv.EINVAL),
+    (dict(n_levels=33), ngv.EINVAL),
+    (dict(n_features=3), ngv.EUNSUPPORTED),
+    (dict(n_neurons=48), ngv.EUNSUPPORTED),
+    (dict(n_levels=16, n_features=8), ngv.EUNSUPPORTED),
+    (dict(log2_hashmap_size=40), ngv.EINVAL),
+    (dict(n_hidden_layers=0), ngv.EINVAL),
+    (dict(base_resolution=1), ngv.EINVAL),
+    (dict(precision=7), ngv.EINVAL),
+])
+def test_plan_rejects(kw, code):
+    _lib_or_skip()
+    cfg = dict(CFG0)
+    prec = kw.pop("precision", "fp32")
+    cfg.update(kw)
+    if prec == 7:
+        with pytest.raises(KeyError):
+            ngv.Plan(**cfg, precision=prec)
+        return
+    with pytest.raises(ngv.NgvolError) as ei:
+        ngv.Plan(**cfg, precision=prec)
+    assert ei.value.code == code
+
+
+def test_null_arguments_rejected_without_launch():
+    import ctypes as C
+    L = _lib_or_skip()
+    p = ngv.Plan(**CFG0)
+    w = ngv.Weights(None, None)
+    assert L.ngvol_infer(p.handle, C.byref(w), None, 10, None, None) == ngv.EINVAL
+    assert L.ngvol_infer(None, C.byref(w), None, 10, None, None) == ngv.EINVAL
+    assert b"NULL" in L.ngvol_last_error()
+    # misaligned pointers are rejected before any launch
+    w2 = ngv.Weights(C.c_void_p(16), None)
+    assert L.ngvol_infer(p.handle, C.byref(w2), C.c_void_p(18), 10, C.c_void_p(32), None) == ngv.EINVAL
+    # n = 0 is a no-op even with null data pointers... after the weights check
+    assert L.ngvol_infer(p.handle, C.byref(w2), None, 0, None, None) == ngv.OK
+    sz = C.c_size_t()
+    assert L.ngvol_train_workspace_bytes(p.handle, 4096, C.byref(sz)) == ngv.OK
+    assert sz.value > 4096 * 32 * 4
