@@ -67,6 +67,7 @@ extern "C" {
 /* MLP arithmetic of a plan. */
 #define NGVOL_FP32 0 /* FP32 operands on the matrix cores (v_mfma_f32_16x16x4_f32) */
 #define NGVOL_BF16 1 /* BF16 operands on MFMA with FP32 accumulation */
+#define NGVOL_FP16 2 /* FP16 operands on MFMA with FP32 accumulation */
 
 /* Element types of volumes and feature buffers. */
 #define NGVOL_DT_F32 0
@@ -98,7 +99,7 @@ typedef struct ngvol_config {
     const int32_t* resolutions; /* host pointer, optional */
     int32_t n_neurons;
     int32_t n_hidden_layers;
-    int32_t precision; /* NGVOL_FP32 | NGVOL_BF16 */
+    int32_t precision; /* NGVOL_FP32 | NGVOL_BF16 | NGVOL_FP16 */
 } ngvol_config;
 
 /* Derived layout of a plan (host struct filled by ngvol_get_layout). */
@@ -202,14 +203,32 @@ int ngvol_encode_debug(const ngvol_plan* plan, const float* d_xyz, int64_t n, ui
                        hipStream_t stream);
 
 /* MLP forward (Section 3.1) on given features: out[n] (FP32) from
- * feat[n][L*F] of type feat_dtype (NGVOL_DT_F32 or NGVOL_DT_BF16), with the
- * plan's precision. */
+ * feat[n][L*F] of type feat_dtype (NGVOL_DT_F32, NGVOL_DT_BF16 or
+ * NGVOL_DT_F16), with the plan's precision. */
 int ngvol_mlp_fwd(const ngvol_plan* plan, const float* d_params, const void* d_feat, int32_t feat_dtype, int64_t n,
                   float* d_out, hipStream_t stream);
 
-/* Fused query: out[n] = Phi(xyz) (encoding + MLP in one kernel). */
+/* Fused query: out[n] = Phi(xyz) (encoding + MLP in one kernel).  With a
+ * workspace of ngvol_infer_workspace_bytes(plan, n) bytes the queries are
+ * first grouped by spatial cell (a counting sort on the device) so that
+ * neighbouring queries share table cache lines; every output still lands in
+ * its own slot and the values are the same.  With d_workspace == NULL the
+ * queries are evaluated in the given order (best for coherent inputs such as
+ * already sorted or ray-ordered coordinates).  The bytes query returns 0 when
+ * n is too small for reordering to pay off.  n < 2^31. */
+int ngvol_infer_workspace_bytes(const ngvol_plan* plan, int64_t n, size_t* bytes);
 int ngvol_infer(const ngvol_plan* plan, const ngvol_weights* w, const float* d_xyz, int64_t n, float* d_out,
-                hipStream_t stream);
+                void* d_workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* The two halves of a reordered ngvol_infer, for coordinates that are
+ * queried more than once: ngvol_sort_queries groups xyz[n] by spatial cell
+ * into the workspace (ngvol_infer_workspace_bytes; EINVAL if that is 0), and
+ * ngvol_infer_sorted evaluates the grouped queries of that workspace, writing
+ * each output to its original slot of out[n]. */
+int ngvol_sort_queries(const ngvol_plan* plan, const float* d_xyz, int64_t n, void* d_workspace,
+                       size_t workspace_bytes, hipStream_t stream);
+int ngvol_infer_sorted(const ngvol_plan* plan, const ngvol_weights* w, const void* d_workspace, int64_t n,
+                       float* d_out, hipStream_t stream);
 
 /* MLP backward: given d_out[n] = dL/dout, adds dL/dW into the MLP part of
  * d_grad (n_params floats, the table part is untouched) and, if
@@ -235,7 +254,9 @@ int ngvol_sample_batch(const ngvol_plan* plan, const ngvol_batch* batch, float* 
 /* Workspace a training step of batch B needs. */
 int ngvol_train_workspace_bytes(const ngvol_plan* plan, int64_t batch_size, size_t* bytes);
 
-/* One training step (Section 4): sampling, forward, mean-squared loss
+/* One training step (Section 4): sampling (the batch is grouped by spatial
+ * cell on the device before use; the loss is a sum so the order of samples
+ * does not matter), forward, mean-squared loss
  * L = (1/B) sum (Phi(x)-y)^2, backward through the MLP (activations
  * recomputed from the stored encoding) and the encoding, then Adam on all
  * parameters; the FP16 shadow (if any) is refreshed by round-to-nearest-even

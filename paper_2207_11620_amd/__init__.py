@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libngvol.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -4
-FP32, BF16 = 0, 1
+FP32, BF16, FP16 = 0, 1, 2
 DT_F32, DT_F16, DT_BF16 = 0, 1, 2
 MAX_LEVELS, MAX_LAYERS = 32, 9
 
@@ -81,7 +81,10 @@ _SIGS = {
     "ngvol_encode": (C.c_int, [_P, C.POINTER(Weights), _P, C.c_int64, _P, _P]),
     "ngvol_encode_debug": (C.c_int, [_P, _P, C.c_int64, _P, _P, _P]),
     "ngvol_mlp_fwd": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int64, _P, _P]),
-    "ngvol_infer": (C.c_int, [_P, C.POINTER(Weights), _P, C.c_int64, _P, _P]),
+    "ngvol_infer_workspace_bytes": (C.c_int, [_P, C.c_int64, C.POINTER(C.c_size_t)]),
+    "ngvol_infer": (C.c_int, [_P, C.POINTER(Weights), _P, C.c_int64, _P, _P, C.c_size_t, _P]),
+    "ngvol_sort_queries": (C.c_int, [_P, _P, C.c_int64, _P, C.c_size_t, _P]),
+    "ngvol_infer_sorted": (C.c_int, [_P, C.POINTER(Weights), _P, C.c_int64, _P, _P]),
     "ngvol_mlp_bwd_workspace_bytes": (C.c_int, [_P, C.c_int64, C.POINTER(C.c_size_t)]),
     "ngvol_mlp_bwd": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P, _P, _P, C.c_size_t, _P]),
     "ngvol_encode_bwd": (C.c_int, [_P, _P, C.c_int64, _P, _P, _P]),
@@ -148,7 +151,7 @@ class Plan:
 
     def __init__(self, n_levels, n_features, log2_hashmap_size, base_resolution=16, per_level_scale=2.0,
                  max_resolution=0, resolutions=None, n_neurons=64, n_hidden_layers=2, precision="fp32"):
-        prec = {"fp32": FP32, "bf16": BF16, FP32: FP32, BF16: BF16}[precision]
+        prec = {"fp32": FP32, "bf16": BF16, "fp16": FP16, FP32: FP32, BF16: BF16, FP16: FP16}[precision]
         self._res = None
         if resolutions is not None:
             self._res = (C.c_int32 * len(resolutions))(*[int(r) for r in resolutions])
@@ -202,19 +205,51 @@ def encode_debug(plan, xyz):
 def mlp_fwd(plan, params, feat):
     torch = _torch()
     n = feat.shape[0]
-    dt = {torch.float32: DT_F32, torch.bfloat16: DT_BF16}[feat.dtype]
+    dt = {torch.float32: DT_F32, torch.bfloat16: DT_BF16, torch.float16: DT_F16}[feat.dtype]
     out = torch.empty(n, dtype=torch.float32, device=feat.device)
     _check(lib().ngvol_mlp_fwd(plan.handle, _ptr(params), _ptr(feat), dt, n, _ptr(out), _stream()))
     return out
 
 
-def infer(plan, params, xyz, table_f16=None, out=None):
+def infer_workspace_bytes(plan, n):
+    nb = C.c_size_t()
+    _check(lib().ngvol_infer_workspace_bytes(plan.handle, n, C.byref(nb)))
+    return nb.value
+
+
+def infer(plan, params, xyz, table_f16=None, out=None, sort=True, workspace=None):
+    """Phi(xyz).  sort=True groups the queries by spatial cell on the device
+    first (same values, better cache locality); sort=False keeps the order."""
     torch = _torch()
     n = xyz.shape[0]
     if out is None:
         out = torch.empty(n, dtype=torch.float32, device=xyz.device)
     w = _weights(params, table_f16)
-    _check(lib().ngvol_infer(plan.handle, C.byref(w), _ptr(xyz), n, _ptr(out), _stream()))
+    nb = infer_workspace_bytes(plan, n) if sort else 0
+    if nb and (workspace is None or workspace.numel() < nb):
+        workspace = torch.empty(nb, dtype=torch.uint8, device=xyz.device)
+    ws = workspace if nb else None
+    _check(lib().ngvol_infer(plan.handle, C.byref(w), _ptr(xyz), n, _ptr(out), _ptr(ws), nb, _stream()))
+    return out
+
+
+def sort_queries(plan, xyz, workspace=None):
+    """Group xyz by spatial cell into a workspace for infer_sorted."""
+    torch = _torch()
+    n = xyz.shape[0]
+    nb = infer_workspace_bytes(plan, n)
+    if workspace is None or workspace.numel() < nb:
+        workspace = torch.empty(max(nb, 256), dtype=torch.uint8, device=xyz.device)
+    _check(lib().ngvol_sort_queries(plan.handle, _ptr(xyz), n, _ptr(workspace), workspace.numel(), _stream()))
+    return workspace
+
+
+def infer_sorted(plan, params, workspace, n, table_f16=None, out=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=workspace.device)
+    w = _weights(params, table_f16)
+    _check(lib().ngvol_infer_sorted(plan.handle, C.byref(w), _ptr(workspace), n, _ptr(out), _stream()))
     return out
 
 

@@ -107,7 +107,9 @@ TrainWorkspace train_workspace(const ngvol_plan* plan, int64_t B) {
   ws.g_off = up((size_t)B * plan->kin * esz);
   ws.partial_off = ws.g_off + up((size_t)B * 4);
   ws.misc_off = ws.partial_off + up((size_t)ws.bwd_grid * plan->md.n_mlp * 4);
-  ws.total = ws.misc_off + 256;
+  ws.bin = bin_plan(plan, B);
+  ws.bin_off = ws.misc_off + 256;
+  ws.total = ws.bin_off + (ws.bin.k ? ws.bin.bytes : 0);
   return ws;
 }
 
@@ -128,7 +130,8 @@ int ngvol_plan_create(const ngvol_config* c, ngvol_plan** out) {
   NGV_REQUIRE(c->n_hidden_layers >= 1 && c->n_hidden_layers <= NGVOL_MAX_LAYERS - 1, "n_hidden_layers must be in [1,%d]",
               NGVOL_MAX_LAYERS - 1);
   NGV_REQUIRE(c->n_neurons >= 1, "n_neurons must be positive");
-  NGV_REQUIRE(c->precision == NGVOL_FP32 || c->precision == NGVOL_BF16, "precision must be NGVOL_FP32 or NGVOL_BF16");
+  NGV_REQUIRE(c->precision == NGVOL_FP32 || c->precision == NGVOL_BF16 || c->precision == NGVOL_FP16,
+              "precision must be NGVOL_FP32, NGVOL_BF16 or NGVOL_FP16");
   if (c->n_features != 2 && c->n_features != 4 && c->n_features != 8)
     return fail(NGVOL_EUNSUPPORTED, "n_features %d unsupported (2, 4 or 8)", c->n_features);
   if (c->n_neurons != 32 && c->n_neurons != 64)
@@ -243,19 +246,65 @@ int ngvol_mlp_fwd(const ngvol_plan* plan, const float* params, const void* feat,
   if (n == 0) return NGVOL_OK;
   NGV_REQUIRE(params && feat && out && aligned16(params) && aligned16(feat) && aligned4(out),
               "params and feat must be non-NULL and 16-byte aligned, out 4-byte aligned");
-  NGV_REQUIRE(dtype == NGVOL_DT_F32 || dtype == NGVOL_DT_BF16, "feat dtype must be NGVOL_DT_F32 or NGVOL_DT_BF16");
+  NGV_REQUIRE(dtype == NGVOL_DT_F32 || dtype == NGVOL_DT_BF16 || dtype == NGVOL_DT_F16,
+              "feat dtype must be NGVOL_DT_F32, NGVOL_DT_BF16 or NGVOL_DT_F16");
   return hip_check(launch_mlp_fwd(plan, params + plan->md.n_table, feat, dtype, n, out, st), "mlp_fwd launch");
 }
 
-int ngvol_infer(const ngvol_plan* plan, const ngvol_weights* w, const float* xyz, int64_t n, float* out,
-                hipStream_t st) {
+int ngvol_infer_workspace_bytes(const ngvol_plan* plan, int64_t n, size_t* bytes) {
+  if (int rc = check_plan(plan)) return rc;
+  NGV_REQUIRE(bytes && n >= 0 && n < ((int64_t)1 << 31), "bytes must be non-NULL and 0 <= n < 2^31");
+  const BinPlan bp = bin_plan(plan, n);
+  *bytes = bp.k ? bp.bytes : 0;
+  return NGVOL_OK;
+}
+
+int ngvol_infer(const ngvol_plan* plan, const ngvol_weights* w, const float* xyz, int64_t n, float* out, void* ws,
+                size_t ws_bytes, hipStream_t st) {
   if (int rc = check_plan(plan)) return rc;
   if (int rc = check_weights(w)) return rc;
-  NGV_REQUIRE(n >= 0, "n must be >= 0");
+  NGV_REQUIRE(n >= 0 && n < ((int64_t)1 << 31), "n must be in [0, 2^31)");
   if (n == 0) return NGVOL_OK;
   NGV_REQUIRE(xyz && out && aligned4(xyz) && aligned4(out), "xyz and out must be non-NULL and 4-byte aligned");
-  return hip_check(launch_infer(plan, tables_of(plan, w), w->params + plan->md.n_table, xyz, n, out, st),
-                   "infer launch");
+  NGV_REQUIRE(aligned16(ws), "workspace must be 16-byte aligned");
+  const float* mlp = w->params + plan->md.n_table;
+  const BinPlan bp = bin_plan(plan, n);
+  if (ws && bp.k) {
+    if (ws_bytes < bp.bytes) return fail(NGVOL_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, bp.bytes);
+    hipError_t e = launch_bin(plan, bp, xyz, nullptr, n, ws, st);
+    if (e != hipSuccess) return hip_check(e, "infer binning launch");
+    char* base = reinterpret_cast<char*>(ws);
+    return hip_check(launch_infer(plan, tables_of(plan, w), mlp, reinterpret_cast<const float*>(base + bp.xyz_off),
+                                  reinterpret_cast<const uint32_t*>(base + bp.aux_off), n, out, st),
+                     "infer launch");
+  }
+  return hip_check(launch_infer(plan, tables_of(plan, w), mlp, xyz, nullptr, n, out, st), "infer launch");
+}
+
+int ngvol_sort_queries(const ngvol_plan* plan, const float* xyz, int64_t n, void* ws, size_t ws_bytes,
+                       hipStream_t st) {
+  if (int rc = check_plan(plan)) return rc;
+  NGV_REQUIRE(n > 0 && n < ((int64_t)1 << 31), "n must be in [1, 2^31)");
+  NGV_REQUIRE(xyz && ws && aligned4(xyz) && aligned16(ws), "xyz and workspace must be non-NULL and aligned");
+  const BinPlan bp = bin_plan(plan, n);
+  NGV_REQUIRE(bp.k, "%lld queries are too few to group (ngvol_infer_workspace_bytes is 0)", (long long)n);
+  if (ws_bytes < bp.bytes) return fail(NGVOL_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, bp.bytes);
+  return hip_check(launch_bin(plan, bp, xyz, nullptr, n, ws, st), "sort_queries launch");
+}
+
+int ngvol_infer_sorted(const ngvol_plan* plan, const ngvol_weights* w, const void* ws, int64_t n, float* out,
+                       hipStream_t st) {
+  if (int rc = check_plan(plan)) return rc;
+  if (int rc = check_weights(w)) return rc;
+  NGV_REQUIRE(n > 0 && n < ((int64_t)1 << 31), "n must be in [1, 2^31)");
+  NGV_REQUIRE(ws && out && aligned16(ws) && aligned4(out), "workspace and out must be non-NULL and aligned");
+  const BinPlan bp = bin_plan(plan, n);
+  NGV_REQUIRE(bp.k, "%lld queries are too few to group (ngvol_infer_workspace_bytes is 0)", (long long)n);
+  const char* base = reinterpret_cast<const char*>(ws);
+  return hip_check(launch_infer(plan, tables_of(plan, w), w->params + plan->md.n_table,
+                                reinterpret_cast<const float*>(base + bp.xyz_off),
+                                reinterpret_cast<const uint32_t*>(base + bp.aux_off), n, out, st),
+                   "infer_sorted launch");
 }
 
 int ngvol_mlp_bwd_workspace_bytes(const ngvol_plan* plan, int64_t n, size_t* bytes) {
@@ -283,7 +332,8 @@ int ngvol_mlp_bwd(const ngvol_plan* plan, const float* params, const float* feat
   int32_t* flag = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(ws) + need - 256);
   BatchArgs ba{};
   ba.B = n;
-  hipError_t e = launch_bwd(plan, 1, params + plan->md.n_table, feat, dout, ba, grad, dfeat, partial, grid, flag, st);
+  hipError_t e = launch_bwd(plan, 1, params + plan->md.n_table, feat, dout, ba, grad, dfeat, partial, grid, flag, 1.0f,
+                            st);
   if (e == hipSuccess) e = launch_reduce_partials(plan, partial, grid, grad, flag, st);
   return hip_check(e, "mlp_bwd launch");
 }
@@ -384,8 +434,23 @@ int ngvol_train_step(const ngvol_plan* plan, const ngvol_train_state* s, const n
   const float* mlp = s->params + plan->md.n_table;
   const float gscale = (float)((double)loss_scale * 2.0 / (double)ba.B);
   hipError_t e = launch_step_begin(loss_acc, flag, st);
+  if (e == hipSuccess && ws.bin.k) {
+    // group the batch by spatial cell; the step then runs on the sorted copy
+    e = launch_bin(plan, ws.bin, nullptr, &ba, ba.B, base + ws.bin_off, st);
+    ba.xyz = reinterpret_cast<const float*>(base + ws.bin_off + ws.bin.xyz_off);
+    ba.target = reinterpret_cast<const float*>(base + ws.bin_off + ws.bin.aux_off);
+  }
   if (e == hipSuccess) e = launch_train_fwd(plan, tp, mlp, ba, e_buf, g_buf, loss_acc, gscale, st);
-  if (e == hipSuccess) e = launch_bwd(plan, 0, mlp, e_buf, g_buf, ba, s->grad, nullptr, partial, ws.bwd_grid, flag, st);
+  // 16-bit backward operands carry dz times a power of two that brings the
+  // per-sample gradient scale S*2/B back to about one
+  float bscale = 1.0f;
+  if (plan->layout.precision != NGVOL_FP32) {
+    int ex = (int)lrint(-log2((double)gscale));
+    ex = ex < -24 ? -24 : (ex > 24 ? 24 : ex);
+    bscale = ldexpf(1.0f, ex);
+  }
+  if (e == hipSuccess)
+    e = launch_bwd(plan, 0, mlp, e_buf, g_buf, ba, s->grad, nullptr, partial, ws.bwd_grid, flag, bscale, st);
   if (e == hipSuccess) e = launch_reduce_partials(plan, partial, ws.bwd_grid, s->grad, flag, st);
   AdamArgs aa{a->learning_rate, a->beta1, a->beta2, a->epsilon, 1.0f / loss_scale};
   if (e == hipSuccess)

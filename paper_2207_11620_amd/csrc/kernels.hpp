@@ -34,10 +34,50 @@ struct BatchArgs {
   int64_t step;
 };
 
+// Spatial binning of n samples (k = 0: not binned).  Workspace byte offsets
+// of the sorted coordinates, the per-sample auxiliary array (query
+// permutation or training targets) and the histogram buffers.
+struct BinPlan {
+  int k, n_bins, blocks;
+  int64_t chunk;
+  size_t xyz_off, aux_off, counts_off, totals_off, offsets_off, bytes;
+};
+BinPlan bin_plan(const ngvol_plan* plan, int64_t n);
+// Sorts `xyz` (queries; aux = permutation) or the batch `ba` (training;
+// aux = targets) into the workspace.
+hipError_t launch_bin(const ngvol_plan* plan, const BinPlan& bp, const float* xyz, const struct BatchArgs* ba,
+                      int64_t n, void* ws, hipStream_t st);
+
 // Workspace carve-up of a training step (byte offsets).
 struct TrainWorkspace {
-  size_t e_off, g_off, partial_off, misc_off, total;
+  size_t e_off, g_off, partial_off, misc_off, bin_off, total;
   int bwd_grid;
+  BinPlan bin;
+};
+
+// Persistent tile schedule: waves of workgroups with the same id mod 8 (the
+// XCD a workgroup is dispatched to) walk one contiguous eighth of the tiles,
+// so that spatially sorted samples keep each XCD's L2 working set compact.
+// Every tile is visited exactly once whatever the grid size.
+struct TileIter {
+  int64_t next, step, end;
+  __device__ explicit TileIter(int64_t n_tiles) {
+    const int wpb = blockDim.x >> 6, wave = threadIdx.x >> 6;
+    const int G = gridDim.x;
+    if (G >= 8) {
+      const int x = blockIdx.x & 7, r = blockIdx.x >> 3;
+      const int nbx = (G - x + 7) >> 3;
+      const int64_t per = (n_tiles + 7) >> 3;
+      const int64_t lo = (int64_t)x * per;
+      end = lo + per < n_tiles ? lo + per : n_tiles;
+      next = lo + (int64_t)r * wpb + wave;
+      step = (int64_t)nbx * wpb;
+    } else {
+      next = (int64_t)blockIdx.x * wpb + wave;
+      step = (int64_t)G * wpb;
+      end = n_tiles;
+    }
+  }
 };
 
 size_t fwd_lds_bytes(const ngvol_plan* plan);
@@ -49,8 +89,9 @@ hipError_t launch_encode(const ngvol_plan* plan, TablePtrs tp, const float* xyz,
                          hipStream_t st);
 hipError_t launch_encode_debug(const ngvol_plan* plan, const float* xyz, int64_t n, uint32_t* idx, float* w,
                                hipStream_t st);
-hipError_t launch_infer(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const float* xyz, int64_t n,
-                        float* out, hipStream_t st);
+// perm (nullable): output slot of each sample, out[perm[s]] = Phi(xyz[s]).
+hipError_t launch_infer(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const float* xyz, const uint32_t* perm,
+                        int64_t n, float* out, hipStream_t st);
 hipError_t launch_sq_error_grid(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const void* vol, int dtype,
                                 const int32_t dims[3], double* sq, hipStream_t st);
 hipError_t launch_mlp_fwd(const ngvol_plan* plan, const float* mlp, const void* feat, int dtype, int64_t n,
@@ -66,7 +107,7 @@ hipError_t launch_sample_batch(const BatchArgs& ba, float* xyz, float* y, hipStr
 // ([grid][n_mlp]); launch_reduce_partials adds them into grad.
 hipError_t launch_bwd(const ngvol_plan* plan, int mode, const float* mlp, const void* e_buf, const float* g_buf,
                       const BatchArgs& ba, float* grad, float* dfeat, float* partial, int grid, int32_t* nonfinite,
-                      hipStream_t st);
+                      float bscale, hipStream_t st);
 hipError_t launch_reduce_partials(const ngvol_plan* plan, const float* partial, int grid, float* grad,
                                   int32_t* nonfinite, hipStream_t st);
 hipError_t launch_encode_bwd(const ngvol_plan* plan, const float* xyz, int64_t n, const float* dfeat, float* grad,

@@ -10,15 +10,6 @@ namespace {
 constexpr int kBwdWaves = 4;
 constexpr int kPitch = 20;  // LDS row pitch (elements) of the per-wave transposed buffers
 
-template <int P>
-struct TE {
-  typedef float type;
-};
-template <>
-struct TE<1> {
-  typedef __bf16 type;
-};
-
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -53,10 +44,15 @@ template <int P, int F, int KIN, int W, int MODE>
 __global__ void __launch_bounds__(256) k_bwd(ModelDesc md, const float* __restrict__ mlp,
                                              const void* __restrict__ e_buf, const float* __restrict__ g_buf,
                                              BatchArgs ba, float* __restrict__ grad, float* __restrict__ dfeat,
-                                             float* __restrict__ partial, int32_t* __restrict__ nonfinite) {
+                                             float* __restrict__ partial, int32_t* __restrict__ nonfinite,
+                                             float bscale) {
   typedef typename Prec<P>::Frag Frag;
   typedef WeightLayout<P, KIN, W> WL;
-  typedef typename TE<P>::type T;
+  typedef typename Prec<P>::T T;
+  // 16-bit operands of the backward carry dz * bscale (a power of two chosen
+  // on the host so loss-scaled gradients stay in the normal range); products
+  // are multiplied back by 1/bscale, which is exact.
+  const float ibscale = 1.0f / bscale;
   constexpr int MB = W / 16;
   constexpr int MBI = KIN / 16;
   constexpr int RT = KIN > W ? KIN : W;
@@ -91,10 +87,9 @@ __global__ void __launch_bounds__(256) k_bwd(ModelDesc md, const float* __restri
     for (int j = 0; j < 4; ++j) dwo[mb][j] = 0.0f;
   bool bad = false;
 
-  const int wpb = blockDim.x >> 6;
-  const int64_t first = (int64_t)blockIdx.x * wpb + wave, stride = (int64_t)gridDim.x * wpb;
   const int64_t n_tiles = (B + 15) >> 4;
-  for (int64_t t = first; t < n_tiles; t += stride) {
+  TileIter it(n_tiles);
+  for (int64_t t = it.next; t < it.end; t += it.step) {
     const int64_t s = t * 16 + nl;
     const bool valid = s < B;
     const int64_t sc = valid ? s : B - 1;
@@ -104,8 +99,7 @@ __global__ void __launch_bounds__(256) k_bwd(ModelDesc md, const float* __restri
       if constexpr (P) {
 #pragma unroll
         for (int b = 0; b < KIN / 32; ++b) {
-          const bf16x8 v = *reinterpret_cast<const bf16x8*>(reinterpret_cast<const __bf16*>(e_buf) + sc * KIN +
-                                                            32 * b + 8 * g);
+          const Frag v = *reinterpret_cast<const Frag*>(reinterpret_cast<const T*>(e_buf) + sc * KIN + 32 * b + 8 * g);
 #pragma unroll
           for (int jj = 0; jj < 8; ++jj) f[b][jj] = (float)v[jj];
         }
@@ -130,11 +124,11 @@ __global__ void __launch_bounds__(256) k_bwd(ModelDesc md, const float* __restri
         }
     }
     if constexpr (P) {
-      // the forward saw BF16-rounded inputs; use the same values here
+      // the forward saw 16-bit rounded inputs; use the same values here
 #pragma unroll
       for (int b = 0; b < KIN / 32; ++b)
 #pragma unroll
-        for (int jj = 0; jj < 8; ++jj) f[b][jj] = (float)(__bf16)f[b][jj];
+        for (int jj = 0; jj < 8; ++jj) f[b][jj] = (float)(T)f[b][jj];
     }
     Frag in[InChunks<P, KIN>::n];
     feat_to_frag<P, KIN>(f, in);
@@ -185,7 +179,7 @@ __global__ void __launch_bounds__(256) k_bwd(ModelDesc md, const float* __restri
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) dzT[(16 * mb + 4 * g + j) * kPitch + nl] = (T)dz[mb][j];
+        for (int j = 0; j < 4; ++j) dzT[(16 * mb + 4 * g + j) * kPitch + nl] = (T)(dz[mb][j] * bscale);
       if (li > 0) {
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
@@ -210,7 +204,7 @@ __global__ void __launch_bounds__(256) k_bwd(ModelDesc md, const float* __restri
           if constexpr (P) {
             const T* pa = dzT + (16 * mo + nl) * kPitch + 4 * g;
             const T* pb = aT + (16 * mi + nl) * kPitch + 4 * g;
-            bf16x4 a4, b4;
+            typename Prec<P>::Frag4 a4, b4;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
               a4[q] = pa[q];
@@ -228,7 +222,7 @@ __global__ void __launch_bounds__(256) k_bwd(ModelDesc md, const float* __restri
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
               const int o = 16 * mo + 4 * g + j;
-              if (acc[j] != 0.0f) atomicAdd(dw + o * in_dim + i, acc[j]);
+              if (acc[j] != 0.0f) atomicAdd(dw + o * in_dim + i, acc[j] * ibscale);
             }
           }
         }
@@ -236,7 +230,14 @@ __global__ void __launch_bounds__(256) k_bwd(ModelDesc md, const float* __restri
       wave_sync();
       // dh = W_li^T dz
       Frag dzf[WL::CHH];
-      pack_hidden<P, W>(dz, dzf, false);
+      {
+        f32x4 dzs[MB];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) dzs[mb][j] = dz[mb][j] * bscale;
+        pack_hidden<P, W>(dzs, dzf, false);
+      }
       if (li > 0) {
         const Frag* base = lds_frag + (fwd_frags + WL::FR0T + (li - 1) * WL::FRHT) * 64;
 #pragma unroll
@@ -246,7 +247,7 @@ __global__ void __launch_bounds__(256) k_bwd(ModelDesc md, const float* __restri
           for (int c = 0; c < WL::CHH; ++c) acc = mfma(base[(mb * WL::CHH + c) * 64 + lane], dzf[c], acc);
           const f32x4 zp = zbuf[((li - 1) * MB + mb) * 64 + lane];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) dz[mb][j] = zp[j] > 0.0f ? acc[j] : 0.0f;
+          for (int j = 0; j < 4; ++j) dz[mb][j] = zp[j] > 0.0f ? acc[j] * ibscale : 0.0f;
         }
       } else {
         const Frag* base = lds_frag + fwd_frags * 64;
@@ -255,6 +256,8 @@ __global__ void __launch_bounds__(256) k_bwd(ModelDesc md, const float* __restri
           f32x4 acc = zero4();
 #pragma unroll
           for (int c = 0; c < WL::CHH; ++c) acc = mfma(base[(mb * WL::CHH + c) * 64 + lane], dzf[c], acc);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[j] *= ibscale;
           de[mb] = acc;
         }
       }
@@ -430,7 +433,7 @@ int bwd_grid(const ngvol_plan* plan, int64_t n) {
 
 hipError_t launch_bwd(const ngvol_plan* plan, int mode, const float* mlp, const void* e_buf, const float* g_buf,
                       const BatchArgs& ba, float* grad, float* dfeat, float* partial, int grid, int32_t* nonfinite,
-                      hipStream_t st) {
+                      float bscale, hipStream_t st) {
   const ModelDesc& md = plan->md;
   const size_t lds = bwd_lds_bytes(plan, kBwdWaves);
   const int P_ = plan->layout.precision;
@@ -438,10 +441,10 @@ hipError_t launch_bwd(const ngvol_plan* plan, int mode, const float* mlp, const 
   do {                                                                                                             \
     if (mode == 0)                                                                                                 \
       hipLaunchKernelGGL((k_bwd<P, F, KIN, W, 0>), dim3(grid), dim3(64 * kBwdWaves), lds, st, md, mlp, e_buf, g_buf, \
-                         ba, grad, dfeat, partial, nonfinite);                                                     \
+                         ba, grad, dfeat, partial, nonfinite, bscale);                                             \
     else                                                                                                           \
       hipLaunchKernelGGL((k_bwd<P, 2, KIN, W, 1>), dim3(grid), dim3(64 * kBwdWaves), lds, st, md, mlp, e_buf, g_buf, \
-                         ba, grad, dfeat, partial, nonfinite);                                                     \
+                         ba, grad, dfeat, partial, nonfinite, bscale);                                             \
   } while (0)
 #define NGV_BWD_W(P, F, KIN)                                   \
   do {                                                         \
@@ -462,6 +465,7 @@ hipError_t launch_bwd(const ngvol_plan* plan, int mode, const float* mlp, const 
     }                                                                   \
   } while (0)
   if (P_ == 1) NGV_BWD_FK(1);
+  else if (P_ == 2) NGV_BWD_FK(2);
   else NGV_BWD_FK(0);
 #undef NGV_BWD_FK
 #undef NGV_BWD_W

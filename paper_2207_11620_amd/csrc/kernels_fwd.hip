@@ -6,19 +6,6 @@
 namespace ngvol {
 
 // ---------------------------------------------------------------------------
-// Persistent tile loop helpers.  A wave owns tiles wave_id, wave_id + n_waves,
-// ...; each tile is 16 samples, one per lane%16.
-// ---------------------------------------------------------------------------
-struct TileIter {
-  int64_t first, stride;
-  __device__ TileIter() {
-    const int wpb = blockDim.x >> 6;
-    first = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
-    stride = (int64_t)gridDim.x * wpb;
-  }
-};
-
-// ---------------------------------------------------------------------------
 // Standalone encoding: feat[n][n_in] FP32.
 // ---------------------------------------------------------------------------
 template <int F, int KIN, typename TT>
@@ -26,9 +13,9 @@ __global__ void __launch_bounds__(256) k_encode(ModelDesc md, TablePtrs tp, cons
                                                 float* __restrict__ feat) {
   const TT* table = table_ptr<TT>(tp);
   const int lane = threadIdx.x & 63, nl = lane & 15, g = lane >> 4;
-  TileIter it;
   const int64_t n_tiles = (n + 15) >> 4;
-  for (int64_t t = it.first; t < n_tiles; t += it.stride) {
+  TileIter it(n_tiles);
+  for (int64_t t = it.next; t < it.end; t += it.step) {
     const int64_t s = t * 16 + nl;
     if (s >= n) continue;
     const float x = clamp01(xyz[3 * s]), y = clamp01(xyz[3 * s + 1]), z = clamp01(xyz[3 * s + 2]);
@@ -66,7 +53,8 @@ __global__ void __launch_bounds__(256) k_encode_debug(ModelDesc md, const float*
 // ---------------------------------------------------------------------------
 template <int P, int F, int KIN, int W, typename TT, int MODE, typename VT>
 __global__ void __launch_bounds__(256) k_infer(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp,
-                                               const float* __restrict__ xyz, int64_t n, float* __restrict__ out,
+                                               const float* __restrict__ xyz, const uint32_t* __restrict__ perm,
+                                               int64_t n, float* __restrict__ out,
                                                const VT* __restrict__ vol, int dx, int dy, int dz,
                                                double* __restrict__ sq_sum) {
   typedef typename Prec<P>::Frag Frag;
@@ -80,9 +68,9 @@ __global__ void __launch_bounds__(256) k_infer(ModelDesc md, TablePtrs tp, const
   const TT* table = table_ptr<TT>(tp);
   const int lane = threadIdx.x & 63, nl = lane & 15, g = lane >> 4;
   double err = 0.0;
-  TileIter it;
   const int64_t n_tiles = (n + 15) >> 4;
-  for (int64_t t = it.first; t < n_tiles; t += it.stride) {
+  TileIter it(n_tiles);
+  for (int64_t t = it.next; t < it.end; t += it.step) {
     const int64_t s = t * 16 + nl;
     const bool valid = s < n;
     float x, y, z;
@@ -107,7 +95,7 @@ __global__ void __launch_bounds__(256) k_infer(ModelDesc md, TablePtrs tp, const
     const float yv = mlp_output<W>(act, lds_wout);
     if (valid && g == 0) {
       if constexpr (MODE == 0) {
-        out[s] = yv;
+        out[perm ? (int64_t)perm[s] : s] = yv;
       } else {
         const double d = (double)yv - (double)load_vox<VT>(vol, (size_t)s);
         err += d * d;
@@ -129,6 +117,8 @@ template <>
 __device__ __forceinline__ float load_feat<float>(const float* p, int64_t i) { return p[i]; }
 template <>
 __device__ __forceinline__ float load_feat<__bf16>(const __bf16* p, int64_t i) { return (float)p[i]; }
+template <>
+__device__ __forceinline__ float load_feat<_Float16>(const _Float16* p, int64_t i) { return (float)p[i]; }
 
 template <int P, int KIN, int W, typename IT>
 __global__ void __launch_bounds__(256) k_mlp_fwd(ModelDesc md, const float* __restrict__ mlp,
@@ -142,9 +132,9 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(ModelDesc md, const float* __re
   __syncthreads();
   const int lane = threadIdx.x & 63, nl = lane & 15, g = lane >> 4;
   const int n_in = md.n_in;
-  TileIter it;
   const int64_t n_tiles = (n + 15) >> 4;
-  for (int64_t t = it.first; t < n_tiles; t += it.stride) {
+  TileIter it(n_tiles);
+  for (int64_t t = it.next; t < it.end; t += it.step) {
     const int64_t s = t * 16 + nl;
     const bool valid = s < n;
     const int64_t sc = valid ? s : n - 1;
@@ -155,7 +145,7 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(ModelDesc md, const float* __re
 #pragma unroll
         for (int b = 0; b < KIN / 32; ++b) {
           const uint4 raw = *reinterpret_cast<const uint4*>(feat + sc * KIN + 32 * b + 8 * g);
-          const __bf16* h = reinterpret_cast<const __bf16*>(&raw);
+          const IT* h = reinterpret_cast<const IT*>(&raw);
 #pragma unroll
           for (int jj = 0; jj < 8; ++jj) f[b][jj] = (float)h[jj];
         }
@@ -207,9 +197,9 @@ __global__ void __launch_bounds__(256) k_train_fwd(ModelDesc md, TablePtrs tp, c
   const int lane = threadIdx.x & 63, nl = lane & 15, g = lane >> 4;
   const int64_t B = ba.B;
   double lsum = 0.0;
-  TileIter it;
   const int64_t n_tiles = (B + 15) >> 4;
-  for (int64_t t = it.first; t < n_tiles; t += it.stride) {
+  TileIter it(n_tiles);
+  for (int64_t t = it.next; t < it.end; t += it.step) {
     const int64_t s = t * 16 + nl;
     const bool valid = s < B;
     const int64_t sc = valid ? s : B - 1;
@@ -229,12 +219,13 @@ __global__ void __launch_bounds__(256) k_train_fwd(ModelDesc md, TablePtrs tp, c
     encode_lane<F, KIN>(md, table, x, y, z, f);
     if (valid) {
       if constexpr (P) {
+        typedef typename Prec<P>::T T16;
 #pragma unroll
         for (int b = 0; b < KIN / 32; ++b) {
-          bf16x8 v;
+          Frag v;
 #pragma unroll
-          for (int jj = 0; jj < 8; ++jj) v[jj] = (__bf16)f[b][jj];
-          *reinterpret_cast<bf16x8*>(reinterpret_cast<__bf16*>(e_buf) + sc * KIN + 32 * b + 8 * g) = v;
+          for (int jj = 0; jj < 8; ++jj) v[jj] = (T16)f[b][jj];
+          *reinterpret_cast<Frag*>(reinterpret_cast<T16*>(e_buf) + sc * KIN + 32 * b + 8 * g) = v;
         }
       } else {
 #pragma unroll
@@ -299,6 +290,7 @@ __global__ void __launch_bounds__(256) k_sample_batch(BatchArgs ba, float* __res
   switch (P_) {                                                              \
     case 0: { constexpr int P = 0; __VA_ARGS__; } break;                     \
     case 1: { constexpr int P = 1; __VA_ARGS__; } break;                     \
+    case 2: { constexpr int P = 2; __VA_ARGS__; } break;                     \
     default: return hipErrorInvalidValue;                                    \
   }
 
@@ -341,8 +333,9 @@ hipError_t launch_encode_debug(const ngvol_plan* plan, const float* xyz, int64_t
 }
 
 template <int MODE, typename VT>
-static hipError_t launch_infer_t(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const float* xyz, int64_t n,
-                                 float* out, const VT* vol, int dx, int dy, int dz, double* sq, hipStream_t st) {
+static hipError_t launch_infer_t(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const float* xyz,
+                                 const uint32_t* perm, int64_t n, float* out, const VT* vol, int dx, int dy, int dz,
+                                 double* sq, hipStream_t st) {
   const ModelDesc& md = plan->md;
   const int64_t n_tiles = (n + 15) / 16;
   const size_t lds = fwd_lds_bytes(plan);
@@ -350,27 +343,27 @@ static hipError_t launch_infer_t(const ngvol_plan* plan, TablePtrs tp, const flo
   NGV_DISPATCH_P(plan->layout.precision, NGV_DISPATCH_F_KIN(md.F, plan->kin, NGV_DISPATCH_W(md.width, {
     if (tp.f16)
       hipLaunchKernelGGL((k_infer<P, F, KIN, W, __half, MODE, VT>), dim3(grid), dim3(256), lds, st, md, tp, mlp, xyz,
-                         n, out, vol, dx, dy, dz, sq);
+                         perm, n, out, vol, dx, dy, dz, sq);
     else
       hipLaunchKernelGGL((k_infer<P, F, KIN, W, float, MODE, VT>), dim3(grid), dim3(256), lds, st, md, tp, mlp, xyz,
-                         n, out, vol, dx, dy, dz, sq);
+                         perm, n, out, vol, dx, dy, dz, sq);
   })));
   return hipGetLastError();
 }
 
-hipError_t launch_infer(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const float* xyz, int64_t n,
-                        float* out, hipStream_t st) {
-  return launch_infer_t<0, float>(plan, tp, mlp, xyz, n, out, nullptr, 1, 1, 1, nullptr, st);
+hipError_t launch_infer(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const float* xyz, const uint32_t* perm,
+                        int64_t n, float* out, hipStream_t st) {
+  return launch_infer_t<0, float>(plan, tp, mlp, xyz, perm, n, out, nullptr, 1, 1, 1, nullptr, st);
 }
 
 hipError_t launch_sq_error_grid(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const void* vol, int dtype,
                                 const int32_t dims[3], double* sq, hipStream_t st) {
   const int64_t n = (int64_t)dims[0] * dims[1] * dims[2];
   if (dtype == NGVOL_DT_F16)
-    return launch_infer_t<1, __half>(plan, tp, mlp, nullptr, n, nullptr, reinterpret_cast<const __half*>(vol),
-                                     dims[0], dims[1], dims[2], sq, st);
-  return launch_infer_t<1, float>(plan, tp, mlp, nullptr, n, nullptr, reinterpret_cast<const float*>(vol), dims[0],
-                                  dims[1], dims[2], sq, st);
+    return launch_infer_t<1, __half>(plan, tp, mlp, nullptr, nullptr, n, nullptr,
+                                     reinterpret_cast<const __half*>(vol), dims[0], dims[1], dims[2], sq, st);
+  return launch_infer_t<1, float>(plan, tp, mlp, nullptr, nullptr, n, nullptr, reinterpret_cast<const float*>(vol),
+                                  dims[0], dims[1], dims[2], sq, st);
 }
 
 hipError_t launch_mlp_fwd(const ngvol_plan* plan, const float* mlp, const void* feat, int dtype, int64_t n,
@@ -383,18 +376,22 @@ hipError_t launch_mlp_fwd(const ngvol_plan* plan, const float* mlp, const void* 
     switch (plan->kin * 100 + md.width) {
       case 3232: { constexpr int KIN = 32, W = 32;
         if (dtype == NGVOL_DT_BF16) hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, __bf16>), dim3(grid), dim3(256), lds, st, md, mlp, (const __bf16*)feat, n, out);
+        else if (dtype == NGVOL_DT_F16) hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, _Float16>), dim3(grid), dim3(256), lds, st, md, mlp, (const _Float16*)feat, n, out);
         else hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, float>), dim3(grid), dim3(256), lds, st, md, mlp, (const float*)feat, n, out);
       } break;
       case 3264: { constexpr int KIN = 32, W = 64;
         if (dtype == NGVOL_DT_BF16) hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, __bf16>), dim3(grid), dim3(256), lds, st, md, mlp, (const __bf16*)feat, n, out);
+        else if (dtype == NGVOL_DT_F16) hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, _Float16>), dim3(grid), dim3(256), lds, st, md, mlp, (const _Float16*)feat, n, out);
         else hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, float>), dim3(grid), dim3(256), lds, st, md, mlp, (const float*)feat, n, out);
       } break;
       case 6432: { constexpr int KIN = 64, W = 32;
         if (dtype == NGVOL_DT_BF16) hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, __bf16>), dim3(grid), dim3(256), lds, st, md, mlp, (const __bf16*)feat, n, out);
+        else if (dtype == NGVOL_DT_F16) hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, _Float16>), dim3(grid), dim3(256), lds, st, md, mlp, (const _Float16*)feat, n, out);
         else hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, float>), dim3(grid), dim3(256), lds, st, md, mlp, (const float*)feat, n, out);
       } break;
       case 6464: { constexpr int KIN = 64, W = 64;
         if (dtype == NGVOL_DT_BF16) hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, __bf16>), dim3(grid), dim3(256), lds, st, md, mlp, (const __bf16*)feat, n, out);
+        else if (dtype == NGVOL_DT_F16) hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, _Float16>), dim3(grid), dim3(256), lds, st, md, mlp, (const _Float16*)feat, n, out);
         else hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, float>), dim3(grid), dim3(256), lds, st, md, mlp, (const float*)feat, n, out);
       } break;
       default: return hipErrorInvalidValue;

@@ -289,6 +289,7 @@ hipError_t launch_render(const ngvol_plan* plan, TablePtrs tp, const float* mlp,
     }                                                                 \
   } while (0)
   if (plan->layout.precision == 1) NGV_RENDER_FK(1);
+  else if (plan->layout.precision == 2) NGV_RENDER_FK(2);
   else NGV_RENDER_FK(0);
 #undef NGV_RENDER_FK
 #undef NGV_RENDER_W

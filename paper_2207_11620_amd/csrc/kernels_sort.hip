@@ -1,0 +1,209 @@
+// Spatial binning of sample coordinates.
+//
+// Random query or training coordinates make every table gather (and every
+// gradient scatter) touch an unrelated cache line.  Reordering the samples
+// so that consecutive 16-sample tiles lie in the same small cell of space
+// lets neighbouring samples share the coarse and middle levels' lines in L2.
+// The order of samples does not change any result of the method (queries
+// are written back to their own slots; the training loss is a sum).
+//
+// The reorder is a counting sort by the Morton code of the sample's cell in
+// a 2^k x 2^k x 2^k grid (k = 4 or 5): per-block LDS histograms, a per-bin
+// prefix over blocks, one scan of the bin totals, and a scatter with LDS
+// cursors.  Within a (block, bin) pair the order is not preserved; only the
+// grouping matters.
+#include "kernels.hpp"
+#include "device_common.hpp"
+
+namespace ngvol {
+
+namespace {
+
+constexpr int kSortThreads = 1024;
+
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {
+  v &= 0x3ffu;
+  v = (v | (v << 16)) & 0x030000FFu;
+  v = (v | (v << 8)) & 0x0300F00Fu;
+  v = (v | (v << 4)) & 0x030C30C3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+__device__ __forceinline__ uint32_t cell_key(float x, float y, float z, int k) {
+  const float s = (float)(1 << k);
+  const uint32_t m = (1u << k) - 1u;
+  const uint32_t qx = min((uint32_t)(clamp01(x) * s), m);
+  const uint32_t qy = min((uint32_t)(clamp01(y) * s), m);
+  const uint32_t qz = min((uint32_t)(clamp01(z) * s), m);
+  return spread3(qx) | (spread3(qy) << 1) | (spread3(qz) << 2);
+}
+
+// Coordinates of sample i: explicit array, or the training-batch generator.
+struct Src {
+  const float* xyz;
+  uint64_t seed;
+  int64_t step, B;
+  __device__ __forceinline__ void get(int64_t i, float& x, float& y, float& z) const {
+    if (xyz) {
+      x = xyz[3 * i];
+      y = xyz[3 * i + 1];
+      z = xyz[3 * i + 2];
+    } else {
+      x = batch_coord(seed, step, B, i, 0);
+      y = batch_coord(seed, step, B, i, 1);
+      z = batch_coord(seed, step, B, i, 2);
+    }
+  }
+};
+
+__global__ void __launch_bounds__(kSortThreads) k_bin_hist(Src src, int64_t n, int k, int64_t chunk,
+                                                           uint32_t* __restrict__ counts) {
+  extern __shared__ uint32_t hist[];
+  const int nb = 1 << (3 * k);
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) hist[b] = 0u;
+  __syncthreads();
+  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t hi = lo + chunk < n ? lo + chunk : n;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    float x, y, z;
+    src.get(i, x, y, z);
+    atomicAdd(hist + cell_key(x, y, z, k), 1u);
+  }
+  __syncthreads();
+  uint32_t* dst = counts + (size_t)blockIdx.x * nb;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) dst[b] = hist[b];
+}
+
+// counts[blk][bin] <- exclusive prefix over blocks; totals[bin] <- sum.
+__global__ void __launch_bounds__(256) k_bin_prefix(uint32_t* __restrict__ counts, int blocks, int nb,
+                                                    uint32_t* __restrict__ totals) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  uint32_t run = 0;
+  for (int k = 0; k < blocks; ++k) {
+    const uint32_t v = counts[(size_t)k * nb + b];
+    counts[(size_t)k * nb + b] = run;
+    run += v;
+  }
+  totals[b] = run;
+}
+
+// Exclusive scan of the bin totals, one block.
+__global__ void __launch_bounds__(kSortThreads) k_bin_scan(const uint32_t* __restrict__ totals, int nb,
+                                                           uint32_t* __restrict__ offsets) {
+  __shared__ uint32_t part[kSortThreads];
+  const int per = (nb + kSortThreads - 1) / kSortThreads;
+  const int lo = threadIdx.x * per;
+  uint32_t s = 0;
+  for (int i = 0; i < per; ++i)
+    if (lo + i < nb) s += totals[lo + i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int d = 1; d < kSortThreads; d <<= 1) {
+    const uint32_t v = threadIdx.x >= (unsigned)d ? part[threadIdx.x - d] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[threadIdx.x] - s;  // exclusive
+  for (int i = 0; i < per; ++i)
+    if (lo + i < nb) {
+      offsets[lo + i] = run;
+      run += totals[lo + i];
+    }
+}
+
+// Scatter: sorted xyz, and either the original index (queries) or the
+// target value (training: explicit or sampled from the volume).
+template <typename VT>
+__global__ void __launch_bounds__(kSortThreads) k_bin_scatter(Src src, int64_t n, int k, int64_t chunk,
+                                                              const uint32_t* __restrict__ counts,
+                                                              const uint32_t* __restrict__ offsets,
+                                                              float* __restrict__ out_xyz, uint32_t* __restrict__ perm,
+                                                              const float* __restrict__ target_in,
+                                                              const VT* __restrict__ vol, int dx, int dy, int dz,
+                                                              float* __restrict__ out_target) {
+  extern __shared__ uint32_t cur[];
+  const int nb = 1 << (3 * k);
+  const uint32_t* mine = counts + (size_t)blockIdx.x * nb;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) cur[b] = offsets[b] + mine[b];
+  __syncthreads();
+  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t hi = lo + chunk < n ? lo + chunk : n;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    float x, y, z;
+    src.get(i, x, y, z);
+    const uint32_t pos = atomicAdd(cur + cell_key(x, y, z, k), 1u);
+    out_xyz[3 * (size_t)pos] = x;
+    out_xyz[3 * (size_t)pos + 1] = y;
+    out_xyz[3 * (size_t)pos + 2] = z;
+    if (perm) perm[pos] = (uint32_t)i;
+    if (out_target) {
+      if (target_in) out_target[pos] = target_in[i];
+      else out_target[pos] = volume_sample<VT>(vol, dx, dy, dz, x, y, z);
+    }
+  }
+}
+
+}  // namespace
+
+BinPlan bin_plan(const ngvol_plan* plan, int64_t n) {
+  BinPlan bp{};
+  if (n < ((int64_t)1 << 15)) return bp;  // too small to pay off
+  bp.k = n >= ((int64_t)1 << 22) ? 5 : 4;
+  bp.n_bins = 1 << (3 * bp.k);
+  int64_t g = (n + 4095) / 4096;
+  if (g > plan->cus) g = plan->cus;
+  if (g < 1) g = 1;
+  bp.blocks = (int)g;
+  bp.chunk = (n + g - 1) / g;
+  auto up = [](size_t v) { return (v + 255) / 256 * 256; };
+  bp.xyz_off = 0;
+  bp.aux_off = up((size_t)n * 12);  // perm (queries) or targets (training)
+  bp.counts_off = bp.aux_off + up((size_t)n * 4);
+  bp.totals_off = bp.counts_off + up((size_t)bp.blocks * bp.n_bins * 4);
+  bp.offsets_off = bp.totals_off + up((size_t)bp.n_bins * 4);
+  bp.bytes = bp.offsets_off + up((size_t)bp.n_bins * 4);
+  return bp;
+}
+
+hipError_t launch_bin(const ngvol_plan* plan, const BinPlan& bp, const float* xyz, const BatchArgs* ba, int64_t n,
+                      void* ws, hipStream_t st) {
+  (void)plan;
+  char* base = reinterpret_cast<char*>(ws);
+  float* sx = reinterpret_cast<float*>(base + bp.xyz_off);
+  uint32_t* counts = reinterpret_cast<uint32_t*>(base + bp.counts_off);
+  uint32_t* totals = reinterpret_cast<uint32_t*>(base + bp.totals_off);
+  uint32_t* offsets = reinterpret_cast<uint32_t*>(base + bp.offsets_off);
+  Src src{xyz, 0, 0, n};
+  if (ba) {
+    src.xyz = ba->xyz;
+    src.seed = ba->seed;
+    src.step = ba->step;
+    src.B = ba->B;
+  }
+  const size_t lds = (size_t)bp.n_bins * 4;
+  hipLaunchKernelGGL(k_bin_hist, dim3(bp.blocks), dim3(kSortThreads), lds, st, src, n, bp.k, bp.chunk, counts);
+  hipLaunchKernelGGL(k_bin_prefix, dim3((bp.n_bins + 255) / 256), dim3(256), 0, st, counts, bp.blocks, bp.n_bins,
+                     totals);
+  hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(kSortThreads), 0, st, totals, bp.n_bins, offsets);
+  if (!ba) {
+    uint32_t* perm = reinterpret_cast<uint32_t*>(base + bp.aux_off);
+    hipLaunchKernelGGL(k_bin_scatter<float>, dim3(bp.blocks), dim3(kSortThreads), lds, st, src, n, bp.k, bp.chunk,
+                       counts, offsets, sx, perm, nullptr, nullptr, 1, 1, 1, nullptr);
+  } else {
+    float* tg = reinterpret_cast<float*>(base + bp.aux_off);
+    if (ba->xyz || ba->vdtype != NGVOL_DT_F16)
+      hipLaunchKernelGGL(k_bin_scatter<float>, dim3(bp.blocks), dim3(kSortThreads), lds, st, src, n, bp.k, bp.chunk,
+                         counts, offsets, sx, nullptr, ba->target, reinterpret_cast<const float*>(ba->volume),
+                         ba->dims[0], ba->dims[1], ba->dims[2], tg);
+    else
+      hipLaunchKernelGGL(k_bin_scatter<__half>, dim3(bp.blocks), dim3(kSortThreads), lds, st, src, n, bp.k,
+                         bp.chunk, counts, offsets, sx, nullptr, nullptr, reinterpret_cast<const __half*>(ba->volume),
+                         ba->dims[0], ba->dims[1], ba->dims[2], tg);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace ngvol

@@ -11,6 +11,7 @@
 //
 // Two precisions share this structure:
 //   P = 1: BF16 operands, v_mfma_f32_16x16x32_bf16 (K = 32 per instruction);
+//   P = 2: FP16 operands, v_mfma_f32_16x16x32_f16 (K = 32, same lane layout);
 //   P = 0: FP32 operands, v_mfma_f32_16x16x4_f32 (K = 4 per instruction).
 // Both accumulate in FP32.
 //
@@ -25,10 +26,15 @@ namespace ngvol {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ f32x4 mfma(const bf16x8& a, const bf16x8& b, const f32x4& c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mfma(const f16x8& a, const f16x8& b, const f32x4& c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
 }
 __device__ __forceinline__ f32x4 mfma(float a, float b, const f32x4& c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -36,6 +42,9 @@ __device__ __forceinline__ f32x4 mfma(float a, float b, const f32x4& c) {
 // K = 16 BF16 product, used where the contraction runs over the 16 samples of a tile.
 __device__ __forceinline__ f32x4 mfma_k16(const bf16x4& a, const bf16x4& b, const f32x4& c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mfma_k16(const f16x4& a, const f16x4& b, const f32x4& c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
 }
 
 __device__ __forceinline__ f32x4 zero4() { return f32x4{0.0f, 0.0f, 0.0f, 0.0f}; }
@@ -45,18 +54,35 @@ struct Prec;
 
 template <>
 struct Prec<1> {
+  typedef __bf16 T;
   typedef bf16x8 Frag;
+  typedef bf16x4 Frag4;
   static constexpr int K = 32;
   static __device__ __forceinline__ Frag zero() {
     Frag f;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) f[i] = (__bf16)0.0f;
+    for (int i = 0; i < 8; ++i) f[i] = (T)0.0f;
+    return f;
+  }
+};
+
+template <>
+struct Prec<2> {
+  typedef _Float16 T;
+  typedef f16x8 Frag;
+  typedef f16x4 Frag4;
+  static constexpr int K = 32;
+  static __device__ __forceinline__ Frag zero() {
+    Frag f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) f[i] = (T)0.0f;
     return f;
   }
 };
 
 template <>
 struct Prec<0> {
+  typedef float T;
   typedef float Frag;
   static constexpr int K = 4;
   static __device__ __forceinline__ Frag zero() { return 0.0f; }
@@ -168,7 +194,7 @@ __device__ void stage_weights(const ModelDesc& md, const float* __restrict__ mlp
         const int col = hid_col<P>(c, g, jj);
         if (row < in_dim && col < W) x = Wm[col * in_dim + row];
       }
-      if constexpr (P) val[jj] = (__bf16)x;
+      if constexpr (P) val[jj] = (typename Prec<P>::T)x;
       else val = x;
     }
     lds_frag[t] = val;
@@ -195,7 +221,7 @@ __device__ __forceinline__ void pack_hidden(const f32x4 act[W / 16], typename Pr
         const int m = 2 * c + (jj >> 2);
         float v = (m < W / 16) ? act[m < W / 16 ? m : 0][jj & 3] : 0.0f;
         if (relu) v = fmaxf(v, 0.0f);
-        out[c][jj] = (__bf16)v;
+        out[c][jj] = (typename Prec<P>::T)v;
       }
     } else {
       float v = act[c >> 2][c & 3];
@@ -293,7 +319,7 @@ __device__ __forceinline__ void feat_to_frag(const float feat[KIN / 32][8],
   for (int b = 0; b < KIN / 32; ++b) {
     if constexpr (P) {
 #pragma unroll
-      for (int jj = 0; jj < 8; ++jj) out[b][jj] = (__bf16)feat[b][jj];
+      for (int jj = 0; jj < 8; ++jj) out[b][jj] = (typename Prec<P>::T)feat[b][jj];
     } else {
 #pragma unroll
       for (int jj = 0; jj < 8; ++jj) out[8 * b + jj] = feat[b][jj];

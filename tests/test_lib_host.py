@@ -109,14 +109,20 @@ def test_null_arguments_rejected_without_launch():
     L = _lib_or_skip()
     p = ngv.Plan(**CFG0)
     w = ngv.Weights(None, None)
-    assert L.ngvol_infer(p.handle, C.byref(w), None, 10, None, None) == ngv.EINVAL
-    assert L.ngvol_infer(None, C.byref(w), None, 10, None, None) == ngv.EINVAL
+    assert L.ngvol_infer(p.handle, C.byref(w), None, 10, None, None, 0, None) == ngv.EINVAL
+    assert L.ngvol_infer(None, C.byref(w), None, 10, None, None, 0, None) == ngv.EINVAL
     assert b"NULL" in L.ngvol_last_error()
     # misaligned pointers are rejected before any launch
     w2 = ngv.Weights(C.c_void_p(16), None)
-    assert L.ngvol_infer(p.handle, C.byref(w2), C.c_void_p(18), 10, C.c_void_p(32), None) == ngv.EINVAL
-    # n = 0 is a no-op even with null data pointers... after the weights check
-    assert L.ngvol_infer(p.handle, C.byref(w2), None, 0, None, None) == ngv.OK
+    assert L.ngvol_infer(p.handle, C.byref(w2), C.c_void_p(18), 10, C.c_void_p(32), None, 0, None) == ngv.EINVAL
+    # n = 0 is a no-op even with null data pointers (after the weights check)
+    assert L.ngvol_infer(p.handle, C.byref(w2), None, 0, None, None, 0, None) == ngv.OK
+    # a workspace smaller than needed is refused
+    nb = C.c_size_t()
+    assert L.ngvol_infer_workspace_bytes(p.handle, 1 << 20, C.byref(nb)) == ngv.OK and nb.value > (1 << 20) * 16
+    assert L.ngvol_infer(p.handle, C.byref(w2), C.c_void_p(32), 1 << 20, C.c_void_p(64), C.c_void_p(128), 64,
+                         None) == ngv.ENOMEM
+    assert L.ngvol_infer_workspace_bytes(p.handle, 1000, C.byref(nb)) == ngv.OK and nb.value == 0
     sz = C.c_size_t()
     assert L.ngvol_train_workspace_bytes(p.handle, 4096, C.byref(sz)) == ngv.OK
     assert sz.value > 4096 * 32 * 4
