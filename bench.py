@@ -10,9 +10,10 @@ metric is encode+MLP samples/s over the whole step: (2^18 + 2^24) / step
 time.  Inputs are synthetic and resident in HBM before timing starts.
 
 Also reported: the same two legs in the plain FP32 form, the PSNR of both
-forms after identical training (quality leg), the roofline of the query
-kernel (measured with events on the launch stream) and the FP64 CPU oracle
-timed on a bounded sample of the same workload.
+forms after identical training (quality leg), online rendering (1024^2
+frames through the trained model with one training step per frame), the
+roofline of the query kernel (measured with events on the launch stream)
+and the FP64 CPU oracle timed on a bounded sample of the same workload.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -56,6 +57,8 @@ def main():
     ap.add_argument("--no-quality", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--render-frames", type=int, default=8)
+    ap.add_argument("--no-render", action="store_true")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -171,11 +174,14 @@ def main():
     # several dB), so each form is trained several times from the same
     # initialisation with different batch seeds and the means are compared.
     quality = None
+    trained = None
     if not args.no_quality:
         res = {"bf16": [], "fp32": []}
         for r in range(args.quality_repeats):
             for name, plan, f16, ls in (("bf16", plan16, True, LOSS_SCALE), ("fp32", plan32, False, 1.0)):
                 s = ngv.TrainState(plan, params0, B_TRAIN, f16_tables=f16)
+                if r == 0 and name == "bf16":
+                    trained = s  # kept for the rendering leg
                 q0 = time.perf_counter()
                 for k in range(args.quality_steps):
                     ngv.train_step(s, volume=vol, seed=SEED + r, step_index=k, loss_scale=ls, **ADAM)
@@ -184,13 +190,58 @@ def main():
                 res[name].append(ngv.psnr(plan, pr, vol, table_f16=tf))
                 log(f"quality {name} run {r}: {args.quality_steps} steps in {time.perf_counter() - q0:.1f}s, "
                     f"PSNR {res[name][-1]:.3f} dB")
-                del s
+                if s is not trained:
+                    del s
         mb, mf = float(np.mean(res["bf16"])), float(np.mean(res["fp32"]))
         quality = {"steps": args.quality_steps, "batch": B_TRAIN, "volume": f"{VOL_D}^3 fbm f32",
                    "repeats": args.quality_repeats, "psnr_bf16_db": [round(v, 3) for v in res["bf16"]],
                    "psnr_fp32_db": [round(v, 3) for v in res["fp32"]], "mean_bf16_db": round(mb, 3),
                    "mean_fp32_db": round(mf, 3), "psnr_loss_db": round(mf - mb, 3),
                    "fp32_run_to_run_std_db": round(float(np.std(res["fp32"])), 3)}
+
+    # ---------------------------------------------------- online render leg
+    # 1024^2 frames through the trained BF16 model (the quality leg's first
+    # run, or the timed state if that leg was skipped), one training step of
+    # B = 2^16 per frame, camera on an orbit; Delta = 1/1024 with jitter.
+    render = None
+    if not args.no_render:
+        W = H = 1024
+        dt = 1.0 / 1024
+        lut = torch.from_numpy(synth.transfer_function_lut()).to(dev)
+        rs = trained if trained is not None else st
+        online = ngv.TrainState(plan16, rs.params, 1 << 16, f16_tables=True)
+        rgba = torch.empty((H, W, 4), dtype=torch.float32, device=dev)
+        rws = torch.empty(256, dtype=torch.uint8, device=dev)
+        cnt = torch.zeros(4, dtype=torch.int64, device=dev)
+        cams = [synth.orbit_camera(2 * math.pi * f / max(args.render_frames, 1), W, H)
+                for f in range(args.render_frames + 1)]
+        # warm-up frame
+        ngv.render(plan16, online.params, cams[0], lut, W, H, dt, 0, table_f16=online.table_f16,
+                   want_counts=False, rgba=rgba, workspace=rws, counters=cnt)
+        torch.cuda.synchronize()
+        ev_r = [(ev(), ev(), ev()) for _ in range(args.render_frames)]
+        evals = used = 0
+        for f in range(args.render_frames):
+            ev_r[f][0].record()
+            ngv.train_step(online, volume=vol, seed=SEED + 77, step_index=f, loss_scale=LOSS_SCALE, **ADAM)
+            ev_r[f][1].record()
+            ngv.render(plan16, online.params, cams[f + 1], lut, W, H, dt, f + 1, table_f16=online.table_f16,
+                       want_counts=False, rgba=rgba, workspace=rws, counters=cnt)
+            ev_r[f][2].record()
+            torch.cuda.synchronize()
+            c = cnt.cpu().numpy()
+            evals += int(c[0])
+            used += int(c[1])
+        tr = sum(e[0].elapsed_time(e[1]) for e in ev_r) / args.render_frames
+        rd = sum(e[1].elapsed_time(e[2]) for e in ev_r) / args.render_frames
+        render = {"frames": args.render_frames, "width": W, "height": H, "dt": dt, "train_batch": 1 << 16,
+                  "frame_ms": round(tr + rd, 3), "fps": round(1000.0 / (tr + rd), 3),
+                  "train_ms_per_frame": round(tr, 3), "render_ms_per_frame": round(rd, 3),
+                  "network_samples_per_frame": evals / args.render_frames,
+                  "composited_samples_per_frame": used / args.render_frames,
+                  "network_samples_per_s": evals / args.render_frames / (rd * 1e-3)}
+        log(f"render: {render['fps']:.2f} fps (train {tr:.2f} ms + render {rd:.2f} ms), "
+            f"{render['network_samples_per_s']:.3e} network samples/s")
 
     # --------------------------------------------------------------- roofline
     # query kernel: algorithmic bytes per query = L*8*F FP16 table reads + 12 B xyz + 4 B out
@@ -241,7 +292,7 @@ def main():
                       "train_samples_per_s": B_TRAIN / (train_ms * 1e-3),
                       "infer_samples_per_s": N_QUERY / ((sort_ms + infer_ms) * 1e-3),
                       "infer_unsorted_ms": round(direct_ms, 4)},
-        "fp32_plain": fp32, "quality": quality, "roofline": roofline, "cpu_baseline": cpu,
+        "fp32_plain": fp32, "quality": quality, "render": render, "roofline": roofline, "cpu_baseline": cpu,
     }
     s = json.dumps(line)
     print(s, flush=True)

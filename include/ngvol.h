@@ -254,9 +254,7 @@ int ngvol_sample_batch(const ngvol_plan* plan, const ngvol_batch* batch, float* 
 /* Workspace a training step of batch B needs. */
 int ngvol_train_workspace_bytes(const ngvol_plan* plan, int64_t batch_size, size_t* bytes);
 
-/* One training step (Section 4): sampling (the batch is grouped by spatial
- * cell on the device before use; the loss is a sum so the order of samples
- * does not matter), forward, mean-squared loss
+/* One training step (Section 4): sampling, forward, mean-squared loss
  * L = (1/B) sum (Phi(x)-y)^2, backward through the MLP (activations
  * recomputed from the stored encoding) and the encoding, then Adam on all
  * parameters; the FP16 shadow (if any) is refreshed by round-to-nearest-even

@@ -105,11 +105,12 @@ TrainWorkspace train_workspace(const ngvol_plan* plan, int64_t B) {
   ws.bwd_grid = bwd_grid(plan, B);
   ws.e_off = 0;
   ws.g_off = up((size_t)B * plan->kin * esz);
-  ws.partial_off = ws.g_off + up((size_t)B * 4);
+  ws.de_off = ws.g_off + up((size_t)B * 4);
+  ws.partial_off = ws.de_off + up((size_t)B * plan->md.n_in * 4);
   ws.misc_off = ws.partial_off + up((size_t)ws.bwd_grid * plan->md.n_mlp * 4);
-  ws.bin = bin_plan(plan, B);
-  ws.bin_off = ws.misc_off + 256;
-  ws.total = ws.bin_off + (ws.bin.k ? ws.bin.bytes : 0);
+  ws.sc = scatter_plan(plan, B);
+  ws.scatter_off = ws.misc_off + 256;
+  ws.total = ws.scatter_off + ws.sc.bytes;
   return ws;
 }
 
@@ -274,8 +275,8 @@ int ngvol_infer(const ngvol_plan* plan, const ngvol_weights* w, const float* xyz
     hipError_t e = launch_bin(plan, bp, xyz, nullptr, n, ws, st);
     if (e != hipSuccess) return hip_check(e, "infer binning launch");
     char* base = reinterpret_cast<char*>(ws);
-    return hip_check(launch_infer(plan, tables_of(plan, w), mlp, reinterpret_cast<const float*>(base + bp.xyz_off),
-                                  reinterpret_cast<const uint32_t*>(base + bp.aux_off), n, out, st),
+    return hip_check(launch_infer(plan, tables_of(plan, w), mlp, nullptr,
+                                  reinterpret_cast<const float4*>(base + bp.rec_off), n, out, st),
                      "infer launch");
   }
   return hip_check(launch_infer(plan, tables_of(plan, w), mlp, xyz, nullptr, n, out, st), "infer launch");
@@ -301,9 +302,8 @@ int ngvol_infer_sorted(const ngvol_plan* plan, const ngvol_weights* w, const voi
   const BinPlan bp = bin_plan(plan, n);
   NGV_REQUIRE(bp.k, "%lld queries are too few to group (ngvol_infer_workspace_bytes is 0)", (long long)n);
   const char* base = reinterpret_cast<const char*>(ws);
-  return hip_check(launch_infer(plan, tables_of(plan, w), w->params + plan->md.n_table,
-                                reinterpret_cast<const float*>(base + bp.xyz_off),
-                                reinterpret_cast<const uint32_t*>(base + bp.aux_off), n, out, st),
+  return hip_check(launch_infer(plan, tables_of(plan, w), w->params + plan->md.n_table, nullptr,
+                                reinterpret_cast<const float4*>(base + bp.rec_off), n, out, st),
                    "infer_sorted launch");
 }
 
@@ -434,12 +434,6 @@ int ngvol_train_step(const ngvol_plan* plan, const ngvol_train_state* s, const n
   const float* mlp = s->params + plan->md.n_table;
   const float gscale = (float)((double)loss_scale * 2.0 / (double)ba.B);
   hipError_t e = launch_step_begin(loss_acc, flag, st);
-  if (e == hipSuccess && ws.bin.k) {
-    // group the batch by spatial cell; the step then runs on the sorted copy
-    e = launch_bin(plan, ws.bin, nullptr, &ba, ba.B, base + ws.bin_off, st);
-    ba.xyz = reinterpret_cast<const float*>(base + ws.bin_off + ws.bin.xyz_off);
-    ba.target = reinterpret_cast<const float*>(base + ws.bin_off + ws.bin.aux_off);
-  }
   if (e == hipSuccess) e = launch_train_fwd(plan, tp, mlp, ba, e_buf, g_buf, loss_acc, gscale, st);
   // 16-bit backward operands carry dz times a power of two that brings the
   // per-sample gradient scale S*2/B back to about one
@@ -449,9 +443,11 @@ int ngvol_train_step(const ngvol_plan* plan, const ngvol_train_state* s, const n
     ex = ex < -24 ? -24 : (ex > 24 ? 24 : ex);
     bscale = ldexpf(1.0f, ex);
   }
+  float* de = reinterpret_cast<float*>(base + ws.de_off);
   if (e == hipSuccess)
-    e = launch_bwd(plan, 0, mlp, e_buf, g_buf, ba, s->grad, nullptr, partial, ws.bwd_grid, flag, bscale, st);
+    e = launch_bwd(plan, 0, mlp, e_buf, g_buf, ba, s->grad, de, partial, ws.bwd_grid, flag, bscale, st);
   if (e == hipSuccess) e = launch_reduce_partials(plan, partial, ws.bwd_grid, s->grad, flag, st);
+  if (e == hipSuccess) e = launch_scatter(plan, ws.sc, ba, de, s->grad, base + ws.scatter_off, st);
   AdamArgs aa{a->learning_rate, a->beta1, a->beta2, a->epsilon, 1.0f / loss_scale};
   if (e == hipSuccess)
     e = launch_adam(plan, s->params, reinterpret_cast<__half*>(s->table_f16), s->grad, s->adam_m, s->adam_v, s->step,

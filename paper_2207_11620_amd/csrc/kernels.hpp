@@ -40,19 +40,35 @@ struct BatchArgs {
 struct BinPlan {
   int k, n_bins, blocks;
   int64_t chunk;
-  size_t xyz_off, aux_off, counts_off, totals_off, offsets_off, bytes;
+  size_t rec_off, counts_off, totals_off, offsets_off, bytes;
 };
 BinPlan bin_plan(const ngvol_plan* plan, int64_t n);
-// Sorts `xyz` (queries; aux = permutation) or the batch `ba` (training;
-// aux = targets) into the workspace.
+// Sorts `xyz` (queries; aux = original index) or the batch `ba` (training;
+// aux = target) into float4 records (x, y, z, aux) in the workspace.
 hipError_t launch_bin(const ngvol_plan* plan, const BinPlan& bp, const float* xyz, const struct BatchArgs* ba,
                       int64_t n, void* ws, hipStream_t st);
 
+// counts[blocks][nb] (per-block bucket counts) -> exclusive prefix over
+// blocks in place; totals[nb] = bucket sizes; offsets[nb] = bucket starts.
+hipError_t launch_count_offsets(uint32_t* counts, int blocks, int nb, uint32_t* totals, uint32_t* offsets,
+                                hipStream_t st);
+
+// Bucketed scatter of dL/dfeature into the table gradient (no global
+// atomics except where one bucket is split over several workgroups).
+struct ScatterPlan {
+  int bshift, n_buckets, blocks, rec_words, max_chunks;
+  int64_t chunk, n_records, chunk_records;
+  size_t rec_off, counts_off, totals_off, offsets_off, bytes;
+};
+ScatterPlan scatter_plan(const ngvol_plan* plan, int64_t B);
+hipError_t launch_scatter(const ngvol_plan* plan, const ScatterPlan& sp, const struct BatchArgs& ba,
+                          const float* dfeat, float* grad, void* ws, hipStream_t st);
+
 // Workspace carve-up of a training step (byte offsets).
 struct TrainWorkspace {
-  size_t e_off, g_off, partial_off, misc_off, bin_off, total;
+  size_t e_off, g_off, de_off, partial_off, misc_off, scatter_off, total;
   int bwd_grid;
-  BinPlan bin;
+  ScatterPlan sc;
 };
 
 // Persistent tile schedule: waves of workgroups with the same id mod 8 (the
@@ -89,8 +105,9 @@ hipError_t launch_encode(const ngvol_plan* plan, TablePtrs tp, const float* xyz,
                          hipStream_t st);
 hipError_t launch_encode_debug(const ngvol_plan* plan, const float* xyz, int64_t n, uint32_t* idx, float* w,
                                hipStream_t st);
-// perm (nullable): output slot of each sample, out[perm[s]] = Phi(xyz[s]).
-hipError_t launch_infer(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const float* xyz, const uint32_t* perm,
+// Either xyz[n][3] in output order, or rec[n] sorted records whose .w holds
+// the output slot: out[slot] = Phi(rec.xyz).
+hipError_t launch_infer(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const float* xyz, const float4* rec,
                         int64_t n, float* out, hipStream_t st);
 hipError_t launch_sq_error_grid(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const void* vol, int dtype,
                                 const int32_t dims[3], double* sq, hipStream_t st);

@@ -38,9 +38,12 @@ size_t bwd_lds_bytes(const ngvol_plan* plan, int waves) {
 }
 
 // ---------------------------------------------------------------------------
-// MLP backward (+ encoding scatter in MODE 0).
+// MLP backward: dW (per-block partial sums) and dL/dfeature written to dfeat.
+// MODE 0 reads the training forward's stored encoding ([B][KIN], 16-bit or
+// FP32), MODE 1 caller features ([n][n_in] FP32).  The table scatter of
+// dfeat is a separate pass (bucketed, see kernels_scatter.hip).
 // ---------------------------------------------------------------------------
-template <int P, int F, int KIN, int W, int MODE>
+template <int P, int KIN, int W, int MODE>
 __global__ void __launch_bounds__(256) k_bwd(ModelDesc md, const float* __restrict__ mlp,
                                              const void* __restrict__ e_buf, const float* __restrict__ g_buf,
                                              BatchArgs ba, float* __restrict__ grad, float* __restrict__ dfeat,
@@ -95,7 +98,7 @@ __global__ void __launch_bounds__(256) k_bwd(ModelDesc md, const float* __restri
     const int64_t sc = valid ? s : B - 1;
     // ---- stored encoding -> layer-0 operands
     float f[KIN / 32][8];
-    if constexpr (MODE == 0) {
+    if constexpr (MODE == 0) {  // stored encoding of the training forward
       if constexpr (P) {
 #pragma unroll
         for (int b = 0; b < KIN / 32; ++b) {
@@ -270,48 +273,14 @@ __global__ void __launch_bounds__(256) k_bwd(ModelDesc md, const float* __restri
 #pragma unroll
         for (int j = 0; j < 4; ++j)
           if (!finite(de[m][j])) bad = true;
-      if constexpr (MODE == 1) {
-        if (dfeat) {
+      if (dfeat) {
 #pragma unroll
-          for (int m = 0; m < MBI; ++m)
+        for (int m = 0; m < MBI; ++m)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              const int k = 16 * m + 4 * g + j;
-              if (k < n_in) dfeat[sc * n_in + k] = de[m][j];
-            }
-        }
-      } else {
-        float x, y, z;
-        if (ba.xyz) {
-          x = clamp01(ba.xyz[3 * sc]);
-          y = clamp01(ba.xyz[3 * sc + 1]);
-          z = clamp01(ba.xyz[3 * sc + 2]);
-        } else {
-          x = batch_coord(ba.seed, ba.step, B, sc, 0);
-          y = batch_coord(ba.seed, ba.step, B, sc, 1);
-          z = batch_coord(ba.seed, ba.step, B, sc, 2);
-        }
-        constexpr int FPL = F < 4 ? F : 4;  // features of one level held in one 4-group
-#pragma unroll
-        for (int m = 0; m < MBI; ++m) {
-#pragma unroll
-          for (int q = 0; q < 4 / FPL; ++q) {
-            const int k0 = 16 * m + 4 * g + q * FPL;
-            const int l = k0 / F;
-            const int f0 = k0 % F;
-            if (l < md.L) {
-              Corners cr;
-              level_corners(md.lv[l], x, y, z, cr);
-#pragma unroll
-              for (int k = 0; k < 8; ++k)
-#pragma unroll
-                for (int ff = 0; ff < FPL; ++ff) {
-                  const float v = cr.w[k] * de[m][q * FPL + ff];
-                  if (v != 0.0f) atomicAdd(grad + (size_t)cr.slot[k] * F + f0 + ff, v);
-                }
-            }
+          for (int j = 0; j < 4; ++j) {
+            const int k = 16 * m + 4 * g + j;
+            if (k < n_in) dfeat[sc * n_in + k] = de[m][j];
           }
-        }
       }
     }
   }
@@ -334,16 +303,28 @@ __global__ void __launch_bounds__(256) k_bwd(ModelDesc md, const float* __restri
   for (int t = threadIdx.x; t < md.n_mlp; t += blockDim.x) dst[t] = lds_dw[t];
 }
 
-// grad_mlp[k] += sum over blocks of partial[b][k] (fixed order).
-__global__ void __launch_bounds__(256) k_reduce_partials(const float* __restrict__ partial, int blocks, int n_mlp,
-                                                         float* __restrict__ grad_mlp, int32_t* __restrict__ nonfinite) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n_mlp) return;
+// grad_mlp[k] += sum over blocks of partial[b][k], in a fixed order: a
+// workgroup covers 64 columns; its 16 thread rows each sum every 16th
+// partial, then the 16 row sums are added in LDS.
+__global__ void __launch_bounds__(1024) k_reduce_partials(const float* __restrict__ partial, int blocks, int n_mlp,
+                                                          float* __restrict__ grad_mlp,
+                                                          int32_t* __restrict__ nonfinite) {
+  __shared__ float part[16][65];
+  const int col = threadIdx.x & 63, row = threadIdx.x >> 6;
+  const int k = blockIdx.x * 64 + col;
   float s = 0.0f;
-  for (int b = 0; b < blocks; ++b) s += partial[(size_t)b * n_mlp + k];
-  const float v = grad_mlp[k] + s;
-  grad_mlp[k] = v;
-  if (!finite(v)) *nonfinite = 1;
+  if (k < n_mlp)
+    for (int b = row; b < blocks; b += 16) s += partial[(size_t)b * n_mlp + k];
+  part[row][col] = s;
+  __syncthreads();
+  if (row == 0 && k < n_mlp) {
+    float t = 0.0f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) t += part[r][col];
+    const float v = grad_mlp[k] + t;
+    grad_mlp[k] = v;
+    if (!finite(v)) *nonfinite = 1;
+  }
 }
 
 // Encoding backward alone: one thread per (sample, level).
@@ -437,37 +418,31 @@ hipError_t launch_bwd(const ngvol_plan* plan, int mode, const float* mlp, const 
   const ModelDesc& md = plan->md;
   const size_t lds = bwd_lds_bytes(plan, kBwdWaves);
   const int P_ = plan->layout.precision;
-#define NGV_BWD_LAUNCH(P, F, KIN, W)                                                                               \
+#define NGV_BWD_LAUNCH(P, KIN, W)                                                                                   \
   do {                                                                                                             \
     if (mode == 0)                                                                                                 \
-      hipLaunchKernelGGL((k_bwd<P, F, KIN, W, 0>), dim3(grid), dim3(64 * kBwdWaves), lds, st, md, mlp, e_buf, g_buf, \
+      hipLaunchKernelGGL((k_bwd<P, KIN, W, 0>), dim3(grid), dim3(64 * kBwdWaves), lds, st, md, mlp, e_buf, g_buf,     \
                          ba, grad, dfeat, partial, nonfinite, bscale);                                             \
     else                                                                                                           \
-      hipLaunchKernelGGL((k_bwd<P, 2, KIN, W, 1>), dim3(grid), dim3(64 * kBwdWaves), lds, st, md, mlp, e_buf, g_buf, \
+      hipLaunchKernelGGL((k_bwd<P, KIN, W, 1>), dim3(grid), dim3(64 * kBwdWaves), lds, st, md, mlp, e_buf, g_buf,     \
                          ba, grad, dfeat, partial, nonfinite, bscale);                                             \
   } while (0)
-#define NGV_BWD_W(P, F, KIN)                                   \
+#define NGV_BWD_W(P, KIN)                                      \
   do {                                                         \
-    if (md.width == 32) NGV_BWD_LAUNCH(P, F, KIN, 32);          \
-    else if (md.width == 64) NGV_BWD_LAUNCH(P, F, KIN, 64);     \
+    if (md.width == 32) NGV_BWD_LAUNCH(P, KIN, 32);             \
+    else if (md.width == 64) NGV_BWD_LAUNCH(P, KIN, 64);        \
     else return hipErrorInvalidValue;                          \
   } while (0)
-#define NGV_BWD_FK(P)                                                   \
+#define NGV_BWD_K(P)                                                    \
   do {                                                                  \
-    switch (md.F * 1000 + plan->kin) {                                  \
-      case 2032: NGV_BWD_W(P, 2, 32); break;                            \
-      case 2064: NGV_BWD_W(P, 2, 64); break;                            \
-      case 4032: NGV_BWD_W(P, 4, 32); break;                            \
-      case 4064: NGV_BWD_W(P, 4, 64); break;                            \
-      case 8032: NGV_BWD_W(P, 8, 32); break;                            \
-      case 8064: NGV_BWD_W(P, 8, 64); break;                            \
-      default: return hipErrorInvalidValue;                             \
-    }                                                                   \
+    if (plan->kin == 32) NGV_BWD_W(P, 32);                              \
+    else if (plan->kin == 64) NGV_BWD_W(P, 64);                         \
+    else return hipErrorInvalidValue;                                   \
   } while (0)
-  if (P_ == 1) NGV_BWD_FK(1);
-  else if (P_ == 2) NGV_BWD_FK(2);
-  else NGV_BWD_FK(0);
-#undef NGV_BWD_FK
+  if (P_ == 1) NGV_BWD_K(1);
+  else if (P_ == 2) NGV_BWD_K(2);
+  else NGV_BWD_K(0);
+#undef NGV_BWD_K
 #undef NGV_BWD_W
 #undef NGV_BWD_LAUNCH
   return hipGetLastError();
@@ -476,7 +451,7 @@ hipError_t launch_bwd(const ngvol_plan* plan, int mode, const float* mlp, const 
 hipError_t launch_reduce_partials(const ngvol_plan* plan, const float* partial, int grid, float* grad,
                                   int32_t* nonfinite, hipStream_t st) {
   const int n = plan->md.n_mlp;
-  hipLaunchKernelGGL(k_reduce_partials, dim3((n + 255) / 256), dim3(256), 0, st, partial, grid, n,
+  hipLaunchKernelGGL(k_reduce_partials, dim3((n + 63) / 64), dim3(1024), 0, st, partial, grid, n,
                      grad + plan->md.n_table, nonfinite);
   return hipGetLastError();
 }

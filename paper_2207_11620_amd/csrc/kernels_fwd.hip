@@ -53,7 +53,7 @@ __global__ void __launch_bounds__(256) k_encode_debug(ModelDesc md, const float*
 // ---------------------------------------------------------------------------
 template <int P, int F, int KIN, int W, typename TT, int MODE, typename VT>
 __global__ void __launch_bounds__(256) k_infer(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp,
-                                               const float* __restrict__ xyz, const uint32_t* __restrict__ perm,
+                                               const float* __restrict__ xyz, const float4* __restrict__ rec,
                                                int64_t n, float* __restrict__ out,
                                                const VT* __restrict__ vol, int dx, int dy, int dz,
                                                double* __restrict__ sq_sum) {
@@ -74,11 +74,20 @@ __global__ void __launch_bounds__(256) k_infer(ModelDesc md, TablePtrs tp, const
     const int64_t s = t * 16 + nl;
     const bool valid = s < n;
     float x, y, z;
+    int64_t slot = s;
     if constexpr (MODE == 0) {
       const int64_t sc = valid ? s : n - 1;
-      x = clamp01(xyz[3 * sc]);
-      y = clamp01(xyz[3 * sc + 1]);
-      z = clamp01(xyz[3 * sc + 2]);
+      if (rec) {
+        const float4 r = rec[sc];
+        x = clamp01(r.x);
+        y = clamp01(r.y);
+        z = clamp01(r.z);
+        slot = (int64_t)__float_as_uint(r.w);
+      } else {
+        x = clamp01(xyz[3 * sc]);
+        y = clamp01(xyz[3 * sc + 1]);
+        z = clamp01(xyz[3 * sc + 2]);
+      }
     } else {
       const int64_t sc = valid ? s : n - 1;
       const int64_t ix = sc % dx, iy = (sc / dx) % dy, iz = sc / ((int64_t)dx * dy);
@@ -95,7 +104,7 @@ __global__ void __launch_bounds__(256) k_infer(ModelDesc md, TablePtrs tp, const
     const float yv = mlp_output<W>(act, lds_wout);
     if (valid && g == 0) {
       if constexpr (MODE == 0) {
-        out[perm ? (int64_t)perm[s] : s] = yv;
+        out[slot] = yv;
       } else {
         const double d = (double)yv - (double)load_vox<VT>(vol, (size_t)s);
         err += d * d;
@@ -334,7 +343,7 @@ hipError_t launch_encode_debug(const ngvol_plan* plan, const float* xyz, int64_t
 
 template <int MODE, typename VT>
 static hipError_t launch_infer_t(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const float* xyz,
-                                 const uint32_t* perm, int64_t n, float* out, const VT* vol, int dx, int dy, int dz,
+                                 const float4* rec, int64_t n, float* out, const VT* vol, int dx, int dy, int dz,
                                  double* sq, hipStream_t st) {
   const ModelDesc& md = plan->md;
   const int64_t n_tiles = (n + 15) / 16;
@@ -343,17 +352,17 @@ static hipError_t launch_infer_t(const ngvol_plan* plan, TablePtrs tp, const flo
   NGV_DISPATCH_P(plan->layout.precision, NGV_DISPATCH_F_KIN(md.F, plan->kin, NGV_DISPATCH_W(md.width, {
     if (tp.f16)
       hipLaunchKernelGGL((k_infer<P, F, KIN, W, __half, MODE, VT>), dim3(grid), dim3(256), lds, st, md, tp, mlp, xyz,
-                         perm, n, out, vol, dx, dy, dz, sq);
+                         rec, n, out, vol, dx, dy, dz, sq);
     else
       hipLaunchKernelGGL((k_infer<P, F, KIN, W, float, MODE, VT>), dim3(grid), dim3(256), lds, st, md, tp, mlp, xyz,
-                         perm, n, out, vol, dx, dy, dz, sq);
+                         rec, n, out, vol, dx, dy, dz, sq);
   })));
   return hipGetLastError();
 }
 
-hipError_t launch_infer(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const float* xyz, const uint32_t* perm,
+hipError_t launch_infer(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const float* xyz, const float4* rec,
                         int64_t n, float* out, hipStream_t st) {
-  return launch_infer_t<0, float>(plan, tp, mlp, xyz, perm, n, out, nullptr, 1, 1, 1, nullptr, st);
+  return launch_infer_t<0, float>(plan, tp, mlp, xyz, rec, n, out, nullptr, 1, 1, 1, nullptr, st);
 }
 
 hipError_t launch_sq_error_grid(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const void* vol, int dtype,

@@ -1,0 +1,229 @@
+// Encoding backward as a bucketed scatter (Section 3.1 encoding, reversed):
+// grad_table[slot][f] += w_corner * dL/dfeature[l*F + f] for every sample,
+// level and corner.
+//
+// FP32 atomic adds to device memory run at a fixed rate on this GPU
+// whatever the footprint, so the scatter avoids them.  Table entries
+// (all levels, concatenated) are cut into buckets of 2^bshift entries whose
+// F features fill 32 KB of LDS:
+//   1. count: per-block LDS histograms of the bucket of every contribution;
+//   2. block prefix and scan of the counts (shared with the spatial sort);
+//   3. fill: each contribution is written as a record (entry, w*d[0..F-1])
+//      at its bucket's next position (LDS cursors);
+//   4. reduce: one workgroup per (bucket, chunk of records) accumulates the
+//      records in LDS and adds the bucket's entries into the gradient -
+//      with plain stores when the bucket fits one chunk (it owns those
+//      entries), with atomics only when a heavily hit bucket is split.
+#include "kernels.hpp"
+#include "device_common.hpp"
+
+namespace ngvol {
+
+namespace {
+
+constexpr int kScThreads = 256;
+constexpr int kReduceThreads = 256;
+constexpr int64_t kChunkRecords = 1 << 16;
+
+struct Coords {
+  const float* xyz;
+  uint64_t seed;
+  int64_t step, B;
+  __device__ __forceinline__ void get(int64_t i, float& x, float& y, float& z) const {
+    if (xyz) {
+      x = clamp01(xyz[3 * i]);
+      y = clamp01(xyz[3 * i + 1]);
+      z = clamp01(xyz[3 * i + 2]);
+    } else {
+      x = batch_coord(seed, step, B, i, 0);
+      y = batch_coord(seed, step, B, i, 1);
+      z = batch_coord(seed, step, B, i, 2);
+    }
+  }
+};
+
+__global__ void __launch_bounds__(kScThreads) k_sc_count(ModelDesc md, Coords src, int64_t B, int64_t chunk,
+                                                         int bshift, int nb, uint32_t* __restrict__ counts) {
+  extern __shared__ uint32_t hist[];
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) hist[b] = 0u;
+  __syncthreads();
+  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t hi = lo + chunk < B ? lo + chunk : B;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    float x, y, z;
+    src.get(i, x, y, z);
+    for (int l = 0; l < md.L; ++l) {
+      Corners cr;
+      level_corners(md.lv[l], x, y, z, cr);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) atomicAdd(hist + (cr.slot[k] >> bshift), 1u);
+    }
+  }
+  __syncthreads();
+  uint32_t* dst = counts + (size_t)blockIdx.x * nb;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) dst[b] = hist[b];
+}
+
+// Record of one contribution: word 0 = entry index, words 1..F = values.
+template <int F>
+struct Rec {
+  static constexpr int words = (1 + F + 3) / 4;  // uint4 words
+};
+
+template <int F>
+__global__ void __launch_bounds__(kScThreads) k_sc_fill(ModelDesc md, Coords src, int64_t B, int64_t chunk, int bshift,
+                                                        int nb, const uint32_t* __restrict__ counts,
+                                                        const uint32_t* __restrict__ offsets,
+                                                        const float* __restrict__ dfeat, uint4* __restrict__ rec) {
+  extern __shared__ uint32_t cur[];
+  const uint32_t* mine = counts + (size_t)blockIdx.x * nb;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) cur[b] = offsets[b] + mine[b];
+  __syncthreads();
+  constexpr int RW = Rec<F>::words;
+  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t hi = lo + chunk < B ? lo + chunk : B;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    float x, y, z;
+    src.get(i, x, y, z);
+    const float* d = dfeat + i * md.n_in;
+    for (int l = 0; l < md.L; ++l) {
+      float dv[F];
+#pragma unroll
+      for (int f = 0; f < F; ++f) dv[f] = d[l * F + f];
+      Corners cr;
+      level_corners(md.lv[l], x, y, z, cr);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const uint32_t pos = atomicAdd(cur + (cr.slot[k] >> bshift), 1u);
+        uint32_t w[RW * 4];
+        w[0] = cr.slot[k];
+#pragma unroll
+        for (int f = 0; f < F; ++f) w[1 + f] = __float_as_uint(cr.w[k] * dv[f]);
+#pragma unroll
+        for (int q = 1 + F; q < RW * 4; ++q) w[q] = 0u;
+        uint4* dst = rec + (size_t)pos * RW;
+#pragma unroll
+        for (int q = 0; q < RW; ++q) dst[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+      }
+    }
+  }
+}
+
+template <int F>
+__global__ void __launch_bounds__(kReduceThreads) k_sc_reduce(const uint4* __restrict__ rec,
+                                                              const uint32_t* __restrict__ totals,
+                                                              const uint32_t* __restrict__ offsets, int bshift,
+                                                              int64_t chunk_records, int64_t n_entries,
+                                                              float* __restrict__ grad) {
+  extern __shared__ float acc[];
+  const int bucket = blockIdx.x;
+  const int64_t cnt = totals[bucket];
+  const int64_t lo = (int64_t)blockIdx.y * chunk_records;
+  if (lo >= cnt) return;
+  const int64_t hi = lo + chunk_records < cnt ? lo + chunk_records : cnt;
+  const int span = (1 << bshift) * F;
+  for (int t = threadIdx.x; t < span; t += blockDim.x) acc[t] = 0.0f;
+  __syncthreads();
+  constexpr int RW = Rec<F>::words;
+  const uint32_t base_entry = (uint32_t)bucket << bshift;
+  const uint4* r0 = rec + (size_t)offsets[bucket] * RW;
+  for (int64_t r = lo + threadIdx.x; r < hi; r += blockDim.x) {
+    uint32_t w[RW * 4];
+#pragma unroll
+    for (int q = 0; q < RW; ++q) {
+      const uint4 u = r0[(size_t)r * RW + q];
+      w[4 * q] = u.x;
+      w[4 * q + 1] = u.y;
+      w[4 * q + 2] = u.z;
+      w[4 * q + 3] = u.w;
+    }
+    const int local = (int)(w[0] - base_entry);
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      const float v = __uint_as_float(w[1 + f]);
+      if (v != 0.0f) atomicAdd(acc + local * F + f, v);
+    }
+  }
+  __syncthreads();
+  const bool owner = cnt <= chunk_records;  // the bucket fits one chunk: this workgroup owns its entries
+  const int64_t first = (int64_t)base_entry * F;
+  const int64_t last = n_entries * F;
+  for (int t = threadIdx.x; t < span; t += blockDim.x) {
+    const int64_t gi = first + t;
+    if (gi >= last) break;
+    const float v = acc[t];
+    if (v == 0.0f) continue;
+    if (owner) grad[gi] += v;
+    else atomicAdd(grad + gi, v);
+  }
+}
+
+}  // namespace
+
+ScatterPlan scatter_plan(const ngvol_plan* plan, int64_t B) {
+  ScatterPlan sp{};
+  const ModelDesc& md = plan->md;
+  const int F = md.F;
+  sp.bshift = F <= 2 ? 12 : (F == 4 ? 11 : 10);  // 2^bshift * F * 4 bytes = 32 KB of LDS
+  const int64_t entries = md.n_table / F;
+  sp.n_buckets = (int)((entries + (1 << sp.bshift) - 1) >> sp.bshift);
+  int64_t g = (B + 1023) / 1024;
+  if (g > plan->cus) g = plan->cus;
+  if (g < 1) g = 1;
+  sp.blocks = (int)g;
+  sp.chunk = (B + g - 1) / g;
+  sp.rec_words = (1 + F + 3) / 4;
+  sp.n_records = B * 8 * md.L;
+  sp.chunk_records = kChunkRecords;
+  // most records one bucket can receive: B*8 per level overlapping it
+  int maxlv = 1;
+  for (int b0 = 0; b0 < sp.n_buckets; ++b0) {
+    const int64_t lo = (int64_t)b0 << sp.bshift, hi = lo + (1 << sp.bshift);
+    int c = 0;
+    for (int l = 0; l < md.L; ++l)
+      if ((int64_t)md.lv[l].offset < hi && (int64_t)md.lv[l].offset + plan->layout.level_entries[l] > lo) ++c;
+    if (c > maxlv) maxlv = c;
+    if (lo > (int64_t)md.lv[md.L - 1].offset) break;  // later buckets lie inside the last level
+  }
+  sp.max_chunks = (int)((B * 8 * maxlv + kChunkRecords - 1) / kChunkRecords);
+  auto up = [](size_t v) { return (v + 255) / 256 * 256; };
+  sp.rec_off = 0;
+  sp.counts_off = up((size_t)sp.n_records * 16 * sp.rec_words);
+  sp.totals_off = sp.counts_off + up((size_t)sp.blocks * sp.n_buckets * 4);
+  sp.offsets_off = sp.totals_off + up((size_t)sp.n_buckets * 4);
+  sp.bytes = sp.offsets_off + up((size_t)sp.n_buckets * 4);
+  return sp;
+}
+
+hipError_t launch_scatter(const ngvol_plan* plan, const ScatterPlan& sp, const BatchArgs& ba, const float* dfeat,
+                          float* grad, void* ws, hipStream_t st) {
+  const ModelDesc& md = plan->md;
+  char* base = reinterpret_cast<char*>(ws);
+  uint4* rec = reinterpret_cast<uint4*>(base + sp.rec_off);
+  uint32_t* counts = reinterpret_cast<uint32_t*>(base + sp.counts_off);
+  uint32_t* totals = reinterpret_cast<uint32_t*>(base + sp.totals_off);
+  uint32_t* offsets = reinterpret_cast<uint32_t*>(base + sp.offsets_off);
+  const Coords src{ba.xyz, ba.seed, ba.step, ba.B};
+  const size_t hist_lds = (size_t)sp.n_buckets * 4;
+  hipLaunchKernelGGL(k_sc_count, dim3(sp.blocks), dim3(kScThreads), hist_lds, st, md, src, ba.B, sp.chunk, sp.bshift,
+                     sp.n_buckets, counts);
+  launch_count_offsets(counts, sp.blocks, sp.n_buckets, totals, offsets, st);
+  const size_t acc_lds = ((size_t)1 << sp.bshift) * md.F * 4;
+  const dim3 rgrid(sp.n_buckets, sp.max_chunks);
+  const int64_t n_entries = md.n_table / md.F;
+#define NGV_SC(FV)                                                                                                 \
+  hipLaunchKernelGGL(k_sc_fill<FV>, dim3(sp.blocks), dim3(kScThreads), hist_lds, st, md, src, ba.B, sp.chunk,      \
+                     sp.bshift, sp.n_buckets, counts, offsets, dfeat, rec);                                        \
+  hipLaunchKernelGGL(k_sc_reduce<FV>, rgrid, dim3(kReduceThreads), acc_lds, st, rec, totals, offsets, sp.bshift,   \
+                     sp.chunk_records, n_entries, grad)
+  switch (md.F) {
+    case 2: NGV_SC(2); break;
+    case 4: NGV_SC(4); break;
+    case 8: NGV_SC(8); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef NGV_SC
+  return hipGetLastError();
+}
+
+}  // namespace ngvol

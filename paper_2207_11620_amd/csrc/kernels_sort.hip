@@ -114,16 +114,16 @@ __global__ void __launch_bounds__(kSortThreads) k_bin_scan(const uint32_t* __res
     }
 }
 
-// Scatter: sorted xyz, and either the original index (queries) or the
-// target value (training: explicit or sampled from the volume).
+// Scatter one 16-byte record per sample: (x, y, z, aux), where aux is the
+// original index (queries, as integer bits) or the target value (training:
+// explicit or sampled from the volume).
 template <typename VT>
 __global__ void __launch_bounds__(kSortThreads) k_bin_scatter(Src src, int64_t n, int k, int64_t chunk,
                                                               const uint32_t* __restrict__ counts,
                                                               const uint32_t* __restrict__ offsets,
-                                                              float* __restrict__ out_xyz, uint32_t* __restrict__ perm,
+                                                              float4* __restrict__ out, bool with_target,
                                                               const float* __restrict__ target_in,
-                                                              const VT* __restrict__ vol, int dx, int dy, int dz,
-                                                              float* __restrict__ out_target) {
+                                                              const VT* __restrict__ vol, int dx, int dy, int dz) {
   extern __shared__ uint32_t cur[];
   const int nb = 1 << (3 * k);
   const uint32_t* mine = counts + (size_t)blockIdx.x * nb;
@@ -135,18 +135,22 @@ __global__ void __launch_bounds__(kSortThreads) k_bin_scatter(Src src, int64_t n
     float x, y, z;
     src.get(i, x, y, z);
     const uint32_t pos = atomicAdd(cur + cell_key(x, y, z, k), 1u);
-    out_xyz[3 * (size_t)pos] = x;
-    out_xyz[3 * (size_t)pos + 1] = y;
-    out_xyz[3 * (size_t)pos + 2] = z;
-    if (perm) perm[pos] = (uint32_t)i;
-    if (out_target) {
-      if (target_in) out_target[pos] = target_in[i];
-      else out_target[pos] = volume_sample<VT>(vol, dx, dy, dz, x, y, z);
-    }
+    float aux;
+    if (!with_target) aux = __uint_as_float((uint32_t)i);
+    else if (target_in) aux = target_in[i];
+    else aux = volume_sample<VT>(vol, dx, dy, dz, x, y, z);
+    out[pos] = make_float4(x, y, z, aux);
   }
 }
 
 }  // namespace
+
+hipError_t launch_count_offsets(uint32_t* counts, int blocks, int nb, uint32_t* totals, uint32_t* offsets,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(k_bin_prefix, dim3((nb + 255) / 256), dim3(256), 0, st, counts, blocks, nb, totals);
+  hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(kSortThreads), 0, st, totals, nb, offsets);
+  return hipGetLastError();
+}
 
 BinPlan bin_plan(const ngvol_plan* plan, int64_t n) {
   BinPlan bp{};
@@ -159,9 +163,8 @@ BinPlan bin_plan(const ngvol_plan* plan, int64_t n) {
   bp.blocks = (int)g;
   bp.chunk = (n + g - 1) / g;
   auto up = [](size_t v) { return (v + 255) / 256 * 256; };
-  bp.xyz_off = 0;
-  bp.aux_off = up((size_t)n * 12);  // perm (queries) or targets (training)
-  bp.counts_off = bp.aux_off + up((size_t)n * 4);
+  bp.rec_off = 0;  // float4 records (x, y, z, aux)
+  bp.counts_off = up((size_t)n * 16);
   bp.totals_off = bp.counts_off + up((size_t)bp.blocks * bp.n_bins * 4);
   bp.offsets_off = bp.totals_off + up((size_t)bp.n_bins * 4);
   bp.bytes = bp.offsets_off + up((size_t)bp.n_bins * 4);
@@ -172,7 +175,7 @@ hipError_t launch_bin(const ngvol_plan* plan, const BinPlan& bp, const float* xy
                       void* ws, hipStream_t st) {
   (void)plan;
   char* base = reinterpret_cast<char*>(ws);
-  float* sx = reinterpret_cast<float*>(base + bp.xyz_off);
+  float4* rec = reinterpret_cast<float4*>(base + bp.rec_off);
   uint32_t* counts = reinterpret_cast<uint32_t*>(base + bp.counts_off);
   uint32_t* totals = reinterpret_cast<uint32_t*>(base + bp.totals_off);
   uint32_t* offsets = reinterpret_cast<uint32_t*>(base + bp.offsets_off);
@@ -185,23 +188,18 @@ hipError_t launch_bin(const ngvol_plan* plan, const BinPlan& bp, const float* xy
   }
   const size_t lds = (size_t)bp.n_bins * 4;
   hipLaunchKernelGGL(k_bin_hist, dim3(bp.blocks), dim3(kSortThreads), lds, st, src, n, bp.k, bp.chunk, counts);
-  hipLaunchKernelGGL(k_bin_prefix, dim3((bp.n_bins + 255) / 256), dim3(256), 0, st, counts, bp.blocks, bp.n_bins,
-                     totals);
-  hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(kSortThreads), 0, st, totals, bp.n_bins, offsets);
+  launch_count_offsets(counts, bp.blocks, bp.n_bins, totals, offsets, st);
   if (!ba) {
-    uint32_t* perm = reinterpret_cast<uint32_t*>(base + bp.aux_off);
     hipLaunchKernelGGL(k_bin_scatter<float>, dim3(bp.blocks), dim3(kSortThreads), lds, st, src, n, bp.k, bp.chunk,
-                       counts, offsets, sx, perm, nullptr, nullptr, 1, 1, 1, nullptr);
+                       counts, offsets, rec, false, nullptr, nullptr, 1, 1, 1);
+  } else if (ba->xyz || ba->vdtype != NGVOL_DT_F16) {
+    hipLaunchKernelGGL(k_bin_scatter<float>, dim3(bp.blocks), dim3(kSortThreads), lds, st, src, n, bp.k, bp.chunk,
+                       counts, offsets, rec, true, ba->target, reinterpret_cast<const float*>(ba->volume), ba->dims[0],
+                       ba->dims[1], ba->dims[2]);
   } else {
-    float* tg = reinterpret_cast<float*>(base + bp.aux_off);
-    if (ba->xyz || ba->vdtype != NGVOL_DT_F16)
-      hipLaunchKernelGGL(k_bin_scatter<float>, dim3(bp.blocks), dim3(kSortThreads), lds, st, src, n, bp.k, bp.chunk,
-                         counts, offsets, sx, nullptr, ba->target, reinterpret_cast<const float*>(ba->volume),
-                         ba->dims[0], ba->dims[1], ba->dims[2], tg);
-    else
-      hipLaunchKernelGGL(k_bin_scatter<__half>, dim3(bp.blocks), dim3(kSortThreads), lds, st, src, n, bp.k,
-                         bp.chunk, counts, offsets, sx, nullptr, nullptr, reinterpret_cast<const __half*>(ba->volume),
-                         ba->dims[0], ba->dims[1], ba->dims[2], tg);
+    hipLaunchKernelGGL(k_bin_scatter<__half>, dim3(bp.blocks), dim3(kSortThreads), lds, st, src, n, bp.k, bp.chunk,
+                       counts, offsets, rec, true, nullptr, reinterpret_cast<const __half*>(ba->volume), ba->dims[0],
+                       ba->dims[1], ba->dims[2]);
   }
   return hipGetLastError();
 }

@@ -417,3 +417,32 @@ def test_render_constant_alpha_closed_form():
     assert np.all(host(n_geo) == 1024) and np.all(host(n_used) == 90)
     a = float(np.float32(0.05))
     np.testing.assert_allclose(host(rgba)[..., 3], 1 - (1 - a) ** 90, rtol=1e-5)
+
+
+def test_online_training_interleave():
+    # one training step between two frames: the second frame is the oracle's
+    # rendering of the updated parameters, the geometry is unchanged
+    name = "tiny"
+    m = oracle_model(name)
+    p = gpu_plan(name, "fp32")
+    vol = synth.gaussian_blobs(48, SEED)
+    st = ngv.TrainState(p, dev(init_params(name, table_scale=0.2)), 4096)
+    for k in range(30):
+        ngv.train_step(st, volume=dev(vol), seed=SEED, step_index=k, loss_scale=128.0)
+    W, H = 96, 64
+    cam, lut = _render_setup(W, H, angle=1.1)
+    dt = 2.0 ** -7
+    lt = dev(lut)
+    a, ng_a, _, _ = ngv.render(p, st.params, cam, lt, W, H, dt, 3)
+    a = host(a).copy()
+    ng_a = host(ng_a).copy()
+    ngv.train_step(st, volume=dev(vol), seed=SEED, step_index=30, loss_scale=128.0)
+    b, ng_b, nu_b, _ = ngv.render(p, st.params, cam, lt, W, H, dt, 3)
+    np.testing.assert_array_equal(host(ng_b), ng_a)
+    assert np.max(np.abs(host(b) - a)) > 0
+    pix = np.random.default_rng(4).choice(W * H, 100, replace=False)
+    ro, _, nuo = oracle.render_pixels(m, host(st.params).astype(np.float64), cam, lut, W, H, dt, 3, pix)
+    g = host(b).reshape(-1, 4)[pix]
+    same = host(nu_b).ravel()[pix] == nuo
+    assert np.all(same | (np.abs(ro[:, 3] - 0.99) < 2e-3))
+    assert np.max(np.abs(g[same] - ro[same])) <= 1e-4
