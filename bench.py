@@ -59,6 +59,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--render-frames", type=int, default=8)
     ap.add_argument("--no-render", action="store_true")
+    ap.add_argument("--no-multi", action="store_true")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -242,6 +243,82 @@ def main():
                   "network_samples_per_s": evals / args.render_frames / (rd * 1e-3)}
         log(f"render: {render['fps']:.2f} fps (train {tr:.2f} ms + render {rd:.2f} ms), "
             f"{render['network_samples_per_s']:.3e} network samples/s")
+        online = rs = None
+
+    # -------------------------------------------------- batched multi-volume
+    # 16 independent models of uneven size (2^16..2^22 entries, 8/12/16
+    # levels), targets 128^3..1024^3 FP16 generated on the device; per step
+    # every model trains on 2^16 samples and answers 2^20 random queries.
+    multi = None
+    if not args.no_multi:
+        st = trained = None  # free the single-model states
+        torch.cuda.empty_cache()
+        specs = synth.multi_volume_specs(16)
+        t0 = time.time()
+        mplans, mstates, mvols, mxyz, mout = [], [], [], [], []
+        for sp in specs:
+            p = ngv.Plan(sp["L"], 2, sp["log2T"], 16, 0.0, 2048, n_neurons=64, n_hidden_layers=2, precision="bf16")
+            mplans.append(p)
+            w0 = torch.from_numpy(synth.init_params(p.n_table_params, p.n_input, 64, 2, 1e-2, sp["seed"])).to(dev)
+            mstates.append(ngv.TrainState(p, w0, 1 << 16, f16_tables=True))
+            gen = synth.gaussian_blobs_torch if sp["kind"] == "blobs" else synth.fractal_value_noise_torch
+            mvols.append(gen(sp["D"], sp["seed"], dev, dtype=torch.float16))
+            mxyz.append(torch.from_numpy(synth.query_coords(1 << 20, sp["seed"])).to(dev))
+            mout.append(torch.empty(1 << 20, dtype=torch.float32, device=dev))
+        torch.cuda.synchronize()
+        log(f"multi: 16 models and targets built in {time.time() - t0:.1f}s")
+
+        def train_all():
+            for i in range(16):
+                ngv.train_step(mstates[i], volume=mvols[i], seed=specs[i]["seed"], step_index=-1,
+                               loss_scale=LOSS_SCALE, **ADAM)
+
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            train_all()  # warm-up, eager
+        torch.cuda.current_stream().wait_stream(side)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            train_all()
+        reps = 5
+        e = [ev() for _ in range(3)]
+        e[0].record()
+        for _ in range(reps):
+            train_all()
+        e[1].record()
+        for _ in range(reps):
+            graph.replay()
+        e[2].record()
+        torch.cuda.synchronize()
+        eager_ms = e[0].elapsed_time(e[1]) / reps
+        graph_ms = e[1].elapsed_time(e[2]) / reps
+        grp = ngv.Multi(mplans)
+        wts = [(s_.params, s_.table_f16) for s_ in mstates]
+        bpc, chunk = grp.autotune(wts, mxyz, mout)
+        e = [ev() for _ in range(3)]
+        e[0].record()
+        for _ in range(reps):
+            for i in range(16):
+                ngv.infer(mplans[i], mstates[i].params, mxyz[i], table_f16=mstates[i].table_f16, out=mout[i],
+                          sort=False)
+        e[1].record()
+        for _ in range(reps):
+            grp.infer(wts, mxyz, mout)
+        e[2].record()
+        torch.cuda.synchronize()
+        seq_ms = e[0].elapsed_time(e[1]) / reps
+        bat_ms = e[1].elapsed_time(e[2]) / reps
+        n_tr, n_q = 16 * (1 << 16), 16 * (1 << 20)
+        multi = {"models": 16, "train_batch_each": 1 << 16, "queries_each": 1 << 20,
+                 "train_eager_ms": round(eager_ms, 3), "train_graph_ms": round(graph_ms, 3),
+                 "query_sequential_ms": round(seq_ms, 3), "query_batched_ms": round(bat_ms, 3),
+                 "autotune": {"blocks_per_cu": bpc, "chunk_tiles": chunk},
+                 "aggregate_samples_per_s": (n_tr + n_q) / ((graph_ms + bat_ms) * 1e-3),
+                 "sequential_samples_per_s": (n_tr + n_q) / ((eager_ms + seq_ms) * 1e-3)}
+        log(f"multi: train eager {eager_ms:.2f} ms / graph {graph_ms:.2f} ms; query sequential {seq_ms:.2f} ms / "
+            f"batched {bat_ms:.2f} ms (autotune {bpc} wg/CU, {chunk} tiles)")
+        del grp, mstates, mvols, mxyz, mout, graph
 
     # --------------------------------------------------------------- roofline
     # query kernel: algorithmic bytes per query = L*8*F FP16 table reads + 12 B xyz + 4 B out
@@ -292,7 +369,8 @@ def main():
                       "train_samples_per_s": B_TRAIN / (train_ms * 1e-3),
                       "infer_samples_per_s": N_QUERY / ((sort_ms + infer_ms) * 1e-3),
                       "infer_unsorted_ms": round(direct_ms, 4)},
-        "fp32_plain": fp32, "quality": quality, "render": render, "roofline": roofline, "cpu_baseline": cpu,
+        "fp32_plain": fp32, "quality": quality, "render": render, "multi_volume": multi, "roofline": roofline,
+        "cpu_baseline": cpu,
     }
     s = json.dumps(line)
     print(s, flush=True)

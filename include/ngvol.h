@@ -153,7 +153,8 @@ typedef struct ngvol_batch {
     int32_t dims[3];     /* Dx, Dy, Dz, each >= 2 */
     int32_t volume_dtype; /* NGVOL_DT_F32 | NGVOL_DT_F16 */
     uint64_t seed;       /* < 2^56 */
-    int64_t step_index;
+    int64_t step_index;  /* >= 0; or -1 (ngvol_train_step only): use the state's device step counter, so a
+                          * captured graph draws a new batch on every replay (a skipped step repeats it) */
 } ngvol_batch;
 
 /* Adam (Kingma and Ba) with bias correction; the paper trains with Adam
@@ -302,6 +303,43 @@ int ngvol_render(const ngvol_plan* plan, const ngvol_weights* w, const ngvol_cam
                  int32_t width, int32_t height, float dt, uint32_t frame_seed, float* d_rgba, uint32_t* d_n_geo,
                  uint32_t* d_n_used, ngvol_render_counters* d_counters, void* d_workspace, size_t workspace_bytes,
                  hipStream_t stream);
+
+/* ----------------------------------------------------------------------- */
+/* Batches of independent neural volumes                                   */
+/* ----------------------------------------------------------------------- */
+#define NGVOL_MULTI_MAX 16
+typedef struct ngvol_multi ngvol_multi;
+
+/* Device bytes of the descriptor table of a group of k models. */
+size_t ngvol_multi_table_bytes(int32_t k);
+
+/* Groups k plans (1 <= k <= 16) that share precision, n_features (2), the
+ * padded input width (32 or 64 features), n_neurons and n_hidden_layers
+ * (NGVOL_EUNSUPPORTED otherwise); the models may differ in levels,
+ * resolutions and table sizes.  Their descriptors are copied into d_table
+ * (caller-owned device memory of ngvol_multi_table_bytes(k) bytes, valid for
+ * the group's lifetime); the call synchronises the stream once.  The plans
+ * may be destroyed afterwards. */
+int ngvol_multi_create(const ngvol_plan* const* plans, int32_t k, void* d_table, size_t table_bytes,
+                       hipStream_t stream, ngvol_multi** out);
+int ngvol_multi_destroy(ngvol_multi* group);
+
+/* Queries of all k models in one persistent launch: model i writes
+ * Phi_i(xyz[i][j]) to out[i][j] for j < n[i], with weights w[i] (host arrays
+ * of k entries; the pointers they hold are device pointers, either all with
+ * or all without FP16 tables).  Work is cut into chunks of 16-sample tiles of
+ * one model, ordered model by model; each workgroup walks a contiguous range
+ * of chunks and restages the MLP weights in LDS when the model changes. */
+int ngvol_multi_infer(const ngvol_multi* group, const ngvol_weights* w, const float* const* xyz, const int64_t* n,
+                      float* const* out, hipStream_t stream);
+
+/* Autotuner: times the candidate launch shapes (workgroups per compute unit
+ * x tiles per chunk) on these inputs (outputs are written), keeps the fastest
+ * for later ngvol_multi_infer calls on the group and reports it (either
+ * pointer may be NULL).  Synchronises the stream; not thread-safe with other
+ * calls on the same group. */
+int ngvol_multi_autotune(ngvol_multi* group, const ngvol_weights* w, const float* const* xyz, const int64_t* n,
+                         float* const* out, hipStream_t stream, int32_t* blocks_per_cu, int32_t* chunk_tiles);
 
 #ifdef __cplusplus
 }

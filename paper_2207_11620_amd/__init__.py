@@ -97,6 +97,12 @@ _SIGS = {
     "ngvol_render_workspace_bytes": (C.c_size_t, []),
     "ngvol_render": (C.c_int, [_P, C.POINTER(Weights), C.POINTER(Camera), _P, C.c_int32, C.c_int32, C.c_float,
                                C.c_uint32, _P, _P, _P, _P, _P, C.c_size_t, _P]),
+    "ngvol_multi_table_bytes": (C.c_size_t, [C.c_int32]),
+    "ngvol_multi_create": (C.c_int, [C.POINTER(_P), C.c_int32, _P, C.c_size_t, _P, C.POINTER(_P)]),
+    "ngvol_multi_destroy": (C.c_int, [_P]),
+    "ngvol_multi_infer": (C.c_int, [_P, C.POINTER(Weights), C.POINTER(_P), C.POINTER(C.c_int64), C.POINTER(_P), _P]),
+    "ngvol_multi_autotune": (C.c_int, [_P, C.POINTER(Weights), C.POINTER(_P), C.POINTER(C.c_int64), C.POINTER(_P),
+                                       _P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -322,6 +328,8 @@ class TrainState:
 
 def train_step(state, volume=None, seed=0, step_index=0, xyz=None, target=None, lr=1e-2, betas=(0.9, 0.99),
                eps=1e-15, loss_scale=1.0):
+    """One training step.  step_index=-1 draws the batch indexed by the state's
+    device step counter (the form to capture in a graph)."""
     B = state.batch_size
     if xyz is not None:
         b = Batch(B, _ptr(xyz), _ptr(target), None, (C.c_int32 * 3)(0, 0, 0), 0, 0, 0)
@@ -382,3 +390,47 @@ def render(plan, params, cam, lut, width, height, dt, frame_seed, table_f16=None
 
 def version():
     return lib().ngvol_version().decode()
+
+
+class Multi:
+    """A group of independent models (same MLP shape, F = 2) queried in one launch."""
+
+    def __init__(self, plans):
+        torch = _torch()
+        k = len(plans)
+        self.plans = list(plans)
+        self.table = torch.empty(max(int(lib().ngvol_multi_table_bytes(k)), 256), dtype=torch.uint8, device="cuda")
+        arr = (_P * k)(*[p.handle for p in plans])
+        h = C.c_void_p()
+        _check(lib().ngvol_multi_create(arr, k, _ptr(self.table), self.table.numel(), _stream(), C.byref(h)))
+        self.handle = h
+        self.k = k
+
+    def _args(self, weights, xyz, outs):
+        k = self.k
+        W = (Weights * k)(*[_weights(p, f) for (p, f) in weights])
+        X = (_P * k)(*[_ptr(x) for x in xyz])
+        N = (C.c_int64 * k)(*[x.shape[0] for x in xyz])
+        O = (_P * k)(*[_ptr(o) for o in outs])
+        return W, X, N, O
+
+    def infer(self, weights, xyz, outs=None):
+        """weights: list of (params, table_f16 or None); xyz: list of [n_i][3] tensors."""
+        torch = _torch()
+        if outs is None:
+            outs = [torch.empty(x.shape[0], dtype=torch.float32, device=x.device) for x in xyz]
+        W, X, N, O = self._args(weights, xyz, outs)
+        _check(lib().ngvol_multi_infer(self.handle, W, X, N, O, _stream()))
+        return outs
+
+    def autotune(self, weights, xyz, outs):
+        W, X, N, O = self._args(weights, xyz, outs)
+        b, c = C.c_int32(), C.c_int32()
+        _check(lib().ngvol_multi_autotune(self.handle, W, X, N, O, _stream(), C.byref(b), C.byref(c)))
+        return b.value, c.value
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.ngvol_multi_destroy(h)
+            self.handle = None

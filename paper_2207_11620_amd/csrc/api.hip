@@ -362,6 +362,7 @@ static int resolve_batch(const ngvol_plan* plan, const ngvol_batch* b, BatchArgs
   ba.vdtype = b->volume_dtype;
   ba.seed = b->seed;
   ba.step = b->step_index;
+  ba.step_ptr = nullptr;
   if (b->xyz) {
     NGV_REQUIRE(b->target && aligned4(b->xyz) && aligned4(b->target),
                 "explicit batch needs 4-byte aligned xyz and target");
@@ -370,7 +371,7 @@ static int resolve_batch(const ngvol_plan* plan, const ngvol_batch* b, BatchArgs
     NGV_REQUIRE(b->dims[0] >= 2 && b->dims[1] >= 2 && b->dims[2] >= 2, "volume dims must be >= 2");
     NGV_REQUIRE(b->volume_dtype == NGVOL_DT_F32 || b->volume_dtype == NGVOL_DT_F16, "volume dtype must be F32 or F16");
     NGV_REQUIRE(b->seed < (1ull << 56), "seed must be < 2^56");
-    NGV_REQUIRE(b->step_index >= 0, "step_index must be >= 0");
+    NGV_REQUIRE(b->step_index >= -1, "step_index must be >= 0, or -1 for the state's step counter");
   }
   return NGVOL_OK;
 }
@@ -380,6 +381,7 @@ int ngvol_sample_batch(const ngvol_plan* plan, const ngvol_batch* b, float* xyz,
   BatchArgs ba{};
   if (int rc = resolve_batch(plan, b, ba)) return rc;
   NGV_REQUIRE(!b->xyz, "ngvol_sample_batch needs a generated batch (xyz == NULL)");
+  NGV_REQUIRE(b->step_index >= 0, "ngvol_sample_batch needs an explicit step_index");
   NGV_REQUIRE(xyz && y && aligned4(xyz) && aligned4(y), "outputs must be non-NULL and 4-byte aligned");
   return hip_check(launch_sample_batch(ba, xyz, y, st), "sample_batch launch");
 }
@@ -419,6 +421,7 @@ int ngvol_train_step(const ngvol_plan* plan, const ngvol_train_state* s, const n
   if (int rc = check_bwd_lds(plan)) return rc;
   BatchArgs ba{};
   if (int rc = resolve_batch(plan, b, ba)) return rc;
+  if (!b->xyz && b->step_index < 0) ba.step_ptr = s->step;  // graph-replayable: batch index = applied steps
   const TrainWorkspace ws = train_workspace(plan, ba.B);
   if (s->workspace_bytes < ws.total)
     return fail(NGVOL_ENOMEM, "workspace of %zu bytes < %zu needed", s->workspace_bytes, ws.total);
@@ -518,6 +521,145 @@ int ngvol_render(const ngvol_plan* plan, const ngvol_weights* w, const ngvol_cam
   ra.queue = reinterpret_cast<unsigned int*>(ws);
   ra.counters = reinterpret_cast<unsigned long long*>(counters);
   return hip_check(launch_render(plan, tables_of(plan, w), w->params + plan->md.n_table, ra, st), "render launch");
+}
+
+// ---------------------------------------------------------------------------
+// Batches of independent volumes.
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct ngvol_multi {
+  int k;
+  ngvol_plan plan0;  // shape shared by the group (precision, widths, device)
+  ngvol::ModelDesc* table;  // device
+  int blocks_per_cu;
+  int chunk_tiles;
+};
+
+namespace {
+
+int multi_args(const ngvol_multi* g, const ngvol_weights* w, const float* const* xyz, const int64_t* n,
+               float* const* out, int chunk_tiles, MultiArgs& a, bool& f16) {
+  NGV_REQUIRE(w && xyz && n && out, "w, xyz, n and out must be non-NULL host arrays");
+  memset(&a, 0, sizeof a);
+  a.k = g->k;
+  a.chunk_tiles = chunk_tiles;
+  a.item_prefix[0] = 0;
+  f16 = w[0].table_f16 != nullptr;
+  for (int i = 0; i < g->k; ++i) {
+    if (int rc = check_weights(&w[i])) return rc;
+    NGV_REQUIRE((w[i].table_f16 != nullptr) == f16, "either every model or none has FP16 tables");
+    NGV_REQUIRE(n[i] >= 0 && n[i] < ((int64_t)1 << 31), "n[%d] out of range", i);
+    NGV_REQUIRE(n[i] == 0 || (xyz[i] && out[i] && aligned4(xyz[i]) && aligned4(out[i])),
+                "xyz[%d] and out[%d] must be non-NULL and 4-byte aligned", i, i);
+    a.params[i] = w[i].params;
+    a.f16[i] = reinterpret_cast<const __half*>(w[i].table_f16);
+    a.xyz[i] = xyz[i];
+    a.out[i] = out[i];
+    a.n[i] = n[i];
+    const int64_t tiles = (n[i] + 15) / 16;
+    a.item_prefix[i + 1] = a.item_prefix[i] + (tiles + chunk_tiles - 1) / chunk_tiles;
+  }
+  return NGVOL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t ngvol_multi_table_bytes(int32_t k) { return (size_t)(k > 0 ? k : 0) * sizeof(ngvol::ModelDesc); }
+
+int ngvol_multi_create(const ngvol_plan* const* plans, int32_t k, void* d_table, size_t table_bytes, hipStream_t st,
+                       ngvol_multi** out) {
+  NGV_REQUIRE(out && plans, "plans and out must be non-NULL");
+  *out = nullptr;
+  NGV_REQUIRE(k >= 1 && k <= NGVOL_MULTI_MAX, "k must be in [1, %d]", NGVOL_MULTI_MAX);
+  NGV_REQUIRE(d_table && aligned16(d_table) && table_bytes >= ngvol_multi_table_bytes(k),
+              "d_table must hold ngvol_multi_table_bytes(k) bytes, 16-byte aligned");
+  for (int i = 0; i < k; ++i) {
+    if (int rc = check_plan(plans[i])) return rc;
+    const ngvol_plan* p = plans[i];
+    const ngvol_plan* q = plans[0];
+    if (p->layout.precision != q->layout.precision || p->md.F != q->md.F || p->kin != q->kin ||
+        p->md.width != q->md.width || p->md.n_hidden != q->md.n_hidden)
+      return fail(NGVOL_EUNSUPPORTED, "model %d differs from model 0 in precision, features, input width or MLP", i);
+  }
+  if (plans[0]->md.F != 2) return fail(NGVOL_EUNSUPPORTED, "batched launches support n_features = 2");
+  ngvol_multi* g = new (std::nothrow) ngvol_multi;
+  if (!g) return fail(NGVOL_ENOMEM, "out of host memory");
+  g->k = k;
+  g->plan0 = *plans[0];
+  g->table = reinterpret_cast<ngvol::ModelDesc*>(d_table);
+  g->blocks_per_cu = 8;
+  g->chunk_tiles = 32;
+  ngvol::ModelDesc host[NGVOL_MULTI_MAX];
+  for (int i = 0; i < k; ++i) host[i] = plans[i]->md;
+  hipError_t e = hipMemcpyAsync(d_table, host, sizeof(ngvol::ModelDesc) * k, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    delete g;
+    return hip_check(e, "multi descriptor upload");
+  }
+  *out = g;
+  return NGVOL_OK;
+}
+
+int ngvol_multi_destroy(ngvol_multi* g) {
+  delete g;
+  return NGVOL_OK;
+}
+
+int ngvol_multi_infer(const ngvol_multi* g, const ngvol_weights* w, const float* const* xyz, const int64_t* n,
+                      float* const* out, hipStream_t st) {
+  NGV_REQUIRE(g, "group is NULL");
+  MultiArgs a;
+  bool f16 = false;
+  if (int rc = multi_args(g, w, xyz, n, out, g->chunk_tiles, a, f16)) return rc;
+  if (a.item_prefix[g->k] == 0) return NGVOL_OK;
+  return hip_check(launch_multi_infer(&g->plan0, g->table, a, f16, g->blocks_per_cu, st), "multi_infer launch");
+}
+
+int ngvol_multi_autotune(ngvol_multi* g, const ngvol_weights* w, const float* const* xyz, const int64_t* n,
+                         float* const* out, hipStream_t st, int32_t* bpc_out, int32_t* chunk_out) {
+  NGV_REQUIRE(g, "group is NULL");
+  static const int kBpc[] = {2, 4, 8, 16};
+  static const int kChunk[] = {8, 32, 128};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  float best = 1e30f;
+  int best_b = g->blocks_per_cu, best_c = g->chunk_tiles;
+  for (int bi = 0; bi < 4 && e == hipSuccess; ++bi)
+    for (int ci = 0; ci < 3 && e == hipSuccess; ++ci) {
+      MultiArgs a;
+      bool f16 = false;
+      if (int rc = multi_args(g, w, xyz, n, out, kChunk[ci], a, f16)) {
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        return rc;
+      }
+      if (a.item_prefix[g->k] == 0) break;
+      e = launch_multi_infer(&g->plan0, g->table, a, f16, kBpc[bi], st);  // warm-up
+      if (e == hipSuccess) e = hipEventRecord(e0, st);
+      for (int r = 0; r < 2 && e == hipSuccess; ++r) e = launch_multi_infer(&g->plan0, g->table, a, f16, kBpc[bi], st);
+      if (e == hipSuccess) e = hipEventRecord(e1, st);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e == hipSuccess && ms < best) {
+        best = ms;
+        best_b = kBpc[bi];
+        best_c = kChunk[ci];
+      }
+    }
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_check(e, "multi autotune");
+  g->blocks_per_cu = best_b;
+  g->chunk_tiles = best_c;
+  if (bpc_out) *bpc_out = best_b;
+  if (chunk_out) *chunk_out = best_c;
+  return NGVOL_OK;
 }
 
 }  // extern "C"

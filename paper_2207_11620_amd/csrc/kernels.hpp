@@ -32,6 +32,8 @@ struct BatchArgs {
   int32_t vdtype;
   uint64_t seed;
   int64_t step;
+  const int64_t* step_ptr;  // if set, the batch index is read from here (the state's step counter)
+  __device__ __forceinline__ int64_t step_index() const { return step_ptr ? *step_ptr : step; }
 };
 
 // Spatial binning of n samples (k = 0: not binned).  Workspace byte offsets
@@ -140,6 +142,21 @@ hipError_t launch_step_begin(double* loss_acc, int32_t* nonfinite, hipStream_t s
 hipError_t launch_step_end(const double* loss_acc, int32_t* nonfinite, int64_t* step, int32_t* skipped,
                            double* loss_out, double inv_b, hipStream_t st);
 hipError_t launch_make_f16(const float* params, __half* out, int64_t n, hipStream_t st);
+
+// Per-call arguments of a batched multi-model query (kernel arguments).
+constexpr int kMultiMax = NGVOL_MULTI_MAX;
+struct MultiArgs {
+  int k;
+  int chunk_tiles;
+  int64_t item_prefix[kMultiMax + 1];  // work items of models 0..m-1
+  const float* params[kMultiMax];
+  const __half* f16[kMultiMax];
+  const float* xyz[kMultiMax];
+  float* out[kMultiMax];
+  int64_t n[kMultiMax];
+};
+hipError_t launch_multi_infer(const ngvol_plan* plan0, const ModelDesc* table, const MultiArgs& a, bool f16,
+                              int blocks_per_cu, hipStream_t st);
 
 struct RenderArgs {
   float cam[12];

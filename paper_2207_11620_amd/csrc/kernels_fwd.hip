@@ -205,6 +205,7 @@ __global__ void __launch_bounds__(256) k_train_fwd(ModelDesc md, TablePtrs tp, c
   const VT* vol = reinterpret_cast<const VT*>(ba.volume);
   const int lane = threadIdx.x & 63, nl = lane & 15, g = lane >> 4;
   const int64_t B = ba.B;
+  const int64_t bstep = ba.step_index();
   double lsum = 0.0;
   const int64_t n_tiles = (B + 15) >> 4;
   TileIter it(n_tiles);
@@ -219,9 +220,9 @@ __global__ void __launch_bounds__(256) k_train_fwd(ModelDesc md, TablePtrs tp, c
       z = clamp01(ba.xyz[3 * sc + 2]);
       target = ba.target[sc];
     } else {
-      x = batch_coord(ba.seed, ba.step, B, sc, 0);
-      y = batch_coord(ba.seed, ba.step, B, sc, 1);
-      z = batch_coord(ba.seed, ba.step, B, sc, 2);
+      x = batch_coord(ba.seed, bstep, B, sc, 0);
+      y = batch_coord(ba.seed, bstep, B, sc, 1);
+      z = batch_coord(ba.seed, bstep, B, sc, 2);
       target = volume_sample<VT>(vol, ba.dims[0], ba.dims[1], ba.dims[2], x, y, z);
     }
     float f[KIN / 32][8];
@@ -267,9 +268,10 @@ template <typename VT>
 __global__ void __launch_bounds__(256) k_sample_batch(BatchArgs ba, float* __restrict__ xyz, float* __restrict__ y) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ba.B) return;
-  const float a = batch_coord(ba.seed, ba.step, ba.B, i, 0);
-  const float b = batch_coord(ba.seed, ba.step, ba.B, i, 1);
-  const float c = batch_coord(ba.seed, ba.step, ba.B, i, 2);
+  const int64_t bstep = ba.step_index();
+  const float a = batch_coord(ba.seed, bstep, ba.B, i, 0);
+  const float b = batch_coord(ba.seed, bstep, ba.B, i, 1);
+  const float c = batch_coord(ba.seed, bstep, ba.B, i, 2);
   xyz[3 * i] = a;
   xyz[3 * i + 1] = b;
   xyz[3 * i + 2] = c;

@@ -1,0 +1,111 @@
+// Batched queries of many independent neural volumes in one persistent
+// launch.
+//
+// The models of a group share the MLP shape (precision, padded input width,
+// width, depth) and the feature count, so one kernel instantiation serves
+// them all; they differ in levels, resolutions and table sizes, which are
+// read from a device table of model descriptors.  Work is cut into items of
+// `chunk_tiles` 16-sample tiles of one model, ordered model by model; each
+// workgroup walks one contiguous range of items, so it meets few model
+// boundaries, and restages the model's MLP weights in LDS at each one.
+#include <type_traits>
+
+#include "kernels.hpp"
+#include "mlp_tile.hpp"
+
+namespace ngvol {
+
+template <int P, int F, int KIN, int W, typename TT>
+__global__ void __launch_bounds__(256) k_multi_infer(const ModelDesc* __restrict__ table, MultiArgs a) {
+  typedef typename Prec<P>::Frag Frag;
+  typedef WeightLayout<P, KIN, W> WL;
+  extern __shared__ __align__(16) unsigned char smem[];
+  Frag* lds_frag = reinterpret_cast<Frag*>(smem);
+  const int nh = table[0].n_hidden;  // shared by the group
+  float* lds_wout = reinterpret_cast<float*>(smem + (size_t)WL::frags(nh, false) * 64 * sizeof(Frag));
+
+  const int lane = threadIdx.x & 63, nl = lane & 15, g = lane >> 4, wave = threadIdx.x >> 6;
+  const int wpb = blockDim.x >> 6;
+  const int64_t total = a.item_prefix[a.k];
+  const int64_t per = (total + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = (int64_t)blockIdx.x * per;
+  const int64_t hi = lo + per < total ? lo + per : total;
+  int cur = -1;
+  int m = 0;
+  for (int64_t item = lo; item < hi; ++item) {
+    while (item >= a.item_prefix[m + 1]) ++m;  // uniform across the workgroup
+    if (m != cur) {
+      __syncthreads();
+      stage_weights<P, KIN, W>(table[m], a.params[m] + table[m].n_table, lds_frag, lds_wout, false);
+      __syncthreads();
+      cur = m;
+    }
+    const ModelDesc& md = table[m];
+    const TT* tab;
+    if constexpr (std::is_same<TT, __half>::value) tab = a.f16[m];
+    else tab = a.params[m];
+    const float* xyz = a.xyz[m];
+    float* out = a.out[m];
+    const int64_t n = a.n[m];
+    const int64_t n_tiles = (n + 15) >> 4;
+    const int64_t first = (item - a.item_prefix[m]) * a.chunk_tiles;
+    for (int j = wave; j < a.chunk_tiles; j += wpb) {
+      const int64_t t = first + j;
+      if (t >= n_tiles) break;
+      const int64_t s = t * 16 + nl;
+      const bool valid = s < n;
+      const int64_t sc = valid ? s : n - 1;
+      const float x = clamp01(xyz[3 * sc]), y = clamp01(xyz[3 * sc + 1]), z = clamp01(xyz[3 * sc + 2]);
+      float f[KIN / 32][8];
+      encode_lane<F, KIN>(md, tab, x, y, z, f);
+      Frag in[InChunks<P, KIN>::n];
+      feat_to_frag<P, KIN>(f, in);
+      f32x4 act[W / 16];
+      mlp_hidden_fwd<P, KIN, W, false>(nh, lds_frag, in, act, nullptr);
+      const float yv = mlp_output<W>(act, lds_wout);
+      if (valid && g == 0) out[s] = yv;
+    }
+  }
+}
+
+hipError_t launch_multi_infer(const ngvol_plan* plan0, const ModelDesc* table, const MultiArgs& a, bool f16,
+                              int blocks_per_cu, hipStream_t st) {
+  const ModelDesc& md = plan0->md;
+  const size_t lds = fwd_lds_bytes(plan0);
+  int64_t grid = a.item_prefix[a.k];
+  const int64_t cap = (int64_t)plan0->cus * blocks_per_cu;
+  if (grid > cap) grid = cap;
+  if (grid < 1) grid = 1;
+#define NGV_MI(P, KIN, W)                                                                                      \
+  do {                                                                                                         \
+    if (f16)                                                                                                   \
+      hipLaunchKernelGGL((k_multi_infer<P, 2, KIN, W, __half>), dim3((unsigned)grid), dim3(256), lds, st, table, a); \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_multi_infer<P, 2, KIN, W, float>), dim3((unsigned)grid), dim3(256), lds, st, table, a);  \
+  } while (0)
+#define NGV_MI_W(P, KIN)                                   \
+  do {                                                     \
+    if (md.width == 32) NGV_MI(P, KIN, 32);                \
+    else if (md.width == 64) NGV_MI(P, KIN, 64);           \
+    else return hipErrorInvalidValue;                      \
+  } while (0)
+#define NGV_MI_K(P)                                        \
+  do {                                                     \
+    if (plan0->kin == 32) NGV_MI_W(P, 32);                 \
+    else if (plan0->kin == 64) NGV_MI_W(P, 64);            \
+    else return hipErrorInvalidValue;                      \
+  } while (0)
+  if (md.F != 2) return hipErrorInvalidValue;
+  switch (plan0->layout.precision) {
+    case 0: NGV_MI_K(0); break;
+    case 1: NGV_MI_K(1); break;
+    case 2: NGV_MI_K(2); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef NGV_MI_K
+#undef NGV_MI_W
+#undef NGV_MI
+  return hipGetLastError();
+}
+
+}  // namespace ngvol

@@ -29,6 +29,10 @@ struct Coords {
   const float* xyz;
   uint64_t seed;
   int64_t step, B;
+  const int64_t* step_ptr;
+  __device__ __forceinline__ void resolve() {
+    if (step_ptr) step = *step_ptr;
+  }
   __device__ __forceinline__ void get(int64_t i, float& x, float& y, float& z) const {
     if (xyz) {
       x = clamp01(xyz[3 * i]);
@@ -45,6 +49,7 @@ struct Coords {
 __global__ void __launch_bounds__(kScThreads) k_sc_count(ModelDesc md, Coords src, int64_t B, int64_t chunk,
                                                          int bshift, int nb, uint32_t* __restrict__ counts) {
   extern __shared__ uint32_t hist[];
+  src.resolve();
   for (int b = threadIdx.x; b < nb; b += blockDim.x) hist[b] = 0u;
   __syncthreads();
   const int64_t lo = (int64_t)blockIdx.x * chunk;
@@ -76,6 +81,7 @@ __global__ void __launch_bounds__(kScThreads) k_sc_fill(ModelDesc md, Coords src
                                                         const uint32_t* __restrict__ offsets,
                                                         const float* __restrict__ dfeat, uint4* __restrict__ rec) {
   extern __shared__ uint32_t cur[];
+  src.resolve();
   const uint32_t* mine = counts + (size_t)blockIdx.x * nb;
   for (int b = threadIdx.x; b < nb; b += blockDim.x) cur[b] = offsets[b] + mine[b];
   __syncthreads();
@@ -203,7 +209,7 @@ hipError_t launch_scatter(const ngvol_plan* plan, const ScatterPlan& sp, const B
   uint32_t* counts = reinterpret_cast<uint32_t*>(base + sp.counts_off);
   uint32_t* totals = reinterpret_cast<uint32_t*>(base + sp.totals_off);
   uint32_t* offsets = reinterpret_cast<uint32_t*>(base + sp.offsets_off);
-  const Coords src{ba.xyz, ba.seed, ba.step, ba.B};
+  const Coords src{ba.xyz, ba.seed, ba.step, ba.B, ba.step_ptr};
   const size_t hist_lds = (size_t)sp.n_buckets * 4;
   hipLaunchKernelGGL(k_sc_count, dim3(sp.blocks), dim3(kScThreads), hist_lds, st, md, src, ba.B, sp.chunk, sp.bshift,
                      sp.n_buckets, counts);

@@ -183,7 +183,7 @@ hipError_t launch_bin(const ngvol_plan* plan, const BinPlan& bp, const float* xy
   if (ba) {
     src.xyz = ba->xyz;
     src.seed = ba->seed;
-    src.step = ba->step;
+    src.step = ba->step;  // training batches are not regrouped (see the training workspace)
     src.B = ba->B;
   }
   const size_t lds = (size_t)bp.n_bins * 4;

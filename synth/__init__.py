@@ -201,3 +201,84 @@ def orbit_camera(angle: float, W: int, H: int, radius: float = 2.0, fov_deg: flo
     V = upv * (2.0 * th / H)
     Wc = fwd - right * th * aspect - upv * th
     return np.concatenate([eye, U, V, Wc]).astype(np.float32)
+
+
+# --------------------------------------------------------------------------
+# The same volumes generated with torch on a device (large targets).
+# --------------------------------------------------------------------------
+
+def _torch_normalise_(vol, lo, hi, chunk):
+    for z0 in range(0, vol.shape[0], chunk):
+        sl = vol[z0:z0 + chunk].float()
+        vol[z0:z0 + chunk] = ((sl - lo) / (hi - lo)).to(vol.dtype)
+    return vol
+
+
+def gaussian_blobs_torch(D: int, seed: int, device, dtype=None, n_blobs: int = 8, chunk: int = 64):
+    """gaussian_blobs() evaluated with torch (FP32 arithmetic) on `device`."""
+    import torch
+    dtype = dtype or torch.float16
+    u = rng_u01_f64(seed, STREAM_VOLUME, np.arange(5 * n_blobs)).reshape(n_blobs, 5)
+    x = (torch.arange(D, device=device, dtype=torch.float32) + 0.5) / D
+    vol = torch.empty((D, D, D), dtype=dtype, device=device)
+    lo, hi = float("inf"), float("-inf")
+    gs = []
+    for k in range(n_blobs):
+        c = u[k, 0:3]
+        sigma = 0.05 + 0.15 * u[k, 3]
+        amp = 0.2 + 0.8 * u[k, 4]
+        gs.append([torch.exp(-((x - float(c[a])) ** 2) / (2.0 * sigma * sigma)) for a in range(3)] + [amp])
+    for z0 in range(0, D, chunk):
+        z1 = min(D, z0 + chunk)
+        acc = torch.zeros((z1 - z0, D, D), dtype=torch.float32, device=device)
+        for gx, gy, gz, amp in gs:
+            acc += amp * gz[z0:z1, None, None] * gy[None, :, None] * gx[None, None, :]
+        lo, hi = min(lo, float(acc.min())), max(hi, float(acc.max()))
+        vol[z0:z1] = acc.to(dtype)
+    return _torch_normalise_(vol, lo, hi, chunk)
+
+
+def fractal_value_noise_torch(D: int, seed: int, device, dtype=None, octaves: int = 6, base_freq: int = 4,
+                              lacunarity: int = 2, gain: float = 0.5, chunk: int = 32):
+    """fractal_value_noise() evaluated with torch (FP32 arithmetic) on `device`."""
+    import torch
+    dtype = dtype or torch.float16
+    x = (np.arange(D, dtype=np.float64) + 0.5) / D
+    octs = []
+    offset = 0
+    amp = 1.0
+    for o in range(octaves):
+        f = base_freq * lacunarity ** o
+        n_lat = (f + 1) ** 3
+        lat = rng_u01_f64(seed, STREAM_VOLUME, np.arange(offset, offset + n_lat)).reshape(f + 1, f + 1, f + 1)
+        offset += n_lat
+        X = x * f
+        i0 = np.minimum(np.floor(X).astype(np.int64), f - 1)
+        t = X - i0
+        s = t * t * (3.0 - 2.0 * t)
+        a = lat[:, :, i0] * (1.0 - s)[None, None, :] + lat[:, :, i0 + 1] * s[None, None, :]
+        b = a[:, i0, :] * (1.0 - s)[None, :, None] + a[:, i0 + 1, :] * s[None, :, None]
+        octs.append((torch.from_numpy(b.astype(np.float32)).to(device), torch.from_numpy(i0).to(device),
+                     torch.from_numpy(s.astype(np.float32)).to(device), amp))
+        amp *= gain
+    vol = torch.empty((D, D, D), dtype=dtype, device=device)
+    lo, hi = float("inf"), float("-inf")
+    for z0 in range(0, D, chunk):
+        z1 = min(D, z0 + chunk)
+        acc = torch.zeros((z1 - z0, D, D), dtype=torch.float32, device=device)
+        for b, i0, s, a in octs:
+            iz = i0[z0:z1]
+            sz = s[z0:z1][:, None, None]
+            acc += a * (b[iz] * (1.0 - sz) + b[iz + 1] * sz)
+        lo, hi = min(lo, float(acc.min())), max(hi, float(acc.max()))
+        vol[z0:z1] = acc.to(dtype)
+    return _torch_normalise_(vol, lo, hi, chunk)
+
+
+def multi_volume_specs(k: int = 16):
+    """The batched workload: model i has log2 T = 16 + (i mod 7), L = (8, 12, 16)[i mod 3]
+    levels from 16 to 2048 vertices, F = 2, a 64-64 MLP; its target is a
+    (128, 256, 512, 1024)[i mod 4]^3 FP16 volume, Gaussian blobs for even i and
+    fractal noise for odd i, seed 1000 + i."""
+    return [dict(log2T=16 + (i % 7), L=(8, 12, 16)[i % 3], D=(128, 256, 512, 1024)[i % 4],
+                 kind="blobs" if i % 2 == 0 else "noise", seed=1000 + i) for i in range(k)]

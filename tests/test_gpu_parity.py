@@ -446,3 +446,78 @@ def test_online_training_interleave():
     same = host(nu_b).ravel()[pix] == nuo
     assert np.all(same | (np.abs(ro[:, 3] - 0.99) < 2e-3))
     assert np.max(np.abs(g[same] - ro[same])) <= 1e-4
+
+
+# ----------------------------------------------------------- multi-volume -----
+
+def _multi_models(k=16, scale=0.5):
+    plans, params = [], []
+    for i, sp in enumerate(synth.multi_volume_specs(k)):
+        p = ngv.Plan(sp["L"], 2, sp["log2T"], 16, 0.0, 2048, n_neurons=64, n_hidden_layers=2, precision="bf16")
+        plans.append(p)
+        params.append(dev(synth.init_params(p.n_table_params, p.n_input, 64, 2, scale, sp["seed"])))
+    return plans, params
+
+
+def test_multi_infer_equals_single_launches():
+    plans, params = _multi_models()
+    f16 = [ngv.make_f16_tables(p, w) for p, w in zip(plans, params)]
+    ns = [1000 + 373 * i for i in range(16)]
+    ns[5] = 0  # an empty model in the batch
+    xyz = [dev(synth.query_coords(max(n, 1), 50 + i)[:n].copy()) for i, n in enumerate(ns)]
+    grp = ngv.Multi(plans)
+    outs = grp.infer(list(zip(params, f16)), xyz)
+    for i in range(16):
+        if ns[i] == 0:
+            continue
+        ref = ngv.infer(plans[i], params[i], xyz[i], table_f16=f16[i], sort=False)
+        np.testing.assert_array_equal(host(outs[i]), host(ref))
+    # spot-check one model against the oracle
+    sp = synth.multi_volume_specs()[3]
+    m = oracle.Model(sp["L"], 2, sp["log2T"], plans[3].resolution, 64, 2)
+    q = host(params[3]).astype(np.float64)
+    q[:m.n_table] = host(f16[3]).astype(np.float64)
+    assert rel_err(host(outs[3]), oracle.forward(m, q, host(xyz[3]))) <= 2e-2
+    # the autotuned launch shape gives the same values
+    b, c = grp.autotune(list(zip(params, f16)), xyz, outs)
+    assert b in (2, 4, 8, 16) and c in (8, 32, 128)
+    outs2 = grp.infer(list(zip(params, f16)), xyz)
+    for i in range(16):
+        np.testing.assert_array_equal(host(outs2[i]), host(outs[i]))
+
+
+def test_multi_rejects_mixed_shapes():
+    a = ngv.Plan(8, 2, 14, 16, 0.0, 2048, n_neurons=64, n_hidden_layers=2, precision="bf16")
+    b = ngv.Plan(8, 2, 14, 16, 0.0, 2048, n_neurons=32, n_hidden_layers=2, precision="bf16")
+    with pytest.raises(ngv.NgvolError) as ei:
+        ngv.Multi([a, b])
+    assert ei.value.code == ngv.EUNSUPPORTED
+
+
+def test_graph_captured_training_matches_eager():
+    # a training step captured in a graph (batch index from the device step
+    # counter) replays like eager steps, within the atomic-order tolerance
+    p = gpu_plan("tiny", "fp32")
+    vol = dev(synth.gaussian_blobs(32, SEED))
+    params = dev(init_params("tiny", table_scale=0.2))
+    eager = ngv.TrainState(p, params, 4096)
+    for k in range(6):
+        ngv.train_step(eager, volume=vol, seed=SEED, step_index=k, loss_scale=128.0)
+    cap = ngv.TrainState(p, params, 4096)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        ngv.train_step(cap, volume=vol, seed=SEED, step_index=-1, loss_scale=128.0)  # step 0, eager
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        ngv.train_step(cap, volume=vol, seed=SEED, step_index=-1, loss_scale=128.0)
+    for _ in range(5):
+        g.replay()
+        torch.cuda.synchronize()
+    assert host(cap.step)[0] == 6
+    # summation order differs (LDS atomics), and Adam turns a near-zero
+    # gradient of either sign into a full step, so compare the bulk
+    d = np.abs(host(cap.params) - host(eager.params))
+    assert np.quantile(d, 0.999) <= 1e-5
+    assert host(cap.loss)[0] == pytest.approx(host(eager.loss)[0], rel=1e-3)

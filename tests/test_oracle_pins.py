@@ -436,3 +436,15 @@ def test_render_constant_alpha_closed_form():
     assert np.all(nu2 == ng2)
     for q in range(4):
         np.testing.assert_allclose(rgba2[q, 3], 1 - (1 - a) ** int(ng2[q]), rtol=1e-13)
+
+
+def test_device_volume_generators_match_numpy():
+    # the torch generators (used for the large batched targets) draw the same volumes
+    torch = pytest.importorskip("torch")
+    a = synth.gaussian_blobs(24, 3)
+    b = synth.gaussian_blobs_torch(24, 3, "cpu", dtype=torch.float32, chunk=7).numpy()
+    np.testing.assert_allclose(a, b, atol=2e-6)
+    c = synth.fractal_value_noise(20, 5)
+    d = synth.fractal_value_noise_torch(20, 5, "cpu", dtype=torch.float32, chunk=6).numpy()
+    np.testing.assert_allclose(c, d, atol=2e-6)
+    assert len(synth.multi_volume_specs()) == 16
