@@ -320,6 +320,31 @@ def main():
             f"batched {bat_ms:.2f} ms (autotune {bpc} wg/CU, {chunk} tiles)")
         del grp, mstates, mvols, mxyz, mout, graph
 
+    # ----------------------------------------------- standalone MLP on MFMA
+    # k_mlp_fwd over an HBM-resident BF16 feature buffer [2^24][32]: the
+    # dense contraction alone, 2 * (32*64 + 64*64 + 64) = 12,416 flop/sample.
+    feat = torch.empty((N_QUERY, MODEL["n_levels"] * MODEL["n_features"]), dtype=torch.bfloat16, device=dev)
+    feat.uniform_(-1.0, 1.0)
+    ymlp = torch.empty(N_QUERY, dtype=torch.float32, device=dev)
+    for _ in range(2):
+        ngv.mlp_fwd(plan16, params0, feat, out=ymlp)
+    e = [ev() for _ in range(2)]
+    e[0].record()
+    for _ in range(10):
+        ngv.mlp_fwd(plan16, params0, feat, out=ymlp)
+    e[1].record()
+    torch.cuda.synchronize()
+    mlp_ms = e[0].elapsed_time(e[1]) / 10
+    flop = 2 * (32 * 64 + 64 * 64 + 64)
+    tf = flop * N_QUERY / (mlp_ms * 1e-3) / 1e12
+    mlp_roofline = {"kernel": "k_mlp_fwd (bf16, 32-64-64-1)", "bound": "mfma", "achieved": round(tf, 1),
+                    "peak": 2500.0, "unit": "TFLOP/s", "frac": round(tf / 2500.0, 4), "flop_per_sample": flop,
+                    "samples_per_launch": N_QUERY, "avg_launch_ms": round(mlp_ms, 4),
+                    "input_bytes_per_sample": 64,
+                    "memory_bound_frac": round(min(1.0, 8000e9 / 68 * flop / 2500e12), 4)}
+    log(f"mlp_fwd bf16: {mlp_ms:.3f} ms, {tf:.1f} TFLOP/s ({tf / 2500 * 100:.1f}% of BF16 peak)")
+    del feat, ymlp
+
     # --------------------------------------------------------------- roofline
     # query kernel: algorithmic bytes per query = L*8*F FP16 table reads + 12 B xyz + 4 B out
     bytes_q = MODEL["n_levels"] * 8 * MODEL["n_features"] * 2 + 12 + 4
@@ -370,7 +395,7 @@ def main():
                       "infer_samples_per_s": N_QUERY / ((sort_ms + infer_ms) * 1e-3),
                       "infer_unsorted_ms": round(direct_ms, 4)},
         "fp32_plain": fp32, "quality": quality, "render": render, "multi_volume": multi, "roofline": roofline,
-        "cpu_baseline": cpu,
+        "mlp_roofline": mlp_roofline, "cpu_baseline": cpu,
     }
     s = json.dumps(line)
     print(s, flush=True)

@@ -208,11 +208,12 @@ def encode_debug(plan, xyz):
     return idx, w
 
 
-def mlp_fwd(plan, params, feat):
+def mlp_fwd(plan, params, feat, out=None):
     torch = _torch()
     n = feat.shape[0]
     dt = {torch.float32: DT_F32, torch.bfloat16: DT_BF16, torch.float16: DT_F16}[feat.dtype]
-    out = torch.empty(n, dtype=torch.float32, device=feat.device)
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=feat.device)
     _check(lib().ngvol_mlp_fwd(plan.handle, _ptr(params), _ptr(feat), dt, n, _ptr(out), _stream()))
     return out
 
