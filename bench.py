@@ -53,7 +53,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--quality-steps", type=int, default=2000)
-    ap.add_argument("--quality-repeats", type=int, default=3)
+    ap.add_argument("--quality-repeats", type=int, default=5)
     ap.add_argument("--no-quality", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
@@ -173,7 +173,8 @@ def main():
     # Training with these hyper-parameters is noisy run to run (FP32 atomics
     # make every run's trajectory different and the final PSNR varies by
     # several dB), so each form is trained several times from the same
-    # initialisation with different batch seeds and the means are compared.
+    # initialisation with different batch seeds and the means and medians
+    # are compared.
     quality = None
     trained = None
     if not args.no_quality:
@@ -198,6 +199,8 @@ def main():
                    "repeats": args.quality_repeats, "psnr_bf16_db": [round(v, 3) for v in res["bf16"]],
                    "psnr_fp32_db": [round(v, 3) for v in res["fp32"]], "mean_bf16_db": round(mb, 3),
                    "mean_fp32_db": round(mf, 3), "psnr_loss_db": round(mf - mb, 3),
+                   "median_bf16_db": round(float(np.median(res["bf16"])), 3),
+                   "median_fp32_db": round(float(np.median(res["fp32"])), 3),
                    "fp32_run_to_run_std_db": round(float(np.std(res["fp32"])), 3)}
 
     # ---------------------------------------------------- online render leg

@@ -58,9 +58,9 @@ hipError_t launch_count_offsets(uint32_t* counts, int blocks, int nb, uint32_t* 
 // Bucketed scatter of dL/dfeature into the table gradient (no global
 // atomics except where one bucket is split over several workgroups).
 struct ScatterPlan {
-  int bshift, n_buckets, blocks, rec_words, max_chunks;
+  int bshift, n_buckets, blocks, rec_words, max_items;
   int64_t chunk, n_records, chunk_records;
-  size_t rec_off, counts_off, totals_off, offsets_off, bytes;
+  size_t rec_off, counts_off, totals_off, offsets_off, items_off, bytes;
 };
 ScatterPlan scatter_plan(const ngvol_plan* plan, int64_t B);
 hipError_t launch_scatter(const ngvol_plan* plan, const ScatterPlan& sp, const struct BatchArgs& ba,

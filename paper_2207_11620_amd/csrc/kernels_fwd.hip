@@ -1,5 +1,7 @@
 // Forward kernels: encoding, fused query, standalone MLP, training forward,
 // grid squared error, sampling step.
+#include <type_traits>
+
 #include "kernels.hpp"
 #include "mlp_tile.hpp"
 
@@ -132,6 +134,9 @@ __device__ __forceinline__ float load_feat<_Float16>(const _Float16* p, int64_t 
 template <int P, int KIN, int W, typename IT>
 __global__ void __launch_bounds__(256) k_mlp_fwd(ModelDesc md, const float* __restrict__ mlp,
                                                  const IT* __restrict__ feat, int64_t n, float* __restrict__ out) {
+  // NB tiles (16 samples each) per wave and iteration: the weight fragments
+  // are read from LDS once per NB tiles and the MFMA chains interleave.
+  constexpr int NB = 4;
   typedef typename Prec<P>::Frag Frag;
   typedef WeightLayout<P, KIN, W> WL;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -141,24 +146,26 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(ModelDesc md, const float* __re
   __syncthreads();
   const int lane = threadIdx.x & 63, nl = lane & 15, g = lane >> 4;
   const int n_in = md.n_in;
-  const int64_t n_tiles = (n + 15) >> 4;
-  TileIter it(n_tiles);
+  const int64_t n_groups = (n + 16 * NB - 1) / (16 * NB);
+  TileIter it(n_groups);
   for (int64_t t = it.next; t < it.end; t += it.step) {
-    const int64_t s = t * 16 + nl;
-    const bool valid = s < n;
-    const int64_t sc = valid ? s : n - 1;
-    float f[KIN / 32][8];
-    if constexpr (sizeof(IT) == 2) {
-      if (n_in == KIN) {
-        // 16-byte vector loads: 8 BF16 features per lane per block
+    Frag in[NB][InChunks<P, KIN>::n];
 #pragma unroll
-        for (int b = 0; b < KIN / 32; ++b) {
-          const uint4 raw = *reinterpret_cast<const uint4*>(feat + sc * KIN + 32 * b + 8 * g);
-          const IT* h = reinterpret_cast<const IT*>(&raw);
+    for (int nb = 0; nb < NB; ++nb) {
+      const int64_t s = (t * NB + nb) * 16 + nl;
+      const int64_t sc = s < n ? s : n - 1;
+      float f[KIN / 32][8];
+      bool direct = false;
+      if constexpr (P != 0 && sizeof(IT) == 2) {
+        if (n_in == KIN && std::is_same<IT, typename Prec<P>::T>::value) {
+          // the stored 16-bit features are the operand: one 16-byte load per lane per block
 #pragma unroll
-          for (int jj = 0; jj < 8; ++jj) f[b][jj] = (float)h[jj];
+          for (int b = 0; b < KIN / 32; ++b)
+            in[nb][b] = *reinterpret_cast<const Frag*>(feat + sc * KIN + 32 * b + 8 * g);
+          direct = true;
         }
-      } else {
+      }
+      if (!direct) {
 #pragma unroll
         for (int b = 0; b < KIN / 32; ++b)
 #pragma unroll
@@ -166,22 +173,17 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(ModelDesc md, const float* __re
             const int k = 32 * b + 8 * g + jj;
             f[b][jj] = k < n_in ? load_feat<IT>(feat, sc * n_in + k) : 0.0f;
           }
+        feat_to_frag<P, KIN>(f, in[nb]);
       }
-    } else {
-#pragma unroll
-      for (int b = 0; b < KIN / 32; ++b)
-#pragma unroll
-        for (int jj = 0; jj < 8; ++jj) {
-          const int k = 32 * b + 8 * g + jj;
-          f[b][jj] = k < n_in ? load_feat<IT>(feat, sc * n_in + k) : 0.0f;
-        }
     }
-    Frag in[InChunks<P, KIN>::n];
-    feat_to_frag<P, KIN>(f, in);
-    f32x4 act[W / 16];
-    mlp_hidden_fwd<P, KIN, W, false>(md.n_hidden, lds_frag, in, act, nullptr);
-    const float yv = mlp_output<W>(act, lds_wout);
-    if (valid && g == 0) out[s] = yv;
+    f32x4 act[NB][W / 16];
+    mlp_hidden_fwd_nb<P, KIN, W, NB>(md.n_hidden, lds_frag, in, act);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const float yv = mlp_output<W>(act[nb], lds_wout);
+      const int64_t s = (t * NB + nb) * 16 + nl;
+      if (s < n && g == 0) out[s] = yv;
+    }
   }
 }
 
@@ -380,7 +382,7 @@ hipError_t launch_sq_error_grid(const ngvol_plan* plan, TablePtrs tp, const floa
 hipError_t launch_mlp_fwd(const ngvol_plan* plan, const float* mlp, const void* feat, int dtype, int64_t n,
                           float* out, hipStream_t st) {
   const ModelDesc& md = plan->md;
-  const int64_t n_tiles = (n + 15) / 16;
+  const int64_t n_tiles = (n + 63) / 64;  // 4-tile groups
   const size_t lds = fwd_lds_bytes(plan);
   const int grid = grid_for(plan, n_tiles, 4, 8);
   NGV_DISPATCH_P(plan->layout.precision, {

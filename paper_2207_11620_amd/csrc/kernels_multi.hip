@@ -33,7 +33,10 @@ __global__ void __launch_bounds__(256) k_multi_infer(const ModelDesc* __restrict
   int cur = -1;
   int m = 0;
   for (int64_t item = lo; item < hi; ++item) {
-    while (item >= a.item_prefix[m + 1]) ++m;  // uniform across the workgroup
+    while (item >= a.item_prefix[m + 1]) ++m;
+    // the model index is uniform across the workgroup: say so, so that its
+    // descriptor is read through the scalar cache
+    m = __builtin_amdgcn_readfirstlane(m);
     if (m != cur) {
       __syncthreads();
       stage_weights<P, KIN, W>(table[m], a.params[m] + table[m].n_table, lds_frag, lds_wout, false);

@@ -10,10 +10,11 @@
 //   2. block prefix and scan of the counts (shared with the spatial sort);
 //   3. fill: each contribution is written as a record (entry, w*d[0..F-1])
 //      at its bucket's next position (LDS cursors);
-//   4. reduce: one workgroup per (bucket, chunk of records) accumulates the
-//      records in LDS and adds the bucket's entries into the gradient -
-//      with plain stores when the bucket fits one chunk (it owns those
-//      entries), with atomics only when a heavily hit bucket is split.
+//   4. reduce: one workgroup per (bucket, chunk of records) - a work list
+//      built on the device from the bucket sizes, so no workgroup is empty -
+//      accumulates the records in LDS and adds the bucket's entries into the
+//      gradient, with plain stores when the bucket fits one chunk (it owns
+//      those entries), with atomics only when a heavily hit bucket is split.
 #include "kernels.hpp"
 #include "device_common.hpp"
 
@@ -115,17 +116,49 @@ __global__ void __launch_bounds__(kScThreads) k_sc_fill(ModelDesc md, Coords src
   }
 }
 
+// Work list of the reduce: one item per (bucket, chunk of records) that has
+// records, built by one workgroup from the bucket sizes.  items[0] holds the
+// count; item i is (bucket, chunk) = (items[2 + 2i], items[3 + 2i]).
+__global__ void __launch_bounds__(1024) k_sc_worklist(const uint32_t* __restrict__ totals, int nb,
+                                                      int64_t chunk_records, uint32_t* __restrict__ items) {
+  __shared__ uint32_t part[1024];
+  const int per = (nb + 1023) / 1024;
+  const int lo = threadIdx.x * per;
+  uint32_t c = 0;
+  for (int i = 0; i < per; ++i)
+    if (lo + i < nb) c += (uint32_t)((totals[lo + i] + chunk_records - 1) / chunk_records);
+  part[threadIdx.x] = c;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    const uint32_t v = threadIdx.x >= (unsigned)d ? part[threadIdx.x - d] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint32_t pos = part[threadIdx.x] - c;
+  for (int i = 0; i < per; ++i) {
+    if (lo + i >= nb) break;
+    const uint32_t nch = (uint32_t)((totals[lo + i] + chunk_records - 1) / chunk_records);
+    for (uint32_t ch = 0; ch < nch; ++ch, ++pos) {
+      items[2 + 2 * (size_t)pos] = (uint32_t)(lo + i);
+      items[3 + 2 * (size_t)pos] = ch;
+    }
+  }
+  if (threadIdx.x == 1023) items[0] = part[1023];
+}
+
 template <int F>
 __global__ void __launch_bounds__(kReduceThreads) k_sc_reduce(const uint4* __restrict__ rec,
                                                               const uint32_t* __restrict__ totals,
-                                                              const uint32_t* __restrict__ offsets, int bshift,
+                                                              const uint32_t* __restrict__ offsets,
+                                                              const uint32_t* __restrict__ items, int bshift,
                                                               int64_t chunk_records, int64_t n_entries,
                                                               float* __restrict__ grad) {
   extern __shared__ float acc[];
-  const int bucket = blockIdx.x;
+  if (blockIdx.x >= items[0]) return;
+  const int bucket = (int)items[2 + 2 * (size_t)blockIdx.x];
   const int64_t cnt = totals[bucket];
-  const int64_t lo = (int64_t)blockIdx.y * chunk_records;
-  if (lo >= cnt) return;
+  const int64_t lo = (int64_t)items[3 + 2 * (size_t)blockIdx.x] * chunk_records;
   const int64_t hi = lo + chunk_records < cnt ? lo + chunk_records : cnt;
   const int span = (1 << bshift) * F;
   for (int t = threadIdx.x; t < span; t += blockDim.x) acc[t] = 0.0f;
@@ -181,23 +214,15 @@ ScatterPlan scatter_plan(const ngvol_plan* plan, int64_t B) {
   sp.rec_words = (1 + F + 3) / 4;
   sp.n_records = B * 8 * md.L;
   sp.chunk_records = kChunkRecords;
-  // most records one bucket can receive: B*8 per level overlapping it
-  int maxlv = 1;
-  for (int b0 = 0; b0 < sp.n_buckets; ++b0) {
-    const int64_t lo = (int64_t)b0 << sp.bshift, hi = lo + (1 << sp.bshift);
-    int c = 0;
-    for (int l = 0; l < md.L; ++l)
-      if ((int64_t)md.lv[l].offset < hi && (int64_t)md.lv[l].offset + plan->layout.level_entries[l] > lo) ++c;
-    if (c > maxlv) maxlv = c;
-    if (lo > (int64_t)md.lv[md.L - 1].offset) break;  // later buckets lie inside the last level
-  }
-  sp.max_chunks = (int)((B * 8 * maxlv + kChunkRecords - 1) / kChunkRecords);
+  // upper bound of the work items: one partial chunk per bucket plus full chunks
+  sp.max_items = sp.n_buckets + (int)((sp.n_records + kChunkRecords - 1) / kChunkRecords);
   auto up = [](size_t v) { return (v + 255) / 256 * 256; };
   sp.rec_off = 0;
   sp.counts_off = up((size_t)sp.n_records * 16 * sp.rec_words);
   sp.totals_off = sp.counts_off + up((size_t)sp.blocks * sp.n_buckets * 4);
   sp.offsets_off = sp.totals_off + up((size_t)sp.n_buckets * 4);
-  sp.bytes = sp.offsets_off + up((size_t)sp.n_buckets * 4);
+  sp.items_off = sp.offsets_off + up((size_t)sp.n_buckets * 4);
+  sp.bytes = sp.items_off + up((size_t)(sp.max_items + 1) * 8);
   return sp;
 }
 
@@ -214,14 +239,16 @@ hipError_t launch_scatter(const ngvol_plan* plan, const ScatterPlan& sp, const B
   hipLaunchKernelGGL(k_sc_count, dim3(sp.blocks), dim3(kScThreads), hist_lds, st, md, src, ba.B, sp.chunk, sp.bshift,
                      sp.n_buckets, counts);
   launch_count_offsets(counts, sp.blocks, sp.n_buckets, totals, offsets, st);
+  uint32_t* items = reinterpret_cast<uint32_t*>(base + sp.items_off);
+  hipLaunchKernelGGL(k_sc_worklist, dim3(1), dim3(1024), 0, st, totals, sp.n_buckets, sp.chunk_records, items);
   const size_t acc_lds = ((size_t)1 << sp.bshift) * md.F * 4;
-  const dim3 rgrid(sp.n_buckets, sp.max_chunks);
+  const dim3 rgrid(sp.max_items);
   const int64_t n_entries = md.n_table / md.F;
 #define NGV_SC(FV)                                                                                                 \
   hipLaunchKernelGGL(k_sc_fill<FV>, dim3(sp.blocks), dim3(kScThreads), hist_lds, st, md, src, ba.B, sp.chunk,      \
                      sp.bshift, sp.n_buckets, counts, offsets, dfeat, rec);                                        \
-  hipLaunchKernelGGL(k_sc_reduce<FV>, rgrid, dim3(kReduceThreads), acc_lds, st, rec, totals, offsets, sp.bshift,   \
-                     sp.chunk_records, n_entries, grad)
+  hipLaunchKernelGGL(k_sc_reduce<FV>, rgrid, dim3(kReduceThreads), acc_lds, st, rec, totals, offsets, items,      \
+                     sp.bshift, sp.chunk_records, n_entries, grad)
   switch (md.F) {
     case 2: NGV_SC(2); break;
     case 4: NGV_SC(4); break;

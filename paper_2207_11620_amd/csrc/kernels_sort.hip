@@ -10,8 +10,8 @@
 // The reorder is a counting sort by the Morton code of the sample's cell in
 // a 2^k x 2^k x 2^k grid (k = 4 or 5): per-block LDS histograms, a per-bin
 // prefix over blocks, one scan of the bin totals, and a scatter with LDS
-// cursors; then each cell's records are sorted by their full Morton code in
-// LDS, so the final order is the Morton order of the points.
+// cursors; then each cell's records are regrouped by 512 sub-cells in LDS,
+// so the order follows the Morton curve down to 1/256 of the domain.
 #include "kernels.hpp"
 #include "device_common.hpp"
 
@@ -143,59 +143,49 @@ __global__ void __launch_bounds__(kSortThreads) k_bin_scatter(Src src, int64_t n
   }
 }
 
-// Within-cell refinement: the records of one cell are sorted by the full
-// 30-bit Morton code of their position (10 bits per axis) with an LDS
-// bitonic sort, so that consecutive tiles are neighbours at every level.
-// Cells with more records than fit are left grouped but unsorted.
+// Within-cell refinement: the records of one cell are regrouped by the next
+// 3 bits per axis of their position (512 sub-cells, Morton order) with an
+// LDS counting sort, so the final order follows the Morton curve down to
+// cells of 2^-(k+3) per axis; the order inside a sub-cell is arbitrary.
+// Cells with more records than fit are left as they are (still grouped).
 constexpr int kRefineMax = 2048;
 
-__device__ __forceinline__ uint32_t morton30(float x, float y, float z) {
-  const uint32_t qx = min((uint32_t)(clamp01(x) * 1024.0f), 1023u);
-  const uint32_t qy = min((uint32_t)(clamp01(y) * 1024.0f), 1023u);
-  const uint32_t qz = min((uint32_t)(clamp01(z) * 1024.0f), 1023u);
-  return spread3(qx) | (spread3(qy) << 1) | (spread3(qz) << 2);
-}
-
-__global__ void __launch_bounds__(256) k_bin_refine(float4* __restrict__ rec, const uint32_t* __restrict__ totals,
-                                                    const uint32_t* __restrict__ offsets) {
-  __shared__ uint32_t key[kRefineMax];
-  __shared__ uint16_t idx[kRefineMax];
+__global__ void __launch_bounds__(512) k_bin_refine(float4* __restrict__ rec, const uint32_t* __restrict__ totals,
+                                                    const uint32_t* __restrict__ offsets, int k) {
   __shared__ float4 buf[kRefineMax];
+  __shared__ uint16_t key[kRefineMax];
+  __shared__ uint16_t rank[kRefineMax];
+  __shared__ uint32_t hist[512];
   const uint32_t cnt = totals[blockIdx.x];
   if (cnt < 2 || cnt > (uint32_t)kRefineMax) return;
   const uint32_t base = offsets[blockIdx.x];
-  uint32_t n2 = 2;
-  while (n2 < cnt) n2 <<= 1;
-  for (uint32_t i = threadIdx.x; i < n2; i += blockDim.x) {
-    if (i < cnt) {
-      const float4 r = rec[base + i];
-      buf[i] = r;
-      key[i] = morton30(r.x, r.y, r.z);
-    } else {
-      key[i] = 0xFFFFFFFFu;
-    }
-    idx[i] = (uint16_t)i;
+  const float scale = (float)(8 << k);  // cells hold 2^-k per axis; 3 more bits each
+  const uint32_t top = (8u << k) - 1u;
+  hist[threadIdx.x] = 0u;  // blockDim.x == 512
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+    const float4 r = rec[base + i];
+    buf[i] = r;
+    const uint32_t qx = min((uint32_t)(clamp01(r.x) * scale), top) & 7u;
+    const uint32_t qy = min((uint32_t)(clamp01(r.y) * scale), top) & 7u;
+    const uint32_t qz = min((uint32_t)(clamp01(r.z) * scale), top) & 7u;
+    const uint32_t k9 = spread3(qx) | (spread3(qy) << 1) | (spread3(qz) << 2);
+    key[i] = (uint16_t)k9;
+    rank[i] = (uint16_t)atomicAdd(hist + k9, 1u);
   }
   __syncthreads();
-  for (uint32_t size = 2; size <= n2; size <<= 1) {
-    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-      for (uint32_t t = threadIdx.x; t < n2 / 2; t += blockDim.x) {
-        const uint32_t i = 2 * stride * (t / stride) + (t % stride);
-        const uint32_t j = i + stride;
-        const bool up = (i & size) == 0;
-        const uint32_t ki = key[i], kj = key[j];
-        if ((ki > kj) == up) {
-          key[i] = kj;
-          key[j] = ki;
-          const uint16_t a = idx[i];
-          idx[i] = idx[j];
-          idx[j] = a;
-        }
-      }
-      __syncthreads();
-    }
+  // exclusive scan of the 512 sub-cell counts
+  const uint32_t v = hist[threadIdx.x];
+  __syncthreads();
+  for (uint32_t d = 1; d < 512; d <<= 1) {
+    const uint32_t add = threadIdx.x >= d ? hist[threadIdx.x - d] : 0u;
+    __syncthreads();
+    hist[threadIdx.x] += add;
+    __syncthreads();
   }
-  for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) rec[base + i] = buf[idx[i]];
+  hist[threadIdx.x] -= v;
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) rec[base + hist[key[i]] + rank[i]] = buf[i];
 }
 
 }  // namespace
@@ -247,7 +237,7 @@ hipError_t launch_bin(const ngvol_plan* plan, const BinPlan& bp, const float* xy
   if (!ba) {
     hipLaunchKernelGGL(k_bin_scatter<float>, dim3(bp.blocks), dim3(kSortThreads), lds, st, src, n, bp.k, bp.chunk,
                        counts, offsets, rec, false, nullptr, nullptr, 1, 1, 1);
-    hipLaunchKernelGGL(k_bin_refine, dim3(bp.n_bins), dim3(256), 0, st, rec, totals, offsets);
+    hipLaunchKernelGGL(k_bin_refine, dim3(bp.n_bins), dim3(512), 0, st, rec, totals, offsets, bp.k);
   } else if (ba->xyz || ba->vdtype != NGVOL_DT_F16) {
     hipLaunchKernelGGL(k_bin_scatter<float>, dim3(bp.blocks), dim3(kSortThreads), lds, st, src, n, bp.k, bp.chunk,
                        counts, offsets, rec, true, ba->target, reinterpret_cast<const float*>(ba->volume), ba->dims[0],

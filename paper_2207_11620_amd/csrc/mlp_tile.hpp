@@ -270,6 +270,52 @@ __device__ __forceinline__ void mlp_hidden_fwd(int n_hidden, const typename Prec
   }
 }
 
+// The same forward over NB tiles at once: each weight fragment is read from
+// LDS once for all NB tiles, and the NB accumulator chains are independent.
+template <int P, int KIN, int W, int NB>
+__device__ __forceinline__ void mlp_hidden_fwd_nb(int n_hidden, const typename Prec<P>::Frag* __restrict__ lds_frag,
+                                                  const typename Prec<P>::Frag in[NB][InChunks<P, KIN>::n],
+                                                  f32x4 act[NB][W / 16]) {
+  typedef WeightLayout<P, KIN, W> WL;
+  typedef typename Prec<P>::Frag Frag;
+  constexpr int MB = W / 16;
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) {
+    f32x4 acc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[nb] = zero4();
+#pragma unroll
+    for (int c = 0; c < WL::CH0; ++c) {
+      const Frag a = lds_frag[(mb * WL::CH0 + c) * 64 + lane];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma(a, in[nb][c], acc[nb]);
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) act[nb][mb] = acc[nb];
+  }
+  for (int li = 1; li < n_hidden; ++li) {
+    Frag b[NB][WL::CHH];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) pack_hidden<P, W>(act[nb], b[nb], true);
+    const Frag* base = lds_frag + (WL::FR0 + (li - 1) * WL::FRH) * 64;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      f32x4 acc[NB];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[nb] = zero4();
+#pragma unroll
+      for (int c = 0; c < WL::CHH; ++c) {
+        const Frag a = base[(mb * WL::CHH + c) * 64 + lane];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma(a, b[nb][c], acc[nb]);
+      }
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) act[nb][mb] = acc[nb];
+    }
+  }
+}
+
 // Output neuron: y = w_out . relu(z_last); every lane of the sample gets y.
 template <int W>
 __device__ __forceinline__ float mlp_output(const f32x4 zlast[W / 16], const float* __restrict__ lds_wout) {

@@ -173,6 +173,39 @@ def test_binned_infer_equals_direct():
         np.testing.assert_array_equal(a, c)
 
 
+def _morton(q, bits):
+    key = np.zeros(q.shape[0], dtype=np.int64)
+    for b in range(bits):
+        for a in range(3):
+            key |= ((q[:, a] >> b) & 1) << (3 * b + a)
+    return key
+
+
+def test_sorted_records_follow_morton_order():
+    # the grouped records are the input points, each with its index, in
+    # Morton order down to cells of 2^-(k+3) per axis (k = 4 below 2^22
+    # points, 5 from there); cells of more than 2048 points keep only the
+    # cell order
+    p = gpu_plan("cfg1", "bf16")
+    for n, k in ((40007, 4), (1 << 22, 5)):
+        xyz = synth.query_coords(n, SEED + 3 * n)
+        ws = ngv.sort_queries(p, dev(xyz))
+        rec = host(ws[: n * 16].view(torch.float32)).reshape(n, 4)
+        idx = rec[:, 3].view(np.uint32).astype(np.int64)
+        assert np.array_equal(np.sort(idx), np.arange(n))
+        np.testing.assert_array_equal(rec[:, :3], xyz[idx])
+        top = (8 << k) - 1
+        q = np.minimum(np.floor(np.clip(rec[:, :3], 0, 1).astype(np.float64) * (8 << k)), top).astype(np.int64)
+        cell = _morton(q >> 3, k)
+        full = _morton(q, k + 3)
+        assert np.all(np.diff(cell) >= 0)
+        counts = np.bincount(cell, minlength=1 << (3 * k))
+        refined = counts[cell] <= 2048
+        ok = np.diff(full) >= 0
+        same_cell = np.diff(cell) == 0
+        assert np.all(ok[same_cell & refined[1:]])
+
+
 def test_binned_training_gradient():
     # a batch large enough to be grouped by cell before the step
     m = oracle_model("cfg1")
