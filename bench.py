@@ -47,6 +47,33 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# HBM bytes per query pass, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+# (scaled by a plain copy's readings); valid only for the kernel sources the
+# counters were taken with.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "query_pass_cfg1_2p24_counters.md")
+CSRC = os.path.join(ROOT, "paper_2207_11620_amd", "csrc")
+
+
+def csrc_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            kv = dict(ln.strip("- `\n").split(": ", 1) for ln in fh if ln.startswith("- `") and ": " in ln)
+    except OSError:
+        return None, "no counter summary"
+    if kv.get("csrc_sha256_16") != csrc_hash():
+        return None, "kernel sources changed since the counters were taken"
+    return int(kv["hbm_bytes_per_launch"]), os.path.relpath(TRAFFIC_FILE, ROOT)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -61,6 +88,8 @@ def main():
     ap.add_argument("--no-render", action="store_true")
     ap.add_argument("--no-multi", action="store_true")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain 1 GiB device copy, the reference for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only; --gpus N > 1 is not supported", file=sys.stderr)
@@ -349,12 +378,24 @@ def main():
     del feat, ymlp
 
     # --------------------------------------------------------------- roofline
-    # query kernel: algorithmic bytes per query = L*8*F FP16 table reads + 12 B xyz + 4 B out
+    # The query pass (k_level_feat, then k_mlp_planes on the feature planes):
+    # algorithmic bytes per query = L*8*F FP16 table reads + 12 B xyz + 4 B out.
     bytes_q = MODEL["n_levels"] * 8 * MODEL["n_features"] * 2 + 12 + 4
     achieved = bytes_q * N_QUERY / (infer_ms * 1e-3) / 1e9
-    roofline = {"kernel": "k_infer (bf16 MLP, fp16 tables)", "bound": "hbm", "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+    traffic, traffic_src = measured_traffic()
+    roofline = {"kernel": "query pass: k_level_feat + k_mlp_planes (bf16 MLP, fp16 tables)", "bound": "hbm",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_source": traffic_src,
                 "bytes_per_query": bytes_q, "queries_per_launch": N_QUERY, "avg_launch_ms": round(infer_ms, 4)}
+
+    if args.copy_calibration:
+        # one plain copy of 2^28 floats (1 GiB read, 1 GiB written); its
+        # FETCH_SIZE / WRITE_SIZE readings convert the counters to bytes
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # ------------------------------------------------------------ CPU oracle
     cpu = None

@@ -209,14 +209,19 @@ int ngvol_encode_debug(const ngvol_plan* plan, const float* d_xyz, int64_t n, ui
 int ngvol_mlp_fwd(const ngvol_plan* plan, const float* d_params, const void* d_feat, int32_t feat_dtype, int64_t n,
                   float* d_out, hipStream_t stream);
 
-/* Fused query: out[n] = Phi(xyz) (encoding + MLP in one kernel).  With a
- * workspace of ngvol_infer_workspace_bytes(plan, n) bytes the queries are
- * first grouped by spatial cell (a counting sort on the device) so that
- * neighbouring queries share table cache lines; every output still lands in
- * its own slot and the values are the same.  With d_workspace == NULL the
- * queries are evaluated in the given order (best for coherent inputs such as
- * already sorted or ray-ordered coordinates).  The bytes query returns 0 when
- * n is too small for reordering to pay off.  n < 2^31. */
+/* Query (Sections 3.1 and 3.2): out[n] = Phi(xyz), encoding + MLP.  Without
+ * a workspace (d_workspace == NULL) one fused kernel evaluates the queries
+ * in the given order (best for coherent inputs such as already sorted or
+ * ray-ordered coordinates).  With a workspace of
+ * ngvol_infer_workspace_bytes(plan, n) bytes the queries are first grouped
+ * by spatial cell (a counting sort on the device) so that neighbouring
+ * queries share table cache lines; for large sets whose tables exceed one
+ * XCD's L2 the grouped queries are then evaluated level group by level
+ * group, each XCD interpolating its own levels for all queries into feature
+ * planes in the workspace, followed by the MLP on those planes.  Every
+ * output lands in its own slot and the values are bitwise the same on all
+ * paths.  The bytes query returns 0 when n is too small for reordering to
+ * pay off.  n < 2^31. */
 int ngvol_infer_workspace_bytes(const ngvol_plan* plan, int64_t n, size_t* bytes);
 int ngvol_infer(const ngvol_plan* plan, const ngvol_weights* w, const float* d_xyz, int64_t n, float* d_out,
                 void* d_workspace, size_t workspace_bytes, hipStream_t stream);
@@ -225,10 +230,12 @@ int ngvol_infer(const ngvol_plan* plan, const ngvol_weights* w, const float* d_x
  * queried more than once: ngvol_sort_queries groups xyz[n] by spatial cell
  * into the workspace (ngvol_infer_workspace_bytes; EINVAL if that is 0), and
  * ngvol_infer_sorted evaluates the grouped queries of that workspace, writing
- * each output to its original slot of out[n]. */
+ * each output to its original slot of out[n].  The plan and n must be those
+ * of the sort; ngvol_infer_sorted also uses the rest of the workspace as
+ * scratch (the grouped records are kept, so it may be called again). */
 int ngvol_sort_queries(const ngvol_plan* plan, const float* d_xyz, int64_t n, void* d_workspace,
                        size_t workspace_bytes, hipStream_t stream);
-int ngvol_infer_sorted(const ngvol_plan* plan, const ngvol_weights* w, const void* d_workspace, int64_t n,
+int ngvol_infer_sorted(const ngvol_plan* plan, const ngvol_weights* w, void* d_workspace, int64_t n,
                        float* d_out, hipStream_t stream);
 
 /* MLP backward: given d_out[n] = dL/dout, adds dL/dW into the MLP part of

@@ -38,7 +38,7 @@ int hip_check(hipError_t e, const char* what) {
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 bool aligned4(const void* p) { return ((uintptr_t)p & 3u) == 0; }
 
-constexpr size_t kLdsBytes = 160 * 1024;  // LDS per workgroup on gfx950
+constexpr size_t kLdsBytes = kLdsLimit;  // LDS per workgroup on gfx950
 
 #define NGV_REQUIRE(cond, ...) \
   do {                         \
@@ -82,7 +82,7 @@ TablePtrs tables_of(const ngvol_plan* p, const ngvol_weights* w) {
 
 // The backward keeps W, W^T, dW and per-wave activations in LDS.
 int check_bwd_lds(const ngvol_plan* p) {
-  const size_t b = bwd_lds_bytes(p, 4);
+  const size_t b = bwd_lds_bytes(p, 1);
   if (b > kLdsBytes)
     return fail(NGVOL_EUNSUPPORTED, "network too large for the LDS-resident backward (%zu > %zu bytes)", b, kLdsBytes);
   return NGVOL_OK;
@@ -200,8 +200,8 @@ int ngvol_plan_create(const ngvol_config* c, ngvol_plan** out) {
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
   p->cus = cus;
   p->device = dev;
-  if (fwd_lds_bytes(p) + 8192 > kLdsBytes) {
-    const size_t b = fwd_lds_bytes(p);
+  if (enc_lds_bytes(p, 1) > kLdsBytes || fwd_lds_bytes(p) + 8192 > kLdsBytes) {
+    const size_t b = enc_lds_bytes(p, 1);
     delete p;
     return fail(NGVOL_EUNSUPPORTED, "network too large for LDS-resident weights (%zu bytes)", b);
   }
@@ -252,6 +252,19 @@ int ngvol_mlp_fwd(const ngvol_plan* plan, const float* params, const void* feat,
   return hip_check(launch_mlp_fwd(plan, params + plan->md.n_table, feat, dtype, n, out, st), "mlp_fwd launch");
 }
 
+// Query on grouped records: level-split passes for large sets, else the
+// fused kernel.
+static hipError_t launch_grouped(const ngvol_plan* plan, const BinPlan& bp, const ngvol_weights* w, void* ws,
+                                 int64_t n, float* out, hipStream_t st) {
+  char* base = reinterpret_cast<char*>(ws);
+  const float4* rec = reinterpret_cast<const float4*>(base + bp.rec_off);
+  const float* mlp = w->params + plan->md.n_table;
+  if (bp.split && w->table_f16)  // FP32 tables (4 MB per level) would not fit an L2 per level pair
+    return launch_infer_split(plan, tables_of(plan, w), mlp, rec, n, out, base + bp.planes_off,
+                              reinterpret_cast<uint32_t*>(base + bp.idx_off), st);
+  return launch_infer(plan, tables_of(plan, w), mlp, nullptr, rec, n, out, st);
+}
+
 int ngvol_infer_workspace_bytes(const ngvol_plan* plan, int64_t n, size_t* bytes) {
   if (int rc = check_plan(plan)) return rc;
   NGV_REQUIRE(bytes && n >= 0 && n < ((int64_t)1 << 31), "bytes must be non-NULL and 0 <= n < 2^31");
@@ -274,10 +287,7 @@ int ngvol_infer(const ngvol_plan* plan, const ngvol_weights* w, const float* xyz
     if (ws_bytes < bp.bytes) return fail(NGVOL_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, bp.bytes);
     hipError_t e = launch_bin(plan, bp, xyz, nullptr, n, ws, st);
     if (e != hipSuccess) return hip_check(e, "infer binning launch");
-    char* base = reinterpret_cast<char*>(ws);
-    return hip_check(launch_infer(plan, tables_of(plan, w), mlp, nullptr,
-                                  reinterpret_cast<const float4*>(base + bp.rec_off), n, out, st),
-                     "infer launch");
+    return hip_check(launch_grouped(plan, bp, w, ws, n, out, st), "infer launch");
   }
   return hip_check(launch_infer(plan, tables_of(plan, w), mlp, xyz, nullptr, n, out, st), "infer launch");
 }
@@ -293,7 +303,7 @@ int ngvol_sort_queries(const ngvol_plan* plan, const float* xyz, int64_t n, void
   return hip_check(launch_bin(plan, bp, xyz, nullptr, n, ws, st), "sort_queries launch");
 }
 
-int ngvol_infer_sorted(const ngvol_plan* plan, const ngvol_weights* w, const void* ws, int64_t n, float* out,
+int ngvol_infer_sorted(const ngvol_plan* plan, const ngvol_weights* w, void* ws, int64_t n, float* out,
                        hipStream_t st) {
   if (int rc = check_plan(plan)) return rc;
   if (int rc = check_weights(w)) return rc;
@@ -301,10 +311,7 @@ int ngvol_infer_sorted(const ngvol_plan* plan, const ngvol_weights* w, const voi
   NGV_REQUIRE(ws && out && aligned16(ws) && aligned4(out), "workspace and out must be non-NULL and aligned");
   const BinPlan bp = bin_plan(plan, n);
   NGV_REQUIRE(bp.k, "%lld queries are too few to group (ngvol_infer_workspace_bytes is 0)", (long long)n);
-  const char* base = reinterpret_cast<const char*>(ws);
-  return hip_check(launch_infer(plan, tables_of(plan, w), w->params + plan->md.n_table, nullptr,
-                                reinterpret_cast<const float4*>(base + bp.rec_off), n, out, st),
-                   "infer_sorted launch");
+  return hip_check(launch_grouped(plan, bp, w, ws, n, out, st), "infer_sorted launch");
 }
 
 int ngvol_mlp_bwd_workspace_bytes(const ngvol_plan* plan, int64_t n, size_t* bytes) {

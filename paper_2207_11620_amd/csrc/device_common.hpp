@@ -5,6 +5,8 @@
 // level floor below are reproducible operation by operation.
 #pragma once
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 #include <stdint.h>
@@ -83,67 +85,128 @@ __device__ __forceinline__ void level_corners(const LevelDesc& lv, float x, floa
   }
 }
 
-// Gather and interpolate the F features of one level.
-template <int F>
-__device__ __forceinline__ void gather_level(const Corners& cr, const float* __restrict__ table, float acc[F]) {
+// Raw table entries: F features of type TT, ED dwords.
+template <int F, typename TT>
+struct Entry {
+  static constexpr int ED = F * (int)sizeof(TT) / 4;
+};
+
+template <int F, typename TT>
+__device__ __forceinline__ void entry_values(const uint32_t* d, float v[F]) {
+  if constexpr (std::is_same<TT, __half>::value) {
 #pragma unroll
-  for (int f = 0; f < F; ++f) acc[f] = 0.0f;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const float* e = table + (size_t)cr.slot[k] * F;
-    float v[F];
-    if constexpr (F == 1) {
-      v[0] = e[0];
-    } else if constexpr (F == 2) {
-      float2 t = *reinterpret_cast<const float2*>(e);
-      v[0] = t.x;
-      v[1] = t.y;
-    } else {
-#pragma unroll
-      for (int q = 0; q < F; q += 4) {
-        float4 t = *reinterpret_cast<const float4*>(e + q);
-        v[q] = t.x;
-        v[q + 1] = t.y;
-        v[q + 2] = t.z;
-        v[q + 3] = t.w;
-      }
+    for (int q = 0; q < F / 2; ++q) {
+      const float2 u = __half22float2(__builtin_bit_cast(__half2, d[q]));
+      v[2 * q] = u.x;
+      v[2 * q + 1] = u.y;
     }
+  } else {
 #pragma unroll
-    for (int f = 0; f < F; ++f) acc[f] = __builtin_fmaf(cr.w[k], v[f], acc[f]);
+    for (int f = 0; f < F; ++f) v[f] = __uint_as_float(d[f]);
   }
 }
 
-template <int F>
-__device__ __forceinline__ void gather_level(const Corners& cr, const __half* __restrict__ table, float acc[F]) {
+template <int ED>
+__device__ __forceinline__ void load_entry(const uint32_t* __restrict__ base, uint32_t slot, uint32_t d[ED]) {
+  const uint32_t* e = base + (size_t)slot * ED;
+  if constexpr (ED == 1) {
+    d[0] = e[0];
+  } else if constexpr (ED == 2) {
+    const uint2 t = *reinterpret_cast<const uint2*>(e);
+    d[0] = t.x;
+    d[1] = t.y;
+  } else {
+#pragma unroll
+    for (int q = 0; q < ED; q += 4) {
+      const uint4 t = *reinterpret_cast<const uint4*>(e + q);
+      d[q] = t.x;
+      d[q + 1] = t.y;
+      d[q + 2] = t.z;
+      d[q + 3] = t.w;
+    }
+  }
+}
+
+// Gather and interpolate the F features of one level:
+// acc[f] = sum over corners k = 0..7, in that order, of w_k * entry_k[f].
+// Corners 2p and 2p+1 differ only in x.  Their slots usually share an
+// aligned 16-byte block: for dense levels they are adjacent, and since the
+// x prime of the hash is 1, x and x+1 hash to slots that differ only in the
+// low bits flipped by the increment.  When entries are at most 8 bytes each
+// pair is read as that one block (one cache-line lookup instead of two) and
+// only partners outside their block are loaded on their own, by the lanes
+// that need them.  All loads are issued before any is used.  n_ent (entries
+// of the whole table) keeps block reads inside the table: a wave with a
+// block past the end takes the plain path.
+template <int F, typename TT>
+__device__ __forceinline__ void gather_level(const Corners& cr, const TT* __restrict__ table, uint32_t n_ent,
+                                             float acc[F]) {
+  constexpr int ED = Entry<F, TT>::ED;
+  const uint32_t* base = reinterpret_cast<const uint32_t*>(table);
+  float v[8][F];
+  bool plain = true;
+  if constexpr (ED <= 2) {
+    constexpr uint32_t E = 4 / ED;  // entries per 16-byte block
+    uint32_t b0[4];
+    bool same[4];
+    bool inside = true;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      b0[p] = cr.slot[2 * p] & ~(E - 1);
+      same[p] = (cr.slot[2 * p + 1] & ~(E - 1)) == b0[p];
+      inside = inside && b0[p] + E <= n_ent;
+    }
+    if (__all(inside)) {
+      plain = false;
+      uint4 blk[4];
+      uint32_t d1[4][ED];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) blk[p] = *reinterpret_cast<const uint4*>(base + (size_t)b0[p] * ED);
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        if (!same[p]) {
+          load_entry<ED>(base, cr.slot[2 * p + 1], d1[p]);
+        } else {
+#pragma unroll
+          for (int q = 0; q < ED; ++q) d1[p][q] = 0u;
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const uint32_t w4[4] = {blk[p].x, blk[p].y, blk[p].z, blk[p].w};
+        const uint32_t j0 = (cr.slot[2 * p] - b0[p]) * ED, j1 = (cr.slot[2 * p + 1] - b0[p]) * ED;
+        uint32_t d0[ED], dd[ED];
+#pragma unroll
+        for (int q = 0; q < ED; ++q) {
+          // select word j of the block without indexing (no scratch, no branches)
+          uint32_t x0 = w4[0], x1 = w4[0];
+#pragma unroll
+          for (int i = 1; i < 4; ++i) {
+            x0 = (j0 + q == (uint32_t)i) ? w4[i] : x0;
+            x1 = (j1 + q == (uint32_t)i) ? w4[i] : x1;
+          }
+          d0[q] = x0;
+          dd[q] = same[p] ? x1 : d1[p][q];
+        }
+        entry_values<F, TT>(d0, v[2 * p]);
+        entry_values<F, TT>(dd, v[2 * p + 1]);
+      }
+    }
+  }
+  if (plain) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      uint32_t d[ED];
+      load_entry<ED>(base, cr.slot[k], d);
+      entry_values<F, TT>(d, v[k]);
+    }
+  }
 #pragma unroll
   for (int f = 0; f < F; ++f) acc[f] = 0.0f;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const __half* e = table + (size_t)cr.slot[k] * F;
-    float v[F];
-    if constexpr (F == 1) {
-      v[0] = __half2float(e[0]);
-    } else if constexpr (F == 2) {
-      __half2 t = *reinterpret_cast<const __half2*>(e);
-      float2 u = __half22float2(t);
-      v[0] = u.x;
-      v[1] = u.y;
-    } else {
+  for (int k = 0; k < 8; ++k)
 #pragma unroll
-      for (int q = 0; q < F; q += 4) {
-        uint2 raw = *reinterpret_cast<const uint2*>(e + q);
-        __half2 a = *reinterpret_cast<__half2*>(&raw.x);
-        __half2 b = *reinterpret_cast<__half2*>(&raw.y);
-        float2 ua = __half22float2(a), ub = __half22float2(b);
-        v[q] = ua.x;
-        v[q + 1] = ua.y;
-        v[q + 2] = ub.x;
-        v[q + 3] = ub.y;
-      }
-    }
-#pragma unroll
-    for (int f = 0; f < F; ++f) acc[f] = __builtin_fmaf(cr.w[k], v[f], acc[f]);
-  }
+    for (int f = 0; f < F; ++f) acc[f] = __builtin_fmaf(cr.w[k], v[k][f], acc[f]);
 }
 
 // Scatter dL/dfeature of one level into the FP32 gradient of its table.
@@ -196,6 +259,14 @@ __device__ __forceinline__ float volume_sample(const T* __restrict__ vol, int dx
   float c0 = __builtin_fmaf(t[1], c10 - c00, c00);
   float c1 = __builtin_fmaf(t[1], c11 - c01, c01);
   return __builtin_fmaf(t[2], c1 - c0, c0);
+}
+
+// Orders a wave's LDS writes before its following LDS reads by other lanes
+// of the same wave (no workgroup barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Wave-wide sums (64 lanes).

@@ -43,6 +43,9 @@ struct BinPlan {
   int k, n_bins, blocks;
   int64_t chunk;
   size_t rec_off, counts_off, totals_off, offsets_off, bytes;
+  // level-split query (large query sets): feature planes and query slots
+  bool split;
+  size_t planes_off, idx_off;
 };
 BinPlan bin_plan(const ngvol_plan* plan, int64_t n);
 // Sorts `xyz` (queries; aux = original index) or the batch `ba` (training;
@@ -98,8 +101,30 @@ struct TileIter {
   }
 };
 
+// Level-split query: which levels (and which part of the queries) each of
+// the 8 XCDs evaluates.
+struct SplitArgs {
+  int n_lv[8];
+  int lv[8][4];
+  int part[8], parts[8];
+};
+bool use_split(const ngvol_plan* plan, int64_t n);
+int split_operand_bytes(const ngvol_plan* plan);
+int64_t split_slab(const ngvol_plan* plan, int64_t n);
+// rec: sorted records (x, y, z, original index); planes/idx: workspace of
+// split_slab * L * F * split_operand_bytes and split_slab * 4 bytes.
+hipError_t launch_infer_split(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const float4* rec, int64_t n,
+                              float* out, void* planes, uint32_t* idx, hipStream_t st);
+
 size_t fwd_lds_bytes(const ngvol_plan* plan);
+// LDS of a workgroup (160 KB on gfx950)
+constexpr size_t kLdsLimit = 160 * 1024;
+// fwd_lds_bytes plus the per-wave encoding stages of the fused kernels, and
+// the waves per workgroup those kernels use
+size_t enc_lds_bytes(const ngvol_plan* plan, int waves);
+int enc_waves(const ngvol_plan* plan);
 size_t bwd_lds_bytes(const ngvol_plan* plan, int waves);
+int bwd_waves(const ngvol_plan* plan);
 int bwd_grid(const ngvol_plan* plan, int64_t n);
 TrainWorkspace train_workspace(const ngvol_plan* plan, int64_t B);
 

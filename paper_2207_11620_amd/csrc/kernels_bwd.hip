@@ -7,14 +7,8 @@ namespace ngvol {
 
 namespace {
 
-constexpr int kBwdWaves = 4;
+constexpr int kBwdMaxWaves = 8;
 constexpr int kPitch = 20;  // LDS row pitch (elements) of the per-wave transposed buffers
-
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 __device__ __forceinline__ bool finite(float v) { return __builtin_isfinite(v); }
 
@@ -44,7 +38,7 @@ size_t bwd_lds_bytes(const ngvol_plan* plan, int waves) {
 // dfeat is a separate pass (bucketed, see kernels_scatter.hip).
 // ---------------------------------------------------------------------------
 template <int P, int KIN, int W, int MODE>
-__global__ void __launch_bounds__(256) k_bwd(ModelDesc md, const float* __restrict__ mlp,
+__global__ void __launch_bounds__(64 * kBwdMaxWaves) k_bwd(ModelDesc md, const float* __restrict__ mlp,
                                              const void* __restrict__ e_buf, const float* __restrict__ g_buf,
                                              BatchArgs ba, float* __restrict__ grad, float* __restrict__ dfeat,
                                              float* __restrict__ partial, int32_t* __restrict__ nonfinite,
@@ -403,9 +397,18 @@ __global__ void __launch_bounds__(256) k_make_f16(const float* __restrict__ p, _
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
+int bwd_waves(const ngvol_plan* plan) {
+  // as many waves per workgroup (up to 8) as the LDS holds: one workgroup
+  // per CU accumulates dW, so its waves are the CU's latency hiding
+  for (int w = kBwdMaxWaves; w > 1; w >>= 1)
+    if (bwd_lds_bytes(plan, w) <= kLdsLimit) return w;
+  return 1;
+}
+
 int bwd_grid(const ngvol_plan* plan, int64_t n) {
   const int64_t n_tiles = (n + 15) / 16;
-  int64_t need = (n_tiles + kBwdWaves - 1) / kBwdWaves;
+  const int waves = bwd_waves(plan);
+  int64_t need = (n_tiles + waves - 1) / waves;
   const int64_t cap = (int64_t)plan->cus;
   if (need > cap) need = cap;
   if (need < 1) need = 1;
@@ -416,15 +419,16 @@ hipError_t launch_bwd(const ngvol_plan* plan, int mode, const float* mlp, const 
                       const BatchArgs& ba, float* grad, float* dfeat, float* partial, int grid, int32_t* nonfinite,
                       float bscale, hipStream_t st) {
   const ModelDesc& md = plan->md;
-  const size_t lds = bwd_lds_bytes(plan, kBwdWaves);
+  const int waves = bwd_waves(plan);
+  const size_t lds = bwd_lds_bytes(plan, waves);
   const int P_ = plan->layout.precision;
 #define NGV_BWD_LAUNCH(P, KIN, W)                                                                                   \
   do {                                                                                                             \
     if (mode == 0)                                                                                                 \
-      hipLaunchKernelGGL((k_bwd<P, KIN, W, 0>), dim3(grid), dim3(64 * kBwdWaves), lds, st, md, mlp, e_buf, g_buf,     \
+      hipLaunchKernelGGL((k_bwd<P, KIN, W, 0>), dim3(grid), dim3(64 * waves), lds, st, md, mlp, e_buf, g_buf,     \
                          ba, grad, dfeat, partial, nonfinite, bscale);                                             \
     else                                                                                                           \
-      hipLaunchKernelGGL((k_bwd<P, KIN, W, 1>), dim3(grid), dim3(64 * kBwdWaves), lds, st, md, mlp, e_buf, g_buf,     \
+      hipLaunchKernelGGL((k_bwd<P, KIN, W, 1>), dim3(grid), dim3(64 * waves), lds, st, md, mlp, e_buf, g_buf,     \
                          ba, grad, dfeat, partial, nonfinite, bscale);                                             \
   } while (0)
 #define NGV_BWD_W(P, KIN)                                      \

@@ -3,6 +3,7 @@
 #include <type_traits>
 
 #include "kernels.hpp"
+#include "dispatch.hpp"
 #include "mlp_tile.hpp"
 
 namespace ngvol {
@@ -13,23 +14,26 @@ namespace ngvol {
 template <int F, int KIN, typename TT>
 __global__ void __launch_bounds__(256) k_encode(ModelDesc md, TablePtrs tp, const float* __restrict__ xyz, int64_t n,
                                                 float* __restrict__ feat) {
+  // one sample per lane; all lanes on the same level at a time
   const TT* table = table_ptr<TT>(tp);
-  const int lane = threadIdx.x & 63, nl = lane & 15, g = lane >> 4;
-  const int64_t n_tiles = (n + 15) >> 4;
-  TileIter it(n_tiles);
+  const int lane = threadIdx.x & 63;
+  const int64_t n_groups = (n + 63) >> 6;
+  TileIter it(n_groups);
   for (int64_t t = it.next; t < it.end; t += it.step) {
-    const int64_t s = t * 16 + nl;
-    if (s >= n) continue;
-    const float x = clamp01(xyz[3 * s]), y = clamp01(xyz[3 * s + 1]), z = clamp01(xyz[3 * s + 2]);
-    float f[KIN / 32][8];
-    encode_lane<F, KIN>(md, table, x, y, z, f);
+    const int64_t s = t * 64 + lane;
+    const bool valid = s < n;
+    const int64_t sc = valid ? s : n - 1;
+    const float x = clamp01(xyz[3 * sc]), y = clamp01(xyz[3 * sc + 1]), z = clamp01(xyz[3 * sc + 2]);
+    for (int l = 0; l < md.L; ++l) {
+      Corners cr;
+      level_corners(md.lv[l], x, y, z, cr);
+      float acc[F];
+      gather_level<F>(cr, table, (uint32_t)(md.n_table / F), acc);
+      if (valid) {
 #pragma unroll
-    for (int b = 0; b < KIN / 32; ++b)
-#pragma unroll
-      for (int jj = 0; jj < 8; ++jj) {
-        const int k = 32 * b + 8 * g + jj;
-        if (k < md.n_in) feat[s * md.n_in + k] = f[b][jj];
+        for (int f = 0; f < F; ++f) feat[s * md.n_in + l * F + f] = acc[f];
       }
+    }
   }
 }
 
@@ -54,31 +58,34 @@ __global__ void __launch_bounds__(256) k_encode_debug(ModelDesc md, const float*
 // accumulate (Phi - volume)^2 in FP64.
 // ---------------------------------------------------------------------------
 template <int P, int F, int KIN, int W, typename TT, int MODE, typename VT>
-__global__ void __launch_bounds__(256) k_infer(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp,
-                                               const float* __restrict__ xyz, const float4* __restrict__ rec,
-                                               int64_t n, float* __restrict__ out,
-                                               const VT* __restrict__ vol, int dx, int dy, int dz,
-                                               double* __restrict__ sq_sum) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P != 0 && KIN == 32 ? 4 : 1)))
+k_infer(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, const float* __restrict__ xyz,
+        const float4* __restrict__ rec, int64_t n, float* __restrict__ out, const VT* __restrict__ vol, int dx, int dy,
+        int dz, double* __restrict__ sq_sum) {
   typedef typename Prec<P>::Frag Frag;
+  typedef typename Prec<P>::T T;
   typedef WeightLayout<P, KIN, W> WL;
   extern __shared__ __align__(16) unsigned char smem[];
   Frag* lds_frag = reinterpret_cast<Frag*>(smem);
-  float* lds_wout = reinterpret_cast<float*>(smem + (size_t)WL::frags(md.n_hidden, false) * 64 * sizeof(Frag));
+  const size_t wbytes = (size_t)WL::frags(md.n_hidden, false) * 64 * sizeof(Frag);
+  float* lds_wout = reinterpret_cast<float*>(smem + wbytes);
   stage_weights<P, KIN, W>(md, mlp, lds_frag, lds_wout, false);
   __syncthreads();
 
   const TT* table = table_ptr<TT>(tp);
-  const int lane = threadIdx.x & 63, nl = lane & 15, g = lane >> 4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  T* stage = reinterpret_cast<T*>(smem + stage_offset(wbytes, W) + wave * Stage<P, KIN>::wave_bytes);
+  T* row = stage + lane * Stage<P, KIN>::pitch;
   double err = 0.0;
-  const int64_t n_tiles = (n + 15) >> 4;
-  TileIter it(n_tiles);
+  const int64_t n_groups = (n + 63) >> 6;
+  TileIter it(n_groups);
   for (int64_t t = it.next; t < it.end; t += it.step) {
-    const int64_t s = t * 16 + nl;
+    const int64_t s = t * 64 + lane;
     const bool valid = s < n;
+    const int64_t sc = valid ? s : n - 1;
     float x, y, z;
     int64_t slot = s;
     if constexpr (MODE == 0) {
-      const int64_t sc = valid ? s : n - 1;
       if (rec) {
         const float4 r = rec[sc];
         x = clamp01(r.x);
@@ -91,20 +98,16 @@ __global__ void __launch_bounds__(256) k_infer(ModelDesc md, TablePtrs tp, const
         z = clamp01(xyz[3 * sc + 2]);
       }
     } else {
-      const int64_t sc = valid ? s : n - 1;
       const int64_t ix = sc % dx, iy = (sc / dx) % dy, iz = sc / ((int64_t)dx * dy);
       x = ((float)ix + 0.5f) / (float)dx;
       y = ((float)iy + 0.5f) / (float)dy;
       z = ((float)iz + 0.5f) / (float)dz;
     }
-    float f[KIN / 32][8];
-    encode_lane<F, KIN>(md, table, x, y, z, f);
-    Frag in[InChunks<P, KIN>::n];
-    feat_to_frag<P, KIN>(f, in);
-    f32x4 act[W / 16];
-    mlp_hidden_fwd<P, KIN, W, false>(md.n_hidden, lds_frag, in, act, nullptr);
-    const float yv = mlp_output<W>(act, lds_wout);
-    if (valid && g == 0) {
+    encode_row<P, F, KIN>(md, table, x, y, z, row, [](int, const Oct<P>&) {});
+    wave_sync();
+    const float yv = mlp_wave64<P, KIN, W>(md.n_hidden, lds_frag, lds_wout, stage);
+    wave_sync();  // the stage is rewritten by the next group
+    if (valid) {
       if constexpr (MODE == 0) {
         out[slot] = yv;
       } else {
@@ -122,21 +125,15 @@ __global__ void __launch_bounds__(256) k_infer(ModelDesc md, TablePtrs tp, const
 // ---------------------------------------------------------------------------
 // Standalone MLP on given features ([n][n_in], FP32 or BF16).
 // ---------------------------------------------------------------------------
-template <typename IT>
-__device__ __forceinline__ float load_feat(const IT* p, int64_t i);
-template <>
-__device__ __forceinline__ float load_feat<float>(const float* p, int64_t i) { return p[i]; }
-template <>
-__device__ __forceinline__ float load_feat<__bf16>(const __bf16* p, int64_t i) { return (float)p[i]; }
-template <>
-__device__ __forceinline__ float load_feat<_Float16>(const _Float16* p, int64_t i) { return (float)p[i]; }
-
 template <int P, int KIN, int W, typename IT>
-__global__ void __launch_bounds__(256) k_mlp_fwd(ModelDesc md, const float* __restrict__ mlp,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P != 0 && KIN == 32 ? 4 : 1)))
+k_mlp_fwd(ModelDesc md, const float* __restrict__ mlp,
                                                  const IT* __restrict__ feat, int64_t n, float* __restrict__ out) {
-  // NB tiles (16 samples each) per wave and iteration: the weight fragments
-  // are read from LDS once per NB tiles and the MFMA chains interleave.
-  constexpr int NB = 4;
+  // NB tiles (16 samples each) per wave and group: the weight fragments are
+  // read from LDS once per group, and the next group's features are loaded
+  // while this one is evaluated.
+  constexpr int NB = 2;
+  constexpr int CH0 = InChunks<P, KIN>::n;
   typedef typename Prec<P>::Frag Frag;
   typedef WeightLayout<P, KIN, W> WL;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -148,43 +145,69 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(ModelDesc md, const float* __re
   const int n_in = md.n_in;
   const int64_t n_groups = (n + 16 * NB - 1) / (16 * NB);
   TileIter it(n_groups);
-  for (int64_t t = it.next; t < it.end; t += it.step) {
-    Frag in[NB][InChunks<P, KIN>::n];
+  auto row = [&](int64_t grp, int nb) -> int64_t {
+    const int64_t s = (grp * NB + nb) * 16 + nl;
+    return s < n ? s : n - 1;
+  };
+  auto st = [&](int64_t grp, int nb, float y, const auto&) {
+    const int64_t s = (grp * NB + nb) * 16 + nl;
+    if (s < n && g == 0) out[s] = y;
+  };
+  if constexpr (P != 0 && std::is_same<IT, typename Prec<P>::T>::value) {
+    if (n_in == KIN) {
+      // the stored 16-bit features are the operand: one 16-byte load per lane per block
+      struct Raw {
+        Frag f[NB][KIN / 32];
+      };
+      mlp_stream<P, KIN, W, NB, Raw>(
+          md.n_hidden, lds_frag, lds_wout, it.next, it.step, it.end,
+          [&](int64_t grp, Raw& r) {
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      const int64_t s = (t * NB + nb) * 16 + nl;
-      const int64_t sc = s < n ? s : n - 1;
-      float f[KIN / 32][8];
-      bool direct = false;
-      if constexpr (P != 0 && sizeof(IT) == 2) {
-        if (n_in == KIN && std::is_same<IT, typename Prec<P>::T>::value) {
-          // the stored 16-bit features are the operand: one 16-byte load per lane per block
+            for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-          for (int b = 0; b < KIN / 32; ++b)
-            in[nb][b] = *reinterpret_cast<const Frag*>(feat + sc * KIN + 32 * b + 8 * g);
-          direct = true;
-        }
-      }
-      if (!direct) {
+              for (int b = 0; b < KIN / 32; ++b)
+                r.f[nb][b] = *reinterpret_cast<const Frag*>(feat + row(grp, nb) * KIN + 32 * b + 8 * g);
+          },
+          [&](const Raw& r, Frag (*in)[CH0]) {
 #pragma unroll
-        for (int b = 0; b < KIN / 32; ++b)
+            for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-          for (int jj = 0; jj < 8; ++jj) {
-            const int k = 32 * b + 8 * g + jj;
-            f[b][jj] = k < n_in ? load_feat<IT>(feat, sc * n_in + k) : 0.0f;
-          }
-        feat_to_frag<P, KIN>(f, in[nb]);
-      }
-    }
-    f32x4 act[NB][W / 16];
-    mlp_hidden_fwd_nb<P, KIN, W, NB>(md.n_hidden, lds_frag, in, act);
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      const float yv = mlp_output<W>(act[nb], lds_wout);
-      const int64_t s = (t * NB + nb) * 16 + nl;
-      if (s < n && g == 0) out[s] = yv;
+              for (int b = 0; b < KIN / 32; ++b) in[nb][b] = r.f[nb][b];
+          },
+          st);
+      return;
     }
   }
+  struct Raw {
+    IT v[NB][KIN / 32][8];
+  };
+  mlp_stream<P, KIN, W, NB, Raw>(
+      md.n_hidden, lds_frag, lds_wout, it.next, it.step, it.end,
+      [&](int64_t grp, Raw& r) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const int64_t sc = row(grp, nb);
+#pragma unroll
+          for (int b = 0; b < KIN / 32; ++b)
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) {
+              const int k = 32 * b + 8 * g + jj;
+              r.v[nb][b][jj] = k < n_in ? feat[sc * n_in + k] : (IT)0.0f;
+            }
+        }
+      },
+      [&](const Raw& r, Frag (*in)[CH0]) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          float f[KIN / 32][8];
+#pragma unroll
+          for (int b = 0; b < KIN / 32; ++b)
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) f[b][jj] = (float)r.v[nb][b][jj];
+          feat_to_frag<P, KIN>(f, in[nb]);
+        }
+      },
+      st);
 }
 
 // ---------------------------------------------------------------------------
@@ -192,27 +215,32 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(ModelDesc md, const float* __re
 // the backward), MLP, loss, and g = S * dL/dy = S * 2 (y_hat - y) / B.
 // ---------------------------------------------------------------------------
 template <int P, int F, int KIN, int W, typename TT, typename VT>
-__global__ void __launch_bounds__(256) k_train_fwd(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp,
-                                                   BatchArgs ba, void* __restrict__ e_buf, float* __restrict__ g_buf,
-                                                   double* __restrict__ loss_acc, float gscale) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P != 0 && KIN == 32 ? 4 : 1)))
+k_train_fwd(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, BatchArgs ba, void* __restrict__ e_buf,
+            float* __restrict__ g_buf, double* __restrict__ loss_acc, float gscale) {
   typedef typename Prec<P>::Frag Frag;
+  typedef typename Prec<P>::T T;
   typedef WeightLayout<P, KIN, W> WL;
   extern __shared__ __align__(16) unsigned char smem[];
   Frag* lds_frag = reinterpret_cast<Frag*>(smem);
-  float* lds_wout = reinterpret_cast<float*>(smem + (size_t)WL::frags(md.n_hidden, false) * 64 * sizeof(Frag));
+  const size_t wbytes = (size_t)WL::frags(md.n_hidden, false) * 64 * sizeof(Frag);
+  float* lds_wout = reinterpret_cast<float*>(smem + wbytes);
   stage_weights<P, KIN, W>(md, mlp, lds_frag, lds_wout, false);
   __syncthreads();
 
   const TT* table = table_ptr<TT>(tp);
   const VT* vol = reinterpret_cast<const VT*>(ba.volume);
-  const int lane = threadIdx.x & 63, nl = lane & 15, g = lane >> 4;
+  T* e = reinterpret_cast<T*>(e_buf);  // stored encoding [B][KIN] in the operand type
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  T* stage = reinterpret_cast<T*>(smem + stage_offset(wbytes, W) + wave * Stage<P, KIN>::wave_bytes);
+  T* row = stage + lane * Stage<P, KIN>::pitch;
   const int64_t B = ba.B;
   const int64_t bstep = ba.step_index();
   double lsum = 0.0;
-  const int64_t n_tiles = (B + 15) >> 4;
-  TileIter it(n_tiles);
+  const int64_t n_groups = (B + 63) >> 6;
+  TileIter it(n_groups);
   for (int64_t t = it.next; t < it.end; t += it.step) {
-    const int64_t s = t * 16 + nl;
+    const int64_t s = t * 64 + lane;
     const bool valid = s < B;
     const int64_t sc = valid ? s : B - 1;
     float x, y, z, target;
@@ -227,33 +255,13 @@ __global__ void __launch_bounds__(256) k_train_fwd(ModelDesc md, TablePtrs tp, c
       z = batch_coord(ba.seed, bstep, B, sc, 2);
       target = volume_sample<VT>(vol, ba.dims[0], ba.dims[1], ba.dims[2], x, y, z);
     }
-    float f[KIN / 32][8];
-    encode_lane<F, KIN>(md, table, x, y, z, f);
+    encode_row<P, F, KIN>(md, table, x, y, z, row, [&](int sb, const Oct<P>& o) {
+      if (valid) *reinterpret_cast<Oct<P>*>(e + s * KIN + 8 * sb) = o;
+    });
+    wave_sync();
+    const float yv = mlp_wave64<P, KIN, W>(md.n_hidden, lds_frag, lds_wout, stage);
+    wave_sync();
     if (valid) {
-      if constexpr (P) {
-        typedef typename Prec<P>::T T16;
-#pragma unroll
-        for (int b = 0; b < KIN / 32; ++b) {
-          Frag v;
-#pragma unroll
-          for (int jj = 0; jj < 8; ++jj) v[jj] = (T16)f[b][jj];
-          *reinterpret_cast<Frag*>(reinterpret_cast<T16*>(e_buf) + sc * KIN + 32 * b + 8 * g) = v;
-        }
-      } else {
-#pragma unroll
-        for (int b = 0; b < KIN / 32; ++b) {
-          float* dst = reinterpret_cast<float*>(e_buf) + sc * KIN + 32 * b + 8 * g;
-          *reinterpret_cast<float4*>(dst) = make_float4(f[b][0], f[b][1], f[b][2], f[b][3]);
-          *reinterpret_cast<float4*>(dst + 4) = make_float4(f[b][4], f[b][5], f[b][6], f[b][7]);
-        }
-      }
-    }
-    Frag in[InChunks<P, KIN>::n];
-    feat_to_frag<P, KIN>(f, in);
-    f32x4 act[W / 16];
-    mlp_hidden_fwd<P, KIN, W, false>(md.n_hidden, lds_frag, in, act, nullptr);
-    const float yv = mlp_output<W>(act, lds_wout);
-    if (valid && g == 0) {
       const float r = yv - target;
       g_buf[s] = gscale * r;
       lsum += (double)r * (double)r;
@@ -283,36 +291,27 @@ __global__ void __launch_bounds__(256) k_sample_batch(BatchArgs ba, float* __res
 // ---------------------------------------------------------------------------
 // Host-side launchers (dispatch over the compile-time shapes).
 // ---------------------------------------------------------------------------
-#define NGV_DISPATCH_F_KIN(F_, KIN_, ...)                                    \
-  switch (F_ * 1000 + KIN_) {                                                \
-    case 2032: { constexpr int F = 2, KIN = 32; __VA_ARGS__; } break;        \
-    case 2064: { constexpr int F = 2, KIN = 64; __VA_ARGS__; } break;        \
-    case 4032: { constexpr int F = 4, KIN = 32; __VA_ARGS__; } break;        \
-    case 4064: { constexpr int F = 4, KIN = 64; __VA_ARGS__; } break;        \
-    case 8032: { constexpr int F = 8, KIN = 32; __VA_ARGS__; } break;        \
-    case 8064: { constexpr int F = 8, KIN = 64; __VA_ARGS__; } break;        \
-    default: return hipErrorInvalidValue;                                    \
-  }
-#define NGV_DISPATCH_W(W_, ...)                                              \
-  switch (W_) {                                                              \
-    case 32: { constexpr int W = 32; __VA_ARGS__; } break;                   \
-    case 64: { constexpr int W = 64; __VA_ARGS__; } break;                   \
-    default: return hipErrorInvalidValue;                                    \
-  }
-#define NGV_DISPATCH_P(P_, ...)                                              \
-  switch (P_) {                                                              \
-    case 0: { constexpr int P = 0; __VA_ARGS__; } break;                     \
-    case 1: { constexpr int P = 1; __VA_ARGS__; } break;                     \
-    case 2: { constexpr int P = 2; __VA_ARGS__; } break;                     \
-    default: return hipErrorInvalidValue;                                    \
-  }
-
 size_t fwd_lds_bytes(const ngvol_plan* plan) {
   const int P = plan->layout.precision, KIN = plan->kin, W = plan->layout.n_neurons, nh = plan->md.n_hidden;
   const int ch0 = P ? KIN / 32 : KIN / 4;
   const int chh = P ? (W + 31) / 32 : W / 4;
   const int frags = (W / 16) * ch0 + (nh - 1) * (W / 16) * chh;
   return (size_t)frags * 64 * (P ? 16 : 4) + (size_t)W * 4;
+}
+
+size_t enc_lds_bytes(const ngvol_plan* plan, int waves) {
+  // staged weights, then one encoding stage of 64 rows per wave
+  const int P = plan->layout.precision, KIN = plan->kin;
+  const size_t esz = P ? 2 : 4;
+  const size_t row = (size_t)(KIN + 16 / esz) * esz;
+  return ((fwd_lds_bytes(plan) + 15) & ~(size_t)15) + (size_t)waves * 64 * row;
+}
+
+int enc_waves(const ngvol_plan* plan) {
+  // 4 waves per workgroup unless the weights and stages would not fit
+  for (int w = 4; w > 1; w >>= 1)
+    if (enc_lds_bytes(plan, w) <= kLdsLimit) return w;
+  return 1;
 }
 
 static int grid_for(const ngvol_plan* plan, int64_t n_tiles, int waves_per_block, int blocks_per_cu) {
@@ -326,8 +325,8 @@ static int grid_for(const ngvol_plan* plan, int64_t n_tiles, int waves_per_block
 hipError_t launch_encode(const ngvol_plan* plan, TablePtrs tp, const float* xyz, int64_t n, float* feat,
                          hipStream_t st) {
   const ModelDesc& md = plan->md;
-  const int64_t n_tiles = (n + 15) / 16;
-  const int grid = grid_for(plan, n_tiles, 4, 8);
+  const int64_t n_groups = (n + 63) / 64;  // 64 samples per wave
+  const int grid = grid_for(plan, n_groups, 4, 8);
   NGV_DISPATCH_F_KIN(md.F, plan->kin, {
     if (tp.f16)
       hipLaunchKernelGGL((k_encode<F, KIN, __half>), dim3(grid), dim3(256), 0, st, md, tp, xyz, n, feat);
@@ -350,15 +349,16 @@ static hipError_t launch_infer_t(const ngvol_plan* plan, TablePtrs tp, const flo
                                  const float4* rec, int64_t n, float* out, const VT* vol, int dx, int dy, int dz,
                                  double* sq, hipStream_t st) {
   const ModelDesc& md = plan->md;
-  const int64_t n_tiles = (n + 15) / 16;
-  const size_t lds = fwd_lds_bytes(plan);
-  const int grid = grid_for(plan, n_tiles, 4, 8);
+  const int64_t n_groups = (n + 63) / 64;  // 64 samples per wave
+  const int waves = enc_waves(plan);
+  const size_t lds = enc_lds_bytes(plan, waves);
+  const int grid = grid_for(plan, n_groups, waves, 32 / waves);
   NGV_DISPATCH_P(plan->layout.precision, NGV_DISPATCH_F_KIN(md.F, plan->kin, NGV_DISPATCH_W(md.width, {
     if (tp.f16)
-      hipLaunchKernelGGL((k_infer<P, F, KIN, W, __half, MODE, VT>), dim3(grid), dim3(256), lds, st, md, tp, mlp, xyz,
+      hipLaunchKernelGGL((k_infer<P, F, KIN, W, __half, MODE, VT>), dim3(grid), dim3(64 * waves), lds, st, md, tp, mlp, xyz,
                          rec, n, out, vol, dx, dy, dz, sq);
     else
-      hipLaunchKernelGGL((k_infer<P, F, KIN, W, float, MODE, VT>), dim3(grid), dim3(256), lds, st, md, tp, mlp, xyz,
+      hipLaunchKernelGGL((k_infer<P, F, KIN, W, float, MODE, VT>), dim3(grid), dim3(64 * waves), lds, st, md, tp, mlp, xyz,
                          rec, n, out, vol, dx, dy, dz, sq);
   })));
   return hipGetLastError();
@@ -382,7 +382,7 @@ hipError_t launch_sq_error_grid(const ngvol_plan* plan, TablePtrs tp, const floa
 hipError_t launch_mlp_fwd(const ngvol_plan* plan, const float* mlp, const void* feat, int dtype, int64_t n,
                           float* out, hipStream_t st) {
   const ModelDesc& md = plan->md;
-  const int64_t n_tiles = (n + 63) / 64;  // 4-tile groups
+  const int64_t n_tiles = (n + 31) / 32;  // 2-tile groups
   const size_t lds = fwd_lds_bytes(plan);
   const int grid = grid_for(plan, n_tiles, 4, 8);
   NGV_DISPATCH_P(plan->layout.precision, {
@@ -416,24 +416,25 @@ hipError_t launch_mlp_fwd(const ngvol_plan* plan, const float* mlp, const void* 
 hipError_t launch_train_fwd(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const BatchArgs& ba, void* e_buf,
                             float* g_buf, double* loss_acc, float gscale, hipStream_t st) {
   const ModelDesc& md = plan->md;
-  const int64_t n_tiles = (ba.B + 15) / 16;
-  const size_t lds = fwd_lds_bytes(plan);
-  const int grid = grid_for(plan, n_tiles, 4, 8);
+  const int64_t n_groups = (ba.B + 63) / 64;  // 64 samples per wave
+  const int waves = enc_waves(plan);
+  const size_t lds = enc_lds_bytes(plan, waves);
+  const int grid = grid_for(plan, n_groups, waves, 32 / waves);
   const bool vf16 = ba.xyz == nullptr && ba.vdtype == NGVOL_DT_F16;
   NGV_DISPATCH_P(plan->layout.precision, NGV_DISPATCH_F_KIN(md.F, plan->kin, NGV_DISPATCH_W(md.width, {
     if (tp.f16) {
       if (vf16)
-        hipLaunchKernelGGL((k_train_fwd<P, F, KIN, W, __half, __half>), dim3(grid), dim3(256), lds, st, md, tp, mlp, ba,
+        hipLaunchKernelGGL((k_train_fwd<P, F, KIN, W, __half, __half>), dim3(grid), dim3(64 * waves), lds, st, md, tp, mlp, ba,
                            e_buf, g_buf, loss_acc, gscale);
       else
-        hipLaunchKernelGGL((k_train_fwd<P, F, KIN, W, __half, float>), dim3(grid), dim3(256), lds, st, md, tp, mlp, ba,
+        hipLaunchKernelGGL((k_train_fwd<P, F, KIN, W, __half, float>), dim3(grid), dim3(64 * waves), lds, st, md, tp, mlp, ba,
                            e_buf, g_buf, loss_acc, gscale);
     } else {
       if (vf16)
-        hipLaunchKernelGGL((k_train_fwd<P, F, KIN, W, float, __half>), dim3(grid), dim3(256), lds, st, md, tp, mlp, ba,
+        hipLaunchKernelGGL((k_train_fwd<P, F, KIN, W, float, __half>), dim3(grid), dim3(64 * waves), lds, st, md, tp, mlp, ba,
                            e_buf, g_buf, loss_acc, gscale);
       else
-        hipLaunchKernelGGL((k_train_fwd<P, F, KIN, W, float, float>), dim3(grid), dim3(256), lds, st, md, tp, mlp, ba,
+        hipLaunchKernelGGL((k_train_fwd<P, F, KIN, W, float, float>), dim3(grid), dim3(64 * waves), lds, st, md, tp, mlp, ba,
                            e_buf, g_buf, loss_acc, gscale);
     }
   })));

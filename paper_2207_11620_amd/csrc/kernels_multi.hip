@@ -5,9 +5,11 @@
 // width, depth) and the feature count, so one kernel instantiation serves
 // them all; they differ in levels, resolutions and table sizes, which are
 // read from a device table of model descriptors.  Work is cut into items of
-// `chunk_tiles` 16-sample tiles of one model, ordered model by model; each
-// workgroup walks one contiguous range of items, so it meets few model
-// boundaries, and restages the model's MLP weights in LDS at each one.
+// `chunk_tiles` 16-sample tiles of one model, ordered model by model; the
+// workgroups take items grid-stride, so the GPU evaluates the models one
+// after another (one model's tables in the caches at a time, no launch gaps
+// between models), and each workgroup restages a model's MLP weights in LDS
+// when it reaches that model's items.
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -16,23 +18,27 @@
 namespace ngvol {
 
 template <int P, int F, int KIN, int W, typename TT>
-__global__ void __launch_bounds__(256) k_multi_infer(const ModelDesc* __restrict__ table, MultiArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P != 0 && KIN == 32 ? 4 : 1)))
+k_multi_infer(const ModelDesc* __restrict__ table, MultiArgs a) {
   typedef typename Prec<P>::Frag Frag;
+  typedef typename Prec<P>::T T;
   typedef WeightLayout<P, KIN, W> WL;
   extern __shared__ __align__(16) unsigned char smem[];
   Frag* lds_frag = reinterpret_cast<Frag*>(smem);
   const int nh = table[0].n_hidden;  // shared by the group
-  float* lds_wout = reinterpret_cast<float*>(smem + (size_t)WL::frags(nh, false) * 64 * sizeof(Frag));
-
-  const int lane = threadIdx.x & 63, nl = lane & 15, g = lane >> 4, wave = threadIdx.x >> 6;
+  const size_t wbytes = (size_t)WL::frags(nh, false) * 64 * sizeof(Frag);
+  float* lds_wout = reinterpret_cast<float*>(smem + wbytes);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wpb = blockDim.x >> 6;
+  T* stage = reinterpret_cast<T*>(smem + stage_offset(wbytes, W) + wave * Stage<P, KIN>::wave_bytes);
+  T* row = stage + lane * Stage<P, KIN>::pitch;
+
+  // items are taken grid-stride, so at any time the whole GPU works on one
+  // or two models and their tables share the caches
   const int64_t total = a.item_prefix[a.k];
-  const int64_t per = (total + gridDim.x - 1) / gridDim.x;
-  const int64_t lo = (int64_t)blockIdx.x * per;
-  const int64_t hi = lo + per < total ? lo + per : total;
   int cur = -1;
   int m = 0;
-  for (int64_t item = lo; item < hi; ++item) {
+  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
     while (item >= a.item_prefix[m + 1]) ++m;
     // the model index is uniform across the workgroup: say so, so that its
     // descriptor is read through the scalar cache
@@ -50,23 +56,22 @@ __global__ void __launch_bounds__(256) k_multi_infer(const ModelDesc* __restrict
     const float* xyz = a.xyz[m];
     float* out = a.out[m];
     const int64_t n = a.n[m];
-    const int64_t n_tiles = (n + 15) >> 4;
-    const int64_t first = (item - a.item_prefix[m]) * a.chunk_tiles;
-    for (int j = wave; j < a.chunk_tiles; j += wpb) {
+    const int64_t n_groups = (n + 63) >> 6;
+    // an item is chunk_tiles 16-sample tiles, i.e. chunk_tiles / 4 wave groups
+    const int64_t gpi = a.chunk_tiles >> 2;
+    const int64_t first = (item - a.item_prefix[m]) * gpi;
+    for (int j = wave; j < gpi; j += wpb) {
       const int64_t t = first + j;
-      if (t >= n_tiles) break;
-      const int64_t s = t * 16 + nl;
+      if (t >= n_groups) break;
+      const int64_t s = t * 64 + lane;
       const bool valid = s < n;
       const int64_t sc = valid ? s : n - 1;
       const float x = clamp01(xyz[3 * sc]), y = clamp01(xyz[3 * sc + 1]), z = clamp01(xyz[3 * sc + 2]);
-      float f[KIN / 32][8];
-      encode_lane<F, KIN>(md, tab, x, y, z, f);
-      Frag in[InChunks<P, KIN>::n];
-      feat_to_frag<P, KIN>(f, in);
-      f32x4 act[W / 16];
-      mlp_hidden_fwd<P, KIN, W, false>(nh, lds_frag, in, act, nullptr);
-      const float yv = mlp_output<W>(act, lds_wout);
-      if (valid && g == 0) out[s] = yv;
+      encode_row<P, F, KIN>(md, tab, x, y, z, row, [](int, const Oct<P>&) {});
+      wave_sync();
+      const float yo = mlp_wave64<P, KIN, W>(nh, lds_frag, lds_wout, stage);
+      wave_sync();
+      if (valid) out[s] = yo;
     }
   }
 }
@@ -74,7 +79,7 @@ __global__ void __launch_bounds__(256) k_multi_infer(const ModelDesc* __restrict
 hipError_t launch_multi_infer(const ngvol_plan* plan0, const ModelDesc* table, const MultiArgs& a, bool f16,
                               int blocks_per_cu, hipStream_t st) {
   const ModelDesc& md = plan0->md;
-  const size_t lds = fwd_lds_bytes(plan0);
+  const size_t lds = enc_lds_bytes(plan0, 4);
   int64_t grid = a.item_prefix[a.k];
   const int64_t cap = (int64_t)plan0->cus * blocks_per_cu;
   if (grid > cap) grid = cap;

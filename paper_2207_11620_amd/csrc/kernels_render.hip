@@ -105,9 +105,17 @@ __device__ __forceinline__ int32_t fetch_pixel(unsigned int* queue, int band0, i
   return -1;
 }
 
+// LDS layout of k_render: staged weights, W_out, the LUT [256][4], the
+// slots and per-sample outputs of every wave, then the encoding stages.
+__host__ __device__ inline size_t render_stage_offset(size_t weight_bytes, int W, int waves) {
+  const size_t end = weight_bytes + (size_t)W * 4 + 1024 * 4 + (size_t)waves * kSlots * sizeof(SlotState) +
+                     (size_t)waves * kSlots * kK * 4;
+  return (end + 15) & ~(size_t)15;
+}
+
 template <int P, int F, int KIN, int W, typename TT>
-__global__ void __launch_bounds__(256) k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp,
-                                                RenderArgs ra) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P != 0 && KIN == 32 ? 4 : 1)))
+k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs ra) {
   typedef typename Prec<P>::Frag Frag;
   typedef WeightLayout<P, KIN, W> WL;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -119,6 +127,10 @@ __global__ void __launch_bounds__(256) k_render(ModelDesc md, TablePtrs tp, cons
   SlotState* slots = reinterpret_cast<SlotState*>(lds_lut + 1024) + wave * kSlots;
   float* yv = reinterpret_cast<float*>(reinterpret_cast<SlotState*>(lds_lut + 1024) + (blockDim.x >> 6) * kSlots) +
               wave * kSlots * kK;
+  typedef typename Prec<P>::T T;
+  T* stage = reinterpret_cast<T*>(smem + render_stage_offset(wbytes, W, blockDim.x >> 6) +
+                                  wave * Stage<P, KIN>::wave_bytes);
+  T* row = stage + (threadIdx.x & 63) * Stage<P, KIN>::pitch;
 
   stage_weights<P, KIN, W>(md, mlp, lds_frag, lds_wout, false);
   for (int t = threadIdx.x; t < 1024; t += blockDim.x) lds_lut[t] = ra.lut[t];
@@ -166,12 +178,11 @@ __global__ void __launch_bounds__(256) k_render(ModelDesc md, TablePtrs tp, cons
     // any live slot in this wave?
     const bool live = lane < kSlots && slots[lane].pix >= 0;
     if (!__any(live)) break;
-    // four 16-sample tiles: slot = 2*tile + nl/8, sample k = slot.k + nl%8
-#pragma unroll 1
-    for (int tile = 0; tile < kSlots * kK / 16; ++tile) {
-      const int si = 2 * tile + (nl >> 3);
+    // lane j evaluates sample k = slot.k + j%8 of slot j/8
+    {
+      const int si = lane >> 3;
       const SlotState& sl = slots[si];
-      const uint32_t k = sl.k + (nl & 7);
+      const uint32_t k = sl.k + (lane & 7);
       const bool valid = sl.pix >= 0 && k < sl.g.n;
       float x = 0.5f, y = 0.5f, z = 0.5f;
       if (valid) {
@@ -180,17 +191,10 @@ __global__ void __launch_bounds__(256) k_render(ModelDesc md, TablePtrs tp, cons
         y = clamp01(y);
         z = clamp01(z);
       }
-      float f[KIN / 32][8];
-      encode_lane<F, KIN>(md, table, x, y, z, f);
-      Frag in[InChunks<P, KIN>::n];
-      feat_to_frag<P, KIN>(f, in);
-      f32x4 act[W / 16];
-      mlp_hidden_fwd<P, KIN, W, false>(md.n_hidden, lds_frag, in, act, nullptr);
-      const float v = mlp_output<W>(act, lds_wout);
-      if (g == 0) {
-        yv[si * kK + (nl & 7)] = v;
-        if (valid) ++n_eval;
-      }
+      encode_row<P, F, KIN>(md, table, x, y, z, row, [](int, const Oct<P>&) {});
+      wave_sync();
+      yv[lane] = mlp_wave64<P, KIN, W>(md.n_hidden, lds_frag, lds_wout, stage);
+      if (valid) ++n_eval;
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -249,8 +253,11 @@ __global__ void __launch_bounds__(256) k_render(ModelDesc md, TablePtrs tp, cons
 }
 
 size_t render_lds_bytes(const ngvol_plan* plan, int waves) {
-  return fwd_lds_bytes(plan) + 1024 * 4 + (size_t)waves * kSlots * sizeof(SlotState) +
-         (size_t)waves * kSlots * kK * 4;
+  const size_t esz = plan->layout.precision ? 2 : 4;
+  const size_t stage = (size_t)64 * (plan->kin + 16 / esz) * esz;
+  return render_stage_offset(fwd_lds_bytes(plan) - (size_t)plan->layout.n_neurons * 4, plan->layout.n_neurons,
+                             waves) +
+         (size_t)waves * stage;
 }
 
 hipError_t launch_render(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const RenderArgs& ra,

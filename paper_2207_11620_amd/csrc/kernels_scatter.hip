@@ -25,6 +25,7 @@ namespace {
 constexpr int kScThreads = 256;
 constexpr int kReduceThreads = 256;
 constexpr int64_t kChunkRecords = 1 << 16;
+constexpr int kUnroll = 4;  // records per thread per round in the reduce
 
 struct Coords {
   const float* xyz;
@@ -166,21 +167,31 @@ __global__ void __launch_bounds__(kReduceThreads) k_sc_reduce(const uint4* __res
   constexpr int RW = Rec<F>::words;
   const uint32_t base_entry = (uint32_t)bucket << bshift;
   const uint4* r0 = rec + (size_t)offsets[bucket] * RW;
-  for (int64_t r = lo + threadIdx.x; r < hi; r += blockDim.x) {
-    uint32_t w[RW * 4];
+  // kUnroll records per thread per round: their loads are all in flight
+  // before the first LDS add
+  for (int64_t rb = lo + threadIdx.x; rb < hi; rb += (int64_t)blockDim.x * kUnroll) {
+    uint32_t w[kUnroll][RW * 4];
 #pragma unroll
-    for (int q = 0; q < RW; ++q) {
-      const uint4 u = r0[(size_t)r * RW + q];
-      w[4 * q] = u.x;
-      w[4 * q + 1] = u.y;
-      w[4 * q + 2] = u.z;
-      w[4 * q + 3] = u.w;
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t r = rb + (int64_t)u * blockDim.x;
+#pragma unroll
+      for (int q = 0; q < RW; ++q) {
+        uint4 x = make_uint4(base_entry, 0u, 0u, 0u);
+        if (r < hi) x = r0[(size_t)r * RW + q];
+        w[u][4 * q] = x.x;
+        w[u][4 * q + 1] = x.y;
+        w[u][4 * q + 2] = x.z;
+        w[u][4 * q + 3] = x.w;
+      }
     }
-    const int local = (int)(w[0] - base_entry);
 #pragma unroll
-    for (int f = 0; f < F; ++f) {
-      const float v = __uint_as_float(w[1 + f]);
-      if (v != 0.0f) atomicAdd(acc + local * F + f, v);
+    for (int u = 0; u < kUnroll; ++u) {
+      const int local = (int)(w[u][0] - base_entry);
+#pragma unroll
+      for (int f = 0; f < F; ++f) {
+        const float v = __uint_as_float(w[u][1 + f]);
+        if (v != 0.0f) atomicAdd(acc + local * F + f, v);
+      }
     }
   }
   __syncthreads();

@@ -213,6 +213,13 @@ BinPlan bin_plan(const ngvol_plan* plan, int64_t n) {
   bp.totals_off = bp.counts_off + up((size_t)bp.blocks * bp.n_bins * 4);
   bp.offsets_off = bp.totals_off + up((size_t)bp.n_bins * 4);
   bp.bytes = bp.offsets_off + up((size_t)bp.n_bins * 4);
+  bp.split = use_split(plan, n);
+  if (bp.split) {
+    const int64_t slab = split_slab(plan, n);
+    bp.planes_off = bp.bytes;
+    bp.idx_off = bp.planes_off + up((size_t)slab * plan->md.L * plan->md.F * split_operand_bytes(plan));
+    bp.bytes = bp.idx_off + up((size_t)slab * 4);
+  }
   return bp;
 }
 

@@ -1,0 +1,215 @@
+// Query by level groups, one group per XCD: the encoding of Section 3.1 and
+// the network of Section 3.2, evaluated in two passes for large query sets.
+//
+// At the paper's sizes the FP16 tables (16 levels of up to 2^19 entries,
+// 24 MB) exceed the L2 of one XCD (4 MB), and the entries a hashed level
+// needs for any region of space are spread over its whole table, so when
+// every XCD evaluates all levels for its share of the queries, most gathers
+// miss its L2.  Here XCD x evaluates only the levels assigned to it (about
+// L/8 of them) for all queries, so its gathers stay in its own L2:
+//   1. k_level_feat: the workgroups placed on XCD x (blockIdx % 8 == x, the
+//      hardware's round-robin placement of workgroups) interpolate their
+//      levels for the queries and write the features into per-level planes
+//      [level][query][F], already in the MLP's operand type;
+//   2. k_mlp_planes: the network on the planes; each result goes to the
+//      query's original slot.
+// The features are converted to the operand type exactly as in the fused
+// kernel, so both paths give bitwise the same outputs.
+#include <type_traits>
+
+#include "kernels.hpp"
+#include "dispatch.hpp"
+#include "mlp_tile.hpp"
+
+namespace ngvol {
+
+namespace {
+
+template <int BYTES>
+struct alignas(BYTES) Bytes {
+  uint32_t w[BYTES / 4];
+};
+
+template <int F, typename OT>
+struct alignas(F * sizeof(OT)) LevelPack {
+  OT v[F];
+};
+
+template <int F, typename TT, typename OT>
+__global__ void __launch_bounds__(256) k_level_feat(ModelDesc md, const TT* __restrict__ table,
+                                                    const float4* __restrict__ rec, int64_t m,
+                                                    OT* __restrict__ planes, uint32_t* __restrict__ idx,
+                                                    SplitArgs sa) {
+  const int x = blockIdx.x & 7;
+  const int r = blockIdx.x >> 3;
+  const int nbx = (int)((gridDim.x - x + 7) >> 3);  // workgroups on this XCD
+  const int wpb = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nlv = sa.n_lv[x];
+  if (nlv == 0) return;
+  const int64_t chunks = (m + 63) >> 6;
+  const int64_t c_lo = chunks * sa.part[x] / sa.parts[x];
+  const int64_t c_hi = chunks * (sa.part[x] + 1) / sa.parts[x];
+  // the XCDs holding level 0 also write the queries' slots
+  const bool write_idx = sa.lv[x][0] == 0;
+  for (int64_t c = c_lo + (int64_t)r * wpb + wave; c < c_hi; c += (int64_t)nbx * wpb) {
+    const int64_t q = c * 64 + lane;
+    const bool valid = q < m;
+    const float4 rr = rec[valid ? q : m - 1];
+    const float px = clamp01(rr.x), py = clamp01(rr.y), pz = clamp01(rr.z);
+    if (write_idx && valid) idx[q] = __float_as_uint(rr.w);
+    for (int i = 0; i < nlv; ++i) {
+      const int l = sa.lv[x][i];
+      Corners cr;
+      level_corners(md.lv[l], px, py, pz, cr);
+      float acc[F];
+      gather_level<F>(cr, table, (uint32_t)(md.n_table / F), acc);
+      LevelPack<F, OT> pk;
+#pragma unroll
+      for (int f = 0; f < F; ++f) pk.v[f] = (OT)acc[f];
+      if (valid) *reinterpret_cast<LevelPack<F, OT>*>(planes + ((int64_t)l * m + q) * F) = pk;
+    }
+  }
+}
+
+template <int P, int F, int KIN, int W, typename OT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P != 0 && KIN == 32 ? 4 : 1)))
+k_mlp_planes(ModelDesc md, const float* __restrict__ mlp, const OT* __restrict__ planes,
+             const uint32_t* __restrict__ idx, int64_t m, float* __restrict__ out) {
+  constexpr int NB = 2;
+  constexpr int CH0 = InChunks<P, KIN>::n;
+  constexpr int LPB = 8 / F;                            // levels per 8-feature block
+  constexpr int LB = F * (int)sizeof(OT);               // bytes of one level's features
+  constexpr int DW = 8 * (int)sizeof(OT) / 4;           // dwords of one block
+  typedef typename Prec<P>::Frag Frag;
+  typedef WeightLayout<P, KIN, W> WL;
+  extern __shared__ __align__(16) unsigned char smem[];
+  Frag* lds_frag = reinterpret_cast<Frag*>(smem);
+  float* lds_wout = reinterpret_cast<float*>(smem + (size_t)WL::frags(md.n_hidden, false) * 64 * sizeof(Frag));
+  stage_weights<P, KIN, W>(md, mlp, lds_frag, lds_wout, false);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, nl = lane & 15, g = lane >> 4;
+  const int L = md.L;
+  const int64_t n_groups = (m + 16 * NB - 1) / (16 * NB);
+  TileIter it(n_groups);
+  struct Raw {
+    uint32_t d[NB][KIN / 32][DW];
+    uint32_t slot[NB];
+  };
+  mlp_stream<P, KIN, W, NB, Raw>(
+      md.n_hidden, lds_frag, lds_wout, it.next, it.step, it.end,
+      [&](int64_t grp, Raw& r) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          int64_t s = (grp * NB + nb) * 16 + nl;
+          s = s < m ? s : m - 1;
+          r.slot[nb] = idx[s];
+#pragma unroll
+          for (int b = 0; b < KIN / 32; ++b)
+#pragma unroll
+            for (int q = 0; q < LPB; ++q) {
+              const int l = (32 * b + 8 * g) / F + q;
+              Bytes<LB> v;
+              if (l < L) {
+                v = *reinterpret_cast<const Bytes<LB>*>(planes + ((int64_t)l * m + s) * F);
+              } else {
+#pragma unroll
+                for (int w = 0; w < LB / 4; ++w) v.w[w] = 0u;
+              }
+#pragma unroll
+              for (int w = 0; w < LB / 4; ++w) r.d[nb][b][q * (LB / 4) + w] = v.w[w];
+            }
+        }
+      },
+      [&](const Raw& r, Frag (*in)[CH0]) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+          for (int b = 0; b < KIN / 32; ++b) {
+            if constexpr (P) {
+              Bytes<16> t;
+#pragma unroll
+              for (int w = 0; w < 4; ++w) t.w[w] = r.d[nb][b][w];
+              in[nb][b] = __builtin_bit_cast(Frag, t);
+            } else {
+#pragma unroll
+              for (int jj = 0; jj < 8; ++jj) in[nb][8 * b + jj] = __uint_as_float(r.d[nb][b][jj]);
+            }
+          }
+      },
+      [&](int64_t grp, int nb, float y, const Raw& r) {
+        const int64_t s = (grp * NB + nb) * 16 + nl;
+        if (s < m && g == 0) out[r.slot[nb]] = y;
+      });
+}
+
+}  // namespace
+
+bool use_split(const ngvol_plan* plan, int64_t n) {
+  // worth it when the queries are many and the FP16 tables exceed one XCD's L2
+  return n >= ((int64_t)1 << 20) && plan->md.L >= 2 && (int64_t)plan->md.n_table * 2 > ((int64_t)4 << 20);
+}
+
+SplitArgs split_args(const ngvol_plan* plan) {
+  SplitArgs sa{};
+  const int L = plan->md.L;
+  for (int x = 0; x < 8; ++x) {
+    if (L >= 8) {
+      for (int l = x; l < L; l += 8) sa.lv[x][sa.n_lv[x]++] = l;
+      sa.part[x] = 0;
+      sa.parts[x] = 1;
+    } else {
+      // fewer levels than XCDs: a level's queries are shared by the XCDs holding it
+      const int l = x % L;
+      sa.lv[x][0] = l;
+      sa.n_lv[x] = 1;
+      sa.part[x] = x / L;
+      sa.parts[x] = (8 - l + L - 1) / L;
+    }
+  }
+  return sa;
+}
+
+int split_operand_bytes(const ngvol_plan* plan) { return plan->layout.precision ? 2 : 4; }
+
+int64_t split_slab(const ngvol_plan* plan, int64_t n) {
+  // planes of at most 1 GiB (or 2^20 queries) per pass, in whole 64-query chunks
+  const int64_t per_query = (int64_t)plan->md.L * plan->md.F * split_operand_bytes(plan);
+  int64_t slab = ((int64_t)1 << 30) / per_query;
+  if (slab < ((int64_t)1 << 20)) slab = (int64_t)1 << 20;
+  slab &= ~(int64_t)63;
+  return slab < n ? slab : n;
+}
+
+hipError_t launch_infer_split(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const float4* rec, int64_t n,
+                              float* out, void* planes, uint32_t* idx, hipStream_t st) {
+  const ModelDesc& md = plan->md;
+  const SplitArgs sa = split_args(plan);
+  const int64_t slab = split_slab(plan, n);
+  const size_t lds = fwd_lds_bytes(plan);
+  for (int64_t s0 = 0; s0 < n; s0 += slab) {
+    const int64_t m = n - s0 < slab ? n - s0 : slab;
+    const int64_t chunks = (m + 63) / 64;
+    int64_t per_xcd = (chunks + 3) / 4;
+    if (per_xcd > plan->cus) per_xcd = plan->cus;
+    if (per_xcd < 1) per_xcd = 1;
+    const dim3 lgrid((unsigned)(8 * per_xcd));
+    int64_t mgrid = (m + 127) / 128;  // 4 waves of 2-tile groups
+    if (mgrid > (int64_t)plan->cus * 8) mgrid = (int64_t)plan->cus * 8;
+    const float4* r = rec + s0;
+    NGV_DISPATCH_P(plan->layout.precision, NGV_DISPATCH_F_KIN(md.F, plan->kin, NGV_DISPATCH_W(md.width, {
+      typedef typename std::conditional<P == 0, float, typename Prec<P>::T>::type OT;
+      OT* pl = reinterpret_cast<OT*>(planes);
+      if (tp.f16)
+        hipLaunchKernelGGL((k_level_feat<F, __half, OT>), lgrid, dim3(256), 0, st, md, tp.f16, r, m, pl, idx, sa);
+      else
+        hipLaunchKernelGGL((k_level_feat<F, float, OT>), lgrid, dim3(256), 0, st, md, tp.f32, r, m, pl, idx, sa);
+      hipLaunchKernelGGL((k_mlp_planes<P, F, KIN, W, OT>), dim3((unsigned)mgrid), dim3(256), lds, st, md, mlp, pl,
+                         idx, m, out);
+    })));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace ngvol

@@ -15,9 +15,10 @@
 //   P = 0: FP32 operands, v_mfma_f32_16x16x4_f32 (K = 4 per instruction).
 // Both accumulate in FP32.
 //
-// Encoded inputs use a different lane ownership: in every 32-feature block b,
-// lane group g owns features 32b + 8g + jj (jj = 0..7) of its sample, i.e.
-// 8/F whole levels, so each lane gathers whole levels.
+// Encoded inputs enter as B operands in which, for every 32-feature block b,
+// lane group g holds features 32b + 8g + jj (jj = 0..7) of sample n.  They
+// are produced with one sample per lane (all lanes on the same level) and
+// redistributed through a per-wave LDS stage.
 #pragma once
 
 #include "device_common.hpp"
@@ -331,31 +332,142 @@ __device__ __forceinline__ float mlp_output(const f32x4 zlast[W / 16], const flo
 }
 
 // ---------------------------------------------------------------------------
-// Encoding of the lane's share of one sample: features 32b + 8g + jj.
+// Streaming evaluation: the wave walks groups of NB tiles; the inputs of the
+// next group are loaded (ld) while the current group runs through the
+// network, with two register buffers used in turn so that the loads stay in
+// flight during the MFMA work.  cv turns loaded data into B operands; st
+// receives y for (group, tile, lane) together with the group's loaded data.
 // ---------------------------------------------------------------------------
-template <int F, int KIN, typename TT>
-__device__ __forceinline__ void encode_lane(const ModelDesc& md, const TT* __restrict__ table, float x, float y,
-                                            float z, float feat[KIN / 32][8]) {
-  const int g = (threadIdx.x & 63) >> 4;
-  constexpr int LPL = 8 / F;  // levels per lane per block
+template <int P, int KIN, int W, int NB, typename Raw, class Ld, class Cv, class St>
+__device__ __forceinline__ void mlp_stream(int n_hidden, const typename Prec<P>::Frag* __restrict__ lds_frag,
+                                           const float* __restrict__ lds_wout, int64_t t, int64_t step, int64_t end,
+                                           Ld ld, Cv cv, St st) {
+  typedef typename Prec<P>::Frag Frag;
+  auto run = [&](int64_t grp, const Raw& r) {
+    Frag in[NB][InChunks<P, KIN>::n];
+    cv(r, in);
+    f32x4 act[NB][W / 16];
+    mlp_hidden_fwd_nb<P, KIN, W, NB>(n_hidden, lds_frag, in, act);
 #pragma unroll
-  for (int b = 0; b < KIN / 32; ++b) {
+    for (int nb = 0; nb < NB; ++nb) st(grp, nb, mlp_output<W>(act[nb], lds_wout), r);
+  };
+  if (t >= end) return;
+  Raw a, b;
+  ld(t, a);
+  while (true) {
+    int64_t tn = t + step;
+    if (tn < end) ld(tn, b);
+    run(t, a);
+    t = tn;
+    if (t >= end) break;
+    tn = t + step;
+    if (tn < end) ld(tn, a);
+    run(t, b);
+    t = tn;
+    if (t >= end) break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Encoding with one sample per lane (64 per wave).  All lanes work on the
+// same level at a time, so the level's descriptor is uniform (scalar loads)
+// and so is the dense/hashed choice.  Each lane writes its features, in the
+// operand type, to its row of a per-wave LDS stage [64][pitch]; after
+// wave_sync, stage_frags gives lane (n, g) the B operands of tile t (samples
+// 16t..16t+15 of the wave's 64): features 32b + 8g + jj of sample 16t + n.
+// The conversion to the operand type is the one feat_to_frag applies.
+// ---------------------------------------------------------------------------
+template <int P, int KIN>
+struct Stage {
+  typedef typename Prec<P>::T T;
+  static constexpr int pitch = KIN + (int)(16 / sizeof(T));  // rows stay 16-byte aligned
+  static constexpr size_t wave_bytes = (size_t)64 * pitch * sizeof(T);
+};
+
+// 8 consecutive operands of one row, as stored in LDS and in memory.
+template <int P>
+struct alignas(16) Oct {
+  typename Prec<P>::T v[8];
+};
+
+// Encodes the lane's sample into its stage row; sink(sb, oct) also receives
+// every 8-feature block (sb = block index), e.g. to store the encoding.
+template <int P, int F, int KIN, typename TT, class Sink>
+__device__ __forceinline__ void encode_row(const ModelDesc& md, const TT* __restrict__ table, float x, float y,
+                                           float z, typename Prec<P>::T* row, Sink sink) {
+  typedef typename Prec<P>::T T;
+  constexpr int LPS = 8 / F;  // levels per 8-feature block
 #pragma unroll
-    for (int q = 0; q < LPL; ++q) {
-      const int l = (32 * b + 8 * g) / F + q;
+  for (int sb = 0; sb < KIN / 8; ++sb) {
+    float v[8];
+#pragma unroll
+    for (int q = 0; q < LPS; ++q) {
+      const int l = sb * LPS + q;
       float acc[F];
       if (l < md.L) {
         Corners cr;
         level_corners(md.lv[l], x, y, z, cr);
-        gather_level<F>(cr, table, acc);
+        gather_level<F>(cr, table, (uint32_t)(md.n_table / F), acc);
       } else {
 #pragma unroll
         for (int f = 0; f < F; ++f) acc[f] = 0.0f;
       }
 #pragma unroll
-      for (int f = 0; f < F; ++f) feat[b][q * F + f] = acc[f];
+      for (int f = 0; f < F; ++f) v[q * F + f] = acc[f];
+    }
+    Oct<P> o;
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj) o.v[jj] = (T)v[jj];
+    *reinterpret_cast<Oct<P>*>(row + 8 * sb) = o;
+    sink(sb, o);
+  }
+}
+
+template <int P, int KIN>
+__device__ __forceinline__ void stage_frags(const typename Prec<P>::T* stage, int t,
+                                            typename Prec<P>::Frag in[InChunks<P, KIN>::n]) {
+  typedef typename Prec<P>::Frag Frag;
+  const int lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4;
+  const typename Prec<P>::T* row = stage + (16 * t + n) * Stage<P, KIN>::pitch;
+#pragma unroll
+  for (int b = 0; b < KIN / 32; ++b) {
+    const Oct<P> o = *reinterpret_cast<const Oct<P>*>(row + 32 * b + 8 * g);
+    if constexpr (P) {
+      in[b] = __builtin_bit_cast(Frag, o);
+    } else {
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) in[8 * b + jj] = o.v[jj];
     }
   }
+}
+
+// Byte offset of the per-wave encoding stages behind the staged weights.
+__device__ __forceinline__ size_t stage_offset(size_t weight_bytes, int W) {
+  return (weight_bytes + (size_t)W * 4 + 15) & ~(size_t)15;
+}
+
+// The network on the wave's 64 staged samples (4 tiles, NB at a time); the
+// lane receives y of its own sample (tile g, column n).
+template <int P, int KIN, int W, int NB = 1>
+__device__ __forceinline__ float mlp_wave64(int n_hidden, const typename Prec<P>::Frag* __restrict__ lds_frag,
+                                            const float* __restrict__ lds_wout, const typename Prec<P>::T* stage) {
+  typedef typename Prec<P>::Frag Frag;
+  const int g = (threadIdx.x & 63) >> 4;
+  float yo = 0.0f;
+#pragma unroll
+  for (int h = 0; h < 4 / NB; ++h) {
+    Frag in[NB][InChunks<P, KIN>::n];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) stage_frags<P, KIN>(stage, NB * h + nb, in[nb]);
+    f32x4 act[NB][W / 16];
+    mlp_hidden_fwd_nb<P, KIN, W, NB>(n_hidden, lds_frag, in, act);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const float y = mlp_output<W>(act[nb], lds_wout);
+      if (g == NB * h + nb) yo = y;
+    }
+  }
+  return yo;
 }
 
 template <int P, int KIN>

@@ -173,6 +173,32 @@ def test_binned_infer_equals_direct():
         np.testing.assert_array_equal(a, c)
 
 
+@pytest.mark.parametrize("name,prec,f16", [("cfg1", "fp32", True), ("cfg1", "fp32", False), ("f4", "fp16", True),
+                                           ("paper", "bf16", True), ("l4", "fp32", True)])
+def test_level_split_equals_fused(name, prec, f16):
+    # above 2^20 queries with FP16 tables larger than one L2 the grouped query
+    # runs level group by level group (one group per XCD) and the MLP on
+    # feature planes; it must give bitwise the outputs of the fused kernel
+    m = oracle_model(name)
+    p = gpu_plan(name, prec)
+    params = init_params(name, table_scale=0.5)
+    n = (1 << 20) + 37
+    xyz = edge_coords(n, seed=SEED % 1000 + len(name))
+    pt, xt = dev(params), dev(xyz)
+    tf = ngv.make_f16_tables(p, pt) if f16 else None
+    a = host(ngv.infer(p, pt, xt, table_f16=tf, sort=False))
+    b = host(ngv.infer(p, pt, xt, table_f16=tf, sort=True))
+    np.testing.assert_array_equal(a, b)
+    if prec == "fp32":
+        # the oracle on the tables the kernels read (FP16-rounded when used)
+        q = params.astype(np.float64)
+        if f16:
+            q[:m.n_table] = host(tf).astype(np.float64)
+        idx = np.r_[np.arange(8), np.linspace(8, n - 1, 1500).astype(np.int64)]
+        ref = oracle.forward(m, q, xyz[idx])
+        assert rel_err(b[idx], ref) <= 1e-5
+
+
 def _morton(q, bits):
     key = np.zeros(q.shape[0], dtype=np.int64)
     for b in range(bits):
