@@ -146,7 +146,7 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    recs = [(ev(), ev(), ev(), ev()) for _ in range(args.steps)]
+    recs = [tuple(ev() for _ in range(4)) for _ in range(args.steps)]
     start, stop = ev(), ev()
     torch.cuda.synchronize()
     wall0 = time.perf_counter()

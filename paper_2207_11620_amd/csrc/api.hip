@@ -630,7 +630,7 @@ int ngvol_multi_autotune(ngvol_multi* g, const ngvol_weights* w, const float* co
                          float* const* out, hipStream_t st, int32_t* bpc_out, int32_t* chunk_out) {
   NGV_REQUIRE(g, "group is NULL");
   static const int kBpc[] = {2, 4, 8, 16};
-  static const int kChunk[] = {8, 32, 128};
+  static const int kChunk[] = {16, 64, 256};  // multiples of 4 tiles: every wave of a workgroup gets a group
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);

@@ -101,18 +101,19 @@ struct TileIter {
   }
 };
 
-// Level-split query: which levels (and which part of the queries) each of
-// the 8 XCDs evaluates.
+// Level groups per XCD (level-split query): XCD x evaluates count[x] levels
+// first[x], first[x]+8, ... for its part of the queries; width = levels of
+// plane storage per group.
 struct SplitArgs {
-  int n_lv[8];
-  int lv[8][4];
+  int first[8], count[8];
   int part[8], parts[8];
+  int width;
 };
 bool use_split(const ngvol_plan* plan, int64_t n);
-int split_operand_bytes(const ngvol_plan* plan);
 int64_t split_slab(const ngvol_plan* plan, int64_t n);
-// rec: sorted records (x, y, z, original index); planes/idx: workspace of
-// split_slab * L * F * split_operand_bytes and split_slab * 4 bytes.
+size_t split_planes_bytes(const ngvol_plan* plan, int64_t n);
+// rec: grouped records (x, y, z, original index); planes/idx: workspace of
+// split_planes_bytes and split_slab * 4 bytes.
 hipError_t launch_infer_split(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const float4* rec, int64_t n,
                               float* out, void* planes, uint32_t* idx, hipStream_t st);
 

@@ -23,9 +23,9 @@ namespace ngvol {
 namespace {
 
 constexpr int kScThreads = 256;
-constexpr int kReduceThreads = 256;
+constexpr int kReduceThreads = 1024;
 constexpr int64_t kChunkRecords = 1 << 16;
-constexpr int kUnroll = 4;  // records per thread per round in the reduce
+constexpr int kUnroll = 8;  // records per thread per round in the reduce
 
 struct Coords {
   const float* xyz;

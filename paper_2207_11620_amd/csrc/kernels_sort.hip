@@ -65,10 +65,19 @@ __global__ void __launch_bounds__(kSortThreads) k_bin_hist(Src src, int64_t n, i
   __syncthreads();
   const int64_t lo = (int64_t)blockIdx.x * chunk;
   const int64_t hi = lo + chunk < n ? lo + chunk : n;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    float x, y, z;
-    src.get(i, x, y, z);
-    atomicAdd(hist + cell_key(x, y, z, k), 1u);
+  // 4 samples per thread per round, their coordinates loaded together
+  for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += 4 * (int64_t)blockDim.x) {
+    uint32_t key[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t i = i0 + (int64_t)u * blockDim.x;
+      float x = 0.0f, y = 0.0f, z = 0.0f;
+      if (i < hi) src.get(i, x, y, z);
+      key[u] = cell_key(x, y, z, k);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i0 + (int64_t)u * blockDim.x < hi) atomicAdd(hist + key[u], 1u);
   }
   __syncthreads();
   uint32_t* dst = counts + (size_t)blockIdx.x * nb;
@@ -76,28 +85,43 @@ __global__ void __launch_bounds__(kSortThreads) k_bin_hist(Src src, int64_t n, i
 }
 
 // counts[blk][bin] <- exclusive prefix over blocks; totals[bin] <- sum.
+// The counts of a bin are read kPrefixBatch at a time, so their loads are
+// in flight together rather than one after another.
+constexpr int kPrefixBatch = 16;
+
 __global__ void __launch_bounds__(256) k_bin_prefix(uint32_t* __restrict__ counts, int blocks, int nb,
                                                     uint32_t* __restrict__ totals) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nb) return;
   uint32_t run = 0;
-  for (int k = 0; k < blocks; ++k) {
-    const uint32_t v = counts[(size_t)k * nb + b];
-    counts[(size_t)k * nb + b] = run;
-    run += v;
+  for (int k0 = 0; k0 < blocks; k0 += kPrefixBatch) {
+    uint32_t v[kPrefixBatch];
+#pragma unroll
+    for (int u = 0; u < kPrefixBatch; ++u) v[u] = k0 + u < blocks ? counts[(size_t)(k0 + u) * nb + b] : 0u;
+#pragma unroll
+    for (int u = 0; u < kPrefixBatch; ++u) {
+      if (k0 + u < blocks) counts[(size_t)(k0 + u) * nb + b] = run;
+      run += v[u];
+    }
   }
   totals[b] = run;
 }
 
-// Exclusive scan of the bin totals, one block.
+// Exclusive scan of the bin totals, one block; each thread owns a run of
+// consecutive bins, read in batches.
 __global__ void __launch_bounds__(kSortThreads) k_bin_scan(const uint32_t* __restrict__ totals, int nb,
                                                            uint32_t* __restrict__ offsets) {
   __shared__ uint32_t part[kSortThreads];
   const int per = (nb + kSortThreads - 1) / kSortThreads;
   const int lo = threadIdx.x * per;
   uint32_t s = 0;
-  for (int i = 0; i < per; ++i)
-    if (lo + i < nb) s += totals[lo + i];
+  for (int i0 = 0; i0 < per; i0 += kPrefixBatch) {
+    uint32_t v[kPrefixBatch];
+#pragma unroll
+    for (int u = 0; u < kPrefixBatch; ++u) v[u] = (i0 + u < per && lo + i0 + u < nb) ? totals[lo + i0 + u] : 0u;
+#pragma unroll
+    for (int u = 0; u < kPrefixBatch; ++u) s += v[u];
+  }
   part[threadIdx.x] = s;
   __syncthreads();
   for (int d = 1; d < kSortThreads; d <<= 1) {
@@ -107,11 +131,16 @@ __global__ void __launch_bounds__(kSortThreads) k_bin_scan(const uint32_t* __res
     __syncthreads();
   }
   uint32_t run = part[threadIdx.x] - s;  // exclusive
-  for (int i = 0; i < per; ++i)
-    if (lo + i < nb) {
-      offsets[lo + i] = run;
-      run += totals[lo + i];
+  for (int i0 = 0; i0 < per; i0 += kPrefixBatch) {
+    uint32_t v[kPrefixBatch];
+#pragma unroll
+    for (int u = 0; u < kPrefixBatch; ++u) v[u] = (i0 + u < per && lo + i0 + u < nb) ? totals[lo + i0 + u] : 0u;
+#pragma unroll
+    for (int u = 0; u < kPrefixBatch; ++u) {
+      if (i0 + u < per && lo + i0 + u < nb) offsets[lo + i0 + u] = run;
+      run += v[u];
     }
+  }
 }
 
 // Scatter one 16-byte record per sample: (x, y, z, aux), where aux is the
@@ -215,10 +244,9 @@ BinPlan bin_plan(const ngvol_plan* plan, int64_t n) {
   bp.bytes = bp.offsets_off + up((size_t)bp.n_bins * 4);
   bp.split = use_split(plan, n);
   if (bp.split) {
-    const int64_t slab = split_slab(plan, n);
     bp.planes_off = bp.bytes;
-    bp.idx_off = bp.planes_off + up((size_t)slab * plan->md.L * plan->md.F * split_operand_bytes(plan));
-    bp.bytes = bp.idx_off + up((size_t)slab * 4);
+    bp.idx_off = bp.planes_off + up(split_planes_bytes(plan, n));
+    bp.bytes = bp.idx_off + up((size_t)split_slab(plan, n) * 4);
   }
   return bp;
 }

@@ -1,19 +1,23 @@
-// Query by level groups, one group per XCD: the encoding of Section 3.1 and
-// the network of Section 3.2, evaluated in two passes for large query sets.
+// Level groups, one per XCD: the encoding of Section 3.1 and the network of
+// Section 3.2 evaluated in two passes for large query sets.
 //
 // At the paper's sizes the FP16 tables (16 levels of up to 2^19 entries,
 // 24 MB) exceed the L2 of one XCD (4 MB), and the entries a hashed level
 // needs for any region of space are spread over its whole table, so when
-// every XCD evaluates all levels for its share of the queries, most gathers
-// miss its L2.  Here XCD x evaluates only the levels assigned to it (about
-// L/8 of them) for all queries, so its gathers stay in its own L2:
+// every XCD evaluates all levels for its share of the queries most gathers
+// miss its L2.  Here XCD x evaluates only its own group of levels
+// {x, x+8, ...} for all queries, so its gathers stay in its own L2; the
+// round-robin groups pair a coarse level (many queries share its corner
+// lines) with a fine one, which balances the XCDs.
 //   1. k_level_feat: the workgroups placed on XCD x (blockIdx % 8 == x, the
 //      hardware's round-robin placement of workgroups) interpolate their
-//      levels for the queries and write the features into per-level planes
-//      [level][query][F], already in the MLP's operand type;
-//   2. k_mlp_planes: the network on the planes; each result goes to the
+//      levels and write them, in the MLP's operand type, into their group's
+//      own plane [query][group levels][F] - one store per query, and no
+//      cache line shared with another XCD's writes;
+//   2. k_mlp_planes: the network on the planes, with the next tiles' features
+//      loaded while the current ones are evaluated; each result goes to the
 //      query's original slot.
-// The features are converted to the operand type exactly as in the fused
+// Features are converted to the operand type exactly as in the fused
 // kernel, so both paths give bitwise the same outputs.
 #include <type_traits>
 
@@ -26,14 +30,21 @@ namespace ngvol {
 namespace {
 
 template <int BYTES>
-struct alignas(BYTES) Bytes {
+struct alignas(BYTES < 16 ? BYTES : 16) Bytes {
   uint32_t w[BYTES / 4];
 };
 
-template <int F, typename OT>
-struct alignas(F * sizeof(OT)) LevelPack {
-  OT v[F];
+template <int F, typename OT, int NL>
+struct alignas(NL * F * sizeof(OT) <= 16 ? NL * F * sizeof(OT) : 16) LevelPack {
+  OT v[NL * F];
 };
+
+// Plane element of (query q, level l, feature 0): group l % 8 (level l
+// itself when L < 8) holds its levels l, l+8, ... side by side, gw per query.
+__device__ __forceinline__ int64_t plane_elem(int64_t q, int l, int F, int gw, int64_t m) {
+  const int x = l & 7, i = l >> 3;
+  return ((int64_t)x * m * gw + q * gw + i) * F;
+}
 
 template <int F, typename TT, typename OT>
 __global__ void __launch_bounds__(256) k_level_feat(ModelDesc md, const TT* __restrict__ table,
@@ -44,29 +55,44 @@ __global__ void __launch_bounds__(256) k_level_feat(ModelDesc md, const TT* __re
   const int r = blockIdx.x >> 3;
   const int nbx = (int)((gridDim.x - x + 7) >> 3);  // workgroups on this XCD
   const int wpb = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int nlv = sa.n_lv[x];
-  if (nlv == 0) return;
+  const int l0 = sa.first[x], nl = sa.count[x], gw = sa.width;
+  if (nl == 0) return;
+  const uint32_t n_ent = (uint32_t)(md.n_table / F);
   const int64_t chunks = (m + 63) >> 6;
   const int64_t c_lo = chunks * sa.part[x] / sa.parts[x];
   const int64_t c_hi = chunks * (sa.part[x] + 1) / sa.parts[x];
   // the XCDs holding level 0 also write the queries' slots
-  const bool write_idx = sa.lv[x][0] == 0;
+  const bool write_idx = l0 == 0;
   for (int64_t c = c_lo + (int64_t)r * wpb + wave; c < c_hi; c += (int64_t)nbx * wpb) {
     const int64_t q = c * 64 + lane;
     const bool valid = q < m;
     const float4 rr = rec[valid ? q : m - 1];
     const float px = clamp01(rr.x), py = clamp01(rr.y), pz = clamp01(rr.z);
     if (write_idx && valid) idx[q] = __float_as_uint(rr.w);
-    for (int i = 0; i < nlv; ++i) {
-      const int l = sa.lv[x][i];
-      Corners cr;
-      level_corners(md.lv[l], px, py, pz, cr);
-      float acc[F];
-      gather_level<F>(cr, table, (uint32_t)(md.n_table / F), acc);
-      LevelPack<F, OT> pk;
+    OT* dst = planes + plane_elem(q, l0, F, gw, m);
+    if (nl == 2 && gw == 2) {
+      LevelPack<F, OT, 2> pk;
 #pragma unroll
-      for (int f = 0; f < F; ++f) pk.v[f] = (OT)acc[f];
-      if (valid) *reinterpret_cast<LevelPack<F, OT>*>(planes + ((int64_t)l * m + q) * F) = pk;
+      for (int i = 0; i < 2; ++i) {
+        Corners cr;
+        level_corners(md.lv[l0 + 8 * i], px, py, pz, cr);
+        float acc[F];
+        gather_level<F>(cr, table, n_ent, acc);
+#pragma unroll
+        for (int f = 0; f < F; ++f) pk.v[i * F + f] = (OT)acc[f];
+      }
+      if (valid) *reinterpret_cast<LevelPack<F, OT, 2>*>(dst) = pk;
+    } else {
+      for (int i = 0; i < nl; ++i) {
+        Corners cr;
+        level_corners(md.lv[l0 + 8 * i], px, py, pz, cr);
+        float acc[F];
+        gather_level<F>(cr, table, n_ent, acc);
+        LevelPack<F, OT, 1> pk;
+#pragma unroll
+        for (int f = 0; f < F; ++f) pk.v[f] = (OT)acc[f];
+        if (valid) *reinterpret_cast<LevelPack<F, OT, 1>*>(dst + i * F) = pk;
+      }
     }
   }
 }
@@ -77,9 +103,9 @@ k_mlp_planes(ModelDesc md, const float* __restrict__ mlp, const OT* __restrict__
              const uint32_t* __restrict__ idx, int64_t m, float* __restrict__ out) {
   constexpr int NB = 2;
   constexpr int CH0 = InChunks<P, KIN>::n;
-  constexpr int LPB = 8 / F;                            // levels per 8-feature block
-  constexpr int LB = F * (int)sizeof(OT);               // bytes of one level's features
-  constexpr int DW = 8 * (int)sizeof(OT) / 4;           // dwords of one block
+  constexpr int LPB = 8 / F;                   // levels per 8-feature block
+  constexpr int LB = F * (int)sizeof(OT);      // bytes of one level's features
+  constexpr int DW = 8 * (int)sizeof(OT) / 4;  // dwords of one block
   typedef typename Prec<P>::Frag Frag;
   typedef WeightLayout<P, KIN, W> WL;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -89,6 +115,7 @@ k_mlp_planes(ModelDesc md, const float* __restrict__ mlp, const OT* __restrict__
   __syncthreads();
   const int lane = threadIdx.x & 63, nl = lane & 15, g = lane >> 4;
   const int L = md.L;
+  const int gw = L >= 8 ? (L + 7) / 8 : 1;
   const int64_t n_groups = (m + 16 * NB - 1) / (16 * NB);
   TileIter it(n_groups);
   struct Raw {
@@ -110,13 +137,13 @@ k_mlp_planes(ModelDesc md, const float* __restrict__ mlp, const OT* __restrict__
               const int l = (32 * b + 8 * g) / F + q;
               Bytes<LB> v;
               if (l < L) {
-                v = *reinterpret_cast<const Bytes<LB>*>(planes + ((int64_t)l * m + s) * F);
+                v = *reinterpret_cast<const Bytes<LB>*>(planes + plane_elem(s, l, F, gw, m));
               } else {
 #pragma unroll
-                for (int w = 0; w < LB / 4; ++w) v.w[w] = 0u;
+                for (int k = 0; k < LB / 4; ++k) v.w[k] = 0u;
               }
 #pragma unroll
-              for (int w = 0; w < LB / 4; ++w) r.d[nb][b][q * (LB / 4) + w] = v.w[w];
+              for (int k = 0; k < LB / 4; ++k) r.d[nb][b][q * (LB / 4) + k] = v.w[k];
             }
         }
       },
@@ -128,7 +155,7 @@ k_mlp_planes(ModelDesc md, const float* __restrict__ mlp, const OT* __restrict__
             if constexpr (P) {
               Bytes<16> t;
 #pragma unroll
-              for (int w = 0; w < 4; ++w) t.w[w] = r.d[nb][b][w];
+              for (int k = 0; k < 4; ++k) t.w[k] = r.d[nb][b][k];
               in[nb][b] = __builtin_bit_cast(Frag, t);
             } else {
 #pragma unroll
@@ -152,16 +179,19 @@ bool use_split(const ngvol_plan* plan, int64_t n) {
 SplitArgs split_args(const ngvol_plan* plan) {
   SplitArgs sa{};
   const int L = plan->md.L;
+  sa.width = L >= 8 ? (L + 7) / 8 : 1;
   for (int x = 0; x < 8; ++x) {
     if (L >= 8) {
-      for (int l = x; l < L; l += 8) sa.lv[x][sa.n_lv[x]++] = l;
+      // levels x, x+8, ... (the plane group x of plane_elem)
+      sa.first[x] = x;
+      sa.count[x] = (L - x + 7) / 8;
       sa.part[x] = 0;
       sa.parts[x] = 1;
     } else {
       // fewer levels than XCDs: a level's queries are shared by the XCDs holding it
       const int l = x % L;
-      sa.lv[x][0] = l;
-      sa.n_lv[x] = 1;
+      sa.first[x] = l;
+      sa.count[x] = 1;
       sa.part[x] = x / L;
       sa.parts[x] = (8 - l + L - 1) / L;
     }
@@ -171,13 +201,23 @@ SplitArgs split_args(const ngvol_plan* plan) {
 
 int split_operand_bytes(const ngvol_plan* plan) { return plan->layout.precision ? 2 : 4; }
 
+static int64_t plane_levels(const ngvol_plan* plan) {
+  // levels of plane storage per query: 8 groups of equal width (or L < 8 single levels)
+  const int L = plan->md.L;
+  return L >= 8 ? 8 * ((L + 7) / 8) : L;
+}
+
 int64_t split_slab(const ngvol_plan* plan, int64_t n) {
   // planes of at most 1 GiB (or 2^20 queries) per pass, in whole 64-query chunks
-  const int64_t per_query = (int64_t)plan->md.L * plan->md.F * split_operand_bytes(plan);
+  const int64_t per_query = plane_levels(plan) * plan->md.F * split_operand_bytes(plan);
   int64_t slab = ((int64_t)1 << 30) / per_query;
   if (slab < ((int64_t)1 << 20)) slab = (int64_t)1 << 20;
   slab &= ~(int64_t)63;
   return slab < n ? slab : n;
+}
+
+size_t split_planes_bytes(const ngvol_plan* plan, int64_t n) {
+  return (size_t)split_slab(plan, n) * plane_levels(plan) * plan->md.F * split_operand_bytes(plan);
 }
 
 hipError_t launch_infer_split(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const float4* rec, int64_t n,
@@ -193,8 +233,9 @@ hipError_t launch_infer_split(const ngvol_plan* plan, TablePtrs tp, const float*
     if (per_xcd > plan->cus) per_xcd = plan->cus;
     if (per_xcd < 1) per_xcd = 1;
     const dim3 lgrid((unsigned)(8 * per_xcd));
-    int64_t mgrid = (m + 127) / 128;  // 4 waves of 2-tile groups
+    int64_t mgrid = (m + 511) / 512;  // about 4 groups of 32 queries per wave
     if (mgrid > (int64_t)plan->cus * 8) mgrid = (int64_t)plan->cus * 8;
+    if (mgrid < 1) mgrid = 1;
     const float4* r = rec + s0;
     NGV_DISPATCH_P(plan->layout.precision, NGV_DISPATCH_F_KIN(md.F, plan->kin, NGV_DISPATCH_W(md.width, {
       typedef typename std::conditional<P == 0, float, typename Prec<P>::T>::type OT;

@@ -142,63 +142,88 @@ __device__ void stage_weights(const ModelDesc& md, const float* __restrict__ mlp
   typedef WeightLayout<P, KIN, W> WL;
   typedef typename Prec<P>::Frag Frag;
   constexpr int EPF = P ? 8 : 1;  // elements per fragment
+  constexpr int U = P ? 4 : 16;   // fragments per thread per round: their loads are in flight together
   const int nh = md.n_hidden;
   const int n_in = md.n_in;
   const int total = WL::frags(nh, bwd) * 64;
-  for (int t = threadIdx.x; t < total; t += blockDim.x) {
-    const int lane = t & 63;
-    int fr = t >> 6;
-    const int i = lane & 15, g = lane >> 4;
-    Frag val = Prec<P>::zero();
-    // which matrix
-    int li, mb, c;
-    bool trans = false;
-    const int fw = WL::FR0 + (nh - 1) * WL::FRH;
-    if (fr >= fw) {
-      trans = true;
-      fr -= fw;
-      if (fr < WL::FR0T) {
-        li = 0;
-        mb = fr / WL::CHH;
-        c = fr % WL::CHH;
-      } else {
-        fr -= WL::FR0T;
-        li = 1 + fr / WL::FRHT;
-        fr %= WL::FRHT;
-        mb = fr / WL::CHH;
-        c = fr % WL::CHH;
-      }
-    } else if (fr < WL::FR0) {
-      li = 0;
-      mb = fr / WL::CH0;
-      c = fr % WL::CH0;
-    } else {
-      fr -= WL::FR0;
-      li = 1 + fr / WL::FRH;
-      fr %= WL::FRH;
-      mb = fr / WL::CHH;
-      c = fr % WL::CHH;
-    }
-    const float* Wm = mlp + md.w_off[li];
-    const int in_dim = li == 0 ? n_in : W;
+  const int fw = WL::FR0 + (nh - 1) * WL::FRH;
+  for (int t0 = threadIdx.x; t0 < total; t0 += blockDim.x * U) {
+    float x[U][EPF];
 #pragma unroll
-    for (int jj = 0; jj < EPF; ++jj) {
-      float x = 0.0f;
-      if (!trans) {
-        // forward: A[row = 16mb + i][k] = W[row][col(k)]
-        const int row = 16 * mb + i;
-        const int col = li == 0 ? enc_col<P>(c, g, jj) : hid_col<P>(c, g, jj);
-        if (row < W && col < in_dim) x = Wm[row * in_dim + col];
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * (int)blockDim.x;
+      const int lane = t & 63;
+      int fr = t >> 6;
+      const int i = lane & 15, g = lane >> 4;
+      // which matrix
+      int li, mb, c;
+      bool trans = false;
+      if (fr >= fw) {
+        trans = true;
+        fr -= fw;
+        if (fr < WL::FR0T) {
+          li = 0;
+          mb = fr / WL::CHH;
+          c = fr % WL::CHH;
+        } else {
+          fr -= WL::FR0T;
+          li = 1 + fr / WL::FRHT;
+          fr %= WL::FRHT;
+          mb = fr / WL::CHH;
+          c = fr % WL::CHH;
+        }
+      } else if (fr < WL::FR0) {
+        li = 0;
+        mb = fr / WL::CH0;
+        c = fr % WL::CH0;
       } else {
-        // backward: A[row = 16mb + i][k] = W^T[row][col(k)] = W[col][row], contracting over W's rows
-        const int row = 16 * mb + i;  // input-side index
-        const int col = hid_col<P>(c, g, jj);
-        if (row < in_dim && col < W) x = Wm[col * in_dim + row];
+        fr -= WL::FR0;
+        li = 1 + fr / WL::FRH;
+        fr %= WL::FRH;
+        mb = fr / WL::CHH;
+        c = fr % WL::CHH;
       }
-      if constexpr (P) val[jj] = (typename Prec<P>::T)x;
-      else val = x;
+      const bool live = t < total;
+      if (!live) li = 0;
+      // matrix offset by selects over the (uniform) offsets, not an indexed load
+      int off = md.w_off[0];
+#pragma unroll
+      for (int q = 1; q < NGVOL_MAX_LAYERS; ++q) off = li == q ? md.w_off[q] : off;
+      const int in_dim = li == 0 ? n_in : W;
+#pragma unroll
+      for (int jj = 0; jj < EPF; ++jj) {
+        int idx = -1;
+        const int row = 16 * mb + i;
+        if (!trans) {
+          // forward: A[row = 16mb + i][k] = W[row][col(k)]
+          const int col = li == 0 ? enc_col<P>(c, g, jj) : hid_col<P>(c, g, jj);
+          if (row < W && col < in_dim) idx = row * in_dim + col;
+        } else {
+          // backward: A[row = 16mb + i][k] = W^T[row][col(k)] = W[col][row], contracting over W's rows
+          const int col = hid_col<P>(c, g, jj);
+          if (row < in_dim && col < W) idx = col * in_dim + row;
+        }
+        // every lane loads (an in-range element when its own is absent), so
+        // that the loads of the round are issued together; zeros are selected after
+        const bool use = live && idx >= 0;
+        x[u][jj] = mlp[use ? off + idx : 0];
+        if (!use) x[u][jj] = 0.0f;
+      }
     }
-    lds_frag[t] = val;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * (int)blockDim.x;
+      if (t < total) {
+        Frag val;
+        if constexpr (P) {
+#pragma unroll
+          for (int jj = 0; jj < EPF; ++jj) val[jj] = (typename Prec<P>::T)x[u][jj];
+        } else {
+          val = x[u][0];
+        }
+        lds_frag[t] = val;
+      }
+    }
   }
   const float* wo = mlp + md.w_off[nh];
   for (int t = threadIdx.x; t < W; t += blockDim.x) lds_wout[t] = wo[t];

@@ -349,6 +349,35 @@ def test_fused_train_step_gradient(name, prec, tol):
     assert host(st.loss)[0] == pytest.approx(loss_ref, rel=1e-4 if prec == "fp32" else 5e-2)
 
 
+@pytest.mark.parametrize("name,prec,tol,explicit", [("cfg1", "fp32", 1e-4, False), ("cfg1", "fp32", 1e-4, True),
+                                                    ("f4", "bf16", None, False), ("l4", "fp32", 1e-4, False)])
+def test_large_batch_f16_train_step_gradient(name, prec, tol, explicit):
+    # a batch above 2^16 samples on the FP16 table shadow, generated or explicit
+    m = oracle_model(name)
+    p = gpu_plan(name, prec)
+    params = init_params(name, table_scale=0.3)
+    vol = synth.gaussian_blobs(32, SEED)
+    B = (1 << 16) + 77
+    xyz = oracle.batch_coords(SEED, 4, B)
+    y = oracle.sample_volume(vol, xyz)
+    st = ngv.TrainState(p, dev(params), B, f16_tables=True)
+    # the forward reads the FP16 shadow of the tables
+    q = params.astype(np.float64)
+    q[:m.n_table] = host(st.table_f16).astype(np.float64)
+    _, g_ref = oracle.loss_grad(m, q, xyz, y)
+    kw = dict(xyz=dev(xyz), target=dev(y.astype(np.float32))) if explicit else dict(volume=dev(vol), seed=SEED,
+                                                                                     step_index=4)
+    ngv.train_step(st, lr=1e-2, betas=(0.9, 0.99), eps=1e-15, loss_scale=128.0, **kw)
+    g = host(st.m).astype(np.float64) / (1 - np.float32(0.9))
+    if tol is None:
+        _check_grad_bf16(g, g_ref, m)
+    else:
+        _check_grad(g, g_ref, m, tol)
+    assert host(st.step)[0] == 1 and host(st.skipped)[0] == 0
+    loss_ref = float(np.mean((oracle.forward(m, q, xyz) - y) ** 2))
+    assert host(st.loss)[0] == pytest.approx(loss_ref, rel=1e-4 if prec == "fp32" else 5e-2)
+
+
 def test_nonfinite_step_is_skipped():
     p = gpu_plan("tiny", "fp32")
     params = init_params("tiny")
@@ -539,7 +568,7 @@ def test_multi_infer_equals_single_launches():
     assert rel_err(host(outs[3]), oracle.forward(m, q, host(xyz[3]))) <= 2e-2
     # the autotuned launch shape gives the same values
     b, c = grp.autotune(list(zip(params, f16)), xyz, outs)
-    assert b in (2, 4, 8, 16) and c in (8, 32, 128)
+    assert b in (2, 4, 8, 16) and c in (16, 64, 256)
     outs2 = grp.infer(list(zip(params, f16)), xyz)
     for i in range(16):
         np.testing.assert_array_equal(host(outs2[i]), host(outs[i]))
