@@ -54,10 +54,14 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "query_pass_cfg1_2p24_counters.md"
 CSRC = os.path.join(ROOT, "paper_2207_11620_amd", "csrc")
 
 
+# the sources the query pass's kernels are built from
+QUERY_SOURCES = ("kernels_split.hip", "mlp_tile.hpp", "device_common.hpp", "kernels.hpp", "dispatch.hpp", "plan.hpp")
+
+
 def csrc_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(os.listdir(CSRC)):
+    for f in QUERY_SOURCES:
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()[:16]

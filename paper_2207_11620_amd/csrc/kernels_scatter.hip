@@ -198,13 +198,23 @@ __global__ void __launch_bounds__(kReduceThreads) k_sc_reduce(const uint4* __res
   const bool owner = cnt <= chunk_records;  // the bucket fits one chunk: this workgroup owns its entries
   const int64_t first = (int64_t)base_entry * F;
   const int64_t last = n_entries * F;
-  for (int t = threadIdx.x; t < span; t += blockDim.x) {
-    const int64_t gi = first + t;
-    if (gi >= last) break;
-    const float v = acc[t];
-    if (v == 0.0f) continue;
-    if (owner) grad[gi] += v;
-    else atomicAdd(grad + gi, v);
+  constexpr int U = 8;  // entries per thread per round; the owner's gradient loads are issued together
+  for (int t0 = threadIdx.x; t0 < span; t0 += blockDim.x * U) {
+    float a[U], old[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * (int)blockDim.x;
+      const bool in = t < span && first + t < last;
+      a[u] = in ? acc[t] : 0.0f;
+      old[u] = (owner && in) ? grad[first + t] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * (int)blockDim.x;
+      if (a[u] == 0.0f) continue;  // also every entry outside the table
+      if (owner) grad[first + t] = old[u] + a[u];
+      else atomicAdd(grad + first + t, a[u]);
+    }
   }
 }
 
