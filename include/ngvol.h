@@ -83,7 +83,9 @@ typedef struct ngvol_plan ngvol_plan;
  * n_levels * n_features <= 64; 1 <= log2_hashmap_size <= 28;
  * n_neurons in {32,64}; 1 <= n_hidden_layers <= 8; the weights of a
  * forward must fit in LDS and the backward (ngvol_mlp_bwd,
- * ngvol_train_step) needs W, W^T and dW in LDS (else NGVOL_EUNSUPPORTED).
+ * ngvol_train_step) needs W, W^T and dW in LDS (else NGVOL_EUNSUPPORTED);
+ * the tables hold at most 2^30 - 4 floats (4 GiB of FP32, else
+ * NGVOL_EUNSUPPORTED).
  * Vertices per axis: resolutions[l] if given; else N_l = base * b^l, used as
  * is when it is an integer (within 1e-9 relative) and rounded up otherwise,
  * with b = per_level_scale, or b = exp((ln max_resolution - ln base)/(L-1))

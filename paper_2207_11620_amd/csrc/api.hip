@@ -176,9 +176,9 @@ int ngvol_plan_create(const ngvol_config* c, ngvol_plan** out) {
     off += entries;
   }
   L.level_offset[md.L] = off;
-  if (off * md.F > ((int64_t)1 << 31)) {
+  if (off * md.F > ((int64_t)1 << 30) - 4) {  // table byte offsets stay 32-bit
     delete p;
-    return fail(NGVOL_EUNSUPPORTED, "tables of %lld entries exceed 2^31 floats", (long long)off);
+    return fail(NGVOL_EUNSUPPORTED, "tables of %lld entries exceed 2^30 - 4 floats (4 GiB)", (long long)off);
   }
   md.n_table = L.n_table_params = off * md.F;
   int64_t pos = 0;

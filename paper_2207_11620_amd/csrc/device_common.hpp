@@ -77,12 +77,36 @@ __device__ __forceinline__ void level_corners(const LevelDesc& lv, float x, floa
   level_axis(y, s, cmax, cy, wy);
   level_axis(z, s, cmax, cz, wz);
   const float ox = 1.0f - wx, oy = 1.0f - wy, oz = 1.0f - wz;
+  // the slots of the 8 corners differ from the first by constants (dense) or
+  // by the hash terms of y+1 and z+1, (v+1)*p = v*p + p (mod 2^32)
+  if (lv.dense) {
+    const uint32_t N = (uint32_t)lv.N, NN = N * N;
+    const uint32_t b = lv.offset + (uint32_t)cx + N * ((uint32_t)cy + N * (uint32_t)cz);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) cr.slot[k] = b + (k & 1) + ((k >> 1) & 1) * N + ((k >> 2) & 1) * NN;
+  } else {
+    const uint32_t hy0 = (uint32_t)cy * 2654435761u, hz0 = (uint32_t)cz * 805459861u;
+    const uint32_t hy1 = hy0 + 2654435761u, hz1 = hz0 + 805459861u;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const uint32_t vx = (uint32_t)cx + (k & 1);
+      const uint32_t hy = (k & 2) ? hy1 : hy0, hz = (k & 4) ? hz1 : hz0;
+      cr.slot[k] = lv.offset + ((vx ^ hy ^ hz) & lv.mask);
+    }
+  }
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const int dx = k & 1, dy = (k >> 1) & 1, dz = (k >> 2) & 1;
-    cr.slot[k] = lv.offset + level_slot(lv, (uint32_t)(cx + dx), (uint32_t)(cy + dy), (uint32_t)(cz + dz));
     cr.w[k] = ((dx ? wx : ox) * (dy ? wy : oy)) * (dz ? wz : oz);
   }
+}
+
+// Element at a 32-bit byte offset from a table base (tables are below 4 GB):
+// the load takes the base in scalar registers and the offset in one vector
+// register.
+template <typename T>
+__device__ __forceinline__ T load_at(const void* base, uint32_t off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
 }
 
 // Raw table entries: F features of type TT, ED dwords.
@@ -107,18 +131,18 @@ __device__ __forceinline__ void entry_values(const uint32_t* d, float v[F]) {
 }
 
 template <int ED>
-__device__ __forceinline__ void load_entry(const uint32_t* __restrict__ base, uint32_t slot, uint32_t d[ED]) {
-  const uint32_t* e = base + (size_t)slot * ED;
+__device__ __forceinline__ void load_entry(const void* __restrict__ base, uint32_t slot, uint32_t d[ED]) {
+  const uint32_t off = slot * (uint32_t)(ED * 4);
   if constexpr (ED == 1) {
-    d[0] = e[0];
+    d[0] = load_at<uint32_t>(base, off);
   } else if constexpr (ED == 2) {
-    const uint2 t = *reinterpret_cast<const uint2*>(e);
+    const uint2 t = load_at<uint2>(base, off);
     d[0] = t.x;
     d[1] = t.y;
   } else {
 #pragma unroll
     for (int q = 0; q < ED; q += 4) {
-      const uint4 t = *reinterpret_cast<const uint4*>(e + q);
+      const uint4 t = load_at<uint4>(base, off + 4 * q);
       d[q] = t.x;
       d[q + 1] = t.y;
       d[q + 2] = t.z;
@@ -142,7 +166,7 @@ template <int F, typename TT>
 __device__ __forceinline__ void gather_level(const Corners& cr, const TT* __restrict__ table, uint32_t n_ent,
                                              float acc[F]) {
   constexpr int ED = Entry<F, TT>::ED;
-  const uint32_t* base = reinterpret_cast<const uint32_t*>(table);
+  const void* base = table;
   float v[8][F];
   bool plain = true;
   if constexpr (ED <= 2) {
@@ -153,15 +177,18 @@ __device__ __forceinline__ void gather_level(const Corners& cr, const TT* __rest
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       b0[p] = cr.slot[2 * p] & ~(E - 1);
-      same[p] = (cr.slot[2 * p + 1] & ~(E - 1)) == b0[p];
-      inside = inside && b0[p] + E <= n_ent;
+      same[p] = ((cr.slot[2 * p + 1] ^ cr.slot[2 * p]) & ~(E - 1)) == 0u;
+    }
+    if ((n_ent & (E - 1)) != 0) {  // only then can a block reach past the table's end
+#pragma unroll
+      for (int p = 0; p < 4; ++p) inside = inside && b0[p] + E <= n_ent;
     }
     if (__all(inside)) {
       plain = false;
       uint4 blk[4];
       uint32_t d1[4][ED];
 #pragma unroll
-      for (int p = 0; p < 4; ++p) blk[p] = *reinterpret_cast<const uint4*>(base + (size_t)b0[p] * ED);
+      for (int p = 0; p < 4; ++p) blk[p] = load_at<uint4>(base, b0[p] * (uint32_t)(ED * 4));
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
         if (!same[p]) {
@@ -173,20 +200,20 @@ __device__ __forceinline__ void gather_level(const Corners& cr, const TT* __rest
       }
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
-        const uint32_t w4[4] = {blk[p].x, blk[p].y, blk[p].z, blk[p].w};
+        // words of the block by two bit tests of the entry's position (no
+        // indexing, no branches)
         const uint32_t j0 = (cr.slot[2 * p] - b0[p]) * ED, j1 = (cr.slot[2 * p + 1] - b0[p]) * ED;
         uint32_t d0[ED], dd[ED];
-#pragma unroll
-        for (int q = 0; q < ED; ++q) {
-          // select word j of the block without indexing (no scratch, no branches)
-          uint32_t x0 = w4[0], x1 = w4[0];
-#pragma unroll
-          for (int i = 1; i < 4; ++i) {
-            x0 = (j0 + q == (uint32_t)i) ? w4[i] : x0;
-            x1 = (j1 + q == (uint32_t)i) ? w4[i] : x1;
-          }
-          d0[q] = x0;
-          dd[q] = same[p] ? x1 : d1[p][q];
+        if constexpr (ED == 1) {
+          const uint32_t l0 = (j0 & 1) ? blk[p].y : blk[p].x, h0 = (j0 & 1) ? blk[p].w : blk[p].z;
+          const uint32_t l1 = (j1 & 1) ? blk[p].y : blk[p].x, h1 = (j1 & 1) ? blk[p].w : blk[p].z;
+          d0[0] = (j0 & 2) ? h0 : l0;
+          dd[0] = same[p] ? ((j1 & 2) ? h1 : l1) : d1[p][0];
+        } else {
+          d0[0] = j0 ? blk[p].z : blk[p].x;
+          d0[1] = j0 ? blk[p].w : blk[p].y;
+          dd[0] = same[p] ? (j1 ? blk[p].z : blk[p].x) : d1[p][0];
+          dd[1] = same[p] ? (j1 ? blk[p].w : blk[p].y) : d1[p][1];
         }
         entry_values<F, TT>(d0, v[2 * p]);
         entry_values<F, TT>(dd, v[2 * p + 1]);

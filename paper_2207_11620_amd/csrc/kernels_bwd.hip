@@ -163,7 +163,7 @@ __global__ void __launch_bounds__(64 * kBwdMaxWaves) k_bwd(ModelDesc md, const f
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const float zz = act[mb][j];
-        const float h = fmaxf(zz, 0.0f);
+        const float h = relu_bits(zz);
         dwo[mb][j] = __builtin_fmaf(gv, h, dwo[mb][j]);
         dz[mb][j] = zz > 0.0f ? lds_wout[16 * mb + 4 * g + j] * gv : 0.0f;
       }
@@ -182,7 +182,7 @@ __global__ void __launch_bounds__(64 * kBwdMaxWaves) k_bwd(ModelDesc md, const f
         for (int mb = 0; mb < MB; ++mb) {
           const f32x4 zp = zbuf[((li - 1) * MB + mb) * 64 + lane];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) aT[(16 * mb + 4 * g + j) * kPitch + nl] = (T)fmaxf(zp[j], 0.0f);
+          for (int j = 0; j < 4; ++j) aT[(16 * mb + 4 * g + j) * kPitch + nl] = (T)relu_bits(zp[j]);
         }
       } else {
 #pragma unroll

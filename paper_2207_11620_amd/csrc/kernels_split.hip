@@ -16,9 +16,12 @@
 //      cache line shared with another XCD's writes;
 //   2. k_mlp_planes: the network on the planes, with the next tiles' features
 //      loaded while the current ones are evaluated; each result goes to the
-//      query's original slot.
+//      query's original slot.  Its first-layer operands take the features in
+//      plane order (the columns of W0 are permuted to match when staged), so
+//      a lane reads its 8 features as whole group entries.
 // Features are converted to the operand type exactly as in the fused
-// kernel, so both paths give bitwise the same outputs.
+// kernel; the products of the first layer are summed in another order, so
+// outputs agree with the fused kernel to FP32 rounding, not bitwise.
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -83,45 +86,74 @@ __global__ void __launch_bounds__(256) k_level_feat(ModelDesc md, const TT* __re
       }
       if (valid) *reinterpret_cast<LevelPack<F, OT, 2>*>(dst) = pk;
     } else {
-      for (int i = 0; i < nl; ++i) {
-        Corners cr;
-        level_corners(md.lv[l0 + 8 * i], px, py, pz, cr);
-        float acc[F];
-        gather_level<F>(cr, table, n_ent, acc);
+      for (int i = 0; i < gw; ++i) {
         LevelPack<F, OT, 1> pk;
+        if (i < nl) {
+          Corners cr;
+          level_corners(md.lv[l0 + 8 * i], px, py, pz, cr);
+          float acc[F];
+          gather_level<F>(cr, table, n_ent, acc);
 #pragma unroll
-        for (int f = 0; f < F; ++f) pk.v[f] = (OT)acc[f];
+          for (int f = 0; f < F; ++f) pk.v[f] = (OT)acc[f];
+        } else {
+#pragma unroll
+          for (int f = 0; f < F; ++f) pk.v[f] = (OT)0.0f;  // padding slot of a short group
+        }
         if (valid) *reinterpret_cast<LevelPack<F, OT, 1>*>(dst + i * F) = pk;
       }
     }
   }
 }
 
-template <int P, int F, int KIN, int W, typename OT>
+// Plane order of the features: entry e = gw*F features of plane group x
+// (levels x, x+8, ... for L >= 8; level x for L < 8), feature p = x*E + i*F + f.
+struct PlaneOrder {
+  int8_t col[64];  // input feature of plane-order position p (-1: none)
+};
+
+// EC: entry class of the planes, 0 for entries of 8 or more features, else
+// the entry size (4 or 2 features); FULL: the planes hold all KIN features
+// (no zero padding to supply).
+template <int P, int F, int KIN, int W, typename OT, int EC, bool FULL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P != 0 && KIN == 32 ? 4 : 1)))
 k_mlp_planes(ModelDesc md, const float* __restrict__ mlp, const OT* __restrict__ planes,
-             const uint32_t* __restrict__ idx, int64_t m, float* __restrict__ out) {
+             const uint32_t* __restrict__ idx, int64_t m, float* __restrict__ out, PlaneOrder po, int E,
+             int n_plane_feat) {
   constexpr int NB = 2;
   constexpr int CH0 = InChunks<P, KIN>::n;
-  constexpr int LPB = 8 / F;                   // levels per 8-feature block
-  constexpr int LB = F * (int)sizeof(OT);      // bytes of one level's features
-  constexpr int DW = 8 * (int)sizeof(OT) / 4;  // dwords of one block
+  constexpr int DW = 8 * (int)sizeof(OT) / 4;  // dwords of one 8-feature block
   typedef typename Prec<P>::Frag Frag;
   typedef WeightLayout<P, KIN, W> WL;
   extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int8_t colmap[64];
+  if (threadIdx.x < 64) colmap[threadIdx.x] = po.col[threadIdx.x];
+  __syncthreads();
   Frag* lds_frag = reinterpret_cast<Frag*>(smem);
   float* lds_wout = reinterpret_cast<float*>(smem + (size_t)WL::frags(md.n_hidden, false) * 64 * sizeof(Frag));
-  stage_weights<P, KIN, W>(md, mlp, lds_frag, lds_wout, false);
+  stage_weights<P, KIN, W>(md, mlp, lds_frag, lds_wout, false, colmap);
   __syncthreads();
   const int lane = threadIdx.x & 63, nl = lane & 15, g = lane >> 4;
-  const int L = md.L;
-  const int gw = L >= 8 ? (L + 7) / 8 : 1;
   const int64_t n_groups = (m + 16 * NB - 1) / (16 * NB);
   TileIter it(n_groups);
   struct Raw {
     uint32_t d[NB][KIN / 32][DW];
     uint32_t slot[NB];
   };
+  // DWS-dword load (1, 2 or 4) at element offset o of the planes
+  auto load1 = [&](int64_t o, uint32_t* w) { w[0] = *reinterpret_cast<const uint32_t*>(planes + o); };
+  auto load2 = [&](int64_t o, uint32_t* w) {
+    const uint2 t = *reinterpret_cast<const uint2*>(planes + o);
+    w[0] = t.x;
+    w[1] = t.y;
+  };
+  auto load4 = [&](int64_t o, uint32_t* w) {
+    const uint4 t = *reinterpret_cast<const uint4*>(planes + o);
+    w[0] = t.x;
+    w[1] = t.y;
+    w[2] = t.z;
+    w[3] = t.w;
+  };
+  constexpr int EPD = 4 / (int)sizeof(OT);  // elements per dword
   mlp_stream<P, KIN, W, NB, Raw>(
       md.n_hidden, lds_frag, lds_wout, it.next, it.step, it.end,
       [&](int64_t grp, Raw& r) {
@@ -131,20 +163,44 @@ k_mlp_planes(ModelDesc md, const float* __restrict__ mlp, const OT* __restrict__
           s = s < m ? s : m - 1;
           r.slot[nb] = idx[s];
 #pragma unroll
-          for (int b = 0; b < KIN / 32; ++b)
+          for (int b = 0; b < KIN / 32; ++b) {
+            uint32_t* d = r.d[nb][b];
+            const int p0 = 32 * b + 8 * g;  // this lane's plane-order features p0 .. p0+7
+            if constexpr (!FULL) {
 #pragma unroll
-            for (int q = 0; q < LPB; ++q) {
-              const int l = (32 * b + 8 * g) / F + q;
-              Bytes<LB> v;
-              if (l < L) {
-                v = *reinterpret_cast<const Bytes<LB>*>(planes + plane_elem(s, l, F, gw, m));
-              } else {
-#pragma unroll
-                for (int k = 0; k < LB / 4; ++k) v.w[k] = 0u;
-              }
-#pragma unroll
-              for (int k = 0; k < LB / 4; ++k) r.d[nb][b][q * (LB / 4) + k] = v.w[k];
+              for (int k = 0; k < DW; ++k) d[k] = 0u;
             }
+            if constexpr (EC == 0) {
+              // the block lies inside entry p0 / E
+              if (FULL || p0 < n_plane_feat) {
+                const int64_t o = ((int64_t)(p0 / E) * m + s) * E + p0 % E;
+#pragma unroll
+                for (int k = 0; k < DW; k += 4) load4(o + k * EPD, d + k);
+              }
+            } else if constexpr (EC == 4) {
+              // two entries of 4 features
+#pragma unroll
+              for (int j = 0; j < 2; ++j) {
+                const int p = p0 + 4 * j;
+                if (FULL || p < n_plane_feat) {
+                  const int64_t o = ((int64_t)(p / 4) * m + s) * 4;
+                  if constexpr (EPD == 2) load2(o, d + 2 * j);
+                  else load4(o, d + 4 * j);
+                }
+              }
+            } else {
+              // four entries of 2 features (EC == 2)
+#pragma unroll
+              for (int j = 0; j < 4; ++j) {
+                const int p = p0 + 2 * j;
+                if (FULL || p < n_plane_feat) {
+                  const int64_t o = ((int64_t)(p / 2) * m + s) * 2;
+                  if constexpr (EPD == 2) load1(o, d + j);
+                  else load2(o, d + 2 * j);
+                }
+              }
+            }
+          }
         }
       },
       [&](const Raw& r, Frag (*in)[CH0]) {
@@ -226,6 +282,23 @@ hipError_t launch_infer_split(const ngvol_plan* plan, TablePtrs tp, const float*
   const SplitArgs sa = split_args(plan);
   const int64_t slab = split_slab(plan, n);
   const size_t lds = fwd_lds_bytes(plan);
+  // plane order of the MLP's input columns
+  const int L = md.L, F_ = md.F;
+  const int E = sa.width * F_;
+  const int n_plane_feat = (L >= 8 ? 8 : L) * E;
+  PlaneOrder po;
+  for (int p = 0; p < 64; ++p) {
+    int col = -1;
+    if (p < n_plane_feat) {
+      const int x = p / E, i = (p % E) / F_, f = p % F_;
+      const int l = L >= 8 ? x + 8 * i : x;
+      if (l < L) col = l * F_ + f;
+    }
+    po.col[p] = (int8_t)col;
+  }
+#define NGV_MP(EC, FULL)                                                                                        \
+  hipLaunchKernelGGL((k_mlp_planes<P, F, KIN, W, OT, EC, FULL>), dim3((unsigned)mgrid), dim3(256), lds, st, md, mlp, \
+                     pl, idx, m, out, po, E, n_plane_feat)
   for (int64_t s0 = 0; s0 < n; s0 += slab) {
     const int64_t m = n - s0 < slab ? n - s0 : slab;
     const int64_t chunks = (m + 63) / 64;
@@ -244,12 +317,22 @@ hipError_t launch_infer_split(const ngvol_plan* plan, TablePtrs tp, const float*
         hipLaunchKernelGGL((k_level_feat<F, __half, OT>), lgrid, dim3(256), 0, st, md, tp.f16, r, m, pl, idx, sa);
       else
         hipLaunchKernelGGL((k_level_feat<F, float, OT>), lgrid, dim3(256), 0, st, md, tp.f32, r, m, pl, idx, sa);
-      hipLaunchKernelGGL((k_mlp_planes<P, F, KIN, W, OT>), dim3((unsigned)mgrid), dim3(256), lds, st, md, mlp, pl,
-                         idx, m, out);
+      const bool full = n_plane_feat >= KIN;
+      if (E >= 8) {
+        if (full) NGV_MP(0, true);
+        else NGV_MP(0, false);
+      } else if (E == 4) {
+        if (full) NGV_MP(4, true);
+        else NGV_MP(4, false);
+      } else {
+        if (full) NGV_MP(2, true);
+        else NGV_MP(2, false);
+      }
     })));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
+#undef NGV_MP
   return hipSuccess;
 }
 

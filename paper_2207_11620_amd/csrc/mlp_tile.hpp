@@ -136,9 +136,11 @@ struct WeightLayout {
 
 // Stage W0..W_{h-1} (and, for the backward, their transposes) into LDS in
 // fragment order, plus W_out in FP32.  Called by the whole workgroup.
+// colmap (optional, LDS): input feature of each first-layer operand column
+// (-1: none), for kernels whose encoded inputs arrive in another order.
 template <int P, int KIN, int W>
 __device__ void stage_weights(const ModelDesc& md, const float* __restrict__ mlp, typename Prec<P>::Frag* lds_frag,
-                              float* lds_wout, bool bwd) {
+                              float* lds_wout, bool bwd, const int8_t* colmap = nullptr) {
   typedef WeightLayout<P, KIN, W> WL;
   typedef typename Prec<P>::Frag Frag;
   constexpr int EPF = P ? 8 : 1;  // elements per fragment
@@ -196,8 +198,9 @@ __device__ void stage_weights(const ModelDesc& md, const float* __restrict__ mlp
         const int row = 16 * mb + i;
         if (!trans) {
           // forward: A[row = 16mb + i][k] = W[row][col(k)]
-          const int col = li == 0 ? enc_col<P>(c, g, jj) : hid_col<P>(c, g, jj);
-          if (row < W && col < in_dim) idx = row * in_dim + col;
+          int col = li == 0 ? enc_col<P>(c, g, jj) : hid_col<P>(c, g, jj);
+          if (li == 0 && colmap) col = col < KIN ? colmap[col] : -1;
+          if (row < W && col >= 0 && col < in_dim) idx = row * in_dim + col;
         } else {
           // backward: A[row = 16mb + i][k] = W^T[row][col(k)] = W[col][row], contracting over W's rows
           const int col = hid_col<P>(c, g, jj);
@@ -235,6 +238,14 @@ __device__ void stage_weights(const ModelDesc& md, const float* __restrict__ mlp
 //   z[li][mb]    : pre-activations kept for the backward (optional)
 //   returns the last hidden activation in act[mb] (FP32, accumulator layout)
 // ---------------------------------------------------------------------------
+// ReLU on the bit pattern: a float with the sign bit set is a negative
+// integer, so max(bits, 0) is max(x, 0) in one integer instruction (the float
+// max would first quiet its matrix-core input).  A NaN with the sign bit set
+// becomes 0.
+__device__ __forceinline__ float relu_bits(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+
+typedef short short8 __attribute__((ext_vector_type(8)));
+
 template <int P, int W>
 __device__ __forceinline__ void pack_hidden(const f32x4 act[W / 16], typename Prec<P>::Frag out[HidChunks<P, W>::n],
                                             bool relu) {
@@ -245,14 +256,19 @@ __device__ __forceinline__ void pack_hidden(const f32x4 act[W / 16], typename Pr
 #pragma unroll
       for (int jj = 0; jj < 8; ++jj) {
         const int m = 2 * c + (jj >> 2);
-        float v = (m < W / 16) ? act[m < W / 16 ? m : 0][jj & 3] : 0.0f;
-        if (relu) v = fmaxf(v, 0.0f);
+        const float v = (m < W / 16) ? act[m < W / 16 ? m : 0][jj & 3] : 0.0f;
         out[c][jj] = (typename Prec<P>::T)v;
       }
+      if (relu) {
+        // on the 16-bit values, two per instruction: rounding then clamping
+        // at zero equals clamping then rounding
+        short8 h = __builtin_bit_cast(short8, out[c]);
+        h = __builtin_elementwise_max(h, (short8)0);
+        out[c] = __builtin_bit_cast(typename Prec<P>::Frag, h);
+      }
     } else {
-      float v = act[c >> 2][c & 3];
-      if (relu) v = fmaxf(v, 0.0f);
-      out[c] = v;
+      const float v = act[c >> 2][c & 3];
+      out[c] = relu ? relu_bits(v) : v;
     }
   }
 }
@@ -350,7 +366,7 @@ __device__ __forceinline__ float mlp_output(const f32x4 zlast[W / 16], const flo
 #pragma unroll
   for (int mb = 0; mb < W / 16; ++mb)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) s = __builtin_fmaf(lds_wout[16 * mb + 4 * g + j], fmaxf(zlast[mb][j], 0.0f), s);
+    for (int j = 0; j < 4; ++j) s = __builtin_fmaf(lds_wout[16 * mb + 4 * g + j], relu_bits(zlast[mb][j]), s);
   s += __shfl_xor(s, 16, 64);
   s += __shfl_xor(s, 32, 64);
   return s;

@@ -178,7 +178,10 @@ def test_binned_infer_equals_direct():
 def test_level_split_equals_fused(name, prec, f16):
     # above 2^20 queries with FP16 tables larger than one L2 the grouped query
     # runs level group by level group (one group per XCD) and the MLP on
-    # feature planes; it must give bitwise the outputs of the fused kernel
+    # feature planes, whose first layer sums its products in plane order:
+    # FP32 agrees with the fused kernel to rounding; 16-bit operands can flip
+    # a rounding of a hidden activation, so they meet the 16-bit bar.  With
+    # FP32 tables the grouped query stays fused and is bitwise the same.
     m = oracle_model(name)
     p = gpu_plan(name, prec)
     params = init_params(name, table_scale=0.5)
@@ -188,15 +191,17 @@ def test_level_split_equals_fused(name, prec, f16):
     tf = ngv.make_f16_tables(p, pt) if f16 else None
     a = host(ngv.infer(p, pt, xt, table_f16=tf, sort=False))
     b = host(ngv.infer(p, pt, xt, table_f16=tf, sort=True))
-    np.testing.assert_array_equal(a, b)
-    if prec == "fp32":
-        # the oracle on the tables the kernels read (FP16-rounded when used)
-        q = params.astype(np.float64)
-        if f16:
-            q[:m.n_table] = host(tf).astype(np.float64)
-        idx = np.r_[np.arange(8), np.linspace(8, n - 1, 1500).astype(np.int64)]
-        ref = oracle.forward(m, q, xyz[idx])
-        assert rel_err(b[idx], ref) <= 1e-5
+    if not f16:
+        np.testing.assert_array_equal(a, b)
+    else:
+        assert rel_err(b, a) <= (1e-6 if prec == "fp32" else 2e-2)
+    # the oracle on the tables the kernels read (FP16-rounded when used)
+    q = params.astype(np.float64)
+    if f16:
+        q[:m.n_table] = host(tf).astype(np.float64)
+    idx = np.r_[np.arange(8), np.linspace(8, n - 1, 1500).astype(np.int64)]
+    ref = oracle.forward(m, q, xyz[idx])
+    assert rel_err(b[idx], ref) <= (1e-5 if prec == "fp32" else 2e-2)
 
 
 def _morton(q, bits):
