@@ -40,7 +40,7 @@ struct BatchArgs {
 // of the sorted coordinates, the per-sample auxiliary array (query
 // permutation or training targets) and the histogram buffers.
 struct BinPlan {
-  int k, n_bins, blocks;
+  int k, sb, n_bins, blocks;
   int64_t chunk;
   size_t rec_off, counts_off, totals_off, offsets_off, bytes;
   // level-split query (large query sets): feature planes and query slots

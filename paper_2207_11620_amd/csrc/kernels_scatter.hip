@@ -8,8 +8,8 @@
 // F features fill 32 KB of LDS:
 //   1. count: per-block LDS histograms of the bucket of every contribution;
 //   2. block prefix and scan of the counts (shared with the spatial sort);
-//   3. fill: each contribution is written as a record (entry, w*d[0..F-1])
-//      at its bucket's next position (LDS cursors);
+//   3. fill: each contribution is written as a packed record
+//      (entry, w*d[0..F-1]) at its bucket's next position (LDS cursors);
 //   4. reduce: one workgroup per (bucket, chunk of records) - a work list
 //      built on the device from the bucket sizes, so no workgroup is empty -
 //      accumulates the records in LDS and adds the bucket's entries into the
@@ -71,23 +71,51 @@ __global__ void __launch_bounds__(kScThreads) k_sc_count(ModelDesc md, Coords sr
   for (int b = threadIdx.x; b < nb; b += blockDim.x) dst[b] = hist[b];
 }
 
-// Record of one contribution: word 0 = entry index, words 1..F = values.
+// Record of one contribution: dword 0 = entry index, dwords 1..F = values,
+// packed (12 bytes for F = 2).
 template <int F>
 struct Rec {
-  static constexpr int words = (1 + F + 3) / 4;  // uint4 words
+  static constexpr int dwords = 1 + F;
 };
+
+struct alignas(4) Dw3 {
+  uint32_t x, y, z;
+};
+
+template <int N>
+__device__ __forceinline__ void store_dwords(uint32_t* __restrict__ dst, const uint32_t* w) {
+  if constexpr (N == 3) {
+    *reinterpret_cast<Dw3*>(dst) = Dw3{w[0], w[1], w[2]};
+  } else {
+#pragma unroll
+    for (int q = 0; q < N; ++q) dst[q] = w[q];
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void load_dwords(const uint32_t* __restrict__ src, uint32_t* w) {
+  if constexpr (N == 3) {
+    const Dw3 t = *reinterpret_cast<const Dw3*>(src);
+    w[0] = t.x;
+    w[1] = t.y;
+    w[2] = t.z;
+  } else {
+#pragma unroll
+    for (int q = 0; q < N; ++q) w[q] = src[q];
+  }
+}
 
 template <int F>
 __global__ void __launch_bounds__(kScThreads) k_sc_fill(ModelDesc md, Coords src, int64_t B, int64_t chunk, int bshift,
                                                         int nb, const uint32_t* __restrict__ counts,
                                                         const uint32_t* __restrict__ offsets,
-                                                        const float* __restrict__ dfeat, uint4* __restrict__ rec) {
+                                                        const float* __restrict__ dfeat, uint32_t* __restrict__ rec) {
   extern __shared__ uint32_t cur[];
   src.resolve();
   const uint32_t* mine = counts + (size_t)blockIdx.x * nb;
   for (int b = threadIdx.x; b < nb; b += blockDim.x) cur[b] = offsets[b] + mine[b];
   __syncthreads();
-  constexpr int RW = Rec<F>::words;
+  constexpr int RD = Rec<F>::dwords;
   const int64_t lo = (int64_t)blockIdx.x * chunk;
   const int64_t hi = lo + chunk < B ? lo + chunk : B;
   for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
@@ -103,15 +131,11 @@ __global__ void __launch_bounds__(kScThreads) k_sc_fill(ModelDesc md, Coords src
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
         const uint32_t pos = atomicAdd(cur + (cr.slot[k] >> bshift), 1u);
-        uint32_t w[RW * 4];
+        uint32_t w[RD];
         w[0] = cr.slot[k];
 #pragma unroll
         for (int f = 0; f < F; ++f) w[1 + f] = __float_as_uint(cr.w[k] * dv[f]);
-#pragma unroll
-        for (int q = 1 + F; q < RW * 4; ++q) w[q] = 0u;
-        uint4* dst = rec + (size_t)pos * RW;
-#pragma unroll
-        for (int q = 0; q < RW; ++q) dst[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+        store_dwords<RD>(rec + (size_t)pos * RD, w);
       }
     }
   }
@@ -149,7 +173,7 @@ __global__ void __launch_bounds__(1024) k_sc_worklist(const uint32_t* __restrict
 }
 
 template <int F>
-__global__ void __launch_bounds__(kReduceThreads) k_sc_reduce(const uint4* __restrict__ rec,
+__global__ void __launch_bounds__(kReduceThreads) k_sc_reduce(const uint32_t* __restrict__ rec,
                                                               const uint32_t* __restrict__ totals,
                                                               const uint32_t* __restrict__ offsets,
                                                               const uint32_t* __restrict__ items, int bshift,
@@ -164,24 +188,22 @@ __global__ void __launch_bounds__(kReduceThreads) k_sc_reduce(const uint4* __res
   const int span = (1 << bshift) * F;
   for (int t = threadIdx.x; t < span; t += blockDim.x) acc[t] = 0.0f;
   __syncthreads();
-  constexpr int RW = Rec<F>::words;
+  constexpr int RD = Rec<F>::dwords;
   const uint32_t base_entry = (uint32_t)bucket << bshift;
-  const uint4* r0 = rec + (size_t)offsets[bucket] * RW;
+  const uint32_t* r0 = rec + (size_t)offsets[bucket] * RD;
   // kUnroll records per thread per round: their loads are all in flight
   // before the first LDS add
   for (int64_t rb = lo + threadIdx.x; rb < hi; rb += (int64_t)blockDim.x * kUnroll) {
-    uint32_t w[kUnroll][RW * 4];
+    uint32_t w[kUnroll][RD];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       const int64_t r = rb + (int64_t)u * blockDim.x;
+      if (r < hi) {
+        load_dwords<RD>(r0 + (size_t)r * RD, w[u]);
+      } else {
+        w[u][0] = base_entry;
 #pragma unroll
-      for (int q = 0; q < RW; ++q) {
-        uint4 x = make_uint4(base_entry, 0u, 0u, 0u);
-        if (r < hi) x = r0[(size_t)r * RW + q];
-        w[u][4 * q] = x.x;
-        w[u][4 * q + 1] = x.y;
-        w[u][4 * q + 2] = x.z;
-        w[u][4 * q + 3] = x.w;
+        for (int q = 1; q < RD; ++q) w[u][q] = 0u;
       }
     }
 #pragma unroll
@@ -232,14 +254,14 @@ ScatterPlan scatter_plan(const ngvol_plan* plan, int64_t B) {
   if (g < 1) g = 1;
   sp.blocks = (int)g;
   sp.chunk = (B + g - 1) / g;
-  sp.rec_words = (1 + F + 3) / 4;
+  sp.rec_words = 1 + F;  // dwords per record
   sp.n_records = B * 8 * md.L;
   sp.chunk_records = kChunkRecords;
   // upper bound of the work items: one partial chunk per bucket plus full chunks
   sp.max_items = sp.n_buckets + (int)((sp.n_records + kChunkRecords - 1) / kChunkRecords);
   auto up = [](size_t v) { return (v + 255) / 256 * 256; };
   sp.rec_off = 0;
-  sp.counts_off = up((size_t)sp.n_records * 16 * sp.rec_words);
+  sp.counts_off = up((size_t)sp.n_records * 4 * sp.rec_words);
   sp.totals_off = sp.counts_off + up((size_t)sp.blocks * sp.n_buckets * 4);
   sp.offsets_off = sp.totals_off + up((size_t)sp.n_buckets * 4);
   sp.items_off = sp.offsets_off + up((size_t)sp.n_buckets * 4);
@@ -251,7 +273,7 @@ hipError_t launch_scatter(const ngvol_plan* plan, const ScatterPlan& sp, const B
                           float* grad, void* ws, hipStream_t st) {
   const ModelDesc& md = plan->md;
   char* base = reinterpret_cast<char*>(ws);
-  uint4* rec = reinterpret_cast<uint4*>(base + sp.rec_off);
+  uint32_t* rec = reinterpret_cast<uint32_t*>(base + sp.rec_off);
   uint32_t* counts = reinterpret_cast<uint32_t*>(base + sp.counts_off);
   uint32_t* totals = reinterpret_cast<uint32_t*>(base + sp.totals_off);
   uint32_t* offsets = reinterpret_cast<uint32_t*>(base + sp.offsets_off);

@@ -160,61 +160,115 @@ __global__ void __launch_bounds__(kSortThreads) k_bin_scatter(Src src, int64_t n
   __syncthreads();
   const int64_t lo = (int64_t)blockIdx.x * chunk;
   const int64_t hi = lo + chunk < n ? lo + chunk : n;
+  if (!with_target) {
+    // queries: 4 per thread per round, so that their loads and their cursor
+    // increments are in flight together
+    for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += 4 * (int64_t)blockDim.x) {
+      float4 r[4];
+      uint32_t key[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t i = i0 + (int64_t)u * blockDim.x;
+        float x = 0.0f, y = 0.0f, z = 0.0f;
+        if (i < hi) src.get(i, x, y, z);
+        r[u] = make_float4(x, y, z, __uint_as_float((uint32_t)i));
+        key[u] = cell_key(x, y, z, k);
+      }
+      uint32_t pos[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (i0 + (int64_t)u * blockDim.x < hi) pos[u] = atomicAdd(cur + key[u], 1u);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (i0 + (int64_t)u * blockDim.x < hi) out[pos[u]] = r[u];
+    }
+    return;
+  }
   for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
     float x, y, z;
     src.get(i, x, y, z);
     const uint32_t pos = atomicAdd(cur + cell_key(x, y, z, k), 1u);
-    float aux;
-    if (!with_target) aux = __uint_as_float((uint32_t)i);
-    else if (target_in) aux = target_in[i];
-    else aux = volume_sample<VT>(vol, dx, dy, dz, x, y, z);
+    const float aux = target_in ? target_in[i] : volume_sample<VT>(vol, dx, dy, dz, x, y, z);
     out[pos] = make_float4(x, y, z, aux);
   }
 }
 
 // Within-cell refinement: the records of one cell are regrouped by the next
-// 3 bits per axis of their position (512 sub-cells, Morton order) with an
-// LDS counting sort, so the final order follows the Morton curve down to
-// cells of 2^-(k+3) per axis; the order inside a sub-cell is arbitrary.
+// SB bits per axis of their position (2^(3 SB) sub-cells, Morton order) with
+// an LDS counting sort, so the final order follows the Morton curve down to
+// cells of 2^-(k+SB) per axis; the order inside a sub-cell is arbitrary.
 // Cells with more records than fit are left as they are (still grouped).
-constexpr int kRefineMax = 2048;
+template <int SB>
+struct Refine {
+  static constexpr int bins = 1 << (3 * SB);
+  static constexpr int threads = SB == 3 ? 512 : 1024;
+  static constexpr int cap = SB == 3 ? 2048 : 6144;  // records of one cell held in LDS
+  static constexpr int per = bins / threads;          // bins per thread in the scan
+};
 
-__global__ void __launch_bounds__(512) k_bin_refine(float4* __restrict__ rec, const uint32_t* __restrict__ totals,
-                                                    const uint32_t* __restrict__ offsets, int k) {
-  __shared__ float4 buf[kRefineMax];
-  __shared__ uint16_t key[kRefineMax];
-  __shared__ uint16_t rank[kRefineMax];
-  __shared__ uint32_t hist[512];
-  const uint32_t cnt = totals[blockIdx.x];
-  if (cnt < 2 || cnt > (uint32_t)kRefineMax) return;
-  const uint32_t base = offsets[blockIdx.x];
-  const float scale = (float)(8 << k);  // cells hold 2^-k per axis; 3 more bits each
-  const uint32_t top = (8u << k) - 1u;
-  hist[threadIdx.x] = 0u;  // blockDim.x == 512
-  __syncthreads();
-  for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
-    const float4 r = rec[base + i];
-    buf[i] = r;
-    const uint32_t qx = min((uint32_t)(clamp01(r.x) * scale), top) & 7u;
-    const uint32_t qy = min((uint32_t)(clamp01(r.y) * scale), top) & 7u;
-    const uint32_t qz = min((uint32_t)(clamp01(r.z) * scale), top) & 7u;
-    const uint32_t k9 = spread3(qx) | (spread3(qy) << 1) | (spread3(qz) << 2);
-    key[i] = (uint16_t)k9;
-    rank[i] = (uint16_t)atomicAdd(hist + k9, 1u);
-  }
-  __syncthreads();
-  // exclusive scan of the 512 sub-cell counts
-  const uint32_t v = hist[threadIdx.x];
-  __syncthreads();
-  for (uint32_t d = 1; d < 512; d <<= 1) {
-    const uint32_t add = threadIdx.x >= d ? hist[threadIdx.x - d] : 0u;
+template <int SB>
+__global__ void __launch_bounds__(Refine<SB>::threads) k_bin_refine(float4* __restrict__ rec,
+                                                                    const uint32_t* __restrict__ totals,
+                                                                    const uint32_t* __restrict__ offsets, int k,
+                                                                    int n_cells) {
+  typedef Refine<SB> R;
+  __shared__ float4 buf[R::cap];
+  __shared__ uint16_t key[R::cap];
+  __shared__ uint16_t rank[R::cap];
+  __shared__ uint32_t hist[R::bins];
+  __shared__ uint32_t wsum[R::threads / 64];
+  const float scale = (float)(1 << (k + SB));  // cells hold 2^-k per axis; SB more bits each
+  const uint32_t top = (1u << (k + SB)) - 1u;
+  const uint32_t low = (1u << SB) - 1u;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // each workgroup walks several cells
+  for (int cell = blockIdx.x; cell < n_cells; cell += gridDim.x) {
+    const uint32_t cnt = totals[cell];
+    if (cnt < 2 || cnt > (uint32_t)R::cap) continue;  // uniform over the workgroup
+    const uint32_t base = offsets[cell];
+    for (int b = threadIdx.x; b < R::bins; b += R::threads) hist[b] = 0u;
     __syncthreads();
-    hist[threadIdx.x] += add;
+    for (uint32_t i = threadIdx.x; i < cnt; i += R::threads) {
+      const float4 r = rec[base + i];
+      buf[i] = r;
+      const uint32_t qx = min((uint32_t)(clamp01(r.x) * scale), top) & low;
+      const uint32_t qy = min((uint32_t)(clamp01(r.y) * scale), top) & low;
+      const uint32_t qz = min((uint32_t)(clamp01(r.z) * scale), top) & low;
+      const uint32_t kk = spread3(qx) | (spread3(qy) << 1) | (spread3(qz) << 2);
+      key[i] = (uint16_t)kk;
+      rank[i] = (uint16_t)atomicAdd(hist + kk, 1u);
+    }
     __syncthreads();
+    // exclusive scan of the sub-cell counts: each thread owns `per`
+    // consecutive bins; their sums are scanned within waves by shuffles,
+    // then across the wave totals
+    uint32_t v[R::per];
+    uint32_t own = 0;
+#pragma unroll
+    for (int j = 0; j < R::per; ++j) {
+      v[j] = hist[threadIdx.x * R::per + j];
+      own += v[j];
+    }
+    uint32_t inc = own;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t t = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += t;
+    }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    uint32_t run = inc - own;
+#pragma unroll
+    for (int w = 0; w < R::threads / 64; ++w) run += w < wave ? wsum[w] : 0u;
+#pragma unroll
+    for (int j = 0; j < R::per; ++j) {
+      hist[threadIdx.x * R::per + j] = run;
+      run += v[j];
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < cnt; i += R::threads) rec[base + hist[key[i]] + rank[i]] = buf[i];
+    __syncthreads();  // buf, key and hist are reused by the next cell
   }
-  hist[threadIdx.x] -= v;
-  __syncthreads();
-  for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) rec[base + hist[key[i]] + rank[i]] = buf[i];
 }
 
 }  // namespace
@@ -229,7 +283,10 @@ hipError_t launch_count_offsets(uint32_t* counts, int blocks, int nb, uint32_t* 
 BinPlan bin_plan(const ngvol_plan* plan, int64_t n) {
   BinPlan bp{};
   if (n < ((int64_t)1 << 15)) return bp;  // too small to pay off
-  bp.k = n >= ((int64_t)1 << 22) ? 5 : 4;
+  // 4096 cells, refined by 3 bits per axis (by 4 from 2^22 queries: cells
+  // of about 4096 records, written in runs of ~16 by each block)
+  bp.k = 4;
+  bp.sb = n >= ((int64_t)1 << 22) ? 4 : 3;
   bp.n_bins = 1 << (3 * bp.k);
   int64_t g = (n + 4095) / 4096;
   if (g > plan->cus) g = plan->cus;
@@ -253,7 +310,6 @@ BinPlan bin_plan(const ngvol_plan* plan, int64_t n) {
 
 hipError_t launch_bin(const ngvol_plan* plan, const BinPlan& bp, const float* xyz, const BatchArgs* ba, int64_t n,
                       void* ws, hipStream_t st) {
-  (void)plan;
   char* base = reinterpret_cast<char*>(ws);
   float4* rec = reinterpret_cast<float4*>(base + bp.rec_off);
   uint32_t* counts = reinterpret_cast<uint32_t*>(base + bp.counts_off);
@@ -272,7 +328,17 @@ hipError_t launch_bin(const ngvol_plan* plan, const BinPlan& bp, const float* xy
   if (!ba) {
     hipLaunchKernelGGL(k_bin_scatter<float>, dim3(bp.blocks), dim3(kSortThreads), lds, st, src, n, bp.k, bp.chunk,
                        counts, offsets, rec, false, nullptr, nullptr, 1, 1, 1);
-    hipLaunchKernelGGL(k_bin_refine, dim3(bp.n_bins), dim3(512), 0, st, rec, totals, offsets, bp.k);
+    if (bp.sb == 3) {
+      int rgrid = plan->cus * 4;  // workgroups walking cells
+      if (rgrid > bp.n_bins) rgrid = bp.n_bins;
+      hipLaunchKernelGGL(k_bin_refine<3>, dim3(rgrid), dim3(Refine<3>::threads), 0, st, rec, totals, offsets, bp.k,
+                         bp.n_bins);
+    } else {
+      int rgrid = plan->cus;
+      if (rgrid > bp.n_bins) rgrid = bp.n_bins;
+      hipLaunchKernelGGL(k_bin_refine<4>, dim3(rgrid), dim3(Refine<4>::threads), 0, st, rec, totals, offsets, bp.k,
+                         bp.n_bins);
+    }
   } else if (ba->xyz || ba->vdtype != NGVOL_DT_F16) {
     hipLaunchKernelGGL(k_bin_scatter<float>, dim3(bp.blocks), dim3(kSortThreads), lds, st, src, n, bp.k, bp.chunk,
                        counts, offsets, rec, true, ba->target, reinterpret_cast<const float*>(ba->volume), ba->dims[0],

@@ -214,24 +214,24 @@ def _morton(q, bits):
 
 def test_sorted_records_follow_morton_order():
     # the grouped records are the input points, each with its index, in
-    # Morton order down to cells of 2^-(k+3) per axis (k = 4 below 2^22
-    # points, 5 from there); cells of more than 2048 points keep only the
-    # cell order
+    # Morton order of 16^3 cells refined by sb bits per axis (3 below 2^22
+    # points, 4 from there); cells of more than 2048 (sb = 3) or 6144
+    # (sb = 4) points keep only the cell order
     p = gpu_plan("cfg1", "bf16")
-    for n, k in ((40007, 4), (1 << 22, 5)):
+    for n, k, sb in ((40007, 4, 3), (1 << 22, 4, 4)):
         xyz = synth.query_coords(n, SEED + 3 * n)
         ws = ngv.sort_queries(p, dev(xyz))
         rec = host(ws[: n * 16].view(torch.float32)).reshape(n, 4)
         idx = rec[:, 3].view(np.uint32).astype(np.int64)
         assert np.array_equal(np.sort(idx), np.arange(n))
         np.testing.assert_array_equal(rec[:, :3], xyz[idx])
-        top = (8 << k) - 1
-        q = np.minimum(np.floor(np.clip(rec[:, :3], 0, 1).astype(np.float64) * (8 << k)), top).astype(np.int64)
-        cell = _morton(q >> 3, k)
-        full = _morton(q, k + 3)
+        top = (1 << (k + sb)) - 1
+        q = np.minimum(np.floor(np.clip(rec[:, :3], 0, 1).astype(np.float64) * (1 << (k + sb))), top).astype(np.int64)
+        cell = _morton(q >> sb, k)
+        full = _morton(q, k + sb)
         assert np.all(np.diff(cell) >= 0)
         counts = np.bincount(cell, minlength=1 << (3 * k))
-        refined = counts[cell] <= 2048
+        refined = counts[cell] <= (2048 if sb == 3 else 6144)
         ok = np.diff(full) >= 0
         same_cell = np.diff(cell) == 0
         assert np.all(ok[same_cell & refined[1:]])
