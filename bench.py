@@ -12,8 +12,11 @@ time.  Inputs are synthetic and resident in HBM before timing starts.
 Also reported: the same two legs in the plain FP32 form, the PSNR of both
 forms after identical training (quality leg), online rendering (1024^2
 frames through the trained model with one training step per frame), the
-roofline of the query kernel (measured with events on the launch stream)
-and the FP64 CPU oracle timed on a bounded sample of the same workload.
+roofline of the query pass (level kernel + MLP on the feature planes,
+measured with events on the launch stream; HBM traffic from the committed
+counter summary while the kernel sources match it), the standalone MLP on
+the matrix cores, a batch of 16 volumes, and the FP64 CPU oracle timed on a
+bounded sample of the same workload.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -84,7 +87,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--quality-steps", type=int, default=2000)
-    ap.add_argument("--quality-repeats", type=int, default=5)
+    ap.add_argument("--quality-repeats", type=int, default=8)
     ap.add_argument("--no-quality", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
@@ -228,13 +231,19 @@ def main():
                 if s is not trained:
                     del s
         mb, mf = float(np.mean(res["bf16"])), float(np.mean(res["fp32"]))
+        # paired by batch seed: the loss of each repeat and its standard error
+        diff = np.array(res["fp32"]) - np.array(res["bf16"])
+        d_se = float(np.std(diff, ddof=1) / math.sqrt(len(diff))) if len(diff) > 1 else float("nan")
         quality = {"steps": args.quality_steps, "batch": B_TRAIN, "volume": f"{VOL_D}^3 fbm f32",
                    "repeats": args.quality_repeats, "psnr_bf16_db": [round(v, 3) for v in res["bf16"]],
                    "psnr_fp32_db": [round(v, 3) for v in res["fp32"]], "mean_bf16_db": round(mb, 3),
                    "mean_fp32_db": round(mf, 3), "psnr_loss_db": round(mf - mb, 3),
                    "median_bf16_db": round(float(np.median(res["bf16"])), 3),
                    "median_fp32_db": round(float(np.median(res["fp32"])), 3),
-                   "fp32_run_to_run_std_db": round(float(np.std(res["fp32"])), 3)}
+                   "paired_loss_db_mean": round(float(np.mean(diff)), 3),
+                   "paired_loss_db_stderr": round(d_se, 3),
+                   "fp32_run_to_run_std_db": round(float(np.std(res["fp32"])), 3),
+                   "bf16_run_to_run_std_db": round(float(np.std(res["bf16"])), 3)}
 
     # ---------------------------------------------------- online render leg
     # 1024^2 frames through the trained BF16 model (the quality leg's first

@@ -218,12 +218,15 @@ int ngvol_mlp_fwd(const ngvol_plan* plan, const float* d_params, const void* d_f
  * ngvol_infer_workspace_bytes(plan, n) bytes the queries are first grouped
  * by spatial cell (a counting sort on the device) so that neighbouring
  * queries share table cache lines; for large sets whose tables exceed one
- * XCD's L2 the grouped queries are then evaluated level group by level
- * group, each XCD interpolating its own levels for all queries into feature
- * planes in the workspace, followed by the MLP on those planes.  Every
- * output lands in its own slot and the values are bitwise the same on all
- * paths.  The bytes query returns 0 when n is too small for reordering to
- * pay off.  n < 2^31. */
+ * XCD's L2 (FP16 tables given, n >= 2^20) the grouped queries are then
+ * evaluated level group by level group, each XCD interpolating its own
+ * levels for all queries into feature planes in the workspace, followed by
+ * the MLP on those planes.  Every output lands in its own slot.  The fused
+ * kernel gives the same values in either order; the level-split path sums
+ * the first layer's products in another order, so its values agree with the
+ * fused kernel to FP32 rounding (with 16-bit operands a hidden activation
+ * may round differently).  The bytes query returns 0 when n is too small
+ * for reordering to pay off.  n < 2^31. */
 int ngvol_infer_workspace_bytes(const ngvol_plan* plan, int64_t n, size_t* bytes);
 int ngvol_infer(const ngvol_plan* plan, const ngvol_weights* w, const float* d_xyz, int64_t n, float* d_out,
                 void* d_workspace, size_t workspace_bytes, hipStream_t stream);

@@ -277,6 +277,46 @@ def encode_bwd(plan, xyz, dfeat, grad):
     _check(lib().ngvol_encode_bwd(plan.handle, _ptr(xyz), xyz.shape[0], _ptr(dfeat), _ptr(grad), _stream()))
 
 
+_volume_fn_cls = None
+
+
+def _volume_fn():
+    """torch.autograd.Function over the library's forward and backward kernels."""
+    global _volume_fn_cls
+    if _volume_fn_cls is None:
+        torch = _torch()
+
+        class _VolumeFn(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, params, xyz, plan, table_f16):
+                feat = encode(plan, params, xyz, table_f16)
+                y = mlp_fwd(plan, params, feat)
+                ctx.plan = plan
+                ctx.save_for_backward(params, xyz, feat)
+                return y
+
+            @staticmethod
+            def backward(ctx, dy):
+                params, xyz, feat = ctx.saved_tensors
+                grad = torch.zeros_like(params)
+                # MLP backward recomputes the activations from the features;
+                # it adds dL/dW and returns dL/dfeature for the table scatter
+                dfeat = mlp_bwd(ctx.plan, params, feat, dy.contiguous().to(torch.float32), grad)
+                encode_bwd(ctx.plan, xyz, dfeat, grad)
+                return grad, None, None, None
+
+        _volume_fn_cls = _VolumeFn
+    return _volume_fn_cls
+
+
+def volume(plan, params, xyz, table_f16=None):
+    """Phi(xyz) as a differentiable torch op.  Gradients flow to `params` (the
+    level tables and the MLP) through the library's backward kernels; the
+    coordinates get none.  With `table_f16` the forward reads the FP16 table
+    shadow (the gradient is that of the shadowed model)."""
+    return _volume_fn().apply(params, xyz, plan, table_f16)
+
+
 def _volume_batch(volume, B, seed, step):
     torch = _torch()
     dt = {torch.float32: DT_F32, torch.float16: DT_F16}[volume.dtype]

@@ -312,6 +312,31 @@ def test_gradients_fp32_standalone(name):
     _check_grad(host(grad), g_ref, m, 1e-4)
 
 
+@pytest.mark.parametrize("name,prec", [("tiny", "fp32"), ("cfg1", "fp32"), ("w32k64", "fp32"), ("cfg1", "bf16")])
+def test_autograd_function_gradient(name, prec):
+    # the differentiable op: torch's backward of a mean-square loss through
+    # ngv.volume equals the oracle's analytic gradient
+    m = oracle_model(name)
+    p = gpu_plan(name, prec)
+    params = init_params(name, table_scale=0.3)
+    rng = np.random.default_rng(21)
+    B = 3001
+    xyz = edge_coords(B, seed=22)
+    y = rng.random(B).astype(np.float32)
+    _, g_ref = oracle.loss_grad(m, params.astype(np.float64), xyz, y.astype(np.float64))
+    pt = dev(params).requires_grad_(True)
+    out = ngv.volume(p, pt, dev(xyz))
+    loss = ((out - dev(y)) ** 2).mean()
+    loss.backward()
+    g = host(pt.grad).astype(np.float64)
+    if prec == "fp32":
+        _check_grad(g, g_ref, m, 1e-4)
+        ref_loss = float(np.mean((oracle.forward(m, params.astype(np.float64), xyz) - y) ** 2))
+        assert float(loss) == pytest.approx(ref_loss, rel=1e-5)
+    else:
+        _check_grad_bf16(g, g_ref, m)
+
+
 def _check_grad_bf16(got, ref, m):
     # No parity bar is set for BF16 gradients (the bar is PSNR after
     # training).  Coarse-level blocks are sums of many cancelling terms, so the
