@@ -42,6 +42,13 @@ N_QUERY = 1 << 24
 B_TRAIN = 1 << 18
 VOL_D = 512
 ADAM = dict(lr=1e-2, betas=(0.9, 0.99), eps=1e-15)
+# the paper's default training setting (appendix default optimiser and loss)
+# on its fixed Table-2 network: 8 levels x 8 features, 2^19 entries, base 4,
+# 64 wide x 4 hidden; L1 loss, 65,536 samples per step
+PAPER_MODEL = dict(n_levels=8, n_features=8, log2_hashmap_size=19, base_resolution=4, per_level_scale=2.0,
+                   n_neurons=64, n_hidden_layers=4)
+PAPER_ADAM = dict(lr=5e-3, betas=(0.9, 0.999), eps=1e-15, l2_reg=1e-6, decay=(2000, 1000, 0.99))
+PAPER_B = 65536
 LOSS_SCALE = 128.0
 HBM_PEAK_GBS = 8000.0
 
@@ -93,6 +100,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--render-frames", type=int, default=8)
     ap.add_argument("--no-render", action="store_true")
+    ap.add_argument("--no-paper-default", action="store_true")
     ap.add_argument("--no-multi", action="store_true")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -204,6 +212,31 @@ def main():
                 "step_samples_per_s": (B_TRAIN + N_QUERY) / ((t32 + i32) * 1e-3)}
         del st32
         log(f"fp32 train {t32:.3f} ms, infer {i32:.3f} ms")
+
+    # ------------------------------------- paper-default training setting
+    paper_default = None
+    if not args.no_paper_default:
+        paper_default = {"model": "L8 F8 T2^19 base 4 x2, 64x4", "loss": "l1", "batch": PAPER_B,
+                         "adam": "5e-3, (0.9, 0.999), 1e-15, l2 1e-6, decay 2000/1000/0.99"}
+        for name, prec, f16, ls in (("bf16", "bf16", True, LOSS_SCALE), ("fp32", "fp32", False, 1.0)):
+            pp = ngv.Plan(**PAPER_MODEL, precision=prec, loss="l1")
+            pw = synth.init_params(pp.n_table_params, pp.n_input, 64, 4, 1e-4, SEED)
+            sp = ngv.TrainState(pp, torch.from_numpy(pw).to(dev), PAPER_B, f16_tables=f16)
+            for k in range(3):
+                ngv.train_step(sp, volume=vol, seed=SEED, step_index=k, loss_scale=ls, **PAPER_ADAM)
+            reps = max(5, min(args.steps, 20))
+            e = [ev() for _ in range(2)]
+            torch.cuda.synchronize()
+            e[0].record()
+            for k in range(reps):
+                ngv.train_step(sp, volume=vol, seed=SEED, step_index=3 + k, loss_scale=ls, **PAPER_ADAM)
+            e[1].record()
+            torch.cuda.synchronize()
+            ms = e[0].elapsed_time(e[1]) / reps
+            paper_default[f"{name}_train_ms"] = round(ms, 4)
+            paper_default[f"{name}_train_samples_per_s"] = PAPER_B / (ms * 1e-3)
+            log(f"paper-default {name} train step {ms:.3f} ms, {PAPER_B / (ms * 1e-3):.3e} samples/s")
+            del sp
 
     # ------------------------------------------------------------ quality leg
     # Training with these hyper-parameters is noisy run to run (FP32 atomics
@@ -451,7 +484,7 @@ def main():
                       "train_samples_per_s": B_TRAIN / (train_ms * 1e-3),
                       "infer_samples_per_s": N_QUERY / ((sort_ms + infer_ms) * 1e-3),
                       "infer_unsorted_ms": round(direct_ms, 4)},
-        "fp32_plain": fp32, "quality": quality, "render": render, "multi_volume": multi, "roofline": roofline,
+        "fp32_plain": fp32, "paper_default_train": paper_default, "quality": quality, "render": render, "multi_volume": multi, "roofline": roofline,
         "mlp_roofline": mlp_roofline, "cpu_baseline": cpu,
     }
     s = json.dumps(line)

@@ -70,6 +70,11 @@ extern "C" {
 #define NGVOL_FP16 2 /* FP16 operands on MFMA with FP32 accumulation */
 
 /* Element types of volumes and feature buffers. */
+/* Training loss (Section 3.1 names L1 as the default loss; the DNS
+ * experiment of Section 7.1 uses L2). */
+#define NGVOL_LOSS_L2 0 /* L = (1/B) sum (Phi(x)-y)^2 */
+#define NGVOL_LOSS_L1 1 /* L = (1/B) sum |Phi(x)-y|; dL/dPhi = sign(Phi(x)-y)/B, sign(0) = 0 */
+
 #define NGVOL_DT_F32 0
 #define NGVOL_DT_F16 1
 #define NGVOL_DT_BF16 2
@@ -83,7 +88,9 @@ typedef struct ngvol_plan ngvol_plan;
  * n_levels * n_features <= 64; 1 <= log2_hashmap_size <= 28;
  * n_neurons in {32,64}; 1 <= n_hidden_layers <= 8; the weights of a
  * forward must fit in LDS and the backward (ngvol_mlp_bwd,
- * ngvol_train_step) needs W, W^T and dW in LDS (else NGVOL_EUNSUPPORTED);
+ * ngvol_train_step) needs W and W^T in LDS (else NGVOL_EUNSUPPORTED; dW
+ * accumulates in LDS too when that leaves room for four waves, else in the
+ * workspace's per-workgroup partial sums);
  * the tables hold at most 2^30 - 4 floats (4 GiB of FP32, else
  * NGVOL_EUNSUPPORTED).
  * Vertices per axis: resolutions[l] if given; else N_l = base * b^l, used as
@@ -102,6 +109,7 @@ typedef struct ngvol_config {
     int32_t n_neurons;
     int32_t n_hidden_layers;
     int32_t precision; /* NGVOL_FP32 | NGVOL_BF16 | NGVOL_FP16 */
+    int32_t loss;      /* NGVOL_LOSS_L2 (0) | NGVOL_LOSS_L1; used by ngvol_train_step */
 } ngvol_config;
 
 /* Derived layout of a plan (host struct filled by ngvol_get_layout). */
@@ -159,11 +167,23 @@ typedef struct ngvol_batch {
                           * captured graph draws a new batch on every replay (a skipped step repeats it) */
 } ngvol_batch;
 
-/* Adam (Kingma and Ba) with bias correction; the paper trains with Adam
- * (Section 3.1).  Gradients are divided by loss_scale before use; if any
- * unscaled contribution is non-finite the whole step is skipped. */
+/* Adam (Kingma and Ba) with bias correction and an exponentially decaying
+ * learning rate; the paper trains with Adam under an exponential decay
+ * (Section 3.1; decay start, interval and base and the L2 regularisation are
+ * the parameters of the appendix's default optimiser configuration).
+ * Gradients are divided by loss_scale before use; if any unscaled
+ * contribution is non-finite the whole step is skipped.
+ * Step k (0-based count of applied steps, the state's step counter) uses
+ *   lr_k = learning_rate * decay_base^floor((k - decay_start) / decay_interval)
+ * when decay_interval > 0 and k >= decay_start, else learning_rate.
+ * l2_reg adds l2_reg * w to the gradient of every MLP weight w (not to the
+ * tables).  Zero l2_reg and decay_interval give plain Adam. */
 typedef struct ngvol_adam {
     double learning_rate, beta1, beta2, epsilon;
+    double l2_reg;          /* >= 0 */
+    int64_t decay_start;    /* >= 0 */
+    int64_t decay_interval; /* >= 0; 0 = no decay */
+    double decay_base;      /* in (0, 1] when decay_interval > 0 */
 } ngvol_adam;
 
 /* Pinhole camera: the unnormalised direction through pixel centre (px,py)
@@ -267,8 +287,8 @@ int ngvol_sample_batch(const ngvol_plan* plan, const ngvol_batch* batch, float* 
 /* Workspace a training step of batch B needs. */
 int ngvol_train_workspace_bytes(const ngvol_plan* plan, int64_t batch_size, size_t* bytes);
 
-/* One training step (Section 4): sampling, forward, mean-squared loss
- * L = (1/B) sum (Phi(x)-y)^2, backward through the MLP (activations
+/* One training step (Section 4): sampling, forward, the plan's loss
+ * (NGVOL_LOSS_L2 or NGVOL_LOSS_L1, mean over the batch), backward through the MLP (activations
  * recomputed from the stored encoding) and the encoding, then Adam on all
  * parameters; the FP16 shadow (if any) is refreshed by round-to-nearest-even
  * from the master.  Gradients are formed at loss_scale times their value

@@ -51,7 +51,11 @@ def lib():
             "orc_sample_volume": (C.c_int, [P, P, P, i64, P]),
             "orc_batch_coords": (C.c_int, [u64, i64, i64, P]),
             "orc_loss_grad": (C.c_int, [P, P, P, P, i64, P, P]),
+            "orc_loss_grad_kind": (C.c_int, [P, P, P, P, i64, C.c_int, P, P]),
+            "orc_lr_at": (dbl, [dbl, i64, i64, i64, dbl]),
             "orc_adam": (C.c_int, [i64, P, P, P, P, i64, dbl, dbl, dbl, dbl]),
+            "orc_adam_reg": (C.c_int, [i64, i64, P, P, P, P, i64, dbl, dbl, dbl, dbl, dbl]),
+            "orc_train_opt": (C.c_int, [P, P, P, P, P, P, u64, i64, i64, i64, C.c_int, P, P]),
             "orc_train": (C.c_int, [P, P, P, P, P, P, u64, i64, i64, i64, dbl, dbl, dbl, dbl, P]),
             "orc_mse_grid": (C.c_int, [P, P, P, P, P]),
             "orc_ray_counts": (C.c_int, [P, C.c_int, C.c_int, u32, flt, P]),
@@ -164,24 +168,37 @@ def batch_coords(seed, step, B):
     return xyz
 
 
-def loss_grad(m: Model, params, xyz, y):
+LOSS_KIND = {"l2": 0, "l1": 1}
+
+
+def loss_grad(m: Model, params, xyz, y, loss="l2"):
+    """(mean loss, dL/dparams) for loss "l2" (mean square) or "l1" (mean absolute)."""
     params, xyz, y = _f64(params), _f32(xyz), _f64(y)
     n = xyz.shape[0]
     g = np.zeros(m.n_params, np.float64)
-    loss = np.zeros(1, np.float64)
-    _chk(lib().orc_loss_grad(_p(m.desc), _p(params), _p(xyz), _p(y), n, _p(g), _p(loss)))
-    return float(loss[0]), g
+    out = np.zeros(1, np.float64)
+    _chk(lib().orc_loss_grad_kind(_p(m.desc), _p(params), _p(xyz), _p(y), n, LOSS_KIND[loss], _p(g), _p(out)))
+    return float(out[0]), g
 
 
-def adam(theta, m_, v_, g, t, lr, b1, b2, eps):
-    """In-place on FP64 arrays theta, m_, v_."""
+def lr_at(lr, k, decay):
+    """Learning rate of 0-based step k under decay = (start, interval, base) or None."""
+    start, interval, base = decay if decay is not None else (0, 0, 1.0)
+    return float(lib().orc_lr_at(lr, k, start, interval, base))
+
+
+def adam(theta, m_, v_, g, t, lr, b1, b2, eps, l2_reg=0.0, reg_from=None):
+    """In-place on FP64 arrays theta, m_, v_; l2_reg * theta joins the gradient
+    of indices >= reg_from (the MLP block when called with n_table)."""
     for a in (theta, m_, v_):
         assert a.dtype == np.float64 and a.flags.c_contiguous
     g = _f64(g)
-    _chk(lib().orc_adam(theta.size, _p(theta), _p(m_), _p(v_), _p(g), t, lr, b1, b2, eps))
+    rf = theta.size if reg_from is None else int(reg_from)
+    _chk(lib().orc_adam_reg(theta.size, rf, _p(theta), _p(m_), _p(v_), _p(g), t, lr, b1, b2, eps, l2_reg))
 
 
-def train(m: Model, params, vol, seed, steps, B, lr, b1, b2, eps, step0=0, state=None):
+def train(m: Model, params, vol, seed, steps, B, lr, b1, b2, eps, step0=0, state=None, loss="l2", l2_reg=0.0,
+          decay=None):
     """Returns (params, (m, v), losses); params is a new FP64 array."""
     theta = _f64(params).copy()
     if state is None:
@@ -191,8 +208,10 @@ def train(m: Model, params, vol, seed, steps, B, lr, b1, b2, eps, step0=0, state
     vol = _f32(vol)
     dims = np.array([vol.shape[2], vol.shape[1], vol.shape[0]], np.int32)
     losses = np.zeros(steps, np.float64)
-    _chk(lib().orc_train(_p(m.desc), _p(theta), _p(am), _p(av), _p(vol), _p(dims), seed, step0, steps, B,
-                         lr, b1, b2, eps, _p(losses)))
+    start, interval, base = decay if decay is not None else (0, 0, 1.0)
+    opt = np.array([lr, b1, b2, eps, l2_reg, start, interval, base], np.float64)
+    _chk(lib().orc_train_opt(_p(m.desc), _p(theta), _p(am), _p(av), _p(vol), _p(dims), seed, step0, steps, B,
+                             LOSS_KIND[loss], _p(opt), _p(losses)))
     return theta, (am, av), losses
 
 

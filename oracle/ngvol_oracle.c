@@ -13,7 +13,9 @@
  *   - a bias-free ReLU MLP on the concatenated features (Section 3.1);
  *   - the sampling step (Section 4): uniform random coordinates in [0,1)^3
  *     with a trilinearly interpolated ground-truth value;
- *   - one optimisation step: loss, analytic gradient, Adam (Section 3.1;
+ *   - one optimisation step: L2 or L1 loss, analytic gradient, Adam with an
+ *     exponentially decaying learning rate and L2 regularisation of the
+ *     network weights (Section 3.1 and the appendix's default optimiser;
  *     Kingma and Ba 2014);
  *   - the ray-marched emission-absorption renderer fed by streamed samples
  *     (Section 5.2.1);
@@ -364,11 +366,16 @@ int orc_batch_coords(uint64_t seed, int64_t step, int64_t B, float* xyz)
 
 /* ------------------------------------------------------------------------ */
 /* Loss and analytic gradient.                                              */
-/* L = (1/B) sum_i (Phi(x_i) - y_i)^2; grad = dL/dparams (all parameters).   */
+/* kind 0 (L2): L = (1/B) sum_i (Phi(x_i) - y_i)^2;                         */
+/* kind 1 (L1, the paper's default loss, Section 3.1):                      */
+/*   L = (1/B) sum_i |Phi(x_i) - y_i|, dL/dPhi_i = sign(Phi_i - y_i)/B with  */
+/*   sign(0) = 0;                                                           */
+/* grad = dL/dparams (all parameters).                                      */
 /* ------------------------------------------------------------------------ */
-int orc_loss_grad(const int32_t* desc, const double* params, const float* xyz, const double* y, int64_t n,
-                  double* grad, double* loss_out)
+int orc_loss_grad_kind(const int32_t* desc, const double* params, const float* xyz, const double* y, int64_t n,
+                       int kind, double* grad, double* loss_out)
 {
+    if (kind != 0 && kind != 1) return -1;
     orc_model m;
     if (orc_model_from_desc(desc, &m) || m.width > 1024 || m.n_in > 1024 || m.n_layers > 16) return -1;
     const double* W = params + m.n_table;
@@ -406,8 +413,14 @@ int orc_loss_grad(const int32_t* desc, const double* params, const float* xyz, c
             orc_encode_one(&m, params, xyz + 3 * i, e);
             double yhat = orc_mlp_one(&m, W, e, z);
             double r = yhat - y[i];
-            loss_t[tid] += r * r;
-            double g = 2.0 * r / (double)n; /* dL/dyhat */
+            double g; /* dL/dyhat */
+            if (kind == 1) {
+                loss_t[tid] += fabs(r);
+                g = (r > 0.0 ? 1.0 : (r < 0.0 ? -1.0 : 0.0)) / (double)n;
+            } else {
+                loss_t[tid] += r * r;
+                g = 2.0 * r / (double)n;
+            }
             /* hidden activations h_j = relu(z_j) */
             for (int li = 0; li < m.n_hidden; ++li)
                 for (int o = 0; o < m.width; ++o) {
@@ -469,19 +482,45 @@ int orc_loss_grad(const int32_t* desc, const double* params, const float* xyz, c
     return 0;
 }
 
+int orc_loss_grad(const int32_t* desc, const double* params, const float* xyz, const double* y, int64_t n,
+                  double* grad, double* loss_out)
+{
+    return orc_loss_grad_kind(desc, params, xyz, y, n, 0, grad, loss_out);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exponentially decaying learning rate (Section 3.1; decay start, interval */
+/* and base from the appendix's default optimiser).  Reading: the rate is    */
+/* constant for the first `start` steps and is then multiplied by `base`     */
+/* once every `interval` steps: step k (0-based) uses                        */
+/* lr * base^floor((k - start) / interval) for k >= start.  interval <= 0    */
+/* means no decay.                                                          */
+/* ------------------------------------------------------------------------ */
+double orc_lr_at(double lr, int64_t k, int64_t start, int64_t interval, double base)
+{
+    if (interval <= 0 || k < start) return lr;
+    int64_t n = (k - start) / interval;
+    double f = 1.0;
+    for (int64_t i = 0; i < n; ++i) f *= base;
+    return lr * f;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Adam (Kingma and Ba 2014), dense, bias-corrected, eps outside the root.  */
-/* t is the 1-based step number.                                            */
+/* t is the 1-based step number.  L2 regularisation (appendix default       */
+/* optimiser, read as a penalty (l2_reg/2)|w|^2 on the network weights):     */
+/* l2_reg * theta_i joins the gradient of every index i >= reg_from.         */
 /* ------------------------------------------------------------------------ */
-int orc_adam(int64_t n, double* theta, double* m, double* v, const double* g, int64_t t, double lr, double b1,
-             double b2, double eps)
+int orc_adam_reg(int64_t n, int64_t reg_from, double* theta, double* m, double* v, const double* g, int64_t t,
+                 double lr, double b1, double b2, double eps, double l2_reg)
 {
     double c1 = 1.0 - pow(b1, (double)t);
     double c2 = 1.0 - pow(b2, (double)t);
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
-        m[i] = b1 * m[i] + (1.0 - b1) * g[i];
-        v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+        double gi = g[i] + (i >= reg_from ? l2_reg * theta[i] : 0.0);
+        m[i] = b1 * m[i] + (1.0 - b1) * gi;
+        v[i] = b2 * v[i] + (1.0 - b2) * gi * gi;
         double mh = m[i] / c1;
         double vh = v[i] / c2;
         theta[i] -= lr * mh / (sqrt(vh) + eps);
@@ -489,14 +528,23 @@ int orc_adam(int64_t n, double* theta, double* m, double* v, const double* g, in
     return 0;
 }
 
+int orc_adam(int64_t n, double* theta, double* m, double* v, const double* g, int64_t t, double lr, double b1,
+             double b2, double eps)
+{
+    return orc_adam_reg(n, n, theta, m, v, g, t, lr, b1, b2, eps, 0.0);
+}
+
 /*
  * `steps` training steps of batch B on a volume: coordinates of step s from
- * orc_batch_coords(seed, step0 + s), targets by orc_sample_volume, MSE loss,
- * Adam at 1-based step t = step0 + s + 1.  m and v are caller-owned state.
+ * orc_batch_coords(seed, step0 + s), targets by orc_sample_volume, loss of
+ * `kind` (0 L2, 1 L1), Adam at 1-based step t = step0 + s + 1 with the rate
+ * orc_lr_at(lr, t - 1, ...) and L2 regularisation of the MLP weights.
+ * opt = {lr, beta1, beta2, eps, l2_reg, decay_start, decay_interval,
+ * decay_base}.  m and v are caller-owned state.
  */
-int orc_train(const int32_t* desc, double* params, double* adam_m, double* adam_v, const float* vol,
-              const int32_t* dims, uint64_t seed, int64_t step0, int64_t steps, int64_t B, double lr, double b1,
-              double b2, double eps, double* losses)
+int orc_train_opt(const int32_t* desc, double* params, double* adam_m, double* adam_v, const float* vol,
+                  const int32_t* dims, uint64_t seed, int64_t step0, int64_t steps, int64_t B, int kind,
+                  const double* opt, double* losses)
 {
     orc_model m;
     if (orc_model_from_desc(desc, &m)) return -1;
@@ -511,17 +559,29 @@ int orc_train(const int32_t* desc, double* params, double* adam_m, double* adam_
     }
     int rc = 0;
     for (int64_t s = 0; s < steps && rc == 0; ++s) {
-        orc_batch_coords(seed, step0 + s, B, xyz);
+        const int64_t k = step0 + s;
+        orc_batch_coords(seed, k, B, xyz);
         orc_sample_volume(vol, dims, xyz, B, y);
         double loss = 0.0;
-        rc = orc_loss_grad(desc, params, xyz, y, B, g, &loss);
+        rc = orc_loss_grad_kind(desc, params, xyz, y, B, kind, g, &loss);
         if (losses) losses[s] = loss;
-        if (rc == 0) orc_adam(m.n_params, params, adam_m, adam_v, g, step0 + s + 1, lr, b1, b2, eps);
+        if (rc == 0) {
+            double lr = orc_lr_at(opt[0], k, (int64_t)opt[5], (int64_t)opt[6], opt[7]);
+            orc_adam_reg(m.n_params, m.n_table, params, adam_m, adam_v, g, k + 1, lr, opt[1], opt[2], opt[3], opt[4]);
+        }
     }
     free(xyz);
     free(y);
     free(g);
     return rc;
+}
+
+int orc_train(const int32_t* desc, double* params, double* adam_m, double* adam_v, const float* vol,
+              const int32_t* dims, uint64_t seed, int64_t step0, int64_t steps, int64_t B, double lr, double b1,
+              double b2, double eps, double* losses)
+{
+    const double opt[8] = {lr, b1, b2, eps, 0.0, 0.0, 0.0, 1.0};
+    return orc_train_opt(desc, params, adam_m, adam_v, vol, dims, seed, step0, steps, B, 0, opt, losses);
 }
 
 /* ------------------------------------------------------------------------ */

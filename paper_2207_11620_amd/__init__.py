@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libngvol.so")
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -4
 FP32, BF16, FP16 = 0, 1, 2
 DT_F32, DT_F16, DT_BF16 = 0, 1, 2
+LOSS_L2, LOSS_L1 = 0, 1
 MAX_LEVELS, MAX_LAYERS = 32, 9
 
 
@@ -34,7 +35,7 @@ class Config(C.Structure):
     _fields_ = [("n_levels", C.c_int32), ("n_features", C.c_int32), ("log2_hashmap_size", C.c_int32),
                 ("base_resolution", C.c_int32), ("per_level_scale", C.c_double), ("max_resolution", C.c_int32),
                 ("resolutions", C.POINTER(C.c_int32)), ("n_neurons", C.c_int32), ("n_hidden_layers", C.c_int32),
-                ("precision", C.c_int32)]
+                ("precision", C.c_int32), ("loss", C.c_int32)]
 
 
 class Layout(C.Structure):
@@ -64,7 +65,8 @@ class Batch(C.Structure):
 
 class Adam(C.Structure):
     _fields_ = [("learning_rate", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
-                ("epsilon", C.c_double)]
+                ("epsilon", C.c_double), ("l2_reg", C.c_double), ("decay_start", C.c_int64),
+                ("decay_interval", C.c_int64), ("decay_base", C.c_double)]
 
 
 class Camera(C.Structure):
@@ -156,14 +158,16 @@ class Plan:
     """Resolved model: hash grid (L levels, F features, 2^log2T entries) + MLP."""
 
     def __init__(self, n_levels, n_features, log2_hashmap_size, base_resolution=16, per_level_scale=2.0,
-                 max_resolution=0, resolutions=None, n_neurons=64, n_hidden_layers=2, precision="fp32"):
+                 max_resolution=0, resolutions=None, n_neurons=64, n_hidden_layers=2, precision="fp32", loss="l2"):
         prec = {"fp32": FP32, "bf16": BF16, "fp16": FP16, FP32: FP32, BF16: BF16, FP16: FP16}[precision]
+        self.loss = loss
+        loss_kind = {"l2": LOSS_L2, "l1": LOSS_L1}[loss]
         self._res = None
         if resolutions is not None:
             self._res = (C.c_int32 * len(resolutions))(*[int(r) for r in resolutions])
         cfg = Config(n_levels, n_features, log2_hashmap_size, base_resolution, float(per_level_scale),
                      int(max_resolution), C.cast(self._res, C.POINTER(C.c_int32)) if self._res else None,
-                     n_neurons, n_hidden_layers, prec)
+                     n_neurons, n_hidden_layers, prec, loss_kind)
         h = C.c_void_p()
         _check(lib().ngvol_plan_create(C.byref(cfg), C.byref(h)))
         self.handle = h
@@ -367,22 +371,29 @@ class TrainState:
         return self.params, self.table_f16
 
 
+def _adam(lr, betas, eps, l2_reg, decay):
+    start, interval, base = decay if decay is not None else (0, 0, 1.0)
+    return Adam(lr, betas[0], betas[1], eps, l2_reg, int(start), int(interval), float(base))
+
+
 def train_step(state, volume=None, seed=0, step_index=0, xyz=None, target=None, lr=1e-2, betas=(0.9, 0.99),
-               eps=1e-15, loss_scale=1.0):
+               eps=1e-15, loss_scale=1.0, l2_reg=0.0, decay=None):
     """One training step.  step_index=-1 draws the batch indexed by the state's
-    device step counter (the form to capture in a graph)."""
+    device step counter (the form to capture in a graph).  decay =
+    (start, interval, base) gives the exponentially decaying learning rate;
+    l2_reg regularises the MLP weights."""
     B = state.batch_size
     if xyz is not None:
         b = Batch(B, _ptr(xyz), _ptr(target), None, (C.c_int32 * 3)(0, 0, 0), 0, 0, 0)
     else:
         b = _volume_batch(volume, B, seed, step_index)
-    a = Adam(lr, betas[0], betas[1], eps)
+    a = _adam(lr, betas, eps, l2_reg, decay)
     _check(lib().ngvol_train_step(state.plan.handle, C.byref(state._c), C.byref(b), C.byref(a),
                                   float(loss_scale), _stream()))
 
 
-def adam_step(state, lr=1e-2, betas=(0.9, 0.99), eps=1e-15, loss_scale=1.0):
-    a = Adam(lr, betas[0], betas[1], eps)
+def adam_step(state, lr=1e-2, betas=(0.9, 0.99), eps=1e-15, loss_scale=1.0, l2_reg=0.0, decay=None):
+    a = _adam(lr, betas, eps, l2_reg, decay)
     _check(lib().ngvol_adam_step(state.plan.handle, C.byref(state._c), C.byref(a), float(loss_scale), _stream()))
 
 

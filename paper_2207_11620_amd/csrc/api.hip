@@ -82,7 +82,7 @@ TablePtrs tables_of(const ngvol_plan* p, const ngvol_weights* w) {
 
 // The backward keeps W, W^T, dW and per-wave activations in LDS.
 int check_bwd_lds(const ngvol_plan* p) {
-  const size_t b = bwd_lds_bytes(p, 1);
+  const size_t b = bwd_lds_bytes(p, 1, true);
   if (b > kLdsBytes)
     return fail(NGVOL_EUNSUPPORTED, "network too large for the LDS-resident backward (%zu > %zu bytes)", b, kLdsBytes);
   return NGVOL_OK;
@@ -133,6 +133,7 @@ int ngvol_plan_create(const ngvol_config* c, ngvol_plan** out) {
   NGV_REQUIRE(c->n_neurons >= 1, "n_neurons must be positive");
   NGV_REQUIRE(c->precision == NGVOL_FP32 || c->precision == NGVOL_BF16 || c->precision == NGVOL_FP16,
               "precision must be NGVOL_FP32, NGVOL_BF16 or NGVOL_FP16");
+  NGV_REQUIRE(c->loss == NGVOL_LOSS_L2 || c->loss == NGVOL_LOSS_L1, "loss must be NGVOL_LOSS_L2 or NGVOL_LOSS_L1");
   if (c->n_features != 2 && c->n_features != 4 && c->n_features != 8)
     return fail(NGVOL_EUNSUPPORTED, "n_features %d unsupported (2, 4 or 8)", c->n_features);
   if (c->n_neurons != 32 && c->n_neurons != 64)
@@ -193,6 +194,7 @@ int ngvol_plan_create(const ngvol_config* c, ngvol_plan** out) {
   L.n_mlp_params = pos;
   md.n_params = L.n_params = md.n_table + pos;
   p->kin = n_in <= 32 ? 32 : 64;
+  p->loss = c->loss;
 
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) dev = 0;
@@ -416,8 +418,25 @@ static int check_adam(const ngvol_adam* a, float loss_scale) {
   NGV_REQUIRE(a->learning_rate >= 0 && a->beta1 >= 0 && a->beta1 < 1 && a->beta2 >= 0 && a->beta2 < 1 &&
                   a->epsilon >= 0,
               "Adam hyper-parameters out of range");
+  NGV_REQUIRE(a->l2_reg >= 0 && std::isfinite(a->l2_reg), "l2_reg must be finite and >= 0");
+  NGV_REQUIRE(a->decay_start >= 0 && a->decay_interval >= 0, "decay_start and decay_interval must be >= 0");
+  NGV_REQUIRE(a->decay_interval == 0 || (a->decay_base > 0 && a->decay_base <= 1), "decay_base must be in (0,1]");
   NGV_REQUIRE(loss_scale > 0.0f && std::isfinite(loss_scale), "loss_scale must be positive and finite");
   return NGVOL_OK;
+}
+
+static AdamArgs adam_args(const ngvol_adam* a, float loss_scale) {
+  AdamArgs aa{};
+  aa.lr = a->learning_rate;
+  aa.b1 = a->beta1;
+  aa.b2 = a->beta2;
+  aa.eps = a->epsilon;
+  aa.l2_reg = a->l2_reg;
+  aa.decay_start = a->decay_start;
+  aa.decay_interval = a->decay_interval;
+  aa.decay_base = a->decay_interval > 0 ? a->decay_base : 1.0;
+  aa.inv_scale = 1.0f / loss_scale;
+  return aa;
 }
 
 int ngvol_train_step(const ngvol_plan* plan, const ngvol_train_state* s, const ngvol_batch* b, const ngvol_adam* a,
@@ -442,9 +461,10 @@ int ngvol_train_step(const ngvol_plan* plan, const ngvol_train_state* s, const n
   tp.f32 = s->params;
   tp.f16 = reinterpret_cast<const __half*>(s->table_f16);
   const float* mlp = s->params + plan->md.n_table;
-  const float gscale = (float)((double)loss_scale * 2.0 / (double)ba.B);
+  // g = S * dL/dy: S * 2 (y - t) / B for L2, S * sign(y - t) / B for L1
+  const float gscale = (float)((double)loss_scale * (plan->loss == NGVOL_LOSS_L1 ? 1.0 : 2.0) / (double)ba.B);
   hipError_t e = launch_step_begin(loss_acc, flag, st);
-  if (e == hipSuccess) e = launch_train_fwd(plan, tp, mlp, ba, e_buf, g_buf, loss_acc, gscale, st);
+  if (e == hipSuccess) e = launch_train_fwd(plan, tp, mlp, ba, e_buf, g_buf, loss_acc, gscale, plan->loss, st);
   // 16-bit backward operands carry dz times a power of two that brings the
   // per-sample gradient scale S*2/B back to about one
   float bscale = 1.0f;
@@ -458,7 +478,7 @@ int ngvol_train_step(const ngvol_plan* plan, const ngvol_train_state* s, const n
     e = launch_bwd(plan, 0, mlp, e_buf, g_buf, ba, s->grad, de, partial, ws.bwd_grid, flag, bscale, st);
   if (e == hipSuccess) e = launch_reduce_partials(plan, partial, ws.bwd_grid, s->grad, flag, st);
   if (e == hipSuccess) e = launch_scatter(plan, ws.sc, ba, de, s->grad, base + ws.scatter_off, st);
-  AdamArgs aa{a->learning_rate, a->beta1, a->beta2, a->epsilon, 1.0f / loss_scale};
+  const AdamArgs aa = adam_args(a, loss_scale);
   if (e == hipSuccess)
     e = launch_adam(plan, s->params, reinterpret_cast<__half*>(s->table_f16), s->grad, s->adam_m, s->adam_v, s->step,
                     flag, aa, st);
@@ -475,7 +495,7 @@ int ngvol_adam_step(const ngvol_plan* plan, const ngvol_train_state* s, const ng
   char* base = reinterpret_cast<char*>(s->workspace);
   double* loss_acc = reinterpret_cast<double*>(base);
   int32_t* flag = reinterpret_cast<int32_t*>(base + 8);
-  AdamArgs aa{a->learning_rate, a->beta1, a->beta2, a->epsilon, 1.0f / loss_scale};
+  const AdamArgs aa = adam_args(a, loss_scale);
   hipError_t e = launch_step_begin(loss_acc, flag, st);
   if (e == hipSuccess)
     e = launch_adam(plan, s->params, reinterpret_cast<__half*>(s->table_f16), s->grad, s->adam_m, s->adam_v, s->step,

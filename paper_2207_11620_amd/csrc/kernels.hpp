@@ -124,7 +124,14 @@ constexpr size_t kLdsLimit = 160 * 1024;
 // the waves per workgroup those kernels use
 size_t enc_lds_bytes(const ngvol_plan* plan, int waves);
 int enc_waves(const ngvol_plan* plan);
-size_t bwd_lds_bytes(const ngvol_plan* plan, int waves);
+// MLP backward launch shape: waves per workgroup and where dW accumulates
+// (LDS, or gdw: the workgroup's row of the partial-sum buffer).
+struct BwdConfig {
+  int waves;
+  bool gdw;
+};
+size_t bwd_lds_bytes(const ngvol_plan* plan, int waves, bool gdw);
+BwdConfig bwd_config(const ngvol_plan* plan);
 int bwd_waves(const ngvol_plan* plan);
 int bwd_grid(const ngvol_plan* plan, int64_t n);
 TrainWorkspace train_workspace(const ngvol_plan* plan, int64_t B);
@@ -142,7 +149,7 @@ hipError_t launch_sq_error_grid(const ngvol_plan* plan, TablePtrs tp, const floa
 hipError_t launch_mlp_fwd(const ngvol_plan* plan, const float* mlp, const void* feat, int dtype, int64_t n,
                           float* out, hipStream_t st);
 hipError_t launch_train_fwd(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const BatchArgs& ba, void* e_buf,
-                            float* g_buf, double* loss_acc, float gscale, hipStream_t st);
+                            float* g_buf, double* loss_acc, float gscale, int loss, hipStream_t st);
 hipError_t launch_sample_batch(const BatchArgs& ba, float* xyz, float* y, hipStream_t st);
 
 // Backward.  MODE 0: training (e_buf holds the stored encoding in the
@@ -158,8 +165,14 @@ hipError_t launch_reduce_partials(const ngvol_plan* plan, const float* partial, 
 hipError_t launch_encode_bwd(const ngvol_plan* plan, const float* xyz, int64_t n, const float* dfeat, float* grad,
                              hipStream_t st);
 
+// Adam with bias correction; step k (0-based applied steps) uses
+// lr * decay_base^floor((k - decay_start) / decay_interval) once k >= decay_start
+// (decay_interval > 0), and l2_reg * w is added to the MLP weights' gradient.
 struct AdamArgs {
   double lr, b1, b2, eps;
+  double l2_reg;
+  int64_t decay_start, decay_interval;
+  double decay_base;
   float inv_scale;
 };
 hipError_t launch_adam(const ngvol_plan* plan, float* params, __half* table_f16, float* grad, float* m, float* v,

@@ -20,13 +20,13 @@ __host__ __device__ constexpr size_t bwd_wave_bytes(int nh) {
   return (size_t)nh * (W / 16) * 64 * 16 + 2 * (size_t)(KIN > W ? KIN : W) * kPitch * (P ? 2 : 4);
 }
 
-size_t bwd_lds_bytes(const ngvol_plan* plan, int waves) {
+size_t bwd_lds_bytes(const ngvol_plan* plan, int waves, bool gdw) {
   const int P = plan->layout.precision, KIN = plan->kin, W = plan->layout.n_neurons, nh = plan->md.n_hidden;
   const int ch0 = P ? KIN / 32 : KIN / 4;
   const int chh = P ? (W + 31) / 32 : W / 4;
   const int frags = (W / 16) * ch0 + (nh - 1) * (W / 16) * chh + (KIN / 16) * chh + (nh - 1) * (W / 16) * chh;
   size_t b = (size_t)frags * 64 * (P ? 16 : 4) + (size_t)W * 4;
-  b += ((size_t)plan->md.n_mlp * 4 + 15) / 16 * 16;
+  if (!gdw) b += ((size_t)plan->md.n_mlp * 4 + 15) / 16 * 16;
   const size_t wave = (size_t)nh * (W / 16) * 64 * 16 + 2 * (size_t)(KIN > W ? KIN : W) * kPitch * (P ? 2 : 4);
   return b + wave * waves;
 }
@@ -35,9 +35,12 @@ size_t bwd_lds_bytes(const ngvol_plan* plan, int waves) {
 // MLP backward: dW (per-block partial sums) and dL/dfeature written to dfeat.
 // MODE 0 reads the training forward's stored encoding ([B][KIN], 16-bit or
 // FP32), MODE 1 caller features ([n][n_in] FP32).  The table scatter of
-// dfeat is a separate pass (bucketed, see kernels_scatter.hip).
+// dfeat is a separate pass (bucketed, see kernels_scatter.hip).  dW
+// accumulates in LDS, or with GDW (networks whose LDS dW would leave room
+// for fewer than four waves) directly in the workgroup's own row of
+// `partial`, which then lives in L2.
 // ---------------------------------------------------------------------------
-template <int P, int KIN, int W, int MODE>
+template <int P, int KIN, int W, int MODE, bool GDW>
 __global__ void __launch_bounds__(64 * kBwdMaxWaves) k_bwd(ModelDesc md, const float* __restrict__ mlp,
                                              const void* __restrict__ e_buf, const float* __restrict__ g_buf,
                                              BatchArgs ba, float* __restrict__ grad, float* __restrict__ dfeat,
@@ -63,8 +66,13 @@ __global__ void __launch_bounds__(64 * kBwdMaxWaves) k_bwd(ModelDesc md, const f
   size_t off = (size_t)all_frags * 64 * sizeof(Frag);
   float* lds_wout = reinterpret_cast<float*>(smem + off);
   off += W * 4;
-  float* lds_dw = reinterpret_cast<float*>(smem + off);
-  off += ((size_t)md.n_mlp * 4 + 15) / 16 * 16;
+  float* lds_dw;
+  if constexpr (GDW) {
+    lds_dw = partial + (size_t)blockIdx.x * md.n_mlp;
+  } else {
+    lds_dw = reinterpret_cast<float*>(smem + off);
+    off += ((size_t)md.n_mlp * 4 + 15) / 16 * 16;
+  }
   const int wave = threadIdx.x >> 6;
   unsigned char* wbase = smem + off + (size_t)wave * bwd_wave_bytes<P, KIN, W>(nh);
   f32x4* zbuf = reinterpret_cast<f32x4*>(wbase);
@@ -292,9 +300,11 @@ __global__ void __launch_bounds__(64 * kBwdMaxWaves) k_bwd(ModelDesc md, const f
       if (nl == 0 && v != 0.0f) atomicAdd(lds_dw + md.w_off[nh] + 16 * mb + 4 * g + j, v);
     }
   if (bad) *nonfinite = 1;
-  __syncthreads();
-  float* dst = partial + (size_t)blockIdx.x * md.n_mlp;
-  for (int t = threadIdx.x; t < md.n_mlp; t += blockDim.x) dst[t] = lds_dw[t];
+  if constexpr (!GDW) {
+    __syncthreads();
+    float* dst = partial + (size_t)blockIdx.x * md.n_mlp;
+    for (int t = threadIdx.x; t < md.n_mlp; t += blockDim.x) dst[t] = lds_dw[t];
+  }
 }
 
 // grad_mlp[k] += sum over blocks of partial[b][k], in a fixed order: a
@@ -340,7 +350,9 @@ __global__ void __launch_bounds__(256) k_encode_bwd(ModelDesc md, const float* _
 // ---------------------------------------------------------------------------
 // Adam over all parameters; skipped (gradient only cleared) when a
 // non-finite contribution was seen.  t = step + 1; c1 = 1 - b1^t and
-// c2 = 1 - b2^t in FP64.
+// c2 = 1 - b2^t in FP64; the step's learning rate follows the exponential
+// decay schedule of the arguments, and l2_reg * w joins the gradient of the
+// MLP weights (indices >= n_table).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_adam(int64_t n, int64_t n_table, float* __restrict__ params,
                                               __half* __restrict__ table_f16, float* __restrict__ grad,
@@ -350,27 +362,33 @@ __global__ void __launch_bounds__(256) k_adam(int64_t n, int64_t n_table, float*
   __shared__ float coef[3];
   const bool skip = *nonfinite != 0;
   if (threadIdx.x == 0) {
-    const double t = (double)(*step + 1);
+    const int64_t k = *step;
+    double lr = a.lr;
+    if (a.decay_interval > 0 && k >= a.decay_start)
+      lr *= pow(a.decay_base, (double)((k - a.decay_start) / a.decay_interval));
+    const double t = (double)(k + 1);
     const double c1 = 1.0 - pow(a.b1, t);
     const double c2 = 1.0 - pow(a.b2, t);
-    coef[0] = (float)(a.lr / c1);  // lr / c1
-    coef[1] = (float)(1.0 / c2);   // 1 / c2
-    coef[2] = 0.0f;
+    coef[0] = (float)(lr / c1);   // lr_k / c1
+    coef[1] = (float)(1.0 / c2);  // 1 / c2
+    coef[2] = (float)a.l2_reg;
   }
   __syncthreads();
-  const float lr_c1 = coef[0], inv_c2 = coef[1];
+  const float lr_c1 = coef[0], inv_c2 = coef[1], l2 = coef[2];
   const float b1 = (float)a.b1, b2 = (float)a.b2, eps = (float)a.eps;
   const float omb1 = (float)(1.0 - a.b1), omb2 = (float)(1.0 - a.b2);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const float gr = grad[i] * a.inv_scale;
+    float gr = grad[i] * a.inv_scale;
     grad[i] = 0.0f;
     if (skip) continue;
+    const float w = params[i];
+    if (i >= n_table) gr = __builtin_fmaf(l2, w, gr);
     const float mi = __builtin_fmaf(b1, m[i], omb1 * gr);
     const float vi = __builtin_fmaf(b2, v[i], omb2 * gr * gr);
     m[i] = mi;
     v[i] = vi;
-    const float p = params[i] - lr_c1 * mi / (sqrtf(vi * inv_c2) + eps);
+    const float p = w - lr_c1 * mi / (sqrtf(vi * inv_c2) + eps);
     params[i] = p;
     if (table_f16 && i < n_table) table_f16[i] = __float2half_rn(p);
   }
@@ -397,13 +415,21 @@ __global__ void __launch_bounds__(256) k_make_f16(const float* __restrict__ p, _
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
-int bwd_waves(const ngvol_plan* plan) {
+BwdConfig bwd_config(const ngvol_plan* plan) {
   // as many waves per workgroup (up to 8) as the LDS holds: one workgroup
-  // per CU accumulates dW, so its waves are the CU's latency hiding
-  for (int w = kBwdMaxWaves; w > 1; w >>= 1)
-    if (bwd_lds_bytes(plan, w) <= kLdsLimit) return w;
-  return 1;
+  // per CU accumulates dW, so its waves are the CU's latency hiding.  dW
+  // moves out of LDS when that buys more waves than the LDS form's (< 4).
+  auto most = [&](bool gdw) {
+    for (int w = kBwdMaxWaves; w >= 1; w >>= 1)
+      if (bwd_lds_bytes(plan, w, gdw) <= kLdsLimit) return w;
+    return 0;
+  };
+  const int wl = most(false), wg = most(true);
+  if (wl >= 4 || wl >= wg) return BwdConfig{wl > 0 ? wl : 1, false};
+  return BwdConfig{wg, true};
 }
+
+int bwd_waves(const ngvol_plan* plan) { return bwd_config(plan).waves; }
 
 int bwd_grid(const ngvol_plan* plan, int64_t n) {
   const int64_t n_tiles = (n + 15) / 16;
@@ -419,17 +445,22 @@ hipError_t launch_bwd(const ngvol_plan* plan, int mode, const float* mlp, const 
                       const BatchArgs& ba, float* grad, float* dfeat, float* partial, int grid, int32_t* nonfinite,
                       float bscale, hipStream_t st) {
   const ModelDesc& md = plan->md;
-  const int waves = bwd_waves(plan);
-  const size_t lds = bwd_lds_bytes(plan, waves);
+  const BwdConfig bc = bwd_config(plan);
+  const int waves = bc.waves;
+  const size_t lds = bwd_lds_bytes(plan, waves, bc.gdw);
   const int P_ = plan->layout.precision;
-#define NGV_BWD_LAUNCH(P, KIN, W)                                                                                   \
-  do {                                                                                                             \
-    if (mode == 0)                                                                                                 \
-      hipLaunchKernelGGL((k_bwd<P, KIN, W, 0>), dim3(grid), dim3(64 * waves), lds, st, md, mlp, e_buf, g_buf,     \
-                         ba, grad, dfeat, partial, nonfinite, bscale);                                             \
-    else                                                                                                           \
-      hipLaunchKernelGGL((k_bwd<P, KIN, W, 1>), dim3(grid), dim3(64 * waves), lds, st, md, mlp, e_buf, g_buf,     \
-                         ba, grad, dfeat, partial, nonfinite, bscale);                                             \
+#define NGV_BWD_GO(P, KIN, W, M, G)                                                                                 \
+  hipLaunchKernelGGL((k_bwd<P, KIN, W, M, G>), dim3(grid), dim3(64 * waves), lds, st, md, mlp, e_buf, g_buf, ba,  \
+                     grad, dfeat, partial, nonfinite, bscale)
+#define NGV_BWD_LAUNCH(P, KIN, W)                          \
+  do {                                                    \
+    if (mode == 0) {                                      \
+      if (bc.gdw) NGV_BWD_GO(P, KIN, W, 0, true);         \
+      else NGV_BWD_GO(P, KIN, W, 0, false);               \
+    } else {                                              \
+      if (bc.gdw) NGV_BWD_GO(P, KIN, W, 1, true);         \
+      else NGV_BWD_GO(P, KIN, W, 1, false);               \
+    }                                                     \
   } while (0)
 #define NGV_BWD_W(P, KIN)                                      \
   do {                                                         \
@@ -449,6 +480,7 @@ hipError_t launch_bwd(const ngvol_plan* plan, int mode, const float* mlp, const 
 #undef NGV_BWD_K
 #undef NGV_BWD_W
 #undef NGV_BWD_LAUNCH
+#undef NGV_BWD_GO
   return hipGetLastError();
 }
 

@@ -212,12 +212,13 @@ k_mlp_fwd(ModelDesc md, const float* __restrict__ mlp,
 
 // ---------------------------------------------------------------------------
 // Training forward: sampling step (or explicit batch), encoding (stored for
-// the backward), MLP, loss, and g = S * dL/dy = S * 2 (y_hat - y) / B.
+// the backward), MLP, loss, and g = S * dL/dy: gscale * (y_hat - y) for L2
+// (gscale = 2S/B), gscale * sign(y_hat - y) for L1 (gscale = S/B).
 // ---------------------------------------------------------------------------
 template <int P, int F, int KIN, int W, typename TT, typename VT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P != 0 && KIN == 32 ? 4 : 1)))
 k_train_fwd(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, BatchArgs ba, void* __restrict__ e_buf,
-            float* __restrict__ g_buf, double* __restrict__ loss_acc, float gscale) {
+            float* __restrict__ g_buf, double* __restrict__ loss_acc, float gscale, int l1) {
   typedef typename Prec<P>::Frag Frag;
   typedef typename Prec<P>::T T;
   typedef WeightLayout<P, KIN, W> WL;
@@ -263,8 +264,13 @@ k_train_fwd(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, BatchArgs
     wave_sync();
     if (valid) {
       const float r = yv - target;
-      g_buf[s] = gscale * r;
-      lsum += (double)r * (double)r;
+      if (l1) {
+        g_buf[s] = r > 0.0f ? gscale : (r < 0.0f ? -gscale : 0.0f);
+        lsum += (double)fabsf(r);
+      } else {
+        g_buf[s] = gscale * r;
+        lsum += (double)r * (double)r;
+      }
     }
   }
   lsum = wave_sum(lsum);
@@ -414,8 +420,9 @@ hipError_t launch_mlp_fwd(const ngvol_plan* plan, const float* mlp, const void* 
 }
 
 hipError_t launch_train_fwd(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const BatchArgs& ba, void* e_buf,
-                            float* g_buf, double* loss_acc, float gscale, hipStream_t st) {
+                            float* g_buf, double* loss_acc, float gscale, int loss, hipStream_t st) {
   const ModelDesc& md = plan->md;
+  const int l1 = loss == NGVOL_LOSS_L1;
   const int64_t n_groups = (ba.B + 63) / 64;  // 64 samples per wave
   const int waves = enc_waves(plan);
   const size_t lds = enc_lds_bytes(plan, waves);
@@ -425,17 +432,17 @@ hipError_t launch_train_fwd(const ngvol_plan* plan, TablePtrs tp, const float* m
     if (tp.f16) {
       if (vf16)
         hipLaunchKernelGGL((k_train_fwd<P, F, KIN, W, __half, __half>), dim3(grid), dim3(64 * waves), lds, st, md, tp, mlp, ba,
-                           e_buf, g_buf, loss_acc, gscale);
+                           e_buf, g_buf, loss_acc, gscale, l1);
       else
         hipLaunchKernelGGL((k_train_fwd<P, F, KIN, W, __half, float>), dim3(grid), dim3(64 * waves), lds, st, md, tp, mlp, ba,
-                           e_buf, g_buf, loss_acc, gscale);
+                           e_buf, g_buf, loss_acc, gscale, l1);
     } else {
       if (vf16)
         hipLaunchKernelGGL((k_train_fwd<P, F, KIN, W, float, __half>), dim3(grid), dim3(64 * waves), lds, st, md, tp, mlp, ba,
-                           e_buf, g_buf, loss_acc, gscale);
+                           e_buf, g_buf, loss_acc, gscale, l1);
       else
         hipLaunchKernelGGL((k_train_fwd<P, F, KIN, W, float, float>), dim3(grid), dim3(64 * waves), lds, st, md, tp, mlp, ba,
-                           e_buf, g_buf, loss_acc, gscale);
+                           e_buf, g_buf, loss_acc, gscale, l1);
     }
   })));
   return hipGetLastError();

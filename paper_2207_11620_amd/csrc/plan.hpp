@@ -31,6 +31,7 @@ struct ngvol_plan {
   ngvol_layout layout;
   ngvol::ModelDesc md;
   int kin;    // input width padded to a multiple of 32 (MFMA K blocks)
+  int loss;   // NGVOL_LOSS_L2 | NGVOL_LOSS_L1 (training steps)
   int cus;    // compute units of the device the plan was created on
   int device;
 };

@@ -30,11 +30,11 @@ def oracle_model(name):
     return oracle.Model(c["L"], c["F"], c["log2T"], res, c["width"], c["n_hidden"])
 
 
-def gpu_plan(name, precision="fp32"):
+def gpu_plan(name, precision="fp32", loss="l2"):
     import paper_2207_11620_amd as ngv
     c = MODELS[name]
     return ngv.Plan(c["L"], c["F"], c["log2T"], c["base"], c["scale"] or 2.0, c["maxres"], n_neurons=c["width"],
-                    n_hidden_layers=c["n_hidden"], precision=precision)
+                    n_hidden_layers=c["n_hidden"], precision=precision, loss=loss)
 
 
 def init_params(name, seed=SEED, table_scale=None):

@@ -431,6 +431,88 @@ def test_nonfinite_step_is_skipped():
     assert host(st.skipped)[0] == 1 and host(st.step)[0] == 1
 
 
+@pytest.mark.parametrize("name,prec,tol", [("tiny", "fp32", 1e-4), ("paper", "fp32", 1e-4), ("paper", "bf16", None)])
+def test_l1_train_step_gradient(name, prec, tol):
+    # L1 loss (the paper's default): g = S sign(y_hat - y) / B.  Targets sit
+    # 0.01-0.1 away from the model, so both sides take the same sign decisions
+    m = oracle_model(name)
+    p = gpu_plan(name, prec, loss="l1")
+    params = init_params(name, table_scale=0.3)
+    B = 4096 + 77
+    xyz = oracle.batch_coords(SEED, 5, B)
+    rng = np.random.default_rng(3)
+    y = oracle.forward(m, params.astype(np.float64), xyz) + rng.choice([-1.0, 1.0], B) * rng.uniform(0.01, 0.1, B)
+    y = y.astype(np.float32)
+    loss_ref, g_ref = oracle.loss_grad(m, params.astype(np.float64), xyz, y, loss="l1")
+    st = ngv.TrainState(p, dev(params), B, f16_tables=False)
+    ngv.train_step(st, xyz=dev(xyz), target=dev(y), lr=5e-3, betas=(0.9, 0.999), eps=1e-15, loss_scale=128.0)
+    g = host(st.m).astype(np.float64) / (1 - np.float32(0.9))
+    if tol is None:
+        _check_grad_bf16(g, g_ref, m)
+    else:
+        _check_grad(g, g_ref, m, tol)
+    assert host(st.step)[0] == 1 and host(st.skipped)[0] == 0
+    assert host(st.loss)[0] == pytest.approx(loss_ref, rel=1e-5 if prec == "fp32" else 5e-2)
+
+
+@pytest.mark.parametrize("k", [0, 4, 5, 6, 7, 11])
+def test_scheduled_adam_step_matches_oracle(k):
+    # decayed rate (start 5, interval 2, base 0.5) at the device step counter k,
+    # L2 regularisation on the MLP weights only, FP16 shadow refreshed
+    name = "tiny"
+    m = oracle_model(name)
+    p = gpu_plan(name)
+    rng = np.random.default_rng(100 + k)
+    params = init_params(name, table_scale=0.3)
+    st = ngv.TrainState(p, dev(params), 256, f16_tables=True)
+    n = m.n_params
+    g = rng.normal(size=n).astype(np.float32)
+    g[rng.random(n) < 0.2] = 0.0
+    m0 = (rng.normal(size=n) * 0.1).astype(np.float32)
+    v0 = (rng.random(n) * 0.01).astype(np.float32)
+    S = 64.0
+    st.grad.copy_(dev(g * np.float32(S)))
+    st.m.copy_(dev(m0))
+    st.v.copy_(dev(v0))
+    st.step.fill_(k)
+    decay, l2 = (5, 2, 0.5), 0.1
+    ngv.adam_step(st, lr=1e-2, betas=(0.9, 0.99), eps=1e-15, loss_scale=S, l2_reg=l2, decay=decay)
+    th, mm, vv = params.astype(np.float64), m0.astype(np.float64), v0.astype(np.float64)
+    oracle.adam(th, mm, vv, g.astype(np.float64), k + 1, oracle.lr_at(1e-2, k, decay), 0.9, 0.99, 1e-15,
+                l2_reg=l2, reg_from=m.n_table)
+    got = host(st.params).astype(np.float64)
+    np.testing.assert_allclose(got - params, th - params, rtol=1e-4, atol=2e-7)
+    # m near zero is a cancellation of two FP32 terms of size ~0.1: a few ulp of those
+    np.testing.assert_allclose(host(st.m), mm, rtol=1e-5, atol=5e-8)
+    np.testing.assert_allclose(host(st.v), vv, rtol=1e-5, atol=1e-12)
+    assert host(st.step)[0] == k + 1 and np.all(host(st.grad) == 0)
+    np.testing.assert_array_equal(host(st.table_f16), host(st.params)[:m.n_table].astype(np.float16))
+
+
+def test_paper_default_training_matches_oracle_psnr():
+    # L1, exponentially decaying rate and L2 regularisation over 60 steps
+    # across two decay boundaries
+    vol = synth.gaussian_blobs(64, SEED)
+    m = oracle_model("tiny")
+    opt = dict(lr=5e-3, betas=(0.9, 0.999), eps=1e-15, l2_reg=1e-6, decay=(20, 20, 0.5))
+    th, _, _ = oracle.train(m, init_params("tiny").astype(np.float64), vol, SEED, 60, 4096, 5e-3, 0.9, 0.999,
+                            1e-15, loss="l1", l2_reg=1e-6, decay=(20, 20, 0.5))
+    psnr_o = oracle.psnr_from_mse(oracle.mse_grid(m, th, vol))
+    res = {}
+    for prec, f16 in (("fp32", False), ("bf16", True)):
+        p = gpu_plan("tiny", prec, loss="l1")
+        st = ngv.TrainState(p, dev(init_params("tiny")), 4096, f16_tables=f16)
+        vt = dev(vol)
+        for s in range(60):
+            ngv.train_step(st, volume=vt, seed=SEED, step_index=s, loss_scale=128.0, **opt)
+        params, f16t = st.weights()
+        res[prec] = ngv.psnr(p, params, vt, table_f16=f16t)
+    print(f"tiny L1 PSNR oracle {psnr_o:.3f}  fp32 {res['fp32']:.3f}  bf16 {res['bf16']:.3f}")
+    assert psnr_o > 20
+    assert abs(res["fp32"] - psnr_o) <= 0.5
+    assert res["bf16"] >= res["fp32"] - 0.5
+
+
 # --------------------------------------------------------------- sampling -----
 
 def test_sampling_step_matches_oracle():

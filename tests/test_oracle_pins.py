@@ -310,6 +310,72 @@ def test_gradient_matches_torch_autograd_for_mlp_block():
     np.testing.assert_allclose(g[:m.n_table], gt, rtol=1e-12, atol=1e-15)
 
 
+def test_l1_gradient_central_differences():
+    # L1 (the paper's default loss, Section 3.1): mean |Phi - y|.  Targets sit
+    # at least 0.05 away from the model so no residual changes sign within +-h
+    m = small_model(L=3, F=2, log2T=10, res=(5, 9, 17), width=16, n_hidden=2)
+    params = rand_params(m, seed=14)
+    rng = np.random.default_rng(15)
+    xyz = rng.random((48, 3)).astype(np.float32)
+    out0 = oracle.forward(m, params, xyz)
+    y = out0 + rng.choice([-1.0, 1.0], 48) * rng.uniform(0.05, 0.3, 48)
+
+    def l1(p):
+        return float(np.mean(np.abs(oracle.forward(m, p, xyz) - y)))
+
+    loss, g = oracle.loss_grad(m, params, xyz, y, loss="l1")
+    assert loss == pytest.approx(l1(params), rel=1e-13)
+    # the L2 gradient of the same batch differs (a swapped loss kind fails here)
+    _, g2 = oracle.loss_grad(m, params, xyz, y)
+    assert np.max(np.abs(g2 - g)) > 1e-3
+    h = 1e-4
+    checked = 0
+    cand = list(range(0, m.n_table, 13)) + list(range(m.n_table, m.n_params, 3))
+    for i in cand:
+        p1, p2, p3 = params.copy(), params.copy(), params.copy()
+        p1[i] += h
+        p2[i] -= h
+        p3[i] += 2 * h
+        la, lb, l0, lc = l1(p1), l1(p2), l1(params), l1(p3)
+        # piecewise polynomial in one parameter: skip where a ReLU flips
+        if abs((lc - la) - (la - l0)) > 1e-9 or abs((la - l0) - (l0 - lb)) > 1e-9:
+            continue
+        assert (la - lb) / (2 * h) == pytest.approx(g[i], rel=1e-6, abs=1e-10), i
+        checked += 1
+    assert checked > 0.8 * len(cand)
+
+
+def test_l1_gradient_matches_torch_autograd():
+    torch = pytest.importorskip("torch")
+    m = small_model(L=3, F=2, log2T=10, res=(5, 9, 17), width=16, n_hidden=3)
+    params = rand_params(m, seed=16)
+    rng = np.random.default_rng(17)
+    xyz = rng.random((128, 3)).astype(np.float32)
+    y = rng.random(128)
+    _, g = oracle.loss_grad(m, params, xyz, y, loss="l1")
+    e = torch.tensor(oracle.encode(m, params, xyz), dtype=torch.float64, requires_grad=True)
+    Ws = []
+    pos = m.n_table
+    for (o, i) in synth.mlp_shapes(m.n_in, m.width, m.n_hidden):
+        Ws.append(torch.tensor(params[pos:pos + o * i].reshape(o, i), dtype=torch.float64, requires_grad=True))
+        pos += o * i
+    h = e
+    for W in Ws[:-1]:
+        h = torch.relu(torch.nn.functional.linear(h, W))
+    out = torch.nn.functional.linear(h, Ws[-1])[:, 0]
+    torch.nn.functional.l1_loss(out, torch.tensor(y)).backward()
+    gm = np.concatenate([W.grad.numpy().ravel() for W in Ws])
+    np.testing.assert_allclose(g[m.n_table:], gm, rtol=1e-12, atol=1e-15)
+    idx, w = oracle.encode_debug(m, xyz)
+    de = e.grad.numpy()
+    gt = np.zeros(m.n_table)
+    for l in range(m.L):
+        for f in range(m.F):
+            slots = 2 * (m.level_offset[l] + idx[:, l, :].astype(np.int64)) + f
+            np.add.at(gt, slots.ravel(), (w[:, l, :] * de[:, 2 * l + f][:, None]).ravel())
+    np.testing.assert_allclose(g[:m.n_table], gt, rtol=1e-12, atol=1e-15)
+
+
 # -------------------------------------------------------------- Adam -----
 
 def test_adam_first_step_closed_form():
@@ -343,6 +409,64 @@ def test_adam_matches_torch_optim():
         oracle.adam(theta, mm, vv, g, t, 1e-2, 0.9, 0.99, 1e-15)
         tp.grad = torch.tensor(g)
         opt.step()
+    np.testing.assert_allclose(theta, tp.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_adam_l2_reg_matches_torch_weight_decay():
+    # L2 regularisation of the network weights = torch Adam's (coupled)
+    # weight_decay on the MLP block only
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(18)
+    n_table, n = 300, 420
+    theta = rng.normal(size=n)
+    tt = torch.tensor(theta[:n_table].copy(), requires_grad=True)
+    tw = torch.tensor(theta[n_table:].copy(), requires_grad=True)
+    opt = torch.optim.Adam([{"params": [tt], "weight_decay": 0.0}, {"params": [tw], "weight_decay": 0.05}],
+                           lr=5e-3, betas=(0.9, 0.999), eps=1e-15)
+    mm, vv = np.zeros(n), np.zeros(n)
+    for t in range(1, 16):
+        g = rng.normal(size=n)
+        g[rng.random(n) < 0.3] = 0.0
+        oracle.adam(theta, mm, vv, g, t, 5e-3, 0.9, 0.999, 1e-15, l2_reg=0.05, reg_from=n_table)
+        tt.grad = torch.tensor(g[:n_table])
+        tw.grad = torch.tensor(g[n_table:])
+        opt.step()
+    np.testing.assert_allclose(theta[:n_table], tt.detach().numpy(), rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(theta[n_table:], tw.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_lr_decay_paper_default_values():
+    # appendix default optimiser: lr 5e-3, decay start 2000, interval 1000, base 0.99
+    d = (2000, 1000, 0.99)
+    assert oracle.lr_at(5e-3, 0, d) == 5e-3
+    assert oracle.lr_at(5e-3, 1999, d) == 5e-3
+    assert oracle.lr_at(5e-3, 2999, d) == 5e-3
+    assert oracle.lr_at(5e-3, 3000, d) == pytest.approx(5e-3 * 0.99, rel=1e-15)
+    assert oracle.lr_at(5e-3, 12999, d) == pytest.approx(5e-3 * 0.99 ** 10, rel=1e-14)
+    assert oracle.lr_at(5e-3, 10 ** 6, None) == 5e-3
+
+
+def test_lr_decay_matches_torch_schedulers():
+    # constant for `start` steps, then a staircase decay: torch's ConstantLR
+    # (factor 1) followed by StepLR
+    torch = pytest.importorskip("torch")
+    start, interval, base = 5, 3, 0.5
+    rng = np.random.default_rng(19)
+    n = 64
+    theta = rng.normal(size=n)
+    tp = torch.tensor(theta.copy(), requires_grad=True)
+    opt = torch.optim.Adam([tp], lr=1e-2, betas=(0.9, 0.99), eps=1e-15)
+    sch = torch.optim.lr_scheduler.SequentialLR(
+        opt, [torch.optim.lr_scheduler.ConstantLR(opt, factor=1.0, total_iters=start),
+              torch.optim.lr_scheduler.StepLR(opt, step_size=interval, gamma=base)], milestones=[start])
+    mm, vv = np.zeros(n), np.zeros(n)
+    for k in range(20):
+        assert oracle.lr_at(1e-2, k, (start, interval, base)) == pytest.approx(opt.param_groups[0]["lr"], rel=1e-14)
+        g = rng.normal(size=n)
+        oracle.adam(theta, mm, vv, g, k + 1, oracle.lr_at(1e-2, k, (start, interval, base)), 0.9, 0.99, 1e-15)
+        tp.grad = torch.tensor(g)
+        opt.step()
+        sch.step()
     np.testing.assert_allclose(theta, tp.detach().numpy(), rtol=1e-12, atol=1e-14)
 
 
