@@ -15,8 +15,10 @@ frames through the trained model with one training step per frame), the
 roofline of the query pass (level kernel + MLP on the feature planes,
 measured with events on the launch stream; HBM traffic from the committed
 counter summary while the kernel sources match it), the standalone MLP on
-the matrix cores, a batch of 16 volumes, and the FP64 CPU oracle timed on a
-bounded sample of the same workload.
+the matrix cores, a batch of 16 volumes, the paper's default training
+setting (L1 loss, decaying learning rate, L2 regularisation) on its fixed
+Table-2 network at 65,536 samples per step, and the FP64 CPU oracle timed on
+a bounded sample of the same workload.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
 """

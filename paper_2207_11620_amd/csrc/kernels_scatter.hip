@@ -24,7 +24,7 @@ namespace {
 
 constexpr int kScThreads = 256;
 constexpr int kReduceThreads = 1024;
-constexpr int64_t kChunkRecords = 1 << 16;
+constexpr int64_t kChunkAdds = 1 << 17;  // LDS feature adds per reduce work item
 constexpr int kUnroll = 8;  // records per thread per round in the reduce
 
 struct Coords {
@@ -185,8 +185,13 @@ __global__ void __launch_bounds__(kReduceThreads) k_sc_reduce(const uint32_t* __
   const int64_t cnt = totals[bucket];
   const int64_t lo = (int64_t)items[3 + 2 * (size_t)blockIdx.x] * chunk_records;
   const int64_t hi = lo + chunk_records < cnt ? lo + chunk_records : cnt;
-  const int span = (1 << bshift) * F;
-  for (int t = threadIdx.x; t < span; t += blockDim.x) acc[t] = 0.0f;
+  // feature-major accumulator acc[f][entry] with a pitch of E + 1: the F
+  // adds of a record, and lanes adding the same feature of different
+  // entries, fall in different banks
+  const int E = 1 << bshift;
+  const int pitch = E + 1;
+  const int span = E * F;
+  for (int t = threadIdx.x; t < pitch * F; t += blockDim.x) acc[t] = 0.0f;
   __syncthreads();
   constexpr int RD = Rec<F>::dwords;
   const uint32_t base_entry = (uint32_t)bucket << bshift;
@@ -212,7 +217,7 @@ __global__ void __launch_bounds__(kReduceThreads) k_sc_reduce(const uint32_t* __
 #pragma unroll
       for (int f = 0; f < F; ++f) {
         const float v = __uint_as_float(w[u][1 + f]);
-        if (v != 0.0f) atomicAdd(acc + local * F + f, v);
+        if (v != 0.0f) atomicAdd(acc + f * pitch + local, v);
       }
     }
   }
@@ -225,9 +230,9 @@ __global__ void __launch_bounds__(kReduceThreads) k_sc_reduce(const uint32_t* __
     float a[U], old[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int t = t0 + u * (int)blockDim.x;
+      const int t = t0 + u * (int)blockDim.x;  // gradient order: entry t / F, feature t % F
       const bool in = t < span && first + t < last;
-      a[u] = in ? acc[t] : 0.0f;
+      a[u] = in ? acc[(t % F) * pitch + t / F] : 0.0f;
       old[u] = (owner && in) ? grad[first + t] : 0.0f;
     }
 #pragma unroll
@@ -256,9 +261,12 @@ ScatterPlan scatter_plan(const ngvol_plan* plan, int64_t B) {
   sp.chunk = (B + g - 1) / g;
   sp.rec_words = 1 + F;  // dwords per record
   sp.n_records = B * 8 * md.L;
-  sp.chunk_records = kChunkRecords;
+  // a chunk is one workgroup's serial share of a bucket's LDS adds: bound it
+  // to kChunkAdds feature adds so the hot coarse buckets spread over as many
+  // workgroups as their records need (F = 8: 16384 records a chunk)
+  sp.chunk_records = kChunkAdds / F;
   // upper bound of the work items: one partial chunk per bucket plus full chunks
-  sp.max_items = sp.n_buckets + (int)((sp.n_records + kChunkRecords - 1) / kChunkRecords);
+  sp.max_items = sp.n_buckets + (int)((sp.n_records + sp.chunk_records - 1) / sp.chunk_records);
   auto up = [](size_t v) { return (v + 255) / 256 * 256; };
   sp.rec_off = 0;
   sp.counts_off = up((size_t)sp.n_records * 4 * sp.rec_words);
@@ -284,7 +292,7 @@ hipError_t launch_scatter(const ngvol_plan* plan, const ScatterPlan& sp, const B
   launch_count_offsets(counts, sp.blocks, sp.n_buckets, totals, offsets, st);
   uint32_t* items = reinterpret_cast<uint32_t*>(base + sp.items_off);
   hipLaunchKernelGGL(k_sc_worklist, dim3(1), dim3(1024), 0, st, totals, sp.n_buckets, sp.chunk_records, items);
-  const size_t acc_lds = ((size_t)1 << sp.bshift) * md.F * 4;
+  const size_t acc_lds = (((size_t)1 << sp.bshift) + 1) * md.F * 4;
   const dim3 rgrid(sp.max_items);
   const int64_t n_entries = md.n_table / md.F;
 #define NGV_SC(FV)                                                                                                 \
