@@ -62,6 +62,11 @@ def lib():
             "orc_ray_points": (C.c_int, [P, C.c_int, C.c_int, u32, flt, i64, u32, u32, P]),
             "orc_render_pixels": (C.c_int, [P, P, P, P, C.c_int, C.c_int, flt, u32, P, i64, P, P, P]),
             "orc_num_threads": (C.c_int, []),
+            "orc_mc_cells": (C.c_int, [P, C.c_int, P, i64, P]),
+            "orc_mc_update": (C.c_int, [P, C.c_int, P, P, i64, P, P]),
+            "orc_mc_opacity": (C.c_int, [P, P, i64, P, P]),
+            "orc_render_pixels_mc": (C.c_int, [P, P, P, P, C.c_int, C.c_int, flt, u32, P, i64, P, C.c_int, P, P, P,
+                                               P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -250,6 +255,53 @@ def render_pixels(m: Model, params, cam, lut, W, H, dt, frame_seed, pix):
     n_used = np.zeros(n, np.uint32)
     _chk(lib().orc_render_pixels(_p(m.desc), _p(params), _p(cam), _p(lut), W, H, dt, frame_seed, _p(pix), n,
                                  _p(rgba), _p(n_geo), _p(n_used)))
+    return rgba, n_geo, n_used
+
+
+def mc_grid(dims, cell):
+    """Cells per axis (x, y, z) of a macro-cell grid over a volume of dims = (Dx, Dy, Dz)."""
+    return tuple((int(d) + cell - 1) // cell for d in dims)
+
+
+def mc_cells(dims, cell, xyz):
+    xyz = _f32(xyz)
+    out = np.zeros(xyz.shape[0], np.int64)
+    _chk(lib().orc_mc_cells(_p(np.asarray(dims, np.int32)), cell, _p(xyz), xyz.shape[0], _p(out)))
+    return out
+
+
+def mc_update(dims, cell, xyz, values, ranges=None):
+    """(vmin, vmax) per cell after the samples; ranges continues earlier ones."""
+    M = mc_grid(dims, cell)
+    n = M[0] * M[1] * M[2]
+    if ranges is None:
+        vmin, vmax = np.full(n, np.inf), np.full(n, -np.inf)
+    else:
+        vmin, vmax = (np.array(r, np.float64) for r in ranges)
+    xyz, values = _f32(xyz), _f32(values)
+    _chk(lib().orc_mc_update(_p(np.asarray(dims, np.int32)), cell, _p(xyz), _p(values), xyz.shape[0], _p(vmin),
+                             _p(vmax)))
+    return vmin, vmax
+
+
+def mc_opacity(ranges, lut):
+    vmin, vmax = (_f64(r) for r in ranges)
+    mu = np.zeros(vmin.size, np.float64)
+    _chk(lib().orc_mc_opacity(_p(vmin), _p(vmax), vmin.size, _p(_f32(lut)), _p(mu)))
+    return mu
+
+
+def render_pixels_mc(m: Model, params, cam, lut, W, H, dt, frame_seed, pix, dims, cell, mu):
+    params, cam, lut = _f64(params), _f32(cam), _f32(lut)
+    pix = np.ascontiguousarray(pix, dtype=np.int64)
+    n = pix.size
+    rgba = np.zeros((n, 4), np.float64)
+    n_geo = np.zeros(n, np.uint32)
+    n_used = np.zeros(n, np.uint32)
+    mu = None if mu is None else _f64(mu)
+    _chk(lib().orc_render_pixels_mc(_p(m.desc), _p(params), _p(cam), _p(lut), W, H, dt, frame_seed, _p(pix), n,
+                                    _p(np.asarray(dims, np.int32)), cell, None if mu is None else _p(mu), _p(rgba),
+                                    _p(n_geo), _p(n_used)))
     return rgba, n_geo, n_used
 
 

@@ -18,7 +18,8 @@
  *     network weights (Section 3.1 and the appendix's default optimiser;
  *     Kingma and Ba 2014);
  *   - the ray-marched emission-absorption renderer fed by streamed samples
- *     (Section 5.2.1);
+ *     (Section 5.2.1), with macro-cell value ranges built from training
+ *     samples and empty-space skipping (Section 5.3);
  *   - decoding the whole grid and its PSNR (Section 6).
  *
  * Readings of the paper where it is silent (the hash, the resolution rule,
@@ -705,9 +706,95 @@ int orc_ray_points(const float* cam, int W, int H, uint32_t frame_seed, float dt
  * rgba[n_pix][4] (premultiplied colour, accumulated alpha), n_geo[n_pix]
  * (geometric count), n_used[n_pix] (samples composited before stopping).
  */
-int orc_render_pixels(const int32_t* desc, const double* params, const float* cam, const float* lut, int W, int H,
-                      float dt, uint32_t frame_seed, const int64_t* pix, int64_t n_pix, double* rgba,
-                      uint32_t* n_geo, uint32_t* n_used)
+/* ------------------------------------------------------------------------ */
+/* Macro-cells (Section 5.3): disjoint cells of `cell` voxels per axis over  */
+/* a D_x x D_y x D_z volume, M_a = ceil(D_a / cell) per axis (the grid may   */
+/* extend past the volume).  Reading: a point p (clamped to [0,1], NaN as 0) */
+/* lies in voxel floor(p_a D_a), the product rounded to binary32, and in     */
+/* cell min(voxel / cell, M_a - 1).  Each cell keeps the range of the        */
+/* values seen in it; per the online construction of Section 5.3 the values  */
+/* are the training samples' targets.  The maximum opacity mu of a cell is    */
+/* the largest alpha the transfer function takes over its range, 0 for a     */
+/* cell no sample has reached.                                               */
+/* ------------------------------------------------------------------------ */
+static int64_t orc_mc_index(const float p[3], const int32_t* dims, int cell)
+{
+    int64_t c[3], M[3];
+    for (int a = 0; a < 3; ++a) {
+        M[a] = (dims[a] + cell - 1) / cell;
+        float q = (float)orc_clamp01f(p[a]);
+        float s = q * (float)dims[a];
+        int64_t vox = (int64_t)floorf(s);
+        c[a] = vox / cell;
+        if (c[a] > M[a] - 1) c[a] = M[a] - 1;
+    }
+    return (c[2] * M[1] + c[1]) * M[0] + c[0];
+}
+
+int orc_mc_cells(const int32_t* dims, int cell, const float* xyz, int64_t n, int64_t* out)
+{
+    for (int64_t i = 0; i < n; ++i) out[i] = orc_mc_index(xyz + 3 * i, dims, cell);
+    return 0;
+}
+
+/* vmin/vmax of every cell over the samples, in sample order; cells start
+ * empty (vmin = +inf, vmax = -inf) unless the caller passes earlier ranges. */
+int orc_mc_update(const int32_t* dims, int cell, const float* xyz, const float* values, int64_t n, double* vmin,
+                  double* vmax)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c = orc_mc_index(xyz + 3 * i, dims, cell);
+        double v = values[i];
+        if (v < vmin[c]) vmin[c] = v;
+        if (v > vmax[c]) vmax[c] = v;
+    }
+    return 0;
+}
+
+/* alpha of the shading transfer function at v: u = 255 clamp(v, 0, 1) and
+ * its fraction in binary32 (as the shading forms them), the blend in FP64 */
+static double orc_tf_alpha(const float* lut, float v)
+{
+    float c = v > 0.0f ? (v < 1.0f ? v : 1.0f) : 0.0f;
+    float u = 255.0f * c;
+    float fi = floorf(u);
+    if (fi > 254.0f) fi = 254.0f;
+    int i0 = (int)fi;
+    float fr = u - fi;
+    return (double)lut[4 * i0 + 3] + (double)fr * ((double)lut[4 * (i0 + 1) + 3] - (double)lut[4 * i0 + 3]);
+}
+
+/* mu = max of the piecewise-linear alpha over [vmin, vmax]: the two ends and
+ * every node strictly inside */
+int orc_mc_opacity(const double* vmin, const double* vmax, int64_t n_cells, const float* lut, double* mu)
+{
+    for (int64_t c = 0; c < n_cells; ++c) {
+        if (!(vmin[c] <= vmax[c])) {
+            mu[c] = 0.0;
+            continue;
+        }
+        float lo = (float)vmin[c], hi = (float)vmax[c];
+        double m = orc_tf_alpha(lut, lo);
+        double b = orc_tf_alpha(lut, hi);
+        if (b > m) m = b;
+        float ul = 255.0f * (lo > 0.0f ? (lo < 1.0f ? lo : 1.0f) : 0.0f);
+        float uh = 255.0f * (hi > 0.0f ? (hi < 1.0f ? hi : 1.0f) : 0.0f);
+        for (int i = 0; i < 256; ++i)
+            if ((float)i > ul && (float)i < uh && (double)lut[4 * i + 3] > m) m = lut[4 * i + 3];
+        mu[c] = m;
+    }
+    return 0;
+}
+
+/*
+ * Rendering of the listed pixels; with mu != NULL a sample whose macro-cell
+ * has mu = 0 is skipped (not evaluated, not composited): empty-space
+ * skipping.  n_used counts composited samples up to termination.
+ */
+int orc_render_pixels_mc(const int32_t* desc, const double* params, const float* cam, const float* lut, int W,
+                         int H, float dt, uint32_t frame_seed, const int64_t* pix, int64_t n_pix,
+                         const int32_t* mc_dims, int mc_cell, const double* mu, double* rgba, uint32_t* n_geo,
+                         uint32_t* n_used)
 {
     orc_model m;
     (void)H;
@@ -723,6 +810,7 @@ int orc_render_pixels(const int32_t* desc, const double* params, const float* ca
         for (uint32_t k = 0; k < r.n; ++k) {
             float pt[3];
             orc_ray_point(&r, k, dt, pt);
+            if (mu && !(mu[orc_mc_index(pt, mc_dims, mc_cell)] > 0.0)) continue;
             orc_encode_one(&m, params, pt, e);
             double v = orc_mlp_one(&m, Wm, e, NULL);
             if (!(v > 0.0)) v = 0.0;
@@ -738,7 +826,7 @@ int orc_render_pixels(const int32_t* desc, const double* params, const float* ca
             double a = c4[3];
             for (int ch = 0; ch < 3; ++ch) C[ch] += (1.0 - A) * a * c4[ch];
             A += (1.0 - A) * a;
-            used = k + 1;
+            used += 1;
             if (A >= 0.99) break;
         }
         for (int ch = 0; ch < 3; ++ch) rgba[4 * q + ch] = C[ch];
@@ -747,6 +835,14 @@ int orc_render_pixels(const int32_t* desc, const double* params, const float* ca
         n_used[q] = used;
     }
     return 0;
+}
+
+int orc_render_pixels(const int32_t* desc, const double* params, const float* cam, const float* lut, int W, int H,
+                      float dt, uint32_t frame_seed, const int64_t* pix, int64_t n_pix, double* rgba,
+                      uint32_t* n_geo, uint32_t* n_used)
+{
+    return orc_render_pixels_mc(desc, params, cam, lut, W, H, dt, frame_seed, pix, n_pix, NULL, 1, NULL, rgba,
+                                n_geo, n_used);
 }
 
 int orc_num_threads(void)

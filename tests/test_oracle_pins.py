@@ -572,3 +572,86 @@ def test_device_volume_generators_match_numpy():
     d = synth.fractal_value_noise_torch(20, 5, "cpu", dtype=torch.float32, chunk=6).numpy()
     np.testing.assert_allclose(c, d, atol=2e-6)
     assert len(synth.multi_volume_specs()) == 16
+
+
+# ------------------------------------------------------------ macro-cells -----
+
+def test_mc_cells_voxel_centres_and_edges():
+    # voxel centres fall in cell voxel // cell; the grid extends past a
+    # volume that is not a multiple of the cell size; p = 1 is in the last cell
+    dims, cell = (100, 64, 130), 64
+    assert oracle.mc_grid(dims, cell) == (2, 1, 3)
+    rng = np.random.default_rng(30)
+    vox = np.stack([rng.integers(0, d, 500) for d in dims], 1)
+    ctr = ((vox + 0.5) / np.array(dims)).astype(np.float32)
+    M = oracle.mc_grid(dims, cell)
+    c = vox // cell
+    want = (c[:, 2] * M[1] + c[:, 1]) * M[0] + c[:, 0]
+    np.testing.assert_array_equal(oracle.mc_cells(dims, cell, ctr), want)
+    edge = np.array([[0, 0, 0], [1, 1, 1], [-0.5, 2.0, np.nan]], np.float32)
+    np.testing.assert_array_equal(oracle.mc_cells(dims, cell, edge), [0, 5, 0])
+
+
+def test_mc_update_matches_grouped_min_max():
+    dims, cell = (64, 48, 80), 16
+    rng = np.random.default_rng(31)
+    xyz = rng.random((5000, 3)).astype(np.float32)
+    v = rng.normal(size=5000).astype(np.float32)
+    ids = oracle.mc_cells(dims, cell, xyz)
+    n = int(np.prod(oracle.mc_grid(dims, cell)))
+    lo, hi = np.full(n, np.inf), np.full(n, -np.inf)
+    np.minimum.at(lo, ids, v.astype(np.float64))
+    np.maximum.at(hi, ids, v.astype(np.float64))
+    # in two batches: ranges carry over
+    r = oracle.mc_update(dims, cell, xyz[:2000], v[:2000])
+    r = oracle.mc_update(dims, cell, xyz[2000:], v[2000:], ranges=r)
+    np.testing.assert_array_equal(r[0], lo)
+    np.testing.assert_array_equal(r[1], hi)
+
+
+def test_mc_opacity_is_max_of_interpolated_alpha():
+    rng = np.random.default_rng(32)
+    lut = rng.random((256, 4)).astype(np.float32)
+    lut[:100, 3] = 0.0  # transparent below v = 100/255
+    lut[180, 3] = 1.0   # a spike at a node
+    nodes = np.arange(256) / 255.0
+    lo = rng.random(300)
+    hi = lo + rng.random(300) * 0.3
+    lo[:3] = [0.1, 0.70, 0.7059]
+    hi[:3] = [0.3, 0.72, 0.71]
+    mu = oracle.mc_opacity((lo, hi), lut)
+    for c in range(300):
+        v = np.linspace(lo[c], hi[c], 4001)
+        ref = max(np.interp(v, nodes, lut[:, 3]).max(),
+                  max((lut[i, 3] for i in range(256) if lo[c] < nodes[i] < hi[c]), default=0.0))
+        assert mu[c] == pytest.approx(ref, abs=2e-6), c
+    assert mu[0] == 0.0 and mu[1] == 1.0 and mu[2] < 1.0
+    # empty cells (no sample yet) are transparent
+    assert oracle.mc_opacity((np.array([np.inf]), np.array([-np.inf])), lut)[0] == 0.0
+
+
+def test_mc_skipping_invariants():
+    m = small_model(L=3, F=2, log2T=10, res=(5, 9, 17), width=16, n_hidden=2)
+    params = rand_params(m, seed=33, table_scale=0.5)
+    cam = np.array([0.5, 0.5, -1.5, 0.002, 0, 0, 0, 0.002, 0, -0.064, -0.064, 1.0], np.float32)
+    lut = np.random.default_rng(34).random((256, 4)).astype(np.float32) * 0.2
+    W = H = 64
+    pix = np.arange(W * H)
+    dims, cell = (64, 64, 64), 16
+    plain = oracle.render_pixels(m, params, cam, lut, W, H, 1 / 64, 7, pix)
+    n = int(np.prod(oracle.mc_grid(dims, cell)))
+    full = oracle.render_pixels_mc(m, params, cam, lut, W, H, 1 / 64, 7, pix, dims, cell, np.ones(n))
+    for a, b in zip(plain, full):
+        np.testing.assert_array_equal(a, b)
+    empty = oracle.render_pixels_mc(m, params, cam, lut, W, H, 1 / 64, 7, pix, dims, cell, np.zeros(n))
+    assert np.all(empty[0] == 0) and np.all(empty[2] == 0)
+    np.testing.assert_array_equal(empty[1], plain[1])
+    # skipping the cells with x >= 1/2 leaves the rays that stay in x < 1/2 unchanged
+    mu = np.ones(n)
+    M = oracle.mc_grid(dims, cell)
+    ids = np.arange(n)
+    mu[(ids % M[0]) >= M[0] // 2] = 0.0
+    half = oracle.render_pixels_mc(m, params, cam, lut, W, H, 1 / 64, 7, pix, dims, cell, mu)
+    left = (pix % W) < W // 2 - 2
+    np.testing.assert_array_equal(half[0][left], plain[0][left])
+    assert np.all(half[2] <= plain[2]) and np.any(half[2] < plain[2])
