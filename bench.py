@@ -290,40 +290,61 @@ def main():
         dt = 1.0 / 1024
         lut = torch.from_numpy(synth.transfer_function_lut()).to(dev)
         rs = trained if trained is not None else st
-        online = ngv.TrainState(plan16, rs.params, 1 << 16, f16_tables=True)
         rgba = torch.empty((H, W, 4), dtype=torch.float32, device=dev)
         rws = torch.empty(256, dtype=torch.uint8, device=dev)
         cnt = torch.zeros(4, dtype=torch.int64, device=dev)
         cams = [synth.orbit_camera(2 * math.pi * f / max(args.render_frames, 1), W, H)
                 for f in range(args.render_frames + 1)]
-        # warm-up frame
-        ngv.render(plan16, online.params, cams[0], lut, W, H, dt, 0, table_f16=online.table_f16,
-                   want_counts=False, rgba=rgba, workspace=rws, counters=cnt)
-        torch.cuda.synchronize()
-        ev_r = [(ev(), ev(), ev()) for _ in range(args.render_frames)]
-        evals = used = 0
-        for f in range(args.render_frames):
-            ev_r[f][0].record()
-            ngv.train_step(online, volume=vol, seed=SEED + 77, step_index=f, loss_scale=LOSS_SCALE, **ADAM)
-            ev_r[f][1].record()
-            ngv.render(plan16, online.params, cams[f + 1], lut, W, H, dt, f + 1, table_f16=online.table_f16,
-                       want_counts=False, rgba=rgba, workspace=rws, counters=cnt)
-            ev_r[f][2].record()
+
+        def frames(mc):
+            # with macro-cells: their value ranges grow from each frame's
+            # training samples (online construction), the opacities follow,
+            # and the marcher skips samples in empty cells
+            online = ngv.TrainState(plan16, rs.params, 1 << 16, f16_tables=True)
+            if mc is not None:  # the first frame's ranges: one training step
+                ngv.train_step(online, volume=vol, seed=SEED + 76, step_index=0, loss_scale=LOSS_SCALE,
+                               macrocells=mc, **ADAM)
+                mc.opacity(lut)
+            ngv.render(plan16, online.params, cams[0], lut, W, H, dt, 0, table_f16=online.table_f16,
+                       want_counts=False, rgba=rgba, workspace=rws, counters=cnt, macrocells=mc)
             torch.cuda.synchronize()
-            c = cnt.cpu().numpy()
-            evals += int(c[0])
-            used += int(c[1])
-        tr = sum(e[0].elapsed_time(e[1]) for e in ev_r) / args.render_frames
-        rd = sum(e[1].elapsed_time(e[2]) for e in ev_r) / args.render_frames
-        render = {"frames": args.render_frames, "width": W, "height": H, "dt": dt, "train_batch": 1 << 16,
-                  "frame_ms": round(tr + rd, 3), "fps": round(1000.0 / (tr + rd), 3),
-                  "train_ms_per_frame": round(tr, 3), "render_ms_per_frame": round(rd, 3),
-                  "network_samples_per_frame": evals / args.render_frames,
-                  "composited_samples_per_frame": used / args.render_frames,
-                  "network_samples_per_s": evals / args.render_frames / (rd * 1e-3)}
-        log(f"render: {render['fps']:.2f} fps (train {tr:.2f} ms + render {rd:.2f} ms), "
-            f"{render['network_samples_per_s']:.3e} network samples/s")
-        online = rs = None
+            ev_r = [(ev(), ev(), ev()) for _ in range(args.render_frames)]
+            evals = used = 0
+            for f in range(args.render_frames):
+                ev_r[f][0].record()
+                ngv.train_step(online, volume=vol, seed=SEED + 77, step_index=f, loss_scale=LOSS_SCALE,
+                               macrocells=mc, **ADAM)
+                if mc is not None:
+                    mc.opacity(lut)
+                ev_r[f][1].record()
+                ngv.render(plan16, online.params, cams[f + 1], lut, W, H, dt, f + 1, table_f16=online.table_f16,
+                           want_counts=False, rgba=rgba, workspace=rws, counters=cnt, macrocells=mc)
+                ev_r[f][2].record()
+                torch.cuda.synchronize()
+                c = cnt.cpu().numpy()
+                evals += int(c[0])
+                used += int(c[1])
+            tr = sum(e[0].elapsed_time(e[1]) for e in ev_r) / args.render_frames
+            rd = sum(e[1].elapsed_time(e[2]) for e in ev_r) / args.render_frames
+            return {"frames": args.render_frames, "width": W, "height": H, "dt": dt, "train_batch": 1 << 16,
+                    "frame_ms": round(tr + rd, 3), "fps": round(1000.0 / (tr + rd), 3),
+                    "train_ms_per_frame": round(tr, 3), "render_ms_per_frame": round(rd, 3),
+                    "network_samples_per_frame": evals / args.render_frames,
+                    "composited_samples_per_frame": used / args.render_frames,
+                    "network_samples_per_s": evals / args.render_frames / (rd * 1e-3)}
+
+        render = frames(None)
+        log(f"render: {render['fps']:.2f} fps (train {render['train_ms_per_frame']:.2f} ms + render "
+            f"{render['render_ms_per_frame']:.2f} ms), {render['network_samples_per_s']:.3e} network samples/s")
+        # empty-space skipping with 64^3-voxel macro-cells built online
+        mc = ngv.MacroCells((VOL_D, VOL_D, VOL_D), 64, device=dev)
+        r_mc = frames(mc)
+        render["macrocells"] = {"cell": 64, "fps": r_mc["fps"], "render_ms_per_frame": r_mc["render_ms_per_frame"],
+                                "network_samples_per_frame": r_mc["network_samples_per_frame"],
+                                "empty_cells": int((mc.mu == 0).sum().item()), "cells": int(mc.mu.numel())}
+        log(f"render with macro-cells: {r_mc['fps']:.2f} fps, {r_mc['network_samples_per_frame']:.3e} network "
+            f"samples per frame ({render['macrocells']['empty_cells']} of {mc.mu.numel()} cells empty)")
+        rs = mc = None
 
     # -------------------------------------------------- batched multi-volume
     # 16 independent models of uneven size (2^16..2^22 entries, 8/12/16

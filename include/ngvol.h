@@ -148,6 +148,24 @@ typedef struct ngvol_train_state {
     size_t workspace_bytes;
 } ngvol_train_state;
 
+/* Macro-cells (Section 5.3): a grid of disjoint cells of `cell` voxels per
+ * axis over a volume of dims = (Dx, Dy, Dz) voxels, M_a = ceil(D_a / cell)
+ * cells per axis (the grid may extend past the volume), cell-major
+ * [Mz][My][Mx].  A point p (clamped to [0,1], NaN as 0) lies in cell
+ * c_a = min(floor(p_a * D_a) / cell, M_a - 1), p_a * D_a rounded to binary32.
+ * range[2c], range[2c+1] hold the minimum and maximum value seen in cell c as
+ * order-preserving keys of binary32 (k(v) = bits | 2^31 for sign 0, ~bits
+ * for sign 1; an empty cell is (0xFFFFFFFF, 0)); the online construction of
+ * Section 5.3 feeds them the training samples.  mu[c] is the largest opacity
+ * the transfer function takes over the cell's range, 0 for an empty cell.
+ * All arrays are device memory owned by the caller. */
+typedef struct ngvol_macrocells {
+    int32_t dims[3];  /* Dx, Dy, Dz, each in [1, 2^20] */
+    int32_t cell;     /* voxels per cell per axis, >= 1; Mx*My*Mz <= 2^24 */
+    uint32_t* range;  /* [Mz*My*Mx][2] */
+    float* mu;        /* [Mz*My*Mx] */
+} ngvol_macrocells;
+
 /* One training batch (Section 4, the sampling step).  Either explicit
  * samples (xyz != NULL: coordinates and targets given), or generated on the
  * device: coordinate axis a of sample i is the binary32 uniform
@@ -165,6 +183,8 @@ typedef struct ngvol_batch {
     uint64_t seed;       /* < 2^56 */
     int64_t step_index;  /* >= 0; or -1 (ngvol_train_step only): use the state's device step counter, so a
                           * captured graph draws a new batch on every replay (a skipped step repeats it) */
+    const ngvol_macrocells* macrocells; /* optional (ngvol_train_step): the batch's (coordinate, target)
+                                         * samples extend the cells' value ranges (NaN targets are ignored) */
 } ngvol_batch;
 
 /* Adam (Kingma and Ba) with bias correction and an exponentially decaying
@@ -309,6 +329,16 @@ int ngvol_make_f16_tables(const ngvol_plan* plan, const float* d_params, uint16_
 int ngvol_sq_error_grid(const ngvol_plan* plan, const ngvol_weights* w, const void* d_volume, const int32_t dims[3],
                         int32_t volume_dtype, double* d_sum_sq, hipStream_t stream);
 
+/* Macro-cells (Section 5.3).  reset: every cell empty.  update: extend the
+ * ranges with n explicit samples (xyz[n][3], values[n], device).  opacity:
+ * mu of every cell for a transfer function d_lut[256][4] (RGBA, the alpha
+ * of the shading below: piecewise linear in v over nodes i/255), the maximum
+ * over the two range ends and every node strictly inside. */
+int ngvol_mc_reset(const ngvol_macrocells* mc, hipStream_t stream);
+int ngvol_mc_update(const ngvol_macrocells* mc, const float* d_xyz, const float* d_values, int64_t n,
+                    hipStream_t stream);
+int ngvol_mc_opacity(const ngvol_macrocells* mc, const float* d_lut, hipStream_t stream);
+
 /* Workspace for ngvol_render (a few counters). */
 size_t ngvol_render_workspace_bytes(void);
 
@@ -325,6 +355,9 @@ size_t ngvol_render_workspace_bytes(void);
  * Shading: v = clamp(Phi,0,1); u = 255 v; i = min(floor(u),254);
  * c = lut[i](1-(u-i)) + lut[i+1](u-i); C += (1-A) c.a c.rgb; A += (1-A) c.a;
  * a ray stops after the sample at which A >= 0.99.
+ * mc (nullable): empty-space skipping (Section 5.3): a sample whose
+ * macro-cell has mu = 0 (mc->mu as left by ngvol_mc_opacity) is neither
+ * evaluated nor composited; a ray scans its samples 64 at a time for them.
  * rgba[H][W][4] FP32 (premultiplied colour, alpha); n_geo[H][W] (nullable):
  * geometric sample counts n; n_used (nullable): samples composited;
  * counters (nullable, device): totals.  lut: device [256][4].
@@ -332,9 +365,9 @@ size_t ngvol_render_workspace_bytes(void);
 /* dt must be in [2^-20, 1]; a ray whose span exceeds 2^24 steps (only a
  * degenerate camera can produce one) gets no samples. */
 int ngvol_render(const ngvol_plan* plan, const ngvol_weights* w, const ngvol_camera* cam, const float* d_lut,
-                 int32_t width, int32_t height, float dt, uint32_t frame_seed, float* d_rgba, uint32_t* d_n_geo,
-                 uint32_t* d_n_used, ngvol_render_counters* d_counters, void* d_workspace, size_t workspace_bytes,
-                 hipStream_t stream);
+                 int32_t width, int32_t height, float dt, uint32_t frame_seed, const ngvol_macrocells* mc,
+                 float* d_rgba, uint32_t* d_n_geo, uint32_t* d_n_used, ngvol_render_counters* d_counters,
+                 void* d_workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* ----------------------------------------------------------------------- */
 /* Batches of independent neural volumes                                   */

@@ -57,10 +57,14 @@ class TrainStateC(C.Structure):
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t)]
 
 
+class MacroCellsC(C.Structure):
+    _fields_ = [("dims", C.c_int32 * 3), ("cell", C.c_int32), ("range", C.c_void_p), ("mu", C.c_void_p)]
+
+
 class Batch(C.Structure):
     _fields_ = [("batch_size", C.c_int64), ("xyz", C.c_void_p), ("target", C.c_void_p), ("volume", C.c_void_p),
                 ("dims", C.c_int32 * 3), ("volume_dtype", C.c_int32), ("seed", C.c_uint64),
-                ("step_index", C.c_int64)]
+                ("step_index", C.c_int64), ("macrocells", C.c_void_p)]
 
 
 class Adam(C.Structure):
@@ -98,7 +102,10 @@ _SIGS = {
     "ngvol_sq_error_grid": (C.c_int, [_P, C.POINTER(Weights), _P, C.POINTER(C.c_int32), C.c_int32, _P, _P]),
     "ngvol_render_workspace_bytes": (C.c_size_t, []),
     "ngvol_render": (C.c_int, [_P, C.POINTER(Weights), C.POINTER(Camera), _P, C.c_int32, C.c_int32, C.c_float,
-                               C.c_uint32, _P, _P, _P, _P, _P, C.c_size_t, _P]),
+                               C.c_uint32, _P, _P, _P, _P, _P, _P, C.c_size_t, _P]),
+    "ngvol_mc_reset": (C.c_int, [_P, _P]),
+    "ngvol_mc_update": (C.c_int, [_P, _P, _P, C.c_int64, _P]),
+    "ngvol_mc_opacity": (C.c_int, [_P, _P, _P]),
     "ngvol_multi_table_bytes": (C.c_size_t, [C.c_int32]),
     "ngvol_multi_create": (C.c_int, [C.POINTER(_P), C.c_int32, _P, C.c_size_t, _P, C.POINTER(_P)]),
     "ngvol_multi_destroy": (C.c_int, [_P]),
@@ -325,7 +332,7 @@ def _volume_batch(volume, B, seed, step):
     torch = _torch()
     dt = {torch.float32: DT_F32, torch.float16: DT_F16}[volume.dtype]
     Dz, Dy, Dx = volume.shape
-    return Batch(B, None, None, _ptr(volume), (C.c_int32 * 3)(Dx, Dy, Dz), dt, seed, step)
+    return Batch(B, None, None, _ptr(volume), (C.c_int32 * 3)(Dx, Dy, Dz), dt, seed, step, None)
 
 
 def sample_batch(plan, volume, B, seed, step):
@@ -377,16 +384,19 @@ def _adam(lr, betas, eps, l2_reg, decay):
 
 
 def train_step(state, volume=None, seed=0, step_index=0, xyz=None, target=None, lr=1e-2, betas=(0.9, 0.99),
-               eps=1e-15, loss_scale=1.0, l2_reg=0.0, decay=None):
+               eps=1e-15, loss_scale=1.0, l2_reg=0.0, decay=None, macrocells=None):
     """One training step.  step_index=-1 draws the batch indexed by the state's
     device step counter (the form to capture in a graph).  decay =
     (start, interval, base) gives the exponentially decaying learning rate;
-    l2_reg regularises the MLP weights."""
+    l2_reg regularises the MLP weights; macrocells (a MacroCells) takes the
+    batch's samples into its value ranges."""
     B = state.batch_size
     if xyz is not None:
-        b = Batch(B, _ptr(xyz), _ptr(target), None, (C.c_int32 * 3)(0, 0, 0), 0, 0, 0)
+        b = Batch(B, _ptr(xyz), _ptr(target), None, (C.c_int32 * 3)(0, 0, 0), 0, 0, 0, None)
     else:
         b = _volume_batch(volume, B, seed, step_index)
+    if macrocells is not None:
+        b.macrocells = C.cast(C.pointer(macrocells._c), C.c_void_p)
     a = _adam(lr, betas, eps, l2_reg, decay)
     _check(lib().ngvol_train_step(state.plan.handle, C.byref(state._c), C.byref(b), C.byref(a),
                                   float(loss_scale), _stream()))
@@ -418,8 +428,9 @@ def psnr(plan, params, volume, table_f16=None):
 
 
 def render(plan, params, cam, lut, width, height, dt, frame_seed, table_f16=None, want_counts=True,
-           rgba=None, workspace=None, counters=None):
-    """Returns (rgba [H][W][4], n_geo [H][W] or None, n_used or None, counters [4] int64)."""
+           rgba=None, workspace=None, counters=None, macrocells=None):
+    """Returns (rgba [H][W][4], n_geo [H][W] or None, n_used or None, counters [4] int64).
+    macrocells (a MacroCells with opacities set): skip samples in empty cells."""
     torch = _torch()
     dev = params.device
     if rgba is None:
@@ -434,10 +445,49 @@ def render(plan, params, cam, lut, width, height, dt, frame_seed, table_f16=None
     camc = Camera((C.c_float * 3)(*c[0:3]), (C.c_float * 3)(*c[3:6]), (C.c_float * 3)(*c[6:9]),
                   (C.c_float * 3)(*c[9:12]))
     w = _weights(params, table_f16)
+    mcp = C.byref(macrocells._c) if macrocells is not None else None
     _check(lib().ngvol_render(plan.handle, C.byref(w), C.byref(camc), _ptr(lut), width, height, float(dt),
-                              frame_seed, _ptr(rgba), _ptr(n_geo), _ptr(n_used), _ptr(counters), _ptr(workspace),
-                              workspace.numel(), _stream()))
+                              frame_seed, mcp, _ptr(rgba), _ptr(n_geo), _ptr(n_used), _ptr(counters),
+                              _ptr(workspace), workspace.numel(), _stream()))
     return rgba, n_geo, n_used, counters
+
+
+class MacroCells:
+    """Macro-cell grid (cells of `cell` voxels per axis) over a volume of
+    dims = (Dx, Dy, Dz) voxels, with device value ranges and opacities."""
+
+    def __init__(self, dims, cell=64, device="cuda"):
+        torch = _torch()
+        self.dims = tuple(int(d) for d in dims)
+        self.cell = int(cell)
+        self.grid = tuple((d + self.cell - 1) // self.cell for d in self.dims)
+        n = self.grid[0] * self.grid[1] * self.grid[2]
+        self.range = torch.empty(2 * n, dtype=torch.int32, device=device)
+        self.mu = torch.zeros(n, dtype=torch.float32, device=device)
+        self._c = MacroCellsC((C.c_int32 * 3)(*self.dims), self.cell, _ptr(self.range), _ptr(self.mu))
+        self.reset()
+
+    def reset(self):
+        _check(lib().ngvol_mc_reset(C.byref(self._c), _stream()))
+
+    def update(self, xyz, values):
+        _check(lib().ngvol_mc_update(C.byref(self._c), _ptr(xyz), _ptr(values), xyz.shape[0], _stream()))
+
+    def opacity(self, lut):
+        _check(lib().ngvol_mc_opacity(C.byref(self._c), _ptr(lut), _stream()))
+
+    def ranges(self):
+        """(vmin, vmax) per cell as float64 numpy arrays (+inf, -inf when empty)."""
+        import numpy as np
+        _torch().cuda.synchronize()
+        k = self.range.cpu().numpy().view(np.uint32).reshape(-1, 2)
+        def val(key):
+            bits = np.where(key & 0x80000000, key & 0x7FFFFFFF, ~key).astype(np.uint32)
+            return bits.view(np.float32).astype(np.float64)
+        lo, hi = val(k[:, 0]), val(k[:, 1])
+        empty = k[:, 0] > k[:, 1]
+        lo[empty], hi[empty] = np.inf, -np.inf
+        return lo, hi
 
 
 def version():

@@ -357,6 +357,25 @@ int ngvol_encode_bwd(const ngvol_plan* plan, const float* xyz, int64_t n, const 
   return hip_check(launch_encode_bwd(plan, xyz, n, dfeat, grad, st), "encode_bwd launch");
 }
 
+static int resolve_mc(const ngvol_macrocells* mc, McGeom& g, bool need_range, bool need_mu) {
+  NGV_REQUIRE(mc, "macrocells is NULL");
+  NGV_REQUIRE(mc->cell >= 1, "macro-cell size must be >= 1");
+  int64_t total = 1;
+  for (int a = 0; a < 3; ++a) {
+    NGV_REQUIRE(mc->dims[a] >= 1 && mc->dims[a] <= (1 << 20), "macro-cell volume dims must be in [1, 2^20]");
+    g.dims[a] = mc->dims[a];
+    g.m[a] = (mc->dims[a] + mc->cell - 1) / mc->cell;
+    total *= g.m[a];
+  }
+  NGV_REQUIRE(total <= ((int64_t)1 << 24), "more than 2^24 macro-cells");
+  g.cell = mc->cell;
+  NGV_REQUIRE(!need_range || (mc->range && aligned4(mc->range)), "macro-cell range must be non-NULL, 4-byte aligned");
+  NGV_REQUIRE(!need_mu || (mc->mu && aligned4(mc->mu)), "macro-cell mu must be non-NULL, 4-byte aligned");
+  g.range = need_range ? mc->range : nullptr;
+  g.mu = need_mu ? mc->mu : nullptr;
+  return NGVOL_OK;
+}
+
 static int resolve_batch(const ngvol_plan* plan, const ngvol_batch* b, BatchArgs& ba) {
   (void)plan;
   NGV_REQUIRE(b, "batch is NULL");
@@ -382,7 +401,32 @@ static int resolve_batch(const ngvol_plan* plan, const ngvol_batch* b, BatchArgs
     NGV_REQUIRE(b->seed < (1ull << 56), "seed must be < 2^56");
     NGV_REQUIRE(b->step_index >= -1, "step_index must be >= 0, or -1 for the state's step counter");
   }
+  ba.mc = McGeom{};
+  if (b->macrocells)
+    if (int rc = resolve_mc(b->macrocells, ba.mc, true, false)) return rc;
   return NGVOL_OK;
+}
+
+int ngvol_mc_reset(const ngvol_macrocells* mc, hipStream_t st) {
+  McGeom g{};
+  if (int rc = resolve_mc(mc, g, true, false)) return rc;
+  return hip_check(launch_mc_reset(g, st), "mc_reset launch");
+}
+
+int ngvol_mc_update(const ngvol_macrocells* mc, const float* xyz, const float* values, int64_t n, hipStream_t st) {
+  McGeom g{};
+  if (int rc = resolve_mc(mc, g, true, false)) return rc;
+  NGV_REQUIRE(n >= 0 && n < ((int64_t)1 << 40), "n out of range");
+  NGV_REQUIRE(n == 0 || (xyz && values && aligned4(xyz) && aligned4(values)),
+              "xyz and values must be non-NULL and 4-byte aligned");
+  return hip_check(launch_mc_update(g, xyz, values, n, st), "mc_update launch");
+}
+
+int ngvol_mc_opacity(const ngvol_macrocells* mc, const float* lut, hipStream_t st) {
+  McGeom g{};
+  if (int rc = resolve_mc(mc, g, true, true)) return rc;
+  NGV_REQUIRE(lut && aligned4(lut), "lut must be non-NULL and 4-byte aligned");
+  return hip_check(launch_mc_opacity(g, lut, st), "mc_opacity launch");
 }
 
 int ngvol_sample_batch(const ngvol_plan* plan, const ngvol_batch* b, float* xyz, float* y, hipStream_t st) {
@@ -524,8 +568,8 @@ int ngvol_sq_error_grid(const ngvol_plan* plan, const ngvol_weights* w, const vo
 size_t ngvol_render_workspace_bytes(void) { return 256; }
 
 int ngvol_render(const ngvol_plan* plan, const ngvol_weights* w, const ngvol_camera* cam, const float* lut, int32_t W,
-                 int32_t H, float dt, uint32_t seed, float* rgba, uint32_t* n_geo, uint32_t* n_used,
-                 ngvol_render_counters* counters, void* ws, size_t ws_bytes, hipStream_t st) {
+                 int32_t H, float dt, uint32_t seed, const ngvol_macrocells* mc, float* rgba, uint32_t* n_geo,
+                 uint32_t* n_used, ngvol_render_counters* counters, void* ws, size_t ws_bytes, hipStream_t st) {
   if (int rc = check_plan(plan)) return rc;
   if (int rc = check_weights(w)) return rc;
   NGV_REQUIRE(cam && lut && rgba && ws, "camera, lut, rgba and workspace must be non-NULL");
@@ -535,7 +579,9 @@ int ngvol_render(const ngvol_plan* plan, const ngvol_weights* w, const ngvol_cam
   NGV_REQUIRE(W >= 1 && H >= 1 && (int64_t)W * H < ((int64_t)1 << 31), "image size out of range");
   NGV_REQUIRE(dt >= 0x1p-20f && dt <= 1.0f, "dt must be in [2^-20, 1]");
   NGV_REQUIRE(ws_bytes >= ngvol_render_workspace_bytes(), "render workspace too small");
-  RenderArgs ra;
+  RenderArgs ra{};
+  if (mc)
+    if (int rc = resolve_mc(mc, ra.mc, false, true)) return rc;
   memcpy(ra.cam, cam, sizeof ra.cam);
   ra.lut = lut;
   ra.width = W;

@@ -23,6 +23,43 @@ template <>
 __device__ __forceinline__ const __half* table_ptr<__half>(const TablePtrs& t) { return t.f16; }
 
 // A training batch, resolved for the kernels.
+// Macro-cell grid on the device: cells per axis, voxel dims, cell size.
+struct McGeom {
+  int32_t dims[3], m[3], cell;
+  uint32_t* range;  // [cells][2] order-preserving keys (min, max), or NULL
+  const float* mu;  // [cells], or NULL
+};
+
+// Order-preserving key of a binary32 value (unsigned compare = float compare).
+__host__ __device__ inline uint32_t order_key(uint32_t bits) {
+  return (bits & 0x80000000u) ? ~bits : (bits | 0x80000000u);
+}
+
+// Macro-cell of a point already clamped to [0,1]: floor(p * D) in binary32,
+// divided by the cell size, capped at the last cell.
+__device__ __forceinline__ uint32_t mc_index(const McGeom& g, float x, float y, float z) {
+  const float p[3] = {x, y, z};
+  uint32_t c[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int v = (int)floorf(__fmul_rn(p[a], (float)g.dims[a]));
+    const int ci = v / g.cell;
+    c[a] = (uint32_t)(ci < g.m[a] - 1 ? ci : g.m[a] - 1);
+  }
+  return (c[2] * (uint32_t)g.m[1] + c[1]) * (uint32_t)g.m[0] + c[0];
+}
+
+// Extend cell c's range by value v (NaN ignored).  A plain read first skips
+// the atomics whenever the range already covers v (ranges only widen, so a
+// stale read can only cause an unneeded atomic).
+__device__ __forceinline__ void mc_extend(uint32_t* range, uint32_t c, float v) {
+  if (v != v) return;
+  const uint32_t key = order_key(__float_as_uint(v));
+  uint32_t* r = range + 2 * (size_t)c;
+  if (key < __hip_atomic_load(r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(r, key);
+  if (key > __hip_atomic_load(r + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(r + 1, key);
+}
+
 struct BatchArgs {
   int64_t B;
   const float* xyz;     // explicit coordinates, or NULL to generate
@@ -33,6 +70,7 @@ struct BatchArgs {
   uint64_t seed;
   int64_t step;
   const int64_t* step_ptr;  // if set, the batch index is read from here (the state's step counter)
+  McGeom mc;                // mc.range set: the samples extend the macro-cell ranges
   __device__ __forceinline__ int64_t step_index() const { return step_ptr ? *step_ptr : step; }
 };
 
@@ -208,7 +246,11 @@ struct RenderArgs {
   uint32_t* n_used;
   unsigned long long* counters;  // [4] in the workspace or caller's struct
   unsigned int* queue;           // ray queue head
+  McGeom mc;                     // mc.mu set: empty-space skipping
 };
+hipError_t launch_mc_reset(const McGeom& g, hipStream_t st);
+hipError_t launch_mc_update(const McGeom& g, const float* xyz, const float* values, int64_t n, hipStream_t st);
+hipError_t launch_mc_opacity(const McGeom& g, const float* lut, hipStream_t st);
 size_t render_lds_bytes(const ngvol_plan* plan, int waves);
 hipError_t launch_render(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const RenderArgs& ra,
                          hipStream_t st);

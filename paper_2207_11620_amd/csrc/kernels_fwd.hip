@@ -262,6 +262,7 @@ k_train_fwd(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, BatchArgs
     wave_sync();
     const float yv = mlp_wave64<P, KIN, W>(md.n_hidden, lds_frag, lds_wout, stage);
     wave_sync();
+    if (valid && ba.mc.range) mc_extend(ba.mc.range, mc_index(ba.mc, x, y, z), target);
     if (valid) {
       const float r = yv - target;
       if (l1) {

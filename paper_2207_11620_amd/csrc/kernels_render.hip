@@ -87,6 +87,11 @@ struct SlotState {
   float C[3], A;
 };
 
+// Empty-space skipping, per slot: this round's samples (those in a non-empty
+// macro-cell), their count, and the first sample index after the round.
+constexpr int kList = kK + 2;
+constexpr int kCnt = kK, kNext = kK + 1;
+
 __global__ void k_render_init(unsigned int* queue, unsigned long long* counters) {
   const int t = threadIdx.x;
   if (t < kBands) queue[t] = 0u;
@@ -109,11 +114,11 @@ __device__ __forceinline__ int32_t fetch_pixel(unsigned int* queue, int band0, i
 // slots and per-sample outputs of every wave, then the encoding stages.
 __host__ __device__ inline size_t render_stage_offset(size_t weight_bytes, int W, int waves) {
   const size_t end = weight_bytes + (size_t)W * 4 + 1024 * 4 + (size_t)waves * kSlots * sizeof(SlotState) +
-                     (size_t)waves * kSlots * kK * 4;
+                     (size_t)waves * kSlots * kK * 4 + (size_t)waves * kSlots * kList * 4;
   return (end + 15) & ~(size_t)15;
 }
 
-template <int P, int F, int KIN, int W, typename TT>
+template <int P, int F, int KIN, int W, typename TT, bool SKIP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P != 0 && KIN == 32 ? 4 : 1)))
 k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs ra) {
   typedef typename Prec<P>::Frag Frag;
@@ -127,6 +132,8 @@ k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs r
   SlotState* slots = reinterpret_cast<SlotState*>(lds_lut + 1024) + wave * kSlots;
   float* yv = reinterpret_cast<float*>(reinterpret_cast<SlotState*>(lds_lut + 1024) + (blockDim.x >> 6) * kSlots) +
               wave * kSlots * kK;
+  uint32_t* lst = reinterpret_cast<uint32_t*>(yv - wave * kSlots * kK + (blockDim.x >> 6) * kSlots * kK) +
+                  wave * kSlots * kList;
   typedef typename Prec<P>::T T;
   T* stage = reinterpret_cast<T*>(smem + render_stage_offset(wbytes, W, blockDim.x >> 6) +
                                   wave * Stage<P, KIN>::wave_bytes);
@@ -174,16 +181,56 @@ k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs r
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 
+  constexpr bool skip_empty = SKIP;  // ra.mc.mu is set
   for (;;) {
     // any live slot in this wave?
     const bool live = lane < kSlots && slots[lane].pix >= 0;
     if (!__any(live)) break;
-    // lane j evaluates sample k = slot.k + j%8 of slot j/8
+    if constexpr (skip_empty) {
+      // each slot's next 64 samples are checked against the macro-cells, one
+      // per lane; the first kK in a non-empty cell are this round's samples
+      for (int s = 0; s < kSlots; ++s) {
+        const SlotState& so = slots[s];
+        const uint32_t k0 = so.k, n = so.g.n;
+        const uint32_t c = k0 + (uint32_t)lane;
+        bool in = false;
+        if (so.pix >= 0 && c < n) {
+          float x, y, z;
+          ray_point(so.g, c, ra.dt, x, y, z);
+          in = ra.mc.mu[mc_index(ra.mc, clamp01(x), clamp01(y), clamp01(z))] > 0.0f;
+        }
+        const unsigned long long mask = __ballot(in);
+        const uint32_t below = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+        const uint32_t total = (uint32_t)__popcll(mask);
+        uint32_t next = k0 + 64u;
+        if (total >= (uint32_t)kK) {
+          const unsigned long long last = __ballot(in && below == (uint32_t)kK - 1u);
+          next = k0 + (uint32_t)(__ffsll((unsigned long long)last) - 1) + 1u;
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (in && below < (uint32_t)kK) lst[s * kList + below] = c;
+        if (lane == 0) {
+          lst[s * kList + kCnt] = total < (uint32_t)kK ? total : (uint32_t)kK;
+          lst[s * kList + kNext] = next < n ? next : n;
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      }
+    }
+    // lane j evaluates sample k = slot.k + j%8 of slot j/8 (with skipping:
+    // the slot's (j%8)-th listed sample)
     {
-      const int si = lane >> 3;
+      const int si = lane >> 3, q = lane & 7;
       const SlotState& sl = slots[si];
-      const uint32_t k = sl.k + (lane & 7);
-      const bool valid = sl.pix >= 0 && k < sl.g.n;
+      uint32_t k;
+      bool valid;
+      if (skip_empty) {
+        valid = sl.pix >= 0 && (uint32_t)q < lst[si * kList + kCnt];
+        k = valid ? lst[si * kList + q] : 0u;
+      } else {
+        k = sl.k + (uint32_t)q;
+        valid = sl.pix >= 0 && k < sl.g.n;
+      }
       float x = 0.5f, y = 0.5f, z = 0.5f;
       if (valid) {
         ray_point(sl.g, k, ra.dt, x, y, z);
@@ -202,7 +249,8 @@ k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs r
       SlotState sl = slots[lane];
       if (sl.pix >= 0) {
         bool done = false;
-        const uint32_t kend = sl.g.n - sl.k < (uint32_t)kK ? sl.g.n - sl.k : (uint32_t)kK;
+        const uint32_t kend =
+            skip_empty ? lst[lane * kList + kCnt] : (sl.g.n - sl.k < (uint32_t)kK ? sl.g.n - sl.k : (uint32_t)kK);
         for (uint32_t q = 0; q < kend; ++q) {
           const float val = fminf(fmaxf(yv[lane * kK + q], 0.0f), 1.0f);
           const float u = 255.0f * val;
@@ -224,7 +272,7 @@ k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs r
             break;
           }
         }
-        sl.k += kend;
+        sl.k = skip_empty ? lst[lane * kList + kNext] : sl.k + kend;
         if (done || sl.k >= sl.g.n) {
           const int32_t p = sl.pix;
           float4* o4 = reinterpret_cast<float4*>(ra.rgba) + p;
@@ -270,12 +318,18 @@ hipError_t launch_render(const ngvol_plan* plan, TablePtrs tp, const float* mlp,
   const int64_t cap = (int64_t)plan->cus * 8;
   if (grid > cap) grid = cap;
   if (grid < 1) grid = 1;
-#define NGV_RENDER(P, F, KIN, W)                                                                                    \
-  do {                                                                                                              \
-    if (tp.f16)                                                                                                     \
-      hipLaunchKernelGGL((k_render<P, F, KIN, W, __half>), dim3((unsigned)grid), dim3(256), lds, st, md, tp, mlp, ra); \
-    else                                                                                                            \
-      hipLaunchKernelGGL((k_render<P, F, KIN, W, float>), dim3((unsigned)grid), dim3(256), lds, st, md, tp, mlp, ra);  \
+  const bool skip = ra.mc.mu != nullptr;
+#define NGV_RENDER_GO(P, F, KIN, W, TT, S) \
+  hipLaunchKernelGGL((k_render<P, F, KIN, W, TT, S>), dim3((unsigned)grid), dim3(256), lds, st, md, tp, mlp, ra)
+#define NGV_RENDER(P, F, KIN, W)                                  \
+  do {                                                            \
+    if (tp.f16) {                                                 \
+      if (skip) NGV_RENDER_GO(P, F, KIN, W, __half, true);        \
+      else NGV_RENDER_GO(P, F, KIN, W, __half, false);            \
+    } else {                                                      \
+      if (skip) NGV_RENDER_GO(P, F, KIN, W, float, true);         \
+      else NGV_RENDER_GO(P, F, KIN, W, float, false);             \
+    }                                                             \
   } while (0)
 #define NGV_RENDER_W(P, F, KIN)                              \
   do {                                                       \
@@ -301,6 +355,7 @@ hipError_t launch_render(const ngvol_plan* plan, TablePtrs tp, const float* mlp,
 #undef NGV_RENDER_FK
 #undef NGV_RENDER_W
 #undef NGV_RENDER
+#undef NGV_RENDER_GO
   return hipGetLastError();
 }
 

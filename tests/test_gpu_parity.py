@@ -619,6 +619,116 @@ def test_render_constant_alpha_closed_form():
     np.testing.assert_allclose(host(rgba)[..., 3], 1 - (1 - a) ** 90, rtol=1e-5)
 
 
+# ------------------------------------------------------------ macro-cells -----
+
+def _mc_lut():
+    lut = synth.transfer_function_lut().copy()
+    lut[:103, 3] = 0.0  # transparent below v = 0.4
+    return lut
+
+
+def test_mc_update_and_opacity_match_oracle():
+    dims, cell = (100, 64, 130), 8
+    rng = np.random.default_rng(40)
+    n = 3000
+    xyz = rng.random((n, 3)).astype(np.float32)
+    xyz[:4] = [[0, 0, 0], [1, 1, 1], [-0.2, 1.5, 0.5], [np.nan, 0.3, 0.7]]
+    v = rng.normal(0.4, 0.4, n).astype(np.float32)
+    v[5], v[6], v[7] = np.nan, -0.0, 0.0
+    mc = ngv.MacroCells(dims, cell)
+    mc.update(dev(xyz[:1000]), dev(v[:1000]))
+    mc.update(dev(xyz[1000:]), dev(v[1000:]))
+    ro = oracle.mc_update(dims, cell, xyz, v)
+    lo, hi = mc.ranges()
+    np.testing.assert_array_equal(lo, ro[0])
+    np.testing.assert_array_equal(hi, ro[1])
+    assert np.any(np.isinf(lo)) and np.any(np.isfinite(lo))  # empty and filled cells
+    lut = _mc_lut()
+    mc.opacity(dev(lut))
+    mu_o = oracle.mc_opacity(ro, lut)
+    mu = host(mc.mu)
+    np.testing.assert_array_equal(mu > 0, mu_o > 0)
+    np.testing.assert_allclose(mu, mu_o, atol=1e-6)
+    assert np.any(mu_o == 0) and np.any(mu_o > 0)
+    # reset empties every cell
+    mc.reset()
+    lo, hi = mc.ranges()
+    assert np.all(np.isinf(lo)) and np.all(np.isinf(hi))
+
+
+def test_train_step_extends_macrocells():
+    dims, cell = (64, 64, 64), 8
+    p = gpu_plan("tiny")
+    vol = synth.gaussian_blobs(64, SEED)
+    B = 4096
+    st = ngv.TrainState(p, dev(init_params("tiny")), B)
+    # explicit batch: the ranges are those of the given samples, bit for bit
+    xyz = oracle.batch_coords(SEED, 2, B)
+    y = oracle.sample_volume(vol, xyz).astype(np.float32)
+    mc = ngv.MacroCells(dims, cell)
+    ngv.train_step(st, xyz=dev(xyz), target=dev(y), loss_scale=128.0, macrocells=mc)
+    ro = oracle.mc_update(dims, cell, xyz, y)
+    lo, hi = mc.ranges()
+    np.testing.assert_array_equal(lo, ro[0])
+    np.testing.assert_array_equal(hi, ro[1])
+    # generated batches of two steps: the device sampler's targets
+    mc.reset()
+    for k in (3, 4):
+        ngv.train_step(st, volume=dev(vol), seed=SEED, step_index=k, loss_scale=128.0, macrocells=mc)
+    r = None
+    for k in (3, 4):
+        xk = oracle.batch_coords(SEED, k, B)
+        r = oracle.mc_update(dims, cell, xk, oracle.sample_volume(vol, xk), ranges=r)
+    lo, hi = mc.ranges()
+    np.testing.assert_array_equal(np.isinf(lo), np.isinf(r[0]))
+    f = np.isfinite(lo)
+    np.testing.assert_allclose(lo[f], r[0][f], atol=1e-6)
+    np.testing.assert_allclose(hi[f], r[1][f], atol=1e-6)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_render_empty_space_skipping_matches_oracle(prec):
+    name = "tiny"
+    m = oracle_model(name)
+    p = gpu_plan(name, prec)
+    vol = synth.gaussian_blobs(64, SEED)
+    th, _, _ = oracle.train(m, init_params(name).astype(np.float64), vol, SEED, 60, 4096, 1e-2, 0.9, 0.99, 1e-15)
+    params = th.astype(np.float32)
+    dims, cell = (64, 64, 64), 8
+    xyz = oracle.batch_coords(SEED, 0, 1 << 16)
+    y = oracle.sample_volume(vol, xyz).astype(np.float32)
+    lut = _mc_lut()
+    mc = ngv.MacroCells(dims, cell)
+    mc.update(dev(xyz), dev(y))
+    mc.opacity(dev(lut))
+    mu_o = oracle.mc_opacity(oracle.mc_update(dims, cell, xyz, y), lut)
+    np.testing.assert_array_equal(host(mc.mu) > 0, mu_o > 0)
+    assert 0.1 < np.mean(mu_o == 0) < 0.95
+    W, H = 160, 120
+    cam, _ = _render_setup(W, H)
+    dt = 2.0 ** -7
+    rgba, n_geo, n_used, cnt = ngv.render(p, dev(params), cam, dev(lut), W, H, dt, 7, macrocells=mc)
+    _, _, _, cnt_plain = ngv.render(p, dev(params), cam, dev(lut), W, H, dt, 7)
+    np.testing.assert_array_equal(host(n_geo).astype(np.uint32), oracle.ray_counts(cam, W, H, 7, dt))
+    c, c0 = host(cnt), host(cnt_plain)
+    print(f"evaluated with skipping {c[0]} of {c0[0]}")
+    assert c[0] < c0[0]
+    img, nu = host(rgba), host(n_used)
+    pix = np.random.default_rng(2).choice(W * H, 300, replace=False)
+    ro, _, nuo = oracle.render_pixels_mc(m, params.astype(np.float64), cam, lut, W, H, dt, 7, pix, dims, cell, mu_o)
+    g = img.reshape(-1, 4)[pix]
+    same = nu.ravel()[pix] == nuo
+    assert np.all(same | (np.abs(ro[:, 3] - 0.99) < 2e-3))
+    tol = 1e-4 if prec == "fp32" else 2e-2
+    assert np.max(np.abs(g[same] - ro[same])) <= tol
+    assert c[1] == nu.sum()
+    # an all-open grid renders exactly as without macro-cells
+    mc.mu.fill_(1.0)
+    a, _, _, _ = ngv.render(p, dev(params), cam, dev(lut), W, H, dt, 7, macrocells=mc)
+    b, _, _, _ = ngv.render(p, dev(params), cam, dev(lut), W, H, dt, 7)
+    np.testing.assert_array_equal(host(a), host(b))
+
+
 def test_online_training_interleave():
     # one training step between two frames: the second frame is the oracle's
     # rendering of the updated parameters, the geometry is unchanged
