@@ -96,7 +96,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--quality-steps", type=int, default=2000)
-    ap.add_argument("--quality-repeats", type=int, default=8)
+    ap.add_argument("--quality-repeats", type=int, default=12)
     ap.add_argument("--no-quality", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
