@@ -227,6 +227,12 @@ typedef struct ngvol_render_counters {
 const char* ngvol_last_error(void);
 const char* ngvol_version(void);
 
+/* Debug mode (also switched on by NGVOL_DEBUG=1 in the environment): every
+ * call then waits for the device after its launches (hipDeviceSynchronize)
+ * and returns NGVOL_EDEVICE with the runtime's message if one of them
+ * failed.  Not for use while a stream is being captured into a graph. */
+int ngvol_set_debug(int32_t on);
+
 /* Create / destroy a plan.  EINVAL for out-of-range fields, EUNSUPPORTED for
  * valid but unsupported widths or feature counts. */
 int ngvol_plan_create(const ngvol_config* cfg, ngvol_plan** out);

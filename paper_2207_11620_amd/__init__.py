@@ -81,6 +81,7 @@ _P = C.c_void_p
 _SIGS = {
     "ngvol_last_error": (C.c_char_p, []),
     "ngvol_version": (C.c_char_p, []),
+    "ngvol_set_debug": (C.c_int, [C.c_int32]),
     "ngvol_plan_create": (C.c_int, [C.POINTER(Config), C.POINTER(_P)]),
     "ngvol_plan_destroy": (C.c_int, [_P]),
     "ngvol_get_layout": (C.c_int, [_P, C.POINTER(Layout)]),
@@ -492,6 +493,11 @@ class MacroCells:
 
 def version():
     return lib().ngvol_version().decode()
+
+
+def set_debug(on=True):
+    """Synchronise and check for device errors after every library call."""
+    _check(lib().ngvol_set_debug(1 if on else 0))
 
 
 class Multi:

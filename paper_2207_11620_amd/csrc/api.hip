@@ -6,7 +6,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <atomic>
 #include <cmath>
+#include <cstdlib>
 
 #include <new>
 #include <string>
@@ -30,7 +32,26 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
+// Debug mode (NGVOL_DEBUG=1 in the environment, or ngvol_set_debug): every
+// call waits for the device after its launches and reports a failure of
+// theirs as its own.
+std::atomic<int> g_debug{-1};
+
+bool debug_on() {
+  int d = g_debug.load(std::memory_order_relaxed);
+  if (d < 0) {
+    const char* e = getenv("NGVOL_DEBUG");
+    d = (e && e[0] && e[0] != '0') ? 1 : 0;
+    g_debug.store(d, std::memory_order_relaxed);
+  }
+  return d != 0;
+}
+
 int hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess && debug_on()) {
+    e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipGetLastError();
+  }
   if (e == hipSuccess) return NGVOL_OK;
   return fail(NGVOL_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
@@ -120,6 +141,11 @@ extern "C" {
 
 const char* ngvol_last_error(void) { return g_err.c_str(); }
 const char* ngvol_version(void) { return "ngvol 0.1 (gfx950)"; }
+
+int ngvol_set_debug(int32_t on) {
+  g_debug.store(on ? 1 : 0, std::memory_order_relaxed);
+  return NGVOL_OK;
+}
 
 int ngvol_plan_create(const ngvol_config* c, ngvol_plan** out) {
   NGV_REQUIRE(c && out, "config and out must be non-NULL");

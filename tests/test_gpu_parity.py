@@ -513,6 +513,23 @@ def test_paper_default_training_matches_oracle_psnr():
     assert res["bf16"] >= res["fp32"] - 0.5
 
 
+def test_debug_mode_synchronises_and_matches():
+    # debug mode waits for and checks every launch; results are unchanged
+    p = gpu_plan("tiny")
+    params = dev(init_params("tiny"))
+    xyz = dev(synth.query_coords(5000, 9))
+    ref = host(ngv.infer(p, params, xyz)).copy()
+    ngv.set_debug(True)
+    try:
+        out = host(ngv.infer(p, params, xyz))
+        st = ngv.TrainState(p, params, 1024)
+        ngv.train_step(st, xyz=xyz[:1024], target=torch.zeros(1024, device="cuda"), loss_scale=128.0)
+        assert host(st.step)[0] == 1
+    finally:
+        ngv.set_debug(False)
+    np.testing.assert_array_equal(out, ref)
+
+
 # --------------------------------------------------------------- sampling -----
 
 def test_sampling_step_matches_oracle():
