@@ -231,17 +231,21 @@ k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs r
         k = sl.k + (uint32_t)q;
         valid = sl.pix >= 0 && k < sl.g.n;
       }
-      float x = 0.5f, y = 0.5f, z = 0.5f;
-      if (valid) {
-        ray_point(sl.g, k, ra.dt, x, y, z);
-        x = clamp01(x);
-        y = clamp01(y);
-        z = clamp01(z);
+      // a round in which no ray of the wave has a sample outside empty
+      // cells only advances the rays
+      if (!skip_empty || __any(valid)) {
+        float x = 0.5f, y = 0.5f, z = 0.5f;
+        if (valid) {
+          ray_point(sl.g, k, ra.dt, x, y, z);
+          x = clamp01(x);
+          y = clamp01(y);
+          z = clamp01(z);
+        }
+        encode_row<P, F, KIN>(md, table, x, y, z, row, [](int, const Oct<P>&) {});
+        wave_sync();
+        yv[lane] = mlp_wave64<P, KIN, W>(md.n_hidden, lds_frag, lds_wout, stage);
+        if (valid) ++n_eval;
       }
-      encode_row<P, F, KIN>(md, table, x, y, z, row, [](int, const Oct<P>&) {});
-      wave_sync();
-      yv[lane] = mlp_wave64<P, KIN, W>(md.n_hidden, lds_frag, lds_wout, stage);
-      if (valid) ++n_eval;
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
