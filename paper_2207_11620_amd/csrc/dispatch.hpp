@@ -27,3 +27,20 @@
     case 2: { constexpr int P = 2; __VA_ARGS__; } break;                     \
     default: return hipErrorInvalidValue;                                    \
   }
+#define NGV_DISPATCH_KIN(KIN_, ...)                                          \
+  switch (KIN_) {                                                            \
+    case 32: { constexpr int KIN = 32; __VA_ARGS__; } break;                 \
+    case 64: { constexpr int KIN = 64; __VA_ARGS__; } break;                 \
+    default: return hipErrorInvalidValue;                                    \
+  }
+
+// Translation units built once per (precision, MLP width) define NGV_PSEL
+// (0, 1 or 2) and NGV_WSEL (32 or 64); NGV_PRIMARY marks the one object of
+// such a unit that also holds its shape-independent code.
+#ifndef NGV_PSEL
+#define NGV_PSEL 0
+#endif
+#ifndef NGV_WSEL
+#define NGV_WSEL 32
+#endif
+#define NGV_PRIMARY (NGV_PSEL == 0 && NGV_WSEL == 32)

@@ -154,8 +154,20 @@ size_t split_planes_bytes(const ngvol_plan* plan, int64_t n);
 // split_planes_bytes and split_slab * 4 bytes.
 hipError_t launch_infer_split(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const float4* rec, int64_t n,
                               float* out, void* planes, uint32_t* idx, hipStream_t st);
+template <int P, int W>
+hipError_t launch_infer_split_p(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const float4* rec, int64_t n,
+                                float* out, void* planes, uint32_t* idx, hipStream_t st);
 
 size_t fwd_lds_bytes(const ngvol_plan* plan);
+// Persistent grid: enough workgroups of waves_per_block waves for n_tiles
+// wave work units, at most blocks_per_cu per compute unit.
+inline int grid_for(const ngvol_plan* plan, int64_t n_tiles, int waves_per_block, int blocks_per_cu) {
+  int64_t need = (n_tiles + waves_per_block - 1) / waves_per_block;
+  const int64_t cap = (int64_t)plan->cus * blocks_per_cu;
+  if (need > cap) need = cap;
+  if (need < 1) need = 1;
+  return (int)need;
+}
 // LDS of a workgroup (160 KB on gfx950)
 constexpr size_t kLdsLimit = 160 * 1024;
 // fwd_lds_bytes plus the per-wave encoding stages of the fused kernels, and
@@ -189,6 +201,20 @@ hipError_t launch_mlp_fwd(const ngvol_plan* plan, const float* mlp, const void* 
 hipError_t launch_train_fwd(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const BatchArgs& ba, void* e_buf,
                             float* g_buf, double* loss_acc, float gscale, int loss, hipStream_t st);
 hipError_t launch_sample_batch(const BatchArgs& ba, float* xyz, float* y, hipStream_t st);
+// The same launchers for one MLP precision P and width W (each defined in
+// the object built for that shape).
+template <int P, int W>
+hipError_t launch_infer_p(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const float* xyz, const float4* rec,
+                          int64_t n, float* out, hipStream_t st);
+template <int P, int W>
+hipError_t launch_sq_error_grid_p(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const void* vol, int dtype,
+                                  const int32_t dims[3], double* sq, hipStream_t st);
+template <int P, int W>
+hipError_t launch_mlp_fwd_p(const ngvol_plan* plan, const float* mlp, const void* feat, int dtype, int64_t n,
+                            float* out, hipStream_t st);
+template <int P, int W>
+hipError_t launch_train_fwd_p(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const BatchArgs& ba,
+                              void* e_buf, float* g_buf, double* loss_acc, float gscale, int loss, hipStream_t st);
 
 // Backward.  MODE 0: training (e_buf holds the stored encoding in the
 // plan's precision, de is scattered into the table gradient; coordinates
@@ -254,5 +280,8 @@ hipError_t launch_mc_opacity(const McGeom& g, const float* lut, hipStream_t st);
 size_t render_lds_bytes(const ngvol_plan* plan, int waves);
 hipError_t launch_render(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const RenderArgs& ra,
                          hipStream_t st);
+template <int P, int W>
+hipError_t launch_render_p(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const RenderArgs& ra,
+                           hipStream_t st);
 
 }  // namespace ngvol

@@ -1,5 +1,6 @@
-// Forward kernels: encoding, fused query, standalone MLP, training forward,
-// grid squared error, sampling step.
+// Forward kernels: encoding, fused query, standalone MLP, grid squared
+// error, sampling step.
+// build: one object per MLP precision and width (NGV_PSEL, NGV_WSEL)
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -37,6 +38,7 @@ __global__ void __launch_bounds__(256) k_encode(ModelDesc md, TablePtrs tp, cons
   }
 }
 
+#if NGV_PRIMARY
 // Corner slots and weights: one thread per (sample, level).
 __global__ void __launch_bounds__(256) k_encode_debug(ModelDesc md, const float* __restrict__ xyz, int64_t n,
                                                       uint32_t* __restrict__ idx, float* __restrict__ w) {
@@ -52,6 +54,7 @@ __global__ void __launch_bounds__(256) k_encode_debug(ModelDesc md, const float*
     if (w) w[t * 8 + k] = cr.w[k];
   }
 }
+#endif
 
 // ---------------------------------------------------------------------------
 // Fused query.  MODE 0: out[s] = Phi(xyz[s]).  MODE 1: grid voxel centres,
@@ -211,74 +214,6 @@ k_mlp_fwd(ModelDesc md, const float* __restrict__ mlp,
 }
 
 // ---------------------------------------------------------------------------
-// Training forward: sampling step (or explicit batch), encoding (stored for
-// the backward), MLP, loss, and g = S * dL/dy: gscale * (y_hat - y) for L2
-// (gscale = 2S/B), gscale * sign(y_hat - y) for L1 (gscale = S/B).
-// ---------------------------------------------------------------------------
-template <int P, int F, int KIN, int W, typename TT, typename VT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P != 0 && KIN == 32 ? 4 : 1)))
-k_train_fwd(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, BatchArgs ba, void* __restrict__ e_buf,
-            float* __restrict__ g_buf, double* __restrict__ loss_acc, float gscale, int l1) {
-  typedef typename Prec<P>::Frag Frag;
-  typedef typename Prec<P>::T T;
-  typedef WeightLayout<P, KIN, W> WL;
-  extern __shared__ __align__(16) unsigned char smem[];
-  Frag* lds_frag = reinterpret_cast<Frag*>(smem);
-  const size_t wbytes = (size_t)WL::frags(md.n_hidden, false) * 64 * sizeof(Frag);
-  float* lds_wout = reinterpret_cast<float*>(smem + wbytes);
-  stage_weights<P, KIN, W>(md, mlp, lds_frag, lds_wout, false);
-  __syncthreads();
-
-  const TT* table = table_ptr<TT>(tp);
-  const VT* vol = reinterpret_cast<const VT*>(ba.volume);
-  T* e = reinterpret_cast<T*>(e_buf);  // stored encoding [B][KIN] in the operand type
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  T* stage = reinterpret_cast<T*>(smem + stage_offset(wbytes, W) + wave * Stage<P, KIN>::wave_bytes);
-  T* row = stage + lane * Stage<P, KIN>::pitch;
-  const int64_t B = ba.B;
-  const int64_t bstep = ba.step_index();
-  double lsum = 0.0;
-  const int64_t n_groups = (B + 63) >> 6;
-  TileIter it(n_groups);
-  for (int64_t t = it.next; t < it.end; t += it.step) {
-    const int64_t s = t * 64 + lane;
-    const bool valid = s < B;
-    const int64_t sc = valid ? s : B - 1;
-    float x, y, z, target;
-    if (ba.xyz) {
-      x = clamp01(ba.xyz[3 * sc]);
-      y = clamp01(ba.xyz[3 * sc + 1]);
-      z = clamp01(ba.xyz[3 * sc + 2]);
-      target = ba.target[sc];
-    } else {
-      x = batch_coord(ba.seed, bstep, B, sc, 0);
-      y = batch_coord(ba.seed, bstep, B, sc, 1);
-      z = batch_coord(ba.seed, bstep, B, sc, 2);
-      target = volume_sample<VT>(vol, ba.dims[0], ba.dims[1], ba.dims[2], x, y, z);
-    }
-    encode_row<P, F, KIN>(md, table, x, y, z, row, [&](int sb, const Oct<P>& o) {
-      if (valid) *reinterpret_cast<Oct<P>*>(e + s * KIN + 8 * sb) = o;
-    });
-    wave_sync();
-    const float yv = mlp_wave64<P, KIN, W>(md.n_hidden, lds_frag, lds_wout, stage);
-    wave_sync();
-    if (valid && ba.mc.range) mc_extend(ba.mc.range, mc_index(ba.mc, x, y, z), target);
-    if (valid) {
-      const float r = yv - target;
-      if (l1) {
-        g_buf[s] = r > 0.0f ? gscale : (r < 0.0f ? -gscale : 0.0f);
-        lsum += (double)fabsf(r);
-      } else {
-        g_buf[s] = gscale * r;
-        lsum += (double)r * (double)r;
-      }
-    }
-  }
-  lsum = wave_sum(lsum);
-  if (lane == 0 && lsum != 0.0) atomicAdd(loss_acc, lsum);
-}
-
-// ---------------------------------------------------------------------------
 // Sampling step alone.
 // ---------------------------------------------------------------------------
 template <typename VT>
@@ -296,8 +231,76 @@ __global__ void __launch_bounds__(256) k_sample_batch(BatchArgs ba, float* __res
 }
 
 // ---------------------------------------------------------------------------
-// Host-side launchers (dispatch over the compile-time shapes).
+// Host-side launchers.  This file is compiled once per MLP precision
+// (NGV_PSEL = 0, 1, 2): each object holds the launchers of its precision,
+// and the first also the precision-independent launchers and dispatchers.
 // ---------------------------------------------------------------------------
+template <int P, int W, int MODE, typename VT>
+static hipError_t launch_infer_t(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const float* xyz,
+                                 const float4* rec, int64_t n, float* out, const VT* vol, int dx, int dy, int dz,
+                                 double* sq, hipStream_t st) {
+  const ModelDesc& md = plan->md;
+  const int64_t n_groups = (n + 63) / 64;  // 64 samples per wave
+  const int waves = enc_waves(plan);
+  const size_t lds = enc_lds_bytes(plan, waves);
+  const int grid = grid_for(plan, n_groups, waves, 32 / waves);
+  NGV_DISPATCH_F_KIN(md.F, plan->kin, {
+    if (tp.f16)
+      hipLaunchKernelGGL((k_infer<P, F, KIN, W, __half, MODE, VT>), dim3(grid), dim3(64 * waves), lds, st, md, tp, mlp,
+                         xyz, rec, n, out, vol, dx, dy, dz, sq);
+    else
+      hipLaunchKernelGGL((k_infer<P, F, KIN, W, float, MODE, VT>), dim3(grid), dim3(64 * waves), lds, st, md, tp, mlp,
+                         xyz, rec, n, out, vol, dx, dy, dz, sq);
+  });
+  return hipGetLastError();
+}
+
+template <int P, int W>
+hipError_t launch_infer_p(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const float* xyz,
+                          const float4* rec, int64_t n, float* out, hipStream_t st) {
+  return launch_infer_t<P, W, 0, float>(plan, tp, mlp, xyz, rec, n, out, nullptr, 1, 1, 1, nullptr, st);
+}
+
+template <int P, int W>
+hipError_t launch_sq_error_grid_p(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const void* vol, int dtype,
+                                  const int32_t dims[3], double* sq, hipStream_t st) {
+  const int64_t n = (int64_t)dims[0] * dims[1] * dims[2];
+  if (dtype == NGVOL_DT_F16)
+    return launch_infer_t<P, W, 1, __half>(plan, tp, mlp, nullptr, nullptr, n, nullptr,
+                                        reinterpret_cast<const __half*>(vol), dims[0], dims[1], dims[2], sq, st);
+  return launch_infer_t<P, W, 1, float>(plan, tp, mlp, nullptr, nullptr, n, nullptr,
+                                     reinterpret_cast<const float*>(vol), dims[0], dims[1], dims[2], sq, st);
+}
+
+template <int P, int W>
+hipError_t launch_mlp_fwd_p(const ngvol_plan* plan, const float* mlp, const void* feat, int dtype, int64_t n,
+                            float* out, hipStream_t st) {
+  const ModelDesc& md = plan->md;
+  const int64_t n_tiles = (n + 31) / 32;  // 2-tile groups
+  const size_t lds = fwd_lds_bytes(plan);
+  const int grid = grid_for(plan, n_tiles, 4, 8);
+  NGV_DISPATCH_KIN(plan->kin, {
+    if (dtype == NGVOL_DT_BF16)
+      hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, __bf16>), dim3(grid), dim3(256), lds, st, md, mlp,
+                         (const __bf16*)feat, n, out);
+    else if (dtype == NGVOL_DT_F16)
+      hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, _Float16>), dim3(grid), dim3(256), lds, st, md, mlp,
+                         (const _Float16*)feat, n, out);
+    else
+      hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, float>), dim3(grid), dim3(256), lds, st, md, mlp,
+                         (const float*)feat, n, out);
+  });
+  return hipGetLastError();
+}
+
+template hipError_t launch_infer_p<NGV_PSEL, NGV_WSEL>(const ngvol_plan*, TablePtrs, const float*, const float*, const float4*,
+                                             int64_t, float*, hipStream_t);
+template hipError_t launch_sq_error_grid_p<NGV_PSEL, NGV_WSEL>(const ngvol_plan*, TablePtrs, const float*, const void*, int,
+                                                     const int32_t*, double*, hipStream_t);
+template hipError_t launch_mlp_fwd_p<NGV_PSEL, NGV_WSEL>(const ngvol_plan*, const float*, const void*, int, int64_t, float*,
+                                               hipStream_t);
+
+#if NGV_PRIMARY
 size_t fwd_lds_bytes(const ngvol_plan* plan) {
   const int P = plan->layout.precision, KIN = plan->kin, W = plan->layout.n_neurons, nh = plan->md.n_hidden;
   const int ch0 = P ? KIN / 32 : KIN / 4;
@@ -319,14 +322,6 @@ int enc_waves(const ngvol_plan* plan) {
   for (int w = 4; w > 1; w >>= 1)
     if (enc_lds_bytes(plan, w) <= kLdsLimit) return w;
   return 1;
-}
-
-static int grid_for(const ngvol_plan* plan, int64_t n_tiles, int waves_per_block, int blocks_per_cu) {
-  int64_t need = (n_tiles + waves_per_block - 1) / waves_per_block;
-  int64_t cap = (int64_t)plan->cus * blocks_per_cu;
-  if (need > cap) need = cap;
-  if (need < 1) need = 1;
-  return (int)need;
 }
 
 hipError_t launch_encode(const ngvol_plan* plan, TablePtrs tp, const float* xyz, int64_t n, float* feat,
@@ -351,102 +346,22 @@ hipError_t launch_encode_debug(const ngvol_plan* plan, const float* xyz, int64_t
   return hipGetLastError();
 }
 
-template <int MODE, typename VT>
-static hipError_t launch_infer_t(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const float* xyz,
-                                 const float4* rec, int64_t n, float* out, const VT* vol, int dx, int dy, int dz,
-                                 double* sq, hipStream_t st) {
-  const ModelDesc& md = plan->md;
-  const int64_t n_groups = (n + 63) / 64;  // 64 samples per wave
-  const int waves = enc_waves(plan);
-  const size_t lds = enc_lds_bytes(plan, waves);
-  const int grid = grid_for(plan, n_groups, waves, 32 / waves);
-  NGV_DISPATCH_P(plan->layout.precision, NGV_DISPATCH_F_KIN(md.F, plan->kin, NGV_DISPATCH_W(md.width, {
-    if (tp.f16)
-      hipLaunchKernelGGL((k_infer<P, F, KIN, W, __half, MODE, VT>), dim3(grid), dim3(64 * waves), lds, st, md, tp, mlp, xyz,
-                         rec, n, out, vol, dx, dy, dz, sq);
-    else
-      hipLaunchKernelGGL((k_infer<P, F, KIN, W, float, MODE, VT>), dim3(grid), dim3(64 * waves), lds, st, md, tp, mlp, xyz,
-                         rec, n, out, vol, dx, dy, dz, sq);
-  })));
-  return hipGetLastError();
-}
-
 hipError_t launch_infer(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const float* xyz, const float4* rec,
                         int64_t n, float* out, hipStream_t st) {
-  return launch_infer_t<0, float>(plan, tp, mlp, xyz, rec, n, out, nullptr, 1, 1, 1, nullptr, st);
+  NGV_DISPATCH_P(plan->layout.precision, NGV_DISPATCH_W(plan->md.width, return launch_infer_p<P, W>(plan, tp, mlp, xyz, rec, n, out, st)));
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_sq_error_grid(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const void* vol, int dtype,
                                 const int32_t dims[3], double* sq, hipStream_t st) {
-  const int64_t n = (int64_t)dims[0] * dims[1] * dims[2];
-  if (dtype == NGVOL_DT_F16)
-    return launch_infer_t<1, __half>(plan, tp, mlp, nullptr, nullptr, n, nullptr,
-                                     reinterpret_cast<const __half*>(vol), dims[0], dims[1], dims[2], sq, st);
-  return launch_infer_t<1, float>(plan, tp, mlp, nullptr, nullptr, n, nullptr, reinterpret_cast<const float*>(vol),
-                                  dims[0], dims[1], dims[2], sq, st);
+  NGV_DISPATCH_P(plan->layout.precision, NGV_DISPATCH_W(plan->md.width, return launch_sq_error_grid_p<P, W>(plan, tp, mlp, vol, dtype, dims, sq, st)));
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_mlp_fwd(const ngvol_plan* plan, const float* mlp, const void* feat, int dtype, int64_t n,
                           float* out, hipStream_t st) {
-  const ModelDesc& md = plan->md;
-  const int64_t n_tiles = (n + 31) / 32;  // 2-tile groups
-  const size_t lds = fwd_lds_bytes(plan);
-  const int grid = grid_for(plan, n_tiles, 4, 8);
-  NGV_DISPATCH_P(plan->layout.precision, {
-    switch (plan->kin * 100 + md.width) {
-      case 3232: { constexpr int KIN = 32, W = 32;
-        if (dtype == NGVOL_DT_BF16) hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, __bf16>), dim3(grid), dim3(256), lds, st, md, mlp, (const __bf16*)feat, n, out);
-        else if (dtype == NGVOL_DT_F16) hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, _Float16>), dim3(grid), dim3(256), lds, st, md, mlp, (const _Float16*)feat, n, out);
-        else hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, float>), dim3(grid), dim3(256), lds, st, md, mlp, (const float*)feat, n, out);
-      } break;
-      case 3264: { constexpr int KIN = 32, W = 64;
-        if (dtype == NGVOL_DT_BF16) hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, __bf16>), dim3(grid), dim3(256), lds, st, md, mlp, (const __bf16*)feat, n, out);
-        else if (dtype == NGVOL_DT_F16) hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, _Float16>), dim3(grid), dim3(256), lds, st, md, mlp, (const _Float16*)feat, n, out);
-        else hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, float>), dim3(grid), dim3(256), lds, st, md, mlp, (const float*)feat, n, out);
-      } break;
-      case 6432: { constexpr int KIN = 64, W = 32;
-        if (dtype == NGVOL_DT_BF16) hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, __bf16>), dim3(grid), dim3(256), lds, st, md, mlp, (const __bf16*)feat, n, out);
-        else if (dtype == NGVOL_DT_F16) hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, _Float16>), dim3(grid), dim3(256), lds, st, md, mlp, (const _Float16*)feat, n, out);
-        else hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, float>), dim3(grid), dim3(256), lds, st, md, mlp, (const float*)feat, n, out);
-      } break;
-      case 6464: { constexpr int KIN = 64, W = 64;
-        if (dtype == NGVOL_DT_BF16) hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, __bf16>), dim3(grid), dim3(256), lds, st, md, mlp, (const __bf16*)feat, n, out);
-        else if (dtype == NGVOL_DT_F16) hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, _Float16>), dim3(grid), dim3(256), lds, st, md, mlp, (const _Float16*)feat, n, out);
-        else hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, float>), dim3(grid), dim3(256), lds, st, md, mlp, (const float*)feat, n, out);
-      } break;
-      default: return hipErrorInvalidValue;
-    }
-  });
-  return hipGetLastError();
-}
-
-hipError_t launch_train_fwd(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const BatchArgs& ba, void* e_buf,
-                            float* g_buf, double* loss_acc, float gscale, int loss, hipStream_t st) {
-  const ModelDesc& md = plan->md;
-  const int l1 = loss == NGVOL_LOSS_L1;
-  const int64_t n_groups = (ba.B + 63) / 64;  // 64 samples per wave
-  const int waves = enc_waves(plan);
-  const size_t lds = enc_lds_bytes(plan, waves);
-  const int grid = grid_for(plan, n_groups, waves, 32 / waves);
-  const bool vf16 = ba.xyz == nullptr && ba.vdtype == NGVOL_DT_F16;
-  NGV_DISPATCH_P(plan->layout.precision, NGV_DISPATCH_F_KIN(md.F, plan->kin, NGV_DISPATCH_W(md.width, {
-    if (tp.f16) {
-      if (vf16)
-        hipLaunchKernelGGL((k_train_fwd<P, F, KIN, W, __half, __half>), dim3(grid), dim3(64 * waves), lds, st, md, tp, mlp, ba,
-                           e_buf, g_buf, loss_acc, gscale, l1);
-      else
-        hipLaunchKernelGGL((k_train_fwd<P, F, KIN, W, __half, float>), dim3(grid), dim3(64 * waves), lds, st, md, tp, mlp, ba,
-                           e_buf, g_buf, loss_acc, gscale, l1);
-    } else {
-      if (vf16)
-        hipLaunchKernelGGL((k_train_fwd<P, F, KIN, W, float, __half>), dim3(grid), dim3(64 * waves), lds, st, md, tp, mlp, ba,
-                           e_buf, g_buf, loss_acc, gscale, l1);
-      else
-        hipLaunchKernelGGL((k_train_fwd<P, F, KIN, W, float, float>), dim3(grid), dim3(64 * waves), lds, st, md, tp, mlp, ba,
-                           e_buf, g_buf, loss_acc, gscale, l1);
-    }
-  })));
-  return hipGetLastError();
+  NGV_DISPATCH_P(plan->layout.precision, NGV_DISPATCH_W(plan->md.width, return launch_mlp_fwd_p<P, W>(plan, mlp, feat, dtype, n, out, st)));
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_sample_batch(const BatchArgs& ba, float* xyz, float* y, hipStream_t st) {
@@ -457,5 +372,6 @@ hipError_t launch_sample_batch(const BatchArgs& ba, float* xyz, float* y, hipStr
     hipLaunchKernelGGL(k_sample_batch<float>, dim3((unsigned)grid), dim3(256), 0, st, ba, xyz, y);
   return hipGetLastError();
 }
+#endif  // NGV_PRIMARY
 
 }  // namespace ngvol

@@ -14,7 +14,9 @@
 // workgroups fetch rays from the band of their XCD (workgroup id mod 8),
 // so neighbouring rays (coherent hash-table footprints) share an L2, and
 // steal from the other bands once their own is empty.
+// build: one object per MLP precision and width (NGV_PSEL, NGV_WSEL)
 #include "kernels.hpp"
+#include "dispatch.hpp"
 #include "mlp_tile.hpp"
 
 namespace ngvol {
@@ -92,11 +94,15 @@ struct SlotState {
 constexpr int kList = kK + 2;
 constexpr int kCnt = kK, kNext = kK + 1;
 
+#if NGV_PRIMARY
 __global__ void k_render_init(unsigned int* queue, unsigned long long* counters) {
   const int t = threadIdx.x;
   if (t < kBands) queue[t] = 0u;
   if (t < 4 && counters) counters[t] = 0ull;
 }
+#else
+__global__ void k_render_init(unsigned int* queue, unsigned long long* counters);
+#endif
 
 // Fetch the next pixel: own band first, then steal from the others.
 __device__ __forceinline__ int32_t fetch_pixel(unsigned int* queue, int band0, int64_t n_pix) {
@@ -304,6 +310,7 @@ k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs r
   }
 }
 
+#if NGV_PRIMARY
 size_t render_lds_bytes(const ngvol_plan* plan, int waves) {
   const size_t esz = plan->layout.precision ? 2 : 4;
   const size_t stage = (size_t)64 * (plan->kin + 16 / esz) * esz;
@@ -311,11 +318,12 @@ size_t render_lds_bytes(const ngvol_plan* plan, int waves) {
                              waves) +
          (size_t)waves * stage;
 }
+#endif
 
-hipError_t launch_render(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const RenderArgs& ra,
-                         hipStream_t st) {
+template <int P, int W>
+hipError_t launch_render_p(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const RenderArgs& ra,
+                           hipStream_t st) {
   const ModelDesc& md = plan->md;
-  hipLaunchKernelGGL(k_render_init, dim3(1), dim3(64), 0, st, ra.queue, ra.counters);
   const size_t lds = render_lds_bytes(plan, 4);
   const int64_t n_pix = (int64_t)ra.width * ra.height;
   int64_t grid = (n_pix + 4 * kSlots - 1) / (4 * kSlots);
@@ -323,44 +331,32 @@ hipError_t launch_render(const ngvol_plan* plan, TablePtrs tp, const float* mlp,
   if (grid > cap) grid = cap;
   if (grid < 1) grid = 1;
   const bool skip = ra.mc.mu != nullptr;
-#define NGV_RENDER_GO(P, F, KIN, W, TT, S) \
-  hipLaunchKernelGGL((k_render<P, F, KIN, W, TT, S>), dim3((unsigned)grid), dim3(256), lds, st, md, tp, mlp, ra)
-#define NGV_RENDER(P, F, KIN, W)                                  \
-  do {                                                            \
-    if (tp.f16) {                                                 \
-      if (skip) NGV_RENDER_GO(P, F, KIN, W, __half, true);        \
-      else NGV_RENDER_GO(P, F, KIN, W, __half, false);            \
-    } else {                                                      \
-      if (skip) NGV_RENDER_GO(P, F, KIN, W, float, true);         \
-      else NGV_RENDER_GO(P, F, KIN, W, float, false);             \
-    }                                                             \
-  } while (0)
-#define NGV_RENDER_W(P, F, KIN)                              \
-  do {                                                       \
-    if (md.width == 32) NGV_RENDER(P, F, KIN, 32);            \
-    else if (md.width == 64) NGV_RENDER(P, F, KIN, 64);       \
-    else return hipErrorInvalidValue;                        \
-  } while (0)
-#define NGV_RENDER_FK(P)                                              \
-  do {                                                                \
-    switch (md.F * 1000 + plan->kin) {                                \
-      case 2032: NGV_RENDER_W(P, 2, 32); break;                       \
-      case 2064: NGV_RENDER_W(P, 2, 64); break;                       \
-      case 4032: NGV_RENDER_W(P, 4, 32); break;                       \
-      case 4064: NGV_RENDER_W(P, 4, 64); break;                       \
-      case 8032: NGV_RENDER_W(P, 8, 32); break;                       \
-      case 8064: NGV_RENDER_W(P, 8, 64); break;                       \
-      default: return hipErrorInvalidValue;                           \
-    }                                                                 \
-  } while (0)
-  if (plan->layout.precision == 1) NGV_RENDER_FK(1);
-  else if (plan->layout.precision == 2) NGV_RENDER_FK(2);
-  else NGV_RENDER_FK(0);
-#undef NGV_RENDER_FK
-#undef NGV_RENDER_W
-#undef NGV_RENDER
-#undef NGV_RENDER_GO
+  NGV_DISPATCH_F_KIN(md.F, plan->kin, {
+    if (tp.f16) {
+      if (skip)
+        hipLaunchKernelGGL((k_render<P, F, KIN, W, __half, true>), dim3((unsigned)grid), dim3(256), lds, st, md, tp, mlp, ra);
+      else
+        hipLaunchKernelGGL((k_render<P, F, KIN, W, __half, false>), dim3((unsigned)grid), dim3(256), lds, st, md, tp, mlp, ra);
+    } else {
+      if (skip)
+        hipLaunchKernelGGL((k_render<P, F, KIN, W, float, true>), dim3((unsigned)grid), dim3(256), lds, st, md, tp, mlp, ra);
+      else
+        hipLaunchKernelGGL((k_render<P, F, KIN, W, float, false>), dim3((unsigned)grid), dim3(256), lds, st, md, tp, mlp, ra);
+    }
+  });
   return hipGetLastError();
 }
+
+template hipError_t launch_render_p<NGV_PSEL, NGV_WSEL>(const ngvol_plan*, TablePtrs, const float*, const RenderArgs&,
+                                              hipStream_t);
+
+#if NGV_PRIMARY
+hipError_t launch_render(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const RenderArgs& ra,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_render_init, dim3(1), dim3(64), 0, st, ra.queue, ra.counters);
+  NGV_DISPATCH_P(plan->layout.precision, NGV_DISPATCH_W(plan->md.width, return launch_render_p<P, W>(plan, tp, mlp, ra, st)));
+  return hipErrorInvalidValue;
+}
+#endif
 
 }  // namespace ngvol

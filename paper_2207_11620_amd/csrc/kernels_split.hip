@@ -22,6 +22,7 @@
 // Features are converted to the operand type exactly as in the fused
 // kernel; the products of the first layer are summed in another order, so
 // outputs agree with the fused kernel to FP32 rounding, not bitwise.
+// build: one object per MLP precision and width (NGV_PSEL, NGV_WSEL)
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -227,12 +228,14 @@ k_mlp_planes(ModelDesc md, const float* __restrict__ mlp, const OT* __restrict__
 
 }  // namespace
 
+#if NGV_PRIMARY
 bool use_split(const ngvol_plan* plan, int64_t n) {
   // worth it when the queries are many and the FP16 tables exceed one XCD's L2
   return n >= ((int64_t)1 << 20) && plan->md.L >= 2 && (int64_t)plan->md.n_table * 2 > ((int64_t)4 << 20);
 }
+#endif
 
-SplitArgs split_args(const ngvol_plan* plan) {
+static SplitArgs split_args(const ngvol_plan* plan) {
   SplitArgs sa{};
   const int L = plan->md.L;
   sa.width = L >= 8 ? (L + 7) / 8 : 1;
@@ -255,7 +258,7 @@ SplitArgs split_args(const ngvol_plan* plan) {
   return sa;
 }
 
-int split_operand_bytes(const ngvol_plan* plan) { return plan->layout.precision ? 2 : 4; }
+static int split_operand_bytes(const ngvol_plan* plan) { return plan->layout.precision ? 2 : 4; }
 
 static int64_t plane_levels(const ngvol_plan* plan) {
   // levels of plane storage per query: 8 groups of equal width (or L < 8 single levels)
@@ -263,6 +266,7 @@ static int64_t plane_levels(const ngvol_plan* plan) {
   return L >= 8 ? 8 * ((L + 7) / 8) : L;
 }
 
+#if NGV_PRIMARY
 int64_t split_slab(const ngvol_plan* plan, int64_t n) {
   // planes of at most 1 GiB (or 2^20 queries) per pass, in whole 64-query chunks
   const int64_t per_query = plane_levels(plan) * plan->md.F * split_operand_bytes(plan);
@@ -275,9 +279,11 @@ int64_t split_slab(const ngvol_plan* plan, int64_t n) {
 size_t split_planes_bytes(const ngvol_plan* plan, int64_t n) {
   return (size_t)split_slab(plan, n) * plane_levels(plan) * plan->md.F * split_operand_bytes(plan);
 }
+#endif
 
-hipError_t launch_infer_split(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const float4* rec, int64_t n,
-                              float* out, void* planes, uint32_t* idx, hipStream_t st) {
+template <int P, int W>
+hipError_t launch_infer_split_p(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const float4* rec, int64_t n,
+                                float* out, void* planes, uint32_t* idx, hipStream_t st) {
   const ModelDesc& md = plan->md;
   const SplitArgs sa = split_args(plan);
   const int64_t slab = split_slab(plan, n);
@@ -310,7 +316,7 @@ hipError_t launch_infer_split(const ngvol_plan* plan, TablePtrs tp, const float*
     if (mgrid > (int64_t)plan->cus * 8) mgrid = (int64_t)plan->cus * 8;
     if (mgrid < 1) mgrid = 1;
     const float4* r = rec + s0;
-    NGV_DISPATCH_P(plan->layout.precision, NGV_DISPATCH_F_KIN(md.F, plan->kin, NGV_DISPATCH_W(md.width, {
+    NGV_DISPATCH_F_KIN(md.F, plan->kin, {
       typedef typename std::conditional<P == 0, float, typename Prec<P>::T>::type OT;
       OT* pl = reinterpret_cast<OT*>(planes);
       if (tp.f16)
@@ -328,12 +334,24 @@ hipError_t launch_infer_split(const ngvol_plan* plan, TablePtrs tp, const float*
         if (full) NGV_MP(2, true);
         else NGV_MP(2, false);
       }
-    })));
+    });
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
 #undef NGV_MP
   return hipSuccess;
 }
+
+template hipError_t launch_infer_split_p<NGV_PSEL, NGV_WSEL>(const ngvol_plan*, TablePtrs, const float*, const float4*, int64_t,
+                                                   float*, void*, uint32_t*, hipStream_t);
+
+#if NGV_PRIMARY
+hipError_t launch_infer_split(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const float4* rec, int64_t n,
+                              float* out, void* planes, uint32_t* idx, hipStream_t st) {
+  NGV_DISPATCH_P(plan->layout.precision,
+                 NGV_DISPATCH_W(plan->md.width, return launch_infer_split_p<P, W>(plan, tp, mlp, rec, n, out, planes, idx, st)));
+  return hipErrorInvalidValue;
+}
+#endif
 
 }  // namespace ngvol
