@@ -47,10 +47,17 @@ bool debug_on() {
   return d != 0;
 }
 
-int hip_check(hipError_t e, const char* what) {
+// In debug mode a call on a stream that is being captured into a graph
+// cannot wait for the device; it then only checks the launches' status.
+int hip_check(hipError_t e, const char* what, hipStream_t st) {
   if (e == hipSuccess && debug_on()) {
-    e = hipDeviceSynchronize();
-    if (e == hipSuccess) e = hipGetLastError();
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
+      e = hipGetLastError();
+    } else {
+      e = hipDeviceSynchronize();
+      if (e == hipSuccess) e = hipGetLastError();
+    }
   }
   if (e == hipSuccess) return NGVOL_OK;
   return fail(NGVOL_EDEVICE, "%s: %s", what, hipGetErrorString(e));
@@ -256,7 +263,7 @@ int ngvol_encode(const ngvol_plan* plan, const ngvol_weights* w, const float* xy
   NGV_REQUIRE(n >= 0, "n must be >= 0");
   if (n == 0) return NGVOL_OK;
   NGV_REQUIRE(xyz && feat && aligned4(xyz) && aligned4(feat), "xyz and feat must be non-NULL and 4-byte aligned");
-  return hip_check(launch_encode(plan, tables_of(plan, w), xyz, n, feat, st), "encode launch");
+  return hip_check(launch_encode(plan, tables_of(plan, w), xyz, n, feat, st), "encode launch", st);
 }
 
 int ngvol_encode_debug(const ngvol_plan* plan, const float* xyz, int64_t n, uint32_t* idx, float* w, hipStream_t st) {
@@ -265,7 +272,7 @@ int ngvol_encode_debug(const ngvol_plan* plan, const float* xyz, int64_t n, uint
   if (n == 0) return NGVOL_OK;
   NGV_REQUIRE(xyz && aligned4(xyz) && aligned4(idx) && aligned4(w), "xyz must be non-NULL; buffers 4-byte aligned");
   NGV_REQUIRE(n * plan->md.L < ((int64_t)1 << 31) * 256, "n too large");
-  return hip_check(launch_encode_debug(plan, xyz, n, idx, w, st), "encode_debug launch");
+  return hip_check(launch_encode_debug(plan, xyz, n, idx, w, st), "encode_debug launch", st);
 }
 
 int ngvol_mlp_fwd(const ngvol_plan* plan, const float* params, const void* feat, int32_t dtype, int64_t n, float* out,
@@ -277,7 +284,7 @@ int ngvol_mlp_fwd(const ngvol_plan* plan, const float* params, const void* feat,
               "params and feat must be non-NULL and 16-byte aligned, out 4-byte aligned");
   NGV_REQUIRE(dtype == NGVOL_DT_F32 || dtype == NGVOL_DT_BF16 || dtype == NGVOL_DT_F16,
               "feat dtype must be NGVOL_DT_F32, NGVOL_DT_BF16 or NGVOL_DT_F16");
-  return hip_check(launch_mlp_fwd(plan, params + plan->md.n_table, feat, dtype, n, out, st), "mlp_fwd launch");
+  return hip_check(launch_mlp_fwd(plan, params + plan->md.n_table, feat, dtype, n, out, st), "mlp_fwd launch", st);
 }
 
 // Query on grouped records: level-split passes for large sets, else the
@@ -314,10 +321,10 @@ int ngvol_infer(const ngvol_plan* plan, const ngvol_weights* w, const float* xyz
   if (ws && bp.k) {
     if (ws_bytes < bp.bytes) return fail(NGVOL_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, bp.bytes);
     hipError_t e = launch_bin(plan, bp, xyz, nullptr, n, ws, st);
-    if (e != hipSuccess) return hip_check(e, "infer binning launch");
-    return hip_check(launch_grouped(plan, bp, w, ws, n, out, st), "infer launch");
+    if (e != hipSuccess) return hip_check(e, "infer binning launch", st);
+    return hip_check(launch_grouped(plan, bp, w, ws, n, out, st), "infer launch", st);
   }
-  return hip_check(launch_infer(plan, tables_of(plan, w), mlp, xyz, nullptr, n, out, st), "infer launch");
+  return hip_check(launch_infer(plan, tables_of(plan, w), mlp, xyz, nullptr, n, out, st), "infer launch", st);
 }
 
 int ngvol_sort_queries(const ngvol_plan* plan, const float* xyz, int64_t n, void* ws, size_t ws_bytes,
@@ -328,7 +335,7 @@ int ngvol_sort_queries(const ngvol_plan* plan, const float* xyz, int64_t n, void
   const BinPlan bp = bin_plan(plan, n);
   NGV_REQUIRE(bp.k, "%lld queries are too few to group (ngvol_infer_workspace_bytes is 0)", (long long)n);
   if (ws_bytes < bp.bytes) return fail(NGVOL_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, bp.bytes);
-  return hip_check(launch_bin(plan, bp, xyz, nullptr, n, ws, st), "sort_queries launch");
+  return hip_check(launch_bin(plan, bp, xyz, nullptr, n, ws, st), "sort_queries launch", st);
 }
 
 int ngvol_infer_sorted(const ngvol_plan* plan, const ngvol_weights* w, void* ws, int64_t n, float* out,
@@ -339,8 +346,27 @@ int ngvol_infer_sorted(const ngvol_plan* plan, const ngvol_weights* w, void* ws,
   NGV_REQUIRE(ws && out && aligned16(ws) && aligned4(out), "workspace and out must be non-NULL and aligned");
   const BinPlan bp = bin_plan(plan, n);
   NGV_REQUIRE(bp.k, "%lld queries are too few to group (ngvol_infer_workspace_bytes is 0)", (long long)n);
-  return hip_check(launch_grouped(plan, bp, w, ws, n, out, st), "infer_sorted launch");
+  return hip_check(launch_grouped(plan, bp, w, ws, n, out, st), "infer_sorted launch", st);
 }
+
+}  // extern "C"
+
+namespace {
+// MLP backward on caller features (MODE 1 of k_bwd), dW partial sums in
+// `partial` ([grid][n_mlp]), then their fixed-order reduction into grad.
+hipError_t launch_mlp_bwd_pass(const ngvol_plan* plan, const float* params, const float* feat, int64_t n,
+                               const float* dout, float* dfeat, float* grad, float* partial, int grid, int32_t* flag,
+                               hipStream_t st) {
+  BatchArgs ba{};
+  ba.B = n;
+  hipError_t e = launch_bwd(plan, 1, params + plan->md.n_table, feat, dout, ba, grad, dfeat, partial, grid, flag, 1.0f,
+                            st);
+  if (e == hipSuccess) e = launch_reduce_partials(plan, partial, grid, grad, flag, st);
+  return e;
+}
+}  // namespace
+
+extern "C" {
 
 int ngvol_mlp_bwd_workspace_bytes(const ngvol_plan* plan, int64_t n, size_t* bytes) {
   if (int rc = check_plan(plan)) return rc;
@@ -365,13 +391,11 @@ int ngvol_mlp_bwd(const ngvol_plan* plan, const float* params, const float* feat
   const int grid = bwd_grid(plan, n);
   float* partial = reinterpret_cast<float*>(ws);
   int32_t* flag = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(ws) + need - 256);
-  BatchArgs ba{};
-  ba.B = n;
-  hipError_t e = launch_bwd(plan, 1, params + plan->md.n_table, feat, dout, ba, grad, dfeat, partial, grid, flag, 1.0f,
-                            st);
-  if (e == hipSuccess) e = launch_reduce_partials(plan, partial, grid, grad, flag, st);
-  return hip_check(e, "mlp_bwd launch");
+  return hip_check(launch_mlp_bwd_pass(plan, params, feat, n, dout, dfeat, grad, partial, grid, flag, st),
+                   "mlp_bwd launch", st);
 }
+
+
 
 int ngvol_encode_bwd(const ngvol_plan* plan, const float* xyz, int64_t n, const float* dfeat, float* grad,
                      hipStream_t st) {
@@ -380,7 +404,7 @@ int ngvol_encode_bwd(const ngvol_plan* plan, const float* xyz, int64_t n, const 
   if (n == 0) return NGVOL_OK;
   NGV_REQUIRE(xyz && dfeat && grad && aligned4(xyz) && aligned4(dfeat) && aligned4(grad),
               "xyz, dfeat and grad must be non-NULL and 4-byte aligned");
-  return hip_check(launch_encode_bwd(plan, xyz, n, dfeat, grad, st), "encode_bwd launch");
+  return hip_check(launch_encode_bwd(plan, xyz, n, dfeat, grad, st), "encode_bwd launch", st);
 }
 
 static int resolve_mc(const ngvol_macrocells* mc, McGeom& g, bool need_range, bool need_mu) {
@@ -436,7 +460,7 @@ static int resolve_batch(const ngvol_plan* plan, const ngvol_batch* b, BatchArgs
 int ngvol_mc_reset(const ngvol_macrocells* mc, hipStream_t st) {
   McGeom g{};
   if (int rc = resolve_mc(mc, g, true, false)) return rc;
-  return hip_check(launch_mc_reset(g, st), "mc_reset launch");
+  return hip_check(launch_mc_reset(g, st), "mc_reset launch", st);
 }
 
 int ngvol_mc_update(const ngvol_macrocells* mc, const float* xyz, const float* values, int64_t n, hipStream_t st) {
@@ -445,14 +469,14 @@ int ngvol_mc_update(const ngvol_macrocells* mc, const float* xyz, const float* v
   NGV_REQUIRE(n >= 0 && n < ((int64_t)1 << 40), "n out of range");
   NGV_REQUIRE(n == 0 || (xyz && values && aligned4(xyz) && aligned4(values)),
               "xyz and values must be non-NULL and 4-byte aligned");
-  return hip_check(launch_mc_update(g, xyz, values, n, st), "mc_update launch");
+  return hip_check(launch_mc_update(g, xyz, values, n, st), "mc_update launch", st);
 }
 
 int ngvol_mc_opacity(const ngvol_macrocells* mc, const float* lut, hipStream_t st) {
   McGeom g{};
   if (int rc = resolve_mc(mc, g, true, true)) return rc;
   NGV_REQUIRE(lut && aligned4(lut), "lut must be non-NULL and 4-byte aligned");
-  return hip_check(launch_mc_opacity(g, lut, st), "mc_opacity launch");
+  return hip_check(launch_mc_opacity(g, lut, st), "mc_opacity launch", st);
 }
 
 int ngvol_sample_batch(const ngvol_plan* plan, const ngvol_batch* b, float* xyz, float* y, hipStream_t st) {
@@ -462,7 +486,7 @@ int ngvol_sample_batch(const ngvol_plan* plan, const ngvol_batch* b, float* xyz,
   NGV_REQUIRE(!b->xyz, "ngvol_sample_batch needs a generated batch (xyz == NULL)");
   NGV_REQUIRE(b->step_index >= 0, "ngvol_sample_batch needs an explicit step_index");
   NGV_REQUIRE(xyz && y && aligned4(xyz) && aligned4(y), "outputs must be non-NULL and 4-byte aligned");
-  return hip_check(launch_sample_batch(ba, xyz, y, st), "sample_batch launch");
+  return hip_check(launch_sample_batch(ba, xyz, y, st), "sample_batch launch", st);
 }
 
 int ngvol_train_workspace_bytes(const ngvol_plan* plan, int64_t B, size_t* bytes) {
@@ -553,7 +577,7 @@ int ngvol_train_step(const ngvol_plan* plan, const ngvol_train_state* s, const n
     e = launch_adam(plan, s->params, reinterpret_cast<__half*>(s->table_f16), s->grad, s->adam_m, s->adam_v, s->step,
                     flag, aa, st);
   if (e == hipSuccess) e = launch_step_end(loss_acc, flag, s->step, s->skipped, s->loss, 1.0 / (double)ba.B, st);
-  return hip_check(e, "train_step launch");
+  return hip_check(e, "train_step launch", st);
 }
 
 int ngvol_adam_step(const ngvol_plan* plan, const ngvol_train_state* s, const ngvol_adam* a, float loss_scale,
@@ -571,13 +595,13 @@ int ngvol_adam_step(const ngvol_plan* plan, const ngvol_train_state* s, const ng
     e = launch_adam(plan, s->params, reinterpret_cast<__half*>(s->table_f16), s->grad, s->adam_m, s->adam_v, s->step,
                     flag, aa, st);
   if (e == hipSuccess) e = launch_step_end(loss_acc, flag, s->step, s->skipped, nullptr, 1.0, st);
-  return hip_check(e, "adam launch");
+  return hip_check(e, "adam launch", st);
 }
 
 int ngvol_make_f16_tables(const ngvol_plan* plan, const float* params, uint16_t* out, hipStream_t st) {
   if (int rc = check_plan(plan)) return rc;
   NGV_REQUIRE(params && out && aligned16(params) && aligned16(out), "params and out must be non-NULL, 16-byte aligned");
-  return hip_check(launch_make_f16(params, reinterpret_cast<__half*>(out), plan->md.n_table, st), "make_f16 launch");
+  return hip_check(launch_make_f16(params, reinterpret_cast<__half*>(out), plan->md.n_table, st), "make_f16 launch", st);
 }
 
 int ngvol_sq_error_grid(const ngvol_plan* plan, const ngvol_weights* w, const void* vol, const int32_t dims[3],
@@ -588,7 +612,7 @@ int ngvol_sq_error_grid(const ngvol_plan* plan, const ngvol_weights* w, const vo
   NGV_REQUIRE(dims[0] >= 1 && dims[1] >= 1 && dims[2] >= 1, "dims must be positive");
   NGV_REQUIRE(dtype == NGVOL_DT_F32 || dtype == NGVOL_DT_F16, "volume dtype must be F32 or F16");
   return hip_check(launch_sq_error_grid(plan, tables_of(plan, w), w->params + plan->md.n_table, vol, dtype, dims, sq, st),
-                   "sq_error_grid launch");
+                   "sq_error_grid launch", st);
 }
 
 size_t ngvol_render_workspace_bytes(void) { return 256; }
@@ -619,7 +643,7 @@ int ngvol_render(const ngvol_plan* plan, const ngvol_weights* w, const ngvol_cam
   ra.n_used = n_used;
   ra.queue = reinterpret_cast<unsigned int*>(ws);
   ra.counters = reinterpret_cast<unsigned long long*>(counters);
-  return hip_check(launch_render(plan, tables_of(plan, w), w->params + plan->md.n_table, ra, st), "render launch");
+  return hip_check(launch_render(plan, tables_of(plan, w), w->params + plan->md.n_table, ra, st), "render launch", st);
 }
 
 // ---------------------------------------------------------------------------
@@ -697,7 +721,7 @@ int ngvol_multi_create(const ngvol_plan* const* plans, int32_t k, void* d_table,
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
     delete g;
-    return hip_check(e, "multi descriptor upload");
+    return hip_check(e, "multi descriptor upload", st);
   }
   *out = g;
   return NGVOL_OK;
@@ -715,7 +739,7 @@ int ngvol_multi_infer(const ngvol_multi* g, const ngvol_weights* w, const float*
   bool f16 = false;
   if (int rc = multi_args(g, w, xyz, n, out, g->chunk_tiles, a, f16)) return rc;
   if (a.item_prefix[g->k] == 0) return NGVOL_OK;
-  return hip_check(launch_multi_infer(&g->plan0, g->table, a, f16, g->blocks_per_cu, st), "multi_infer launch");
+  return hip_check(launch_multi_infer(&g->plan0, g->table, a, f16, g->blocks_per_cu, st), "multi_infer launch", st);
 }
 
 int ngvol_multi_autotune(ngvol_multi* g, const ngvol_weights* w, const float* const* xyz, const int64_t* n,
@@ -753,7 +777,7 @@ int ngvol_multi_autotune(ngvol_multi* g, const ngvol_weights* w, const float* co
     }
   if (e0) hipEventDestroy(e0);
   if (e1) hipEventDestroy(e1);
-  if (e != hipSuccess) return hip_check(e, "multi autotune");
+  if (e != hipSuccess) return hip_check(e, "multi autotune", st);
   g->blocks_per_cu = best_b;
   g->chunk_tiles = best_c;
   if (bpc_out) *bpc_out = best_b;
