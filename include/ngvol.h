@@ -299,6 +299,26 @@ int ngvol_mlp_bwd_workspace_bytes(const ngvol_plan* plan, int64_t n, size_t* byt
 int ngvol_mlp_bwd(const ngvol_plan* plan, const float* d_params, const float* d_feat, int64_t n, const float* d_dout,
                   float* d_dfeat, float* d_grad, void* d_workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* Allocation-free MLP backward, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same computation and outputs as ngvol_mlp_bwd
+ * (dW added into the MLP part of d_grad; dL/dfeat into d_dfeat if non-NULL),
+ * with no workspace argument.  Its per-workgroup dW partial sums live in a
+ * static device array of ngvol_mlp_bwd_noalloc_scratch_bytes() bytes (8 MiB)
+ * that the library holds on every GPU it runs on until the process ends; no
+ * call allocates or frees memory.  One partial-sum row (4 * n_mlp bytes) per
+ * workgroup: the call uses at most (8 MiB - 256) / (4 n_mlp) workgroups
+ * (each takes more tiles when that is fewer than ngvol_mlp_bwd would use),
+ * and returns NGVOL_EINVAL if not even one row fits.  Every row a call reads
+ * is written by that call first, so nothing carries over from the previous
+ * call; but all calls on one GPU share the array, so calls that overlap in
+ * time on one GPU (different streams or threads) race and must be ordered by
+ * the caller.  The address of the array is looked up on the first call on
+ * each device (the calling thread's current device). */
+size_t ngvol_mlp_bwd_noalloc_scratch_bytes(void);
+int ngvol_mlp_bwd_noalloc(const ngvol_plan* plan, const float* d_params, const float* d_feat, int64_t n,
+                          const float* d_dout, float* d_dfeat, float* d_grad, hipStream_t stream);
+
 /* Encoding backward: accumulates grad_table[slot][f] += w_corner *
  * dfeat[l*F+f] over all samples, levels and corners into d_grad (atomic,
  * so the summation order is unspecified). */

@@ -94,6 +94,8 @@ _SIGS = {
     "ngvol_infer_sorted": (C.c_int, [_P, C.POINTER(Weights), _P, C.c_int64, _P, _P]),
     "ngvol_mlp_bwd_workspace_bytes": (C.c_int, [_P, C.c_int64, C.POINTER(C.c_size_t)]),
     "ngvol_mlp_bwd": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P, _P, _P, C.c_size_t, _P]),
+    "ngvol_mlp_bwd_noalloc_scratch_bytes": (C.c_size_t, []),
+    "ngvol_mlp_bwd_noalloc": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P, _P, _P]),
     "ngvol_encode_bwd": (C.c_int, [_P, _P, C.c_int64, _P, _P, _P]),
     "ngvol_sample_batch": (C.c_int, [_P, C.POINTER(Batch), _P, _P, _P]),
     "ngvol_train_workspace_bytes": (C.c_int, [_P, C.c_int64, C.POINTER(C.c_size_t)]),
@@ -282,6 +284,16 @@ def mlp_bwd(plan, params, feat, dout, grad, want_dfeat=True):
     dfeat = torch.empty((n, plan.n_input), dtype=torch.float32, device=feat.device) if want_dfeat else None
     _check(lib().ngvol_mlp_bwd(plan.handle, _ptr(params), _ptr(feat), n, _ptr(dout), _ptr(dfeat), _ptr(grad),
                                _ptr(ws), nb.value, _stream()))
+    return dfeat
+
+
+def mlp_bwd_noalloc(plan, params, feat, dout, grad, dfeat=None):
+    """ngvol_mlp_bwd_noalloc: adds dL/dW into grad's MLP block and, if a
+    [n][n_input] FP32 dfeat tensor is given, writes dL/dfeat into it.  The
+    library call allocates nothing (its scratch is a static device array)."""
+    n = feat.shape[0]
+    _check(lib().ngvol_mlp_bwd_noalloc(plan.handle, _ptr(params), _ptr(feat), n, _ptr(dout), _ptr(dfeat),
+                                       _ptr(grad), _stream()))
     return dfeat
 
 

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <atomic>
+#include <mutex>
 #include <cmath>
 #include <cstdlib>
 
@@ -395,7 +396,76 @@ int ngvol_mlp_bwd(const ngvol_plan* plan, const float* params, const float* feat
                    "mlp_bwd launch", st);
 }
 
+}  // extern "C"
 
+// ---------------------------------------------------------------------------
+// Allocation-free MLP backward.  Its partial sums live in `scratch`, a
+// file-scope device array: every GPU the library runs on holds its own copy
+// at its own address until the process ends.  Host code never uses the
+// array's name as an address; the address is resolved once per device, with
+// that device current, on the entry point's first call there.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)8 << 20;
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+// Device address of the current device's scratch array (NULL + error on failure).
+int scratch_address(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(NGVOL_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(NGVOL_EUNSUPPORTED, "device %d beyond the %d supported", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(NGVOL_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return NGVOL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t ngvol_mlp_bwd_noalloc_scratch_bytes(void) { return kScratchBytes; }
+
+int ngvol_mlp_bwd_noalloc(const ngvol_plan* plan, const float* params, const float* feat, int64_t n, const float* dout,
+                          float* dfeat, float* grad, hipStream_t st) {
+  if (int rc = check_plan(plan)) return rc;
+  NGV_REQUIRE(n >= 0, "n must be >= 0");
+  if (n == 0) return NGVOL_OK;
+  NGV_REQUIRE(params && feat && dout && grad, "params, feat, dout and grad must be non-NULL");
+  NGV_REQUIRE(aligned16(params) && aligned4(feat) && aligned4(dout) && aligned4(grad) && aligned4(dfeat),
+              "params must be 16-byte aligned, other buffers 4-byte aligned");
+  if (int rc = check_bwd_lds(plan)) return rc;
+  // one partial-sum row of n_mlp floats per workgroup, then the 256-byte flag block
+  const size_t row = (size_t)plan->md.n_mlp * 4;
+  if (row + 256 > kScratchBytes)
+    return fail(NGVOL_EINVAL, "one partial-sum row of %zu bytes exceeds the %zu-byte scratch", row, kScratchBytes);
+  const int64_t rows = (int64_t)((kScratchBytes - 256) / row);
+  int grid = bwd_grid(plan, n);
+  if (grid > rows) grid = (int)rows;  // fewer workgroups, each taking more tiles
+  void* base = nullptr;
+  if (int rc = scratch_address(&base)) return rc;
+  float* partial = reinterpret_cast<float*>(base);
+  int32_t* flag = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(base) + kScratchBytes - 256);
+  return hip_check(launch_mlp_bwd_pass(plan, params, feat, n, dout, dfeat, grad, partial, grid, flag, st),
+                   "mlp_bwd_noalloc launch", st);
+}
 
 int ngvol_encode_bwd(const ngvol_plan* plan, const float* xyz, int64_t n, const float* dfeat, float* grad,
                      hipStream_t st) {
