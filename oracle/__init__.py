@@ -87,13 +87,15 @@ def _chk(rc):
 
 class Model:
     """Hash-grid + MLP description: levels L, features F, table 2**log2T,
-    vertices per axis N_l (``res``), MLP width and number of hidden layers."""
+    vertices per axis N_l (``res``), MLP width, number of hidden layers and
+    whether the output neuron is followed by a ReLU."""
 
-    def __init__(self, L, F, log2T, res, width, n_hidden):
+    def __init__(self, L, F, log2T, res, width, n_hidden, out_relu=False):
         self.L, self.F, self.log2T, self.width, self.n_hidden = L, F, log2T, width, n_hidden
+        self.out_relu = bool(out_relu)
         self.res = [int(r) for r in res]
         assert len(self.res) == L
-        self.desc = np.array([L, F, log2T, width, n_hidden] + self.res, dtype=np.int32)
+        self.desc = np.array([L, F, log2T, width, n_hidden, int(self.out_relu)] + self.res, dtype=np.int32)
         size = np.zeros(L, np.int64)
         off = np.zeros(L + 1, np.int64)
         counts = np.zeros(3, np.int64)

@@ -10,7 +10,8 @@
  *   - a multi-resolution hash-grid encoding (Section 3.1, Fig. 1B): per level,
  *     the 8 corners of the enclosing grid cell are looked up in that level's
  *     table and trilinearly interpolated, and level features are concatenated;
- *   - a bias-free ReLU MLP on the concatenated features (Section 3.1);
+ *   - a bias-free ReLU MLP on the concatenated features (Section 3.1), its
+ *     output neuron either linear or, as an option, followed by a ReLU;
  *   - the sampling step (Section 4): uniform random coordinates in [0,1)^3
  *     with a trilinearly interpolated ground-truth value;
  *   - one optimisation step: L2 or L1 loss, analytic gradient, Adam with an
@@ -67,7 +68,7 @@ double orc_rng_u01(uint64_t seed, uint32_t stream, uint64_t index)
 /* ------------------------------------------------------------------------ */
 /* Model description and parameter layout.                                  */
 /*                                                                          */
-/* desc = { L, F, log2T, width, n_hidden, N_0, ..., N_{L-1} }               */
+/* desc = { L, F, log2T, width, n_hidden, out_relu, N_0, ..., N_{L-1} }     */
 /* Level l is a grid of N_l vertices per axis spanning [0,1].  It is stored */
 /* densely when N_l^3 <= T and hashed into T entries otherwise, so its      */
 /* table has min(T, N_l^3) entries of F features (entry-major).  Tables     */
@@ -83,6 +84,7 @@ typedef struct {
     int64_t off[ORC_MAX_LEVELS + 1];
     int64_t n_table, n_mlp, n_params;
     int n_layers;         /* n_hidden + 1 matrices */
+    int out_relu;         /* 1: ReLU on the output neuron */
     int64_t w_off[16];    /* offset of each matrix, relative to the MLP block */
     int w_in[16], w_out[16];
 } orc_model;
@@ -95,14 +97,15 @@ static int orc_model_from_desc(const int32_t* desc, orc_model* m)
     m->log2T = desc[2];
     m->width = desc[3];
     m->n_hidden = desc[4];
-    if (m->L < 1 || m->L > ORC_MAX_LEVELS || m->F < 1 || m->log2T < 1 || m->log2T > 30 ||
+    m->out_relu = desc[5];
+    if ((m->out_relu != 0 && m->out_relu != 1) || m->L < 1 || m->L > ORC_MAX_LEVELS || m->F < 1 || m->log2T < 1 || m->log2T > 30 ||
         m->width < 1 || m->n_hidden < 1 || m->n_hidden > 14)
         return -1;
     m->T = (int64_t)1 << m->log2T;
     m->n_in = m->L * m->F;
     m->off[0] = 0;
     for (int l = 0; l < m->L; ++l) {
-        int64_t N = desc[5 + l];
+        int64_t N = desc[6 + l];
         if (N < 2) return -1;
         m->N[l] = (int32_t)N;
         int64_t cube = N * N * N;
@@ -262,11 +265,15 @@ int orc_encode_debug(const int32_t* desc, const float* xyz, int64_t n, uint32_t*
 }
 
 /* ------------------------------------------------------------------------ */
-/* MLP (Section 3.1): bias-free, ReLU on hidden layers, identity output.    */
+/* MLP (Section 3.1): bias-free, ReLU on hidden layers; the output neuron    */
+/* is linear, or followed by a ReLU (an option: Section 3.1 speaks of ReLU   */
+/* activations for the layers, and the appendix's network listing for       */
+/* time-varying data ends in one).                                          */
 /* ------------------------------------------------------------------------ */
 
-/* Forward for one sample; keeps pre-activations z[layer][width] if asked. */
-static double orc_mlp_one(const orc_model* m, const double* W, const double* e, double* z_keep)
+/* Forward for one sample; keeps pre-activations z[layer][width] if asked and
+ * the output neuron's input in *z_out if asked. */
+static double orc_mlp_one_z(const orc_model* m, const double* W, const double* e, double* z_keep, double* z_out)
 {
     double a[1024], b[1024];
     const double* in = e;
@@ -277,7 +284,10 @@ static double orc_mlp_one(const orc_model* m, const double* W, const double* e, 
         for (int o = 0; o < no; ++o) {
             double s = 0.0;
             for (int k = 0; k < n_in; ++k) s += Wl[(int64_t)o * n_in + k] * in[k];
-            if (li == m->n_layers - 1) return s;
+            if (li == m->n_layers - 1) {
+                if (z_out) *z_out = s;
+                return (m->out_relu && !(s > 0.0)) ? 0.0 : s;
+            }
             if (z_keep) z_keep[li * m->width + o] = s;
             b[o] = s > 0.0 ? s : 0.0;
         }
@@ -286,6 +296,11 @@ static double orc_mlp_one(const orc_model* m, const double* W, const double* e, 
         n_in = no;
     }
     return 0.0; /* not reached */
+}
+
+static double orc_mlp_one(const orc_model* m, const double* W, const double* e, double* z_keep)
+{
+    return orc_mlp_one_z(m, W, e, z_keep, NULL);
 }
 
 int orc_mlp_fwd(const int32_t* desc, const double* W, const double* feat, int64_t n, double* out)
@@ -412,9 +427,10 @@ int orc_loss_grad_kind(const int32_t* desc, const double* params, const float* x
 #pragma omp for schedule(static)
         for (int64_t i = 0; i < n; ++i) {
             orc_encode_one(&m, params, xyz + 3 * i, e);
-            double yhat = orc_mlp_one(&m, W, e, z);
+            double zo = 0.0;
+            double yhat = orc_mlp_one_z(&m, W, e, z, &zo);
             double r = yhat - y[i];
-            double g; /* dL/dyhat */
+            double g; /* dL/dz_out: dL/dyhat, times ReLU'(z_out) (0 at 0) with an output ReLU */
             if (kind == 1) {
                 loss_t[tid] += fabs(r);
                 g = (r > 0.0 ? 1.0 : (r < 0.0 ? -1.0 : 0.0)) / (double)n;
@@ -422,6 +438,7 @@ int orc_loss_grad_kind(const int32_t* desc, const double* params, const float* x
                 loss_t[tid] += r * r;
                 g = 2.0 * r / (double)n;
             }
+            if (m.out_relu && !(zo > 0.0)) g = 0.0;
             /* hidden activations h_j = relu(z_j) */
             for (int li = 0; li < m.n_hidden; ++li)
                 for (int o = 0; o < m.width; ++o) {
@@ -798,7 +815,7 @@ int orc_render_pixels_mc(const int32_t* desc, const double* params, const float*
 {
     orc_model m;
     (void)H;
-    if (orc_model_from_desc(&desc[0], &m) || m.width > 1024 || m.n_in > 1024) return -1;
+    if (orc_model_from_desc(desc, &m) || m.width > 1024 || m.n_in > 1024) return -1;
     const double* Wm = params + m.n_table;
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t q = 0; q < n_pix; ++q) {

@@ -655,3 +655,254 @@ def test_mc_skipping_invariants():
     left = (pix % W) < W // 2 - 2
     np.testing.assert_array_equal(half[0][left], plain[0][left])
     assert np.all(half[2] <= plain[2]) and np.any(half[2] < plain[2])
+
+
+# ------------------------------------------------------- output ReLU -----
+# Reading of Section 3.1 (ReLU activations for the MLP layers) and of the
+# appendix's time-varying network listing (output activation ReLU): the
+# output neuron may be followed by a ReLU, with ReLU'(0) = 0.
+
+def test_output_relu_forward_equals_blas_chain():
+    res = oracle.resolutions(16, 16, 0, 2048)
+    m = oracle.Model(16, 2, 19, res, 64, 2, out_relu=True)
+    m_lin = oracle.Model(16, 2, 19, res, 64, 2)
+    rng = np.random.default_rng(40)
+    W = rng.normal(size=m.n_mlp) * 0.2
+    feat = rng.normal(size=(400, 32))
+    W1 = W[:64 * 32].reshape(64, 32)
+    W2 = W[64 * 32: 64 * 32 + 64 * 64].reshape(64, 64)
+    W3 = W[64 * 32 + 64 * 64:].reshape(1, 64)
+    z = (np.maximum(np.maximum(feat @ W1.T, 0) @ W2.T, 0) @ W3.T)[:, 0]
+    assert (z < 0).sum() > 50 and (z > 0).sum() > 50  # both signs occur
+    np.testing.assert_allclose(oracle.mlp_fwd(m, W, feat), np.maximum(z, 0), rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(oracle.mlp_fwd(m_lin, W, feat), z, rtol=1e-13, atol=1e-13)
+
+
+def test_output_relu_gradient_central_differences():
+    m = oracle.Model(3, 2, 10, [5, 9, 17], 16, 2, out_relu=True)
+    params = rand_params(m, seed=43)
+    rng = np.random.default_rng(42)
+    xyz = rng.random((64, 3)).astype(np.float32)
+    y = rng.random(64) * 0.3
+    out = oracle.forward(m, params, xyz)
+    assert (out == 0).sum() > 5 and (out > 0).sum() > 5
+    loss, g = oracle.loss_grad(m, params, xyz, y)
+    assert loss == pytest.approx(float(np.mean((out - y) ** 2)), rel=1e-13)
+    h = 1e-4
+    checked = 0
+    cand = list(range(0, m.n_table, 13)) + list(range(m.n_table, m.n_params))
+    for i in cand:
+        ls = []
+        for k in (-2, -1, 0, 1, 2):
+            p = params.copy()
+            p[i] += k * h
+            ls.append(float(np.mean((oracle.forward(m, p, xyz) - y) ** 2)))
+        # piecewise quadratic: skip parameters where a ReLU (hidden or output)
+        # changes state within +-2h (the second differences disagree)
+        d2 = [ls[k + 1] - 2 * ls[k] + ls[k - 1] for k in (1, 2, 3)]
+        if max(d2) - min(d2) > 1e-9 * max(1e-12, abs(ls[2])) + 1e-15:
+            continue
+        fd = (ls[3] - ls[1]) / (2 * h)
+        assert fd == pytest.approx(g[i], rel=1e-6, abs=1e-11), i
+        checked += 1
+    assert checked > 0.7 * len(cand)
+
+
+def test_output_relu_gradient_matches_torch_autograd():
+    torch = pytest.importorskip("torch")
+    m = oracle.Model(3, 2, 10, [5, 9, 17], 16, 3, out_relu=True)
+    params = rand_params(m, seed=43)
+    rng = np.random.default_rng(44)
+    xyz = rng.random((128, 3)).astype(np.float32)
+    y = rng.random(128) * 0.3
+    for loss_kind in ("l2", "l1"):
+        _, g = oracle.loss_grad(m, params, xyz, y, loss=loss_kind)
+        e = torch.tensor(oracle.encode(m, params, xyz), dtype=torch.float64)
+        Ws = []
+        pos = m.n_table
+        for (o, i) in synth.mlp_shapes(m.n_in, m.width, m.n_hidden):
+            Ws.append(torch.tensor(params[pos:pos + o * i].reshape(o, i), dtype=torch.float64, requires_grad=True))
+            pos += o * i
+        hh = e
+        for W in Ws[:-1]:
+            hh = torch.relu(torch.nn.functional.linear(hh, W))
+        out = torch.relu(torch.nn.functional.linear(hh, Ws[-1])[:, 0])
+        r = out - torch.tensor(y)
+        loss = torch.mean(r ** 2) if loss_kind == "l2" else torch.mean(torch.abs(r))
+        loss.backward()
+        gm = np.concatenate([W.grad.numpy().ravel() for W in Ws])
+        np.testing.assert_allclose(g[m.n_table:], gm, rtol=1e-12, atol=1e-15)
+
+
+def test_output_relu_negative_outputs_give_zero_gradient():
+    # every output's input negative: Phi = 0, loss = mean(y^2), and no
+    # parameter receives any gradient
+    m = oracle.Model(2, 2, 10, [5, 9], 8, 1, out_relu=True)
+    params = np.zeros(m.n_params)
+    params[:m.n_table] = 0.5                     # features 0.5 everywhere
+    params[m.n_table:m.n_table + 8 * 4] = 1.0    # hidden = relu(sum) = 2
+    params[m.n_table + 8 * 4:] = -1.0            # output input = -16
+    xyz = np.random.default_rng(45).random((32, 3)).astype(np.float32)
+    y = np.linspace(0.1, 0.9, 32)
+    assert np.all(oracle.forward(m, params, xyz) == 0.0)
+    loss, g = oracle.loss_grad(m, params, xyz, y)
+    assert loss == pytest.approx(float(np.mean(y ** 2)), rel=1e-14)
+    assert np.all(g == 0.0)
+
+
+# ---------------------------------------------- renderer: shading -----
+
+def _const_phi_model(c):
+    # Phi = c everywhere: every table entry 1 (so every level feature is 1 by
+    # the partition of unity), one hidden neuron with weight 1, output weight c
+    m = oracle.Model(1, 1, 10, [5], 1, 1)
+    params = np.zeros(m.n_params)
+    params[:m.n_table] = 1.0
+    params[m.n_table:] = [1.0, c]
+    return m, params
+
+
+def _ramp_lut():
+    # distinct RGBA at every node, alpha increasing: a wrong node, a swapped
+    # blend weight or an uncapped index all change the result
+    i = np.arange(256, dtype=np.float64)
+    return np.stack([i / 255, 1 - i / 255, 0.25 + 0.5 * (i % 7) / 6, 0.001 + 0.0002 * i], 1).astype(np.float32)
+
+
+@pytest.mark.parametrize("c", [0.25, 0.6013, 0.999, 1.0, 1.7, -0.3])
+def test_render_transfer_function_blend_closed_form(c):
+    m, params = _const_phi_model(c)
+    lut = _ramp_lut().astype(np.float64)
+    cam = np.array([0.3, 0.6, -1.0, 0, 0, 0, 0, 0, 0, 0, 0, 1], np.float32)  # +z through the cube: 1024 samples
+    rgba, ng, nu = oracle.render_pixels(m, params, cam, _ramp_lut(), 2, 2, 2.0 ** -10, 11, np.arange(4))
+    v = min(max(c, 0.0), 1.0)
+    u = 255.0 * v
+    i0 = min(math.floor(u), 254)
+    f = u - i0
+    rgba_tf = (1 - f) * lut[i0] + f * lut[i0 + 1]   # linear interpolation between table nodes
+    a = rgba_tf[3]
+    n_stop = math.ceil(math.log(0.01) / math.log(1 - a))
+    n = min(n_stop, 1024)
+    assert np.all(ng == 1024) and np.all(nu == n)
+    A = 1 - (1 - a) ** n          # identical samples: A_n = 1 - (1 - a)^n
+    # Phi is c up to FP64 rounding of the partition of unity (1e-16), hence the atol
+    np.testing.assert_allclose(rgba[:, 3], A, rtol=1e-11, atol=1e-13)
+    np.testing.assert_allclose(rgba[:, :3], np.broadcast_to(rgba_tf[:3] * A, (4, 3)), rtol=1e-11, atol=1e-13)
+
+
+# --------------------------------------------- renderer: ray geometry -----
+
+def _cam_axis(o, d):
+    # every pixel's ray: origin o, direction d (du = dv = 0)
+    return np.array(list(o) + [0, 0, 0, 0, 0, 0] + list(d), np.float32)
+
+
+def test_ray_counts_negative_directions():
+    dt = 2.0 ** -10
+    for o, d in [((0.3, 0.6, 2.0), (0, 0, -1)), ((1.5, 0.25, 0.75), (-1, 0, 0)), ((0.5, 3.0, 0.5), (0, -1, 0))]:
+        n = oracle.ray_counts(_cam_axis(o, d), 8, 8, 3, dt)
+        assert np.all(n == 1024), (o, d)
+    # the same rays pointing away from the cube miss it
+    for o, d in [((0.3, 0.6, 2.0), (0, 0, 1)), ((1.5, 0.25, 0.75), (1, 0, 0))]:
+        assert np.all(oracle.ray_counts(_cam_axis(o, d), 4, 4, 3, dt) == 0)
+
+
+@pytest.mark.parametrize("sign", [1, -1])
+def test_ray_counts_and_points_on_the_diagonal(sign):
+    # the main diagonal, entered at one corner: chord sqrt(3), so
+    # n = ceil(sqrt(3) * 1024 - j); samples lie on the diagonal at t_k
+    dt = 2.0 ** -10
+    o = (-0.5, -0.5, -0.5) if sign > 0 else (1.5, 1.5, 1.5)
+    cam = _cam_axis(o, (sign, sign, sign))
+    W = H = 16
+    n = oracle.ray_counts(cam, W, H, 7, dt).ravel()
+    q = math.sqrt(3.0) * 1024
+    checked = 0
+    for p in range(W * H):
+        j = oracle.rng_u01(7, 5, p)
+        want = math.ceil(q - j)
+        if abs((q - j) - round(q - j)) < 1e-3:
+            continue  # binary32 span rounding may decide these
+        assert n[p] == want, p
+        checked += 1
+        if p % 37 == 0:
+            pts = oracle.ray_points(cam, W, H, 7, dt, p, 0, 3).astype(np.float64)
+            start = 0.0 if sign > 0 else 1.0
+            for k in range(3):
+                t_in = (k + j) * dt / math.sqrt(3.0)   # distance along each axis from the entry corner
+                np.testing.assert_allclose(pts[k], start + sign * t_in, atol=2e-7)
+    assert checked > 200
+
+
+def test_ray_counts_oblique_against_exact_intersection():
+    # pinhole camera looking at the cube from an oblique position; counts
+    # against the exact FP64 slab intersection (pixels within 1e-3 of a
+    # ceiling boundary are skipped)
+    dt = 2.0 ** -10
+    o = np.array([1.7, -0.4, -1.1])
+    look = np.array([0.5, 0.5, 0.5]) - o
+    fwd = look / np.linalg.norm(look)
+    right = np.cross(fwd, [0.0, 1.0, 0.0])
+    right /= np.linalg.norm(right)
+    up = np.cross(right, fwd)
+    W = H = 24
+    s = math.tan(math.radians(20)) * 2 / H
+    du, dv = right * s, -up * s
+    d00 = fwd - du * W / 2 - dv * H / 2
+    cam = np.concatenate([o, du, dv, d00]).astype(np.float32)
+    n = oracle.ray_counts(cam, W, H, 9, dt).ravel()
+    c32 = cam.astype(np.float64)
+    checked = hits = 0
+    for p in range(W * H):
+        px, py = p % W, p // W
+        d = c32[9:12] + (px + 0.5) * c32[3:6] + (py + 0.5) * c32[6:9]
+        d /= np.linalg.norm(d)
+        with np.errstate(divide="ignore"):
+            inv = 1.0 / d
+        t1, t2 = (0 - c32[:3]) * inv, (1 - c32[:3]) * inv
+        tn, tf = max(np.max(np.minimum(t1, t2)), 0.0), np.min(np.maximum(t1, t2))
+        j = oracle.rng_u01(9, 5, p)
+        want = max(0, math.ceil((tf - tn) / dt - j)) if tn < tf else 0
+        x = (tf - tn) / dt - j
+        if tn < tf and abs(x - round(x)) < 1e-2:
+            continue
+        assert n[p] == want, p
+        checked += 1
+        hits += want > 0
+    assert checked > 500 and hits > 100
+
+
+# ------------------------------------------------ training loop wiring -----
+
+def test_train_loop_equals_composed_steps():
+    # oracle.train = for each step k: batch k (stream 3), trilinear targets,
+    # loss gradient, Adam at t = k + 1 with the step-k learning rate.  Compose
+    # the same from the individually pinned pieces, starting at step 3 with a
+    # decay that changes the rate every step (a wrong step, rate or t index
+    # changes the result).
+    m = small_model(L=3, F=2, log2T=10, res=(5, 9, 17), width=16, n_hidden=2)
+    params = rand_params(m, seed=46, table_scale=0.1)
+    vol = synth.gaussian_blobs(12, 47)
+    decay = (4, 1, 0.5)
+    am, av = np.zeros(m.n_params), np.zeros(m.n_params)
+    rng = np.random.default_rng(48)
+    am[:] = rng.normal(size=m.n_params) * 1e-3   # state as after earlier steps
+    av[:] = rng.random(m.n_params) * 1e-5
+    got, (gm, gv), losses = oracle.train(m, params, vol, 5, 3, 200, 1e-2, 0.9, 0.99, 1e-15, step0=3,
+                                         state=(am, av), loss="l1", l2_reg=1e-3, decay=decay)
+    theta, mm, vv = params.copy(), am.copy(), av.copy()
+    for s in range(3):
+        k = 3 + s
+        xyz = oracle.batch_coords(5, k, 200)
+        y = oracle.sample_volume(vol, xyz)
+        loss, g = oracle.loss_grad(m, theta, xyz, y, loss="l1")
+        assert losses[s] == pytest.approx(loss, rel=1e-15)
+        oracle.adam(theta, mm, vv, g, k + 1, oracle.lr_at(1e-2, k, decay), 0.9, 0.99, 1e-15, l2_reg=1e-3,
+                    reg_from=m.n_table)
+    np.testing.assert_array_equal(got, theta)
+    np.testing.assert_array_equal(gm, mm)
+    np.testing.assert_array_equal(gv, vv)
+    # the rate of steps 3, 4, 5 is lr, lr/2, lr/4: the run is not the constant-rate one
+    flat, _, _ = oracle.train(m, params, vol, 5, 3, 200, 1e-2, 0.9, 0.99, 1e-15, step0=3, state=(am, av),
+                              loss="l1", l2_reg=1e-3)
+    assert np.max(np.abs(flat - got)) > 1e-4
