@@ -75,6 +75,12 @@ extern "C" {
 #define NGVOL_LOSS_L2 0 /* L = (1/B) sum (Phi(x)-y)^2 */
 #define NGVOL_LOSS_L1 1 /* L = (1/B) sum |Phi(x)-y|; dL/dPhi = sign(Phi(x)-y)/B, sign(0) = 0 */
 
+/* Activation of the output neuron.  Section 3.1 describes ReLU activations
+ * for the MLP layers; the network listing of the appendix for time-varying
+ * data ends in a ReLU.  The hidden layers always use ReLU. */
+#define NGVOL_ACT_NONE 0 /* identity output */
+#define NGVOL_ACT_RELU 1 /* Phi = max(0, w_out . h); its derivative at 0 is taken as 0 */
+
 #define NGVOL_DT_F32 0
 #define NGVOL_DT_F16 1
 #define NGVOL_DT_BF16 2
@@ -110,6 +116,7 @@ typedef struct ngvol_config {
     int32_t n_hidden_layers;
     int32_t precision; /* NGVOL_FP32 | NGVOL_BF16 | NGVOL_FP16 */
     int32_t loss;      /* NGVOL_LOSS_L2 (0) | NGVOL_LOSS_L1; used by ngvol_train_step */
+    int32_t output_activation; /* NGVOL_ACT_NONE (0) | NGVOL_ACT_RELU */
 } ngvol_config;
 
 /* Derived layout of a plan (host struct filled by ngvol_get_layout). */
@@ -146,6 +153,7 @@ typedef struct ngvol_train_state {
     double* loss;        /* [1] mean loss of the last step (unscaled) */
     void* workspace;     /* ngvol_train_workspace_bytes(plan, B) bytes */
     size_t workspace_bytes;
+    int64_t* draws;      /* [1] or NULL: number of steps taken, applied or skipped (every step adds 1) */
 } ngvol_train_state;
 
 /* Macro-cells (Section 5.3): a grid of disjoint cells of `cell` voxels per
@@ -181,8 +189,10 @@ typedef struct ngvol_batch {
     int32_t dims[3];     /* Dx, Dy, Dz, each >= 2 */
     int32_t volume_dtype; /* NGVOL_DT_F32 | NGVOL_DT_F16 */
     uint64_t seed;       /* < 2^56 */
-    int64_t step_index;  /* >= 0; or -1 (ngvol_train_step only): use the state's device step counter, so a
-                          * captured graph draws a new batch on every replay (a skipped step repeats it) */
+    int64_t step_index;  /* >= 0; or -1 (ngvol_train_step only): the batch index is read on the device from
+                          * the state's draw counter (or, if the state has none, its step counter), so a
+                          * captured graph draws a new batch on every replay (with the step counter, a
+                          * skipped step would draw the same batch again) */
     const ngvol_macrocells* macrocells; /* optional (ngvol_train_step): the batch's (coordinate, target)
                                          * samples extend the cells' value ranges (NaN targets are ignored) */
 } ngvol_batch;
@@ -330,7 +340,12 @@ int ngvol_encode_bwd(const ngvol_plan* plan, const float* d_xyz, int64_t n, cons
 int ngvol_sample_batch(const ngvol_plan* plan, const ngvol_batch* batch, float* d_xyz, float* d_target,
                        hipStream_t stream);
 
-/* Workspace a training step of batch B needs. */
+/* Workspace a training step of batch B needs.  A step scatters B * 8 * L
+ * table-gradient records with 32-bit positions: B * 8 * L >= 2^32 is
+ * NGVOL_EINVAL; tables of more than 40960 gradient buckets (2^12 entries per
+ * bucket for F = 2, 2^11 for F = 4, 2^10 for F = 8), whose histogram would
+ * not fit in LDS, are NGVOL_EUNSUPPORTED.  ngvol_train_step checks the same
+ * before launching anything. */
 int ngvol_train_workspace_bytes(const ngvol_plan* plan, int64_t batch_size, size_t* bytes);
 
 /* One training step (Section 4): sampling, forward, the plan's loss
@@ -354,6 +369,14 @@ int ngvol_make_f16_tables(const ngvol_plan* plan, const float* d_params, uint16_
  * for values normalised to [0,1] (Section 6). */
 int ngvol_sq_error_grid(const ngvol_plan* plan, const ngvol_weights* w, const void* d_volume, const int32_t dims[3],
                         int32_t volume_dtype, double* d_sum_sq, hipStream_t stream);
+
+/* Decoding quality (Section 6): the network evaluated at every voxel centre
+ * (i+1/2)/D of the volume, *d_mse (device double) = mean of (Phi - v)^2 over
+ * all voxels, accumulated in FP64 on the device, and, if d_psnr is non-NULL,
+ * *d_psnr (device double) = -10 log10(MSE), the PSNR of values normalised to
+ * [0,1] (peak 1).  Both outputs are overwritten; nothing is synchronised. */
+int ngvol_psnr(const ngvol_plan* plan, const ngvol_weights* w, const void* d_volume, const int32_t dims[3],
+               int32_t volume_dtype, double* d_mse, double* d_psnr, hipStream_t stream);
 
 /* Macro-cells (Section 5.3).  reset: every cell empty.  update: extend the
  * ranges with n explicit samples (xyz[n][3], values[n], device).  opacity:

@@ -35,7 +35,7 @@ class Config(C.Structure):
     _fields_ = [("n_levels", C.c_int32), ("n_features", C.c_int32), ("log2_hashmap_size", C.c_int32),
                 ("base_resolution", C.c_int32), ("per_level_scale", C.c_double), ("max_resolution", C.c_int32),
                 ("resolutions", C.POINTER(C.c_int32)), ("n_neurons", C.c_int32), ("n_hidden_layers", C.c_int32),
-                ("precision", C.c_int32), ("loss", C.c_int32)]
+                ("precision", C.c_int32), ("loss", C.c_int32), ("output_activation", C.c_int32)]
 
 
 class Layout(C.Structure):
@@ -54,7 +54,7 @@ class Weights(C.Structure):
 class TrainStateC(C.Structure):
     _fields_ = [("params", C.c_void_p), ("table_f16", C.c_void_p), ("grad", C.c_void_p), ("adam_m", C.c_void_p),
                 ("adam_v", C.c_void_p), ("step", C.c_void_p), ("skipped", C.c_void_p), ("loss", C.c_void_p),
-                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t)]
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t), ("draws", C.c_void_p)]
 
 
 class MacroCellsC(C.Structure):
@@ -103,6 +103,7 @@ _SIGS = {
     "ngvol_adam_step": (C.c_int, [_P, C.POINTER(TrainStateC), C.POINTER(Adam), C.c_float, _P]),
     "ngvol_make_f16_tables": (C.c_int, [_P, _P, _P, _P]),
     "ngvol_sq_error_grid": (C.c_int, [_P, C.POINTER(Weights), _P, C.POINTER(C.c_int32), C.c_int32, _P, _P]),
+    "ngvol_psnr": (C.c_int, [_P, C.POINTER(Weights), _P, C.POINTER(C.c_int32), C.c_int32, _P, _P, _P]),
     "ngvol_render_workspace_bytes": (C.c_size_t, []),
     "ngvol_render": (C.c_int, [_P, C.POINTER(Weights), C.POINTER(Camera), _P, C.c_int32, C.c_int32, C.c_float,
                                C.c_uint32, _P, _P, _P, _P, _P, _P, C.c_size_t, _P]),
@@ -168,7 +169,8 @@ class Plan:
     """Resolved model: hash grid (L levels, F features, 2^log2T entries) + MLP."""
 
     def __init__(self, n_levels, n_features, log2_hashmap_size, base_resolution=16, per_level_scale=2.0,
-                 max_resolution=0, resolutions=None, n_neurons=64, n_hidden_layers=2, precision="fp32", loss="l2"):
+                 max_resolution=0, resolutions=None, n_neurons=64, n_hidden_layers=2, precision="fp32", loss="l2",
+                 output_activation="none"):
         prec = {"fp32": FP32, "bf16": BF16, "fp16": FP16, FP32: FP32, BF16: BF16, FP16: FP16}[precision]
         self.loss = loss
         loss_kind = {"l2": LOSS_L2, "l1": LOSS_L1}[loss]
@@ -177,7 +179,8 @@ class Plan:
             self._res = (C.c_int32 * len(resolutions))(*[int(r) for r in resolutions])
         cfg = Config(n_levels, n_features, log2_hashmap_size, base_resolution, float(per_level_scale),
                      int(max_resolution), C.cast(self._res, C.POINTER(C.c_int32)) if self._res else None,
-                     n_neurons, n_hidden_layers, prec, loss_kind)
+                     n_neurons, n_hidden_layers, prec, loss_kind, {"none": 0, "relu": 1}[output_activation])
+        self.output_activation = output_activation
         h = C.c_void_p()
         _check(lib().ngvol_plan_create(C.byref(cfg), C.byref(h)))
         self.handle = h
@@ -378,6 +381,7 @@ class TrainState:
         self.m = torch.zeros_like(self.params)
         self.v = torch.zeros_like(self.params)
         self.step = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.draws = torch.zeros(1, dtype=torch.int64, device=dev)
         self.skipped = torch.zeros(1, dtype=torch.int32, device=dev)
         self.loss = torch.zeros(1, dtype=torch.float64, device=dev)
         nb = C.c_size_t()
@@ -385,7 +389,8 @@ class TrainState:
         self.workspace = torch.empty(nb.value, dtype=torch.uint8, device=dev)
         self.batch_size = batch_size
         self._c = TrainStateC(_ptr(self.params), _ptr(self.table_f16), _ptr(self.grad), _ptr(self.m), _ptr(self.v),
-                              _ptr(self.step), _ptr(self.skipped), _ptr(self.loss), _ptr(self.workspace), nb.value)
+                              _ptr(self.step), _ptr(self.skipped), _ptr(self.loss), _ptr(self.workspace), nb.value,
+                              _ptr(self.draws))
 
     def weights(self):
         return self.params, self.table_f16
@@ -399,7 +404,8 @@ def _adam(lr, betas, eps, l2_reg, decay):
 def train_step(state, volume=None, seed=0, step_index=0, xyz=None, target=None, lr=1e-2, betas=(0.9, 0.99),
                eps=1e-15, loss_scale=1.0, l2_reg=0.0, decay=None, macrocells=None):
     """One training step.  step_index=-1 draws the batch indexed by the state's
-    device step counter (the form to capture in a graph).  decay =
+    device draw counter (steps taken, applied or skipped: the form to capture
+    in a graph).  decay =
     (start, interval, base) gives the exponentially decaying learning rate;
     l2_reg regularises the MLP weights; macrocells (a MacroCells) takes the
     batch's samples into its value ranges."""
@@ -433,11 +439,19 @@ def sq_error_grid(plan, params, volume, table_f16=None, out=None):
     return out
 
 
-def psnr(plan, params, volume, table_f16=None):
-    import math
-    s = sq_error_grid(plan, params, volume, table_f16)
-    mse = float(s.item()) / volume.numel()
-    return -10.0 * math.log10(mse)
+def psnr(plan, params, volume, table_f16=None, out=None):
+    """ngvol_psnr: (MSE, PSNR) over all voxel centres, reduced in FP64 on the
+    device; out (two float64 device values) receives them."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty(2, dtype=torch.float64, device=volume.device)
+    dt = {torch.float32: DT_F32, torch.float16: DT_F16}[volume.dtype]
+    Dz, Dy, Dx = volume.shape
+    dims = (C.c_int32 * 3)(Dx, Dy, Dz)
+    w = _weights(params, table_f16)
+    _check(lib().ngvol_psnr(plan.handle, C.byref(w), _ptr(volume), dims, dt, _ptr(out), _ptr(out[1:]), _stream()))
+    mse, p = out.tolist()
+    return p
 
 
 def render(plan, params, cam, lut, width, height, dt, frame_seed, table_f16=None, want_counts=True,

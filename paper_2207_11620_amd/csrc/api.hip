@@ -168,6 +168,8 @@ int ngvol_plan_create(const ngvol_config* c, ngvol_plan** out) {
   NGV_REQUIRE(c->precision == NGVOL_FP32 || c->precision == NGVOL_BF16 || c->precision == NGVOL_FP16,
               "precision must be NGVOL_FP32, NGVOL_BF16 or NGVOL_FP16");
   NGV_REQUIRE(c->loss == NGVOL_LOSS_L2 || c->loss == NGVOL_LOSS_L1, "loss must be NGVOL_LOSS_L2 or NGVOL_LOSS_L1");
+  NGV_REQUIRE(c->output_activation == NGVOL_ACT_NONE || c->output_activation == NGVOL_ACT_RELU,
+              "output_activation must be NGVOL_ACT_NONE or NGVOL_ACT_RELU");
   if (c->n_features != 2 && c->n_features != 4 && c->n_features != 8)
     return fail(NGVOL_EUNSUPPORTED, "n_features %d unsupported (2, 4 or 8)", c->n_features);
   if (c->n_neurons != 32 && c->n_neurons != 64)
@@ -194,6 +196,7 @@ int ngvol_plan_create(const ngvol_config* c, ngvol_plan** out) {
   L.n_hidden_layers = md.n_hidden = c->n_hidden_layers;
   L.precision = c->precision;
   md.n_layers = md.n_hidden + 1;
+  md.out_relu = c->output_activation == NGVOL_ACT_RELU;
   int64_t off = 0;
   for (int l = 0; l < md.L; ++l) {
     const int64_t N = res[l];
@@ -559,9 +562,25 @@ int ngvol_sample_batch(const ngvol_plan* plan, const ngvol_batch* b, float* xyz,
   return hip_check(launch_sample_batch(ba, xyz, y, st), "sample_batch launch", st);
 }
 
+// Limits of the bucketed table-gradient scatter: record positions and bucket
+// offsets are 32-bit (B * 8 * L < 2^32 records), and one workgroup counts
+// every bucket of the tables in an LDS histogram (4 bytes per 2^bshift
+// entries).
+static int check_train_limits(const ngvol_plan* plan, int64_t B) {
+  const ScatterPlan sp = scatter_plan(plan, B);
+  if (sp.n_records >= ((int64_t)1 << 32))
+    return fail(NGVOL_EINVAL, "batch of %lld samples gives %lld table-gradient records (B*8*L must be < 2^32)",
+                (long long)B, (long long)sp.n_records);
+  if ((size_t)sp.n_buckets * 4 > kLdsBytes)
+    return fail(NGVOL_EUNSUPPORTED, "tables of %lld entries need a %zu-byte gradient bucket histogram (> %zu of LDS)",
+                (long long)(plan->md.n_table / plan->md.F), (size_t)sp.n_buckets * 4, kLdsBytes);
+  return NGVOL_OK;
+}
+
 int ngvol_train_workspace_bytes(const ngvol_plan* plan, int64_t B, size_t* bytes) {
   if (int rc = check_plan(plan)) return rc;
-  NGV_REQUIRE(bytes && B > 0, "bytes must be non-NULL and B > 0");
+  NGV_REQUIRE(bytes && B > 0 && B < ((int64_t)1 << 31), "bytes must be non-NULL and 0 < B < 2^31");
+  if (int rc = check_train_limits(plan, B)) return rc;
   *bytes = train_workspace(plan, B).total;
   return NGVOL_OK;
 }
@@ -572,8 +591,8 @@ static int check_state(const ngvol_plan* plan, const ngvol_train_state* s) {
   NGV_REQUIRE(s->params && s->grad && s->adam_m && s->adam_v && s->step && s->workspace,
               "state needs params, grad, adam_m, adam_v, step and workspace");
   NGV_REQUIRE(aligned16(s->params) && aligned16(s->grad) && aligned16(s->adam_m) && aligned16(s->adam_v) &&
-                  aligned16(s->table_f16) && aligned16(s->workspace),
-              "state buffers must be 16-byte aligned");
+                  aligned16(s->table_f16) && aligned16(s->workspace) && ((uintptr_t)s->draws & 7u) == 0,
+              "state buffers must be 16-byte aligned (draws 8-byte aligned)");
   return NGVOL_OK;
 }
 
@@ -611,7 +630,8 @@ int ngvol_train_step(const ngvol_plan* plan, const ngvol_train_state* s, const n
   if (int rc = check_bwd_lds(plan)) return rc;
   BatchArgs ba{};
   if (int rc = resolve_batch(plan, b, ba)) return rc;
-  if (!b->xyz && b->step_index < 0) ba.step_ptr = s->step;  // graph-replayable: batch index = applied steps
+  if (!b->xyz && b->step_index < 0) ba.step_ptr = s->draws ? s->draws : s->step;  // graph-replayable batch index
+  if (int rc = check_train_limits(plan, ba.B)) return rc;
   const TrainWorkspace ws = train_workspace(plan, ba.B);
   if (s->workspace_bytes < ws.total)
     return fail(NGVOL_ENOMEM, "workspace of %zu bytes < %zu needed", s->workspace_bytes, ws.total);
@@ -641,12 +661,13 @@ int ngvol_train_step(const ngvol_plan* plan, const ngvol_train_state* s, const n
   if (e == hipSuccess)
     e = launch_bwd(plan, 0, mlp, e_buf, g_buf, ba, s->grad, de, partial, ws.bwd_grid, flag, bscale, st);
   if (e == hipSuccess) e = launch_reduce_partials(plan, partial, ws.bwd_grid, s->grad, flag, st);
-  if (e == hipSuccess) e = launch_scatter(plan, ws.sc, ba, de, s->grad, base + ws.scatter_off, st);
+  if (e == hipSuccess) e = launch_scatter(plan, ws.sc, ba, de, s->grad, base + ws.scatter_off, flag, st);
   const AdamArgs aa = adam_args(a, loss_scale);
   if (e == hipSuccess)
     e = launch_adam(plan, s->params, reinterpret_cast<__half*>(s->table_f16), s->grad, s->adam_m, s->adam_v, s->step,
                     flag, aa, st);
-  if (e == hipSuccess) e = launch_step_end(loss_acc, flag, s->step, s->skipped, s->loss, 1.0 / (double)ba.B, st);
+  if (e == hipSuccess)
+    e = launch_step_end(loss_acc, flag, s->step, s->draws, s->skipped, s->loss, 1.0 / (double)ba.B, st);
   return hip_check(e, "train_step launch", st);
 }
 
@@ -664,7 +685,7 @@ int ngvol_adam_step(const ngvol_plan* plan, const ngvol_train_state* s, const ng
   if (e == hipSuccess)
     e = launch_adam(plan, s->params, reinterpret_cast<__half*>(s->table_f16), s->grad, s->adam_m, s->adam_v, s->step,
                     flag, aa, st);
-  if (e == hipSuccess) e = launch_step_end(loss_acc, flag, s->step, s->skipped, nullptr, 1.0, st);
+  if (e == hipSuccess) e = launch_step_end(loss_acc, flag, s->step, s->draws, s->skipped, nullptr, 1.0, st);
   return hip_check(e, "adam launch", st);
 }
 
@@ -683,6 +704,22 @@ int ngvol_sq_error_grid(const ngvol_plan* plan, const ngvol_weights* w, const vo
   NGV_REQUIRE(dtype == NGVOL_DT_F32 || dtype == NGVOL_DT_F16, "volume dtype must be F32 or F16");
   return hip_check(launch_sq_error_grid(plan, tables_of(plan, w), w->params + plan->md.n_table, vol, dtype, dims, sq, st),
                    "sq_error_grid launch", st);
+}
+
+int ngvol_psnr(const ngvol_plan* plan, const ngvol_weights* w, const void* vol, const int32_t dims[3], int32_t dtype,
+               double* mse, double* psnr, hipStream_t st) {
+  if (int rc = check_plan(plan)) return rc;
+  if (int rc = check_weights(w)) return rc;
+  NGV_REQUIRE(vol && mse && dims && aligned16(vol) && ((uintptr_t)mse & 7u) == 0 && ((uintptr_t)psnr & 7u) == 0,
+              "volume, dims and d_mse must be non-NULL; the volume 16-byte, the outputs 8-byte aligned");
+  NGV_REQUIRE(dims[0] >= 1 && dims[1] >= 1 && dims[2] >= 1, "dims must be positive");
+  NGV_REQUIRE(dtype == NGVOL_DT_F32 || dtype == NGVOL_DT_F16, "volume dtype must be F32 or F16");
+  const double n = (double)dims[0] * (double)dims[1] * (double)dims[2];
+  hipError_t e = launch_zero_f64(mse, st);
+  if (e == hipSuccess)
+    e = launch_sq_error_grid(plan, tables_of(plan, w), w->params + plan->md.n_table, vol, dtype, dims, mse, st);
+  if (e == hipSuccess) e = launch_psnr_finish(mse, 1.0 / n, psnr, st);
+  return hip_check(e, "psnr launch", st);
 }
 
 size_t ngvol_render_workspace_bytes(void) { return 256; }

@@ -69,7 +69,7 @@ struct BatchArgs {
   int32_t vdtype;
   uint64_t seed;
   int64_t step;
-  const int64_t* step_ptr;  // if set, the batch index is read from here (the state's step counter)
+  const int64_t* step_ptr;  // if set, the batch index is read from here (the state's draw or step counter)
   McGeom mc;                // mc.range set: the samples extend the macro-cell ranges
   __device__ __forceinline__ int64_t step_index() const { return step_ptr ? *step_ptr : step; }
 };
@@ -104,8 +104,9 @@ struct ScatterPlan {
   size_t rec_off, counts_off, totals_off, offsets_off, items_off, bytes;
 };
 ScatterPlan scatter_plan(const ngvol_plan* plan, int64_t B);
+// A non-finite gradient sum sets *nonfinite (the step is then skipped).
 hipError_t launch_scatter(const ngvol_plan* plan, const ScatterPlan& sp, const struct BatchArgs& ba,
-                          const float* dfeat, float* grad, void* ws, hipStream_t st);
+                          const float* dfeat, float* grad, void* ws, int32_t* nonfinite, hipStream_t st);
 
 // Workspace carve-up of a training step (byte offsets).
 struct TrainWorkspace {
@@ -158,6 +159,10 @@ template <int P, int W>
 hipError_t launch_infer_split_p(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const float4* rec, int64_t n,
                                 float* out, void* planes, uint32_t* idx, hipStream_t st);
 
+// LDS of the staged forward weights: the fragments of W_0..W_{h-1}
+// (mlp_weight_bytes), then W_out and its output-layer fragments (wout_bytes).
+size_t mlp_weight_bytes(const ngvol_plan* plan);
+size_t wout_bytes(const ngvol_plan* plan);
 size_t fwd_lds_bytes(const ngvol_plan* plan);
 // Persistent grid: enough workgroups of waves_per_block waves for n_tiles
 // wave work units, at most blocks_per_cu per compute unit.
@@ -242,8 +247,12 @@ struct AdamArgs {
 hipError_t launch_adam(const ngvol_plan* plan, float* params, __half* table_f16, float* grad, float* m, float* v,
                        int64_t* step, const int32_t* nonfinite, const AdamArgs& a, hipStream_t st);
 hipError_t launch_step_begin(double* loss_acc, int32_t* nonfinite, hipStream_t st);
-hipError_t launch_step_end(const double* loss_acc, int32_t* nonfinite, int64_t* step, int32_t* skipped,
-                           double* loss_out, double inv_b, hipStream_t st);
+hipError_t launch_step_end(const double* loss_acc, int32_t* nonfinite, int64_t* step, int64_t* draws,
+                           int32_t* skipped, double* loss_out, double inv_b, hipStream_t st);
+// *p = 0 (a kernel, so that graph capture records no memset node)
+hipError_t launch_zero_f64(double* p, hipStream_t st);
+// *mse = *mse * inv_n; *psnr = -10 log10(*mse) if psnr != NULL
+hipError_t launch_psnr_finish(double* mse, double inv_n, double* psnr, hipStream_t st);
 hipError_t launch_make_f16(const float* params, __half* out, int64_t n, hipStream_t st);
 
 // Per-call arguments of a batched multi-model query (kernel arguments).

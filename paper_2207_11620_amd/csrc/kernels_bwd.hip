@@ -14,6 +14,65 @@ __device__ __forceinline__ bool finite(float v) { return __builtin_isfinite(v); 
 
 }  // namespace
 
+// dW of one layer over the 16 samples of a tile, accumulated in registers:
+// acc[mo][mi] += dz^T[16mo.., s] a[s, 16mi..] with dz^T and a^T the wave's
+// transposed LDS rows ([neuron][sample], pitch kPitch).  Each operand
+// fragment is read once (one 8-byte load for 16-bit operands) and used for
+// a whole row or column of blocks.  Output element j of lane (nl, g) is
+// dW[16mo + 4g + j][16mi + nl].
+template <int P, int NO, int NI>
+__device__ __forceinline__ void dw_accumulate(const typename Prec<P>::T* dzT, const typename Prec<P>::T* aT,
+                                              f32x4 (&acc)[NO][NI]) {
+  const int lane = threadIdx.x & 63, nl = lane & 15, g = lane >> 4;
+  if constexpr (P != 0) {
+    typedef typename Prec<P>::Frag4 F4;
+    F4 a[NO], b[NI];
+#pragma unroll
+    for (int mo = 0; mo < NO; ++mo)
+      a[mo] = __builtin_bit_cast(F4, *reinterpret_cast<const uint2*>(dzT + (16 * mo + nl) * kPitch + 4 * g));
+#pragma unroll
+    for (int mi = 0; mi < NI; ++mi)
+      b[mi] = __builtin_bit_cast(F4, *reinterpret_cast<const uint2*>(aT + (16 * mi + nl) * kPitch + 4 * g));
+#pragma unroll
+    for (int mo = 0; mo < NO; ++mo)
+#pragma unroll
+      for (int mi = 0; mi < NI; ++mi) acc[mo][mi] = mfma_k16(a[mo], b[mi], acc[mo][mi]);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      float a[NO], b[NI];
+#pragma unroll
+      for (int mo = 0; mo < NO; ++mo) a[mo] = dzT[(16 * mo + nl) * kPitch + 4 * q + g];
+#pragma unroll
+      for (int mi = 0; mi < NI; ++mi) b[mi] = aT[(16 * mi + nl) * kPitch + 4 * q + g];
+#pragma unroll
+      for (int mo = 0; mo < NO; ++mo)
+#pragma unroll
+        for (int mi = 0; mi < NI; ++mi) acc[mo][mi] = mfma(a[mo], b[mi], acc[mo][mi]);
+    }
+  }
+}
+
+// Adds register dW blocks into a row-major [out][in_dim] matrix (columns
+// >= in_dim are padding and dropped), scaled by `scale`.
+template <int NO, int NI>
+__device__ __forceinline__ void dw_flush(const f32x4 (&acc)[NO][NI], float* dw, int in_dim, float scale) {
+  const int lane = threadIdx.x & 63, nl = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int mo = 0; mo < NO; ++mo)
+#pragma unroll
+    for (int mi = 0; mi < NI; ++mi) {
+      const int i = 16 * mi + nl;
+      if (i < in_dim) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          float* p = dw + (16 * mo + 4 * g + j) * in_dim + i;
+          *p += acc[mo][mi][j] * scale;
+        }
+      }
+    }
+}
+
 template <int P, int KIN, int W>
 __host__ __device__ constexpr size_t bwd_wave_bytes(int nh) {
   // z of every hidden layer (f32x4 per lane per block) + dz^T and a^T
@@ -35,12 +94,16 @@ size_t bwd_lds_bytes(const ngvol_plan* plan, int waves, bool gdw) {
 // MLP backward: dW (per-block partial sums) and dL/dfeature written to dfeat.
 // MODE 0 reads the training forward's stored encoding ([B][KIN], 16-bit or
 // FP32), MODE 1 caller features ([n][n_in] FP32).  The table scatter of
-// dfeat is a separate pass (bucketed, see kernels_scatter.hip).  dW
-// accumulates in LDS, or with GDW (networks whose LDS dW would leave room
-// for fewer than four waves) directly in the workgroup's own row of
-// `partial`, which then lives in L2.
+// dfeat is a separate pass (bucketed, see kernels_scatter.hip).  The
+// workgroup's dW sum lives in LDS, or with GDW (networks whose LDS dW would
+// leave room for fewer than four waves) directly in the workgroup's own row
+// of `partial`, which then lives in L2.  With NHC = 2 (two hidden layers,
+// fixed at compile time) every wave keeps its dW in MFMA accumulators over
+// all its tiles and the waves add them into the workgroup sum in turn at the
+// end, in a fixed order and without atomics; otherwise each tile adds its
+// 16-sample products into the sum with LDS (or L2) atomics.
 // ---------------------------------------------------------------------------
-template <int P, int KIN, int W, int MODE, bool GDW>
+template <int P, int KIN, int W, int MODE, bool GDW, int NHC>
 __global__ void __launch_bounds__(64 * kBwdMaxWaves) k_bwd(ModelDesc md, const float* __restrict__ mlp,
                                              const void* __restrict__ e_buf, const float* __restrict__ g_buf,
                                              BatchArgs ba, float* __restrict__ grad, float* __restrict__ dfeat,
@@ -56,7 +119,7 @@ __global__ void __launch_bounds__(64 * kBwdMaxWaves) k_bwd(ModelDesc md, const f
   constexpr int MB = W / 16;
   constexpr int MBI = KIN / 16;
   constexpr int RT = KIN > W ? KIN : W;
-  const int nh = md.n_hidden;
+  const int nh = NHC > 0 ? NHC : md.n_hidden;
   const int n_in = md.n_in;
 
   extern __shared__ __align__(16) unsigned char smem[];
@@ -91,6 +154,18 @@ __global__ void __launch_bounds__(64 * kBwdMaxWaves) k_bwd(ModelDesc md, const f
 #pragma unroll
     for (int j = 0; j < 4; ++j) dwo[mb][j] = 0.0f;
   bool bad = false;
+  // NHC == 2: the wave's dW of layers 1 and 0 over all its tiles
+  f32x4 dacc1[NHC == 2 ? MB : 1][NHC == 2 ? MB : 1];
+  f32x4 dacc0[NHC == 2 ? MB : 1][NHC == 2 ? MBI : 1];
+  if constexpr (NHC == 2) {
+#pragma unroll
+    for (int mo = 0; mo < MB; ++mo) {
+#pragma unroll
+      for (int mi = 0; mi < MB; ++mi) dacc1[mo][mi] = zero4();
+#pragma unroll
+      for (int mi = 0; mi < MBI; ++mi) dacc0[mo][mi] = zero4();
+    }
+  }
 
   const int64_t n_tiles = (B + 15) >> 4;
   TileIter it(n_tiles);
@@ -148,6 +223,7 @@ __global__ void __launch_bounds__(64 * kBwdMaxWaves) k_bwd(ModelDesc md, const f
       act[mb] = acc;
       zbuf[mb * 64 + lane] = acc;
     }
+#pragma unroll
     for (int li = 1; li < nh; ++li) {
       Frag bfr[WL::CHH];
       pack_hidden<P, W>(act, bfr, true);
@@ -163,7 +239,21 @@ __global__ void __launch_bounds__(64 * kBwdMaxWaves) k_bwd(ModelDesc md, const f
     }
 
     // ---- output layer
-    const float gv = valid ? g_buf[sc] : 0.0f;
+    float gv = valid ? g_buf[sc] : 0.0f;
+    if constexpr (MODE == 1) {
+      // an output ReLU passes d_out only where its input was positive (the
+      // training forward has already applied this to its gradient)
+      if (md.out_relu) {
+        float zo = 0.0f;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) zo = __builtin_fmaf(lds_wout[16 * mb + 4 * g + j], relu_bits(act[mb][j]), zo);
+        zo += __shfl_xor(zo, 16, 64);
+        zo += __shfl_xor(zo, 32, 64);
+        if (!(zo > 0.0f)) gv = 0.0f;
+      }
+    }
     if (!finite(gv)) bad = true;
     f32x4 dz[MB];
 #pragma unroll
@@ -178,6 +268,7 @@ __global__ void __launch_bounds__(64 * kBwdMaxWaves) k_bwd(ModelDesc md, const f
 
     // ---- hidden layers, last to first
     f32x4 de[MBI];
+#pragma unroll
     for (int li = nh - 1; li >= 0; --li) {
       const int in_dim = li == 0 ? n_in : W;
       // dz^T and a^T of this layer into the wave's LDS buffers
@@ -200,6 +291,10 @@ __global__ void __launch_bounds__(64 * kBwdMaxWaves) k_bwd(ModelDesc md, const f
       }
       wave_sync();
       // dW_li[o][i] += sum_s dz[s][o] a[s][i]
+      if constexpr (NHC == 2) {
+        if (li == 1) dw_accumulate<P, MB, MB>(dzT, aT, dacc1);
+        else dw_accumulate<P, MB, MBI>(dzT, aT, dacc0);
+      } else {
       float* dw = lds_dw + md.w_off[li];
       const int mbi_n = li == 0 ? MBI : MB;
 #pragma unroll
@@ -231,6 +326,7 @@ __global__ void __launch_bounds__(64 * kBwdMaxWaves) k_bwd(ModelDesc md, const f
             }
           }
         }
+      }
       }
       wave_sync();
       // dh = W_li^T dz
@@ -297,9 +393,27 @@ __global__ void __launch_bounds__(64 * kBwdMaxWaves) k_bwd(ModelDesc md, const f
       v += __shfl_xor(v, 2, 64);
       v += __shfl_xor(v, 4, 64);
       v += __shfl_xor(v, 8, 64);
-      if (nl == 0 && v != 0.0f) atomicAdd(lds_dw + md.w_off[nh] + 16 * mb + 4 * g + j, v);
+      dwo[mb][j] = v;
     }
   if (bad) *nonfinite = 1;
+  // ---- the waves add their sums into the workgroup's dW one after another
+  // (every lane owns distinct elements, so a turn needs no atomics)
+  const int wpb = blockDim.x >> 6;
+  for (int w = 0; w < wpb; ++w) {
+    __syncthreads();
+    if (wave == w) {
+      if constexpr (NHC == 2) {
+        dw_flush<MB, MB>(dacc1, lds_dw + md.w_off[1], W, ibscale);
+        dw_flush<MB, MBI>(dacc0, lds_dw + md.w_off[0], n_in, ibscale);
+      }
+      if (nl == 0) {
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) lds_dw[md.w_off[nh] + 16 * mb + 4 * g + j] += dwo[mb][j];
+      }
+    }
+  }
   if constexpr (!GDW) {
     __syncthreads();
     float* dst = partial + (size_t)blockIdx.x * md.n_mlp;
@@ -399,12 +513,22 @@ __global__ void k_step_begin(double* loss_acc, int32_t* nonfinite) {
   *nonfinite = 0;
 }
 
-__global__ void k_step_end(const double* loss_acc, int32_t* nonfinite, int64_t* step, int32_t* skipped,
-                           double* loss_out, double inv_b) {
+__global__ void k_step_end(const double* loss_acc, int32_t* nonfinite, int64_t* step, int64_t* draws,
+                           int32_t* skipped, double* loss_out, double inv_b) {
   const int32_t bad = *nonfinite;
   if (!bad) *step += 1;
+  if (draws) *draws += 1;
   if (skipped) *skipped = bad;
   if (loss_out) *loss_out = *loss_acc * inv_b;
+}
+
+__global__ void k_zero_f64(double* p) { *p = 0.0; }
+
+// MSE = sum * inv_n; PSNR = -10 log10(MSE) (peak 1), both in FP64
+__global__ void k_psnr_finish(double* mse, double inv_n, double* psnr) {
+  const double m = *mse * inv_n;
+  *mse = m;
+  if (psnr) *psnr = -10.0 * log10(m);
 }
 
 __global__ void __launch_bounds__(256) k_make_f16(const float* __restrict__ p, __half* __restrict__ o, int64_t n) {
@@ -449,9 +573,15 @@ hipError_t launch_bwd(const ngvol_plan* plan, int mode, const float* mlp, const 
   const int waves = bc.waves;
   const size_t lds = bwd_lds_bytes(plan, waves, bc.gdw);
   const int P_ = plan->layout.precision;
-#define NGV_BWD_GO(P, KIN, W, M, G)                                                                                 \
-  hipLaunchKernelGGL((k_bwd<P, KIN, W, M, G>), dim3(grid), dim3(64 * waves), lds, st, md, mlp, e_buf, g_buf, ba,  \
-                     grad, dfeat, partial, nonfinite, bscale)
+#define NGV_BWD_GO(P, KIN, W, M, G)                                                                                \
+  do {                                                                                                         \
+    if (md.n_hidden == 2)                                                                                      \
+      hipLaunchKernelGGL((k_bwd<P, KIN, W, M, G, 2>), dim3(grid), dim3(64 * waves), lds, st, md, mlp, e_buf,   \
+                         g_buf, ba, grad, dfeat, partial, nonfinite, bscale);                                  \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_bwd<P, KIN, W, M, G, 0>), dim3(grid), dim3(64 * waves), lds, st, md, mlp, e_buf,   \
+                         g_buf, ba, grad, dfeat, partial, nonfinite, bscale);                                  \
+  } while (0)
 #define NGV_BWD_LAUNCH(P, KIN, W)                          \
   do {                                                    \
     if (mode == 0) {                                      \
@@ -524,9 +654,20 @@ hipError_t launch_step_begin(double* loss_acc, int32_t* nonfinite, hipStream_t s
   return hipGetLastError();
 }
 
-hipError_t launch_step_end(const double* loss_acc, int32_t* nonfinite, int64_t* step, int32_t* skipped,
-                           double* loss_out, double inv_b, hipStream_t st) {
-  hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, st, loss_acc, nonfinite, step, skipped, loss_out, inv_b);
+hipError_t launch_step_end(const double* loss_acc, int32_t* nonfinite, int64_t* step, int64_t* draws,
+                           int32_t* skipped, double* loss_out, double inv_b, hipStream_t st) {
+  hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, st, loss_acc, nonfinite, step, draws, skipped, loss_out,
+                     inv_b);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_f64(double* p, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(1), 0, st, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_psnr_finish(double* mse, double inv_n, double* psnr, hipStream_t st) {
+  hipLaunchKernelGGL(k_psnr_finish, dim3(1), dim3(1), 0, st, mse, inv_n, psnr);
   return hipGetLastError();
 }
 

@@ -77,7 +77,7 @@ k_infer(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, const float* 
 
   const TT* table = table_ptr<TT>(tp);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  T* stage = reinterpret_cast<T*>(smem + stage_offset(wbytes, W) + wave * Stage<P, KIN>::wave_bytes);
+  T* stage = reinterpret_cast<T*>(smem + stage_offset<P, W>(wbytes) + wave * Stage<P, KIN>::wave_bytes);
   T* row = stage + lane * Stage<P, KIN>::pitch;
   double err = 0.0;
   const int64_t n_groups = (n + 63) >> 6;
@@ -108,7 +108,7 @@ k_infer(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, const float* 
     }
     encode_row<P, F, KIN>(md, table, x, y, z, row, [](int, const Oct<P>&) {});
     wave_sync();
-    const float yv = mlp_wave64<P, KIN, W>(md.n_hidden, lds_frag, lds_wout, stage);
+    const float yv = mlp_wave64<P, KIN, W>(md.n_hidden, md.out_relu != 0, lds_frag, lds_wout, stage);
     wave_sync();  // the stage is rewritten by the next group
     if (valid) {
       if constexpr (MODE == 0) {
@@ -128,13 +128,14 @@ k_infer(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, const float* 
 // ---------------------------------------------------------------------------
 // Standalone MLP on given features ([n][n_in], FP32 or BF16).
 // ---------------------------------------------------------------------------
-template <int P, int KIN, int W, typename IT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P != 0 && KIN == 32 ? 4 : 1)))
+template <int P, int KIN, int W, typename IT, int NHC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mlp_waves_per_eu(P, KIN, NHC))))
 k_mlp_fwd(ModelDesc md, const float* __restrict__ mlp,
                                                  const IT* __restrict__ feat, int64_t n, float* __restrict__ out) {
   // NB tiles (16 samples each) per wave and group: the weight fragments are
-  // read from LDS once per group, and the next group's features are loaded
-  // while this one is evaluated.
+  // read once per group (with NHC = 2 hidden layers fixed at compile time
+  // the kernel keeps all of them in registers), and the next group's
+  // features are loaded while this one is evaluated.
   constexpr int NB = 2;
   constexpr int CH0 = InChunks<P, KIN>::n;
   typedef typename Prec<P>::Frag Frag;
@@ -162,8 +163,8 @@ k_mlp_fwd(ModelDesc md, const float* __restrict__ mlp,
       struct Raw {
         Frag f[NB][KIN / 32];
       };
-      mlp_stream<P, KIN, W, NB, Raw>(
-          md.n_hidden, lds_frag, lds_wout, it.next, it.step, it.end,
+      mlp_stream<P, KIN, W, NB, Raw, NHC>(
+          md.n_hidden, md.out_relu != 0, lds_frag, lds_wout, it.next, it.step, it.end,
           [&](int64_t grp, Raw& r) {
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb)
@@ -184,8 +185,8 @@ k_mlp_fwd(ModelDesc md, const float* __restrict__ mlp,
   struct Raw {
     IT v[NB][KIN / 32][8];
   };
-  mlp_stream<P, KIN, W, NB, Raw>(
-      md.n_hidden, lds_frag, lds_wout, it.next, it.step, it.end,
+  mlp_stream<P, KIN, W, NB, Raw, NHC>(
+      md.n_hidden, md.out_relu != 0, lds_frag, lds_wout, it.next, it.step, it.end,
       [&](int64_t grp, Raw& r) {
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
@@ -280,15 +281,27 @@ hipError_t launch_mlp_fwd_p(const ngvol_plan* plan, const float* mlp, const void
   const size_t lds = fwd_lds_bytes(plan);
   const int grid = grid_for(plan, n_tiles, 4, 8);
   NGV_DISPATCH_KIN(plan->kin, {
-    if (dtype == NGVOL_DT_BF16)
-      hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, __bf16>), dim3(grid), dim3(256), lds, st, md, mlp,
-                         (const __bf16*)feat, n, out);
-    else if (dtype == NGVOL_DT_F16)
-      hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, _Float16>), dim3(grid), dim3(256), lds, st, md, mlp,
-                         (const _Float16*)feat, n, out);
-    else
-      hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, float>), dim3(grid), dim3(256), lds, st, md, mlp,
-                         (const float*)feat, n, out);
+    if (md.n_hidden == 2) {
+      if (dtype == NGVOL_DT_BF16)
+        hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, __bf16, 2>), dim3(grid), dim3(256), lds, st, md, mlp,
+                           (const __bf16*)feat, n, out);
+      else if (dtype == NGVOL_DT_F16)
+        hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, _Float16, 2>), dim3(grid), dim3(256), lds, st, md, mlp,
+                           (const _Float16*)feat, n, out);
+      else
+        hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, float, 2>), dim3(grid), dim3(256), lds, st, md, mlp,
+                           (const float*)feat, n, out);
+    } else {
+      if (dtype == NGVOL_DT_BF16)
+        hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, __bf16, 0>), dim3(grid), dim3(256), lds, st, md, mlp,
+                           (const __bf16*)feat, n, out);
+      else if (dtype == NGVOL_DT_F16)
+        hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, _Float16, 0>), dim3(grid), dim3(256), lds, st, md, mlp,
+                           (const _Float16*)feat, n, out);
+      else
+        hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, float, 0>), dim3(grid), dim3(256), lds, st, md, mlp,
+                           (const float*)feat, n, out);
+    }
   });
   return hipGetLastError();
 }
@@ -301,13 +314,21 @@ template hipError_t launch_mlp_fwd_p<NGV_PSEL, NGV_WSEL>(const ngvol_plan*, cons
                                                hipStream_t);
 
 #if NGV_PRIMARY
-size_t fwd_lds_bytes(const ngvol_plan* plan) {
+size_t mlp_weight_bytes(const ngvol_plan* plan) {
   const int P = plan->layout.precision, KIN = plan->kin, W = plan->layout.n_neurons, nh = plan->md.n_hidden;
   const int ch0 = P ? KIN / 32 : KIN / 4;
   const int chh = P ? (W + 31) / 32 : W / 4;
   const int frags = (W / 16) * ch0 + (nh - 1) * (W / 16) * chh;
-  return (size_t)frags * 64 * (P ? 16 : 4) + (size_t)W * 4;
+  return (size_t)frags * 64 * (P ? 16 : 4);
 }
+
+size_t wout_bytes(const ngvol_plan* plan) {
+  // W_out in FP32, then (16-bit operands) the output layer's fragments
+  const int P = plan->layout.precision, W = plan->layout.n_neurons;
+  return (size_t)W * 4 + (P ? (size_t)((W + 31) / 32) * 64 * 16 : 0);
+}
+
+size_t fwd_lds_bytes(const ngvol_plan* plan) { return mlp_weight_bytes(plan) + wout_bytes(plan); }
 
 size_t enc_lds_bytes(const ngvol_plan* plan, int waves) {
   // staged weights, then one encoding stage of 64 rows per wave

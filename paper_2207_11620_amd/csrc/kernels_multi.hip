@@ -30,7 +30,7 @@ k_multi_infer(const ModelDesc* __restrict__ table, MultiArgs a) {
   float* lds_wout = reinterpret_cast<float*>(smem + wbytes);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wpb = blockDim.x >> 6;
-  T* stage = reinterpret_cast<T*>(smem + stage_offset(wbytes, W) + wave * Stage<P, KIN>::wave_bytes);
+  T* stage = reinterpret_cast<T*>(smem + stage_offset<P, W>(wbytes) + wave * Stage<P, KIN>::wave_bytes);
   T* row = stage + lane * Stage<P, KIN>::pitch;
 
   // items are taken grid-stride, so at any time the whole GPU works on one
@@ -69,7 +69,7 @@ k_multi_infer(const ModelDesc* __restrict__ table, MultiArgs a) {
       const float x = clamp01(xyz[3 * sc]), y = clamp01(xyz[3 * sc + 1]), z = clamp01(xyz[3 * sc + 2]);
       encode_row<P, F, KIN>(md, tab, x, y, z, row, [](int, const Oct<P>&) {});
       wave_sync();
-      const float yo = mlp_wave64<P, KIN, W>(nh, lds_frag, lds_wout, stage);
+      const float yo = mlp_wave64<P, KIN, W>(nh, md.out_relu != 0, lds_frag, lds_wout, stage);
       wave_sync();
       if (valid) out[s] = yo;
     }

@@ -116,10 +116,11 @@ __device__ __forceinline__ int32_t fetch_pixel(unsigned int* queue, int band0, i
   return -1;
 }
 
-// LDS layout of k_render: staged weights, W_out, the LUT [256][4], the
-// slots and per-sample outputs of every wave, then the encoding stages.
-__host__ __device__ inline size_t render_stage_offset(size_t weight_bytes, int W, int waves) {
-  const size_t end = weight_bytes + (size_t)W * 4 + 1024 * 4 + (size_t)waves * kSlots * sizeof(SlotState) +
+// LDS layout of k_render: staged weights, the W_out region, the LUT
+// [256][4], the slots and per-sample outputs of every wave, then the
+// encoding stages.
+__host__ __device__ inline size_t render_stage_offset(size_t weight_bytes, size_t wout_bytes, int waves) {
+  const size_t end = weight_bytes + wout_bytes + 1024 * 4 + (size_t)waves * kSlots * sizeof(SlotState) +
                      (size_t)waves * kSlots * kK * 4 + (size_t)waves * kSlots * kList * 4;
   return (end + 15) & ~(size_t)15;
 }
@@ -133,7 +134,7 @@ k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs r
   Frag* lds_frag = reinterpret_cast<Frag*>(smem);
   const size_t wbytes = (size_t)WL::frags(md.n_hidden, false) * 64 * sizeof(Frag);
   float* lds_wout = reinterpret_cast<float*>(smem + wbytes);
-  float* lds_lut = lds_wout + W;  // [256][4]
+  float* lds_lut = reinterpret_cast<float*>(smem + wbytes + wout_region_bytes<P, W>());  // [256][4]
   const int wave = threadIdx.x >> 6;
   SlotState* slots = reinterpret_cast<SlotState*>(lds_lut + 1024) + wave * kSlots;
   float* yv = reinterpret_cast<float*>(reinterpret_cast<SlotState*>(lds_lut + 1024) + (blockDim.x >> 6) * kSlots) +
@@ -141,7 +142,7 @@ k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs r
   uint32_t* lst = reinterpret_cast<uint32_t*>(yv - wave * kSlots * kK + (blockDim.x >> 6) * kSlots * kK) +
                   wave * kSlots * kList;
   typedef typename Prec<P>::T T;
-  T* stage = reinterpret_cast<T*>(smem + render_stage_offset(wbytes, W, blockDim.x >> 6) +
+  T* stage = reinterpret_cast<T*>(smem + render_stage_offset(wbytes, wout_region_bytes<P, W>(), blockDim.x >> 6) +
                                   wave * Stage<P, KIN>::wave_bytes);
   T* row = stage + (threadIdx.x & 63) * Stage<P, KIN>::pitch;
 
@@ -249,7 +250,7 @@ k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs r
         }
         encode_row<P, F, KIN>(md, table, x, y, z, row, [](int, const Oct<P>&) {});
         wave_sync();
-        yv[lane] = mlp_wave64<P, KIN, W>(md.n_hidden, lds_frag, lds_wout, stage);
+        yv[lane] = mlp_wave64<P, KIN, W>(md.n_hidden, md.out_relu != 0, lds_frag, lds_wout, stage);
         if (valid) ++n_eval;
       }
     }
@@ -314,8 +315,7 @@ k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs r
 size_t render_lds_bytes(const ngvol_plan* plan, int waves) {
   const size_t esz = plan->layout.precision ? 2 : 4;
   const size_t stage = (size_t)64 * (plan->kin + 16 / esz) * esz;
-  return render_stage_offset(fwd_lds_bytes(plan) - (size_t)plan->layout.n_neurons * 4, plan->layout.n_neurons,
-                             waves) +
+  return render_stage_offset(mlp_weight_bytes(plan), wout_bytes(plan), waves) +
          (size_t)waves * stage;
 }
 #endif

@@ -178,7 +178,8 @@ __global__ void __launch_bounds__(kReduceThreads) k_sc_reduce(const uint32_t* __
                                                               const uint32_t* __restrict__ offsets,
                                                               const uint32_t* __restrict__ items, int bshift,
                                                               int64_t chunk_records, int64_t n_entries,
-                                                              float* __restrict__ grad) {
+                                                              float* __restrict__ grad,
+                                                              int32_t* __restrict__ nonfinite) {
   extern __shared__ float acc[];
   if (blockIdx.x >= items[0]) return;
   const int bucket = (int)items[2 + 2 * (size_t)blockIdx.x];
@@ -226,6 +227,7 @@ __global__ void __launch_bounds__(kReduceThreads) k_sc_reduce(const uint32_t* __
   const int64_t first = (int64_t)base_entry * F;
   const int64_t last = n_entries * F;
   constexpr int U = 8;  // entries per thread per round; the owner's gradient loads are issued together
+  bool bad = false;
   for (int t0 = threadIdx.x; t0 < span; t0 += blockDim.x * U) {
     float a[U], old[U];
 #pragma unroll
@@ -239,10 +241,19 @@ __global__ void __launch_bounds__(kReduceThreads) k_sc_reduce(const uint32_t* __
     for (int u = 0; u < U; ++u) {
       const int t = t0 + u * (int)blockDim.x;
       if (a[u] == 0.0f) continue;  // also every entry outside the table
-      if (owner) grad[first + t] = old[u] + a[u];
-      else atomicAdd(grad + first + t, a[u]);
+      // a sum that leaves the finite range marks the step as skipped (the
+      // last atomic on an entry sees its final value)
+      float v;
+      if (owner) {
+        v = old[u] + a[u];
+        grad[first + t] = v;
+      } else {
+        v = atomicAdd(grad + first + t, a[u]) + a[u];
+      }
+      if (!__builtin_isfinite(v)) bad = true;
     }
   }
+  if (bad) *nonfinite = 1;
 }
 
 }  // namespace
@@ -278,7 +289,7 @@ ScatterPlan scatter_plan(const ngvol_plan* plan, int64_t B) {
 }
 
 hipError_t launch_scatter(const ngvol_plan* plan, const ScatterPlan& sp, const BatchArgs& ba, const float* dfeat,
-                          float* grad, void* ws, hipStream_t st) {
+                          float* grad, void* ws, int32_t* nonfinite, hipStream_t st) {
   const ModelDesc& md = plan->md;
   char* base = reinterpret_cast<char*>(ws);
   uint32_t* rec = reinterpret_cast<uint32_t*>(base + sp.rec_off);
@@ -299,7 +310,7 @@ hipError_t launch_scatter(const ngvol_plan* plan, const ScatterPlan& sp, const B
   hipLaunchKernelGGL(k_sc_fill<FV>, dim3(sp.blocks), dim3(kScThreads), hist_lds, st, md, src, ba.B, sp.chunk,      \
                      sp.bshift, sp.n_buckets, counts, offsets, dfeat, rec);                                        \
   hipLaunchKernelGGL(k_sc_reduce<FV>, rgrid, dim3(kReduceThreads), acc_lds, st, rec, totals, offsets, items,      \
-                     sp.bshift, sp.chunk_records, n_entries, grad)
+                     sp.bshift, sp.chunk_records, n_entries, grad, nonfinite)
   switch (md.F) {
     case 2: NGV_SC(2); break;
     case 4: NGV_SC(4); break;

@@ -115,8 +115,8 @@ struct PlaneOrder {
 // EC: entry class of the planes, 0 for entries of 8 or more features, else
 // the entry size (4 or 2 features); FULL: the planes hold all KIN features
 // (no zero padding to supply).
-template <int P, int F, int KIN, int W, typename OT, int EC, bool FULL>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P != 0 && KIN == 32 ? 4 : 1)))
+template <int P, int F, int KIN, int W, typename OT, int EC, bool FULL, int NHC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mlp_waves_per_eu(P, KIN, NHC))))
 k_mlp_planes(ModelDesc md, const float* __restrict__ mlp, const OT* __restrict__ planes,
              const uint32_t* __restrict__ idx, int64_t m, float* __restrict__ out, PlaneOrder po, int E,
              int n_plane_feat) {
@@ -155,8 +155,8 @@ k_mlp_planes(ModelDesc md, const float* __restrict__ mlp, const OT* __restrict__
     w[3] = t.w;
   };
   constexpr int EPD = 4 / (int)sizeof(OT);  // elements per dword
-  mlp_stream<P, KIN, W, NB, Raw>(
-      md.n_hidden, lds_frag, lds_wout, it.next, it.step, it.end,
+  mlp_stream<P, KIN, W, NB, Raw, NHC>(
+      md.n_hidden, md.out_relu != 0, lds_frag, lds_wout, it.next, it.step, it.end,
       [&](int64_t grp, Raw& r) {
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
@@ -303,8 +303,14 @@ hipError_t launch_infer_split_p(const ngvol_plan* plan, TablePtrs tp, const floa
     po.col[p] = (int8_t)col;
   }
 #define NGV_MP(EC, FULL)                                                                                        \
-  hipLaunchKernelGGL((k_mlp_planes<P, F, KIN, W, OT, EC, FULL>), dim3((unsigned)mgrid), dim3(256), lds, st, md, mlp, \
-                     pl, idx, m, out, po, E, n_plane_feat)
+  do {                                                                                                          \
+    if (md.n_hidden == 2)                                                                                       \
+      hipLaunchKernelGGL((k_mlp_planes<P, F, KIN, W, OT, EC, FULL, 2>), dim3((unsigned)mgrid), dim3(256), lds, st, \
+                         md, mlp, pl, idx, m, out, po, E, n_plane_feat);                                        \
+    else                                                                                                        \
+      hipLaunchKernelGGL((k_mlp_planes<P, F, KIN, W, OT, EC, FULL, 0>), dim3((unsigned)mgrid), dim3(256), lds, st, \
+                         md, mlp, pl, idx, m, out, po, E, n_plane_feat);                                        \
+  } while (0)
   for (int64_t s0 = 0; s0 < n; s0 += slab) {
     const int64_t m = n - s0 < slab ? n - s0 : slab;
     const int64_t chunks = (m + 63) / 64;

@@ -32,7 +32,7 @@ k_train_fwd(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, BatchArgs
   const VT* vol = reinterpret_cast<const VT*>(ba.volume);
   T* e = reinterpret_cast<T*>(e_buf);  // stored encoding [B][KIN] in the operand type
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  T* stage = reinterpret_cast<T*>(smem + stage_offset(wbytes, W) + wave * Stage<P, KIN>::wave_bytes);
+  T* stage = reinterpret_cast<T*>(smem + stage_offset<P, W>(wbytes) + wave * Stage<P, KIN>::wave_bytes);
   T* row = stage + lane * Stage<P, KIN>::pitch;
   const int64_t B = ba.B;
   const int64_t bstep = ba.step_index();
@@ -59,16 +59,19 @@ k_train_fwd(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, BatchArgs
       if (valid) *reinterpret_cast<Oct<P>*>(e + s * KIN + 8 * sb) = o;
     });
     wave_sync();
-    const float yv = mlp_wave64<P, KIN, W>(md.n_hidden, lds_frag, lds_wout, stage);
+    const float yv = mlp_wave64<P, KIN, W>(md.n_hidden, md.out_relu != 0, lds_frag, lds_wout, stage);
     wave_sync();
     if (valid && ba.mc.range) mc_extend(ba.mc.range, mc_index(ba.mc, x, y, z), target);
     if (valid) {
       const float r = yv - target;
+      // with an output ReLU the gradient passes only where its input was
+      // positive (ReLU'(0) = 0): there the output is positive too
+      const bool pass = !md.out_relu || yv > 0.0f;
       if (l1) {
-        g_buf[s] = r > 0.0f ? gscale : (r < 0.0f ? -gscale : 0.0f);
+        g_buf[s] = pass ? (r > 0.0f ? gscale : (r < 0.0f ? -gscale : 0.0f)) : 0.0f;
         lsum += (double)fabsf(r);
       } else {
-        g_buf[s] = gscale * r;
+        g_buf[s] = pass ? gscale * r : 0.0f;
         lsum += (double)r * (double)r;
       }
     }

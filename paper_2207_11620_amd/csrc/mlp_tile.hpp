@@ -15,6 +15,12 @@
 //   P = 0: FP32 operands, v_mfma_f32_16x16x4_f32 (K = 4 per instruction).
 // Both accumulate in FP32.
 //
+// The output neuron (W_out, one row) is a VALU dot product for P = 0.  For
+// 16-bit operands it is one more MFMA per K chunk: its A operand holds W_out
+// in rows 0, 4, 8 and 12 and zeros elsewhere, so that accumulator element 0
+// of every lane (n, g) is the output of sample n - each lane receives its
+// sample's output without a shuffle.  An optional ReLU follows it.
+//
 // Encoded inputs enter as B operands in which, for every 32-feature block b,
 // lane group g holds features 32b + 8g + jj (jj = 0..7) of sample n.  They
 // are produced with one sample per lane (all lanes on the same level) and
@@ -134,8 +140,24 @@ struct WeightLayout {
   }
 };
 
+// The region behind the staged matrices: W_out in FP32 (W floats) and, for
+// 16-bit operands in the forward, the output layer's A fragments.
+template <int P, int W>
+__host__ __device__ constexpr size_t wout_region_bytes() {
+  return (size_t)W * 4 + (P != 0 ? (size_t)HidChunks<P, W>::n * 64 * sizeof(typename Prec<P>::Frag) : 0);
+}
+template <int P, int W>
+__device__ __forceinline__ typename Prec<P>::Frag* out_frags(float* lds_wout) {
+  return reinterpret_cast<typename Prec<P>::Frag*>(lds_wout + W);
+}
+template <int P, int W>
+__device__ __forceinline__ const typename Prec<P>::Frag* out_frags(const float* lds_wout) {
+  return reinterpret_cast<const typename Prec<P>::Frag*>(lds_wout + W);
+}
+
 // Stage W0..W_{h-1} (and, for the backward, their transposes) into LDS in
-// fragment order, plus W_out in FP32.  Called by the whole workgroup.
+// fragment order, plus W_out in FP32 and (forward, 16-bit operands) as
+// output-layer fragments.  Called by the whole workgroup.
 // colmap (optional, LDS): input feature of each first-layer operand column
 // (-1: none), for kernels whose encoded inputs arrive in another order.
 template <int P, int KIN, int W>
@@ -230,6 +252,22 @@ __device__ void stage_weights(const ModelDesc& md, const float* __restrict__ mlp
   }
   const float* wo = mlp + md.w_off[nh];
   for (int t = threadIdx.x; t < W; t += blockDim.x) lds_wout[t] = wo[t];
+  if constexpr (P != 0) {
+    // forward: the output layer's A operands (W_out in rows 0, 4, 8, 12)
+    if (!bwd) {
+      Frag* ofrag = out_frags<P, W>(lds_wout);
+      for (int t = threadIdx.x; t < HidChunks<P, W>::n * 64; t += blockDim.x) {
+        const int lane = t & 63, c = t >> 6, i = lane & 15, g = lane >> 4;
+        Frag val;
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) {
+          const int col = hid_col<P>(c, g, jj);
+          val[jj] = (typename Prec<P>::T)((i & 3) == 0 && col < W ? wo[col] : 0.0f);
+        }
+        ofrag[t] = val;
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -246,13 +284,39 @@ __device__ __forceinline__ float relu_bits(float x) { return __int_as_float(max(
 
 typedef short short8 __attribute__((ext_vector_type(8)));
 
+// Two FP32 values to a BF16 pair with round-to-nearest-even.  A two-wide
+// vector conversion becomes one v_cvt_pk_bf16_f32 (element-wise conversions
+// are converted one value at a time and then merged), and the compiler sees
+// it, so it keeps the wait states a read of a matrix-core result needs.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t cvt_pk_bf16(float lo, float hi) {
+  const f32x2 v = {lo, hi};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+}
+
+// Hidden activations (accumulator layout) to the B operands of the next
+// layer: chunk c takes blocks 2c and 2c+1 (16-bit operands) or element c&3
+// of block c>>2 (FP32).  relu: clamp at zero, done on the 16-bit values two
+// per instruction (rounding then clamping equals clamping then rounding).
 template <int P, int W>
 __device__ __forceinline__ void pack_hidden(const f32x4 act[W / 16], typename Prec<P>::Frag out[HidChunks<P, W>::n],
                                             bool relu) {
   constexpr int CHH = HidChunks<P, W>::n;
 #pragma unroll
   for (int c = 0; c < CHH; ++c) {
-    if constexpr (P) {
+    if constexpr (P == 1) {
+      uint32_t w[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = 2 * c + (q >> 1);
+        w[q] = (m < W / 16) ? cvt_pk_bf16(act[m < W / 16 ? m : 0][2 * (q & 1)], act[m < W / 16 ? m : 0][2 * (q & 1) + 1])
+                            : 0u;
+      }
+      short8 h = __builtin_bit_cast(short8, w);
+      if (relu) h = __builtin_elementwise_max(h, (short8)0);
+      out[c] = __builtin_bit_cast(typename Prec<P>::Frag, h);
+    } else if constexpr (P == 2) {
 #pragma unroll
       for (int jj = 0; jj < 8; ++jj) {
         const int m = 2 * c + (jj >> 2);
@@ -260,8 +324,6 @@ __device__ __forceinline__ void pack_hidden(const f32x4 act[W / 16], typename Pr
         out[c][jj] = (typename Prec<P>::T)v;
       }
       if (relu) {
-        // on the 16-bit values, two per instruction: rounding then clamping
-        // at zero equals clamping then rounding
         short8 h = __builtin_bit_cast(short8, out[c]);
         h = __builtin_elementwise_max(h, (short8)0);
         out[c] = __builtin_bit_cast(typename Prec<P>::Frag, h);
@@ -273,48 +335,22 @@ __device__ __forceinline__ void pack_hidden(const f32x4 act[W / 16], typename Pr
   }
 }
 
-template <int P, int KIN, int W, bool KEEP_Z>
-__device__ __forceinline__ void mlp_hidden_fwd(int n_hidden, const typename Prec<P>::Frag* __restrict__ lds_frag,
-                                               const typename Prec<P>::Frag in_frag[InChunks<P, KIN>::n],
-                                               f32x4 act[W / 16], f32x4 (*zkeep)[W / 16]) {
-  typedef WeightLayout<P, KIN, W> WL;
-  typedef typename Prec<P>::Frag Frag;
-  constexpr int MB = W / 16;
-  const int lane = threadIdx.x & 63;
-  // layer 0
-#pragma unroll
-  for (int mb = 0; mb < MB; ++mb) {
-    f32x4 acc = zero4();
-#pragma unroll
-    for (int c = 0; c < WL::CH0; ++c) acc = mfma(lds_frag[(mb * WL::CH0 + c) * 64 + lane], in_frag[c], acc);
-    act[mb] = acc;
-  }
-  if constexpr (KEEP_Z) {
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb) zkeep[0][mb] = act[mb];
-  }
-  // hidden layers 1..n_hidden-1
-  for (int li = 1; li < n_hidden; ++li) {
-    Frag b[WL::CHH];
-    pack_hidden<P, W>(act, b, true);
-    const Frag* base = lds_frag + (WL::FR0 + (li - 1) * WL::FRH) * 64;
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-      f32x4 acc = zero4();
-#pragma unroll
-      for (int c = 0; c < WL::CHH; ++c) acc = mfma(base[(mb * WL::CHH + c) * 64 + lane], b[c], acc);
-      act[mb] = acc;
-    }
-    if constexpr (KEEP_Z) {
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb) zkeep[li][mb] = act[mb];
-    }
-  }
+// Occupancy target (waves per SIMD) of the streaming MLP kernels: 4 for
+// 16-bit operands and 32 inputs (their registers fit), 2 when the depth is
+// fixed at compile time (the kernel then keeps every weight fragment in
+// registers next to two tiles' activations), else no target.
+__host__ __device__ constexpr int mlp_waves_per_eu(int P, int KIN, int NHC) {
+  return P != 0 && NHC > 0 ? 2 : (P != 0 && KIN == 32 ? 4 : 1);
 }
 
-// The same forward over NB tiles at once: each weight fragment is read from
-// LDS once for all NB tiles, and the NB accumulator chains are independent.
-template <int P, int KIN, int W, int NB>
+// Forward through the hidden layers over NB tiles at once: each weight
+// fragment is read once for all NB tiles, and the NB accumulator chains are
+// independent.  in[nb][c]: B operands of the encoded input; returns the last
+// hidden pre-activations in act[nb][mb] (FP32, accumulator layout).  NHC > 0
+// fixes the number of hidden layers at compile time (the layer loop unrolls
+// and a kernel that never writes LDS can keep every weight in registers);
+// NHC = 0 takes n_hidden.
+template <int P, int KIN, int W, int NB, int NHC = 0>
 __device__ __forceinline__ void mlp_hidden_fwd_nb(int n_hidden, const typename Prec<P>::Frag* __restrict__ lds_frag,
                                                   const typename Prec<P>::Frag in[NB][InChunks<P, KIN>::n],
                                                   f32x4 act[NB][W / 16]) {
@@ -322,6 +358,7 @@ __device__ __forceinline__ void mlp_hidden_fwd_nb(int n_hidden, const typename P
   typedef typename Prec<P>::Frag Frag;
   constexpr int MB = W / 16;
   const int lane = threadIdx.x & 63;
+  const int nh = NHC > 0 ? NHC : n_hidden;
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb) {
     f32x4 acc[NB];
@@ -336,7 +373,8 @@ __device__ __forceinline__ void mlp_hidden_fwd_nb(int n_hidden, const typename P
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) act[nb][mb] = acc[nb];
   }
-  for (int li = 1; li < n_hidden; ++li) {
+#pragma unroll
+  for (int li = 1; li < nh; ++li) {
     Frag b[NB][WL::CHH];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) pack_hidden<P, W>(act[nb], b[nb], true);
@@ -358,18 +396,36 @@ __device__ __forceinline__ void mlp_hidden_fwd_nb(int n_hidden, const typename P
   }
 }
 
-// Output neuron: y = w_out . relu(z_last); every lane of the sample gets y.
-template <int W>
-__device__ __forceinline__ float mlp_output(const f32x4 zlast[W / 16], const float* __restrict__ lds_wout) {
-  const int g = (threadIdx.x & 63) >> 4;
-  float s = 0.0f;
+// Output neuron: y = w_out . relu(z_last), then ReLU if relu_out; every lane
+// of the sample gets y.  P = 0: FP32 dot product over the lane's neurons and
+// a sum over the four lane groups; 16-bit operands: the output MFMA.
+template <int P, int W>
+__device__ __forceinline__ float mlp_output(const f32x4 zlast[W / 16], const float* __restrict__ lds_wout,
+                                            bool relu_out) {
+  float y;
+  if constexpr (P == 0) {
+    const int g = (threadIdx.x & 63) >> 4;
+    float s = 0.0f;
 #pragma unroll
-  for (int mb = 0; mb < W / 16; ++mb)
+    for (int mb = 0; mb < W / 16; ++mb)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) s = __builtin_fmaf(lds_wout[16 * mb + 4 * g + j], relu_bits(zlast[mb][j]), s);
-  s += __shfl_xor(s, 16, 64);
-  s += __shfl_xor(s, 32, 64);
-  return s;
+      for (int j = 0; j < 4; ++j) s = __builtin_fmaf(lds_wout[16 * mb + 4 * g + j], relu_bits(zlast[mb][j]), s);
+    s += __shfl_xor(s, 16, 64);
+    s += __shfl_xor(s, 32, 64);
+    y = s;
+  } else {
+    typedef typename Prec<P>::Frag Frag;
+    constexpr int CHH = HidChunks<P, W>::n;
+    const int lane = threadIdx.x & 63;
+    Frag b[CHH];
+    pack_hidden<P, W>(zlast, b, true);
+    const Frag* of = out_frags<P, W>(lds_wout);
+    f32x4 acc = zero4();
+#pragma unroll
+    for (int c = 0; c < CHH; ++c) acc = mfma(of[c * 64 + lane], b[c], acc);
+    y = acc[0];
+  }
+  return relu_out ? relu_bits(y) : y;
 }
 
 // ---------------------------------------------------------------------------
@@ -379,8 +435,8 @@ __device__ __forceinline__ float mlp_output(const f32x4 zlast[W / 16], const flo
 // flight during the MFMA work.  cv turns loaded data into B operands; st
 // receives y for (group, tile, lane) together with the group's loaded data.
 // ---------------------------------------------------------------------------
-template <int P, int KIN, int W, int NB, typename Raw, class Ld, class Cv, class St>
-__device__ __forceinline__ void mlp_stream(int n_hidden, const typename Prec<P>::Frag* __restrict__ lds_frag,
+template <int P, int KIN, int W, int NB, typename Raw, int NHC, class Ld, class Cv, class St>
+__device__ __forceinline__ void mlp_stream(int n_hidden, bool relu_out, const typename Prec<P>::Frag* __restrict__ lds_frag,
                                            const float* __restrict__ lds_wout, int64_t t, int64_t step, int64_t end,
                                            Ld ld, Cv cv, St st) {
   typedef typename Prec<P>::Frag Frag;
@@ -388,9 +444,9 @@ __device__ __forceinline__ void mlp_stream(int n_hidden, const typename Prec<P>:
     Frag in[NB][InChunks<P, KIN>::n];
     cv(r, in);
     f32x4 act[NB][W / 16];
-    mlp_hidden_fwd_nb<P, KIN, W, NB>(n_hidden, lds_frag, in, act);
+    mlp_hidden_fwd_nb<P, KIN, W, NB, NHC>(n_hidden, lds_frag, in, act);
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) st(grp, nb, mlp_output<W>(act[nb], lds_wout), r);
+    for (int nb = 0; nb < NB; ++nb) st(grp, nb, mlp_output<P, W>(act[nb], lds_wout, relu_out), r);
   };
   if (t >= end) return;
   Raw a, b;
@@ -483,14 +539,15 @@ __device__ __forceinline__ void stage_frags(const typename Prec<P>::T* stage, in
 }
 
 // Byte offset of the per-wave encoding stages behind the staged weights.
-__device__ __forceinline__ size_t stage_offset(size_t weight_bytes, int W) {
-  return (weight_bytes + (size_t)W * 4 + 15) & ~(size_t)15;
+template <int P, int W>
+__device__ __forceinline__ size_t stage_offset(size_t weight_bytes) {
+  return (weight_bytes + wout_region_bytes<P, W>() + 15) & ~(size_t)15;
 }
 
 // The network on the wave's 64 staged samples (4 tiles, NB at a time); the
 // lane receives y of its own sample (tile g, column n).
 template <int P, int KIN, int W, int NB = 1>
-__device__ __forceinline__ float mlp_wave64(int n_hidden, const typename Prec<P>::Frag* __restrict__ lds_frag,
+__device__ __forceinline__ float mlp_wave64(int n_hidden, bool relu_out, const typename Prec<P>::Frag* __restrict__ lds_frag,
                                             const float* __restrict__ lds_wout, const typename Prec<P>::T* stage) {
   typedef typename Prec<P>::Frag Frag;
   const int g = (threadIdx.x & 63) >> 4;
@@ -504,7 +561,7 @@ __device__ __forceinline__ float mlp_wave64(int n_hidden, const typename Prec<P>
     mlp_hidden_fwd_nb<P, KIN, W, NB>(n_hidden, lds_frag, in, act);
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-      const float y = mlp_output<W>(act[nb], lds_wout);
+      const float y = mlp_output<P, W>(act[nb], lds_wout, relu_out);
       if (g == NB * h + nb) yo = y;
     }
   }

@@ -18,6 +18,7 @@ struct LevelDesc {
 // through the scalar cache).
 struct ModelDesc {
   int32_t L, F, n_in, width, n_hidden, n_layers;
+  int32_t out_relu;  // 1: ReLU on the output neuron
   int64_t n_table;  // table floats
   int64_t n_params;
   int32_t w_off[NGVOL_MAX_LAYERS];  // matrix offsets relative to the MLP block

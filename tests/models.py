@@ -24,17 +24,18 @@ MODELS = {
 }
 
 
-def oracle_model(name):
+def oracle_model(name, out_relu=False):
     c = MODELS[name]
     res = oracle.resolutions(c["L"], c["base"], c["scale"], c["maxres"])
-    return oracle.Model(c["L"], c["F"], c["log2T"], res, c["width"], c["n_hidden"])
+    return oracle.Model(c["L"], c["F"], c["log2T"], res, c["width"], c["n_hidden"], out_relu=out_relu)
 
 
-def gpu_plan(name, precision="fp32", loss="l2"):
+def gpu_plan(name, precision="fp32", loss="l2", out_relu=False):
     import paper_2207_11620_amd as ngv
     c = MODELS[name]
     return ngv.Plan(c["L"], c["F"], c["log2T"], c["base"], c["scale"] or 2.0, c["maxres"], n_neurons=c["width"],
-                    n_hidden_layers=c["n_hidden"], precision=precision, loss=loss)
+                    n_hidden_layers=c["n_hidden"], precision=precision, loss=loss,
+                    output_activation="relu" if out_relu else "none")
 
 
 def init_params(name, seed=SEED, table_scale=None):

@@ -126,3 +126,47 @@ def test_null_arguments_rejected_without_launch():
     sz = C.c_size_t()
     assert L.ngvol_train_workspace_bytes(p.handle, 4096, C.byref(sz)) == ngv.OK
     assert sz.value > 4096 * 32 * 4
+
+
+def _fake_state(p):
+    """A training state whose device pointers are never dereferenced on the
+    host (every call below is refused before any launch)."""
+    import ctypes as C
+    addr = lambda k: C.c_void_p(4096 * (k + 1))
+    st = ngv.TrainStateC(addr(0), None, addr(1), addr(2), addr(3), addr(4), addr(5), addr(6), addr(7), 1 << 40)
+    return st
+
+
+def test_train_limits_checked_on_the_host():
+    import ctypes as C
+    L = _lib_or_skip()
+    p = ngv.Plan(**CFG1)  # 16 levels: 128 table-gradient records per sample
+    sz = C.c_size_t()
+    # B * 8 * L = 2^32 records would overflow the scatter's 32-bit positions
+    assert L.ngvol_train_workspace_bytes(p.handle, 1 << 25, C.byref(sz)) == ngv.EINVAL
+    assert b"2^32" in L.ngvol_last_error()
+    assert L.ngvol_train_workspace_bytes(p.handle, (1 << 25) - 1, C.byref(sz)) == ngv.OK
+    st = _fake_state(p)
+    batch = ngv.Batch(1 << 25, None, None, C.c_void_p(1 << 20), (C.c_int32 * 3)(64, 64, 64), 0, 1, 0, None)
+    adam = ngv.Adam(1e-2, 0.9, 0.99, 1e-15, 0.0, 0, 0, 1.0)
+    assert L.ngvol_train_step(p.handle, C.byref(st), C.byref(batch), C.byref(adam), 128.0, None) == ngv.EINVAL
+    # a table whose gradient-bucket histogram exceeds the LDS: 2^28 entries of
+    # 2 features = 65536 buckets of 2^12 entries
+    big = ngv.Plan(1, 2, 28, resolutions=[1024], n_neurons=32, n_hidden_layers=1)
+    assert L.ngvol_train_workspace_bytes(big.handle, 4096, C.byref(sz)) == ngv.EUNSUPPORTED
+    batch.batch_size = 4096
+    assert L.ngvol_train_step(big.handle, C.byref(st), C.byref(batch), C.byref(adam), 128.0, None) == ngv.EUNSUPPORTED
+    ok = ngv.Plan(1, 2, 27, resolutions=[1024], n_neurons=32, n_hidden_layers=1)  # 32768 buckets: fits
+    assert L.ngvol_train_workspace_bytes(ok.handle, 4096, C.byref(sz)) == ngv.OK
+
+
+def test_output_activation_option():
+    _lib_or_skip()
+    p = ngv.Plan(**CFG0, output_activation="relu")
+    assert p.output_activation == "relu"
+    with pytest.raises(ngv.NgvolError) as ei:
+        import ctypes as C
+        cfg = ngv.Config(8, 2, 14, 4, 1.5, 0, None, 32, 2, 0, 0, 5)
+        h = C.c_void_p()
+        ngv._check(ngv.lib().ngvol_plan_create(C.byref(cfg), C.byref(h)))
+    assert ei.value.code == ngv.EINVAL
