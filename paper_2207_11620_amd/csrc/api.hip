@@ -298,9 +298,12 @@ static hipError_t launch_grouped(const ngvol_plan* plan, const BinPlan& bp, cons
   char* base = reinterpret_cast<char*>(ws);
   const float4* rec = reinterpret_cast<const float4*>(base + bp.rec_off);
   const float* mlp = w->params + plan->md.n_table;
-  if (bp.split && w->table_f16)  // FP32 tables (4 MB per level) would not fit an L2 per level pair
+  if (bp.split && w->table_f16) {  // FP32 tables (4 MB per level) would not fit an L2 per level pair
+    const BinRanges bins{reinterpret_cast<const uint32_t*>(base + bp.offsets_off),
+                         reinterpret_cast<const uint32_t*>(base + bp.totals_off), bp.k};
     return launch_infer_split(plan, tables_of(plan, w), mlp, rec, n, out, base + bp.planes_off,
-                              reinterpret_cast<uint32_t*>(base + bp.idx_off), st);
+                              reinterpret_cast<uint32_t*>(base + bp.idx_off), bins, st);
+  }
   return launch_infer(plan, tables_of(plan, w), mlp, nullptr, rec, n, out, st);
 }
 

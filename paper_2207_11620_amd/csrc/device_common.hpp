@@ -63,20 +63,38 @@ __device__ __forceinline__ uint32_t level_slot(const LevelDesc& lv, uint32_t vx,
   return (vx ^ (vy * 2654435761u) ^ (vz * 805459861u)) & lv.mask;
 }
 
+// Cell of a point at one level: the corner vertex c (lowest corner) per
+// axis and the trilinear weights of the 8 corners, corner k = (k&1, (k>>1)&1,
+// (k>>2)&1).
+struct Cell {
+  int c[3];
+  float w[8];
+};
+
+__device__ __forceinline__ void level_cell(const LevelDesc& lv, float x, float y, float z, Cell& cl) {
+  const float s = (float)(lv.N - 1);
+  const float cmax = (float)(lv.N - 2);
+  float wx, wy, wz;
+  level_axis(x, s, cmax, cl.c[0], wx);
+  level_axis(y, s, cmax, cl.c[1], wy);
+  level_axis(z, s, cmax, cl.c[2], wz);
+  const float ox = 1.0f - wx, oy = 1.0f - wy, oz = 1.0f - wz;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int dx = k & 1, dy = (k >> 1) & 1, dz = (k >> 2) & 1;
+    cl.w[k] = ((dx ? wx : ox) * (dy ? wy : oy)) * (dz ? wz : oz);
+  }
+}
+
 struct Corners {
   uint32_t slot[8];  // with level offset
   float w[8];
 };
 
 __device__ __forceinline__ void level_corners(const LevelDesc& lv, float x, float y, float z, Corners& cr) {
-  const float s = (float)(lv.N - 1);
-  const float cmax = (float)(lv.N - 2);
-  int cx, cy, cz;
-  float wx, wy, wz;
-  level_axis(x, s, cmax, cx, wx);
-  level_axis(y, s, cmax, cy, wy);
-  level_axis(z, s, cmax, cz, wz);
-  const float ox = 1.0f - wx, oy = 1.0f - wy, oz = 1.0f - wz;
+  Cell cl;
+  level_cell(lv, x, y, z, cl);
+  const int cx = cl.c[0], cy = cl.c[1], cz = cl.c[2];
   // the slots of the 8 corners differ from the first by constants (dense) or
   // by the hash terms of y+1 and z+1, (v+1)*p = v*p + p (mod 2^32)
   if (lv.dense) {
@@ -95,10 +113,7 @@ __device__ __forceinline__ void level_corners(const LevelDesc& lv, float x, floa
     }
   }
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const int dx = k & 1, dy = (k >> 1) & 1, dz = (k >> 2) & 1;
-    cr.w[k] = ((dx ? wx : ox) * (dy ? wy : oy)) * (dz ? wz : oz);
-  }
+  for (int k = 0; k < 8; ++k) cr.w[k] = cl.w[k];
 }
 
 // Element at a 32-bit byte offset from a table base (tables are below 4 GB):

@@ -148,16 +148,38 @@ struct SplitArgs {
   int part[8], parts[8];
   int width;
 };
+// Brick-staged level groups (2 levels of plane storage per query): the
+// grouping's bins (Morton order, 2^k per axis) give each brick's records;
+// pair p holds levels lev[p][0..1] (-1: none), lds_off[p][i] is the byte
+// offset of level i's vertex box in LDS (-1: gathered from the table), and
+// XCD x works on the (pair, brick) items [item_lo[x], item_lo[x+1]) of the
+// pair-major list (item = pair * n_bins + brick).
+struct BrickArgs {
+  const uint32_t* bin_off;
+  const uint32_t* bin_cnt;
+  int k, n_bins;
+  int lev[8][2];
+  int lds_off[8][2];
+  int item_lo[9];
+  int gw;
+};
 bool use_split(const ngvol_plan* plan, int64_t n);
 int64_t split_slab(const ngvol_plan* plan, int64_t n);
 size_t split_planes_bytes(const ngvol_plan* plan, int64_t n);
 // rec: grouped records (x, y, z, original index); planes/idx: workspace of
 // split_planes_bytes and split_slab * 4 bytes.
+// bin_off/bin_cnt (nullable): the grouping's per-bin record ranges over 2^bin_k
+// bins per axis, for the brick-staged level kernel.
+struct BinRanges {
+  const uint32_t* off;
+  const uint32_t* cnt;
+  int k;
+};
 hipError_t launch_infer_split(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const float4* rec, int64_t n,
-                              float* out, void* planes, uint32_t* idx, hipStream_t st);
+                              float* out, void* planes, uint32_t* idx, BinRanges bins, hipStream_t st);
 template <int P, int W>
 hipError_t launch_infer_split_p(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const float4* rec, int64_t n,
-                                float* out, void* planes, uint32_t* idx, hipStream_t st);
+                                float* out, void* planes, uint32_t* idx, BinRanges bins, hipStream_t st);
 
 // LDS of the staged forward weights: the fragments of W_0..W_{h-1}
 // (mlp_weight_bytes), then W_out and its output-layer fragments (wout_bytes).

@@ -223,8 +223,7 @@ __global__ void __launch_bounds__(64 * kBwdMaxWaves) k_bwd(ModelDesc md, const f
       act[mb] = acc;
       zbuf[mb * 64 + lane] = acc;
     }
-#pragma unroll
-    for (int li = 1; li < nh; ++li) {
+    auto fwd_layer = [&](int li) {
       Frag bfr[WL::CHH];
       pack_hidden<P, W>(act, bfr, true);
       const Frag* base = lds_frag + (WL::FR0 + (li - 1) * WL::FRH) * 64;
@@ -236,6 +235,12 @@ __global__ void __launch_bounds__(64 * kBwdMaxWaves) k_bwd(ModelDesc md, const f
         act[mb] = acc;
         zbuf[(li * MB + mb) * 64 + lane] = acc;
       }
+    };
+    if constexpr (NHC > 0) {
+#pragma unroll
+      for (int li = 1; li < NHC; ++li) fwd_layer(li);
+    } else {
+      for (int li = 1; li < nh; ++li) fwd_layer(li);
     }
 
     // ---- output layer
@@ -268,8 +273,7 @@ __global__ void __launch_bounds__(64 * kBwdMaxWaves) k_bwd(ModelDesc md, const f
 
     // ---- hidden layers, last to first
     f32x4 de[MBI];
-#pragma unroll
-    for (int li = nh - 1; li >= 0; --li) {
+    auto bwd_layer = [&](int li) {
       const int in_dim = li == 0 ? n_in : W;
       // dz^T and a^T of this layer into the wave's LDS buffers
 #pragma unroll
@@ -362,6 +366,12 @@ __global__ void __launch_bounds__(64 * kBwdMaxWaves) k_bwd(ModelDesc md, const f
           de[mb] = acc;
         }
       }
+    };
+    if constexpr (NHC > 0) {
+#pragma unroll
+      for (int li = NHC - 1; li >= 0; --li) bwd_layer(li);
+    } else {
+      for (int li = nh - 1; li >= 0; --li) bwd_layer(li);
     }
 
     // ---- dL/dfeature: lane holds features 16m + 4g + j

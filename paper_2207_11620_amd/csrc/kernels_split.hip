@@ -106,6 +106,174 @@ __global__ void __launch_bounds__(256) k_level_feat(ModelDesc md, const TT* __re
   }
 }
 
+// ---------------------------------------------------------------------------
+// Brick-staged level groups.  The grouped records come in Morton order of
+// 2^k cells per axis (bins), so the records of one cell of space (a brick of
+// 1/2^k per axis) are one contiguous range.  For a level whose vertices over
+// a brick fit in LDS, the workgroup first copies that box of vertices from
+// the table into LDS - rows of consecutive vertices, whose slots (dense, or
+// hashed with an x prime of 1) lie in a few aligned blocks, so a wave's loads
+// touch a few cache lines - and then reads every query's 8 corners from LDS.
+// Corner values, weights and the order of the interpolation are those of
+// gather_level, so the features are bitwise the same; levels whose box does
+// not fit are gathered from the table as before.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int compact3(uint32_t v) {
+  v &= 0x09249249u;
+  v = (v ^ (v >> 2)) & 0x030C30C3u;
+  v = (v ^ (v >> 4)) & 0x0300F00Fu;
+  v = (v ^ (v >> 8)) & 0x030000FFu;
+  v = (v ^ (v >> 16)) & 0x000003FFu;
+  return (int)v;
+}
+
+// Vertex range of level resolution N over brick coordinate q (of 2^k): the
+// cells of the points with floor(x 2^k) = q are min(floor(x (N-1)), N-2) in
+// [lo, hi], so the corners lie in [lo, hi + 1].
+__host__ __device__ __forceinline__ void brick_range(int N, int q, int k, int& lo, int& n) {
+  lo = (q * (N - 1)) >> k;
+  int hi = ((q + 1) * (N - 1)) >> k;
+  hi = hi < N - 2 ? hi : N - 2;
+  n = hi - lo + 2;
+}
+
+struct BrickBox {
+  int lo[3], n[3];
+};
+
+// e / d for 0 <= e < 2^22 and d >= 1, from a float reciprocal: the
+// product is within one of the quotient, which one step corrects.
+__device__ __forceinline__ int small_div(int e, int d, float inv) {
+  int q = (int)((float)e * inv);
+  const int r = e - q * d;
+  q += r >= d ? 1 : (r < 0 ? -1 : 0);
+  return q;
+}
+
+// Copy the vertices of level lv over brick (bq) into LDS dst[z][y][x][ED].
+template <int ED, typename TT>
+__device__ __forceinline__ void stage_box(const LevelDesc& lv, const TT* __restrict__ table, const BrickBox& bb,
+                                          uint32_t* __restrict__ dst) {
+  constexpr int U = 8;  // entries per thread per round: their loads are in flight together
+  const int nx = bb.n[0], nxy = bb.n[0] * bb.n[1], total = nxy * bb.n[2];
+  const float inx = 1.0f / (float)nx, inxy = 1.0f / (float)nxy;
+  const void* base = table;
+  for (int e0 = threadIdx.x; e0 < total; e0 += (int)blockDim.x * U) {
+    uint32_t d[U][ED];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * (int)blockDim.x;
+      const int ee = e < total ? e : 0;
+      const int iz = small_div(ee, nxy, inxy), rem = ee - iz * nxy, iy = small_div(rem, nx, inx), ix = rem - iy * nx;
+      const uint32_t slot = lv.offset + level_slot(lv, (uint32_t)(bb.lo[0] + ix), (uint32_t)(bb.lo[1] + iy),
+                                                   (uint32_t)(bb.lo[2] + iz));
+      load_entry<ED>(base, slot, d[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * (int)blockDim.x;
+      if (e < total) {
+#pragma unroll
+        for (int q = 0; q < ED; ++q) dst[e * ED + q] = d[u][q];
+      }
+    }
+  }
+}
+
+// F features of one level for a point, from the level's box in LDS.
+template <int F, typename TT>
+__device__ __forceinline__ void lookup_box(const LevelDesc& lv, const BrickBox& bb, const uint32_t* __restrict__ box,
+                                           float x, float y, float z, float acc[F]) {
+  constexpr int ED = Entry<F, TT>::ED;
+  Cell cl;
+  level_cell(lv, x, y, z, cl);
+  const int nx = bb.n[0], nxy = bb.n[0] * bb.n[1];
+  const int li = (cl.c[0] - bb.lo[0]) + nx * ((cl.c[1] - bb.lo[1]) + bb.n[1] * (cl.c[2] - bb.lo[2]));
+  float v[8][F];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int e = li + (k & 1) + ((k >> 1) & 1) * nx + ((k >> 2) & 1) * nxy;
+    uint32_t d[ED];
+#pragma unroll
+    for (int q = 0; q < ED; ++q) d[q] = box[e * ED + q];
+    entry_values<F, TT>(d, v[k]);
+  }
+#pragma unroll
+  for (int f = 0; f < F; ++f) acc[f] = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+#pragma unroll
+    for (int f = 0; f < F; ++f) acc[f] = __builtin_fmaf(cl.w[k], v[k][f], acc[f]);
+}
+
+template <int F, typename TT, typename OT>
+__global__ void __launch_bounds__(256) k_level_brick(ModelDesc md, const TT* __restrict__ table,
+                                                     const float4* __restrict__ rec, int64_t s0, int64_t m,
+                                                     OT* __restrict__ planes, uint32_t* __restrict__ idx,
+                                                     BrickArgs ba) {
+  constexpr int ED = Entry<F, TT>::ED;
+  extern __shared__ __align__(16) uint32_t lds[];
+  const int x = blockIdx.x & 7;
+  const int r = blockIdx.x >> 3;
+  const int nbx = (int)((gridDim.x - x + 7) >> 3);  // workgroups on this XCD
+  const uint32_t n_ent = (uint32_t)(md.n_table / F);
+  const int gw = ba.gw;
+  // the XCD's segment of the (pair, brick) items, pair-major
+  for (int it = ba.item_lo[x] + r; it < ba.item_lo[x + 1]; it += nbx) {
+    const int p = it / ba.n_bins, b = it - p * ba.n_bins;
+    const int la = ba.lev[p][0], lb = ba.lev[p][1];
+    const int64_t g0 = (int64_t)ba.bin_off[b], g1 = g0 + (int64_t)ba.bin_cnt[b];
+    const int64_t q0 = g0 - s0 > 0 ? g0 - s0 : 0, q1 = g1 - s0 < m ? g1 - s0 : m;
+    if (q0 >= q1) continue;  // uniform over the workgroup
+    const bool sa = ba.lds_off[p][0] >= 0, sb = lb >= 0 && ba.lds_off[p][1] >= 0;
+    const bool write_idx = la == 0;  // the pair holding level 0 also writes the queries' slots
+    const int bq[3] = {compact3((uint32_t)b), compact3((uint32_t)b >> 1), compact3((uint32_t)b >> 2)};
+    BrickBox bba, bbb;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      brick_range(md.lv[la].N, bq[a], ba.k, bba.lo[a], bba.n[a]);
+      brick_range(md.lv[lb >= 0 ? lb : la].N, bq[a], ba.k, bbb.lo[a], bbb.n[a]);
+    }
+    const uint32_t* box_a = lds + (sa ? ba.lds_off[p][0] / 4 : 0);
+    const uint32_t* box_b = lds + (sb ? ba.lds_off[p][1] / 4 : 0);
+    __syncthreads();  // the previous item's boxes are no longer read
+    if (sa) stage_box<ED>(md.lv[la], table, bba, lds + ba.lds_off[p][0] / 4);
+    if (sb) stage_box<ED>(md.lv[lb], table, bbb, lds + ba.lds_off[p][1] / 4);
+    __syncthreads();
+    for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
+      const float4 rr = rec[s0 + q];
+      const float px = clamp01(rr.x), py = clamp01(rr.y), pz = clamp01(rr.z);
+      if (write_idx) idx[q] = __float_as_uint(rr.w);
+      LevelPack<F, OT, 2> pk;
+      float acc[F];
+      if (sa) {
+        lookup_box<F, TT>(md.lv[la], bba, box_a, px, py, pz, acc);
+      } else {
+        Corners cr;
+        level_corners(md.lv[la], px, py, pz, cr);
+        gather_level<F>(cr, table, n_ent, acc);
+      }
+#pragma unroll
+      for (int f = 0; f < F; ++f) pk.v[f] = (OT)acc[f];
+      if (lb >= 0) {
+        if (sb) {
+          lookup_box<F, TT>(md.lv[lb], bbb, box_b, px, py, pz, acc);
+        } else {
+          Corners cr;
+          level_corners(md.lv[lb], px, py, pz, cr);
+          gather_level<F>(cr, table, n_ent, acc);
+        }
+#pragma unroll
+        for (int f = 0; f < F; ++f) pk.v[F + f] = (OT)acc[f];
+      } else {
+#pragma unroll
+        for (int f = 0; f < F; ++f) pk.v[F + f] = (OT)0.0f;  // padding slot of a short group
+      }
+      *reinterpret_cast<LevelPack<F, OT, 2>*>(planes + plane_elem(q, la, F, gw, m)) = pk;
+    }
+  }
+}
+
 // Plane order of the features: entry e = gw*F features of plane group x
 // (levels x, x+8, ... for L >= 8; level x for L < 8), feature p = x*E + i*F + f.
 struct PlaneOrder {
@@ -281,11 +449,82 @@ size_t split_planes_bytes(const ngvol_plan* plan, int64_t n) {
 }
 #endif
 
+// LDS a brick-staged workgroup may give to its levels' vertex boxes (four
+// workgroups per compute unit).
+constexpr size_t kBrickLds = 40 * 1024;
+
+// Brick-staged levels for plans of 8..16 levels (two levels of plane storage
+// per query) whose table entries are at most 8 bytes.  Pair p holds levels p
+// and p + 8; a level is staged when its largest box over a brick fits in what
+// the pair leaves of kBrickLds.  The (pair, brick) items, pair-major, are cut
+// into 8 contiguous segments of equal estimated cost, one per XCD, so that
+// the XCDs whose pairs are staged share the others' gathers (a staged level
+// costs about kStagedCost of a gathered one).  Returns false when the plan or
+// the workspace does not qualify; lds = bytes the launch needs.
+constexpr double kStagedCost = 0.15;
+
+static bool brick_args(const ngvol_plan* plan, BinRanges bins, int entry_bytes, BrickArgs& ba, size_t& lds) {
+  const ModelDesc& md = plan->md;
+  if (!bins.off || !bins.cnt || md.L < 8 || md.L > 16 || entry_bytes > 8) return false;
+  ba = BrickArgs{};
+  ba.bin_off = bins.off;
+  ba.bin_cnt = bins.cnt;
+  ba.k = bins.k;
+  ba.n_bins = 1 << (3 * bins.k);
+  ba.gw = 2;
+  lds = 0;
+  double cost[8];
+  for (int p = 0; p < 8; ++p) {
+    size_t used = 0;
+    cost[p] = 0.0;
+    for (int i = 0; i < 2; ++i) {
+      const int l = p + 8 * i;
+      ba.lev[p][i] = l < md.L ? l : -1;
+      ba.lds_off[p][i] = -1;
+      if (l >= md.L) continue;
+      int most = 0;
+      for (int q = 0; q < (1 << bins.k); ++q) {
+        int lo, n;
+        brick_range(md.lv[l].N, q, bins.k, lo, n);
+        most = n > most ? n : most;
+      }
+      const size_t bytes = ((size_t)most * most * most * entry_bytes + 15) & ~(size_t)15;
+      if (used + bytes <= kBrickLds) {
+        ba.lds_off[p][i] = (int)used;
+        used += bytes;
+        cost[p] += kStagedCost;
+      } else {
+        cost[p] += 1.0;
+      }
+    }
+    lds = used > lds ? used : lds;
+  }
+  // equal-cost segments of the pair-major item list
+  double total = 0.0;
+  for (int p = 0; p < 8; ++p) total += cost[p];
+  ba.item_lo[0] = 0;
+  int p = 0;
+  double before = 0.0;  // cost of the pairs before p
+  for (int x = 1; x < 8; ++x) {
+    const double target = total * x / 8.0;
+    while (p < 7 && before + cost[p] <= target) before += cost[p++];
+    const double frac = cost[p] > 0.0 ? (target - before) / cost[p] : 0.0;
+    int cut = p * ba.n_bins + (int)(frac * ba.n_bins + 0.5);
+    cut = cut < ba.item_lo[x - 1] ? ba.item_lo[x - 1] : cut;
+    ba.item_lo[x] = cut;
+  }
+  ba.item_lo[8] = 8 * ba.n_bins;
+  return true;
+}
+
 template <int P, int W>
 hipError_t launch_infer_split_p(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const float4* rec, int64_t n,
-                                float* out, void* planes, uint32_t* idx, hipStream_t st) {
+                                float* out, void* planes, uint32_t* idx, BinRanges bins, hipStream_t st) {
   const ModelDesc& md = plan->md;
   const SplitArgs sa = split_args(plan);
+  BrickArgs bk;
+  size_t brick_lds = 0;
+  const bool brick = brick_args(plan, bins, md.F * (tp.f16 ? 2 : 4), bk, brick_lds);
   const int64_t slab = split_slab(plan, n);
   const size_t lds = fwd_lds_bytes(plan);
   // plane order of the MLP's input columns
@@ -325,10 +564,28 @@ hipError_t launch_infer_split_p(const ngvol_plan* plan, TablePtrs tp, const floa
     NGV_DISPATCH_F_KIN(md.F, plan->kin, {
       typedef typename std::conditional<P == 0, float, typename Prec<P>::T>::type OT;
       OT* pl = reinterpret_cast<OT*>(planes);
-      if (tp.f16)
+      if (brick) {
+        // four workgroups per compute unit on each XCD
+        int64_t per = (int64_t)bk.n_bins;
+        const int64_t cap = (int64_t)plan->cus / 8 * 4;
+        if (per > cap) per = cap;
+        if (per < 1) per = 1;
+        const dim3 bgrid((unsigned)(8 * per));
+        if constexpr (F * 2 <= 8) {
+          if (tp.f16)
+            hipLaunchKernelGGL((k_level_brick<F, __half, OT>), bgrid, dim3(256), brick_lds, st, md, tp.f16, rec, s0,
+                               m, pl, idx, bk);
+        }
+        if constexpr (F * 4 <= 8) {
+          if (!tp.f16)
+            hipLaunchKernelGGL((k_level_brick<F, float, OT>), bgrid, dim3(256), brick_lds, st, md, tp.f32, rec, s0,
+                               m, pl, idx, bk);
+        }
+      } else if (tp.f16) {
         hipLaunchKernelGGL((k_level_feat<F, __half, OT>), lgrid, dim3(256), 0, st, md, tp.f16, r, m, pl, idx, sa);
-      else
+      } else {
         hipLaunchKernelGGL((k_level_feat<F, float, OT>), lgrid, dim3(256), 0, st, md, tp.f32, r, m, pl, idx, sa);
+      }
       const bool full = n_plane_feat >= KIN;
       if (E >= 8) {
         if (full) NGV_MP(0, true);
@@ -348,14 +605,16 @@ hipError_t launch_infer_split_p(const ngvol_plan* plan, TablePtrs tp, const floa
   return hipSuccess;
 }
 
-template hipError_t launch_infer_split_p<NGV_PSEL, NGV_WSEL>(const ngvol_plan*, TablePtrs, const float*, const float4*, int64_t,
-                                                   float*, void*, uint32_t*, hipStream_t);
+template hipError_t launch_infer_split_p<NGV_PSEL, NGV_WSEL>(const ngvol_plan*, TablePtrs, const float*,
+                                                             const float4*, int64_t, float*, void*, uint32_t*,
+                                                             BinRanges, hipStream_t);
 
 #if NGV_PRIMARY
 hipError_t launch_infer_split(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const float4* rec, int64_t n,
-                              float* out, void* planes, uint32_t* idx, hipStream_t st) {
+                              float* out, void* planes, uint32_t* idx, BinRanges bins, hipStream_t st) {
   NGV_DISPATCH_P(plan->layout.precision,
-                 NGV_DISPATCH_W(plan->md.width, return launch_infer_split_p<P, W>(plan, tp, mlp, rec, n, out, planes, idx, st)));
+                 NGV_DISPATCH_W(plan->md.width,
+                                return launch_infer_split_p<P, W>(plan, tp, mlp, rec, n, out, planes, idx, bins, st)));
   return hipErrorInvalidValue;
 }
 #endif

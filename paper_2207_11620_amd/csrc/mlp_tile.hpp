@@ -358,7 +358,6 @@ __device__ __forceinline__ void mlp_hidden_fwd_nb(int n_hidden, const typename P
   typedef typename Prec<P>::Frag Frag;
   constexpr int MB = W / 16;
   const int lane = threadIdx.x & 63;
-  const int nh = NHC > 0 ? NHC : n_hidden;
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb) {
     f32x4 acc[NB];
@@ -373,8 +372,7 @@ __device__ __forceinline__ void mlp_hidden_fwd_nb(int n_hidden, const typename P
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) act[nb][mb] = acc[nb];
   }
-#pragma unroll
-  for (int li = 1; li < nh; ++li) {
+  auto layer = [&](int li) {
     Frag b[NB][WL::CHH];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) pack_hidden<P, W>(act[nb], b[nb], true);
@@ -393,6 +391,12 @@ __device__ __forceinline__ void mlp_hidden_fwd_nb(int n_hidden, const typename P
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) act[nb][mb] = acc[nb];
     }
+  };
+  if constexpr (NHC > 0) {
+#pragma unroll
+    for (int li = 1; li < NHC; ++li) layer(li);
+  } else {
+    for (int li = 1; li < n_hidden; ++li) layer(li);
   }
 }
 
