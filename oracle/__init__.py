@@ -67,6 +67,10 @@ def lib():
             "orc_mc_opacity": (C.c_int, [P, P, i64, P, P]),
             "orc_render_pixels_mc": (C.c_int, [P, P, P, P, C.c_int, C.c_int, flt, u32, P, i64, P, C.c_int, P, P, P,
                                                P]),
+            "orc_adaptive_steps": (C.c_int, [flt, flt, C.c_int]),
+            "orc_mc_traverse": (C.c_int, [P, C.c_int, u32, flt, i64, P, C.c_int, C.c_int, P, P, i64, P]),
+            "orc_render_pixels_adaptive": (C.c_int, [P, P, P, P, C.c_int, C.c_int, flt, u32, P, i64, P, C.c_int, P,
+                                                     flt, C.c_int, P, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -304,6 +308,38 @@ def render_pixels_mc(m: Model, params, cam, lut, W, H, dt, frame_seed, pix, dims
     _chk(lib().orc_render_pixels_mc(_p(m.desc), _p(params), _p(cam), _p(lut), W, H, dt, frame_seed, _p(pix), n,
                                     _p(np.asarray(dims, np.int32)), cell, None if mu is None else _p(mu), _p(rgba),
                                     _p(n_geo), _p(n_used)))
+    return rgba, n_geo, n_used
+
+
+def adaptive_steps(mu, s2=64.0, p=2):
+    """Grid steps a sample in a cell of maximum opacity mu represents (binary32)."""
+    return int(lib().orc_adaptive_steps(mu, s2, int(p)))
+
+
+def mc_traverse(cam, W, frame_seed, dt, pix, dims, cell, dda=True, cap=1 << 16):
+    """(cells, first sample index in each) along a pixel's ray."""
+    cam = _f32(cam)
+    cells = np.zeros(cap, np.int64)
+    first = np.zeros(cap, np.uint32)
+    cnt = np.zeros(1, np.int64)
+    _chk(lib().orc_mc_traverse(_p(cam), W, frame_seed, dt, int(pix), _p(np.asarray(dims, np.int32)), cell,
+                               1 if dda else 0, _p(cells), _p(first), cap, _p(cnt)))
+    n = int(cnt[0])
+    return cells[:n].copy(), first[:n].copy()
+
+
+def render_pixels_adaptive(m: Model, params, cam, lut, W, H, dt, frame_seed, pix, dims, cell, mu, s2=64.0, p=2):
+    """Adaptive ray marching through macro-cells of maximum opacity mu (binary32)."""
+    params, cam, lut = _f64(params), _f32(cam), _f32(lut)
+    pix = np.ascontiguousarray(pix, dtype=np.int64)
+    n = pix.size
+    rgba = np.zeros((n, 4), np.float64)
+    n_geo = np.zeros(n, np.uint32)
+    n_used = np.zeros(n, np.uint32)
+    mu = _f32(mu)
+    _chk(lib().orc_render_pixels_adaptive(_p(m.desc), _p(params), _p(cam), _p(lut), W, H, dt, frame_seed, _p(pix), n,
+                                          _p(np.asarray(dims, np.int32)), cell, _p(mu), s2, int(p), _p(rgba),
+                                          _p(n_geo), _p(n_used)))
     return rgba, n_geo, n_used
 
 

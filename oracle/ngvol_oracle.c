@@ -854,6 +854,175 @@ int orc_render_pixels_mc(const int32_t* desc, const double* params, const float*
     return 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Adaptive ray marching through macro-cells (Section 5.3).                  */
+/*                                                                          */
+/* Reading: samples stay on the ray's grid t_k = t_near + (k + j) dt.  From  */
+/* sample k in cell c (the cell of its binary32 point):                      */
+/*   - mu(c) = 0: the cell is transparent and bypassed: k moves to the first */
+/*     sample outside c;                                                    */
+/*   - otherwise the sample is evaluated and represents m grid steps, where  */
+/*     m = min(n(mu), exit(c) - k, n_r - k), n(mu) = max(1, floor(sbar)) and */
+/*     sbar = max(s1 + (s2 - s1) |min(mu,1) - 1|^p, s1) with s1 = 1 grid     */
+/*     step (binary32, one rounding per operation, the power by repeated     */
+/*     multiplication, p a positive integer); its opacity is corrected to    */
+/*     1 - (1 - alpha)^m (alpha itself when m = 1), and k moves by m.        */
+/* exit(c), the first sample outside c, is found by a DDA step: the ray's    */
+/* exit from the cell's box, the grid index just past it, and an exact       */
+/* correction by testing the cells of the neighbouring samples.              */
+/* ------------------------------------------------------------------------ */
+int orc_adaptive_steps(float mu, float s2, int p)
+{
+    float m = mu < 1.0f ? mu : 1.0f;
+    float d = fabsf(m - 1.0f);
+    float pw = 1.0f;
+    for (int i = 0; i < p; ++i) pw = pw * d;
+    float t = (s2 - 1.0f) * pw;
+    float sb = 1.0f + t;
+    if (sb < 1.0f) sb = 1.0f;
+    return (int)floorf(sb);
+}
+
+static int64_t orc_ray_cell(const orc_ray* r, uint32_t k, float dt, const int32_t* dims, int cell)
+{
+    float pt[3];
+    orc_ray_point(r, k, dt, pt);
+    return orc_mc_index(pt, dims, cell);
+}
+
+/* first sample index > k outside the cell of sample k, by scanning */
+static uint32_t orc_cell_exit_scan(const orc_ray* r, uint32_t k, float dt, const int32_t* dims, int cell)
+{
+    int64_t c = orc_ray_cell(r, k, dt, dims, cell);
+    uint32_t q = k + 1;
+    while (q < r->n && orc_ray_cell(r, q, dt, dims, cell) == c) ++q;
+    return q;
+}
+
+/* the same by a DDA step: leave the cell's box along the ray, take the grid
+ * index past that parameter, and correct it on the samples' own cells */
+static uint32_t orc_cell_exit_dda(const orc_ray* r, uint32_t k, float dt, const int32_t* dims, int cell)
+{
+    float pt[3];
+    orc_ray_point(r, k, dt, pt);
+    int64_t c = orc_mc_index(pt, dims, cell);
+    float t_exit = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        if (r->d[a] == 0.0f) continue;
+        int64_t M = (dims[a] + cell - 1) / cell;
+        float q = (float)orc_clamp01f(pt[a]);
+        int64_t ca = (int64_t)floorf(q * (float)dims[a]) / cell;
+        if (ca > M - 1) ca = M - 1;
+        float bound;
+        if (r->d[a] > 0.0f) {
+            if (ca == M - 1) continue; /* the last cell reaches the cube's face */
+            bound = (float)((ca + 1) * cell) / (float)dims[a];
+        } else {
+            if (ca == 0) continue;
+            bound = (float)(ca * cell) / (float)dims[a];
+        }
+        float ta = (bound - r->o[a]) / r->d[a];
+        if (ta < t_exit) t_exit = ta;
+    }
+    uint32_t q;
+    if (!(t_exit < INFINITY)) {
+        q = r->n;
+    } else {
+        float g = ceilf((t_exit - r->t0) / dt - r->j);
+        q = g <= (float)(k + 1) ? k + 1 : (g >= (float)r->n ? r->n : (uint32_t)g);
+    }
+    while (q < r->n && orc_ray_cell(r, q, dt, dims, cell) == c) ++q;
+    while (q > k + 1 && orc_ray_cell(r, q - 1, dt, dims, cell) != c) --q;
+    return q;
+}
+
+/* the cells a pixel's ray visits and the first sample in each: by the DDA
+ * step (mode 1) or by scanning every sample (mode 0) */
+int orc_mc_traverse(const float* cam, int W, uint32_t frame_seed, float dt, int64_t pix, const int32_t* dims,
+                    int cell, int mode, int64_t* cells, uint32_t* first, int64_t cap, int64_t* count)
+{
+    orc_ray r = orc_make_ray(cam, W, (int)(pix % W), (int)(pix / W), frame_seed, dt);
+    int64_t n = 0;
+    uint32_t k = 0;
+    while (k < r.n) {
+        if (n >= cap) return -2;
+        cells[n] = orc_ray_cell(&r, k, dt, dims, cell);
+        first[n] = k;
+        ++n;
+        k = mode ? orc_cell_exit_dda(&r, k, dt, dims, cell) : orc_cell_exit_scan(&r, k, dt, dims, cell);
+    }
+    *count = n;
+    return 0;
+}
+
+/*
+ * Adaptive ray marching of the listed pixels through macro-cells of maximum
+ * opacity mu (binary32 values, as the renderer stores them): s2 the largest
+ * step in grid steps, p the exponent.  Outputs as orc_render_pixels; n_used
+ * counts evaluated samples up to termination.
+ */
+int orc_render_pixels_adaptive(const int32_t* desc, const double* params, const float* cam, const float* lut, int W,
+                               int H, float dt, uint32_t frame_seed, const int64_t* pix, int64_t n_pix,
+                               const int32_t* mc_dims, int mc_cell, const float* mu, float s2, int p, double* rgba,
+                               uint32_t* n_geo, uint32_t* n_used)
+{
+    orc_model m;
+    (void)H;
+    if (orc_model_from_desc(desc, &m) || m.width > 1024 || m.n_in > 1024 || p < 1 || p > 8 || !(s2 >= 1.0f))
+        return -1;
+    const double* Wm = params + m.n_table;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t q = 0; q < n_pix; ++q) {
+        int64_t px = pix[q];
+        orc_ray r = orc_make_ray(cam, W, (int)(px % W), (int)(px / W), frame_seed, dt);
+        double C[3] = {0.0, 0.0, 0.0}, A = 0.0;
+        uint32_t used = 0;
+        double e[1024];
+        uint32_t k = 0;
+        while (k < r.n) {
+            float pt[3];
+            orc_ray_point(&r, k, dt, pt);
+            float muc = mu[orc_mc_index(pt, mc_dims, mc_cell)];
+            if (!(muc > 0.0f)) {
+                k = orc_cell_exit_dda(&r, k, dt, mc_dims, mc_cell);
+                continue;
+            }
+            uint32_t steps = (uint32_t)orc_adaptive_steps(muc, s2, p);
+            uint32_t kn = k + 1;
+            if (steps > 1) {
+                uint32_t ke = orc_cell_exit_dda(&r, k, dt, mc_dims, mc_cell);
+                kn = k + steps < ke ? k + steps : ke;
+            }
+            if (kn > r.n) kn = r.n;
+            uint32_t span = kn - k;
+            orc_encode_one(&m, params, pt, e);
+            double v = orc_mlp_one(&m, Wm, e, NULL);
+            if (!(v > 0.0)) v = 0.0;
+            if (v > 1.0) v = 1.0;
+            double u = 255.0 * v;
+            double fi = floor(u);
+            if (fi > 254.0) fi = 254.0;
+            int i0 = (int)fi;
+            double f = u - fi;
+            double c4[4];
+            for (int ch = 0; ch < 4; ++ch)
+                c4[ch] = (double)lut[4 * i0 + ch] * (1.0 - f) + (double)lut[4 * (i0 + 1) + ch] * f;
+            double a = c4[3];
+            if (span > 1) a = 1.0 - pow(1.0 - a, (double)span); /* opacity of `span` grid steps */
+            for (int ch = 0; ch < 3; ++ch) C[ch] += (1.0 - A) * a * c4[ch];
+            A += (1.0 - A) * a;
+            used += 1;
+            if (A >= 0.99) break;
+            k = kn;
+        }
+        for (int ch = 0; ch < 3; ++ch) rgba[4 * q + ch] = C[ch];
+        rgba[4 * q + 3] = A;
+        n_geo[q] = r.n;
+        n_used[q] = used;
+    }
+    return 0;
+}
+
 int orc_render_pixels(const int32_t* desc, const double* params, const float* cam, const float* lut, int W, int H,
                       float dt, uint32_t frame_seed, const int64_t* pix, int64_t n_pix, double* rgba,
                       uint32_t* n_geo, uint32_t* n_used)

@@ -906,3 +906,105 @@ def test_train_loop_equals_composed_steps():
     flat, _, _ = oracle.train(m, params, vol, 5, 3, 200, 1e-2, 0.9, 0.99, 1e-15, step0=3, state=(am, av),
                               loss="l1", l2_reg=1e-3)
     assert np.max(np.abs(flat - got)) > 1e-4
+
+
+# ------------------------------------------- adaptive marching (Section 5.3) -----
+
+def test_adaptive_step_closed_form():
+    # sbar = max(1 + 63 |min(mu,1) - 1|^2, 1): 1 at mu >= 1, 64 at mu = 0
+    assert oracle.adaptive_steps(1.0) == 1 and oracle.adaptive_steps(3.5) == 1
+    assert oracle.adaptive_steps(0.0) == 64
+    assert oracle.adaptive_steps(0.5) == 16       # 1 + 63/4 = 16.75
+    assert oracle.adaptive_steps(0.5, p=1) == 32  # 1 + 63/2 = 32.5
+    assert oracle.adaptive_steps(0.75, s2=9.0) == 1  # 1 + 8/16 = 1.5
+    mus = np.linspace(0, 1.2, 241)
+    steps = [oracle.adaptive_steps(float(u)) for u in mus]
+    assert all(a >= b for a, b in zip(steps, steps[1:]))  # more opaque cells, smaller steps
+    for u, n in zip(mus, steps):
+        sb = max(1 + 63 * abs(min(u, 1) - 1) ** 2, 1)
+        assert n == math.floor(sb) or abs(sb - round(sb)) < 1e-5
+
+
+def _cells_by_scan(cam, W, seed, dt, pix, dims, cell):
+    """Cell of every sample of a pixel's ray, from the sample points."""
+    n = int(oracle.ray_counts(cam, W, max(1, pix // W + 1), seed, dt).ravel()[pix])
+    pts = oracle.ray_points(cam, W, 1, seed, dt, pix, 0, n)
+    return oracle.mc_cells(dims, cell, pts)
+
+
+@pytest.mark.parametrize("o,d", [((0.3, 0.6, -1.0), (0, 0, 1)), ((0.4, 0.55, 2.0), (0, 0, -1)),
+                                 ((-0.5, -0.5, -0.5), (1, 1, 1)), ((1.5, 1.4, 1.3), (-1, -1, -1)),
+                                 ((-0.2, 0.3, 0.1), (1, 0.35, 0.2))])
+def test_dda_traversal_equals_sample_scan(o, d):
+    dt, dims, cell = 2.0 ** -10, (64, 48, 80), 16
+    cam = np.array(list(o) + [0, 0, 0, 0, 0, 0] + list(d), np.float32)
+    for seed in (1, 2, 3):
+        lab = _cells_by_scan(cam, 1, seed, dt, 0, dims, cell)
+        assert lab.size > 0
+        starts = np.flatnonzero(np.r_[True, lab[1:] != lab[:-1]])
+        cells, first = oracle.mc_traverse(cam, 1, seed, dt, 0, dims, cell, dda=True)
+        np.testing.assert_array_equal(first, starts)
+        np.testing.assert_array_equal(cells, lab[starts])
+        c2, f2 = oracle.mc_traverse(cam, 1, seed, dt, 0, dims, cell, dda=False)
+        np.testing.assert_array_equal(c2, cells)
+        np.testing.assert_array_equal(f2, first)
+        assert len(set(cells.tolist())) == len(cells)  # a convex cell is entered once
+
+
+def test_dda_cell_sequence_on_an_axis_ray():
+    # +z through a 64^3 volume with 16-voxel cells: cells change at z = 1/4,
+    # 1/2, 3/4, i.e. at the first sample with (k + j) dt >= z - t_near
+    dt, dims, cell = 2.0 ** -10, (64, 64, 64), 16
+    cam = np.array([0.3, 0.6, -1.0, 0, 0, 0, 0, 0, 0, 0, 0, 1], np.float32)
+    for seed in range(4):
+        j = oracle.rng_u01(seed, 5, 0)
+        cells, first = oracle.mc_traverse(cam, 1, seed, dt, 0, dims, cell)
+        cx, cy = int(0.3 * 64) // 16, int(0.6 * 64) // 16
+        np.testing.assert_array_equal(cells, [(cz * 4 + cy) * 4 + cx for cz in range(4)])
+        np.testing.assert_array_equal(first, [0] + [math.ceil(z * 1024 - j) for z in (0.25, 0.5, 0.75)])
+
+
+def test_adaptive_render_at_full_opacity_is_the_fixed_step_render():
+    # mu >= 1 everywhere: one grid step per sample and no correction, so the
+    # image is the fixed-step one bit for bit
+    m = small_model(L=3, F=2, log2T=10, res=(5, 9, 17), width=16, n_hidden=2)
+    params = rand_params(m, seed=50, table_scale=0.5)
+    cam = np.array([0.5, 0.5, -1.5, 0.002, 0, 0, 0, 0.002, 0, -0.064, -0.064, 1.0], np.float32)
+    lut = np.random.default_rng(51).random((256, 4)).astype(np.float32) * 0.2
+    W = H = 48
+    pix = np.arange(W * H)
+    dims, cell = (64, 64, 64), 16
+    n = int(np.prod(oracle.mc_grid(dims, cell)))
+    plain = oracle.render_pixels(m, params, cam, lut, W, H, 1 / 64, 7, pix)
+    ad = oracle.render_pixels_adaptive(m, params, cam, lut, W, H, 1 / 64, 7, pix, dims, cell, np.full(n, 1.5))
+    for a, b in zip(plain, ad):
+        np.testing.assert_array_equal(a, b)
+    # every cell transparent: nothing is evaluated
+    none = oracle.render_pixels_adaptive(m, params, cam, lut, W, H, 1 / 64, 7, pix, dims, cell, np.zeros(n))
+    assert np.all(none[0] == 0) and np.all(none[2] == 0)
+    np.testing.assert_array_equal(none[1], plain[1])
+
+
+def test_adaptive_render_constant_alpha_closed_form():
+    # constant Phi (constant alpha a per grid step) through cells whose mu
+    # gives 16-step samples: the corrected opacities compose to the same
+    # 1 - (1 - a)^n as n single steps; samples = one per 16 steps, restarted
+    # at every cell boundary
+    m, params = _const_phi_model(0.25)
+    lut = np.zeros((256, 4), np.float32)
+    lut[:] = [0.3, 0.5, 0.7, 0.001]
+    dt, dims, cell = 2.0 ** -10, (64, 64, 64), 16
+    nc = int(np.prod(oracle.mc_grid(dims, cell)))
+    mu = np.full(nc, 0.5, np.float32)                   # 16 steps
+    assert oracle.adaptive_steps(0.5) == 16
+    cam = np.array([0.3, 0.6, -1.0, 0, 0, 0, 0, 0, 0, 0, 0, 1], np.float32)
+    rgba, ng, nu = oracle.render_pixels_adaptive(m, params, cam, lut, 2, 2, dt, 5, np.arange(4), dims, cell, mu)
+    a = float(np.float32(0.001))
+    assert np.all(ng == 1024)
+    np.testing.assert_allclose(rgba[:, 3], 1 - (1 - a) ** 1024, rtol=1e-12)
+    rgb = np.array([0.3, 0.5, 0.7], np.float32).astype(np.float64)  # the table's binary32 colour
+    np.testing.assert_allclose(rgba[:, :3], np.outer(np.full(4, 1 - (1 - a) ** 1024), rgb), rtol=1e-12)
+    for q in range(4):
+        cells, first = oracle.mc_traverse(cam, 2, 5, dt, q, dims, cell)
+        seg = np.diff(np.r_[first, 1024])
+        assert nu[q] == int(np.sum(np.ceil(seg / 16)))
