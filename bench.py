@@ -486,12 +486,12 @@ def main():
     del feat, ymlp
 
     # --------------------------------------------------------------- roofline
-    # The query pass (k_level_feat, then k_mlp_planes on the feature planes):
+    # The query pass (k_level_brick, then k_mlp_planes on the feature planes):
     # algorithmic bytes per query = L*8*F FP16 table reads + 12 B xyz + 4 B out.
     bytes_q = MODEL["n_levels"] * 8 * MODEL["n_features"] * 2 + 12 + 4
     achieved = bytes_q * N_QUERY / (infer_ms * 1e-3) / 1e9
     traffic, traffic_src = measured_traffic()
-    roofline = {"kernel": "query pass: k_level_feat + k_mlp_planes (bf16 MLP, fp16 tables)", "bound": "hbm",
+    roofline = {"kernel": "query pass: k_level_brick + k_mlp_planes (bf16 MLP, fp16 tables)", "bound": "hbm",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_source": traffic_src,
                 "bytes_per_query": bytes_q, "queries_per_launch": N_QUERY, "avg_launch_ms": round(infer_ms, 4)}

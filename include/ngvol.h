@@ -418,6 +418,35 @@ int ngvol_render(const ngvol_plan* plan, const ngvol_weights* w, const ngvol_cam
                  float* d_rgba, uint32_t* d_n_geo, uint32_t* d_n_used, ngvol_render_counters* d_counters,
                  void* d_workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* Rendering options of ngvol_render_ex. */
+#define NGVOL_RENDER_RM 0 /* emission-absorption ray marching (Section 5.2.1) */
+
+typedef struct ngvol_render_opts {
+    int32_t mode;     /* NGVOL_RENDER_RM */
+    /* Adaptive marching through the macro-cells (Section 5.3; needs mc with
+     * mu set).  Samples stay on the ray's grid t_k; from sample k in cell c
+     * of maximum opacity mu: mu = 0 bypasses the cell (k moves to the first
+     * sample outside it, found by a DDA step along the ray and an exact
+     * check of the neighbouring samples' cells); otherwise the sample is
+     * evaluated and stands for m = min(n(mu), exit(c) - k, n - k) grid steps
+     * with n(mu) = max(1, floor(max(1 + (step_max - 1) |min(mu,1) - 1|^p, 1)))
+     * in binary32 (the power by repeated multiplication), its opacity is
+     * corrected to 1 - (1 - alpha)^m (alpha itself for m = 1), and k moves
+     * by m.  0: fixed steps, with mc only skipping samples in transparent
+     * cells as ngvol_render does. */
+    int32_t adaptive;
+    float step_max;   /* s2 in grid steps, >= 1 (the paper uses 64) */
+    int32_t step_exp; /* p, 1..8 (the paper uses 2) */
+} ngvol_render_opts;
+
+/* ngvol_render with options (opts NULL: the defaults of ngvol_render, i.e.
+ * mode RM with fixed steps).  Counters and outputs as ngvol_render; n_used
+ * counts the samples composited (evaluated) up to termination. */
+int ngvol_render_ex(const ngvol_plan* plan, const ngvol_weights* w, const ngvol_camera* cam, const float* d_lut,
+                    int32_t width, int32_t height, float dt, uint32_t frame_seed, const ngvol_macrocells* mc,
+                    const ngvol_render_opts* opts, float* d_rgba, uint32_t* d_n_geo, uint32_t* d_n_used,
+                    ngvol_render_counters* d_counters, void* d_workspace, size_t workspace_bytes, hipStream_t stream);
+
 /* ----------------------------------------------------------------------- */
 /* Batches of independent neural volumes                                   */
 /* ----------------------------------------------------------------------- */

@@ -77,6 +77,10 @@ class Camera(C.Structure):
     _fields_ = [("origin", C.c_float * 3), ("du", C.c_float * 3), ("dv", C.c_float * 3), ("dir00", C.c_float * 3)]
 
 
+class RenderOpts(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("adaptive", C.c_int32), ("step_max", C.c_float), ("step_exp", C.c_int32)]
+
+
 _P = C.c_void_p
 _SIGS = {
     "ngvol_last_error": (C.c_char_p, []),
@@ -107,6 +111,8 @@ _SIGS = {
     "ngvol_render_workspace_bytes": (C.c_size_t, []),
     "ngvol_render": (C.c_int, [_P, C.POINTER(Weights), C.POINTER(Camera), _P, C.c_int32, C.c_int32, C.c_float,
                                C.c_uint32, _P, _P, _P, _P, _P, _P, C.c_size_t, _P]),
+    "ngvol_render_ex": (C.c_int, [_P, C.POINTER(Weights), C.POINTER(Camera), _P, C.c_int32, C.c_int32, C.c_float,
+                                  C.c_uint32, _P, C.POINTER(RenderOpts), _P, _P, _P, _P, _P, C.c_size_t, _P]),
     "ngvol_mc_reset": (C.c_int, [_P, _P]),
     "ngvol_mc_update": (C.c_int, [_P, _P, _P, C.c_int64, _P]),
     "ngvol_mc_opacity": (C.c_int, [_P, _P, _P]),
@@ -455,9 +461,11 @@ def psnr(plan, params, volume, table_f16=None, out=None):
 
 
 def render(plan, params, cam, lut, width, height, dt, frame_seed, table_f16=None, want_counts=True,
-           rgba=None, workspace=None, counters=None, macrocells=None):
+           rgba=None, workspace=None, counters=None, macrocells=None, adaptive=False, step_max=64.0, step_exp=2):
     """Returns (rgba [H][W][4], n_geo [H][W] or None, n_used or None, counters [4] int64).
-    macrocells (a MacroCells with opacities set): skip samples in empty cells."""
+    macrocells (a MacroCells with opacities set): skip samples in empty cells;
+    with adaptive=True also march with steps of up to step_max grid steps,
+    shortened by the cells' opacities with exponent step_exp (ngvol_render_ex)."""
     torch = _torch()
     dev = params.device
     if rgba is None:
@@ -473,9 +481,17 @@ def render(plan, params, cam, lut, width, height, dt, frame_seed, table_f16=None
                   (C.c_float * 3)(*c[9:12]))
     w = _weights(params, table_f16)
     mcp = C.byref(macrocells._c) if macrocells is not None else None
-    _check(lib().ngvol_render(plan.handle, C.byref(w), C.byref(camc), _ptr(lut), width, height, float(dt),
-                              frame_seed, mcp, _ptr(rgba), _ptr(n_geo), _ptr(n_used), _ptr(counters),
-                              _ptr(workspace), workspace.numel(), _stream()))
+    if adaptive:
+        if macrocells is None:
+            raise ValueError("adaptive marching needs macrocells")
+        opts = RenderOpts(0, 1, float(step_max), int(step_exp))
+        _check(lib().ngvol_render_ex(plan.handle, C.byref(w), C.byref(camc), _ptr(lut), width, height, float(dt),
+                                     frame_seed, mcp, C.byref(opts), _ptr(rgba), _ptr(n_geo), _ptr(n_used),
+                                     _ptr(counters), _ptr(workspace), workspace.numel(), _stream()))
+    else:
+        _check(lib().ngvol_render(plan.handle, C.byref(w), C.byref(camc), _ptr(lut), width, height, float(dt),
+                                  frame_seed, mcp, _ptr(rgba), _ptr(n_geo), _ptr(n_used), _ptr(counters),
+                                  _ptr(workspace), workspace.numel(), _stream()))
     return rgba, n_geo, n_used, counters
 
 

@@ -727,9 +727,10 @@ int ngvol_psnr(const ngvol_plan* plan, const ngvol_weights* w, const void* vol, 
 
 size_t ngvol_render_workspace_bytes(void) { return 256; }
 
-int ngvol_render(const ngvol_plan* plan, const ngvol_weights* w, const ngvol_camera* cam, const float* lut, int32_t W,
-                 int32_t H, float dt, uint32_t seed, const ngvol_macrocells* mc, float* rgba, uint32_t* n_geo,
-                 uint32_t* n_used, ngvol_render_counters* counters, void* ws, size_t ws_bytes, hipStream_t st) {
+int ngvol_render_ex(const ngvol_plan* plan, const ngvol_weights* w, const ngvol_camera* cam, const float* lut,
+                    int32_t W, int32_t H, float dt, uint32_t seed, const ngvol_macrocells* mc,
+                    const ngvol_render_opts* opts, float* rgba, uint32_t* n_geo, uint32_t* n_used,
+                    ngvol_render_counters* counters, void* ws, size_t ws_bytes, hipStream_t st) {
   if (int rc = check_plan(plan)) return rc;
   if (int rc = check_weights(w)) return rc;
   NGV_REQUIRE(cam && lut && rgba && ws, "camera, lut, rgba and workspace must be non-NULL");
@@ -740,6 +741,17 @@ int ngvol_render(const ngvol_plan* plan, const ngvol_weights* w, const ngvol_cam
   NGV_REQUIRE(dt >= 0x1p-20f && dt <= 1.0f, "dt must be in [2^-20, 1]");
   NGV_REQUIRE(ws_bytes >= ngvol_render_workspace_bytes(), "render workspace too small");
   RenderArgs ra{};
+  if (opts) {
+    NGV_REQUIRE(opts->mode == NGVOL_RENDER_RM, "unknown render mode %d", opts->mode);
+    if (opts->adaptive) {
+      NGV_REQUIRE(mc, "adaptive marching needs macro-cells");
+      NGV_REQUIRE(opts->step_max >= 1.0f && opts->step_max <= 65536.0f, "step_max must be in [1, 65536]");
+      NGV_REQUIRE(opts->step_exp >= 1 && opts->step_exp <= 8, "step_exp must be in [1, 8]");
+      ra.adaptive = 1;
+      ra.step_max = opts->step_max;
+      ra.step_exp = opts->step_exp;
+    }
+  }
   if (mc)
     if (int rc = resolve_mc(mc, ra.mc, false, true)) return rc;
   memcpy(ra.cam, cam, sizeof ra.cam);
@@ -754,6 +766,13 @@ int ngvol_render(const ngvol_plan* plan, const ngvol_weights* w, const ngvol_cam
   ra.queue = reinterpret_cast<unsigned int*>(ws);
   ra.counters = reinterpret_cast<unsigned long long*>(counters);
   return hip_check(launch_render(plan, tables_of(plan, w), w->params + plan->md.n_table, ra, st), "render launch", st);
+}
+
+int ngvol_render(const ngvol_plan* plan, const ngvol_weights* w, const ngvol_camera* cam, const float* lut, int32_t W,
+                 int32_t H, float dt, uint32_t seed, const ngvol_macrocells* mc, float* rgba, uint32_t* n_geo,
+                 uint32_t* n_used, ngvol_render_counters* counters, void* ws, size_t ws_bytes, hipStream_t st) {
+  return ngvol_render_ex(plan, w, cam, lut, W, H, dt, seed, mc, nullptr, rgba, n_geo, n_used, counters, ws, ws_bytes,
+                         st);
 }
 
 // ---------------------------------------------------------------------------

@@ -303,7 +303,10 @@ struct RenderArgs {
   uint32_t* n_used;
   unsigned long long* counters;  // [4] in the workspace or caller's struct
   unsigned int* queue;           // ray queue head
-  McGeom mc;                     // mc.mu set: empty-space skipping
+  McGeom mc;                     // mc.mu set: empty-space skipping, or adaptive marching
+  int32_t adaptive;              // with mc.mu: adaptive steps (Section 5.3) instead of skipping only
+  float step_max;                // largest step in grid steps (s2)
+  int32_t step_exp;              // exponent p of the step formula
 };
 hipError_t launch_mc_reset(const McGeom& g, hipStream_t st);
 hipError_t launch_mc_update(const McGeom& g, const float* xyz, const float* values, int64_t n, hipStream_t st);

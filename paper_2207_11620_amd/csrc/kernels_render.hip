@@ -81,6 +81,51 @@ __device__ __forceinline__ void ray_point(const RayGeom& r, uint32_t k, float dt
   z = __fadd_rn(r.o[2], __fmul_rn(t, r.d[2]));
 }
 
+__device__ __forceinline__ uint32_t sample_cell(const RayGeom& r, uint32_t k, float dt, const McGeom& g) {
+  float x, y, z;
+  ray_point(r, k, dt, x, y, z);
+  return mc_index(g, clamp01(x), clamp01(y), clamp01(z));
+}
+
+// First sample index after k outside the macro-cell of sample k: the ray's
+// exit from the cell's box (a DDA step), the grid index just past it, then
+// an exact correction on the samples' own cells (their cell indices change
+// monotonically along the ray, so the result is the first such sample).
+__device__ uint32_t cell_exit(const RayGeom& r, uint32_t k, float dt, const McGeom& g) {
+  float p[3];
+  ray_point(r, k, dt, p[0], p[1], p[2]);
+  const uint32_t c = mc_index(g, clamp01(p[0]), clamp01(p[1]), clamp01(p[2]));
+  float t_exit = INFINITY;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (r.d[a] == 0.0f) continue;
+    const int M = g.m[a];
+    const float q = clamp01(p[a]);
+    int ca = (int)floorf(__fmul_rn(q, (float)g.dims[a])) / g.cell;
+    ca = ca < M - 1 ? ca : M - 1;
+    float bound;
+    if (r.d[a] > 0.0f) {
+      if (ca == M - 1) continue;  // the last cell reaches the cube's face
+      bound = __fdiv_rn((float)((ca + 1) * g.cell), (float)g.dims[a]);
+    } else {
+      if (ca == 0) continue;
+      bound = __fdiv_rn((float)(ca * g.cell), (float)g.dims[a]);
+    }
+    const float ta = __fdiv_rn(__fsub_rn(bound, r.o[a]), r.d[a]);
+    t_exit = fminf(t_exit, ta);
+  }
+  uint32_t q;
+  if (!(t_exit < INFINITY)) {
+    q = r.n;
+  } else {
+    const float gq = ceilf(__fsub_rn(__fdiv_rn(__fsub_rn(t_exit, r.t0), dt), r.j));
+    q = gq <= (float)(k + 1) ? k + 1 : (gq >= (float)r.n ? r.n : (uint32_t)gq);
+  }
+  while (q < r.n && sample_cell(r, q, dt, g) == c) ++q;
+  while (q > k + 1 && sample_cell(r, q - 1, dt, g) != c) --q;
+  return q;
+}
+
 struct SlotState {
   RayGeom g;
   int32_t pix;  // -1: empty
@@ -89,10 +134,29 @@ struct SlotState {
   float C[3], A;
 };
 
-// Empty-space skipping, per slot: this round's samples (those in a non-empty
-// macro-cell), their count, and the first sample index after the round.
-constexpr int kList = kK + 2;
-constexpr int kCnt = kK, kNext = kK + 1;
+// Macro-cell modes, per slot: this round's samples (empty-space skipping:
+// those in a non-empty macro-cell; adaptive marching: the samples of the
+// adaptive walk), the grid steps each stands for (adaptive), their count,
+// and the first sample index after the round.
+constexpr int kSpan = kK;
+constexpr int kCnt = 2 * kK, kNext = 2 * kK + 1;
+constexpr int kList = 2 * kK + 2;
+
+// Macro-cell modes of the marcher.
+constexpr int kMcNone = 0, kMcSkip = 1, kMcAdaptive = 2;
+
+// Grid steps a sample in a cell of maximum opacity mu stands for (Section
+// 5.3): sbar = max(1 + (s2 - 1) |min(mu,1) - 1|^p, 1), floored; binary32,
+// one rounding per operation.
+__device__ __forceinline__ uint32_t adaptive_steps(float mu, float s2, int p) {
+  const float m = fminf(mu, 1.0f);
+  const float d = fabsf(__fsub_rn(m, 1.0f));
+  float pw = 1.0f;
+  for (int i = 0; i < p; ++i) pw = __fmul_rn(pw, d);
+  const float t = __fmul_rn(__fsub_rn(s2, 1.0f), pw);
+  const float sb = fmaxf(__fadd_rn(1.0f, t), 1.0f);
+  return (uint32_t)floorf(sb);
+}
 
 #if NGV_PRIMARY
 __global__ void k_render_init(unsigned int* queue, unsigned long long* counters) {
@@ -125,7 +189,7 @@ __host__ __device__ inline size_t render_stage_offset(size_t weight_bytes, size_
   return (end + 15) & ~(size_t)15;
 }
 
-template <int P, int F, int KIN, int W, typename TT, bool SKIP>
+template <int P, int F, int KIN, int W, typename TT, int MC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P != 0 && KIN == 32 ? 4 : 1)))
 k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs ra) {
   typedef typename Prec<P>::Frag Frag;
@@ -188,7 +252,8 @@ k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs r
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 
-  constexpr bool skip_empty = SKIP;  // ra.mc.mu is set
+  constexpr bool skip_empty = MC == kMcSkip;     // ra.mc.mu is set
+  constexpr bool adaptive = MC == kMcAdaptive;   // ra.mc.mu is set
   for (;;) {
     // any live slot in this wave?
     const bool live = lane < kSlots && slots[lane].pix >= 0;
@@ -224,14 +289,48 @@ k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs r
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       }
     }
-    // lane j evaluates sample k = slot.k + j%8 of slot j/8 (with skipping:
-    // the slot's (j%8)-th listed sample)
+    if constexpr (adaptive) {
+      // each slot's owner lane walks its ray: a transparent cell is passed
+      // whole, an opaque one gives a sample standing for adaptive_steps of
+      // the cell's mu grid steps (cut at the cell's exit)
+      if (lane < kSlots) {
+        const SlotState& so = slots[lane];
+        uint32_t k = so.k, cnt = 0;
+        const uint32_t n = so.g.n;
+        if (so.pix >= 0) {
+          while (cnt < (uint32_t)kK && k < n) {
+            const float mu = ra.mc.mu[sample_cell(so.g, k, ra.dt, ra.mc)];
+            if (!(mu > 0.0f)) {
+              k = cell_exit(so.g, k, ra.dt, ra.mc);
+              continue;
+            }
+            const uint32_t steps = adaptive_steps(mu, ra.step_max, ra.step_exp);
+            uint32_t kn = k + 1;
+            if (steps > 1) {
+              const uint32_t ke = cell_exit(so.g, k, ra.dt, ra.mc);
+              kn = k + steps < ke ? k + steps : ke;
+            }
+            kn = kn < n ? kn : n;
+            lst[lane * kList + cnt] = k;
+            lst[lane * kList + kSpan + cnt] = kn - k;
+            ++cnt;
+            k = kn;
+          }
+        }
+        lst[lane * kList + kCnt] = cnt;
+        lst[lane * kList + kNext] = k;
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+    // lane j evaluates sample k = slot.k + j%8 of slot j/8 (with skipping or
+    // adaptive marching: the slot's (j%8)-th listed sample)
     {
       const int si = lane >> 3, q = lane & 7;
       const SlotState& sl = slots[si];
       uint32_t k;
       bool valid;
-      if (skip_empty) {
+      if (skip_empty || adaptive) {
         valid = sl.pix >= 0 && (uint32_t)q < lst[si * kList + kCnt];
         k = valid ? lst[si * kList + q] : 0u;
       } else {
@@ -240,7 +339,7 @@ k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs r
       }
       // a round in which no ray of the wave has a sample outside empty
       // cells only advances the rays
-      if (!skip_empty || __any(valid)) {
+      if (!(skip_empty || adaptive) || __any(valid)) {
         float x = 0.5f, y = 0.5f, z = 0.5f;
         if (valid) {
           ray_point(sl.g, k, ra.dt, x, y, z);
@@ -260,8 +359,8 @@ k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs r
       SlotState sl = slots[lane];
       if (sl.pix >= 0) {
         bool done = false;
-        const uint32_t kend =
-            skip_empty ? lst[lane * kList + kCnt] : (sl.g.n - sl.k < (uint32_t)kK ? sl.g.n - sl.k : (uint32_t)kK);
+        const uint32_t kend = (skip_empty || adaptive) ? lst[lane * kList + kCnt]
+                                                       : (sl.g.n - sl.k < (uint32_t)kK ? sl.g.n - sl.k : (uint32_t)kK);
         for (uint32_t q = 0; q < kend; ++q) {
           const float val = fminf(fmaxf(yv[lane * kK + q], 0.0f), 1.0f);
           const float u = 255.0f * val;
@@ -272,7 +371,13 @@ k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs r
 #pragma unroll
           for (int ch = 0; ch < 4; ++ch) c4[ch] = __builtin_fmaf(fr, lds_lut[4 * (i0 + 1) + ch] - lds_lut[4 * i0 + ch],
                                                                    lds_lut[4 * i0 + ch]);
-          const float w = (1.0f - sl.A) * c4[3];
+          float a = c4[3];
+          if constexpr (adaptive) {
+            // opacity of a sample standing for `span` grid steps
+            const uint32_t span = lst[lane * kList + kSpan + q];
+            if (span > 1u) a = __fsub_rn(1.0f, powf(__fsub_rn(1.0f, a), (float)span));
+          }
+          const float w = (1.0f - sl.A) * a;
           sl.C[0] = __builtin_fmaf(w, c4[0], sl.C[0]);
           sl.C[1] = __builtin_fmaf(w, c4[1], sl.C[1]);
           sl.C[2] = __builtin_fmaf(w, c4[2], sl.C[2]);
@@ -283,7 +388,7 @@ k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs r
             break;
           }
         }
-        sl.k = skip_empty ? lst[lane * kList + kNext] : sl.k + kend;
+        sl.k = (skip_empty || adaptive) ? lst[lane * kList + kNext] : sl.k + kend;
         if (done || sl.k >= sl.g.n) {
           const int32_t p = sl.pix;
           float4* o4 = reinterpret_cast<float4*>(ra.rgba) + p;
@@ -330,20 +435,21 @@ hipError_t launch_render_p(const ngvol_plan* plan, TablePtrs tp, const float* ml
   const int64_t cap = (int64_t)plan->cus * 8;
   if (grid > cap) grid = cap;
   if (grid < 1) grid = 1;
-  const bool skip = ra.mc.mu != nullptr;
+#define NGV_RENDER_GO(TT, MCM)                                                                                    \
+  hipLaunchKernelGGL((k_render<P, F, KIN, W, TT, MCM>), dim3((unsigned)grid), dim3(256), lds, st, md, tp, mlp, ra)
   NGV_DISPATCH_F_KIN(md.F, plan->kin, {
+    const int mcm = ra.mc.mu == nullptr ? kMcNone : (ra.adaptive ? kMcAdaptive : kMcSkip);
     if (tp.f16) {
-      if (skip)
-        hipLaunchKernelGGL((k_render<P, F, KIN, W, __half, true>), dim3((unsigned)grid), dim3(256), lds, st, md, tp, mlp, ra);
-      else
-        hipLaunchKernelGGL((k_render<P, F, KIN, W, __half, false>), dim3((unsigned)grid), dim3(256), lds, st, md, tp, mlp, ra);
+      if (mcm == kMcNone) NGV_RENDER_GO(__half, kMcNone);
+      else if (mcm == kMcSkip) NGV_RENDER_GO(__half, kMcSkip);
+      else NGV_RENDER_GO(__half, kMcAdaptive);
     } else {
-      if (skip)
-        hipLaunchKernelGGL((k_render<P, F, KIN, W, float, true>), dim3((unsigned)grid), dim3(256), lds, st, md, tp, mlp, ra);
-      else
-        hipLaunchKernelGGL((k_render<P, F, KIN, W, float, false>), dim3((unsigned)grid), dim3(256), lds, st, md, tp, mlp, ra);
+      if (mcm == kMcNone) NGV_RENDER_GO(float, kMcNone);
+      else if (mcm == kMcSkip) NGV_RENDER_GO(float, kMcSkip);
+      else NGV_RENDER_GO(float, kMcAdaptive);
     }
   });
+#undef NGV_RENDER_GO
   return hipGetLastError();
 }
 

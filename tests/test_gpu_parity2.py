@@ -4,6 +4,8 @@ trained-model BF16 bound, the device PSNR and graph-replayed training after a
 skipped step.  Same bars as test_gpu_parity.py: FP32 outputs <= 1e-5, FP32
 gradients <= 1e-4 (normwise, per block), BF16-MFMA outputs <= 2e-2 absolute.
 """
+import functools
+
 import numpy as np
 import pytest
 
@@ -103,6 +105,7 @@ def test_output_relu_autograd_function():
 
 # --------------------------------------- the benchmark's render config -----
 
+@functools.lru_cache(maxsize=1)
 def _render_model():
     # the query model (16 levels, 2^19, 32-64-64-1) fitted for 30 steps by the
     # oracle to a fractal-noise target, so the transfer function sees real values
@@ -150,6 +153,87 @@ def test_render_bench_configuration_matches_oracle(skip):
     assert np.all(same | (np.abs(ro[:, 3] - 0.99) < 2e-2))
     assert np.max(np.abs(img[pix][same] - ro[same])) <= 2e-2
     assert host(cnt)[1] == nu.sum()
+
+
+@pytest.mark.parametrize("prec,s2,pexp", [("fp32", 64.0, 2), ("bf16", 64.0, 2), ("fp32", 16.0, 1), ("fp32", 200.0, 5)])
+def test_render_adaptive_matches_oracle(prec, s2, pexp):
+    # adaptive marching through macro-cells of known binary32 opacities (the
+    # oracle's, copied to the device): the walk is integer work (cell
+    # indices, step counts, DDA exits), so the evaluated-sample counts agree
+    # exactly except where termination at A = 0.99 is a rounding tie
+    m, params, vol = _render_model()
+    p = gpu_plan("cfg1", prec)
+    pt = dev(params)
+    W = H = 192
+    cam = synth.orbit_camera(0.9, W, H)
+    lut = synth.transfer_function_lut().copy()
+    lut[:103, 3] = 0.0
+    dt = 2.0 ** -9
+    dims, cell = (48, 48, 48), 8
+    xyz = oracle.batch_coords(SEED, 0, 1 << 16)
+    y = oracle.sample_volume(vol, xyz).astype(np.float32)
+    mu_o = oracle.mc_opacity(oracle.mc_update(dims, cell, xyz, y), lut).astype(np.float32)
+    assert np.any(mu_o == 0) and np.any((mu_o > 0) & (mu_o < 0.9))
+    mc = ngv.MacroCells(dims, cell)
+    mc.mu.copy_(dev(mu_o))
+    rgba, n_geo, n_used, cnt = ngv.render(p, pt, cam, dev(lut), W, H, dt, 5, macrocells=mc, adaptive=True,
+                                          step_max=s2, step_exp=pexp)
+    _, _, nu_skip, cnt_skip = ngv.render(p, pt, cam, dev(lut), W, H, dt, 5, macrocells=mc)
+    np.testing.assert_array_equal(host(n_geo).astype(np.uint32), oracle.ray_counts(cam, W, H, 5, dt))
+    img, nu = host(rgba).reshape(-1, 4), host(n_used).ravel()
+    c, cs = host(cnt), host(cnt_skip)
+    print(f"evaluated: adaptive {c[0]}, skipping only {cs[0]}")
+    assert c[0] < cs[0]
+    assert c[1] == nu.sum()
+    hit = np.flatnonzero(host(n_geo).ravel() > 0)
+    pix = np.random.default_rng(4).choice(hit, 300, replace=False)
+    ro, _, nuo = oracle.render_pixels_adaptive(m, params.astype(np.float64), cam, lut, W, H, dt, 5, pix, dims, cell,
+                                               mu_o, s2, pexp)
+    same = nu[pix] == nuo
+    assert np.mean(same) > 0.9
+    assert np.all(same | (np.abs(ro[:, 3] - 0.99) < 2e-2))
+    tol = 1e-4 if prec == "fp32" else 2e-2
+    assert np.max(np.abs(img[pix][same] - ro[same])) <= tol
+
+
+def test_render_adaptive_degenerate_grids():
+    # opacity >= 1 everywhere, or s2 = 1: every step is one grid step, so the
+    # adaptive walk evaluates exactly the samples of the fixed-step marcher
+    # (with the same skipping) and the images agree bit for bit
+    m, params, vol = _render_model()
+    p = gpu_plan("cfg1", "fp32")
+    pt = dev(params)
+    W, H = 128, 96
+    cam = synth.orbit_camera(0.3, W, H)
+    lut = dev(synth.transfer_function_lut())
+    dt = 2.0 ** -8
+    mc = ngv.MacroCells((48, 48, 48), 8)
+    mc.mu.fill_(1.0)
+    a, _, na, _ = ngv.render(p, pt, cam, lut, W, H, dt, 3, macrocells=mc, adaptive=True)
+    b, _, nb, _ = ngv.render(p, pt, cam, lut, W, H, dt, 3)
+    np.testing.assert_array_equal(host(a), host(b))
+    np.testing.assert_array_equal(host(na), host(nb))
+    g = np.random.default_rng(5).random(mc.mu.numel()).astype(np.float32)
+    g[g < 0.3] = 0.0
+    mc.mu.copy_(dev(g))
+    a, _, na, _ = ngv.render(p, pt, cam, lut, W, H, dt, 3, macrocells=mc, adaptive=True, step_max=1.0)
+    b, _, nb, _ = ngv.render(p, pt, cam, lut, W, H, dt, 3, macrocells=mc)
+    np.testing.assert_array_equal(host(a), host(b))
+    np.testing.assert_array_equal(host(na), host(nb))
+
+
+def test_render_ex_rejects_bad_options():
+    m, params, vol = _render_model()
+    p = gpu_plan("cfg1", "fp32")
+    pt = dev(params)
+    lut = dev(synth.transfer_function_lut())
+    cam = synth.orbit_camera(0.3, 32, 32)
+    mc = ngv.MacroCells((48, 48, 48), 8)
+    with pytest.raises(ValueError):
+        ngv.render(p, pt, cam, lut, 32, 32, 2.0 ** -8, 3, adaptive=True)
+    for kw in ({"step_max": 0.5}, {"step_exp": 0}, {"step_exp": 9}):
+        with pytest.raises(RuntimeError):
+            ngv.render(p, pt, cam, lut, 32, 32, 2.0 ** -8, 3, macrocells=mc, adaptive=True, **kw)
 
 
 # -------------------------------------------- 16 models in one graph -----
