@@ -297,7 +297,7 @@ def main():
         cams = [synth.orbit_camera(2 * math.pi * f / max(args.render_frames, 1), W, H)
                 for f in range(args.render_frames + 1)]
 
-        def frames(mc):
+        def frames(mc, adaptive=False):
             # with macro-cells: their value ranges grow from each frame's
             # training samples (online construction), the opacities follow,
             # and the marcher skips samples in empty cells
@@ -307,7 +307,7 @@ def main():
                                macrocells=mc, **ADAM)
                 mc.opacity(lut)
             ngv.render(plan16, online.params, cams[0], lut, W, H, dt, 0, table_f16=online.table_f16,
-                       want_counts=False, rgba=rgba, workspace=rws, counters=cnt, macrocells=mc)
+                       want_counts=False, rgba=rgba, workspace=rws, counters=cnt, macrocells=mc, adaptive=adaptive)
             torch.cuda.synchronize()
             ev_r = [(ev(), ev(), ev()) for _ in range(args.render_frames)]
             evals = used = 0
@@ -319,7 +319,8 @@ def main():
                     mc.opacity(lut)
                 ev_r[f][1].record()
                 ngv.render(plan16, online.params, cams[f + 1], lut, W, H, dt, f + 1, table_f16=online.table_f16,
-                           want_counts=False, rgba=rgba, workspace=rws, counters=cnt, macrocells=mc)
+                           want_counts=False, rgba=rgba, workspace=rws, counters=cnt, macrocells=mc,
+                           adaptive=adaptive)
                 ev_r[f][2].record()
                 torch.cuda.synchronize()
                 c = cnt.cpu().numpy()
@@ -345,6 +346,14 @@ def main():
                                 "empty_cells": int((mc.mu == 0).sum().item()), "cells": int(mc.mu.numel())}
         log(f"render with macro-cells: {r_mc['fps']:.2f} fps, {r_mc['network_samples_per_frame']:.3e} network "
             f"samples per frame ({render['macrocells']['empty_cells']} of {mc.mu.numel()} cells empty)")
+        # adaptive marching (steps of up to 64 grid steps, exponent 2)
+        mc.reset()
+        r_ad = frames(mc, adaptive=True)
+        render["adaptive"] = {"cell": 64, "step_max": 64, "step_exp": 2, "fps": r_ad["fps"],
+                              "render_ms_per_frame": r_ad["render_ms_per_frame"],
+                              "network_samples_per_frame": r_ad["network_samples_per_frame"]}
+        log(f"render with adaptive marching: {r_ad['fps']:.2f} fps, {r_ad['network_samples_per_frame']:.3e} network "
+            f"samples per frame")
         rs = mc = None
         # a sparse target: Gaussian blobs (256^3, FP32), the query network
         # trained 300 steps with 16^3-voxel macro-cells built online (the
@@ -362,16 +371,22 @@ def main():
         mcb.opacity(lut_s)
         sparse = {"volume": "256^3 gaussian blobs", "cell": 16, "cells": int(mcb.mu.numel()),
                   "empty_cells": int((mcb.mu == 0).sum().item())}
-        for name, m_ in (("plain", None), ("macrocells", mcb)):
+        ref_img = None
+        for name, m_, ad in (("plain", None, False), ("macrocells", mcb, False), ("adaptive", mcb, True)):
             ngv.render(plan16, sb.params, cams[0], lut_s, W, H, dt, 0, table_f16=sb.table_f16, want_counts=False,
-                       rgba=rgba, workspace=rws, counters=cnt, macrocells=m_)
+                       rgba=rgba, workspace=rws, counters=cnt, macrocells=m_, adaptive=ad)
+            if ref_img is None:
+                ref_img = rgba.clone()
+            else:  # the frame's difference from fixed-step marching, RGB in [0, 1]
+                mse = float(((rgba[..., :3] - ref_img[..., :3]) ** 2).double().mean().item())
+                sparse[f"{name}_image_psnr_db_vs_plain"] = round(-10 * math.log10(mse), 2) if mse > 0 else None
             e = [ev() for _ in range(2)]
             torch.cuda.synchronize()
             e[0].record()
             n_ev = 0
             for f in range(3):
                 ngv.render(plan16, sb.params, cams[f + 1], lut_s, W, H, dt, f + 1, table_f16=sb.table_f16,
-                           want_counts=False, rgba=rgba, workspace=rws, counters=cnt, macrocells=m_)
+                           want_counts=False, rgba=rgba, workspace=rws, counters=cnt, macrocells=m_, adaptive=ad)
                 torch.cuda.synchronize()
                 n_ev += int(cnt.cpu().numpy()[0])
             e[1].record()
@@ -382,7 +397,9 @@ def main():
         render["sparse"] = sparse
         log(f"sparse render: {sparse['plain_render_ms']:.2f} ms plain, {sparse['macrocells_render_ms']:.2f} ms with "
             f"macro-cells ({sparse['empty_cells']} of {sparse['cells']} cells empty; samples "
-            f"{sparse['plain_network_samples_per_frame']:.3e} -> {sparse['macrocells_network_samples_per_frame']:.3e})")
+            f"{sparse['plain_network_samples_per_frame']:.3e} -> {sparse['macrocells_network_samples_per_frame']:.3e}); "
+            f"adaptive {sparse['adaptive_render_ms']:.2f} ms, {sparse['adaptive_network_samples_per_frame']:.3e} "
+            f"samples")
         bv = sb = mcb = None
 
     # -------------------------------------------------- batched multi-volume
