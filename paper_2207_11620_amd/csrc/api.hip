@@ -15,6 +15,7 @@
 #include <string>
 
 #include "kernels.hpp"
+#include "render.hpp"
 
 using namespace ngvol;
 

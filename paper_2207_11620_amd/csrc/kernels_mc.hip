@@ -3,6 +3,7 @@
 // marcher uses to skip empty space.
 #include "device_common.hpp"
 #include "kernels.hpp"
+#include "render.hpp"
 
 namespace ngvol {
 

@@ -16,6 +16,7 @@
 // steal from the other bands once their own is empty.
 // build: one object per MLP precision and width (NGV_PSEL, NGV_WSEL)
 #include "kernels.hpp"
+#include "render.hpp"
 #include "dispatch.hpp"
 #include "mlp_tile.hpp"
 
