@@ -71,6 +71,10 @@ def lib():
             "orc_mc_traverse": (C.c_int, [P, C.c_int, u32, flt, i64, P, C.c_int, C.c_int, P, P, i64, P]),
             "orc_render_pixels_adaptive": (C.c_int, [P, P, P, P, C.c_int, C.c_int, flt, u32, P, i64, P, C.c_int, P,
                                                      flt, C.c_int, P, P, P]),
+            "orc_render_pixels_shadow": (C.c_int, [P, P, P, P, C.c_int, C.c_int, flt, u32, P, i64, P, C.c_int, P, P,
+                                                   P, P, P, P]),
+            "orc_render_pixels_pt": (C.c_int, [P, P, P, P, C.c_int, C.c_int, u32, P, i64, P, C.c_int, P, P, P, P, P,
+                                               P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -345,3 +349,40 @@ def render_pixels_adaptive(m: Model, params, cam, lut, W, H, dt, frame_seed, pix
 
 def num_threads():
     return int(lib().orc_num_threads())
+
+
+def render_pixels_shadow(m: Model, params, cam, lut, W, H, dt, frame_seed, pix, light, dims=(1, 1, 1), cell=1,
+                         mu=None):
+    """Ray marching with a single-shot shadow from the sample of highest
+    contribution towards the light; returns (rgba, n_geo, n_used, kstar)."""
+    params, cam, lut = _f64(params), _f32(cam), _f32(lut)
+    pix = np.ascontiguousarray(pix, dtype=np.int64)
+    n = pix.size
+    rgba = np.zeros((n, 4), np.float64)
+    n_geo = np.zeros(n, np.uint32)
+    n_used = np.zeros(n, np.uint32)
+    kstar = np.zeros(n, np.uint32)
+    mu = None if mu is None else _f64(mu)
+    _chk(lib().orc_render_pixels_shadow(_p(m.desc), _p(params), _p(cam), _p(lut), W, H, dt, frame_seed, _p(pix), n,
+                                        _p(np.asarray(dims, np.int32)), cell, None if mu is None else _p(mu), _p(_f32(light)), _p(rgba),
+                                        _p(n_geo), _p(n_used), _p(kstar)))
+    return rgba, n_geo, n_used, kstar
+
+
+def render_pixels_pt(m: Model, params, cam, lut, W, H, frame_seed, pix, density, light, radiance, background,
+                     spp=1, rr_depth=4, max_depth=1024, dims=(1, 1, 1), cell=1, mu=None):
+    """Path tracing with Woodcock tracking and shadow rays (macro-cell
+    majorants when mu is given, binary32); returns (rgba, n_real, n_samples)."""
+    params, cam, lut = _f64(params), _f32(cam), _f32(lut)
+    pix = np.ascontiguousarray(pix, dtype=np.int64)
+    n = pix.size
+    rgba = np.zeros((n, 4), np.float64)
+    n_real = np.zeros(n, np.uint32)
+    n_samp = np.zeros(n, np.uint32)
+    fo = np.array([density, *light, *radiance, *background], np.float32)
+    io = np.array([spp, rr_depth, max_depth], np.int32)
+    mu = None if mu is None else _f32(mu)
+    _chk(lib().orc_render_pixels_pt(_p(m.desc), _p(params), _p(cam), _p(lut), W, H, frame_seed, _p(pix), n,
+                                    _p(np.asarray(dims, np.int32)), cell, None if mu is None else _p(mu), _p(fo), _p(io), _p(rgba),
+                                    _p(n_real), _p(n_samp)))
+    return rgba, n_real, n_samp

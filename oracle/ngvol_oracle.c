@@ -1031,6 +1031,403 @@ int orc_render_pixels(const int32_t* desc, const double* params, const float* ca
                                 n_geo, n_used);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Shared pieces of the shadow ray marcher and the path tracer.              */
+/* ------------------------------------------------------------------------ */
+
+/* v / |v| in binary32, |v| formed as the camera rule forms it */
+static void orc_unit3(const float v[3], float out[3])
+{
+    float q0 = v[0] * v[0], q1 = v[1] * v[1], q2 = v[2] * v[2];
+    float nrm = sqrtf((q0 + q1) + q2);
+    for (int a = 0; a < 3; ++a) out[a] = v[a] / nrm;
+}
+
+/* slab test of o + t d against [0,1]^3 (binary32): t_near = max(t_min, 0) */
+static void orc_slab(const float o[3], const float d[3], float* tn, float* tf)
+{
+    float tmin = -INFINITY, tmax = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        float inv = 1.0f / d[a];
+        float ta = (0.0f - o[a]) * inv;
+        float tb = (1.0f - o[a]) * inv;
+        tmin = fmaxf(tmin, fminf(ta, tb));
+        tmax = fminf(tmax, fmaxf(ta, tb));
+    }
+    *tn = fmaxf(tmin, 0.0f);
+    *tf = tmax;
+}
+
+/* Ray from o along the unit direction d with jitter j, sample count by the
+ * camera rays' rule: n = max(0, ceil((t_far - t_near)/dt - j)) */
+static orc_ray orc_ray_from(const float o[3], const float d[3], float j, float dt)
+{
+    orc_ray r;
+    float tn, tf;
+    orc_slab(o, d, &tn, &tf);
+    for (int a = 0; a < 3; ++a) {
+        r.o[a] = o[a];
+        r.d[a] = d[a];
+    }
+    r.t0 = tn;
+    r.j = j;
+    r.n = 0;
+    if (tn < tf) {
+        float q = (tf - tn) / dt;
+        if (q <= 16777216.0f) {
+            float c = ceilf(q - j);
+            if (c > 0.0f) r.n = (uint32_t)c;
+        }
+    }
+    return r;
+}
+
+/* transfer function at the network value phi: rgba by the linear blend of
+ * the ray marcher (FP64) */
+static void orc_tf(const float* lut, double phi, double c4[4])
+{
+    double v = phi > 0.0 ? (phi < 1.0 ? phi : 1.0) : 0.0;
+    double u = 255.0 * v;
+    double fi = floor(u);
+    if (fi > 254.0) fi = 254.0;
+    int i0 = (int)fi;
+    double f = u - fi;
+    for (int ch = 0; ch < 4; ++ch) c4[ch] = (double)lut[4 * i0 + ch] * (1.0 - f) + (double)lut[4 * (i0 + 1) + ch] * f;
+}
+
+/*
+ * Ray marching with a single-shot heuristic shadow (Section 5.2; Brownlee et
+ * al.: only the point of highest contribution is shaded).
+ *
+ * Reading: the primary ray is marched and composited as orc_render_pixels_mc
+ * (with mu != NULL, samples in cells of mu = 0 skipped).  Its sample of
+ * largest contribution w_k = (1 - A_{k-1}) alpha_k (the first one on ties;
+ * none when every w_k is 0) is the shading point p*, its binary32 sample
+ * position.  A shadow ray leaves p* along the unit light direction l (binary32,
+ * l / |l|) with the pixel's jitter j and the primary rays' count rule; its
+ * samples t_k = t_near + (k + j) dt for k >= 1 (k = 0, next to p* itself, is
+ * left out), with the same skipping, give the transmittance
+ * T = prod (1 - alpha_k), ending after the sample at which T <= 0.01.  The
+ * pixel is (T C, A): T attenuates the whole primary colour.
+ * kstar[q] is the index k of p* (UINT32_MAX when there is none).
+ */
+int orc_render_pixels_shadow(const int32_t* desc, const double* params, const float* cam, const float* lut, int W,
+                             int H, float dt, uint32_t frame_seed, const int64_t* pix, int64_t n_pix,
+                             const int32_t* mc_dims, int mc_cell, const double* mu, const float* light, double* rgba,
+                             uint32_t* n_geo, uint32_t* n_used, uint32_t* kstar)
+{
+    orc_model m;
+    (void)H;
+    if (orc_model_from_desc(desc, &m) || m.width > 1024 || m.n_in > 1024) return -1;
+    const double* Wm = params + m.n_table;
+    float l[3];
+    orc_unit3(light, l);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t q = 0; q < n_pix; ++q) {
+        int64_t p = pix[q];
+        orc_ray r = orc_make_ray(cam, W, (int)(p % W), (int)(p / W), frame_seed, dt);
+        double C[3] = {0.0, 0.0, 0.0}, A = 0.0, wbest = 0.0;
+        int64_t best = -1;
+        uint32_t used = 0;
+        double e[1024], c4[4];
+        for (uint32_t k = 0; k < r.n; ++k) {
+            float pt[3];
+            orc_ray_point(&r, k, dt, pt);
+            if (mu && !(mu[orc_mc_index(pt, mc_dims, mc_cell)] > 0.0)) continue;
+            orc_encode_one(&m, params, pt, e);
+            orc_tf(lut, orc_mlp_one(&m, Wm, e, NULL), c4);
+            double w = (1.0 - A) * c4[3];
+            if (w > wbest) {
+                wbest = w;
+                best = k;
+            }
+            for (int ch = 0; ch < 3; ++ch) C[ch] += w * c4[ch];
+            A += w;
+            used += 1;
+            if (A >= 0.99) break;
+        }
+        double T = 1.0;
+        if (best >= 0) {
+            float ps[3];
+            orc_ray_point(&r, (uint32_t)best, dt, ps);
+            orc_ray s = orc_ray_from(ps, l, r.j, dt);
+            for (uint32_t k = 1; k < s.n; ++k) {
+                float pt[3];
+                orc_ray_point(&s, k, dt, pt);
+                if (mu && !(mu[orc_mc_index(pt, mc_dims, mc_cell)] > 0.0)) continue;
+                orc_encode_one(&m, params, pt, e);
+                orc_tf(lut, orc_mlp_one(&m, Wm, e, NULL), c4);
+                T *= 1.0 - c4[3];
+                if (T <= 0.01) break;
+            }
+        }
+        for (int ch = 0; ch < 3; ++ch) rgba[4 * q + ch] = T * C[ch];
+        rgba[4 * q + 3] = A;
+        n_geo[q] = r.n;
+        n_used[q] = used;
+        kstar[q] = best >= 0 ? (uint32_t)best : UINT32_MAX;
+    }
+    return 0;
+}
+
+/*
+ * Volumetric path tracing with Woodcock tracking (Section 5.2.2, Algorithm 1)
+ * and next-event estimation by shadow rays, with macro-cell majorants walked
+ * by optical thickness (Section 5.3, Eqs. 1 and 2; Hofmann et al.).
+ *
+ * Readings (the paper gives the structure, not the estimator):
+ *   - medium: extinction sigma(x) = density * alpha(phi(x)) and albedo
+ *     rgb(phi(x)), both from the transfer function as the ray marcher reads
+ *     it (phi clamped to [0,1], linear blend); the phase function is
+ *     isotropic, sampled exactly, so a scattering event multiplies the
+ *     throughput by the albedo;
+ *   - majorant: density * mu(c) in macro-cell c (mu the cells' opacities, as
+ *     binary32); without macro-cells density * max_i alpha_i over the table,
+ *     for the whole cube;
+ *   - a directional light of radiance E along the unit direction l (binary32,
+ *     l / |l|, pointing towards the light) and a background radiance B for
+ *     rays that leave the cube;
+ *   - the path state machine of the paper's listing: a scattering ray that
+ *     meets a real collision becomes a shadow ray from that point towards
+ *     the light; a shadow ray that leaves the cube adds beta E / (4 pi) (the
+ *     isotropic phase value), one that meets a real collision adds nothing;
+ *     either way the path then continues as a scattering ray from the same
+ *     point in a new direction; a scattering ray that leaves the cube adds
+ *     beta B and ends the path;
+ *   - Russian roulette at the real collisions of scattering rays after the
+ *     first rr_depth of them: survive with q = min(1, max_c beta_c), then
+ *     beta /= q; the path also ends after max_depth such collisions (once
+ *     their shadow ray is done) and after 2^16 tentative collisions;
+ *   - geometry in binary32 (one rounding per operation): positions
+ *     o + t d, distances, optical thickness sums; the transcendental values
+ *     (-ln(1 - zeta), cos, sin, sqrt of the direction) in FP64, rounded to
+ *     binary32; radiance and throughput in FP64 here;
+ *   - random numbers: stream 8 of the counter generator, index
+ *     ((pixel * spp + s) * 2^24 + i) for the i-th draw of path s of a pixel,
+ *     drawn in this order: zeta for each tracking step, xi at each tentative
+ *     collision, the roulette u when it applies, u1 and u2 for each new
+ *     direction (z = 1 - 2 u1, phi = 2 pi u2).
+ *
+ * Tracking from distance t with target thickness tau = -ln(1 - zeta): with
+ * macro-cells, the walk starts in the cell of the point at t and visits
+ * cells by a 3-D DDA (cell boundaries at multiples of cell/dims, an axis
+ * steps when its boundary distance equals the segment's end); the first
+ * cell in which the accumulated thickness would exceed tau holds the
+ * collision t_c = t_i + (tau - acc) / m_i.  Without macro-cells,
+ * t_c = t + tau / m.  Reaching t_far first means the ray leaves the cube.
+ * A tentative collision is real when xi * m < density * alpha(phi(x)).
+ *
+ * Output per pixel: the mean radiance over spp paths (rgb) and the fraction
+ * of paths whose camera ray met a real collision (alpha); n_real and n_samp
+ * count real and tentative collisions over the pixel's paths.
+ */
+#define ORC_PT_MAX_SAMPLES 65536u
+#define ORC_PI 3.14159265358979323846
+
+typedef struct {
+    float density, light[3], E[3], B[3];
+    int spp, rr_depth, max_depth;
+} orc_pt_opts;
+
+static int orc_track(const float o[3], const float d[3], float t, float tf, float tau, float density, float amax,
+                     const int32_t* dims, int cell, const float* mu, float* tc, float* maj)
+{
+    if (!mu) {
+        float m = density * amax;
+        if (!(m > 0.0f)) return 0;
+        float tt = t + tau / m;
+        if (!(tt < tf)) return 0;
+        *tc = tt;
+        *maj = m;
+        return 1;
+    }
+    int64_t M[3], ca[3];
+    for (int a = 0; a < 3; ++a) {
+        M[a] = (dims[a] + cell - 1) / cell;
+        float pa = o[a] + t * d[a];
+        float qa = (float)orc_clamp01f(pa);
+        ca[a] = (int64_t)floorf(qa * (float)dims[a]) / cell;
+        if (ca[a] > M[a] - 1) ca[a] = M[a] - 1;
+    }
+    float acc = 0.0f;
+    for (int64_t it = 0; it < M[0] + M[1] + M[2] + 3; ++it) {
+        float ta[3], tb = tf;
+        for (int a = 0; a < 3; ++a) {
+            ta[a] = INFINITY;
+            if (d[a] > 0.0f) {
+                int64_t b = (ca[a] + 1) * cell;
+                if (b > dims[a]) b = dims[a];
+                ta[a] = ((float)b / (float)dims[a] - o[a]) / d[a];
+            } else if (d[a] < 0.0f) {
+                ta[a] = ((float)(ca[a] * cell) / (float)dims[a] - o[a]) / d[a];
+            }
+            tb = fminf(tb, ta[a]);
+        }
+        float seg = tb - t;
+        if (seg < 0.0f) seg = 0.0f;
+        float m = density * mu[(ca[2] * M[1] + ca[1]) * M[0] + ca[0]];
+        float dtau = m * seg;
+        if (m > 0.0f && acc + dtau > tau) {
+            *tc = t + (tau - acc) / m;
+            *maj = m;
+            return 1;
+        }
+        acc = acc + dtau;
+        if (!(tb < tf)) return 0;
+        for (int a = 0; a < 3; ++a)
+            if (d[a] != 0.0f && ta[a] == tb) {
+                ca[a] += d[a] > 0.0f ? 1 : -1;
+                if (ca[a] < 0 || ca[a] >= M[a]) return 0;
+            }
+        t = tb;
+    }
+    return 0;
+}
+
+static void orc_pt_path(const orc_model* m, const double* params, const double* Wm, const float* lut,
+                        const orc_pt_opts* po, const float l[3], float amax, const int32_t* dims, int cell,
+                        const float* mu, uint64_t seed, uint64_t key, const float eye[3], const float dcam[3],
+                        double L[3], int* hit, uint32_t* n_samp, uint32_t* n_real)
+{
+    uint64_t i = 0;
+    double e[1024], c4[4], beta[3] = {1.0, 1.0, 1.0};
+    float o[3], d[3], xs[3], t, tf;
+    for (int a = 0; a < 3; ++a) {
+        o[a] = eye[a];
+        d[a] = dcam[a];
+    }
+    orc_slab(o, d, &t, &tf);
+    if (!(t < tf)) {
+        for (int ch = 0; ch < 3; ++ch) L[ch] += po->B[ch];
+        return;
+    }
+    int shadow = 0, depth = 0;
+    uint32_t samples = 0;
+    for (;;) {
+        int new_dir = 0;
+        if (samples >= ORC_PT_MAX_SAMPLES) return;
+        float zeta = (float)orc_rng_u01(seed, 8u, key + i++);
+        float tau = (float)(-log(1.0 - (double)zeta));
+        float tc, maj;
+        if (!orc_track(o, d, t, tf, tau, po->density, amax, dims, cell, mu, &tc, &maj)) {
+            if (!shadow) {
+                for (int ch = 0; ch < 3; ++ch) L[ch] += beta[ch] * (double)po->B[ch];
+                return;
+            }
+            for (int ch = 0; ch < 3; ++ch) L[ch] += beta[ch] * (double)po->E[ch] / (4.0 * ORC_PI);
+            new_dir = 1;
+        } else {
+            float x[3];
+            for (int a = 0; a < 3; ++a) x[a] = o[a] + tc * d[a];
+            orc_encode_one(m, params, x, e);
+            orc_tf(lut, orc_mlp_one(m, Wm, e, NULL), c4);
+            ++samples;
+            ++*n_samp;
+            float xi = (float)orc_rng_u01(seed, 8u, key + i++);
+            if (!((double)xi * (double)maj < (double)po->density * c4[3])) {
+                t = tc; /* null collision: the ray goes on */
+                continue;
+            }
+            ++*n_real;
+            if (shadow) {
+                new_dir = 1; /* the light is blocked */
+            } else {
+                if (depth == 0) *hit = 1;
+                ++depth;
+                if (depth > po->rr_depth) {
+                    double q = beta[0];
+                    if (beta[1] > q) q = beta[1];
+                    if (beta[2] > q) q = beta[2];
+                    if (q > 1.0) q = 1.0;
+                    double u = orc_rng_u01(seed, 8u, key + i++);
+                    if (u >= q) return;
+                    for (int ch = 0; ch < 3; ++ch) beta[ch] /= q;
+                }
+                for (int ch = 0; ch < 3; ++ch) beta[ch] *= c4[ch];
+                for (int a = 0; a < 3; ++a) {
+                    xs[a] = x[a];
+                    o[a] = x[a];
+                    d[a] = l[a];
+                }
+                shadow = 1;
+                orc_slab(o, d, &t, &tf);
+                if (!(t < tf)) {
+                    for (int ch = 0; ch < 3; ++ch) L[ch] += beta[ch] * (double)po->E[ch] / (4.0 * ORC_PI);
+                    new_dir = 1;
+                }
+            }
+        }
+        if (new_dir) {
+            shadow = 0;
+            if (depth >= po->max_depth) return;
+            float u1 = (float)orc_rng_u01(seed, 8u, key + i++);
+            float u2 = (float)orc_rng_u01(seed, 8u, key + i++);
+            float z = 1.0f - 2.0f * u1;
+            double rr = sqrt(fmax(0.0, 1.0 - (double)z * (double)z));
+            double ph = 2.0 * ORC_PI * (double)u2;
+            o[0] = xs[0];
+            o[1] = xs[1];
+            o[2] = xs[2];
+            d[0] = (float)(rr * cos(ph));
+            d[1] = (float)(rr * sin(ph));
+            d[2] = z;
+            orc_slab(o, d, &t, &tf);
+            if (!(t < tf)) {
+                for (int ch = 0; ch < 3; ++ch) L[ch] += beta[ch] * (double)po->B[ch];
+                return;
+            }
+        }
+    }
+}
+
+/* opts = { density, light[3], E[3], B[3] } as floats, iopts = { spp,
+ * rr_depth, max_depth }; mu (binary32, nullable) with mc_dims, mc_cell. */
+int orc_render_pixels_pt(const int32_t* desc, const double* params, const float* cam, const float* lut, int W,
+                         int H, uint32_t frame_seed, const int64_t* pix, int64_t n_pix, const int32_t* mc_dims,
+                         int mc_cell, const float* mu, const float* fopts, const int32_t* iopts, double* rgba,
+                         uint32_t* n_real, uint32_t* n_samp)
+{
+    orc_model m;
+    (void)H;
+    if (orc_model_from_desc(desc, &m) || m.width > 1024 || m.n_in > 1024) return -1;
+    orc_pt_opts po;
+    po.density = fopts[0];
+    for (int a = 0; a < 3; ++a) {
+        po.light[a] = fopts[1 + a];
+        po.E[a] = fopts[4 + a];
+        po.B[a] = fopts[7 + a];
+    }
+    po.spp = iopts[0];
+    po.rr_depth = iopts[1];
+    po.max_depth = iopts[2];
+    if (po.spp < 1 || po.spp > 256 || po.rr_depth < 0 || po.max_depth < 1 || po.max_depth > 1024) return -1;
+    const double* Wm = params + m.n_table;
+    float l[3], amax = 0.0f;
+    orc_unit3(po.light, l);
+    for (int i = 0; i < 256; ++i)
+        if (lut[4 * i + 3] > amax) amax = lut[4 * i + 3];
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t q = 0; q < n_pix; ++q) {
+        int64_t p = pix[q];
+        orc_ray r = orc_make_ray(cam, W, (int)(p % W), (int)(p / W), frame_seed, 1.0f);
+        double L[3] = {0.0, 0.0, 0.0};
+        int hits = 0;
+        uint32_t nr = 0, ns = 0;
+        for (int sidx = 0; sidx < po.spp; ++sidx) {
+            int hit = 0;
+            uint64_t key = ((uint64_t)p * (uint64_t)po.spp + (uint64_t)sidx) << 24;
+            orc_pt_path(&m, params, Wm, lut, &po, l, amax, mc_dims, mc_cell, mu, (uint64_t)frame_seed, key, r.o, r.d,
+                        L, &hit, &ns, &nr);
+            hits += hit;
+        }
+        for (int ch = 0; ch < 3; ++ch) rgba[4 * q + ch] = L[ch] / po.spp;
+        rgba[4 * q + 3] = (double)hits / po.spp;
+        n_real[q] = nr;
+        n_samp[q] = ns;
+    }
+    return 0;
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP
