@@ -419,29 +419,72 @@ int ngvol_render(const ngvol_plan* plan, const ngvol_weights* w, const ngvol_cam
                  void* d_workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* Rendering options of ngvol_render_ex. */
-#define NGVOL_RENDER_RM 0 /* emission-absorption ray marching (Section 5.2.1) */
+#define NGVOL_RENDER_RM 0        /* emission-absorption ray marching (Section 5.2.1) */
+#define NGVOL_RENDER_RM_SHADOW 1 /* ray marching with a single-shot heuristic shadow (Section 5.2) */
+#define NGVOL_RENDER_PT 2        /* volumetric path tracing (Section 5.2.2, Algorithm 1) */
 
 typedef struct ngvol_render_opts {
-    int32_t mode;     /* NGVOL_RENDER_RM */
-    /* Adaptive marching through the macro-cells (Section 5.3; needs mc with
-     * mu set).  Samples stay on the ray's grid t_k; from sample k in cell c
-     * of maximum opacity mu: mu = 0 bypasses the cell (k moves to the first
-     * sample outside it, found by a DDA step along the ray and an exact
+    int32_t mode; /* NGVOL_RENDER_RM, NGVOL_RENDER_RM_SHADOW or NGVOL_RENDER_PT */
+    /* RM: adaptive marching through the macro-cells (Section 5.3; needs mc
+     * with mu set).  Samples stay on the ray's grid t_k; from sample k in
+     * cell c of maximum opacity mu: mu = 0 bypasses the cell (k moves to the
+     * first sample outside it, found by a DDA step along the ray and an exact
      * check of the neighbouring samples' cells); otherwise the sample is
      * evaluated and stands for m = min(n(mu), exit(c) - k, n - k) grid steps
      * with n(mu) = max(1, floor(max(1 + (step_max - 1) |min(mu,1) - 1|^p, 1)))
      * in binary32 (the power by repeated multiplication), its opacity is
      * corrected to 1 - (1 - alpha)^m (alpha itself for m = 1), and k moves
      * by m.  0: fixed steps, with mc only skipping samples in transparent
-     * cells as ngvol_render does. */
+     * cells as ngvol_render does.  RM only. */
     int32_t adaptive;
     float step_max;   /* s2 in grid steps, >= 1 (the paper uses 64) */
     int32_t step_exp; /* p, 1..8 (the paper uses 2) */
+    /* RM_SHADOW and PT: direction towards a directional light (normalised in
+     * binary32 on the device; must not be zero).
+     * RM_SHADOW: the primary ray is marched as in RM (mc: empty cells
+     * skipped); its sample of largest contribution (1 - A_{k-1}) alpha_k,
+     * the first on ties, is the shading point.  A shadow ray leaves that
+     * sample's position along the light direction with the pixel's jitter
+     * and the primary rays' sample rule, from its sample k = 1 on, and
+     * multiplies the transmittance T by (1 - alpha) per sample, ending after
+     * the sample at which T <= 0.01.  The pixel is (T C, A). */
+    float light_dir[3];
+    /* PT: medium of extinction density * alpha(phi) and albedo rgb(phi)
+     * (the transfer function at the clamped network value phi), isotropic
+     * scattering; majorant density * mu per macro-cell when mc is given (the
+     * cells visited by a 3-D DDA, the optical thickness accumulated per
+     * cell), else density * (largest alpha of the table) for the whole cube.
+     * A scattering ray that meets a real collision spawns a shadow ray
+     * towards the light, tracked the same way: leaving the cube it adds
+     * throughput * light_radiance / (4 pi), meeting a real collision it adds
+     * nothing; the path then scatters into a uniformly drawn direction.  A
+     * scattering ray leaving the cube adds throughput * background and ends
+     * the path.  From real scattering collision rr_depth + 1 on, Russian
+     * roulette keeps the path with probability q = min(1, max throughput)
+     * and divides the throughput by q; a path also ends after max_depth
+     * scattering collisions and after 65536 tentative collisions.  Random
+     * numbers come from stream 8 of the library's counter generator, keyed
+     * by (frame_seed, (pixel * spp + path) * 2^24 + draw).  Output: rgba =
+     * (mean radiance over spp paths, fraction of paths whose camera ray met
+     * a real collision); n_geo counts the pixel's real collisions, n_used
+     * its tentative collisions (network samples). */
+    float light_radiance[3];
+    float background[3];
+    float density;     /* > 0 */
+    int32_t spp;       /* paths per pixel, 1..256 */
+    int32_t rr_depth;  /* >= 0 (the paper uses 4) */
+    int32_t max_depth; /* 1..1024 */
+    /* Optional per-pixel output [H][W] (NULL: none).  RM_SHADOW: the index k
+     * of the shading point on the primary ray, UINT32_MAX when there is none. */
+    uint32_t* d_aux;
 } ngvol_render_opts;
 
 /* ngvol_render with options (opts NULL: the defaults of ngvol_render, i.e.
- * mode RM with fixed steps).  Counters and outputs as ngvol_render; n_used
- * counts the samples composited (evaluated) up to termination. */
+ * mode RM with fixed steps).  Counters and outputs as ngvol_render (RM and
+ * RM_SHADOW: n_geo and n_used count the primary ray's samples; PT: see
+ * ngvol_render_opts; counters = {network samples, PT: real collisions, else
+ * composited primary samples, PT: paths, else rays, 0}).  RM_SHADOW with
+ * adaptive marching is NGVOL_EUNSUPPORTED. */
 int ngvol_render_ex(const ngvol_plan* plan, const ngvol_weights* w, const ngvol_camera* cam, const float* d_lut,
                     int32_t width, int32_t height, float dt, uint32_t frame_seed, const ngvol_macrocells* mc,
                     const ngvol_render_opts* opts, float* d_rgba, uint32_t* d_n_geo, uint32_t* d_n_used,

@@ -78,7 +78,13 @@ class Camera(C.Structure):
 
 
 class RenderOpts(C.Structure):
-    _fields_ = [("mode", C.c_int32), ("adaptive", C.c_int32), ("step_max", C.c_float), ("step_exp", C.c_int32)]
+    _fields_ = [("mode", C.c_int32), ("adaptive", C.c_int32), ("step_max", C.c_float), ("step_exp", C.c_int32),
+                ("light_dir", C.c_float * 3), ("light_radiance", C.c_float * 3), ("background", C.c_float * 3),
+                ("density", C.c_float), ("spp", C.c_int32), ("rr_depth", C.c_int32), ("max_depth", C.c_int32),
+                ("d_aux", C.c_void_p)]
+
+
+RENDER_MODES = {"rm": 0, "rm_shadow": 1, "pt": 2}
 
 
 _P = C.c_void_p
@@ -461,11 +467,18 @@ def psnr(plan, params, volume, table_f16=None, out=None):
 
 
 def render(plan, params, cam, lut, width, height, dt, frame_seed, table_f16=None, want_counts=True,
-           rgba=None, workspace=None, counters=None, macrocells=None, adaptive=False, step_max=64.0, step_exp=2):
+           rgba=None, workspace=None, counters=None, macrocells=None, adaptive=False, step_max=64.0, step_exp=2,
+           mode="rm", light=(0.0, 0.0, 1.0), radiance=(1.0, 1.0, 1.0), background=(0.0, 0.0, 0.0), density=1.0,
+           spp=1, rr_depth=4, max_depth=1024, aux=None):
     """Returns (rgba [H][W][4], n_geo [H][W] or None, n_used or None, counters [4] int64).
     macrocells (a MacroCells with opacities set): skip samples in empty cells;
     with adaptive=True also march with steps of up to step_max grid steps,
-    shortened by the cells' opacities with exponent step_exp (ngvol_render_ex)."""
+    shortened by the cells' opacities with exponent step_exp.  mode "rm_shadow"
+    adds a single-shot shadow towards `light`; mode "pt" path-traces the
+    volume (density, light, radiance, background, spp, rr_depth, max_depth;
+    macro-cells give per-cell majorants).  aux: optional int32 [H][W] output
+    (rm_shadow: index of the shading sample).  Options go through
+    ngvol_render_ex."""
     torch = _torch()
     dev = params.device
     if rgba is None:
@@ -481,10 +494,14 @@ def render(plan, params, cam, lut, width, height, dt, frame_seed, table_f16=None
                   (C.c_float * 3)(*c[9:12]))
     w = _weights(params, table_f16)
     mcp = C.byref(macrocells._c) if macrocells is not None else None
-    if adaptive:
-        if macrocells is None:
+    if adaptive or mode != "rm" or aux is not None:
+        if adaptive and macrocells is None:
             raise ValueError("adaptive marching needs macrocells")
-        opts = RenderOpts(0, 1, float(step_max), int(step_exp))
+        f3 = C.c_float * 3
+        opts = RenderOpts(RENDER_MODES[mode], 1 if adaptive else 0, float(step_max), int(step_exp),
+                          f3(*[float(v) for v in light]), f3(*[float(v) for v in radiance]),
+                          f3(*[float(v) for v in background]), float(density), int(spp), int(rr_depth),
+                          int(max_depth), _ptr(aux))
         _check(lib().ngvol_render_ex(plan.handle, C.byref(w), C.byref(camc), _ptr(lut), width, height, float(dt),
                                      frame_seed, mcp, C.byref(opts), _ptr(rgba), _ptr(n_geo), _ptr(n_used),
                                      _ptr(counters), _ptr(workspace), workspace.numel(), _stream()))

@@ -742,15 +742,46 @@ int ngvol_render_ex(const ngvol_plan* plan, const ngvol_weights* w, const ngvol_
   NGV_REQUIRE(dt >= 0x1p-20f && dt <= 1.0f, "dt must be in [2^-20, 1]");
   NGV_REQUIRE(ws_bytes >= ngvol_render_workspace_bytes(), "render workspace too small");
   RenderArgs ra{};
+  ra.mode = NGVOL_RENDER_RM;
   if (opts) {
-    NGV_REQUIRE(opts->mode == NGVOL_RENDER_RM, "unknown render mode %d", opts->mode);
+    const int mode = opts->mode;
+    NGV_REQUIRE(mode == NGVOL_RENDER_RM || mode == NGVOL_RENDER_RM_SHADOW || mode == NGVOL_RENDER_PT,
+                "unknown render mode %d", mode);
+    ra.mode = mode;
     if (opts->adaptive) {
+      if (mode != NGVOL_RENDER_RM) return fail(NGVOL_EUNSUPPORTED, "adaptive marching is available in mode RM only");
       NGV_REQUIRE(mc, "adaptive marching needs macro-cells");
       NGV_REQUIRE(opts->step_max >= 1.0f && opts->step_max <= 65536.0f, "step_max must be in [1, 65536]");
       NGV_REQUIRE(opts->step_exp >= 1 && opts->step_exp <= 8, "step_exp must be in [1, 8]");
       ra.adaptive = 1;
       ra.step_max = opts->step_max;
       ra.step_exp = opts->step_exp;
+    }
+    if (mode != NGVOL_RENDER_RM) {
+      const float* l = opts->light_dir;
+      NGV_REQUIRE(std::isfinite(l[0]) && std::isfinite(l[1]) && std::isfinite(l[2]) &&
+                      (l[0] != 0.0f || l[1] != 0.0f || l[2] != 0.0f),
+                  "light_dir must be finite and non-zero");
+      const double n2 = (double)l[0] * l[0] + (double)l[1] * l[1] + (double)l[2] * l[2];
+      NGV_REQUIRE(n2 > 1e-30 && n2 < 1e30, "light_dir length out of range");
+      memcpy(ra.light, l, sizeof ra.light);
+      NGV_REQUIRE(aligned4(opts->d_aux), "aux must be 4-byte aligned");
+      ra.aux = opts->d_aux;
+    }
+    if (mode == NGVOL_RENDER_PT) {
+      for (int c = 0; c < 3; ++c)
+        NGV_REQUIRE(std::isfinite(opts->light_radiance[c]) && std::isfinite(opts->background[c]),
+                    "light_radiance and background must be finite");
+      NGV_REQUIRE(std::isfinite(opts->density) && opts->density > 0.0f, "density must be positive and finite");
+      NGV_REQUIRE(opts->spp >= 1 && opts->spp <= 256, "spp must be in [1, 256]");
+      NGV_REQUIRE(opts->rr_depth >= 0, "rr_depth must be >= 0");
+      NGV_REQUIRE(opts->max_depth >= 1 && opts->max_depth <= 1024, "max_depth must be in [1, 1024]");
+      memcpy(ra.radiance, opts->light_radiance, sizeof ra.radiance);
+      memcpy(ra.background, opts->background, sizeof ra.background);
+      ra.density = opts->density;
+      ra.spp = opts->spp;
+      ra.rr_depth = opts->rr_depth;
+      ra.max_depth = opts->max_depth;
     }
   }
   if (mc)

@@ -17,6 +17,7 @@
 // build: one object per MLP precision and width (NGV_PSEL, NGV_WSEL)
 #include "kernels.hpp"
 #include "render.hpp"
+#include "ray_geom.hpp"
 #include "dispatch.hpp"
 #include "mlp_tile.hpp"
 
@@ -25,68 +26,7 @@ namespace ngvol {
 namespace {
 constexpr int kSlots = 8;  // rays per wave
 constexpr int kK = 8;      // samples per ray per round
-constexpr int kBands = 8;  // one work band per XCD
 }  // namespace
-
-struct RayGeom {
-  float o[3], d[3], t0, j;
-  uint32_t n;
-};
-
-// Ray of pixel (px, py): binary32, one rounding per operation, no FMA.
-__device__ __forceinline__ RayGeom make_ray(const float* cam, int W, int px, int py, uint32_t seed, float dt) {
-  RayGeom r;
-  const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
-  float dir[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const float t1 = __fmul_rn(fx, cam[3 + a]);
-    const float t2 = __fadd_rn(cam[9 + a], t1);
-    const float t3 = __fmul_rn(fy, cam[6 + a]);
-    dir[a] = __fadd_rn(t2, t3);
-  }
-  const float n2 = __fadd_rn(__fadd_rn(__fmul_rn(dir[0], dir[0]), __fmul_rn(dir[1], dir[1])), __fmul_rn(dir[2], dir[2]));
-  const float nrm = __fsqrt_rn(n2);
-  float tmin = -INFINITY, tmax = INFINITY;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    r.o[a] = cam[a];
-    r.d[a] = __fdiv_rn(dir[a], nrm);
-    const float inv = __fdiv_rn(1.0f, r.d[a]);
-    const float ta = __fmul_rn(__fsub_rn(0.0f, r.o[a]), inv);
-    const float tb = __fmul_rn(__fsub_rn(1.0f, r.o[a]), inv);
-    tmin = fmaxf(tmin, fminf(ta, tb));
-    tmax = fminf(tmax, fmaxf(ta, tb));
-  }
-  const float tn = fmaxf(tmin, 0.0f);
-  r.t0 = tn;
-  r.j = rng_u01((uint64_t)seed, 5u, (uint64_t)py * (uint64_t)W + (uint64_t)px);
-  r.n = 0;
-  if (tn < tmax) {
-    const float q = __fdiv_rn(__fsub_rn(tmax, tn), dt);
-    // a unit-cube chord is at most sqrt(3) long; more than 2^24 steps (or a
-    // NaN span) means a degenerate ray, which gets no samples
-    if (q <= 16777216.0f) {
-      const float c = ceilf(__fsub_rn(q, r.j));
-      if (c > 0.0f) r.n = (uint32_t)c;
-    }
-  }
-  return r;
-}
-
-__device__ __forceinline__ void ray_point(const RayGeom& r, uint32_t k, float dt, float& x, float& y, float& z) {
-  const float kj = __fadd_rn((float)k, r.j);
-  const float t = __fadd_rn(r.t0, __fmul_rn(kj, dt));
-  x = __fadd_rn(r.o[0], __fmul_rn(t, r.d[0]));
-  y = __fadd_rn(r.o[1], __fmul_rn(t, r.d[1]));
-  z = __fadd_rn(r.o[2], __fmul_rn(t, r.d[2]));
-}
-
-__device__ __forceinline__ uint32_t sample_cell(const RayGeom& r, uint32_t k, float dt, const McGeom& g) {
-  float x, y, z;
-  ray_point(r, k, dt, x, y, z);
-  return mc_index(g, clamp01(x), clamp01(y), clamp01(z));
-}
 
 // First sample index after k outside the macro-cell of sample k: the ray's
 // exit from the cell's box (a DDA step), the grid index just past it, then
@@ -133,6 +73,11 @@ struct SlotState {
   uint32_t k;   // next sample index
   uint32_t used;
   float C[3], A;
+  // single-shot shadow: the phase (0 primary, 1 shadow ray), the largest
+  // contribution so far and its sample index, the primary ray's sample
+  // count, and the shadow ray's transmittance
+  uint32_t phase, kmax, n0;
+  float wmax, T;
 };
 
 // Macro-cell modes, per slot: this round's samples (empty-space skipping:
@@ -169,18 +114,6 @@ __global__ void k_render_init(unsigned int* queue, unsigned long long* counters)
 __global__ void k_render_init(unsigned int* queue, unsigned long long* counters);
 #endif
 
-// Fetch the next pixel: own band first, then steal from the others.
-__device__ __forceinline__ int32_t fetch_pixel(unsigned int* queue, int band0, int64_t n_pix) {
-  for (int i = 0; i < kBands; ++i) {
-    const int b = (band0 + i) % kBands;
-    const int64_t lo = n_pix * b / kBands, hi = n_pix * (b + 1) / kBands;
-    if (__hip_atomic_load(queue + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= (unsigned)(hi - lo)) continue;
-    const unsigned q = atomicAdd(queue + b, 1u);
-    if ((int64_t)q < hi - lo) return (int32_t)(lo + q);
-  }
-  return -1;
-}
-
 // LDS layout of k_render: staged weights, the W_out region, the LUT
 // [256][4], the slots and per-sample outputs of every wave, then the
 // encoding stages.
@@ -190,7 +123,7 @@ __host__ __device__ inline size_t render_stage_offset(size_t weight_bytes, size_
   return (end + 15) & ~(size_t)15;
 }
 
-template <int P, int F, int KIN, int W, typename TT, int MC>
+template <int P, int F, int KIN, int W, typename TT, int MC, bool SH>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P != 0 && KIN == 32 ? 4 : 1)))
 k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs ra) {
   typedef typename Prec<P>::Frag Frag;
@@ -233,6 +166,11 @@ k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs r
       sl.used = 0;
       sl.C[0] = sl.C[1] = sl.C[2] = 0.0f;
       sl.A = 0.0f;
+      sl.phase = 0;
+      sl.kmax = 0xFFFFFFFFu;
+      sl.n0 = sl.g.n;
+      sl.wmax = 0.0f;
+      sl.T = 1.0f;
       if (sl.g.n > 0) {
         ++n_rays;
         return;
@@ -242,8 +180,11 @@ k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs r
       *o4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       if (ra.n_geo) ra.n_geo[p] = 0u;
       if (ra.n_used) ra.n_used[p] = 0u;
+      if (SH && ra.aux) ra.aux[p] = 0xFFFFFFFFu;
     }
   };
+  float lhat[3] = {0.0f, 0.0f, 1.0f};
+  if constexpr (SH) unit3(ra.light, lhat);
 
   if (lane < kSlots) {
     SlotState sl;
@@ -363,22 +304,28 @@ k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs r
         const uint32_t kend = (skip_empty || adaptive) ? lst[lane * kList + kCnt]
                                                        : (sl.g.n - sl.k < (uint32_t)kK ? sl.g.n - sl.k : (uint32_t)kK);
         for (uint32_t q = 0; q < kend; ++q) {
-          const float val = fminf(fmaxf(yv[lane * kK + q], 0.0f), 1.0f);
-          const float u = 255.0f * val;
-          const float fi = fminf(floorf(u), 254.0f);
-          const int i0 = (int)fi;
-          const float fr = u - fi;
           float c4[4];
-#pragma unroll
-          for (int ch = 0; ch < 4; ++ch) c4[ch] = __builtin_fmaf(fr, lds_lut[4 * (i0 + 1) + ch] - lds_lut[4 * i0 + ch],
-                                                                   lds_lut[4 * i0 + ch]);
+          tf_lookup(lds_lut, yv[lane * kK + q], c4);
           float a = c4[3];
           if constexpr (adaptive) {
             // opacity of a sample standing for `span` grid steps
             const uint32_t span = lst[lane * kList + kSpan + q];
             if (span > 1u) a = __fsub_rn(1.0f, powf(__fsub_rn(1.0f, a), (float)span));
           }
+          if (SH && sl.phase) {
+            // shadow ray: transmittance towards the light
+            sl.T = sl.T * (1.0f - a);
+            if (sl.T <= 0.01f) {
+              done = true;
+              break;
+            }
+            continue;
+          }
           const float w = (1.0f - sl.A) * a;
+          if (SH && w > sl.wmax) {
+            sl.wmax = w;
+            sl.kmax = (skip_empty || adaptive) ? lst[lane * kList + q] : sl.k + q;
+          }
           sl.C[0] = __builtin_fmaf(w, c4[0], sl.C[0]);
           sl.C[1] = __builtin_fmaf(w, c4[1], sl.C[1]);
           sl.C[2] = __builtin_fmaf(w, c4[2], sl.C[2]);
@@ -390,12 +337,26 @@ k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs r
           }
         }
         sl.k = (skip_empty || adaptive) ? lst[lane * kList + kNext] : sl.k + kend;
+        if constexpr (SH) {
+          // the primary ray is done: a shadow ray leaves its largest
+          // contribution's sample point towards the light (its samples from
+          // k = 1 on); with no such point, or no samples, T stays 1
+          if ((done || sl.k >= sl.g.n) && sl.phase == 0 && sl.wmax > 0.0f) {
+            float ps[3];
+            ray_point(sl.g, sl.kmax, ra.dt, ps[0], ps[1], ps[2]);
+            sl.g = ray_from(ps, lhat, sl.g.j, ra.dt);
+            sl.phase = 1;
+            sl.k = 1;
+            done = false;
+          }
+        }
         if (done || sl.k >= sl.g.n) {
           const int32_t p = sl.pix;
           float4* o4 = reinterpret_cast<float4*>(ra.rgba) + p;
-          *o4 = make_float4(sl.C[0], sl.C[1], sl.C[2], sl.A);
-          if (ra.n_geo) ra.n_geo[p] = sl.g.n;
+          *o4 = make_float4(sl.T * sl.C[0], sl.T * sl.C[1], sl.T * sl.C[2], sl.A);
+          if (ra.n_geo) ra.n_geo[p] = sl.n0;
           if (ra.n_used) ra.n_used[p] = sl.used;
+          if (SH && ra.aux) ra.aux[p] = sl.kmax;
           n_used_tot += sl.used;
           refill(sl);
         }
@@ -437,7 +398,17 @@ hipError_t launch_render_p(const ngvol_plan* plan, TablePtrs tp, const float* ml
   if (grid > cap) grid = cap;
   if (grid < 1) grid = 1;
 #define NGV_RENDER_GO(TT, MCM)                                                                                    \
-  hipLaunchKernelGGL((k_render<P, F, KIN, W, TT, MCM>), dim3((unsigned)grid), dim3(256), lds, st, md, tp, mlp, ra)
+  do {                                                                                                            \
+    if constexpr (MCM != kMcAdaptive) {                                                                          \
+      if (ra.mode == NGVOL_RENDER_RM_SHADOW) {                                                                    \
+        hipLaunchKernelGGL((k_render<P, F, KIN, W, TT, MCM, true>), dim3((unsigned)grid), dim3(256), lds, st, md,   \
+                           tp, mlp, ra);                                                                          \
+        break;                                                                                                    \
+      }                                                                                                           \
+    }                                                                                                             \
+    hipLaunchKernelGGL((k_render<P, F, KIN, W, TT, MCM, false>), dim3((unsigned)grid), dim3(256), lds, st, md,      \
+                       tp, mlp, ra);                                                                              \
+  } while (0)
   NGV_DISPATCH_F_KIN(md.F, plan->kin, {
     const int mcm = ra.mc.mu == nullptr ? kMcNone : (ra.adaptive ? kMcAdaptive : kMcSkip);
     if (tp.f16) {
@@ -461,6 +432,9 @@ template hipError_t launch_render_p<NGV_PSEL, NGV_WSEL>(const ngvol_plan*, Table
 hipError_t launch_render(const ngvol_plan* plan, TablePtrs tp, const float* mlp, const RenderArgs& ra,
                          hipStream_t st) {
   hipLaunchKernelGGL(k_render_init, dim3(1), dim3(64), 0, st, ra.queue, ra.counters);
+  if (ra.mode == NGVOL_RENDER_PT)
+    NGV_DISPATCH_P(plan->layout.precision,
+                   NGV_DISPATCH_W(plan->md.width, return launch_render_pt_p<P, W>(plan, tp, mlp, ra, st)));
   NGV_DISPATCH_P(plan->layout.precision, NGV_DISPATCH_W(plan->md.width, return launch_render_p<P, W>(plan, tp, mlp, ra, st)));
   return hipErrorInvalidValue;
 }
