@@ -12,7 +12,8 @@ time.  Inputs are synthetic and resident in HBM before timing starts.
 Also reported: the same two legs in the plain FP32 form, the PSNR of both
 forms after identical training (quality leg), online rendering (1024^2
 frames through the trained model with one training step per frame, with
-and without macro-cells, and on a sparse blob target), the
+and without macro-cells, with adaptive marching, on a sparse blob target,
+with single-shot shadows and path-traced), the
 roofline of the query pass (level kernel + MLP on the feature planes,
 measured with events on the launch stream; HBM traffic from the committed
 counter summary while the kernel sources match it), the standalone MLP on
@@ -354,6 +355,37 @@ def main():
                               "network_samples_per_frame": r_ad["network_samples_per_frame"]}
         log(f"render with adaptive marching: {r_ad['fps']:.2f} fps, {r_ad['network_samples_per_frame']:.3e} network "
             f"samples per frame")
+        # lighting (Section 5.2): single-shot shadows, and path tracing with
+        # one path per pixel through a medium of extinction alpha / Delta
+        # (the ray marcher's optical thickness), with global and per-cell
+        # majorants; the macro-cells are the online ones of the last leg
+        light = (0.4, 0.9, -0.3)
+        pt_kw = dict(mode="pt", light=light, radiance=(6.0, 6.0, 6.0), background=(0.05, 0.05, 0.08),
+                     density=1.0 / dt, spp=1, rr_depth=4, max_depth=64)
+        lighting = {"light": light, "pt_density": 1.0 / dt, "pt_spp": 1, "pt_rr_depth": 4}
+        for name, kw in (("rm_shadow", dict(mode="rm_shadow", light=light, macrocells=None)),
+                         ("rm_shadow_macrocells", dict(mode="rm_shadow", light=light, macrocells=mc)),
+                         ("pt_global_majorant", dict(pt_kw, macrocells=None)),
+                         ("pt_macrocells", dict(pt_kw, macrocells=mc))):
+            ngv.render(plan16, rs.params, cams[0], lut, W, H, dt, 0, table_f16=rs.table_f16, want_counts=False,
+                       rgba=rgba, workspace=rws, counters=cnt, **kw)
+            torch.cuda.synchronize()
+            e = [ev() for _ in range(2)]
+            e[0].record()
+            n_ev = 0
+            for f in range(3):
+                ngv.render(plan16, rs.params, cams[f + 1], lut, W, H, dt, f + 1, table_f16=rs.table_f16,
+                           want_counts=False, rgba=rgba, workspace=rws, counters=cnt, **kw)
+                torch.cuda.synchronize()
+                n_ev += int(cnt.cpu().numpy()[0])
+            e[1].record()
+            torch.cuda.synchronize()
+            ms = e[0].elapsed_time(e[1]) / 3
+            lighting[name] = {"render_ms": round(ms, 3), "fps": round(1000.0 / ms, 2),
+                              "network_samples_per_frame": n_ev / 3,
+                              "network_samples_per_s": n_ev / 3 / (ms * 1e-3)}
+            log(f"{name}: {ms:.2f} ms per 1024^2 frame, {n_ev / 3:.3e} network samples")
+        render["lighting"] = lighting
         rs = mc = None
         # a sparse target: Gaussian blobs (256^3, FP32), the query network
         # trained 300 steps with 16^3-voxel macro-cells built online (the
