@@ -98,7 +98,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--quality-steps", type=int, default=2000)
-    ap.add_argument("--quality-repeats", type=int, default=12)
+    ap.add_argument("--quality-repeats", type=int, default=8)
     ap.add_argument("--no-quality", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
@@ -217,6 +217,33 @@ def main():
         del st32
         log(f"fp32 train {t32:.3f} ms, infer {i32:.3f} ms")
 
+    # ------------------------------------------- FP16-MFMA form, same step
+    fp16 = None
+    if not args.no_fp32:
+        plan_h = ngv.Plan(**MODEL, precision="fp16")
+        sth = ngv.TrainState(plan_h, params0, B_TRAIN, f16_tables=True)
+        reps = max(3, min(args.steps, 10))
+        for s_ in range(2):
+            ngv.train_step(sth, volume=vol, seed=SEED, step_index=s_, loss_scale=LOSS_SCALE, **ADAM)
+            ngv.sort_queries(plan_h, xyz, qws)
+            ngv.infer_sorted(plan_h, sth.params, qws, N_QUERY, table_f16=sth.table_f16, out=out)
+        torch.cuda.synchronize()
+        e = [ev() for _ in range(3)]
+        e[0].record()
+        for s_ in range(reps):
+            ngv.train_step(sth, volume=vol, seed=SEED, step_index=2 + s_, loss_scale=LOSS_SCALE, **ADAM)
+        e[1].record()
+        for s_ in range(reps):
+            ngv.sort_queries(plan_h, xyz, qws)
+            ngv.infer_sorted(plan_h, sth.params, qws, N_QUERY, table_f16=sth.table_f16, out=out)
+        e[2].record()
+        torch.cuda.synchronize()
+        th_, ih_ = e[0].elapsed_time(e[1]) / reps, e[1].elapsed_time(e[2]) / reps
+        fp16 = {"train_ms": round(th_, 4), "sort_infer_ms": round(ih_, 4),
+                "step_samples_per_s": (B_TRAIN + N_QUERY) / ((th_ + ih_) * 1e-3)}
+        del sth
+        log(f"fp16 train {th_:.3f} ms, sort+infer {ih_:.3f} ms")
+
     # ------------------------------------- paper-default training setting
     paper_default = None
     if not args.no_paper_default:
@@ -243,44 +270,65 @@ def main():
             del sp
 
     # ------------------------------------------------------------ quality leg
-    # Training with these hyper-parameters is noisy run to run (FP32 atomics
-    # make every run's trajectory different and the final PSNR varies by
-    # several dB), so each form is trained several times from the same
-    # initialisation with different batch seeds and the means and medians
-    # are compared.
+    # Both forms trained from the same initialisation on the same batches
+    # (paired by batch seed), PSNR over the whole 512^3 grid.  With the
+    # configured optimiser (lr 1e-2, eps 1e-15, no decay) the PSNR of one run
+    # swings by several dB from one checkpoint to the next, so a final PSNR
+    # is a draw from that trajectory and the comparison stays undecided; the
+    # second recipe anneals the learning rate over the last quarter of the
+    # steps (x0.99 per step), after which every run ends within a few
+    # hundredths of a dB of its neighbours and the paired loss is resolved.
+    # Reported: the mean paired loss FP32 - BF16, its standard error and the
+    # one-sided 95% upper bound (Student t, repeats - 1 degrees of freedom).
     quality = None
     trained = None
     if not args.no_quality:
-        res = {"bf16": [], "fp32": []}
-        for r in range(args.quality_repeats):
-            for name, plan, f16, ls in (("bf16", plan16, True, LOSS_SCALE), ("fp32", plan32, False, 1.0)):
-                s = ngv.TrainState(plan, params0, B_TRAIN, f16_tables=f16)
-                if r == 0 and name == "bf16":
-                    trained = s  # kept for the rendering leg
-                q0 = time.perf_counter()
-                for k in range(args.quality_steps):
-                    ngv.train_step(s, volume=vol, seed=SEED + r, step_index=k, loss_scale=ls, **ADAM)
-                torch.cuda.synchronize()
-                pr, tf = s.weights()
-                res[name].append(ngv.psnr(plan, pr, vol, table_f16=tf))
-                log(f"quality {name} run {r}: {args.quality_steps} steps in {time.perf_counter() - q0:.1f}s, "
-                    f"PSNR {res[name][-1]:.3f} dB")
-                if s is not trained:
-                    del s
-        mb, mf = float(np.mean(res["bf16"])), float(np.mean(res["fp32"]))
-        # paired by batch seed: the loss of each repeat and its standard error
-        diff = np.array(res["fp32"]) - np.array(res["bf16"])
-        d_se = float(np.std(diff, ddof=1) / math.sqrt(len(diff))) if len(diff) > 1 else float("nan")
-        quality = {"steps": args.quality_steps, "batch": B_TRAIN, "volume": f"{VOL_D}^3 fbm f32",
-                   "repeats": args.quality_repeats, "psnr_bf16_db": [round(v, 3) for v in res["bf16"]],
-                   "psnr_fp32_db": [round(v, 3) for v in res["fp32"]], "mean_bf16_db": round(mb, 3),
-                   "mean_fp32_db": round(mf, 3), "psnr_loss_db": round(mf - mb, 3),
-                   "median_bf16_db": round(float(np.median(res["bf16"])), 3),
-                   "median_fp32_db": round(float(np.median(res["fp32"])), 3),
-                   "paired_loss_db_mean": round(float(np.mean(diff)), 3),
-                   "paired_loss_db_stderr": round(d_se, 3),
-                   "fp32_run_to_run_std_db": round(float(np.std(res["fp32"])), 3),
-                   "bf16_run_to_run_std_db": round(float(np.std(res["bf16"])), 3)}
+        from scipy.stats import t as student_t
+        Q = args.quality_steps
+        plan_h = ngv.Plan(**MODEL, precision="fp16")
+        recipes = (("annealed", dict(decay=(Q - Q // 4, 1, 0.99)), args.quality_repeats),
+                   ("constant_lr", {}, max(2, args.quality_repeats // 2)))
+        quality = {"steps": Q, "batch": B_TRAIN, "volume": f"{VOL_D}^3 fbm f32",
+                   "criterion": "annealed recipe: one-sided 95% upper bound of the paired PSNR loss <= 0.5 dB",
+                   "forms": "each form trains and is evaluated in its own precision (BF16 or FP16 MFMA with FP16 "
+                            "tables, or plain FP32)"}
+        for rname, extra, reps in recipes:
+            res = {"bf16": [], "fp16": [], "fp32": []}
+            for r in range(reps):
+                for name, plan, f16, ls in (("bf16", plan16, True, LOSS_SCALE), ("fp16", plan_h, True, LOSS_SCALE),
+                                            ("fp32", plan32, False, 1.0)):
+                    s = ngv.TrainState(plan, params0, B_TRAIN, f16_tables=f16)
+                    if r == 0 and name == "bf16" and trained is None:
+                        trained = s  # kept for the rendering leg
+                    q0 = time.perf_counter()
+                    for k in range(Q):
+                        ngv.train_step(s, volume=vol, seed=SEED + r, step_index=k, loss_scale=ls, **ADAM, **extra)
+                    torch.cuda.synchronize()
+                    pr, tf = s.weights()
+                    res[name].append(ngv.psnr(plan, pr, vol, table_f16=tf))
+                    log(f"quality {rname} {name} run {r}: {Q} steps in {time.perf_counter() - q0:.1f}s, "
+                        f"PSNR {res[name][-1]:.3f} dB")
+                    if s is not trained:
+                        del s
+            qr = {"repeats": reps}
+            for name in ("bf16", "fp16", "fp32"):
+                qr[f"psnr_{name}_db"] = [round(v, 3) for v in res[name]]
+                qr[f"mean_{name}_db"] = round(float(np.mean(res[name])), 3)
+            qr["run_to_run_std_db"] = {k: round(float(np.std(v, ddof=1)), 3) for k, v in res.items()}
+            for name in ("bf16", "fp16"):
+                diff = np.array(res["fp32"]) - np.array(res[name])
+                n = len(diff)
+                d_se = float(np.std(diff, ddof=1) / math.sqrt(n))
+                upper = float(np.mean(diff) + student_t.ppf(0.95, n - 1) * d_se)
+                qr[f"paired_loss_{name}_db"] = {"mean": round(float(np.mean(diff)), 3), "stderr": round(d_se, 3),
+                                                "upper95": round(upper, 3)}
+                if rname == "annealed":
+                    quality[f"criterion_met_{name}"] = bool(upper <= 0.5)
+                log(f"quality {rname} {name}: paired loss {np.mean(diff):.3f} +- {d_se:.3f} dB "
+                    f"(upper 95% {upper:.3f})")
+            quality[rname] = qr
+            if rname == "annealed":
+                quality["decay"] = list(extra["decay"])
 
     # ---------------------------------------------------- online render leg
     # 1024^2 frames through the trained BF16 model (the quality leg's first
@@ -576,12 +624,35 @@ def main():
         oracle.adam(pd, m_, v_, g, 1, **{"lr": 1e-2, "b1": 0.9, "b2": 0.99, "eps": 1e-15})
         t_adam = time.perf_counter() - c0
         t_step = t_inf * (N_QUERY / nq) + t_lg * (B_TRAIN / nb) + t_adam
-        cpu = {"value": (B_TRAIN + N_QUERY) / t_step, "unit": "samples/s", "cores": oracle.num_threads(),
+        threads = oracle.num_threads()
+        # the same sample at one thread, a sixteenth of the size
+        oracle.set_threads(1)
+        c0 = time.perf_counter()
+        oracle.forward(om, pd, xyz_h[:nq // 16])
+        t_inf1 = time.perf_counter() - c0
+        c0 = time.perf_counter()
+        oracle.loss_grad(om, pd, bx[:nb // 16], by[:nb // 16])
+        t_lg1 = time.perf_counter() - c0
+        oracle.set_threads(threads)
+        t_step1 = t_inf1 * (N_QUERY / (nq // 16)) + t_lg1 * (B_TRAIN / (nb // 16)) + t_adam * threads
+        model_name = "unknown"
+        try:
+            with open("/proc/cpuinfo") as fh:
+                model_name = next(ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name"))
+        except (OSError, StopIteration):
+            pass
+        cpu = {"value": (B_TRAIN + N_QUERY) / t_step, "unit": "samples/s", "cores": threads,
                "kind": "oracle",
                "sample": f"FP64 oracle: query of {nq} of the 2^24 coordinates ({t_inf:.2f}s), loss+gradient of a "
                          f"{nb}-sample batch ({t_lg:.2f}s) and one dense Adam update ({t_adam:.2f}s), scaled to "
-                         f"one step of 2^18 training + 2^24 query samples"}
-        log(f"cpu oracle: {cpu['value']:.3e} samples/s on {cpu['cores']} threads")
+                         f"one step of 2^18 training + 2^24 query samples",
+               "single_thread_value": (B_TRAIN + N_QUERY) / t_step1,
+               "single_thread_sample": f"query of {nq // 16} coordinates ({t_inf1:.2f}s) and loss+gradient of "
+                                       f"{nb // 16} samples ({t_lg1:.2f}s) on one thread; Adam taken as the "
+                                       f"{threads}-thread time x {threads}",
+               "host_cpu": model_name, "affinity_cpus": len(os.sched_getaffinity(0))}
+        log(f"cpu oracle: {cpu['value']:.3e} samples/s on {threads} threads, "
+            f"{cpu['single_thread_value']:.3e} on one ({model_name})")
 
     line = {
         "metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
@@ -595,7 +666,7 @@ def main():
                       "train_samples_per_s": B_TRAIN / (train_ms * 1e-3),
                       "infer_samples_per_s": N_QUERY / ((sort_ms + infer_ms) * 1e-3),
                       "infer_unsorted_ms": round(direct_ms, 4)},
-        "fp32_plain": fp32, "paper_default_train": paper_default, "quality": quality, "render": render, "multi_volume": multi, "roofline": roofline,
+        "fp32_plain": fp32, "fp16_mfma": fp16, "paper_default_train": paper_default, "quality": quality, "render": render, "multi_volume": multi, "roofline": roofline,
         "mlp_roofline": mlp_roofline, "cpu_baseline": cpu,
     }
     s = json.dumps(line)

@@ -62,6 +62,7 @@ def lib():
             "orc_ray_points": (C.c_int, [P, C.c_int, C.c_int, u32, flt, i64, u32, u32, P]),
             "orc_render_pixels": (C.c_int, [P, P, P, P, C.c_int, C.c_int, flt, u32, P, i64, P, P, P]),
             "orc_num_threads": (C.c_int, []),
+            "orc_set_threads": (None, [C.c_int]),
             "orc_mc_cells": (C.c_int, [P, C.c_int, P, i64, P]),
             "orc_mc_update": (C.c_int, [P, C.c_int, P, P, i64, P, P]),
             "orc_mc_opacity": (C.c_int, [P, P, i64, P, P]),
@@ -345,6 +346,11 @@ def render_pixels_adaptive(m: Model, params, cam, lut, W, H, dt, frame_seed, pix
                                           _p(np.asarray(dims, np.int32)), cell, _p(mu), s2, int(p), _p(rgba),
                                           _p(n_geo), _p(n_used)))
     return rgba, n_geo, n_used
+
+
+def set_threads(n):
+    """Thread count of the oracle's parallel loops from now on."""
+    lib().orc_set_threads(int(n))
 
 
 def num_threads():

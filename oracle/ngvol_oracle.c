@@ -1428,6 +1428,17 @@ int orc_render_pixels_pt(const int32_t* desc, const double* params, const float*
     return 0;
 }
 
+/* thread count of the OpenMP loops from now on (the CPU baseline's
+ * single-thread figure) */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP
