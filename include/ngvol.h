@@ -240,7 +240,8 @@ const char* ngvol_version(void);
 /* Debug mode (also switched on by NGVOL_DEBUG=1 in the environment): every
  * call then waits for the device after its launches (hipDeviceSynchronize)
  * and returns NGVOL_EDEVICE with the runtime's message if one of them
- * failed.  Not for use while a stream is being captured into a graph. */
+ * failed.  On a stream that is being captured into a graph it only checks
+ * the launch status (hipGetLastError), which leaves the capture intact. */
 int ngvol_set_debug(int32_t on);
 
 /* Create / destroy a plan.  EINVAL for out-of-range fields, EUNSUPPORTED for
