@@ -62,6 +62,8 @@ def lib():
             "orc_ray_points": (C.c_int, [P, C.c_int, C.c_int, u32, flt, i64, u32, u32, P]),
             "orc_render_pixels": (C.c_int, [P, P, P, P, C.c_int, C.c_int, flt, u32, P, i64, P, P, P]),
             "orc_num_threads": (C.c_int, []),
+            "orc_ooc_slots": (C.c_int, [P, C.c_int, i64, i64, u64, i64, P]),
+            "orc_ooc_sample": (C.c_int, [P, P, C.c_int, i64, i64, u64, i64, i64, P, P, P]),
             "orc_set_threads": (None, [C.c_int]),
             "orc_mc_cells": (C.c_int, [P, C.c_int, P, i64, P]),
             "orc_mc_update": (C.c_int, [P, C.c_int, P, P, i64, P, P]),
@@ -392,3 +394,22 @@ def render_pixels_pt(m: Model, params, cam, lut, W, H, frame_seed, pix, density,
                                     _p(np.asarray(dims, np.int32)), cell, None if mu is None else _p(mu), _p(fo), _p(io), _p(rgba),
                                     _p(n_real), _p(n_samp)))
     return rgba, n_real, n_samp
+
+
+def ooc_slots(dims, block, R, S, seed, step):
+    """Block id held by every slot of the out-of-core buffer after step's loads."""
+    out = np.zeros(R, np.int64)
+    _chk(lib().orc_ooc_slots(_p(np.asarray(dims, np.int32)), block, R, S, seed, step, _p(out)))
+    return out
+
+
+def ooc_sample(vol, block, R, S, seed, step, B):
+    """Out-of-core samples of a step: (xyz [B][3] f32, y [B] f64, block id [B])."""
+    vol = _f32(vol)
+    Dz, Dy, Dx = vol.shape
+    xyz = np.zeros((B, 3), np.float32)
+    y = np.zeros(B, np.float64)
+    blk = np.zeros(B, np.int64)
+    _chk(lib().orc_ooc_sample(_p(vol), _p(np.array([Dx, Dy, Dz], np.int32)), block, R, S, seed, step, B, _p(xyz),
+                              _p(y), _p(blk)))
+    return xyz, y, blk

@@ -370,6 +370,76 @@ int orc_sample_volume(const float* vol, const int32_t* dims, const float* xyz, i
     return 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Out-of-core sampling (Section 4.1).                                       */
+/*                                                                          */
+/* Reading: the volume is cut into blocks of b^3 voxels (the last block of   */
+/* an axis may be partial), numbered z-major over the block grid             */
+/* G_a = ceil(D_a / b).  A buffer of R slots holds blocks.  Block loads are  */
+/* numbered j = 0, 1, ...: load j brings block                               */
+/* ((r_j >> 40) * n_blocks) >> 24, r_j = SplitMix64(seed, stream 9, j);      */
+/* loads 0..R-1 fill slots 0..R-1 before the first sampling step (the warm-  */
+/* up), and the refresh before step k >= 1 makes loads                       */
+/* j = R + (k-1) S + i, i < S, into slots ((k-1) S + i) mod R (the S oldest). */
+/* Sample i of step k takes draws d = 0..6 of stream 10 at index             */
+/* (k B + i) 8 + d: the slot ((r_0 >> 40) R) >> 24; a voxel of the slot's    */
+/* block, per axis origin_a + (((r_a >> 40) n_a) >> 24) with n_a the block's */
+/* extent min(b, D_a - origin_a); the jitter u_a = (r >> 40) 2^-24 from      */
+/* d = 4..6.  The coordinate is x_a = (v_a + u_a) / D_a in binary32 (the     */
+/* voxel centre moved by U[-1/2, 1/2)), the target the volume's trilinear    */
+/* sample at x (orc_volume_at): a one-voxel ghost layer around a block holds */
+/* every voxel that sample needs.                                            */
+/* ------------------------------------------------------------------------ */
+static int64_t orc_ooc_pick(uint64_t r, int64_t n) { return (int64_t)(((r >> 40) * (uint64_t)n) >> 24); }
+
+/* block in every slot after the loads up to and including step `step`'s */
+int orc_ooc_slots(const int32_t* dims, int b, int64_t R, int64_t S, uint64_t seed, int64_t step, int64_t* slot_block)
+{
+    if (b < 1 || R < 1 || S < 1 || S > R || step < 0) return -1;
+    int64_t G[3];
+    for (int a = 0; a < 3; ++a) G[a] = (dims[a] + b - 1) / b;
+    const int64_t nb = G[0] * G[1] * G[2];
+    for (int64_t j = 0; j < R; ++j) slot_block[j] = orc_ooc_pick(orc_rng_u64(seed, 9u, (uint64_t)j), nb);
+    for (int64_t k = 1; k <= step; ++k)
+        for (int64_t i = 0; i < S; ++i) {
+            const int64_t j = R + (k - 1) * S + i;
+            slot_block[((k - 1) * S + i) % R] = orc_ooc_pick(orc_rng_u64(seed, 9u, (uint64_t)j), nb);
+        }
+    return 0;
+}
+
+/* the B samples of step `step`: coordinates, targets and the block each
+ * came from */
+int orc_ooc_sample(const float* vol, const int32_t* dims, int b, int64_t R, int64_t S, uint64_t seed, int64_t step,
+                   int64_t B, float* xyz, double* y, int64_t* block_of)
+{
+    int64_t* slots = (int64_t*)malloc(sizeof(int64_t) * (size_t)R);
+    if (!slots) return -2;
+    if (orc_ooc_slots(dims, b, R, S, seed, step, slots)) {
+        free(slots);
+        return -1;
+    }
+    int64_t G[3];
+    for (int a = 0; a < 3; ++a) G[a] = (dims[a] + b - 1) / b;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < B; ++i) {
+        const uint64_t base = (uint64_t)(step * B + i) * 8u;
+        const int64_t blk = slots[orc_ooc_pick(orc_rng_u64(seed, 10u, base), R)];
+        const int64_t bc[3] = {blk % G[0], (blk / G[0]) % G[1], blk / (G[0] * G[1])};
+        for (int a = 0; a < 3; ++a) {
+            const int64_t origin = bc[a] * b;
+            const int64_t ext = dims[a] - origin < b ? dims[a] - origin : b;
+            const int64_t v = origin + orc_ooc_pick(orc_rng_u64(seed, 10u, base + 1u + (uint64_t)a), ext);
+            const float u = (float)(orc_rng_u64(seed, 10u, base + 4u + (uint64_t)a) >> 40) * 0x1p-24f;
+            xyz[3 * i + a] = ((float)v + u) / (float)dims[a];
+        }
+        y[i] = orc_volume_at(vol, dims, xyz + 3 * i);
+        if (block_of) block_of[i] = blk;
+    }
+    free(slots);
+    return 0;
+}
+
 /* Training batch of step `step`: stream 3, index = step*B*3 + i*3 + axis. */
 int orc_batch_coords(uint64_t seed, int64_t step, int64_t B, float* xyz)
 {
