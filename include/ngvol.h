@@ -492,6 +492,76 @@ int ngvol_render_ex(const ngvol_plan* plan, const ngvol_weights* w, const ngvol_
                     ngvol_render_counters* d_counters, void* d_workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* ----------------------------------------------------------------------- */
+/* Out-of-core sampling (Section 4.1)                                      */
+/* ----------------------------------------------------------------------- */
+/* A volume larger than memory is sampled through a buffer of R blocks of
+ * about 64 KB chosen at random, S of which are replaced before every
+ * sampling step; samples pick a buffered block, a voxel of it, and jitter the
+ * voxel centre by up to half a voxel (a one-voxel ghost layer around every
+ * block holds the neighbours the trilinear interpolation needs).  Here the
+ * buffer lives in device memory and the samples are drawn on the device; the
+ * blocks come from a bricked file (one record per block) read by host threads.
+ *
+ * Schedule (both the block choice and the sample draws use the library's
+ * counter generator): blocks are b^3 voxels, the last block of an axis
+ * possibly partial, numbered x-fastest over the block grid
+ * G_a = ceil(D_a / b).  Block load j takes block ((r_j >> 40) * n_blocks) >> 24
+ * with r_j from stream 9 at index j; loads 0..R-1 fill slots 0..R-1 (step 0,
+ * the warm-up), and step k >= 1 makes loads R + (k-1) S + i (i < S) into
+ * slots ((k-1) S + i) mod R.  Sample i of step k draws the slot, a voxel of
+ * the slot's block and the jitter u in [0,1)^3 from stream 10 at indices
+ * (k B + i) 8 + 0..6 (as ((r >> 40) n) >> 24 and (r >> 40) 2^-24); its
+ * coordinate is x_a = (v_a + u_a) / D_a in binary32 and its target the
+ * volume's cell-centred trilinear sample at x (as ngvol_sample_batch). */
+typedef struct ngvol_ooc ngvol_ooc;
+
+typedef struct ngvol_ooc_info {
+    int32_t dims[3], dtype, block, grid[3];
+    int64_t n_blocks, record_bytes, R, S;
+} ngvol_ooc_info;
+
+/* Write the bricked copy of a raw volume ([Dz][Dy][Dx], x fastest, FP32 or
+ * FP16 as dtype) that ngvol_ooc_open reads: a 4096-byte header, then one
+ * record per block, in block order, of (block + 2)^3 values x-fastest (the
+ * block and its ghost layer, indices clamped to the volume), padded to a
+ * multiple of 4096 bytes.  block in [2, 254].  Host only; EINVAL on a short
+ * or unreadable input or a failed write. */
+int ngvol_ooc_brick_file(const char* raw_path, const int32_t dims[3], int32_t dtype, int32_t block,
+                         const char* bricked_path);
+
+/* Open a bricked file for sampling with R slots and S refreshes per step
+ * (1 <= S <= R < 2^31), draws keyed by seed, n_threads host reader threads
+ * (1..64).  Allocates pinned host staging for two chunks of S records and a
+ * copy stream of its own (default priority) on the current device.  Host
+ * objects only; the caller owns the device buffer (ngvol_ooc_device_bytes). */
+int ngvol_ooc_open(const char* bricked_path, int64_t R, int64_t S, uint64_t seed, int32_t n_threads,
+                   ngvol_ooc** out);
+int ngvol_ooc_close(ngvol_ooc* ooc);
+int ngvol_ooc_get_info(const ngvol_ooc* ooc, ngvol_ooc_info* out);
+/* Bytes of the caller's device buffer: the R slots, a staging area for S
+ * records, and the slot table. */
+size_t ngvol_ooc_device_bytes(const ngvol_ooc* ooc);
+
+/* Load the blocks of step `step` into their slots of d_buf (16-byte
+ * aligned): all R at step 0, S from step 1 on; steps must follow each other
+ * (0, 1, 2, ...; 0 restarts).  The records are read on the host threads
+ * into pinned staging before the call returns; the copies and a placement
+ * kernel run on the library's copy stream after all work enqueued on
+ * `stream` before the call (so they may overlap whatever the caller enqueues
+ * next, e.g. the training step of the previous samples); the next
+ * ngvol_ooc_sample on `stream` waits for them. */
+int ngvol_ooc_refresh(ngvol_ooc* ooc, int64_t step, void* d_buf, hipStream_t stream);
+
+/* The B samples of step `step` (after its refresh): d_xyz [B][3] and
+ * d_target [B] (FP32, 4-byte aligned), on `stream`.  B < 2^31. */
+int ngvol_ooc_sample(ngvol_ooc* ooc, int64_t step, int64_t B, const void* d_buf, float* d_xyz, float* d_target,
+                     hipStream_t stream);
+
+/* Host copy of the block id held by each slot after the last refresh
+ * (R int32). */
+int ngvol_ooc_slots(const ngvol_ooc* ooc, int32_t* host_slot_block);
+
+/* ----------------------------------------------------------------------- */
 /* Batches of independent neural volumes                                   */
 /* ----------------------------------------------------------------------- */
 #define NGVOL_MULTI_MAX 16

@@ -87,6 +87,11 @@ class RenderOpts(C.Structure):
 RENDER_MODES = {"rm": 0, "rm_shadow": 1, "pt": 2}
 
 
+class OocInfo(C.Structure):
+    _fields_ = [("dims", C.c_int32 * 3), ("dtype", C.c_int32), ("block", C.c_int32), ("grid", C.c_int32 * 3),
+                ("n_blocks", C.c_int64), ("record_bytes", C.c_int64), ("R", C.c_int64), ("S", C.c_int64)]
+
+
 _P = C.c_void_p
 _SIGS = {
     "ngvol_last_error": (C.c_char_p, []),
@@ -120,6 +125,14 @@ _SIGS = {
     "ngvol_render_ex": (C.c_int, [_P, C.POINTER(Weights), C.POINTER(Camera), _P, C.c_int32, C.c_int32, C.c_float,
                                   C.c_uint32, _P, C.POINTER(RenderOpts), _P, _P, _P, _P, _P, C.c_size_t, _P]),
     "ngvol_mc_reset": (C.c_int, [_P, _P]),
+    "ngvol_ooc_brick_file": (C.c_int, [C.c_char_p, _P, C.c_int32, C.c_int32, C.c_char_p]),
+    "ngvol_ooc_open": (C.c_int, [C.c_char_p, C.c_int64, C.c_int64, C.c_uint64, C.c_int32, C.POINTER(_P)]),
+    "ngvol_ooc_close": (C.c_int, [_P]),
+    "ngvol_ooc_get_info": (C.c_int, [_P, C.POINTER(OocInfo)]),
+    "ngvol_ooc_device_bytes": (C.c_size_t, [_P]),
+    "ngvol_ooc_refresh": (C.c_int, [_P, C.c_int64, _P, _P]),
+    "ngvol_ooc_sample": (C.c_int, [_P, C.c_int64, C.c_int64, _P, _P, _P, _P]),
+    "ngvol_ooc_slots": (C.c_int, [_P, _P]),
     "ngvol_mc_update": (C.c_int, [_P, _P, _P, C.c_int64, _P]),
     "ngvol_mc_opacity": (C.c_int, [_P, _P, _P]),
     "ngvol_multi_table_bytes": (C.c_size_t, [C.c_int32]),
@@ -601,3 +614,56 @@ class Multi:
         if h is not None and _lib is not None:
             _lib.ngvol_multi_destroy(h)
             self.handle = None
+
+
+def ooc_brick_file(raw_path, dims, dtype, block, bricked_path):
+    """ngvol_ooc_brick_file: bricked copy (block^3 voxels per record plus a
+    ghost layer) of a raw [Dz][Dy][Dx] volume; dtype "f32" or "f16"."""
+    dt = {"f32": DT_F32, "f16": DT_F16}[dtype]
+    d = (C.c_int32 * 3)(*[int(v) for v in dims])
+    _check(lib().ngvol_ooc_brick_file(os.fsencode(raw_path), d, dt, int(block), os.fsencode(bricked_path)))
+
+
+class OutOfCore:
+    """Out-of-core sampler over a bricked volume file: R device-resident block
+    slots (S refreshed per step), samples drawn on the device."""
+
+    def __init__(self, bricked_path, R, S, seed, threads=8, device="cuda"):
+        torch = _torch()
+        h = C.c_void_p()
+        _check(lib().ngvol_ooc_open(os.fsencode(bricked_path), int(R), int(S), int(seed), int(threads),
+                                    C.byref(h)))
+        self._h = h
+        self.info = OocInfo()
+        _check(lib().ngvol_ooc_get_info(h, C.byref(self.info)))
+        self.buf = torch.empty(int(lib().ngvol_ooc_device_bytes(h)), dtype=torch.uint8, device=device)
+
+    def refresh(self, step):
+        _check(lib().ngvol_ooc_refresh(self._h, int(step), _ptr(self.buf), _stream()))
+
+    def sample(self, step, B, xyz=None, target=None):
+        torch = _torch()
+        if xyz is None:
+            xyz = torch.empty((B, 3), dtype=torch.float32, device=self.buf.device)
+        if target is None:
+            target = torch.empty(B, dtype=torch.float32, device=self.buf.device)
+        _check(lib().ngvol_ooc_sample(self._h, int(step), int(B), _ptr(self.buf), _ptr(xyz), _ptr(target),
+                                      _stream()))
+        return xyz, target
+
+    def slots(self):
+        import numpy as np
+        out = np.zeros(self.info.R, np.int32)
+        _check(lib().ngvol_ooc_slots(self._h, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value is not None:
+            lib().ngvol_ooc_close(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -128,6 +128,10 @@ int check_weights(const ngvol_weights* w) {
 
 namespace ngvol {
 
+// Error reporting for the entry points defined in other sources.
+int api_fail(int code, const char* msg) { return fail(code, "%s", msg); }
+int api_hip_check(hipError_t e, const char* what, hipStream_t st) { return hip_check(e, what, st); }
+
 TrainWorkspace train_workspace(const ngvol_plan* plan, int64_t B) {
   TrainWorkspace ws;
   auto up = [](size_t v) { return (v + 255) / 256 * 256; };
