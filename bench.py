@@ -106,6 +106,7 @@ def main():
     ap.add_argument("--no-render", action="store_true")
     ap.add_argument("--no-paper-default", action="store_true")
     ap.add_argument("--no-multi", action="store_true")
+    ap.add_argument("--no-ooc", action="store_true")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy, the reference for HBM byte counters")
@@ -243,6 +244,90 @@ def main():
                 "step_samples_per_s": (B_TRAIN + N_QUERY) / ((th_ + ih_) * 1e-3)}
         del sth
         log(f"fp16 train {th_:.3f} ms, sort+infer {ih_:.3f} ms")
+
+    # ------------------------------------------------- out-of-core sampling
+    # the 512^3 target as a bricked file (23^3-voxel blocks + ghost layer,
+    # 64 KB records; the file sits in the host page cache, so this measures
+    # the host read and transfer path, not a disk), a device buffer of
+    # R = 4096 blocks with S = 1024 replaced per step, and the training step
+    # fed from it; the refresh of step k+1 overlaps the training of step k
+    ooc = None
+    if not args.no_ooc:
+        import shutil
+        import tempfile
+        tmpd = tempfile.mkdtemp(prefix="ngvol_ooc_")
+        try:
+            raw, brk = os.path.join(tmpd, "v.raw"), os.path.join(tmpd, "v.brk")
+            vol_h.tofile(raw)
+            c0 = time.perf_counter()
+            ngv.ooc_brick_file(raw, (VOL_D,) * 3, "f32", 23, brk)
+            t_brick = time.perf_counter() - c0
+            os.remove(raw)
+            R_OOC, S_OOC = 4096, 1024
+            oc = ngv.OutOfCore(brk, R_OOC, S_OOC, SEED, threads=16)
+            rec = oc.info.record_bytes
+            sto = ngv.TrainState(plan16, params0, B_TRAIN, f16_tables=True)
+            xb = torch.empty((B_TRAIN, 3), dtype=torch.float32, device=dev)
+            yb = torch.empty(B_TRAIN, dtype=torch.float32, device=dev)
+            c0 = time.perf_counter()
+            oc.refresh(0)
+            torch.cuda.synchronize()
+            t_warm = time.perf_counter() - c0
+            n_o = 20
+            host_refresh = 0.0
+            for k in range(2):  # warm-up of the loop
+                oc.sample(k, B_TRAIN, xb, yb)
+                oc.refresh(k + 1)
+                ngv.train_step(sto, xyz=xb, target=yb, loss_scale=LOSS_SCALE, **ADAM)
+            torch.cuda.synchronize()
+            e = [ev() for _ in range(2)]
+            w0 = time.perf_counter()
+            e[0].record()
+            for k in range(2, 2 + n_o):
+                oc.sample(k, B_TRAIN, xb, yb)
+                h0 = time.perf_counter()
+                oc.refresh(k + 1)
+                host_refresh += time.perf_counter() - h0
+                ngv.train_step(sto, xyz=xb, target=yb, loss_scale=LOSS_SCALE, **ADAM)
+            e[1].record()
+            torch.cuda.synchronize()
+            ms_over = e[0].elapsed_time(e[1]) / n_o
+            wall_over = (time.perf_counter() - w0) / n_o * 1e3
+            # the same loop with the refresh finished before the step starts
+            e = [ev() for _ in range(2)]
+            w0 = time.perf_counter()
+            e[0].record()
+            for k in range(2 + n_o, 2 + 2 * n_o):
+                oc.sample(k, B_TRAIN, xb, yb)
+                oc.refresh(k + 1)
+                torch.cuda.synchronize()  # the copies finish before the step starts
+                ngv.train_step(sto, xyz=xb, target=yb, loss_scale=LOSS_SCALE, **ADAM)
+            e[1].record()
+            torch.cuda.synchronize()
+            wall_serial = (time.perf_counter() - w0) / n_o * 1e3
+            # in-core sampling of the same step, for reference
+            e = [ev() for _ in range(2)]
+            e[0].record()
+            for k in range(n_o):
+                ngv.train_step(sto, volume=vol, seed=SEED, step_index=k, loss_scale=LOSS_SCALE, **ADAM)
+            e[1].record()
+            torch.cuda.synchronize()
+            ms_in = e[0].elapsed_time(e[1]) / n_o
+            ooc = {"volume": f"{VOL_D}^3 f32 bricked, block 23 (+ghost), {rec} B records",
+                   "R": R_OOC, "S": S_OOC, "batch": B_TRAIN, "brick_file_s": round(t_brick, 2),
+                   "warmup_refresh_s": round(t_warm, 3),
+                   "step_ms_overlapped_wall": round(wall_over, 3), "step_ms_overlapped_gpu": round(ms_over, 3),
+                   "step_ms_serial_wall": round(wall_serial, 3), "step_ms_in_core": round(ms_in, 3),
+                   "host_refresh_ms": round(host_refresh / n_o * 1e3, 3),
+                   "refresh_read_GBps": round(S_OOC * rec / (host_refresh / n_o) / 1e9, 2),
+                   "samples_per_s": B_TRAIN / (wall_over * 1e-3)}
+            log(f"out-of-core: step {wall_over:.2f} ms overlapped, {wall_serial:.2f} ms serial "
+                f"(in-core {ms_in:.2f} ms); refresh {host_refresh / n_o * 1e3:.2f} ms host "
+                f"({ooc['refresh_read_GBps']} GB/s of records)")
+            oc.close()
+            del sto, xb, yb
+        finally:
+            shutil.rmtree(tmpd, ignore_errors=True)
 
     # ------------------------------------- paper-default training setting
     paper_default = None
@@ -666,7 +751,7 @@ def main():
                       "train_samples_per_s": B_TRAIN / (train_ms * 1e-3),
                       "infer_samples_per_s": N_QUERY / ((sort_ms + infer_ms) * 1e-3),
                       "infer_unsorted_ms": round(direct_ms, 4)},
-        "fp32_plain": fp32, "fp16_mfma": fp16, "paper_default_train": paper_default, "quality": quality, "render": render, "multi_volume": multi, "roofline": roofline,
+        "fp32_plain": fp32, "fp16_mfma": fp16, "paper_default_train": paper_default, "out_of_core": ooc, "quality": quality, "render": render, "multi_volume": multi, "roofline": roofline,
         "mlp_roofline": mlp_roofline, "cpu_baseline": cpu,
     }
     s = json.dumps(line)
