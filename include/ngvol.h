@@ -544,12 +544,14 @@ size_t ngvol_ooc_device_bytes(const ngvol_ooc* ooc);
 
 /* Load the blocks of step `step` into their slots of d_buf (16-byte
  * aligned): all R at step 0, S from step 1 on; steps must follow each other
- * (0, 1, 2, ...; 0 restarts).  The records are read on the host threads
- * into pinned staging before the call returns; the copies and a placement
- * kernel run on the library's copy stream after all work enqueued on
- * `stream` before the call (so they may overlap whatever the caller enqueues
- * next, e.g. the training step of the previous samples); the next
- * ngvol_ooc_sample on `stream` waits for them. */
+ * (0, 1, 2, ...; 0 restarts).  The records of a step are read by the host
+ * threads into pinned staging: in the background right after the previous
+ * refresh returns (the schedule is known in advance), else during the call.
+ * The copies and a placement kernel run on the library's copy stream after
+ * all work enqueued on `stream` before the call (so they may overlap
+ * whatever the caller enqueues next, e.g. the training step of the previous
+ * samples); the next ngvol_ooc_sample on `stream` waits for them.  One
+ * ngvol_ooc is used by one host thread at a time. */
 int ngvol_ooc_refresh(ngvol_ooc* ooc, int64_t step, void* d_buf, hipStream_t stream);
 
 /* The B samples of step `step` (after its refresh): d_xyz [B][3] and

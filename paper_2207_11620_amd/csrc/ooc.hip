@@ -121,12 +121,19 @@ struct ngvol_ooc {
   BrickHeader h{};
   int64_t R = 0, S = 0, last_step = -1;
   uint64_t seed = 0;
-  int n_threads = 1;
+  int n_threads = 1, device = 0;
   std::vector<int32_t> slot_block;
   unsigned char* pinned = nullptr;  // two halves of S records + S (slot, block) pairs
   size_t half_bytes = 0;
+  int next_half = 0;  // the pinned half the next chunk uses
   hipStream_t copy = nullptr;
   hipEvent_t ev_ready = nullptr, ev_done = nullptr, ev_half[2] = {nullptr, nullptr};
+  // the next step's records, read in the background after a refresh
+  std::thread prefetch;
+  int64_t pf_step = -1;
+  int pf_half = 0;
+  bool pf_ok = false;
+  std::vector<int32_t> pf_slot, pf_blk;
 };
 
 namespace {
@@ -194,6 +201,79 @@ __global__ void __launch_bounds__(256) k_ooc_sample(OocSampleArgs a) {
   a.xyz[3 * i + 0] = x[0];
   a.xyz[3 * i + 1] = x[1];
   a.xyz[3 * i + 2] = x[2];
+}
+
+// The loads of a step: (slot, block), all R slots at step 0, S from step 1.
+void loads_of(const ngvol_ooc* o, int64_t step, std::vector<int32_t>& slot, std::vector<int32_t>& blk) {
+  const int64_t R = o->R, S = o->S, nb = o->h.n_blocks;
+  const int64_t n = step == 0 ? R : S;
+  slot.resize((size_t)n);
+  blk.resize((size_t)n);
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t j = step == 0 ? i : R + (step - 1) * S + i;
+    slot[(size_t)i] = (int32_t)(step == 0 ? i : ((step - 1) * S + i) % R);
+    blk[(size_t)i] = (int32_t)pick(host_rng(o->seed, 9u, (uint64_t)j), nb);
+  }
+}
+
+// Reads n records into a pinned half on the reader threads and appends the
+// (slot, block) list the placement kernel reads.
+bool read_chunk(const ngvol_ooc* o, unsigned char* half, const int32_t* slot, const int32_t* blk, int64_t n) {
+  const int64_t rec = o->h.record_bytes;
+  const int nt = (int)std::min<int64_t>(o->n_threads, n);
+  std::vector<int> ok((size_t)nt, 1);
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nt; ++t)
+    pool.emplace_back([&, t]() {
+      for (int64_t i = t; i < n; i += nt)
+        if (!pread_all(o->fd, half + (size_t)i * (size_t)rec, (size_t)rec, kHeaderBytes + (int64_t)blk[i] * rec))
+          ok[(size_t)t] = 0;
+    });
+  for (auto& th : pool) th.join();
+  int32_t* list = reinterpret_cast<int32_t*>(half + (size_t)n * (size_t)rec);
+  for (int64_t i = 0; i < n; ++i) {
+    list[2 * i] = slot[i];
+    list[2 * i + 1] = blk[i];
+  }
+  for (int v : ok)
+    if (!v) return false;
+  return true;
+}
+
+// One staged chunk to the device: copy, then the placement kernel, on the
+// copy stream; the half is free again once ev_half[h] has passed.
+hipError_t enqueue_chunk(ngvol_ooc* o, int h, int64_t n, unsigned char* base, const OocLayout& L) {
+  const int64_t rec = o->h.record_bytes;
+  unsigned char* stage = base + L.stage_off;
+  hipError_t e = hipMemcpyAsync(stage, o->pinned + (size_t)h * o->half_bytes, (size_t)n * (size_t)rec + 8 * (size_t)n,
+                                hipMemcpyHostToDevice, o->copy);
+  if (e == hipSuccess) e = hipEventRecord(o->ev_half[h], o->copy);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_ooc_place, dim3((unsigned)n), dim3(256), 0, o->copy, stage, n, rec, base + L.slots_off,
+                       reinterpret_cast<int32_t*>(base + L.table_off));
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+void join_prefetch(ngvol_ooc* o) {
+  if (o->prefetch.joinable()) o->prefetch.join();
+}
+
+// Reads step `step`'s records into the next half in the background.
+void start_prefetch(ngvol_ooc* o, int64_t step) {
+  const int h = o->next_half;
+  o->next_half ^= 1;
+  o->pf_half = h;
+  o->pf_step = step;
+  o->pf_ok = false;
+  o->prefetch = std::thread([o, h, step]() {
+    (void)hipSetDevice(o->device);
+    if (hipEventSynchronize(o->ev_half[h]) != hipSuccess) return;  // its last copy has finished
+    loads_of(o, step, o->pf_slot, o->pf_blk);
+    o->pf_ok = read_chunk(o, o->pinned + (size_t)h * o->half_bytes, o->pf_slot.data(), o->pf_blk.data(),
+                          (int64_t)o->pf_slot.size());
+  });
 }
 
 }  // namespace
@@ -306,6 +386,7 @@ int ngvol_ooc_open(const char* bricked_path, int64_t R, int64_t S, uint64_t seed
   o->S = S;
   o->seed = seed;
   o->n_threads = n_threads;
+  if (hipGetDevice(&o->device) != hipSuccess) return bail(NGVOL_EDEVICE, "no current device");
   try {
     o->slot_block.assign((size_t)R, -1);
   } catch (const std::bad_alloc&) {
@@ -334,6 +415,7 @@ int ngvol_ooc_open(const char* bricked_path, int64_t R, int64_t S, uint64_t seed
 
 int ngvol_ooc_close(ngvol_ooc* o) {
   if (!o) return NGVOL_OK;
+  join_prefetch(o);
   if (o->copy) (void)hipStreamSynchronize(o->copy);
   for (hipEvent_t e : {o->ev_ready, o->ev_done, o->ev_half[0], o->ev_half[1]})
     if (e) (void)hipEventDestroy(e);
@@ -369,60 +451,39 @@ int ngvol_ooc_refresh(ngvol_ooc* o, int64_t step, void* d_buf, hipStream_t strea
   if (((uintptr_t)d_buf & 15u) != 0) return api_fail(NGVOL_EINVAL, "buffer must be 16-byte aligned");
   if (step < 0 || (step != 0 && step != o->last_step + 1))
     return api_fail(NGVOL_EINVAL, "refresh steps must follow each other (0, 1, 2, ...)");
-  const int64_t R = o->R, S = o->S, rec = o->h.record_bytes, nb = o->h.n_blocks;
-  // the loads of this step: (slot, block)
-  std::vector<int32_t> slot, blk;
-  const int64_t n_loads = step == 0 ? R : S;
-  slot.resize((size_t)n_loads);
-  blk.resize((size_t)n_loads);
-  for (int64_t i = 0; i < n_loads; ++i) {
-    const int64_t j = step == 0 ? i : R + (step - 1) * S + i;
-    slot[(size_t)i] = (int32_t)(step == 0 ? i : ((step - 1) * S + i) % R);
-    blk[(size_t)i] = (int32_t)pick(host_rng(o->seed, 9u, (uint64_t)j), nb);
-  }
-  const OocLayout L = layout_of(R, S, rec);
+  join_prefetch(o);
+  const bool have = o->pf_step == step && step >= 1 && o->pf_ok;
+  o->pf_step = -1;
+  const OocLayout L = layout_of(o->R, o->S, o->h.record_bytes);
   unsigned char* base = static_cast<unsigned char*>(d_buf);
   // copies start after the caller's earlier work on `stream`
   if (int rc = api_hip_check(hipEventRecord(o->ev_ready, stream), "ooc refresh", stream)) return rc;
   if (int rc = api_hip_check(hipStreamWaitEvent(o->copy, o->ev_ready, 0), "ooc refresh", stream)) return rc;
-  for (int64_t c0 = 0, chunk = 0; c0 < n_loads; c0 += S, ++chunk) {
-    const int64_t n = std::min(S, n_loads - c0);
-    const int hh = (int)(chunk & 1);
-    unsigned char* half = o->pinned + (size_t)hh * o->half_bytes;
-    if (int rc = api_hip_check(hipEventSynchronize(o->ev_half[hh]), "ooc staging", stream)) return rc;
-    // the records, read by the host threads
-    const int nt = (int)std::min<int64_t>(o->n_threads, n);
-    std::vector<int> ok((size_t)nt, 1);
-    std::vector<std::thread> pool;
-    for (int t = 0; t < nt; ++t)
-      pool.emplace_back([&, t]() {
-        for (int64_t i = t; i < n; i += nt)
-          if (!pread_all(o->fd, half + (size_t)i * (size_t)rec, (size_t)rec,
-                         kHeaderBytes + (int64_t)blk[(size_t)(c0 + i)] * rec))
-            ok[(size_t)t] = 0;
-      });
-    for (auto& th : pool) th.join();
-    for (int v : ok)
-      if (!v) return api_fail(NGVOL_EINVAL, "read of a block record failed");
-    int32_t* list = reinterpret_cast<int32_t*>(half + (size_t)n * (size_t)rec);
-    for (int64_t i = 0; i < n; ++i) {
-      list[2 * i] = slot[(size_t)(c0 + i)];
-      list[2 * i + 1] = blk[(size_t)(c0 + i)];
+  std::vector<int32_t> slot, blk;
+  if (have) {
+    // read in the background after the previous refresh
+    slot.swap(o->pf_slot);
+    blk.swap(o->pf_blk);
+    if (int rc = api_hip_check(enqueue_chunk(o, o->pf_half, (int64_t)slot.size(), base, L), "ooc refresh copy",
+                               o->copy))
+      return rc;
+  } else {
+    loads_of(o, step, slot, blk);
+    const int64_t n_loads = (int64_t)slot.size();
+    for (int64_t c0 = 0; c0 < n_loads; c0 += o->S) {
+      const int64_t n = std::min(o->S, n_loads - c0);
+      const int hh = o->next_half;
+      o->next_half ^= 1;
+      if (int rc = api_hip_check(hipEventSynchronize(o->ev_half[hh]), "ooc staging", stream)) return rc;
+      if (!read_chunk(o, o->pinned + (size_t)hh * o->half_bytes, slot.data() + c0, blk.data() + c0, n))
+        return api_fail(NGVOL_EINVAL, "read of a block record failed");
+      if (int rc = api_hip_check(enqueue_chunk(o, hh, n, base, L), "ooc refresh copy", o->copy)) return rc;
     }
-    unsigned char* stage = base + L.stage_off;
-    hipError_t e = hipMemcpyAsync(stage, half, (size_t)n * (size_t)rec + 8 * (size_t)n, hipMemcpyHostToDevice,
-                                  o->copy);
-    if (e == hipSuccess) e = hipEventRecord(o->ev_half[hh], o->copy);
-    if (e == hipSuccess) {
-      hipLaunchKernelGGL(k_ooc_place, dim3((unsigned)n), dim3(256), 0, o->copy, stage, n, rec, base + L.slots_off,
-                         reinterpret_cast<int32_t*>(base + L.table_off));
-      e = hipGetLastError();
-    }
-    if (int rc = api_hip_check(e, "ooc refresh copy", o->copy)) return rc;
   }
   if (int rc = api_hip_check(hipEventRecord(o->ev_done, o->copy), "ooc refresh", stream)) return rc;
-  for (int64_t i = 0; i < n_loads; ++i) o->slot_block[(size_t)slot[(size_t)i]] = blk[(size_t)i];
+  for (size_t i = 0; i < slot.size(); ++i) o->slot_block[(size_t)slot[i]] = blk[i];
   o->last_step = step;
+  start_prefetch(o, step + 1);
   return NGVOL_OK;
 }
 
