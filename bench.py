@@ -635,7 +635,8 @@ def main():
         multi = {"models": 16, "train_batch_each": 1 << 16, "queries_each": 1 << 20,
                  "train_eager_ms": round(eager_ms, 3), "train_graph_ms": round(graph_ms, 3),
                  "query_sequential_ms": round(seq_ms, 3), "query_batched_ms": round(bat_ms, 3),
-                 "autotune": {"blocks_per_cu": bpc, "chunk_tiles": chunk},
+                 "autotune": {"blocks_per_cu": bpc, "chunk_tiles": chunk,
+                              "strategy": "one launch per model" if bpc == 0 else "persistent launch"},
                  "aggregate_samples_per_s": (n_tr + n_q) / ((graph_ms + bat_ms) * 1e-3),
                  "sequential_samples_per_s": (n_tr + n_q) / ((eager_ms + seq_ms) * 1e-3)}
         log(f"multi: train eager {eager_ms:.2f} ms / graph {graph_ms:.2f} ms; query sequential {seq_ms:.2f} ms / "

@@ -583,20 +583,24 @@ int ngvol_multi_create(const ngvol_plan* const* plans, int32_t k, void* d_table,
                        hipStream_t stream, ngvol_multi** out);
 int ngvol_multi_destroy(ngvol_multi* group);
 
-/* Queries of all k models in one persistent launch: model i writes
- * Phi_i(xyz[i][j]) to out[i][j] for j < n[i], with weights w[i] (host arrays
- * of k entries; the pointers they hold are device pointers, either all with
- * or all without FP16 tables).  Work is cut into chunks of 16-sample tiles of
- * one model, ordered model by model; each workgroup walks a contiguous range
- * of chunks and restages the MLP weights in LDS when the model changes. */
+/* Queries of all k models in one call: model i writes Phi_i(xyz[i][j]) to
+ * out[i][j] for j < n[i], with weights w[i] (host arrays of k entries; the
+ * pointers they hold are device pointers, either all with or all without
+ * FP16 tables).  By default one persistent launch: work is cut into chunks
+ * of 16-sample tiles of one model, ordered model by model, taken grid-stride
+ * by the workgroups, which restage the MLP weights in LDS when the model
+ * changes.  After ngvol_multi_autotune it may instead issue one single-model
+ * launch per model, back to back on the stream, when that was faster (large
+ * models, each filling the GPU on its own). */
 int ngvol_multi_infer(const ngvol_multi* group, const ngvol_weights* w, const float* const* xyz, const int64_t* n,
                       float* const* out, hipStream_t stream);
 
 /* Autotuner: times the candidate launch shapes (workgroups per compute unit
- * x tiles per chunk) on these inputs (outputs are written), keeps the fastest
- * for later ngvol_multi_infer calls on the group and reports it (either
- * pointer may be NULL).  Synchronises the stream; not thread-safe with other
- * calls on the same group. */
+ * x tiles per chunk of the persistent launch, and one launch per model) on
+ * these inputs (outputs are written), keeps the fastest for later
+ * ngvol_multi_infer calls on the group and reports it (either pointer may be
+ * NULL; 0 and 0 for one launch per model).  Synchronises the stream; not
+ * thread-safe with other calls on the same group. */
 int ngvol_multi_autotune(ngvol_multi* group, const ngvol_weights* w, const float* const* xyz, const int64_t* n,
                          float* const* out, hipStream_t stream, int32_t* blocks_per_cu, int32_t* chunk_tiles);
 

@@ -819,8 +819,9 @@ int ngvol_render(const ngvol_plan* plan, const ngvol_weights* w, const ngvol_cam
 struct ngvol_multi {
   int k;
   ngvol_plan plan0;  // shape shared by the group (precision, widths, device)
+  ngvol_plan plans[NGVOL_MULTI_MAX];  // copies, for per-model launches
   ngvol::ModelDesc* table;  // device
-  int blocks_per_cu;
+  int blocks_per_cu;  // 0: one single-model launch per model
   int chunk_tiles;
 };
 
@@ -851,6 +852,23 @@ int multi_args(const ngvol_multi* g, const ngvol_weights* w, const float* const*
   return NGVOL_OK;
 }
 
+
+// The group's queries: one persistent launch over all models
+// (blocks_per_cu > 0), or back-to-back single-model launches (0), which
+// the autotuner picks when the models are large enough for one launch each
+// to fill the GPU.
+hipError_t multi_launch(const ngvol_multi* g, const ngvol_weights* w, const MultiArgs& a, bool f16, int bpc,
+                        hipStream_t st) {
+  if (bpc > 0) return launch_multi_infer(&g->plan0, g->table, a, f16, bpc, st);
+  for (int i = 0; i < g->k; ++i) {
+    if (a.n[i] == 0) continue;
+    const ngvol_plan* p = &g->plans[i];
+    hipError_t e = launch_infer(p, tables_of(p, &w[i]), w[i].params + p->md.n_table, a.xyz[i], nullptr, a.n[i],
+                                a.out[i], st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
 }  // namespace
 
 extern "C" {
@@ -877,6 +895,7 @@ int ngvol_multi_create(const ngvol_plan* const* plans, int32_t k, void* d_table,
   if (!g) return fail(NGVOL_ENOMEM, "out of host memory");
   g->k = k;
   g->plan0 = *plans[0];
+  for (int i = 0; i < k; ++i) g->plans[i] = *plans[i];
   g->table = reinterpret_cast<ngvol::ModelDesc*>(d_table);
   g->blocks_per_cu = 8;
   g->chunk_tiles = 32;
@@ -902,9 +921,9 @@ int ngvol_multi_infer(const ngvol_multi* g, const ngvol_weights* w, const float*
   NGV_REQUIRE(g, "group is NULL");
   MultiArgs a;
   bool f16 = false;
-  if (int rc = multi_args(g, w, xyz, n, out, g->chunk_tiles, a, f16)) return rc;
+  if (int rc = multi_args(g, w, xyz, n, out, g->chunk_tiles > 0 ? g->chunk_tiles : 16, a, f16)) return rc;
   if (a.item_prefix[g->k] == 0) return NGVOL_OK;
-  return hip_check(launch_multi_infer(&g->plan0, g->table, a, f16, g->blocks_per_cu, st), "multi_infer launch", st);
+  return hip_check(multi_launch(g, w, a, f16, g->blocks_per_cu, st), "multi_infer launch", st);
 }
 
 int ngvol_multi_autotune(ngvol_multi* g, const ngvol_weights* w, const float* const* xyz, const int64_t* n,
@@ -927,9 +946,9 @@ int ngvol_multi_autotune(ngvol_multi* g, const ngvol_weights* w, const float* co
         return rc;
       }
       if (a.item_prefix[g->k] == 0) break;
-      e = launch_multi_infer(&g->plan0, g->table, a, f16, kBpc[bi], st);  // warm-up
+      e = multi_launch(g, w, a, f16, kBpc[bi], st);  // warm-up
       if (e == hipSuccess) e = hipEventRecord(e0, st);
-      for (int r = 0; r < 2 && e == hipSuccess; ++r) e = launch_multi_infer(&g->plan0, g->table, a, f16, kBpc[bi], st);
+      for (int r = 0; r < 2 && e == hipSuccess; ++r) e = multi_launch(g, w, a, f16, kBpc[bi], st);
       if (e == hipSuccess) e = hipEventRecord(e1, st);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0.0f;
@@ -940,6 +959,28 @@ int ngvol_multi_autotune(ngvol_multi* g, const ngvol_weights* w, const float* co
         best_c = kChunk[ci];
       }
     }
+  // one single-model launch per model
+  if (e == hipSuccess) {
+    MultiArgs a;
+    bool f16 = false;
+    if (int rc = multi_args(g, w, xyz, n, out, 16, a, f16)) {
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      return rc;
+    }
+    e = multi_launch(g, w, a, f16, 0, st);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    for (int r = 0; r < 2 && e == hipSuccess; ++r) e = multi_launch(g, w, a, f16, 0, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess && ms < best) {
+      best = ms;
+      best_b = 0;
+      best_c = 0;
+    }
+  }
   if (e0) hipEventDestroy(e0);
   if (e1) hipEventDestroy(e1);
   if (e != hipSuccess) return hip_check(e, "multi autotune", st);
