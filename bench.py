@@ -603,8 +603,20 @@ def main():
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph):
             train_all()
+        grp = ngv.Multi(mplans)
+        mseeds = [sp["seed"] for sp in specs]
+
+        def train_forked():
+            grp.train_step(mstates, mvols, mseeds, step_index=-1, loss_scale=LOSS_SCALE, **ADAM)
+
+        with torch.cuda.stream(side):
+            train_forked()  # warm-up
+        torch.cuda.current_stream().wait_stream(side)
+        graph_f = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph_f):
+            train_forked()
         reps = 5
-        e = [ev() for _ in range(3)]
+        e = [ev() for _ in range(5)]
         e[0].record()
         for _ in range(reps):
             train_all()
@@ -612,10 +624,17 @@ def main():
         for _ in range(reps):
             graph.replay()
         e[2].record()
+        for _ in range(reps):
+            train_forked()
+        e[3].record()
+        for _ in range(reps):
+            graph_f.replay()
+        e[4].record()
         torch.cuda.synchronize()
         eager_ms = e[0].elapsed_time(e[1]) / reps
         graph_ms = e[1].elapsed_time(e[2]) / reps
-        grp = ngv.Multi(mplans)
+        forked_ms = e[2].elapsed_time(e[3]) / reps
+        forked_graph_ms = e[3].elapsed_time(e[4]) / reps
         wts = [(s_.params, s_.table_f16) for s_ in mstates]
         bpc, chunk = grp.autotune(wts, mxyz, mout)
         e = [ev() for _ in range(3)]
@@ -634,14 +653,16 @@ def main():
         n_tr, n_q = 16 * (1 << 16), 16 * (1 << 20)
         multi = {"models": 16, "train_batch_each": 1 << 16, "queries_each": 1 << 20,
                  "train_eager_ms": round(eager_ms, 3), "train_graph_ms": round(graph_ms, 3),
+                 "train_batched_ms": round(forked_ms, 3), "train_batched_graph_ms": round(forked_graph_ms, 3),
                  "query_sequential_ms": round(seq_ms, 3), "query_batched_ms": round(bat_ms, 3),
                  "autotune": {"blocks_per_cu": bpc, "chunk_tiles": chunk,
                               "strategy": "one launch per model" if bpc == 0 else "persistent launch"},
-                 "aggregate_samples_per_s": (n_tr + n_q) / ((graph_ms + bat_ms) * 1e-3),
+                 "aggregate_samples_per_s": (n_tr + n_q) / ((min(graph_ms, forked_graph_ms) + bat_ms) * 1e-3),
                  "sequential_samples_per_s": (n_tr + n_q) / ((eager_ms + seq_ms) * 1e-3)}
-        log(f"multi: train eager {eager_ms:.2f} ms / graph {graph_ms:.2f} ms; query sequential {seq_ms:.2f} ms / "
+        log(f"multi: train eager {eager_ms:.2f} ms / graph {graph_ms:.2f} ms / batched (forked) {forked_ms:.2f} ms / "
+            f"batched graph {forked_graph_ms:.2f} ms; query sequential {seq_ms:.2f} ms / "
             f"batched {bat_ms:.2f} ms (autotune {bpc} wg/CU, {chunk} tiles)")
-        del grp, mstates, mvols, mxyz, mout, graph
+        del grp, mstates, mvols, mxyz, mout, graph, graph_f
 
     # ----------------------------------------------- standalone MLP on MFMA
     # k_mlp_fwd over an HBM-resident BF16 feature buffer [2^24][32]: the

@@ -604,6 +604,18 @@ int ngvol_multi_infer(const ngvol_multi* group, const ngvol_weights* w, const fl
 int ngvol_multi_autotune(ngvol_multi* group, const ngvol_weights* w, const float* const* xyz, const int64_t* n,
                          float* const* out, hipStream_t stream, int32_t* blocks_per_cu, int32_t* chunk_tiles);
 
+/* Training steps of all k models of the group in one call (Section 4 per
+ * model; the batch of volumes of the multi-volume workload): model i takes
+ * one ngvol_train_step with states[i] and batches[i] (host arrays of k
+ * entries, distinct states) and the shared Adam settings and loss scale.
+ * Every model's arguments are checked before anything is launched.  The steps
+ * are spread over the group's own streams (up to 4), forked from `stream`
+ * and joined back to it, so small steps of different models run
+ * concurrently; captured on `stream`, the call becomes a graph with parallel
+ * branches.  Results equal k separate ngvol_train_step calls. */
+int ngvol_multi_train_step(const ngvol_multi* group, const ngvol_train_state* states, const ngvol_batch* batches,
+                           const ngvol_adam* adam, float loss_scale, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -141,6 +141,8 @@ _SIGS = {
     "ngvol_multi_infer": (C.c_int, [_P, C.POINTER(Weights), C.POINTER(_P), C.POINTER(C.c_int64), C.POINTER(_P), _P]),
     "ngvol_multi_autotune": (C.c_int, [_P, C.POINTER(Weights), C.POINTER(_P), C.POINTER(C.c_int64), C.POINTER(_P),
                                        _P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "ngvol_multi_train_step": (C.c_int, [_P, C.POINTER(TrainStateC), C.POINTER(Batch), C.POINTER(Adam), C.c_float,
+                                         _P]),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -608,6 +610,17 @@ class Multi:
         b, c = C.c_int32(), C.c_int32()
         _check(lib().ngvol_multi_autotune(self.handle, W, X, N, O, _stream(), C.byref(b), C.byref(c)))
         return b.value, c.value
+
+    def train_step(self, states, volumes, seeds, step_index=-1, lr=1e-2, betas=(0.9, 0.99), eps=1e-15,
+                   loss_scale=1.0, l2_reg=0.0, decay=None):
+        """ngvol_multi_train_step: one training step of every model (states[i]
+        on generated batches of volumes[i] with seeds[i]); step_index -1 draws
+        each model's batch by its device draw counter (graph-replayable)."""
+        k = self.k
+        S = (TrainStateC * k)(*[st._c for st in states])
+        Bt = (Batch * k)(*[_volume_batch(v, st.batch_size, sd, step_index) for st, v, sd in zip(states, volumes, seeds)])
+        a = _adam(lr, betas, eps, l2_reg, decay)
+        _check(lib().ngvol_multi_train_step(self.handle, S, Bt, C.byref(a), float(loss_scale), _stream()))
 
     def __del__(self):
         h = getattr(self, "handle", None)

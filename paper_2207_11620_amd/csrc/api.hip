@@ -630,19 +630,31 @@ static AdamArgs adam_args(const ngvol_adam* a, float loss_scale) {
   return aa;
 }
 
-int ngvol_train_step(const ngvol_plan* plan, const ngvol_train_state* s, const ngvol_batch* b, const ngvol_adam* a,
-                     float loss_scale, hipStream_t st) {
+}  // extern "C"
+
+namespace {
+
+// A training step's host-side checks, done before anything is launched.
+int train_prepare(const ngvol_plan* plan, const ngvol_train_state* s, const ngvol_batch* b, const ngvol_adam* a,
+                  float loss_scale, BatchArgs& ba, TrainWorkspace& ws) {
   if (int rc = check_plan(plan)) return rc;
   if (int rc = check_state(plan, s)) return rc;
   if (int rc = check_adam(a, loss_scale)) return rc;
   if (int rc = check_bwd_lds(plan)) return rc;
-  BatchArgs ba{};
+  NGV_REQUIRE(b, "batch is NULL");
+  ba = BatchArgs{};
   if (int rc = resolve_batch(plan, b, ba)) return rc;
   if (!b->xyz && b->step_index < 0) ba.step_ptr = s->draws ? s->draws : s->step;  // graph-replayable batch index
   if (int rc = check_train_limits(plan, ba.B)) return rc;
-  const TrainWorkspace ws = train_workspace(plan, ba.B);
+  ws = train_workspace(plan, ba.B);
   if (s->workspace_bytes < ws.total)
     return fail(NGVOL_ENOMEM, "workspace of %zu bytes < %zu needed", s->workspace_bytes, ws.total);
+  return NGVOL_OK;
+}
+
+// The step's launches: sampling and forward, backward, scatter, Adam.
+hipError_t train_enqueue(const ngvol_plan* plan, const ngvol_train_state* s, const BatchArgs& ba,
+                         const TrainWorkspace& ws, const ngvol_adam* a, float loss_scale, hipStream_t st) {
   char* base = reinterpret_cast<char*>(s->workspace);
   void* e_buf = base + ws.e_off;
   float* g_buf = reinterpret_cast<float*>(base + ws.g_off);
@@ -676,7 +688,19 @@ int ngvol_train_step(const ngvol_plan* plan, const ngvol_train_state* s, const n
                     flag, aa, st);
   if (e == hipSuccess)
     e = launch_step_end(loss_acc, flag, s->step, s->draws, s->skipped, s->loss, 1.0 / (double)ba.B, st);
-  return hip_check(e, "train_step launch", st);
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ngvol_train_step(const ngvol_plan* plan, const ngvol_train_state* s, const ngvol_batch* b, const ngvol_adam* a,
+                     float loss_scale, hipStream_t st) {
+  BatchArgs ba;
+  TrainWorkspace ws;
+  if (int rc = train_prepare(plan, s, b, a, loss_scale, ba, ws)) return rc;
+  return hip_check(train_enqueue(plan, s, ba, ws, a, loss_scale, st), "train_step launch", st);
 }
 
 int ngvol_adam_step(const ngvol_plan* plan, const ngvol_train_state* s, const ngvol_adam* a, float loss_scale,
@@ -823,7 +847,23 @@ struct ngvol_multi {
   ngvol::ModelDesc* table;  // device
   int blocks_per_cu;  // 0: one single-model launch per model
   int chunk_tiles;
+  // batched training: the models' steps run on these streams, forked from
+  // and joined back to the caller's stream
+  static constexpr int kStreams = 4;
+  hipStream_t streams[kStreams] = {};
+  hipEvent_t ev_fork = nullptr, ev_join[kStreams] = {};
 };
+
+namespace {
+void multi_release(ngvol_multi* g) {
+  for (int j = 0; j < ngvol_multi::kStreams; ++j) {
+    if (g->ev_join[j]) (void)hipEventDestroy(g->ev_join[j]);
+    if (g->streams[j]) (void)hipStreamDestroy(g->streams[j]);
+  }
+  if (g->ev_fork) (void)hipEventDestroy(g->ev_fork);
+  delete g;
+}
+}  // namespace
 
 namespace {
 
@@ -903,17 +943,49 @@ int ngvol_multi_create(const ngvol_plan* const* plans, int32_t k, void* d_table,
   for (int i = 0; i < k; ++i) host[i] = plans[i]->md;
   hipError_t e = hipMemcpyAsync(d_table, host, sizeof(ngvol::ModelDesc) * k, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming);
+  for (int j = 0; j < ngvol_multi::kStreams && e == hipSuccess; ++j) {
+    e = hipStreamCreateWithFlags(&g->streams[j], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&g->ev_join[j], hipEventDisableTiming);
+  }
   if (e != hipSuccess) {
-    delete g;
-    return hip_check(e, "multi descriptor upload", st);
+    multi_release(g);
+    return hip_check(e, "multi group set-up", st);
   }
   *out = g;
   return NGVOL_OK;
 }
 
 int ngvol_multi_destroy(ngvol_multi* g) {
-  delete g;
+  if (g) {
+    for (int j = 0; j < ngvol_multi::kStreams; ++j)
+      if (g->streams[j]) (void)hipStreamSynchronize(g->streams[j]);
+    multi_release(g);
+  }
   return NGVOL_OK;
+}
+
+int ngvol_multi_train_step(const ngvol_multi* g, const ngvol_train_state* states, const ngvol_batch* batches,
+                           const ngvol_adam* adam, float loss_scale, hipStream_t st) {
+  NGV_REQUIRE(g && states && batches, "group, states and batches must be non-NULL");
+  BatchArgs ba[NGVOL_MULTI_MAX];
+  TrainWorkspace ws[NGVOL_MULTI_MAX];
+  for (int i = 0; i < g->k; ++i)
+    if (int rc = train_prepare(&g->plans[i], &states[i], &batches[i], adam, loss_scale, ba[i], ws[i])) return rc;
+  for (int i = 0; i < g->k; ++i)
+    for (int j = 0; j < i; ++j)
+      NGV_REQUIRE(states[i].workspace != states[j].workspace && states[i].params != states[j].params,
+                  "models %d and %d share a training state", j, i);
+  const int ns = g->k < ngvol_multi::kStreams ? g->k : ngvol_multi::kStreams;
+  hipError_t e = hipEventRecord(g->ev_fork, st);
+  for (int j = 0; j < ns && e == hipSuccess; ++j) e = hipStreamWaitEvent(g->streams[j], g->ev_fork, 0);
+  for (int i = 0; i < g->k && e == hipSuccess; ++i)
+    e = train_enqueue(&g->plans[i], &states[i], ba[i], ws[i], adam, loss_scale, g->streams[i % ns]);
+  for (int j = 0; j < ns && e == hipSuccess; ++j) {
+    e = hipEventRecord(g->ev_join[j], g->streams[j]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, g->ev_join[j], 0);
+  }
+  return hip_check(e, "multi train_step launch", st);
 }
 
 int ngvol_multi_infer(const ngvol_multi* g, const ngvol_weights* w, const float* const* xyz, const int64_t* n,

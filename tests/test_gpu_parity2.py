@@ -276,6 +276,48 @@ def test_multi_model_training_graph_matches_eager():
         np.testing.assert_array_equal(host(a.table_f16), host(a.params[:plans[i].n_table_params].half()))
 
 
+def test_multi_train_step_forked_and_graphed_matches_eager():
+    # ngvol_multi_train_step: the 16 models' steps forked over the group's
+    # streams, eagerly and captured in one graph (parallel branches), against
+    # per-model eager steps
+    specs = synth.multi_volume_specs(16)
+    plans, params, vols = [], [], []
+    for i, sp in enumerate(specs):
+        p = ngv.Plan(sp["L"], 2, sp["log2T"], 16, 0.0, 2048, n_neurons=64, n_hidden_layers=2, precision="bf16")
+        plans.append(p)
+        params.append(dev(synth.init_params(p.n_table_params, p.n_input, 64, 2, 0.05, sp["seed"])))
+        v = synth.gaussian_blobs(24, sp["seed"]) if i % 2 == 0 else synth.fractal_value_noise(24, sp["seed"])
+        vols.append(dev(v.astype(np.float16)))
+    seeds = [SEED + i for i in range(16)]
+    B, steps = 4096, 4
+    eager = [ngv.TrainState(p, w, B, f16_tables=True) for p, w in zip(plans, params)]
+    for k in range(steps):
+        for st, v, sd in zip(eager, vols, seeds):
+            ngv.train_step(st, volume=v, seed=sd, step_index=k, loss_scale=128.0)
+    grp = ngv.Multi(plans)
+    forked = [ngv.TrainState(p, w, B, f16_tables=True) for p, w in zip(plans, params)]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        grp.train_step(forked, vols, seeds, step_index=-1, loss_scale=128.0)   # step 0, eager
+        grp.train_step(forked, vols, seeds, step_index=-1, loss_scale=128.0)   # step 1, eager
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        grp.train_step(forked, vols, seeds, step_index=-1, loss_scale=128.0)
+    for _ in range(steps - 2):
+        g.replay()
+        torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(forked, eager)):
+        assert host(a.step)[0] == steps and host(a.draws)[0] == steps, i
+        d = np.abs(host(a.params) - host(b.params))
+        assert np.quantile(d, 0.999) <= 1e-5, i
+        assert host(a.loss)[0] == pytest.approx(host(b.loss)[0], rel=1e-3), i
+    # a state given twice is refused before anything runs
+    with pytest.raises(RuntimeError):
+        grp.train_step([forked[0]] * 16, vols, seeds)
+
+
 # --------------------------------------------- trained-model BF16 bound -----
 
 def test_bf16_trained_model_within_2e2_absolute():
