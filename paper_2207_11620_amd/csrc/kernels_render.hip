@@ -80,10 +80,11 @@ struct SlotState {
   float wmax, T;
 };
 
-// Macro-cell modes, per slot: this round's samples (empty-space skipping:
-// those in a non-empty macro-cell; adaptive marching: the samples of the
-// adaptive walk), the grid steps each stands for (adaptive), their count,
-// and the first sample index after the round.
+// Macro-cell modes, per slot: this round's samples (the walk through the
+// cells: empty-space skipping lists the samples of non-empty cells,
+// adaptive marching one sample per adaptive step), the grid steps each
+// stands for (adaptive), their count, and the first sample index after the
+// round.
 constexpr int kSpan = kK;
 constexpr int kCnt = 2 * kK, kNext = 2 * kK + 1;
 constexpr int kList = 2 * kK + 2;
@@ -200,41 +201,11 @@ k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs r
     // any live slot in this wave?
     const bool live = lane < kSlots && slots[lane].pix >= 0;
     if (!__any(live)) break;
-    if constexpr (skip_empty) {
-      // each slot's next 64 samples are checked against the macro-cells, one
-      // per lane; the first kK in a non-empty cell are this round's samples
-      for (int s = 0; s < kSlots; ++s) {
-        const SlotState& so = slots[s];
-        const uint32_t k0 = so.k, n = so.g.n;
-        const uint32_t c = k0 + (uint32_t)lane;
-        bool in = false;
-        if (so.pix >= 0 && c < n) {
-          float x, y, z;
-          ray_point(so.g, c, ra.dt, x, y, z);
-          in = ra.mc.mu[mc_index(ra.mc, clamp01(x), clamp01(y), clamp01(z))] > 0.0f;
-        }
-        const unsigned long long mask = __ballot(in);
-        const uint32_t below = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-        const uint32_t total = (uint32_t)__popcll(mask);
-        uint32_t next = k0 + 64u;
-        if (total >= (uint32_t)kK) {
-          const unsigned long long last = __ballot(in && below == (uint32_t)kK - 1u);
-          next = k0 + (uint32_t)(__ffsll((unsigned long long)last) - 1) + 1u;
-        }
-        __builtin_amdgcn_wave_barrier();
-        if (in && below < (uint32_t)kK) lst[s * kList + below] = c;
-        if (lane == 0) {
-          lst[s * kList + kCnt] = total < (uint32_t)kK ? total : (uint32_t)kK;
-          lst[s * kList + kNext] = next < n ? next : n;
-        }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      }
-    }
-    if constexpr (adaptive) {
+    if constexpr (skip_empty || adaptive) {
       // each slot's owner lane walks its ray: a transparent cell is passed
-      // whole, an opaque one gives a sample standing for adaptive_steps of
-      // the cell's mu grid steps (cut at the cell's exit)
+      // whole (a DDA jump to its exit); in an opaque cell every sample is
+      // listed (skipping), or one sample stands for adaptive_steps of the
+      // cell's mu grid steps, cut at the cell's exit (adaptive marching)
       if (lane < kSlots) {
         const SlotState& so = slots[lane];
         uint32_t k = so.k, cnt = 0;
@@ -246,7 +217,7 @@ k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs r
               k = cell_exit(so.g, k, ra.dt, ra.mc);
               continue;
             }
-            const uint32_t steps = adaptive_steps(mu, ra.step_max, ra.step_exp);
+            const uint32_t steps = adaptive ? adaptive_steps(mu, ra.step_max, ra.step_exp) : 1u;
             uint32_t kn = k + 1;
             if (steps > 1) {
               const uint32_t ke = cell_exit(so.g, k, ra.dt, ra.mc);
