@@ -126,9 +126,13 @@ k_infer(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, const float* 
 }
 
 // ---------------------------------------------------------------------------
-// Standalone MLP on given features ([n][n_in], FP32 or BF16).
+// Standalone MLP on given features ([n][n_in], FP32 or BF16).  DIRECT: the
+// features are stored in the operand type with n_in = KIN, so a lane's
+// operand block is one 16-byte load; otherwise they are converted element by
+// element (zero beyond n_in).  The two loaders are separate instantiations,
+// so the direct kernel carries none of the element-wise code.
 // ---------------------------------------------------------------------------
-template <int P, int KIN, int W, typename IT, int NHC>
+template <int P, int KIN, int W, typename IT, int NHC, bool DIRECT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mlp_waves_per_eu(P, KIN, NHC))))
 k_mlp_fwd(ModelDesc md, const float* __restrict__ mlp,
                                                  const IT* __restrict__ feat, int64_t n, float* __restrict__ out) {
@@ -157,8 +161,9 @@ k_mlp_fwd(ModelDesc md, const float* __restrict__ mlp,
     const int64_t s = (grp * NB + nb) * 16 + nl;
     if (s < n && g == 0) out[s] = y;
   };
-  if constexpr (P != 0 && std::is_same<IT, typename Prec<P>::T>::value) {
-    if (n_in == KIN) {
+  if constexpr (DIRECT) {
+    static_assert(P != 0 && std::is_same<IT, typename Prec<P>::T>::value, "direct loads need operand-typed features");
+    {
       // the stored 16-bit features are the operand: one 16-byte load per lane per block
       struct Raw {
         Frag f[NB][KIN / 32];
@@ -179,39 +184,39 @@ k_mlp_fwd(ModelDesc md, const float* __restrict__ mlp,
               for (int b = 0; b < KIN / 32; ++b) in[nb][b] = r.f[nb][b];
           },
           st);
-      return;
     }
+  } else {
+    struct Raw {
+      IT v[NB][KIN / 32][8];
+    };
+    mlp_stream<P, KIN, W, NB, Raw, NHC>(
+        md.n_hidden, md.out_relu != 0, lds_frag, lds_wout, it.next, it.step, it.end,
+        [&](int64_t grp, Raw& r) {
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            const int64_t sc = row(grp, nb);
+#pragma unroll
+            for (int b = 0; b < KIN / 32; ++b)
+#pragma unroll
+              for (int jj = 0; jj < 8; ++jj) {
+                const int k = 32 * b + 8 * g + jj;
+                r.v[nb][b][jj] = k < n_in ? feat[sc * n_in + k] : (IT)0.0f;
+              }
+          }
+        },
+        [&](const Raw& r, Frag (*in)[CH0]) {
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            float f[KIN / 32][8];
+#pragma unroll
+            for (int b = 0; b < KIN / 32; ++b)
+#pragma unroll
+              for (int jj = 0; jj < 8; ++jj) f[b][jj] = (float)r.v[nb][b][jj];
+            feat_to_frag<P, KIN>(f, in[nb]);
+          }
+        },
+        st);
   }
-  struct Raw {
-    IT v[NB][KIN / 32][8];
-  };
-  mlp_stream<P, KIN, W, NB, Raw, NHC>(
-      md.n_hidden, md.out_relu != 0, lds_frag, lds_wout, it.next, it.step, it.end,
-      [&](int64_t grp, Raw& r) {
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          const int64_t sc = row(grp, nb);
-#pragma unroll
-          for (int b = 0; b < KIN / 32; ++b)
-#pragma unroll
-            for (int jj = 0; jj < 8; ++jj) {
-              const int k = 32 * b + 8 * g + jj;
-              r.v[nb][b][jj] = k < n_in ? feat[sc * n_in + k] : (IT)0.0f;
-            }
-        }
-      },
-      [&](const Raw& r, Frag (*in)[CH0]) {
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          float f[KIN / 32][8];
-#pragma unroll
-          for (int b = 0; b < KIN / 32; ++b)
-#pragma unroll
-            for (int jj = 0; jj < 8; ++jj) f[b][jj] = (float)r.v[nb][b][jj];
-          feat_to_frag<P, KIN>(f, in[nb]);
-        }
-      },
-      st);
 }
 
 // ---------------------------------------------------------------------------
@@ -280,29 +285,30 @@ hipError_t launch_mlp_fwd_p(const ngvol_plan* plan, const float* mlp, const void
   const int64_t n_tiles = (n + 31) / 32;  // 2-tile groups
   const size_t lds = fwd_lds_bytes(plan);
   const int grid = grid_for(plan, n_tiles, 4, 8);
+#define NGV_MLPF(IT, NHC)                                                                                      \
+  do {                                                                                                         \
+    if constexpr (P != 0 && std::is_same<IT, typename Prec<P>::T>::value) {                                    \
+      if (md.n_in == KIN) {                                                                                    \
+        hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, IT, NHC, true>), dim3(grid), dim3(256), lds, st, md, mlp,     \
+                           (const IT*)feat, n, out);                                                           \
+        break;                                                                                                 \
+      }                                                                                                        \
+    }                                                                                                          \
+    hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, IT, NHC, false>), dim3(grid), dim3(256), lds, st, md, mlp,        \
+                       (const IT*)feat, n, out);                                                               \
+  } while (0)
   NGV_DISPATCH_KIN(plan->kin, {
     if (md.n_hidden == 2) {
-      if (dtype == NGVOL_DT_BF16)
-        hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, __bf16, 2>), dim3(grid), dim3(256), lds, st, md, mlp,
-                           (const __bf16*)feat, n, out);
-      else if (dtype == NGVOL_DT_F16)
-        hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, _Float16, 2>), dim3(grid), dim3(256), lds, st, md, mlp,
-                           (const _Float16*)feat, n, out);
-      else
-        hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, float, 2>), dim3(grid), dim3(256), lds, st, md, mlp,
-                           (const float*)feat, n, out);
+      if (dtype == NGVOL_DT_BF16) NGV_MLPF(__bf16, 2);
+      else if (dtype == NGVOL_DT_F16) NGV_MLPF(_Float16, 2);
+      else NGV_MLPF(float, 2);
     } else {
-      if (dtype == NGVOL_DT_BF16)
-        hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, __bf16, 0>), dim3(grid), dim3(256), lds, st, md, mlp,
-                           (const __bf16*)feat, n, out);
-      else if (dtype == NGVOL_DT_F16)
-        hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, _Float16, 0>), dim3(grid), dim3(256), lds, st, md, mlp,
-                           (const _Float16*)feat, n, out);
-      else
-        hipLaunchKernelGGL((k_mlp_fwd<P, KIN, W, float, 0>), dim3(grid), dim3(256), lds, st, md, mlp,
-                           (const float*)feat, n, out);
+      if (dtype == NGVOL_DT_BF16) NGV_MLPF(__bf16, 0);
+      else if (dtype == NGVOL_DT_F16) NGV_MLPF(_Float16, 0);
+      else NGV_MLPF(float, 0);
     }
   });
+#undef NGV_MLPF
   return hipGetLastError();
 }
 
