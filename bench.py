@@ -681,11 +681,27 @@ def main():
     mlp_ms = e[0].elapsed_time(e[1]) / 10
     flop = 2 * (32 * 64 + 64 * 64 + 64)
     tf = flop * N_QUERY / (mlp_ms * 1e-3) / 1e12
+    # context for both rooflines: what a plain 4 GiB device-to-device copy
+    # reaches on this machine (read + write bytes per second)
+    cp_src = torch.empty(1 << 30, dtype=torch.float32, device=dev)
+    cp_dst = torch.empty_like(cp_src)
+    cp_dst.copy_(cp_src)
+    e = [ev() for _ in range(2)]
+    e[0].record()
+    for _ in range(5):
+        cp_dst.copy_(cp_src)
+    e[1].record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * 4 * (1 << 30) / (e[0].elapsed_time(e[1]) / 5 * 1e-3) / 1e9
+    del cp_src, cp_dst
+    mlp_in_gbs = N_QUERY * 68 / (mlp_ms * 1e-3) / 1e9
     mlp_roofline = {"kernel": "k_mlp_fwd (bf16, 32-64-64-1)", "bound": "mfma", "achieved": round(tf, 1),
                     "peak": 2500.0, "unit": "TFLOP/s", "frac": round(tf / 2500.0, 4), "flop_per_sample": flop,
                     "samples_per_launch": N_QUERY, "avg_launch_ms": round(mlp_ms, 4),
                     "input_bytes_per_sample": 64,
-                    "memory_bound_frac": round(min(1.0, 8000e9 / 68 * flop / 2500e12), 4)}
+                    "memory_bound_frac": round(min(1.0, 8000e9 / 68 * flop / 2500e12), 4),
+                    "stream_GBps": round(mlp_in_gbs, 1), "measured_copy_GBps": round(copy_gbs, 1),
+                    "intensity_cap_at_copy_TFLOPs": round(copy_gbs * 1e9 / 68 * flop / 1e12, 1)}
     log(f"mlp_fwd bf16: {mlp_ms:.3f} ms, {tf:.1f} TFLOP/s ({tf / 2500 * 100:.1f}% of BF16 peak)")
     del feat, ymlp
 
@@ -698,7 +714,7 @@ def main():
     roofline = {"kernel": "query pass: k_level_brick + k_mlp_planes (bf16 MLP, fp16 tables)", "bound": "hbm",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_source": traffic_src,
-                "bytes_per_query": bytes_q, "queries_per_launch": N_QUERY, "avg_launch_ms": round(infer_ms, 4)}
+                "bytes_per_query": bytes_q, "queries_per_launch": N_QUERY, "avg_launch_ms": round(infer_ms, 4), "measured_copy_GBps": round(copy_gbs, 1)}
 
     if args.copy_calibration:
         # one plain copy of 2^28 floats (1 GiB read, 1 GiB written); its

@@ -11,8 +11,9 @@
 // the wave then evaluates its 64 collision points through the network on the
 // matrix cores in one batch, and every lane decides real or null collision
 // and moves its path on (the shade step).  A lane whose pixel is done takes
-// the next pixel from the device work queue, which stands in for the
-// paper's stream compaction: no lane idles while pixels remain.
+// the next pixel of its wave's 8x8-pixel tiles, fetched from the device work
+// queue, which stands in for the paper's stream compaction: no lane idles
+// while pixels remain, and a wave's camera rays stay neighbours.
 //
 // Path geometry is binary32 with one rounding per operation (positions,
 // distances, optical-thickness sums); -ln(1 - zeta) and the new directions'
@@ -138,8 +139,10 @@ __global__ void __launch_bounds__(256) k_render_pt(ModelDesc md, TablePtrs tp, c
   const uint64_t seed = (uint64_t)ra.seed;
   const int spp = ra.spp;
 
-  // the lane's pixel and path
-  int32_t pix = fetch_pixel(ra.queue, band0, n_pix);
+  // the lane's pixel (-2 while it waits for one, -1 once the frame has none
+  // left) and path
+  PixelPool pool = pool_init();
+  int32_t pix = -2;
   int s = 0;
   bool fresh = true;
   uint64_t key = 0;
@@ -164,7 +167,7 @@ __global__ void __launch_bounds__(256) k_render_pt(ModelDesc md, TablePtrs tp, c
     s = 0;
     L[0] = L[1] = L[2] = 0.0f;
     hits = nreal = nsamp = 0;
-    pix = fetch_pixel(ra.queue, band0, n_pix);
+    pix = -2;  // a new pixel comes from the wave's tiles next round
   };
   auto add = [&](const float* r) {
 #pragma unroll
@@ -196,6 +199,16 @@ __global__ void __launch_bounds__(256) k_render_pt(ModelDesc md, TablePtrs tp, c
   };
 
   for (;;) {
+    // lanes whose pixel is done take the next pixels of the wave's tiles
+    {
+      const bool want = pix == -2;
+      const int32_t p = pool_take(pool, want, ra.queue, band0, ra.width, ra.height);
+      if (want) {
+        pix = p >= 0 ? p : -1;
+        s = 0;
+        fresh = true;
+      }
+    }
     // sample: advance the path to its next tentative collision
     bool cand = false;
     float x[3] = {0.5f, 0.5f, 0.5f}, tc = 0.0f, maj = 0.0f;
@@ -237,7 +250,10 @@ __global__ void __launch_bounds__(256) k_render_pt(ModelDesc md, TablePtrs tp, c
       add(E4);  // the shadow ray reaches the light
       new_direction();
     }
-    if (!__any(cand)) break;
+    if (!__any(cand)) {
+      if (__any(pix == -2)) continue;  // pixels finished without a collision this round
+      break;
+    }
 
     // batch inference: the wave's 64 collision points through the network
     encode_row<P, F, KIN>(md, table, clamp01(x[0]), clamp01(x[1]), clamp01(x[2]), row, [](int, const Oct<P>&) {});

@@ -6,12 +6,14 @@
 // round it streams K = 8 sample coordinates per ray (a 64-sample batch,
 // four 16-sample MFMA tiles), evaluates the network on them, and composites
 // them front to back.  A ray that has terminated or run out of samples is
-// written out and its slot refilled from a device work queue, which plays
-// the role of stream compaction: no wave ever works on a dead ray, and no
-// control returns to the host until the frame is done.
+// written out and its slot refilled at the next round from the wave's
+// 8x8-pixel tiles, taken from a device work queue: this plays the role of
+// stream compaction (no wave works on a dead ray, and no control returns to
+// the host until the frame is done), and the 8 rays of a wave stay
+// neighbours, so their samples share cache lines.
 //
-// Work distribution is XCD-aware: the frame is cut into 8 bands of rows,
-// workgroups fetch rays from the band of their XCD (workgroup id mod 8),
+// Work distribution is XCD-aware: the tiles are cut into 8 bands of rows,
+// workgroups take tiles from the band of their XCD (workgroup id mod 8),
 // so neighbouring rays (coherent hash-table footprints) share an L2, and
 // steal from the other bands once their own is empty.
 // build: one object per MLP precision and width (NGV_PSEL, NGV_WSEL)
@@ -78,6 +80,9 @@ struct SlotState {
   // count, and the shadow ray's transmittance
   uint32_t phase, kmax, n0;
   float wmax, T;
+  // macro-cell walk: exit index and mu of the cell of the current sample
+  uint32_t kexit;
+  float mu_cur;
 };
 
 // Macro-cell modes, per slot: this round's samples (the walk through the
@@ -155,49 +160,65 @@ k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs r
   const int64_t n_pix = (int64_t)ra.width * ra.height;
   unsigned long long n_eval = 0, n_used_tot = 0, n_rays = 0;
 
-  // Owner lanes (lane < kSlots) keep their slot in LDS.
-  auto refill = [&](SlotState& sl) {
+  // Owner lanes (lane < kSlots) keep their slot in LDS.  A slot's pixel is
+  // >= 0 while its ray is marched, -2 while it waits for a new pixel and -1
+  // once the frame has none left.
+  auto start = [&](SlotState& sl, int32_t p) -> bool {
+    const int px = p % ra.width, py = p / ra.width;
+    sl.pix = p;
+    sl.g = make_ray(ra.cam, ra.width, px, py, ra.seed, ra.dt);
+    sl.k = 0;
+    sl.used = 0;
+    sl.C[0] = sl.C[1] = sl.C[2] = 0.0f;
+    sl.A = 0.0f;
+    sl.phase = 0;
+    sl.kmax = 0xFFFFFFFFu;
+    sl.n0 = sl.g.n;
+    sl.wmax = 0.0f;
+    sl.T = 1.0f;
+    sl.kexit = 0;
+    sl.mu_cur = 0.0f;
+    if (sl.g.n > 0) {
+      ++n_rays;
+      return true;
+    }
+    // empty ray: write it out
+    float4* o4 = reinterpret_cast<float4*>(ra.rgba) + p;
+    *o4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (ra.n_geo) ra.n_geo[p] = 0u;
+    if (ra.n_used) ra.n_used[p] = 0u;
+    if (SH && ra.aux) ra.aux[p] = 0xFFFFFFFFu;
+    sl.pix = -2;
+    return false;
+  };
+  // waiting slots take pixels of the wave's tiles (whole wave)
+  PixelPool pool = pool_init();
+  auto fill = [&]() {
     for (;;) {
-      const int32_t p = fetch_pixel(ra.queue, band0, n_pix);
-      sl.pix = p;
-      if (p < 0) return;
-      const int px = p % ra.width, py = p / ra.width;
-      sl.g = make_ray(ra.cam, ra.width, px, py, ra.seed, ra.dt);
-      sl.k = 0;
-      sl.used = 0;
-      sl.C[0] = sl.C[1] = sl.C[2] = 0.0f;
-      sl.A = 0.0f;
-      sl.phase = 0;
-      sl.kmax = 0xFFFFFFFFu;
-      sl.n0 = sl.g.n;
-      sl.wmax = 0.0f;
-      sl.T = 1.0f;
-      if (sl.g.n > 0) {
-        ++n_rays;
-        return;
+      const bool want = lane < kSlots && slots[lane].pix == -2;
+      if (!__any(want)) return;
+      const int32_t p = pool_take(pool, want, ra.queue, band0, ra.width, ra.height);
+      if (want) {
+        SlotState sl = slots[lane];
+        if (p < 0) sl.pix = -1;
+        else start(sl, p);
+        slots[lane] = sl;
       }
-      // empty ray: write it out and take another
-      float4* o4 = reinterpret_cast<float4*>(ra.rgba) + p;
-      *o4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      if (ra.n_geo) ra.n_geo[p] = 0u;
-      if (ra.n_used) ra.n_used[p] = 0u;
-      if (SH && ra.aux) ra.aux[p] = 0xFFFFFFFFu;
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
   };
   float lhat[3] = {0.0f, 0.0f, 1.0f};
   if constexpr (SH) unit3(ra.light, lhat);
 
-  if (lane < kSlots) {
-    SlotState sl;
-    refill(sl);
-    slots[lane] = sl;
-  }
+  if (lane < kSlots) slots[lane].pix = -2;
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 
   constexpr bool skip_empty = MC == kMcSkip;     // ra.mc.mu is set
   constexpr bool adaptive = MC == kMcAdaptive;   // ra.mc.mu is set
   for (;;) {
+    fill();
     // any live slot in this wave?
     const bool live = lane < kSlots && slots[lane].pix >= 0;
     if (!__any(live)) break;
@@ -207,21 +228,27 @@ k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs r
       // listed (skipping), or one sample stands for adaptive_steps of the
       // cell's mu grid steps, cut at the cell's exit (adaptive marching)
       if (lane < kSlots) {
-        const SlotState& so = slots[lane];
+        SlotState& so = slots[lane];
         uint32_t k = so.k, cnt = 0;
         const uint32_t n = so.g.n;
         if (so.pix >= 0) {
+          // the slot remembers the cell it is in (its exit index and mu), so
+          // a cell is looked up once, not once per sample
+          uint32_t kexit = so.kexit;
+          float mu = so.mu_cur;
           while (cnt < (uint32_t)kK && k < n) {
-            const float mu = ra.mc.mu[sample_cell(so.g, k, ra.dt, ra.mc)];
+            if (k >= kexit) {
+              mu = ra.mc.mu[sample_cell(so.g, k, ra.dt, ra.mc)];
+              kexit = cell_exit(so.g, k, ra.dt, ra.mc);
+            }
             if (!(mu > 0.0f)) {
-              k = cell_exit(so.g, k, ra.dt, ra.mc);
+              k = kexit;
               continue;
             }
-            const uint32_t steps = adaptive ? adaptive_steps(mu, ra.step_max, ra.step_exp) : 1u;
             uint32_t kn = k + 1;
-            if (steps > 1) {
-              const uint32_t ke = cell_exit(so.g, k, ra.dt, ra.mc);
-              kn = k + steps < ke ? k + steps : ke;
+            if constexpr (adaptive) {
+              const uint32_t steps = adaptive_steps(mu, ra.step_max, ra.step_exp);
+              kn = k + steps < kexit ? k + steps : kexit;
             }
             kn = kn < n ? kn : n;
             lst[lane * kList + cnt] = k;
@@ -229,6 +256,8 @@ k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs r
             ++cnt;
             k = kn;
           }
+          so.kexit = kexit;
+          so.mu_cur = mu;
         }
         lst[lane * kList + kCnt] = cnt;
         lst[lane * kList + kNext] = k;
@@ -318,6 +347,7 @@ k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs r
             sl.g = ray_from(ps, lhat, sl.g.j, ra.dt);
             sl.phase = 1;
             sl.k = 1;
+            sl.kexit = 0;
             done = false;
           }
         }
@@ -329,7 +359,7 @@ k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs r
           if (ra.n_used) ra.n_used[p] = sl.used;
           if (SH && ra.aux) ra.aux[p] = sl.kmax;
           n_used_tot += sl.used;
-          refill(sl);
+          sl.pix = -2;
         }
         slots[lane] = sl;
       }

@@ -127,4 +127,46 @@ __device__ __forceinline__ int32_t fetch_pixel(unsigned int* queue, int band0, i
   return -1;
 }
 
+// Wave-level pixel pool: the frame is cut into 8x8-pixel tiles taken one at
+// a time by a wave from the banded queue above (one atomic per 64 pixels),
+// so the rays a wave works on at any time are neighbours and their samples
+// share cache lines.  The pool is wave-uniform state kept in registers.
+struct PixelPool {
+  int64_t tile;  // current tile, -1 before the first
+  int pos;       // next pixel of the tile (64: used up)
+  bool done;     // the queue is empty
+};
+
+__device__ __forceinline__ PixelPool pool_init() { return PixelPool{-1, 64, false}; }
+
+// Gives every lane with `want` set a pixel of the wave's tiles, in lane
+// order (-1 once the frame has no pixels left).  Called by the whole wave.
+__device__ inline int32_t pool_take(PixelPool& pool, bool want, unsigned int* queue, int band0, int W, int H) {
+  const int lane = threadIdx.x & 63;
+  const int tiles_x = (W + 7) >> 3, tiles_y = (H + 7) >> 3;
+  const int64_t n_tiles = (int64_t)tiles_x * tiles_y;
+  int32_t got = -1;
+  unsigned long long m = __ballot(want);
+  while (m && !pool.done) {
+    if (pool.pos >= 64) {
+      int32_t t = -1;
+      if (lane == 0) t = fetch_pixel(queue, band0, n_tiles);
+      t = __builtin_amdgcn_readfirstlane(t);
+      if (t < 0) {
+        pool.done = true;
+        break;
+      }
+      pool.tile = t;
+      pool.pos = 0;
+    }
+    const int w = pool.pos++;
+    const int px = (int)(pool.tile % tiles_x) * 8 + (w & 7), py = (int)(pool.tile / tiles_x) * 8 + (w >> 3);
+    if (px >= W || py >= H) continue;  // outside the frame (edge tile)
+    const int leader = __ffsll(m) - 1;
+    if (lane == leader) got = py * W + px;
+    m &= m - 1;
+  }
+  return got;
+}
+
 }  // namespace ngvol
