@@ -429,7 +429,7 @@ def main():
         rws = torch.empty(256, dtype=torch.uint8, device=dev)
         cnt = torch.zeros(4, dtype=torch.int64, device=dev)
         cams = [synth.orbit_camera(2 * math.pi * f / max(args.render_frames, 1), W, H)
-                for f in range(args.render_frames + 1)]
+                for f in range(max(args.render_frames, 3) + 1)]
 
         def frames(mc, adaptive=False):
             # with macro-cells: their value ranges grow from each frame's

@@ -475,8 +475,11 @@ typedef struct ngvol_render_opts {
     int32_t spp;       /* paths per pixel, 1..256 */
     int32_t rr_depth;  /* >= 0 (the paper uses 4) */
     int32_t max_depth; /* 1..1024 */
-    /* Optional per-pixel output [H][W] (NULL: none).  RM_SHADOW: the index k
-     * of the shading point on the primary ray, UINT32_MAX when there is none. */
+    /* Per-pixel output [H][W].  RM_SHADOW (required): the index k of the
+     * shading point on the primary ray, UINT32_MAX when there is none; the
+     * camera rays are marched first, recording these, then the shadow rays
+     * in a second pass (as the paper's listing runs them), which scales the
+     * recorded colours by T.  Other modes: unused. */
     uint32_t* d_aux;
 } ngvol_render_opts;
 

@@ -512,6 +512,8 @@ def render(plan, params, cam, lut, width, height, dt, frame_seed, table_f16=None
     if adaptive or mode != "rm" or aux is not None:
         if adaptive and macrocells is None:
             raise ValueError("adaptive marching needs macrocells")
+        if mode == "rm_shadow" and aux is None:
+            aux = torch.empty((height, width), dtype=torch.int32, device=dev)
         f3 = C.c_float * 3
         opts = RenderOpts(RENDER_MODES[mode], 1 if adaptive else 0, float(step_max), int(step_exp),
                           f3(*[float(v) for v in light]), f3(*[float(v) for v in radiance]),

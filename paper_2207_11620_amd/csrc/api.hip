@@ -794,6 +794,8 @@ int ngvol_render_ex(const ngvol_plan* plan, const ngvol_weights* w, const ngvol_
       NGV_REQUIRE(n2 > 1e-30 && n2 < 1e30, "light_dir length out of range");
       memcpy(ra.light, l, sizeof ra.light);
       NGV_REQUIRE(aligned4(opts->d_aux), "aux must be 4-byte aligned");
+      NGV_REQUIRE(mode != NGVOL_RENDER_RM_SHADOW || opts->d_aux,
+                  "RM_SHADOW needs d_aux (width x height uint32) for the shading points");
       ra.aux = opts->d_aux;
     }
     if (mode == NGVOL_RENDER_PT) {

@@ -75,10 +75,10 @@ struct SlotState {
   uint32_t k;   // next sample index
   uint32_t used;
   float C[3], A;
-  // single-shot shadow: the phase (0 primary, 1 shadow ray), the largest
-  // contribution so far and its sample index, the primary ray's sample
-  // count, and the shadow ray's transmittance
-  uint32_t phase, kmax, n0;
+  // single-shot shadow: the largest contribution so far and its sample
+  // index (first pass), the primary ray's sample count, and the shadow
+  // ray's transmittance (second pass)
+  uint32_t kmax, n0;
   float wmax, T;
   // macro-cell walk: exit index and mu of the cell of the current sample
   uint32_t kexit;
@@ -129,7 +129,10 @@ __host__ __device__ inline size_t render_stage_offset(size_t weight_bytes, size_
   return (end + 15) & ~(size_t)15;
 }
 
-template <int P, int F, int KIN, int W, typename TT, int MC, bool SH>
+// SHM: 0 plain; 1 the camera-ray pass of single-shot shadows, which also
+// records each pixel's shading point; 2 the shadow-ray pass, which marches
+// from the recorded points towards the light and scales the pixels.
+template <int P, int F, int KIN, int W, typename TT, int MC, int SHM>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P != 0 && KIN == 32 ? 4 : 1)))
 k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs ra) {
   typedef typename Prec<P>::Frag Frag;
@@ -163,21 +166,37 @@ k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs r
   // Owner lanes (lane < kSlots) keep their slot in LDS.  A slot's pixel is
   // >= 0 while its ray is marched, -2 while it waits for a new pixel and -1
   // once the frame has none left.
+  constexpr bool rec = SHM == 1, shadow = SHM == 2;
+  float lhat[3] = {0.0f, 0.0f, 1.0f};
+  if constexpr (shadow) unit3(ra.light, lhat);
   auto start = [&](SlotState& sl, int32_t p) -> bool {
     const int px = p % ra.width, py = p / ra.width;
     sl.pix = p;
     sl.g = make_ray(ra.cam, ra.width, px, py, ra.seed, ra.dt);
     sl.k = 0;
+    sl.kexit = 0;
+    sl.mu_cur = 0.0f;
+    sl.T = 1.0f;
+    if constexpr (shadow) {
+      // the shadow ray from the pixel's shading point, from its sample 1 on;
+      // a pixel without one, or a ray with no sample beyond it, keeps T = 1
+      const uint32_t ks = ra.aux[p];
+      if (ks != 0xFFFFFFFFu) {
+        float ps[3];
+        ray_point(sl.g, ks, ra.dt, ps[0], ps[1], ps[2]);
+        sl.g = ray_from(ps, lhat, sl.g.j, ra.dt);
+        sl.k = 1;
+        if (sl.g.n > 1u) return true;
+      }
+      sl.pix = -2;
+      return false;
+    }
     sl.used = 0;
     sl.C[0] = sl.C[1] = sl.C[2] = 0.0f;
     sl.A = 0.0f;
-    sl.phase = 0;
     sl.kmax = 0xFFFFFFFFu;
     sl.n0 = sl.g.n;
     sl.wmax = 0.0f;
-    sl.T = 1.0f;
-    sl.kexit = 0;
-    sl.mu_cur = 0.0f;
     if (sl.g.n > 0) {
       ++n_rays;
       return true;
@@ -187,7 +206,7 @@ k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs r
     *o4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     if (ra.n_geo) ra.n_geo[p] = 0u;
     if (ra.n_used) ra.n_used[p] = 0u;
-    if (SH && ra.aux) ra.aux[p] = 0xFFFFFFFFu;
+    if (rec) ra.aux[p] = 0xFFFFFFFFu;
     sl.pix = -2;
     return false;
   };
@@ -208,9 +227,6 @@ k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs r
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
   };
-  float lhat[3] = {0.0f, 0.0f, 1.0f};
-  if constexpr (SH) unit3(ra.light, lhat);
-
   if (lane < kSlots) slots[lane].pix = -2;
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -312,7 +328,7 @@ k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs r
             const uint32_t span = lst[lane * kList + kSpan + q];
             if (span > 1u) a = __fsub_rn(1.0f, powf(__fsub_rn(1.0f, a), (float)span));
           }
-          if (SH && sl.phase) {
+          if constexpr (shadow) {
             // shadow ray: transmittance towards the light
             sl.T = sl.T * (1.0f - a);
             if (sl.T <= 0.01f) {
@@ -322,7 +338,7 @@ k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs r
             continue;
           }
           const float w = (1.0f - sl.A) * a;
-          if (SH && w > sl.wmax) {
+          if (rec && w > sl.wmax) {
             sl.wmax = w;
             sl.kmax = (skip_empty || adaptive) ? lst[lane * kList + q] : sl.k + q;
           }
@@ -337,28 +353,20 @@ k_render(ModelDesc md, TablePtrs tp, const float* __restrict__ mlp, RenderArgs r
           }
         }
         sl.k = (skip_empty || adaptive) ? lst[lane * kList + kNext] : sl.k + kend;
-        if constexpr (SH) {
-          // the primary ray is done: a shadow ray leaves its largest
-          // contribution's sample point towards the light (its samples from
-          // k = 1 on); with no such point, or no samples, T stays 1
-          if ((done || sl.k >= sl.g.n) && sl.phase == 0 && sl.wmax > 0.0f) {
-            float ps[3];
-            ray_point(sl.g, sl.kmax, ra.dt, ps[0], ps[1], ps[2]);
-            sl.g = ray_from(ps, lhat, sl.g.j, ra.dt);
-            sl.phase = 1;
-            sl.k = 1;
-            sl.kexit = 0;
-            done = false;
-          }
-        }
         if (done || sl.k >= sl.g.n) {
           const int32_t p = sl.pix;
           float4* o4 = reinterpret_cast<float4*>(ra.rgba) + p;
-          *o4 = make_float4(sl.T * sl.C[0], sl.T * sl.C[1], sl.T * sl.C[2], sl.A);
-          if (ra.n_geo) ra.n_geo[p] = sl.n0;
-          if (ra.n_used) ra.n_used[p] = sl.used;
-          if (SH && ra.aux) ra.aux[p] = sl.kmax;
-          n_used_tot += sl.used;
+          if constexpr (shadow) {
+            // T attenuates the whole colour of the camera-ray pass
+            const float4 c = *o4;
+            *o4 = make_float4(sl.T * c.x, sl.T * c.y, sl.T * c.z, c.w);
+          } else {
+            *o4 = make_float4(sl.C[0], sl.C[1], sl.C[2], sl.A);
+            if (ra.n_geo) ra.n_geo[p] = sl.n0;
+            if (ra.n_used) ra.n_used[p] = sl.used;
+            if (rec) ra.aux[p] = sl.kmax;
+            n_used_tot += sl.used;
+          }
           sl.pix = -2;
         }
         slots[lane] = sl;
@@ -402,13 +410,17 @@ hipError_t launch_render_p(const ngvol_plan* plan, TablePtrs tp, const float* ml
   do {                                                                                                            \
     if constexpr (MCM != kMcAdaptive) {                                                                          \
       if (ra.mode == NGVOL_RENDER_RM_SHADOW) {                                                                    \
-        hipLaunchKernelGGL((k_render<P, F, KIN, W, TT, MCM, true>), dim3((unsigned)grid), dim3(256), lds, st, md,   \
-                           tp, mlp, ra);                                                                          \
+        /* camera rays (recording the shading points), then the shadow rays */                                  \
+        hipLaunchKernelGGL((k_render<P, F, KIN, W, TT, MCM, 1>), dim3((unsigned)grid), dim3(256), lds, st, md, tp,  \
+                           mlp, ra);                                                                              \
+        hipLaunchKernelGGL(k_render_init, dim3(1), dim3(64), 0, st, ra.queue, nullptr);                          \
+        hipLaunchKernelGGL((k_render<P, F, KIN, W, TT, MCM, 2>), dim3((unsigned)grid), dim3(256), lds, st, md, tp,  \
+                           mlp, ra);                                                                              \
         break;                                                                                                    \
       }                                                                                                           \
     }                                                                                                             \
-    hipLaunchKernelGGL((k_render<P, F, KIN, W, TT, MCM, false>), dim3((unsigned)grid), dim3(256), lds, st, md,      \
-                       tp, mlp, ra);                                                                              \
+    hipLaunchKernelGGL((k_render<P, F, KIN, W, TT, MCM, 0>), dim3((unsigned)grid), dim3(256), lds, st, md, tp,      \
+                       mlp, ra);                                                                                  \
   } while (0)
   NGV_DISPATCH_F_KIN(md.F, plan->kin, {
     const int mcm = ra.mc.mu == nullptr ? kMcNone : (ra.adaptive ? kMcAdaptive : kMcSkip);
