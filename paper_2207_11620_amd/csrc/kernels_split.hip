@@ -23,6 +23,7 @@
 // kernel; the products of the first layer are summed in another order, so
 // outputs agree with the fused kernel to FP32 rounding, not bitwise.
 // build: one object per MLP precision and width (NGV_PSEL, NGV_WSEL)
+#include <cmath>
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -225,20 +226,21 @@ __global__ void __launch_bounds__(256) k_level_brick(ModelDesc md, const TT* __r
     const int64_t g0 = (int64_t)ba.bin_off[b], g1 = g0 + (int64_t)ba.bin_cnt[b];
     const int64_t q0 = g0 - s0 > 0 ? g0 - s0 : 0, q1 = g1 - s0 < m ? g1 - s0 : m;
     if (q0 >= q1) continue;  // uniform over the workgroup
+    const LevelDesc lva = md.lv[la], lvb = md.lv[lb >= 0 ? lb : la];  // held in registers over the item
     const bool sa = ba.lds_off[p][0] >= 0, sb = lb >= 0 && ba.lds_off[p][1] >= 0;
     const bool write_idx = la == 0;  // the pair holding level 0 also writes the queries' slots
     const int bq[3] = {compact3((uint32_t)b), compact3((uint32_t)b >> 1), compact3((uint32_t)b >> 2)};
     BrickBox bba, bbb;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      brick_range(md.lv[la].N, bq[a], ba.k, bba.lo[a], bba.n[a]);
-      brick_range(md.lv[lb >= 0 ? lb : la].N, bq[a], ba.k, bbb.lo[a], bbb.n[a]);
+      brick_range(lva.N, bq[a], ba.k, bba.lo[a], bba.n[a]);
+      brick_range(lvb.N, bq[a], ba.k, bbb.lo[a], bbb.n[a]);
     }
     const uint32_t* box_a = lds + (sa ? ba.lds_off[p][0] / 4 : 0);
     const uint32_t* box_b = lds + (sb ? ba.lds_off[p][1] / 4 : 0);
     __syncthreads();  // the previous item's boxes are no longer read
-    if (sa) stage_box<ED>(md.lv[la], table, bba, lds + ba.lds_off[p][0] / 4);
-    if (sb) stage_box<ED>(md.lv[lb], table, bbb, lds + ba.lds_off[p][1] / 4);
+    if (sa) stage_box<ED>(lva, table, bba, lds + ba.lds_off[p][0] / 4);
+    if (sb) stage_box<ED>(lvb, table, bbb, lds + ba.lds_off[p][1] / 4);
     __syncthreads();
     for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
       const float4 rr = rec[s0 + q];
@@ -247,20 +249,20 @@ __global__ void __launch_bounds__(256) k_level_brick(ModelDesc md, const TT* __r
       LevelPack<F, OT, 2> pk;
       float acc[F];
       if (sa) {
-        lookup_box<F, TT>(md.lv[la], bba, box_a, px, py, pz, acc);
+        lookup_box<F, TT>(lva, bba, box_a, px, py, pz, acc);
       } else {
         Corners cr;
-        level_corners(md.lv[la], px, py, pz, cr);
+        level_corners(lva, px, py, pz, cr);
         gather_level<F>(cr, table, n_ent, acc);
       }
 #pragma unroll
       for (int f = 0; f < F; ++f) pk.v[f] = (OT)acc[f];
       if (lb >= 0) {
         if (sb) {
-          lookup_box<F, TT>(md.lv[lb], bbb, box_b, px, py, pz, acc);
+          lookup_box<F, TT>(lvb, bbb, box_b, px, py, pz, acc);
         } else {
           Corners cr;
-          level_corners(md.lv[lb], px, py, pz, cr);
+          level_corners(lvb, px, py, pz, cr);
           gather_level<F>(cr, table, n_ent, acc);
         }
 #pragma unroll
@@ -458,12 +460,26 @@ constexpr size_t kBrickLds = 40 * 1024;
 // and p + 8; a level is staged when its largest box over a brick fits in what
 // the pair leaves of kBrickLds.  The (pair, brick) items, pair-major, are cut
 // into 8 contiguous segments of equal estimated cost, one per XCD, so that
-// the XCDs whose pairs are staged share the others' gathers (a staged level
-// costs about kStagedCost of a gathered one).  Returns false when the plan or
-// the workspace does not qualify; lds = bytes the launch needs.
-constexpr double kStagedCost = 0.15;
+// the XCDs whose pairs are staged share the others' gathers.  Returns false
+// when the plan or the workspace does not qualify; lds = bytes the launch
+// needs.
+//
+// Estimated cost of one level over all queries, in units of a staged level
+// (whose per-query arithmetic bounds it).  A gathered level costs more the
+// fewer corner lines neighbouring queries share: with rho = cells of the
+// level per mean query spacing, (N - 1) / n^(1/3), the cost measured on
+// MI355X (2^24 grouped queries, levels of 406 to 2047 cells, FP16 tables)
+// follows 4.2 - 3.92 exp(-rho / 2) within 2 %; it is kept above the cost of
+// a staged level.
+static double level_cost(int N, int64_t n, bool staged) {
+  if (staged) return 1.0;
+  const double rho = (double)(N - 1) / std::cbrt((double)(n > 1 ? n : 1));
+  const double c = 4.2 - 3.92 * std::exp(-rho / 2.0);
+  return c > 1.2 ? c : 1.2;
+}
 
-static bool brick_args(const ngvol_plan* plan, BinRanges bins, int entry_bytes, BrickArgs& ba, size_t& lds) {
+static bool brick_args(const ngvol_plan* plan, BinRanges bins, int64_t n, int entry_bytes, BrickArgs& ba,
+                       size_t& lds) {
   const ModelDesc& md = plan->md;
   if (!bins.off || !bins.cnt || md.L < 8 || md.L > 16 || entry_bytes > 8) return false;
   ba = BrickArgs{};
@@ -489,13 +505,12 @@ static bool brick_args(const ngvol_plan* plan, BinRanges bins, int entry_bytes, 
         most = n > most ? n : most;
       }
       const size_t bytes = ((size_t)most * most * most * entry_bytes + 15) & ~(size_t)15;
-      if (used + bytes <= kBrickLds) {
+      const bool staged = used + bytes <= kBrickLds;
+      if (staged) {
         ba.lds_off[p][i] = (int)used;
         used += bytes;
-        cost[p] += kStagedCost;
-      } else {
-        cost[p] += 1.0;
       }
+      cost[p] += level_cost(md.lv[l].N, n, staged);
     }
     lds = used > lds ? used : lds;
   }
@@ -524,7 +539,7 @@ hipError_t launch_infer_split_p(const ngvol_plan* plan, TablePtrs tp, const floa
   const SplitArgs sa = split_args(plan);
   BrickArgs bk;
   size_t brick_lds = 0;
-  const bool brick = brick_args(plan, bins, md.F * (tp.f16 ? 2 : 4), bk, brick_lds);
+  const bool brick = brick_args(plan, bins, n, md.F * (tp.f16 ? 2 : 4), bk, brick_lds);
   const int64_t slab = split_slab(plan, n);
   const size_t lds = fwd_lds_bytes(plan);
   // plane order of the MLP's input columns

@@ -204,6 +204,34 @@ def test_level_split_equals_fused(name, prec, f16):
     assert rel_err(b[idx], ref) <= (1e-5 if prec == "fp32" else 2e-2)
 
 
+@pytest.mark.parametrize("n", [(1 << 21) + 5, (1 << 22) + 3])
+def test_level_split_crowded_cells(n):
+    # grouped queries whose cells are uneven: one 1/16 brick holds a quarter
+    # of the queries (too many to be regrouped within the cell) and a few
+    # sit on the top faces and corner; the brick-staged level kernel takes
+    # any record count per brick, and FP32 agrees with the fused kernel to
+    # rounding (features are staged or gathered bitwise alike)
+    m = oracle_model("cfg1")
+    p = gpu_plan("cfg1", "fp32")
+    params = init_params("cfg1", table_scale=0.5)
+    rng = np.random.default_rng(n)
+    xyz = rng.random((n, 3), dtype=np.float32)
+    crowd = n // 4
+    xyz[:crowd] = (0.3125 + rng.random((crowd, 3)) * 0.0625).astype(np.float32)
+    xyz[crowd:crowd + 8] = np.float32(1.0)
+    xyz[crowd + 8:crowd + 16, 1] = np.float32(0.0)
+    pt, xt = dev(params), dev(xyz)
+    tf = ngv.make_f16_tables(p, pt)
+    a = host(ngv.infer(p, pt, xt, table_f16=tf, sort=False))
+    b = host(ngv.infer(p, pt, xt, table_f16=tf, sort=True))
+    assert rel_err(b, a) <= 1e-6
+    q = params.astype(np.float64)
+    q[:m.n_table] = host(tf).astype(np.float64)
+    idx = np.r_[np.arange(24), crowd - 1 - np.arange(8), np.linspace(24, n - 1, 1500).astype(np.int64)]
+    ref = oracle.forward(m, q, xyz[idx])
+    assert rel_err(b[idx], ref) <= 1e-5
+
+
 def _morton(q, bits):
     key = np.zeros(q.shape[0], dtype=np.int64)
     for b in range(bits):
