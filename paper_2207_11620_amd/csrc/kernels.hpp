@@ -158,9 +158,10 @@ struct BrickArgs {
   const uint32_t* bin_off;
   const uint32_t* bin_cnt;
   int k, n_bins;
-  int lev[8][2];
-  int lds_off[8][2];
-  int item_lo[9];
+  int lev[8][2];      // levels of list pair i (-1: none)
+  int lds_off[8][2];  // LDS byte offsets of their staged boxes (-1: gathered)
+  int n_shared;       // list pairs 0 .. n_shared-1: their bricks are shared by all XCDs
+  int item_lo[9];     // XCD x: list items [item_lo[x], item_lo[x+1]) of the other pairs
   int gw;
 };
 bool use_split(const ngvol_plan* plan, int64_t n);

@@ -219,8 +219,15 @@ __global__ void __launch_bounds__(256) k_level_brick(ModelDesc md, const TT* __r
   const int nbx = (int)((gridDim.x - x + 7) >> 3);  // workgroups on this XCD
   const uint32_t n_ent = (uint32_t)(md.n_table / F);
   const int gw = ba.gw;
-  // the XCD's segment of the (pair, brick) items, pair-major
-  for (int it = ba.item_lo[x] + r; it < ba.item_lo[x + 1]; it += nbx) {
+  // the XCD's items: an eighth of the bricks of each of the first n_shared
+  // pairs of the list, spread evenly among its segment of the (pair, brick)
+  // items of the others, pair-major
+  const int slice = ba.n_bins >> 3;
+  const int n_sh = ba.n_shared * slice;
+  const int o_lo = ba.item_lo[x], n_all = n_sh + (ba.item_lo[x + 1] - o_lo);
+  for (int v = r; v < n_all; v += nbx) {
+    const int js = (int)((int64_t)v * n_sh / n_all), js1 = (int)((int64_t)(v + 1) * n_sh / n_all);
+    const int it = js1 > js ? (js / slice) * ba.n_bins + x * slice + js % slice : o_lo + (v - js);
     const int p = it / ba.n_bins, b = it - p * ba.n_bins;
     const int la = ba.lev[p][0], lb = ba.lev[p][1];
     const int64_t g0 = (int64_t)ba.bin_off[b], g1 = g0 + (int64_t)ba.bin_cnt[b];
@@ -500,9 +507,9 @@ static bool brick_args(const ngvol_plan* plan, BinRanges bins, int64_t n, int en
       if (l >= md.L) continue;
       int most = 0;
       for (int q = 0; q < (1 << bins.k); ++q) {
-        int lo, n;
-        brick_range(md.lv[l].N, q, bins.k, lo, n);
-        most = n > most ? n : most;
+        int lo, cnt;
+        brick_range(md.lv[l].N, q, bins.k, lo, cnt);
+        most = cnt > most ? cnt : most;
       }
       const size_t bytes = ((size_t)most * most * most * entry_bytes + 15) & ~(size_t)15;
       const bool staged = used + bytes <= kBrickLds;
@@ -514,18 +521,45 @@ static bool brick_args(const ngvol_plan* plan, BinRanges bins, int64_t n, int en
     }
     lds = used > lds ? used : lds;
   }
-  // equal-cost segments of the pair-major item list
+  // Pairs whose levels are all staged are bound by their arithmetic, the
+  // others by their gathers: the former go first in the list and every XCD
+  // takes an eighth of their bricks, interleaved with its segment of the
+  // latter, so that each compute unit has both kinds of work in flight.
+  int order[8], n_sh = 0;
+  for (int p = 0; p < 8; ++p) {
+    const bool shared = ba.lds_off[p][0] >= 0 && (ba.lev[p][1] < 0 || ba.lds_off[p][1] >= 0);
+    if (shared) order[n_sh++] = p;
+  }
+  int n_list = n_sh;
+  for (int p = 0; p < 8; ++p) {
+    const bool shared = ba.lds_off[p][0] >= 0 && (ba.lev[p][1] < 0 || ba.lds_off[p][1] >= 0);
+    if (!shared) order[n_list++] = p;
+  }
+  BrickArgs src = ba;
+  double c2[8];
+  for (int i = 0; i < 8; ++i) {
+    for (int j = 0; j < 2; ++j) {
+      ba.lev[i][j] = src.lev[order[i]][j];
+      ba.lds_off[i][j] = src.lds_off[order[i]][j];
+    }
+    c2[i] = cost[order[i]];
+  }
+  ba.n_shared = n_sh;
+  // equal-cost segments of the other pairs' items (list positions from
+  // n_sh * n_bins on)
   double total = 0.0;
-  for (int p = 0; p < 8; ++p) total += cost[p];
-  ba.item_lo[0] = 0;
-  int p = 0;
-  double before = 0.0;  // cost of the pairs before p
+  for (int i = n_sh; i < 8; ++i) total += c2[i];
+  const int base = n_sh * ba.n_bins;
+  ba.item_lo[0] = base;
+  int i = n_sh;
+  double before = 0.0;  // cost of the list pairs before i
   for (int x = 1; x < 8; ++x) {
     const double target = total * x / 8.0;
-    while (p < 7 && before + cost[p] <= target) before += cost[p++];
-    const double frac = cost[p] > 0.0 ? (target - before) / cost[p] : 0.0;
-    int cut = p * ba.n_bins + (int)(frac * ba.n_bins + 0.5);
+    while (i < 7 && before + c2[i] <= target) before += c2[i++];
+    const double frac = c2[i] > 0.0 ? (target - before) / c2[i] : 0.0;
+    int cut = i * ba.n_bins + (int)(frac * ba.n_bins + 0.5);
     cut = cut < ba.item_lo[x - 1] ? ba.item_lo[x - 1] : cut;
+    cut = cut > 8 * ba.n_bins ? 8 * ba.n_bins : cut;
     ba.item_lo[x] = cut;
   }
   ba.item_lo[8] = 8 * ba.n_bins;
