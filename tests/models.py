@@ -4,8 +4,9 @@ Shapes follow the workloads: the tiny Gaussian-blob fit (8 levels, growth
 1.5 from 4, 2^14 entries, 16-32-32-1), the inference/training model (16
 levels from 16 to 2048, 2^19 entries, 32-64-64-1), the paper's fixed
 Table-2 network (8 levels x 8 features, 2^19, 64 wide, 4 hidden), a
-4-feature variant, a 32-level narrow model and a 4-level model with large
-tables (fewer levels than XCDs).
+4-feature variant, a 32-level narrow model, a 4-level model with large
+tables (fewer levels than XCDs) and a 12-level model (level pairs of the
+level-split query that hold one level).
 """
 import numpy as np
 
@@ -21,6 +22,7 @@ MODELS = {
     "f4": dict(L=16, F=4, log2T=16, base=16, scale=0.0, maxres=1024, width=64, n_hidden=2, table_scale=1e-2),
     "w32k64": dict(L=32, F=2, log2T=12, base=4, scale=1.2, maxres=0, width=32, n_hidden=3, table_scale=1e-2),
     "l4": dict(L=4, F=2, log2T=20, base=64, scale=0.0, maxres=1024, width=32, n_hidden=1, table_scale=1e-2),
+    "l12": dict(L=12, F=2, log2T=19, base=16, scale=0.0, maxres=1024, width=64, n_hidden=2, table_scale=1e-2),
 }
 
 
