@@ -572,7 +572,8 @@ int ngvol_ooc_slots(const ngvol_ooc* ooc, int32_t* host_slot_block);
 #define NGVOL_MULTI_MAX 16
 typedef struct ngvol_multi ngvol_multi;
 
-/* Device bytes of the descriptor table of a group of k models. */
+/* Device bytes of the descriptor table of a group of k models (the k
+ * descriptors and the persistent query's work counter). */
 size_t ngvol_multi_table_bytes(int32_t k);
 
 /* Groups k plans (1 <= k <= 16) that share precision, n_features (2), the
@@ -590,11 +591,12 @@ int ngvol_multi_destroy(ngvol_multi* group);
  * out[i][j] for j < n[i], with weights w[i] (host arrays of k entries; the
  * pointers they hold are device pointers, either all with or all without
  * FP16 tables).  By default one persistent launch: work is cut into chunks
- * of 16-sample tiles of one model, ordered model by model, taken grid-stride
- * by the workgroups, which restage the MLP weights in LDS when the model
- * changes.  After ngvol_multi_autotune it may instead issue one single-model
- * launch per model, back to back on the stream, when that was faster (large
- * models, each filling the GPU on its own). */
+ * of 16-sample tiles of one model, ordered model by model, taken in order
+ * from a work counter in the group's table by the workgroups, which restage
+ * the MLP weights in LDS when the model changes.  The counter is shared by
+ * the group's calls: calls on one group must not overlap (issue them on one
+ * stream).  After ngvol_multi_autotune it may instead issue one single-model
+ * launch per model, back to back on the stream, when that was faster. */
 int ngvol_multi_infer(const ngvol_multi* group, const ngvol_weights* w, const float* const* xyz, const int64_t* n,
                       float* const* out, hipStream_t stream);
 

@@ -847,6 +847,7 @@ struct ngvol_multi {
   ngvol_plan plan0;  // shape shared by the group (precision, widths, device)
   ngvol_plan plans[NGVOL_MULTI_MAX];  // copies, for per-model launches
   ngvol::ModelDesc* table;  // device
+  uint32_t* next_item;      // device work counter of the persistent query, after the table
   int blocks_per_cu;  // 0: one single-model launch per model
   int chunk_tiles;
   // batched training: the models' steps run on these streams, forked from
@@ -901,7 +902,7 @@ int multi_args(const ngvol_multi* g, const ngvol_weights* w, const float* const*
 // to fill the GPU.
 hipError_t multi_launch(const ngvol_multi* g, const ngvol_weights* w, const MultiArgs& a, bool f16, int bpc,
                         hipStream_t st) {
-  if (bpc > 0) return launch_multi_infer(&g->plan0, g->table, a, f16, bpc, st);
+  if (bpc > 0) return launch_multi_infer(&g->plan0, g->table, a, f16, bpc, g->next_item, st);
   for (int i = 0; i < g->k; ++i) {
     if (a.n[i] == 0) continue;
     const ngvol_plan* p = &g->plans[i];
@@ -915,7 +916,13 @@ hipError_t multi_launch(const ngvol_multi* g, const ngvol_weights* w, const Mult
 
 extern "C" {
 
-size_t ngvol_multi_table_bytes(int32_t k) { return (size_t)(k > 0 ? k : 0) * sizeof(ngvol::ModelDesc); }
+// the k descriptors, then (at a 256-byte boundary) the persistent query's
+// work counter
+static size_t multi_counter_offset(int32_t k) {
+  return ((size_t)(k > 0 ? k : 0) * sizeof(ngvol::ModelDesc) + 255) / 256 * 256;
+}
+
+size_t ngvol_multi_table_bytes(int32_t k) { return multi_counter_offset(k) + 256; }
 
 int ngvol_multi_create(const ngvol_plan* const* plans, int32_t k, void* d_table, size_t table_bytes, hipStream_t st,
                        ngvol_multi** out) {
@@ -939,8 +946,12 @@ int ngvol_multi_create(const ngvol_plan* const* plans, int32_t k, void* d_table,
   g->plan0 = *plans[0];
   for (int i = 0; i < k; ++i) g->plans[i] = *plans[i];
   g->table = reinterpret_cast<ngvol::ModelDesc*>(d_table);
-  g->blocks_per_cu = 8;
-  g->chunk_tiles = 32;
+  g->next_item = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(d_table) + multi_counter_offset(k));
+  // untuned shape: few workgroups per compute unit, since the models' random
+  // gathers evict each other's lines when many are in flight (16 models of
+  // 2^20 queries: 6.2 ms at 1 per CU, 6.6 at 2, 7.1 at 4, 8.1 at 8)
+  g->blocks_per_cu = 2;
+  g->chunk_tiles = 16;
   ngvol::ModelDesc host[NGVOL_MULTI_MAX];
   for (int i = 0; i < k; ++i) host[i] = plans[i]->md;
   hipError_t e = hipMemcpyAsync(d_table, host, sizeof(ngvol::ModelDesc) * k, hipMemcpyHostToDevice, st);
@@ -1003,7 +1014,7 @@ int ngvol_multi_infer(const ngvol_multi* g, const ngvol_weights* w, const float*
 int ngvol_multi_autotune(ngvol_multi* g, const ngvol_weights* w, const float* const* xyz, const int64_t* n,
                          float* const* out, hipStream_t st, int32_t* bpc_out, int32_t* chunk_out) {
   NGV_REQUIRE(g, "group is NULL");
-  static const int kBpc[] = {2, 4, 8, 16};
+  static const int kBpc[] = {1, 2, 4, 8};
   static const int kChunk[] = {16, 64, 256};  // multiples of 4 tiles: every wave of a workgroup gets a group
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipEventCreate(&e0);

@@ -290,7 +290,8 @@ struct MultiArgs {
   float* out[kMultiMax];
   int64_t n[kMultiMax];
 };
+// next_item: the group's device work counter (zeroed by the launch).
 hipError_t launch_multi_infer(const ngvol_plan* plan0, const ModelDesc* table, const MultiArgs& a, bool f16,
-                              int blocks_per_cu, hipStream_t st);
+                              int blocks_per_cu, uint32_t* next_item, hipStream_t st);
 
 }  // namespace ngvol

@@ -6,10 +6,12 @@
 // them all; they differ in levels, resolutions and table sizes, which are
 // read from a device table of model descriptors.  Work is cut into items of
 // `chunk_tiles` 16-sample tiles of one model, ordered model by model; the
-// workgroups take items grid-stride, so the GPU evaluates the models one
-// after another (one model's tables in the caches at a time, no launch gaps
-// between models), and each workgroup restages a model's MLP weights in LDS
-// when it reaches that model's items.
+// workgroups take the next item from a device counter, so all of them work
+// within one window of consecutive items and the GPU evaluates the models
+// one after another (one model's tables in the caches at a time, no launch
+// gaps between models; workgroups that took items grid-stride drifted apart
+// by several models and shared the L2 among them), and each workgroup
+// restages a model's MLP weights in LDS when it reaches that model's items.
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -19,7 +21,7 @@ namespace ngvol {
 
 template <int P, int F, int KIN, int W, typename TT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P != 0 && KIN == 32 ? 4 : 1)))
-k_multi_infer(const ModelDesc* __restrict__ table, MultiArgs a) {
+k_multi_infer(const ModelDesc* __restrict__ table, MultiArgs a, uint32_t* __restrict__ next_item) {
   typedef typename Prec<P>::Frag Frag;
   typedef typename Prec<P>::T T;
   typedef WeightLayout<P, KIN, W> WL;
@@ -33,12 +35,20 @@ k_multi_infer(const ModelDesc* __restrict__ table, MultiArgs a) {
   T* stage = reinterpret_cast<T*>(smem + stage_offset<P, W>(wbytes) + wave * Stage<P, KIN>::wave_bytes);
   T* row = stage + lane * Stage<P, KIN>::pitch;
 
-  // items are taken grid-stride, so at any time the whole GPU works on one
-  // or two models and their tables share the caches
+  // items are taken in order from the counter (zeroed before the launch);
+  // a workgroup leaves at the first number past the last item, so every
+  // workgroup ends.  The number is passed through LDS, alternating between
+  // two slots: a slot is written again only after the next barrier, which
+  // every wave reaches after reading it.
+  __shared__ uint32_t taken[2];
   const int64_t total = a.item_prefix[a.k];
   int cur = -1;
   int m = 0;
-  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+  for (int it = 0;; ++it) {
+    if (threadIdx.x == 0) taken[it & 1] = atomicAdd(next_item, 1u);
+    __syncthreads();
+    const int64_t item = (int64_t)taken[it & 1];
+    if (item >= total) break;  // uniform over the workgroup
     while (item >= a.item_prefix[m + 1]) ++m;
     // the model index is uniform across the workgroup: say so, so that its
     // descriptor is read through the scalar cache
@@ -76,9 +86,15 @@ k_multi_infer(const ModelDesc* __restrict__ table, MultiArgs a) {
   }
 }
 
+__global__ void k_multi_reset(uint32_t* next_item) {
+  if (threadIdx.x == 0) *next_item = 0u;
+}
+
 hipError_t launch_multi_infer(const ngvol_plan* plan0, const ModelDesc* table, const MultiArgs& a, bool f16,
-                              int blocks_per_cu, hipStream_t st) {
+                              int blocks_per_cu, uint32_t* next_item, hipStream_t st) {
   const ModelDesc& md = plan0->md;
+  // a kernel, not a memset, so that the call can be captured in a graph
+  hipLaunchKernelGGL(k_multi_reset, dim3(1), dim3(64), 0, st, next_item);
   const size_t lds = enc_lds_bytes(plan0, 4);
   int64_t grid = a.item_prefix[a.k];
   const int64_t cap = (int64_t)plan0->cus * blocks_per_cu;
@@ -87,9 +103,11 @@ hipError_t launch_multi_infer(const ngvol_plan* plan0, const ModelDesc* table, c
 #define NGV_MI(P, KIN, W)                                                                                      \
   do {                                                                                                         \
     if (f16)                                                                                                   \
-      hipLaunchKernelGGL((k_multi_infer<P, 2, KIN, W, __half>), dim3((unsigned)grid), dim3(256), lds, st, table, a); \
+      hipLaunchKernelGGL((k_multi_infer<P, 2, KIN, W, __half>), dim3((unsigned)grid), dim3(256), lds, st, table, a, \
+                         next_item);                                                                           \
     else                                                                                                       \
-      hipLaunchKernelGGL((k_multi_infer<P, 2, KIN, W, float>), dim3((unsigned)grid), dim3(256), lds, st, table, a);  \
+      hipLaunchKernelGGL((k_multi_infer<P, 2, KIN, W, float>), dim3((unsigned)grid), dim3(256), lds, st, table, a,  \
+                         next_item);                                                                           \
   } while (0)
 #define NGV_MI_W(P, KIN)                                   \
   do {                                                     \
