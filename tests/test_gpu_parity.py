@@ -266,8 +266,9 @@ def test_sorted_records_follow_morton_order():
         assert np.all(ok[same_cell & refined[1:]])
 
 
-def test_binned_training_gradient():
-    # a batch large enough to be grouped by cell before the step
+def test_large_training_batch_gradient():
+    # a 2^16-sample step on the query model: the table gradient goes through
+    # the bucketed scatter with split coarse-level buckets
     m = oracle_model("cfg1")
     p = gpu_plan("cfg1", "fp32")
     params = init_params("cfg1", table_scale=0.3)
