@@ -843,6 +843,38 @@ def test_multi_infer_equals_single_launches():
         np.testing.assert_array_equal(host(outs2[i]), host(outs[i]))
 
 
+def test_multi_infer_graph_replays_match_eager():
+    # the persistent multi-model query zeroes its work counter with a kernel,
+    # so a captured call replays: every replay (with eager work in between)
+    # gives the eager outputs
+    import torch
+    plans, params = _multi_models(k=6)
+    f16 = [ngv.make_f16_tables(p, w) for p, w in zip(plans, params)]
+    ns = [20000 + 7919 * i for i in range(6)]
+    xyz = [dev(synth.query_coords(n, 70 + i)) for i, n in enumerate(ns)]
+    grp = ngv.Multi(plans)
+    wts = list(zip(params, f16))
+    ref = [host(o) for o in grp.infer(wts, xyz)]
+    outs = [torch.empty(n, dtype=torch.float32, device="cuda") for n in ns]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        grp.infer(wts, xyz, outs)  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        grp.infer(wts, xyz, outs)
+    for r in range(3):
+        for o in outs:
+            o.fill_(-1.0)
+        grp.infer(wts, xyz)  # eager use of the same group between replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for i in range(6):
+            np.testing.assert_array_equal(host(outs[i]), ref[i], err_msg=f"replay {r}, model {i}")
+
+
 def test_multi_rejects_mixed_shapes():
     a = ngv.Plan(8, 2, 14, 16, 0.0, 2048, n_neurons=64, n_hidden_layers=2, precision="bf16")
     b = ngv.Plan(8, 2, 14, 16, 0.0, 2048, n_neurons=32, n_hidden_layers=2, precision="bf16")
