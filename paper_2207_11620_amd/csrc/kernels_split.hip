@@ -462,8 +462,9 @@ size_t split_planes_bytes(const ngvol_plan* plan, int64_t n) {
 // workgroups per compute unit).
 constexpr size_t kBrickLds = 40 * 1024;
 
-// Brick-staged levels for plans of 8..16 levels (two levels of plane storage
-// per query) whose table entries are at most 8 bytes.  Pair p holds levels p
+// Brick-staged levels for plans of 9..16 levels (two levels of plane storage
+// per group; 8 or fewer levels have one, and take k_level_feat) whose table
+// entries are at most 8 bytes.  Pair p holds levels p
 // and p + 8; a level is staged when its largest box over a brick fits in what
 // the pair leaves of kBrickLds.  The (pair, brick) items, pair-major, are cut
 // into 8 contiguous segments of equal estimated cost, one per XCD, so that
@@ -488,7 +489,7 @@ static double level_cost(int N, int64_t n, bool staged) {
 static bool brick_args(const ngvol_plan* plan, BinRanges bins, int64_t n, int entry_bytes, BrickArgs& ba,
                        size_t& lds) {
   const ModelDesc& md = plan->md;
-  if (!bins.off || !bins.cnt || md.L < 8 || md.L > 16 || entry_bytes > 8) return false;
+  if (!bins.off || !bins.cnt || md.L <= 8 || md.L > 16 || entry_bytes > 8) return false;
   ba = BrickArgs{};
   ba.bin_off = bins.off;
   ba.bin_cnt = bins.cnt;
@@ -550,6 +551,10 @@ static bool brick_args(const ngvol_plan* plan, BinRanges bins, int64_t n, int en
   double total = 0.0;
   for (int i = n_sh; i < 8; ++i) total += c2[i];
   const int base = n_sh * ba.n_bins;
+  if (n_sh == 8) {  // every pair is shared: no segments
+    for (int x = 0; x <= 8; ++x) ba.item_lo[x] = base;
+    return true;
+  }
   ba.item_lo[0] = base;
   int i = n_sh;
   double before = 0.0;  // cost of the list pairs before i

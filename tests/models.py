@@ -5,8 +5,10 @@ Shapes follow the workloads: the tiny Gaussian-blob fit (8 levels, growth
 levels from 16 to 2048, 2^19 entries, 32-64-64-1), the paper's fixed
 Table-2 network (8 levels x 8 features, 2^19, 64 wide, 4 hidden), a
 4-feature variant, a 32-level narrow model, a 4-level model with large
-tables (fewer levels than XCDs) and a 12-level model (level pairs of the
-level-split query that hold one level).
+tables (fewer levels than XCDs), a 12-level model (level pairs of the
+level-split query that hold one level), and 8- and 12-level models whose
+levels all fit LDS over a brick (one level per XCD group; every level pair
+shared by all XCDs).
 """
 import numpy as np
 
@@ -23,6 +25,8 @@ MODELS = {
     "w32k64": dict(L=32, F=2, log2T=12, base=4, scale=1.2, maxres=0, width=32, n_hidden=3, table_scale=1e-2),
     "l4": dict(L=4, F=2, log2T=20, base=64, scale=0.0, maxres=1024, width=32, n_hidden=1, table_scale=1e-2),
     "l12": dict(L=12, F=2, log2T=19, base=16, scale=0.0, maxres=1024, width=64, n_hidden=2, table_scale=1e-2),
+    "l8s": dict(L=8, F=2, log2T=19, base=16, scale=0.0, maxres=256, width=64, n_hidden=2, table_scale=1e-2),
+    "l12s": dict(L=12, F=2, log2T=19, base=16, scale=0.0, maxres=256, width=64, n_hidden=2, table_scale=1e-2),
 }
 
 

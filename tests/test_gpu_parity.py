@@ -175,7 +175,8 @@ def test_binned_infer_equals_direct():
 
 @pytest.mark.parametrize("name,prec,f16", [("cfg1", "fp32", True), ("cfg1", "fp32", False), ("f4", "fp16", True),
                                            ("paper", "bf16", True), ("l4", "fp32", True), ("l12", "fp32", True),
-                                           ("l12", "bf16", True)])
+                                           ("l12", "bf16", True), ("l8s", "fp32", True),
+                                           ("l12s", "fp32", True)])
 def test_level_split_equals_fused(name, prec, f16):
     # above 2^20 queries with FP16 tables larger than one L2 the grouped query
     # runs level group by level group (one group per XCD) and the MLP on
