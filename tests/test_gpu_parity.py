@@ -206,6 +206,26 @@ def test_level_split_equals_fused(name, prec, f16):
     assert rel_err(b[idx], ref) <= (1e-5 if prec == "fp32" else 2e-2)
 
 
+def test_level_split_several_slabs():
+    # FP32 operands make 128-byte planes per query, so the planes hold 2^23
+    # queries at a time and a larger query set runs the level kernels slab by
+    # slab, with bricks cut at the slab boundaries
+    m = oracle_model("cfg1")
+    p = gpu_plan("cfg1", "fp32")
+    params = init_params("cfg1", table_scale=0.5)
+    n = (1 << 23) + (1 << 20) + 4099
+    xyz = synth.query_coords(n, SEED + 11)
+    pt, xt = dev(params), dev(xyz)
+    tf = ngv.make_f16_tables(p, pt)
+    a = host(ngv.infer(p, pt, xt, table_f16=tf, sort=False))
+    b = host(ngv.infer(p, pt, xt, table_f16=tf, sort=True))
+    assert rel_err(b, a) <= 1e-6
+    q = params.astype(np.float64)
+    q[:m.n_table] = host(tf).astype(np.float64)
+    idx = np.r_[np.arange(8), n - 1 - np.arange(8), np.random.default_rng(3).choice(n, 2000, replace=False)]
+    assert rel_err(b[idx], oracle.forward(m, q, xyz[idx])) <= 1e-5
+
+
 @pytest.mark.parametrize("n", [(1 << 21) + 5, (1 << 22) + 3])
 def test_level_split_crowded_cells(n):
     # grouped queries whose cells are uneven: one 1/16 brick holds a quarter
