@@ -674,6 +674,32 @@ def test_render_counts_bit_exact_and_pixels(prec):
     np.testing.assert_array_equal(host(rgba2), img)
 
 
+@pytest.mark.parametrize("name,prec", [("paper", "fp32"), ("paper", "bf16"), ("f4", "fp32")])
+def test_render_other_network_shapes(name, prec):
+    # the renderer's other instantiations: 64 input features (8 levels x 8
+    # features; 16 x 4), and the Table-2 network's four hidden layers
+    m = oracle_model(name)
+    p = gpu_plan(name, prec)
+    params = init_params(name, table_scale=0.3)
+    W, H = 96, 72
+    cam, lut = _render_setup(W, H, angle=1.1)
+    dt = 2.0 ** -7
+    rgba, n_geo, n_used, cnt = ngv.render(p, dev(params), cam, dev(lut), W, H, dt, 3)
+    n_o = oracle.ray_counts(cam, W, H, 3, dt)
+    np.testing.assert_array_equal(host(n_geo).astype(np.uint32), n_o)
+    img = host(rgba)
+    nu = host(n_used)
+    pix = np.random.default_rng(5).choice(W * H, 200, replace=False)
+    ro, ng, nuo = oracle.render_pixels(m, params.astype(np.float64), cam, lut, W, H, dt, 3, pix)
+    g = img.reshape(-1, 4)[pix]
+    same = nu.ravel()[pix] == nuo
+    assert np.all(same | (np.abs(ro[:, 3] - 0.99) < 2e-3))
+    assert np.count_nonzero(same) >= 150
+    tol = 1e-4 if prec == "fp32" else 2e-2
+    assert np.max(np.abs(g[same] - ro[same])) <= tol
+    assert host(cnt)[1] == nu.sum()
+
+
 def test_render_constant_alpha_closed_form():
     # all weights zero -> Phi = 0 -> constant colour from LUT[0]
     p = gpu_plan("tiny", "fp32")
