@@ -854,13 +854,28 @@ def test_online_training_interleave():
 
 # ----------------------------------------------------------- multi-volume -----
 
-def _multi_models(k=16, scale=0.5):
+def _multi_models(k=16, scale=0.5, width=64, n_hidden=2, precision="bf16"):
     plans, params = [], []
     for i, sp in enumerate(synth.multi_volume_specs(k)):
-        p = ngv.Plan(sp["L"], 2, sp["log2T"], 16, 0.0, 2048, n_neurons=64, n_hidden_layers=2, precision="bf16")
+        p = ngv.Plan(sp["L"], 2, sp["log2T"], 16, 0.0, 2048, n_neurons=width, n_hidden_layers=n_hidden,
+                     precision=precision)
         plans.append(p)
-        params.append(dev(synth.init_params(p.n_table_params, p.n_input, 64, 2, scale, sp["seed"])))
+        params.append(dev(synth.init_params(p.n_table_params, p.n_input, width, n_hidden, scale, sp["seed"])))
     return plans, params
+
+
+@pytest.mark.parametrize("width,n_hidden,precision", [(32, 3, "bf16"), (32, 2, "fp32"), (64, 1, "fp16")])
+def test_multi_infer_other_shapes(width, n_hidden, precision):
+    # the group kernel's other instantiations equal single-model launches
+    plans, params = _multi_models(k=5, width=width, n_hidden=n_hidden, precision=precision)
+    f16 = [ngv.make_f16_tables(p, w) for p, w in zip(plans, params)]
+    ns = [3000 + 1237 * i for i in range(5)]
+    xyz = [dev(synth.query_coords(n, 90 + i)) for i, n in enumerate(ns)]
+    grp = ngv.Multi(plans)
+    outs = grp.infer(list(zip(params, f16)), xyz)
+    for i in range(5):
+        ref = ngv.infer(plans[i], params[i], xyz[i], table_f16=f16[i], sort=False)
+        np.testing.assert_array_equal(host(outs[i]), host(ref))
 
 
 def test_multi_infer_equals_single_launches():
