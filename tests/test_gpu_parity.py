@@ -113,6 +113,11 @@ def test_mlp_fwd_fp32_and_bf16(name):
     # BF16 feature buffer: same result as rounding the FP32 features first
     gotbb = host(ngv.mlp_fwd(gpu_plan(name, "bf16"), dev(params), dev(feat).to(torch.bfloat16)))
     np.testing.assert_array_equal(gotbb, gotb)
+    # and likewise FP16 features on the FP16 form
+    goth = host(ngv.mlp_fwd(gpu_plan(name, "fp16"), dev(params), dev(feat)))
+    assert rel_err(goth, ref) <= 2e-2
+    gothh = host(ngv.mlp_fwd(gpu_plan(name, "fp16"), dev(params), dev(feat).to(torch.float16)))
+    np.testing.assert_array_equal(gothh, goth)
 
 
 @pytest.mark.parametrize("name", ["tiny", "cfg1", "paper", "f4", "w32k64"])
