@@ -196,6 +196,51 @@ def test_render_adaptive_matches_oracle(prec, s2, pexp):
     assert np.max(np.abs(img[pix][same] - ro[same])) <= tol
 
 
+@functools.lru_cache(maxsize=1)
+def _render_model_table2():
+    name = "paper"
+    m = oracle_model(name)
+    vol = synth.fractal_value_noise(48, SEED)
+    th, _, _ = oracle.train(m, init_params(name).astype(np.float64), vol, SEED, 30, 4096, 1e-2, 0.9, 0.99, 1e-15)
+    return m, th.astype(np.float32), vol
+
+
+@pytest.mark.parametrize("adaptive", [False, True])
+def test_render_macrocells_table2_network(adaptive):
+    # skipping and adaptive marching in the renderer's 64-input, four-hidden-
+    # layer instantiation (the Table-2 network), FP32, against the oracle
+    m, params, vol = _render_model_table2()
+    p = gpu_plan("paper", "fp32")
+    pt = dev(params)
+    W = H = 128
+    cam = synth.orbit_camera(0.4, W, H)
+    lut = synth.transfer_function_lut().copy()
+    lut[:103, 3] = 0.0
+    dt = 2.0 ** -9
+    dims, cell = (48, 48, 48), 8
+    xyz = oracle.batch_coords(SEED, 2, 1 << 16)
+    y = oracle.sample_volume(vol, xyz).astype(np.float32)
+    mu_o = oracle.mc_opacity(oracle.mc_update(dims, cell, xyz, y), lut).astype(np.float32)
+    assert np.any(mu_o == 0)
+    mc = ngv.MacroCells(dims, cell)
+    mc.mu.copy_(dev(mu_o))
+    rgba, n_geo, n_used, cnt = ngv.render(p, pt, cam, dev(lut), W, H, dt, 6, macrocells=mc, adaptive=adaptive)
+    np.testing.assert_array_equal(host(n_geo).astype(np.uint32), oracle.ray_counts(cam, W, H, 6, dt))
+    img, nu = host(rgba).reshape(-1, 4), host(n_used).ravel()
+    hit = np.flatnonzero(host(n_geo).ravel() > 0)
+    pix = np.random.default_rng(9).choice(hit, 200, replace=False)
+    q = params.astype(np.float64)
+    if adaptive:
+        ro, _, nuo = oracle.render_pixels_adaptive(m, q, cam, lut, W, H, dt, 6, pix, dims, cell, mu_o, 64.0, 2)
+    else:
+        ro, _, nuo = oracle.render_pixels_mc(m, q, cam, lut, W, H, dt, 6, pix, dims, cell, mu_o)
+    same = nu[pix] == nuo
+    assert np.mean(same) > 0.9
+    assert np.all(same | (np.abs(ro[:, 3] - 0.99) < 2e-2))
+    assert np.max(np.abs(img[pix][same] - ro[same])) <= 1e-4
+    assert host(cnt)[1] == nu.sum()
+
+
 def test_render_adaptive_degenerate_grids():
     # opacity >= 1 everywhere, or s2 = 1: every step is one grid step, so the
     # adaptive walk evaluates exactly the samples of the fixed-step marcher
