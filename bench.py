@@ -112,7 +112,7 @@ def main():
                     help="run one plain 1 GiB device copy, the reference for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU only; --gpus N > 1 is not supported", file=sys.stderr)
+        print("bench.py: measures one GPU; --gpus N > 1 is not supported", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
