@@ -13,7 +13,10 @@
 //      hardware's round-robin placement of workgroups) interpolate their
 //      levels and write them, in the MLP's operand type, into their group's
 //      own plane [query][group levels][F] - one store per query, and no
-//      cache line shared with another XCD's writes;
+//      cache line shared with another XCD's writes.  For plans of 9..16
+//      levels k_level_brick (below) takes its place: it works on level pairs
+//      over spatial bricks, staging the levels that fit in LDS, and spreads
+//      the fully staged pairs over all XCDs;
 //   2. k_mlp_planes: the network on the planes, with the next tiles' features
 //      loaded while the current ones are evaluated; each result goes to the
 //      query's original slot.  Its first-layer operands take the features in
