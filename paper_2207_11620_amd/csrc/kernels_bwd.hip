@@ -1,6 +1,7 @@
 // Backward kernels: MLP backward with activation recompute (MFMA), encoding
 // scatter-add, partial-sum reduction, Adam and step bookkeeping.
 #include "kernels.hpp"
+#include "lds_add.hpp"
 #include "mlp_tile.hpp"
 
 namespace ngvol {
@@ -326,7 +327,10 @@ __global__ void __launch_bounds__(64 * kBwdMaxWaves) k_bwd(ModelDesc md, const f
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
               const int o = 16 * mo + 4 * g + j;
-              if (acc[j] != 0.0f) atomicAdd(dw + o * in_dim + i, acc[j] * ibscale);
+              if (acc[j] != 0.0f) {
+                if constexpr (GDW) atomicAdd(dw + o * in_dim + i, acc[j] * ibscale);  // L2
+                else lds_add_f32(dw + o * in_dim + i, acc[j] * ibscale);
+              }
             }
           }
         }
